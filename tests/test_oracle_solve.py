@@ -1,0 +1,214 @@
+"""Pins of the oracle's constrained solve and post-processing (no GPU).
+
+Pins: exact reproduction of linear fields on conformed meshes (Q1 patch test),
+an independent dense brute-force assembly and solve on tiny meshes, mirror
+symmetry (psi odd in y, so bodies on y = 0 carry psi_b = 0 and the transverse
+pair carries opposite values), zero circulation of each body, convergence to
+the analytic isolated-cylinder solution psi = U y (1 - a^2/r^2) under mesh
+refinement, and the internal arithmetic of the paper's Table 1.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from oracle.cg import cg
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+@pytest.mark.parametrize("case", [
+    W.single_cylinder(64),
+    W.five_cylinders(96, 48, 0.25, extent=(-6, 6, -3, 3)),
+    W.five_cylinders(90, 46, 0.05, extent=(-6, 6, -3, 3)),
+])
+def test_patch_test_linear_field(case):
+    """psi = a + b x + c y prescribed on all four sides and on every body node
+    is reproduced exactly at every free node (isoparametric Q1 elements
+    represent linear fields)."""
+    mesh = O.conform(case.grid, case.circles, 200)
+    X, Y = mesh.coords()
+    lin = (0.3 + 0.7 * X - 1.3 * Y).ravel()
+    flow = W.Flow(1.0, (W.BC_DIRICHLET_UY,) * 4)
+    sol = O.solve(mesh, flow, g=lin, body_fixed=lin)
+    np.testing.assert_allclose(sol.psi, lin, atol=1e-12)
+    # U y with the case's own natural outlet (psi_x = 0 there)
+    uy = (case.flow.U * Y).ravel()
+    sol = O.solve(mesh, case.flow, body_fixed=uy)
+    np.testing.assert_allclose(sol.psi, uy, atol=1e-12)
+
+
+def brute_dense_solution(mesh, flow):
+    """Independent dense assembly of the reduced system with Python loops."""
+    grid = mesh.grid
+    nx, ny = grid.nx, grid.ny
+    X, Y = mesh.coords()
+    body = mesh.body
+    dmask = O.dirichlet_mask(grid, flow)
+    g = O.dirichlet_values(grid, flow, mesh.circles).reshape(ny + 1, nx + 1)
+    nb = len(mesh.circles)
+    unknown = {}
+    for j in range(ny + 1):
+        for i in range(nx + 1):
+            if body[j, i] < 0 and not dmask[j, i]:
+                unknown[(j, i)] = len(unknown)
+    nfree = len(unknown)
+    for j in range(ny + 1):
+        for i in range(nx + 1):
+            if body[j, i] >= 0:
+                unknown[(j, i)] = nfree + int(body[j, i])
+    n = nfree + nb
+    A = np.zeros((n, n))
+    rhs = np.zeros(n)
+    for j in range(ny):
+        for i in range(nx):
+            nodes = [(j, i), (j, i + 1), (j + 1, i + 1), (j + 1, i)]
+            bs = [int(body[q]) for q in nodes]
+            if bs[0] >= 0 and all(v == bs[0] for v in bs):
+                continue
+            Ke = O.element_stiffness(np.array([X[q] for q in nodes]), np.array([Y[q] for q in nodes]))
+            for a, qa in enumerate(nodes):
+                if qa not in unknown:
+                    continue
+                for c, qc in enumerate(nodes):
+                    if qc in unknown:
+                        A[unknown[qa], unknown[qc]] += Ke[a, c]
+                    else:
+                        rhs[unknown[qa]] -= Ke[a, c] * g[qc]
+    y = np.linalg.solve(A, rhs)
+    return y[nfree:], A
+
+
+@pytest.mark.parametrize("nx,ny,circles", [
+    (16, 8, [(0.0, 0.0, 1.0)]),
+    (24, 8, [(-1.75, 0.0, 1.0), (1.75, 0.1, 1.0)]),
+])
+def test_dense_brute_force(nx, ny, circles):
+    g = W.Grid(nx, ny, -4.0, 4.0, -2.0, 2.0)
+    mesh = O.conform(g, circles, 200)
+    flow = W.Flow(1.3, (W.BC_DIRICHLET_UY, W.BC_NATURAL, W.BC_DIRICHLET_UY, W.BC_DIRICHLET_UY))
+    sol = O.solve(mesh, flow)
+    psib, A = brute_dense_solution(mesh, flow)
+    np.testing.assert_allclose(sol.psi_b, psib, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(sol.A.toarray(), A, atol=1e-13)
+    assert np.all(np.linalg.eigvalsh(A) > 0)
+
+
+def test_single_cylinder_symmetry_and_counts():
+    case = W.single_cylinder(64)
+    mesh = O.conform(case.grid, case.circles, 200)
+    sol = O.solve(mesh, case.flow)
+    assert sol.ndof == 4020
+    assert abs(sol.psi_b[0]) <= 1e-12
+    psi = sol.psi.reshape(65, 65)
+    np.testing.assert_allclose(psi, -psi[::-1], atol=1e-12)
+
+
+def test_five_cylinder_symmetry_and_circulation():
+    case = W.five_cylinders(128, 64, 0.25, extent=(-8, 8, -4, 4))
+    mesh = O.conform(case.grid, case.circles, 200)
+    sol = O.solve(mesh, case.flow)
+    scale = np.abs(sol.psi).max()
+    assert np.all(np.abs(sol.psi_b[:3]) <= 1e-12 * scale)
+    assert abs(sol.psi_b[3] + sol.psi_b[4]) <= 1e-12 * scale
+    assert sol.psi_b[4] > 0
+    # zero circulation: sum over each body's nodes of (K psi) vanishes
+    Kpsi = sol.K @ sol.psi
+    absK = abs(sol.K) @ np.abs(sol.psi)
+    body = mesh.body.ravel()
+    for b in range(5):
+        sel = body == b
+        assert abs(Kpsi[sel].sum()) <= 1e-12 * absK[sel].sum()
+    # free-node equations hold too
+    free = sol.dof[: sol.dof.size] >= 0
+    free &= body < 0
+    assert np.abs(Kpsi[free]).max() <= 1e-11 * absK[free].max()
+
+
+def test_no_body_channel_is_uniform_flow():
+    g = W.Grid(20, 10, -2.0, 2.0, -1.0, 1.0)
+    mesh = O.conform(g, [], 200)
+    flow = W.Flow(2.5, (W.BC_DIRICHLET_UY, W.BC_NATURAL, W.BC_DIRICHLET_UY, W.BC_DIRICHLET_UY))
+    sol = O.solve(mesh, flow)
+    X, Y = O.node_coords(g)
+    np.testing.assert_allclose(sol.psi, 2.5 * Y.ravel(), atol=1e-13)
+
+
+def _cyl_error(n):
+    case = W.single_cylinder(n, exact_bc=True)
+    mesh = O.conform(case.grid, case.circles, 200)
+    sol = O.solve(mesh, case.flow)
+    X, Y = mesh.coords()
+    fl = (mesh.kind == O.FLUID).ravel()
+    r2 = (X * X + Y * Y).ravel()[fl]
+    exact = (Y.ravel()[fl]) * (1.0 - 0.25 / r2)
+    return np.abs(sol.psi[fl] - exact).max(), sol, mesh
+
+
+def test_analytic_cylinder_second_order():
+    errs = [_cyl_error(n)[0] for n in (64, 128, 256)]
+    assert errs[0] < 0.04 and errs[1] < 0.006 and errs[2] < 0.0015
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+
+
+def test_analytic_cylinder_truncation_floor_with_uniform_boundary_data():
+    """With psi = U y on the sides of [-8,8]^2 the difference to the unbounded
+    solution is set by the truncated far field U a^2 y / r^2 <= U a^2 / L."""
+    case = W.single_cylinder(128)
+    mesh = O.conform(case.grid, case.circles, 200)
+    sol = O.solve(mesh, case.flow)
+    X, Y = mesh.coords()
+    fl = (mesh.kind == O.FLUID).ravel()
+    r2 = (X * X + Y * Y).ravel()[fl]
+    err = np.abs(sol.psi[fl] - Y.ravel()[fl] * (1 - 0.25 / r2)).max()
+    assert 0.02 < err < 0.045
+
+
+def test_surface_velocity_converges_to_formula_on_exact_field():
+    """The discrete u_t converges to the same difference formula evaluated on
+    the exact stream function, and tracks 2 U sin(theta)."""
+    out = []
+    for n in (64, 256):
+        _, sol, mesh = _cyl_error(n)
+        th, ut, bb = O.surface_samples(mesh, sol.psi, sol.psi_b)
+        X, Y = mesh.coords()
+        r2 = X * X + Y * Y
+        with np.errstate(divide="ignore", invalid="ignore"):
+            exact = np.where(mesh.kind == O.FLUID, Y * (1 - 0.25 / r2), 0.0).ravel()
+        _, ut_exact, _ = O.surface_samples(mesh, exact, np.zeros(1))
+        out.append(np.abs(ut - ut_exact).max())
+        assert len(th) > 0 and np.all(bb == 0)
+        assert np.corrcoef(ut, 2 * np.sin(th))[0, 1] > 0.97
+    assert out[1] < out[0] / 4
+
+
+def test_table1_internal_arithmetic():
+    """CoPFI = (psi5 - psi4)/(U (y5 - y4)) reproduces the printed Q54 / delta in
+    the paper's units (U = 2 m/s, domain height 0.5 m, centre distance
+    delta * 0.5 m); psi4 + psi5 = 1 by the channel's mirror symmetry."""
+    rows = np.loadtxt(os.path.join(HERE, "golden", "table1_gap_ratio.txt"))
+    for delta, psi1, psi5, psi4, q54, cop in rows:
+        psi_b = np.array([psi1, 0, 0, psi4, psi5])
+        Q, J = O.copfi(psi_b, 3, 4, 2.0, 0.25 - 0.25 * delta, 0.25 + 0.25 * delta)
+        assert Q == pytest.approx(q54, abs=1.5e-5)
+        assert J == pytest.approx(cop, abs=5e-5)
+        assert psi4 + psi5 == pytest.approx(1.0, abs=1.5e-5)
+        assert psi1 == pytest.approx(0.5, abs=1.5e-5)
+
+
+def test_dof_count_1024x512():
+    case = W.five_cyl_1024()
+    k, b = O.classify(case.grid, case.circles)
+    dof, nfree, ndof = O.dof_numbering(case.grid, b, case.flow, 5)
+    assert ndof == 520722
+
+
+def test_cg_matches_direct():
+    case = W.five_cylinders(96, 48, 0.25, extent=(-6, 6, -3, 3))
+    mesh = O.conform(case.grid, case.circles, 200)
+    sol = O.solve(mesh, case.flow)
+    x, k, rel = cg(sol.A.tocsr(), sol.b, rtol=1e-13)
+    assert rel <= 1e-13
+    np.testing.assert_allclose(x, sol.y, rtol=0, atol=1e-10 * np.abs(sol.y).max())
