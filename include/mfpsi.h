@@ -1,0 +1,194 @@
+/*
+ * mfpsi -- matrix-free multi-body stream-function solver for AMD MI355X (gfx950).
+ *
+ * C ABI of libmfpsi.so.  The method is that of Sadasivan & Yadav, "A Computational
+ * Approach for Multi-Body Potential-Flow Interaction Effects Using Matrix-Free FEM and
+ * Body-Conforming Grids":
+ *
+ *   mfp_mesh_conform   section "Body-Conforming Grid Generation" (projection of
+ *                      just-inside nodes, displacement d_ik = x_ik - x_gk, Laplacian
+ *                      propagation of d, x_new = x_old + d);
+ *   mfp_psi_solve      sections "Governing Equation", "Boundary Conditions",
+ *                      "Weak formulation", "Matrix-Free Conjugate Gradient with Multiple
+ *                      Constraint Enforcement", Algorithm 1 (appendix), "Velocity Field
+ *                      and Surface Tangential Velocity", and the CoPFI definition of
+ *                      "Effect of Gap Ratio";
+ *   mfp_element_apply  the matrix-free element product of Algorithm 1 on its own;
+ *   mfp_psi_grad / mfp_mesh_conform_grad
+ *                      the adjoint of that map (the automated sensitivity analysis named
+ *                      in the Conclusions as the next step).
+ *
+ * Conventions common to every entry point
+ * ---------------------------------------
+ * - Background grid: nx x ny cells, (nx+1)(ny+1) nodes; node (i, j) sits at
+ *   x0 + i*hx, y0 + j*hy with hx = (x1-x0)/nx, hy = (y1-y0)/ny; flat node id
+ *   j*(nx+1) + i (x fastest).
+ * - Pointers named *_h are HOST memory.  Every other array pointer is DEVICE memory
+ *   owned by the caller; the library never allocates, frees or keeps them.
+ * - Displacements are stored component-major: disp[0 .. n) = x, disp[n .. 2n) = y,
+ *   n = (nx+1)(ny+1).
+ * - Scratch memory comes from the caller's workspace (ws, ws_bytes), at least the
+ *   size reported by the matching *_workspace_size call, 256-byte aligned.  Its
+ *   contents on entry are ignored.
+ * - `stream` is a hipStream_t (NULL = the legacy default stream).  All device work is
+ *   enqueued on it.  Calls that report host-side results (psi_b_h, stats_h, ...)
+ *   synchronise that stream before returning; mfp_mesh_conform and mfp_element_apply
+ *   synchronise it only to read their error flags.
+ * - Return value: 0 = MFP_OK, > 0 = warning (results written), < 0 = error (outputs
+ *   unspecified).  mfp_last_error() returns a thread-local message for the last
+ *   non-zero status of the calling thread.  No C++ exception crosses the ABI.
+ * - One call at a time per workspace; calls with distinct workspaces may overlap on
+ *   different streams.
+ */
+#ifndef MFPSI_H
+#define MFPSI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---------------------------------------------------------------- */
+#define MFP_OK 0
+#define MFP_W_NOCONV 1      /* kmax reached before the tolerance                     */
+#define MFP_W_STAGNATION 2  /* FP32 inner solves stalled; FP64 iterations finished it */
+#define MFP_E_ARG -1        /* invalid argument (NULL pointer, bad size, bad code)    */
+#define MFP_E_HIP -2        /* a HIP runtime call failed                              */
+#define MFP_E_GEOMETRY -3   /* circles overlap, touch the outer band or are < 2 cells */
+#define MFP_E_TANGLED -4    /* a Gauss-point Jacobian of an active cell is <= 0       */
+#define MFP_E_BREAKDOWN -5  /* CG breakdown: p.Ap <= 0 or not finite                  */
+#define MFP_E_WORKSPACE -6  /* workspace too small                                    */
+
+/* ---- node kinds written by mfp_mesh_conform ---------------------------------------- */
+#define MFP_FLUID 0   /* not inside any body                                           */
+#define MFP_SNAPPED 1 /* body node with a fluid node among its 8 neighbours: on Gamma_i */
+#define MFP_DEEP 2    /* body node with no fluid neighbour: stays put                    */
+
+/* ---- side boundary conditions (side order: left, right, bottom, top) -------------- */
+#define MFP_BC_NATURAL 0       /* zero normal derivative of psi: nodes stay unknowns     */
+#define MFP_BC_DIRICHLET_UY 1  /* psi = U * y                                            */
+#define MFP_BC_DIRICHLET_CYL 2 /* psi = U (y-cy)(1 - a^2/rho^2) about circle 0 (tests)   */
+
+/* ---- solver precisions ------------------------------------------------------------ */
+#define MFP_FP64 0    /* FP64 vectors and FP64 element apply                           */
+#define MFP_FP32 1    /* FP32 vectors and apply; FP64 scalars and body sums            */
+#define MFP_FP32_IR 2 /* FP32 inner CG wrapped in FP64 iterative refinement            */
+
+#define MFP_MAX_BODIES 64
+
+typedef struct {
+  int32_t nx, ny;         /* cells in x and y, each >= 2                                */
+  double x0, x1, y0, y1;  /* domain, x1 > x0, y1 > y0                                   */
+} mfp_grid;
+
+typedef struct {
+  double cx, cy, r;       /* circle centre and radius                                   */
+} mfp_circle;
+
+typedef struct {
+  double U;               /* free-stream speed                                          */
+  int32_t side_bc[4];     /* MFP_BC_* for left, right, bottom, top                      */
+} mfp_flow;
+
+typedef struct {
+  int32_t precision;      /* MFP_FP64 / MFP_FP32 / MFP_FP32_IR                          */
+  double rtol;            /* stop when ||r_k|| <= rtol ||r_0|| (unknowns incl. bodies)  */
+  int64_t kmax;           /* CG iteration cap (all inner iterations together)           */
+  int32_t check_every;    /* host convergence poll period in iterations (>= 1)          */
+  double inner_rtol;      /* MFP_FP32_IR: relative tolerance of each inner FP32 solve   */
+  int32_t max_outer;      /* MFP_FP32_IR: cap on refinement steps                       */
+  const double* psi0;     /* optional DEVICE warm start (nodal psi, may be NULL)        */
+  int32_t profile_every;  /* > 0: time every n-th apply launch with HIP events -> stats */
+} mfp_solver_opts;
+
+typedef struct {
+  int64_t iters;          /* CG iterations (inner + FP64)                               */
+  int64_t outer_iters;    /* refinement steps (MFP_FP32_IR), else 0                     */
+  int64_t applies;        /* element-operator applications (all precisions)             */
+  int64_t n_dof;          /* N_int + N_N + N_b                                          */
+  int64_t n_free;         /* N_int + N_N                                                */
+  double relres_true;     /* ||b - A x|| / ||b - A x0|| recomputed in FP64 at the end   */
+  double rnorm0;          /* ||b - A x0||                                               */
+  double solve_ms;        /* device time of the iteration phase (HIP events)            */
+  double apply_ms;        /* mean duration of one apply launch (profile_every > 0)      */
+  int64_t apply_samples;  /* launches behind apply_ms                                   */
+  int64_t n_plain_tiles;  /* 64x8 node tiles on the constant-stencil path               */
+  int64_t n_tiles;        /* all node tiles                                             */
+} mfp_stats;
+
+/* Message for the last non-zero status returned on this thread ("" if none). */
+const char* mfp_last_error(void);
+
+/* Host-only geometry check (no device work): MFP_OK or MFP_E_GEOMETRY / MFP_E_ARG.
+ * Rejects: nbody outside [0, MFP_MAX_BODIES]; nx or ny < 2; any radius below
+ * 2 max(hx, hy); a circle closer than one cell to a side; two circles whose centre
+ * distance is not above the sum of their radii. */
+int mfp_check_geometry(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody);
+
+/* Workspace bytes for mfp_mesh_conform. */
+size_t mfp_conform_workspace_size(const mfp_grid* grid, int32_t nbody);
+
+/* Body-conforming mesh (section "Body-Conforming Grid Generation").
+ *   kind[n]  MFP_FLUID / MFP_SNAPPED / MFP_DEEP, body[n] = body index or -1, where a
+ *            node is inside body b iff (x-cx)^2 + (y-cy)^2 <= r^2 in FP64;
+ *   disp     radial projection c + (r/rho)(x - c) - x on snapped nodes, zero on deep and
+ *            outer-boundary nodes, and `nsweeps` Jacobi sweeps
+ *            d <- wx (d_E + d_W) + wy (d_N + d_S), wx = hy^2/(2(hx^2+hy^2)),
+ *            wy = hx^2/(2(hx^2+hy^2)), on the remaining fluid nodes (start 0).
+ * All outputs are (nx+1)(ny+1) node arrays (disp twice that), device memory.
+ * Returns MFP_E_TANGLED if an active cell has a non-positive Gauss-point Jacobian.
+ * Results are bit-for-bit reproducible (no fused multiply-add in this step). */
+int mfp_mesh_conform(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                     int32_t nsweeps, double* disp, int8_t* kind, int8_t* body,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for mfp_psi_solve / mfp_element_apply with this precision. */
+size_t mfp_solve_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t precision);
+
+/* Matrix-free element product q = K p (Algorithm 1's element loop, section "Weak
+ * formulation": K_e = int (grad N)^T (grad N) dOmega, bilinear quads, 2x2 Gauss),
+ * summed over active cells (cells whose four nodes are not all in one body), on the
+ * mesh X = background + disp.  No boundary conditions are applied: q is the full
+ * nodal product.  precision MFP_FP64: p, q are double[(nx+1)(ny+1)];
+ * MFP_FP32: float[(nx+1)(ny+1)] (geometry rounded to FP32 relative to the cell).
+ * `repeat` >= 1 launches the same kernel that many times (timing); apply_ms_h, if
+ * non-NULL, receives the mean kernel duration in milliseconds. */
+int mfp_element_apply(const mfp_grid* grid, const double* disp, const int8_t* body,
+                      int32_t precision, const void* p, void* q, int32_t repeat,
+                      double* apply_ms_h, void* ws, size_t ws_bytes, void* stream);
+
+/* Constrained stream-function solve on a conformed mesh.
+ * Unknowns: free nodes (interior and natural-boundary nodes) plus one psi_b per body
+ * (all of a body's nodes tied to it); Dirichlet sides prescribed by `flow`.  Solves
+ * A y = b with A = T^T K T, b = -T^T K g by conjugate gradients (Algorithm 1), to
+ * ||r_k|| <= rtol ||r_0||.
+ * Outputs:
+ *   psi         device double[(nx+1)(ny+1)]: nodal psi (body nodes carry psi_b);
+ *   psi_b_h     host double[nbody];
+ *   Q_h         host: psi_b[pair_hi] - psi_b[pair_lo]          (may be NULL);
+ *   copfi_h     host: Q / (U (cy[pair_hi] - cy[pair_lo]))      (may be NULL);
+ *               pair indices < 0 skip Q and CoPFI;
+ *   samples     device double[2*sample_cap]: (theta, u_t) pairs, u_t = (psi_c - psi_b)/d_nc
+ *               on every edge joining two nodes snapped to the same body, in each active
+ *               cell with a fluid node; ordered by (body, cell id, local edge); may be
+ *               NULL when sample_cap == 0;
+ *   sample_body device int8[sample_cap];
+ *   n_samples_h host: number of samples that exist (may exceed sample_cap);
+ *   stats_h     host (may be NULL).
+ * Returns MFP_W_NOCONV if kmax was reached, MFP_E_BREAKDOWN on CG breakdown. */
+int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                  const double* disp, const int8_t* kind, const int8_t* body,
+                  const mfp_flow* flow, const mfp_solver_opts* opts,
+                  int32_t pair_lo, int32_t pair_hi,
+                  double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
+                  double* samples, int8_t* sample_body, int32_t sample_cap,
+                  int32_t* n_samples_h, mfp_stats* stats_h,
+                  void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFPSI_H */

@@ -1,0 +1,12 @@
+"""MI355X-native matrix-free multi-body stream-function solver.
+
+Python face of libmfpsi.so: a body-conforming Q1 mesh from a Cartesian grid and
+circles, the multi-point-constrained conjugate-gradient solve for psi, and the
+derived body stream-function values, surface velocities, inter-body flow rate
+and CoPFI.  All arithmetic runs in the library's HIP kernels.
+"""
+from .binding import (MfpError, check_geometry, element_apply, last_error, load,
+                      mesh_conform, psi_solve, solve_workspace_size, EXPORTS)
+
+__all__ = ["MfpError", "check_geometry", "element_apply", "last_error", "load",
+           "mesh_conform", "psi_solve", "solve_workspace_size", "EXPORTS"]

@@ -1,0 +1,234 @@
+"""ctypes binding of libmfpsi.so (see include/mfpsi.h for the C ABI).
+
+Argument marshalling only: tensors supply device pointers, the current HIP stream
+comes from torch, every computation runs in the library's kernels.  Missing or
+unloadable native code raises; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (POINTER, Structure, byref, c_char_p, c_double, c_int8, c_int32,
+                    c_int64, c_size_t, c_void_p)
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmfpsi.so")
+
+MFP_OK, MFP_W_NOCONV, MFP_W_STAGNATION = 0, 1, 2
+MFP_E_ARG, MFP_E_HIP, MFP_E_GEOMETRY, MFP_E_TANGLED, MFP_E_BREAKDOWN, MFP_E_WORKSPACE = (
+    -1, -2, -3, -4, -5, -6)
+MFP_FLUID, MFP_SNAPPED, MFP_DEEP = 0, 1, 2
+BC_NATURAL, BC_DIRICHLET_UY, BC_DIRICHLET_CYL = 0, 1, 2
+FP64, FP32, FP32_IR = 0, 1, 2
+MAX_BODIES = 64
+_PREC = {"fp64": FP64, "fp32": FP32, "fp32_ir": FP32_IR}
+
+# Every symbol the header declares (checked by the CPU test-suite).
+EXPORTS = [
+    "mfp_last_error", "mfp_check_geometry", "mfp_conform_workspace_size",
+    "mfp_mesh_conform", "mfp_solve_workspace_size", "mfp_element_apply", "mfp_psi_solve",
+]
+
+
+class MfpGrid(Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("x0", c_double), ("x1", c_double),
+                ("y0", c_double), ("y1", c_double)]
+
+
+class MfpCircle(Structure):
+    _fields_ = [("cx", c_double), ("cy", c_double), ("r", c_double)]
+
+
+class MfpFlow(Structure):
+    _fields_ = [("U", c_double), ("side_bc", c_int32 * 4)]
+
+
+class MfpSolverOpts(Structure):
+    _fields_ = [("precision", c_int32), ("rtol", c_double), ("kmax", c_int64),
+                ("check_every", c_int32), ("inner_rtol", c_double), ("max_outer", c_int32),
+                ("psi0", c_void_p), ("profile_every", c_int32)]
+
+
+class MfpStats(Structure):
+    _fields_ = [("iters", c_int64), ("outer_iters", c_int64), ("applies", c_int64),
+                ("n_dof", c_int64), ("n_free", c_int64), ("relres_true", c_double),
+                ("rnorm0", c_double), ("solve_ms", c_double), ("apply_ms", c_double),
+                ("apply_samples", c_int64), ("n_plain_tiles", c_int64), ("n_tiles", c_int64)]
+
+
+class MfpError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"mfpsi status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libmfpsi.so once; raise if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not built: run `python -m paper_2512_12232_amd.build`")
+    lib = ctypes.CDLL(path)
+    lib.mfp_last_error.restype = c_char_p
+    lib.mfp_check_geometry.argtypes = [POINTER(MfpGrid), POINTER(MfpCircle), c_int32]
+    lib.mfp_conform_workspace_size.restype = c_size_t
+    lib.mfp_conform_workspace_size.argtypes = [POINTER(MfpGrid), c_int32]
+    lib.mfp_mesh_conform.argtypes = [POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_int32,
+                                     c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
+    lib.mfp_solve_workspace_size.restype = c_size_t
+    lib.mfp_solve_workspace_size.argtypes = [POINTER(MfpGrid), c_int32, c_int32]
+    lib.mfp_element_apply.argtypes = [POINTER(MfpGrid), c_void_p, c_void_p, c_int32, c_void_p,
+                                      c_void_p, c_int32, POINTER(c_double), c_void_p, c_size_t,
+                                      c_void_p]
+    lib.mfp_psi_solve.argtypes = [
+        POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_void_p, c_void_p, c_void_p,
+        POINTER(MfpFlow), POINTER(MfpSolverOpts), c_int32, c_int32, c_void_p,
+        POINTER(c_double), POINTER(c_double), POINTER(c_double), c_void_p, c_void_p, c_int32,
+        POINTER(c_int32), POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
+    _lib = lib
+    return lib
+
+
+def last_error() -> str:
+    return load().mfp_last_error().decode()
+
+
+def _check(status: int, allow_warn: bool = True) -> int:
+    if status < 0 or (status > 0 and not allow_warn):
+        raise MfpError(status, last_error())
+    return status
+
+
+def make_grid(g) -> MfpGrid:
+    return MfpGrid(int(g.nx), int(g.ny), float(g.x0), float(g.x1), float(g.y0), float(g.y1))
+
+
+def make_circles(circles: Sequence) -> ctypes.Array:
+    arr = (MfpCircle * max(1, len(circles)))()
+    for k, (cx, cy, r) in enumerate(circles):
+        arr[k] = MfpCircle(float(cx), float(cy), float(r))
+    return arr
+
+
+def make_flow(flow) -> MfpFlow:
+    f = MfpFlow()
+    f.U = float(flow.U)
+    for k in range(4):
+        f.side_bc[k] = int(flow.side_bc[k])
+    return f
+
+
+def _stream() -> c_void_p:
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> c_void_p:
+    return c_void_p(t.data_ptr() if t is not None else 0)
+
+
+def check_geometry(grid, circles) -> int:
+    """Host-only geometry check; returns the status code."""
+    g = make_grid(grid)
+    c = make_circles(circles)
+    return load().mfp_check_geometry(byref(g), c, len(circles))
+
+
+def workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def mesh_conform(grid, circles, nsweeps: int = 200, device="cuda"):
+    """Returns (disp[2*nodes] f64, kind[nodes] i8, body[nodes] i8) device tensors."""
+    lib = load()
+    g = make_grid(grid)
+    c = make_circles(circles)
+    n = (g.nx + 1) * (g.ny + 1)
+    disp = torch.empty(2 * n, dtype=torch.float64, device=device)
+    kind = torch.empty(n, dtype=torch.int8, device=device)
+    body = torch.empty(n, dtype=torch.int8, device=device)
+    wsz = lib.mfp_conform_workspace_size(byref(g), len(circles))
+    ws = workspace(wsz, device)
+    _check(lib.mfp_mesh_conform(byref(g), c, len(circles), int(nsweeps), _ptr(disp),
+                                _ptr(kind), _ptr(body), _ptr(ws), ws.numel(), _stream()))
+    return disp, kind, body
+
+
+def element_apply(grid, disp: torch.Tensor, body: torch.Tensor, p: torch.Tensor,
+                  precision: str = "fp64", repeat: int = 1):
+    """q = K p over active cells (no boundary conditions).  Returns (q, mean ms)."""
+    lib = load()
+    g = make_grid(grid)
+    prec = _PREC[precision]
+    dt = torch.float64 if prec == FP64 else torch.float32
+    p = p.to(dt).contiguous()
+    q = torch.empty_like(p)
+    wsz = lib.mfp_solve_workspace_size(byref(g), MAX_BODIES, prec)
+    ws = workspace(wsz, p.device)
+    ms = c_double(0.0)
+    _check(lib.mfp_element_apply(byref(g), _ptr(disp), _ptr(body), prec, _ptr(p), _ptr(q),
+                                 int(repeat), byref(ms), _ptr(ws), ws.numel(), _stream()))
+    return q, ms.value
+
+
+@dataclass
+class SolveResult:
+    psi: torch.Tensor
+    psi_b: list
+    Q: float
+    copfi: float
+    theta: torch.Tensor
+    ut: torch.Tensor
+    sample_body: torch.Tensor
+    n_samples: int
+    stats: dict
+    status: int
+
+
+def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1e-12,
+              kmax=10 ** 7, check_every=64, inner_rtol=1e-4, max_outer=100, pair=(-1, -1),
+              sample_cap=None, ws: Optional[torch.Tensor] = None,
+              allow_warn: bool = True, profile_every: int = 0) -> SolveResult:
+    lib = load()
+    g = make_grid(grid)
+    c = make_circles(circles)
+    nb = len(circles)
+    f = make_flow(flow)
+    prec = _PREC[precision]
+    o = MfpSolverOpts(prec, float(rtol), int(kmax), int(check_every), float(inner_rtol),
+                      int(max_outer), None, int(profile_every))
+    n = (g.nx + 1) * (g.ny + 1)
+    dev = disp.device
+    psi = torch.empty(n, dtype=torch.float64, device=dev)
+    if sample_cap is None:
+        sample_cap = 64 * (g.nx + g.ny) if nb else 0
+    samples = torch.empty(max(2 * sample_cap, 2), dtype=torch.float64, device=dev)
+    sbody = torch.empty(max(sample_cap, 1), dtype=torch.int8, device=dev)
+    psib = (c_double * max(nb, 1))()
+    Q = c_double(float("nan"))
+    cop = c_double(float("nan"))
+    ns = c_int32(0)
+    st = MfpStats()
+    if ws is None:
+        ws = workspace(lib.mfp_solve_workspace_size(byref(g), nb, prec), dev)
+    status = _check(lib.mfp_psi_solve(
+        byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o),
+        int(pair[0]), int(pair[1]), _ptr(psi), psib, byref(Q), byref(cop), _ptr(samples),
+        _ptr(sbody), int(sample_cap), byref(ns), byref(st), _ptr(ws), ws.numel(), _stream()),
+        allow_warn)
+    m = min(ns.value, sample_cap)
+    stats = {k: getattr(st, k) for k, _ in MfpStats._fields_}
+    return SolveResult(psi, [psib[k] for k in range(nb)], Q.value, cop.value,
+                       samples[0:2 * m:2], samples[1:2 * m:2], sbody[:m], ns.value, stats,
+                       status)
+
+
+def solve_workspace_size(grid, nbody: int, precision: str = "fp64") -> int:
+    g = make_grid(grid)
+    return load().mfp_solve_workspace_size(byref(g), int(nbody), _PREC[precision])

@@ -1,0 +1,272 @@
+// Body-conforming mesh on the GPU (section "Body-Conforming Grid Generation").
+//
+//   k_classify      node -> body id by the FP64 test (x-cx)^2 + (y-cy)^2 <= r^2
+//   k_snap          body nodes with a fluid node among their eight neighbours are
+//                   moved radially onto their circle (d_ik = x_ik - x_gk); others deep
+//   k_jacobi_sweep  one Jacobi sweep d <- wx (d_E + d_W) + wy (d_N + d_S) of the
+//                   displacement Laplace problem on fluid nodes off the outer boundary
+//   k_tangle        Gauss-point Jacobian determinants of active cells must be > 0
+//
+// Every floating-point expression here is evaluated without contraction into fused
+// multiply-adds, so the mesh is reproducible bit for bit and equals a plain IEEE
+// evaluation of the same expressions in the same order.  Sweep k only touches the
+// node box around the circles widened by k + 2 nodes: a Jacobi sweep moves
+// information by one node per sweep, so every node outside that box still holds its
+// initial value (zero), exactly as if the whole grid had been swept.
+#include <cmath>
+
+#include "mfp_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace mfp {
+
+struct GridD {
+  int nx, ny;
+  double x0, y0, hx, hy;
+};
+
+__global__ void k_classify(GridD g, const mfp_circle* __restrict__ circ, int nb,
+                           int8_t* __restrict__ kind, int8_t* __restrict__ body) {
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(n / (g.nx + 1));
+    const int i = (int)(n - (long long)j * (g.nx + 1));
+    const double x = g.x0 + (double)i * g.hx;
+    const double y = g.y0 + (double)j * g.hy;
+    int b_in = -1;
+    for (int b = 0; b < nb; ++b) {
+      const double dx = x - circ[b].cx;
+      const double dy = y - circ[b].cy;
+      if (dx * dx + dy * dy <= circ[b].r * circ[b].r) b_in = b;
+    }
+    body[n] = (int8_t)b_in;
+    kind[n] = MFP_FLUID;
+  }
+}
+
+__global__ void k_snap(GridD g, const mfp_circle* __restrict__ circ,
+                       int8_t* __restrict__ kind, const int8_t* __restrict__ body,
+                       double* __restrict__ disp) {
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int b = body[n];
+    double ddx = 0.0, ddy = 0.0;
+    if (b >= 0) {
+      const int j = (int)(n / (g.nx + 1));
+      const int i = (int)(n - (long long)j * (g.nx + 1));
+      bool near_fluid = false;
+      for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+          const int ii = i + di, jj = j + dj;
+          if (ii >= 0 && ii <= g.nx && jj >= 0 && jj <= g.ny &&
+              body[(long long)jj * (g.nx + 1) + ii] < 0)
+            near_fluid = true;
+        }
+      kind[n] = near_fluid ? MFP_SNAPPED : MFP_DEEP;
+      if (near_fluid) {
+        const double x = g.x0 + (double)i * g.hx;
+        const double y = g.y0 + (double)j * g.hy;
+        const double cx = circ[b].cx, cy = circ[b].cy, r = circ[b].r;
+        const double dx = x - cx;
+        const double dy = y - cy;
+        const double rho = __builtin_sqrt(dx * dx + dy * dy);
+        const double s = r / rho;
+        const double px = cx + s * dx;
+        const double py = cy + s * dy;
+        ddx = px - x;
+        ddy = py - y;
+      }
+    }
+    disp[n] = ddx;
+    disp[n + nn] = ddy;
+  }
+}
+
+// One sweep over the box [i0,i1] x [j0,j1] (interior nodes only).
+__global__ void k_jacobi_sweep(int nx, int ny, int i0, int j0, int bw, int bh, double wx,
+                               double wy, const int8_t* __restrict__ kind,
+                               const double* __restrict__ src, double* __restrict__ dst) {
+  const long long nn = (long long)(nx + 1) * (ny + 1);
+  const int i = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int j = j0 + (int)blockIdx.y;
+  if (i >= i0 + bw || (int)blockIdx.y >= bh) return;
+  const long long n = (long long)j * (nx + 1) + i;
+  const double* sx = src;
+  const double* sy = src + nn;
+  if (kind[n] == MFP_FLUID) {
+    const long long e = n + 1, w = n - 1, no = n + (nx + 1), so = n - (nx + 1);
+    dst[n] = wx * (sx[e] + sx[w]) + wy * (sx[no] + sx[so]);
+    dst[n + nn] = wx * (sy[e] + sy[w]) + wy * (sy[no] + sy[so]);
+  } else {
+    dst[n] = sx[n];
+    dst[n + nn] = sy[n];
+  }
+}
+
+// Jacobian determinants at the four Gauss points of every active cell in the box.
+__global__ void k_tangle(GridD g, int ci0, int cj0, int bw, int bh,
+                         const int8_t* __restrict__ body, const double* __restrict__ disp,
+                         int* __restrict__ bad) {
+  const int ci = ci0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int cj = cj0 + (int)blockIdx.y;
+  if (ci >= ci0 + bw || (int)blockIdx.y >= bh) return;
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  const long long n0 = (long long)cj * (g.nx + 1) + ci;
+  const long long nd[4] = {n0, n0 + 1, n0 + g.nx + 2, n0 + g.nx + 1};
+  const int b0 = body[nd[0]];
+  if (b0 >= 0 && body[nd[1]] == b0 && body[nd[2]] == b0 && body[nd[3]] == b0) return;
+  const double bx[4] = {0.0, g.hx, g.hx, 0.0}, by[4] = {0.0, 0.0, g.hy, g.hy};
+  double x[4], y[4];
+  for (int a = 0; a < 4; ++a) {
+    x[a] = bx[a] + disp[nd[a]];
+    y[a] = by[a] + disp[nd[a] + nn];
+  }
+  const double s = 0.57735026918962576451;
+  const double xi_a[4] = {-1, 1, 1, -1}, eta_a[4] = {-1, -1, 1, 1};
+  for (int q = 0; q < 4; ++q) {
+    const double xi = xi_a[q] * s, eta = eta_a[q] * s;
+    double j11 = 0, j12 = 0, j21 = 0, j22 = 0;
+    for (int a = 0; a < 4; ++a) {
+      const double nxi = 0.25 * xi_a[a] * (1.0 + eta_a[a] * eta);
+      const double neta = 0.25 * eta_a[a] * (1.0 + xi_a[a] * xi);
+      j11 += nxi * x[a];
+      j12 += nxi * y[a];
+      j21 += neta * x[a];
+      j22 += neta * y[a];
+    }
+    if (!(j11 * j22 - j12 * j21 > 0.0)) atomicOr(bad, 1);
+  }
+}
+
+static GridD to_dev(const mfp_grid& g) {
+  return GridD{g.nx, g.ny, g.x0, g.y0, grid_hx(g), grid_hy(g)};
+}
+
+// Union of the circles' node boxes widened by `pad`, clipped to [lo, hi].
+static Box union_box(const mfp_grid& g, const mfp_circle* c, int nb, int pad, int ilo,
+                     int ihi, int jlo, int jhi) {
+  Box u{1, 0, 1, 0};
+  bool first = true;
+  for (int b = 0; b < nb; ++b) {
+    Box x = circle_box(g, c[b], pad, ilo, ihi, jlo, jhi);
+    if (x.empty()) continue;
+    if (first) {
+      u = x;
+      first = false;
+    } else {
+      u.i0 = x.i0 < u.i0 ? x.i0 : u.i0;
+      u.j0 = x.j0 < u.j0 ? x.j0 : u.j0;
+      u.i1 = x.i1 > u.i1 ? x.i1 : u.i1;
+      u.j1 = x.j1 > u.j1 ? x.j1 : u.j1;
+    }
+  }
+  return u;
+}
+
+struct ConformWs {
+  mfp_circle* circ;
+  double* tmp;  // second displacement buffer
+  int* flag;
+};
+
+static size_t conform_layout(const mfp_grid* g, int nb, void* ws, ConformWs* out) {
+  Bump bp(ws);
+  const size_t nn = (size_t)(g->nx + 1) * (g->ny + 1);
+  ConformWs w;
+  w.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
+  w.tmp = bp.take<double>(2 * nn);
+  w.flag = bp.take<int>(64);
+  if (out) *out = w;
+  return bp.off + 256;
+}
+
+}  // namespace mfp
+
+using namespace mfp;
+
+extern "C" size_t mfp_conform_workspace_size(const mfp_grid* grid, int32_t nbody) {
+  if (!grid || grid->nx < 2 || grid->ny < 2) return 0;
+  return conform_layout(grid, nbody, nullptr, nullptr);
+}
+
+extern "C" int mfp_mesh_conform(const mfp_grid* grid, const mfp_circle* circles_h,
+                                int32_t nbody, int32_t nsweeps, double* disp, int8_t* kind,
+                                int8_t* body, void* ws, size_t ws_bytes, void* stream_) {
+  clear_error();
+  MFP_TRY(check_geometry(grid, circles_h, nbody));
+  if (nsweeps < 0) {
+    set_error("nsweeps < 0");
+    return MFP_E_ARG;
+  }
+  if (!disp || !kind || !body || !ws) {
+    set_error("NULL output or workspace pointer");
+    return MFP_E_ARG;
+  }
+  const size_t need = conform_layout(grid, nbody, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  ConformWs w;
+  conform_layout(grid, nbody, ws, &w);
+  const mfp_grid& g = *grid;
+  const GridD gd = to_dev(g);
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  if (nbody > 0)
+    MFP_TRY_HIP(hipMemcpyAsync(w.circ, circles_h, sizeof(mfp_circle) * nbody,
+                               hipMemcpyHostToDevice, st));
+  MFP_TRY_HIP(hipMemsetAsync(w.flag, 0, sizeof(int), st));
+  const int nblk = (int)((nn + BLOCK - 1) / BLOCK < 65536 ? (nn + BLOCK - 1) / BLOCK : 65536);
+  k_classify<<<nblk, BLOCK, 0, st>>>(gd, w.circ, nbody, kind, body);
+  MFP_TRY_HIP(hipGetLastError());
+  k_snap<<<nblk, BLOCK, 0, st>>>(gd, w.circ, kind, body, disp);
+  MFP_TRY_HIP(hipGetLastError());
+
+  const double hx = gd.hx, hy = gd.hy;
+  const double s = 2.0 * (hx * hx + hy * hy);
+  const double wx = (hy * hy) / s, wy = (hx * hx) / s;
+  if (nsweeps > 0 && nbody > 0) {
+    MFP_TRY_HIP(hipMemcpyAsync(w.tmp, disp, sizeof(double) * 2 * nn,
+                               hipMemcpyDeviceToDevice, st));
+    double* a = disp;
+    double* b = w.tmp;
+    for (int k = 1; k <= nsweeps; ++k) {
+      const Box bx = union_box(g, circles_h, nbody, k + 1, 1, g.nx - 1, 1, g.ny - 1);
+      if (!bx.empty()) {
+        const int bw = bx.i1 - bx.i0 + 1, bh = bx.j1 - bx.j0 + 1;
+        dim3 grd((bw + BLOCK - 1) / BLOCK, bh);
+        k_jacobi_sweep<<<grd, BLOCK, 0, st>>>(g.nx, g.ny, bx.i0, bx.j0, bw, bh, wx, wy,
+                                              kind, a, b);
+        MFP_TRY_HIP(hipGetLastError());
+      }
+      double* t = a;
+      a = b;
+      b = t;
+    }
+    if (a != disp)
+      MFP_TRY_HIP(hipMemcpyAsync(disp, a, sizeof(double) * 2 * nn,
+                                 hipMemcpyDeviceToDevice, st));
+  }
+  if (nbody > 0) {
+    // cells whose nodes may have moved: the sweep box plus one cell
+    const Box cb = union_box(g, circles_h, nbody, nsweeps + 3, 0, g.nx - 1, 0, g.ny - 1);
+    if (!cb.empty()) {
+      const int bw = cb.i1 - cb.i0 + 1, bh = cb.j1 - cb.j0 + 1;
+      dim3 grd((bw + BLOCK - 1) / BLOCK, bh);
+      k_tangle<<<grd, BLOCK, 0, st>>>(gd, cb.i0, cb.j0, bw, bh, body, disp, w.flag);
+      MFP_TRY_HIP(hipGetLastError());
+    }
+  }
+  int bad = 0;
+  MFP_TRY_HIP(hipMemcpyAsync(&bad, w.flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  if (bad) {
+    set_error("tangled mesh: an active cell has a non-positive Jacobian determinant");
+    return MFP_E_TANGLED;
+  }
+  return MFP_OK;
+}

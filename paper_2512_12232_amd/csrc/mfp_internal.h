@@ -1,0 +1,117 @@
+// Internal definitions shared by the HIP sources of libmfpsi.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "mfpsi.h"
+
+namespace mfp {
+
+// ---- errors ---------------------------------------------------------------------
+void set_error(const char* fmt, ...);
+void clear_error();
+
+#define MFP_TRY_HIP(call)                                                        \
+  do {                                                                           \
+    hipError_t e_ = (call);                                                      \
+    if (e_ != hipSuccess) {                                                      \
+      ::mfp::set_error("%s failed: %s", #call, hipGetErrorString(e_));          \
+      return MFP_E_HIP;                                                          \
+    }                                                                            \
+  } while (0)
+
+#define MFP_TRY(expr)            \
+  do {                           \
+    int s_ = (expr);             \
+    if (s_ < 0) return s_;       \
+  } while (0)
+
+// ---- geometry helpers (host) ------------------------------------------------------
+int check_grid(const mfp_grid* g);
+int check_geometry(const mfp_grid* g, const mfp_circle* c, int nb);
+inline double grid_hx(const mfp_grid& g) { return (g.x1 - g.x0) / g.nx; }
+inline double grid_hy(const mfp_grid& g) { return (g.y1 - g.y0) / g.ny; }
+
+// Inclusive node-index box covering circle b, expanded by `pad` nodes and clipped to
+// [lo, hi] in each direction.
+struct Box {
+  int i0, i1, j0, j1;
+  bool empty() const { return i1 < i0 || j1 < j0; }
+  long long count() const { return empty() ? 0 : (long long)(i1 - i0 + 1) * (j1 - j0 + 1); }
+};
+Box circle_box(const mfp_grid& g, const mfp_circle& c, int pad, int ilo, int ihi, int jlo,
+               int jhi);
+
+// ---- workspace bump allocator ----------------------------------------------------
+struct Bump {
+  char* base;     // may be nullptr when only measuring
+  size_t off = 0;
+  explicit Bump(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += n * sizeof(T);
+    return p;
+  }
+};
+
+// ---- padded node layout used by the solver ----------------------------------------
+// Node (i, j) of the (nx+1) x (ny+1) grid lives at index (j+1)*P + (i+1); a ring of
+// halo nodes (tag TAG_HALO, zero values) surrounds the domain and the pitch P is a
+// multiple of 64 so that each tile row starts on a 512-byte boundary.
+constexpr int TX = 64;        // tile width in nodes (one wavefront per row)
+constexpr int TY = 8;         // tile height in nodes
+constexpr int FW = TX + 2;    // footprint width (one halo column each side)
+constexpr int FH = TY + 2;    // footprint height
+constexpr int CW = TX + 1;    // cells touching a tile, per row
+constexpr int CH = TY + 1;    // rows of cells touching a tile
+constexpr int BLOCK = 256;
+
+struct Layout {
+  int nx, ny;     // cells
+  int ntx, nty;   // tiles
+  int P;          // pitch (nodes per padded row)
+  int rows;       // padded rows
+  long long n;    // P * rows
+  int ntiles() const { return ntx * nty; }
+};
+
+inline Layout make_layout(int nx, int ny) {
+  Layout L;
+  L.nx = nx;
+  L.ny = ny;
+  L.ntx = (nx + 1 + TX - 1) / TX;
+  L.nty = (ny + 1 + TY - 1) / TY;
+  L.P = TX * (L.ntx + 1);
+  L.rows = TY * L.nty + 2;
+  L.n = (long long)L.P * L.rows;
+  return L;
+}
+
+// Internal node tags.
+enum : int8_t { TAG_FREE = 0, TAG_DIR = 1, TAG_HALO = 2, TAG_BODY0 = 3 };
+
+// Device-resident solver scalars.  Quantities that a kernel reads for iteration k
+// while its block 0 writes the value for the next iteration are double-buffered by
+// iteration parity, so no kernel reads a slot that the same launch writes.
+struct DevState {
+  double rr[2];                          // r.r of iterate k in slot k&1
+  double rb_rr[2];                       // body part of r.r of iterate k in slot k&1
+  double pb[2][MFP_MAX_BODIES];          // body directions p_b of iteration k, slot k&1
+  double xb[2][MFP_MAX_BODIES];          // body unknowns of iterate k, slot k&1
+  double rb[2][MFP_MAX_BODIES];          // body residuals of iterate k, slot k&1
+  double qb[MFP_MAX_BODIES];             // body sums of the last plain apply
+  double rr0, rr_stop, rr_final, rr_true;
+  double alpha, beta, pq;
+  double copfi, Q;
+  long long iters;                       // index of the final iterate once done != 0
+  long long kmax;
+  int done;                              // 0 running, 1 converged, 2 breakdown, 3 kmax
+  int pad_;
+};
+
+}  // namespace mfp

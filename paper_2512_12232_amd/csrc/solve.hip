@@ -1,0 +1,955 @@
+// Constrained stream-function solve: setup, conjugate-gradient kernels and the
+// host drivers of mfp_psi_solve and mfp_element_apply.
+//
+// Unknowns (section "Matrix-Free Conjugate Gradient with Multiple Constraint
+// Enforcement"): free nodes plus one value psi_b per body, N_dof = N_int + N_N + N_b.
+// The solver keeps full padded node vectors.  Free nodes hold their own entries;
+// every node of body b stands for the single unknown psi_b (its direction value is
+// p_b, its residual lives in rb[b]); Dirichlet and halo nodes hold zero.  Then
+//   (A p)_free = (K p)_free and (A p)_b = sum over the nodes of body b of (K p)_n,
+// which is Algorithm 1's assembly of element results into r (interior nodes) and rb
+// (body DOFs), and p.Ap = sum_free p (Kp) + sum_b p_b (Ap)_b.
+// One CG iteration is two kernels:
+//   k_apply<FUSED>  p = r + beta p_old (body nodes p_b), q = K p, partial p.q;
+//                   the last block finishes p.Ap, alpha and the body unknowns;
+//   k_update        x += alpha p, r -= alpha q, partial r.r; the last block finishes
+//                   r.r, beta, the convergence test and p_b = rb + beta p_b.
+// Scalars never leave the device; the host polls a done flag every few iterations.
+#include <cmath>
+#include <cstring>
+#include <type_traits>
+#include <vector>
+
+#include "apply.h"
+
+namespace mfp {
+
+struct SetupArgs {
+  Layout L;
+  int nx, ny;
+  double x0, y0, hx, hy, inv_hx;
+  double U;
+  int bc[4];
+  double c0x, c0y, c0r;          // circle 0 (cylinder boundary data)
+  const double* disp;            // caller displacement (unpadded)
+  const int8_t* kind;
+  const int8_t* body;
+  int8_t* tag;
+  double* dx;
+  double* dy;
+  float* dxf;
+  float* dyf;
+  double* g;
+  double* x;
+  double* r;
+  double* p0;
+  double* p1;
+  double* q;
+  long long* nfree;
+};
+
+__device__ double side_value(int code, double x, double y, const SetupArgs& a) {
+  if (code == MFP_BC_DIRICHLET_UY) return a.U * y;
+  if (code == MFP_BC_DIRICHLET_CYL) {
+    const double dx = x - a.c0x, dy = y - a.c0y;
+    const double rho2 = dx * dx + dy * dy;
+    return a.U * dy * (1.0 - a.c0r * a.c0r / rho2);
+  }
+  return 0.0;
+}
+
+__global__ void k_setup(SetupArgs a) {
+  const long long n = a.L.n;
+  long long cnt = 0;
+  const long long nn = (long long)(a.nx + 1) * (a.ny + 1);
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int row = (int)(e / a.L.P), col = (int)(e - (long long)row * a.L.P);
+    const int i = col - 1, j = row - 1;
+    int8_t tg = TAG_HALO;
+    double dxv = 0.0, dyv = 0.0, gv = 0.0;
+    if (i >= 0 && i <= a.nx && j >= 0 && j <= a.ny) {
+      const long long nd = (long long)j * (a.nx + 1) + i;
+      const int b = a.body ? a.body[nd] : -1;
+      const bool left = i == 0 && a.bc[0] != MFP_BC_NATURAL;
+      const bool right = i == a.nx && a.bc[1] != MFP_BC_NATURAL;
+      const bool bot = j == 0 && a.bc[2] != MFP_BC_NATURAL;
+      const bool top = j == a.ny && a.bc[3] != MFP_BC_NATURAL;
+      if (b >= 0) {
+        tg = (int8_t)(TAG_BODY0 + b);
+      } else if (left || right || bot || top) {
+        tg = TAG_DIR;
+        const double x = a.x0 + (double)i * a.hx, y = a.y0 + (double)j * a.hy;
+        const int code = bot ? a.bc[2] : top ? a.bc[3] : left ? a.bc[0] : a.bc[1];
+        gv = side_value(code, x, y, a);
+      } else {
+        tg = TAG_FREE;
+        ++cnt;
+      }
+      if (a.disp) {
+        dxv = a.disp[nd] * a.inv_hx;
+        dyv = a.disp[nd + nn] * a.inv_hx;
+      }
+    }
+    a.tag[e] = tg;
+    a.dx[e] = dxv;
+    a.dy[e] = dyv;
+    if (a.dxf) {
+      a.dxf[e] = (float)dxv;
+      a.dyf[e] = (float)dyv;
+    }
+    if (a.g) a.g[e] = gv;
+    if (a.x) a.x[e] = 0.0;
+    if (a.r) a.r[e] = 0.0;
+    if (a.p0) a.p0[e] = 0.0;
+    if (a.p1) a.p1[e] = 0.0;
+    if (a.q) a.q[e] = 0.0;
+  }
+  if (a.nfree && cnt) atomicAdd((unsigned long long*)a.nfree, (unsigned long long)cnt);
+}
+
+// Per tile: constant-stencil flag (footprint all free and undisplaced) and the set
+// of bodies among the tile's own nodes.  One block per tile.
+__global__ void k_tile_meta(Layout L, const int8_t* __restrict__ tag,
+                            const double* __restrict__ dx, const double* __restrict__ dy,
+                            uint8_t* __restrict__ tplain, unsigned long long* __restrict__ tbody) {
+  const int t = blockIdx.x;
+  const int ty = t / L.ntx, tx = t - ty * L.ntx;
+  const long long base = (long long)(ty * TY) * L.P + tx * TX;
+  int plain = 1;
+  unsigned long long bm = 0;
+  for (int e = threadIdx.x; e < FH * FW; e += BLOCK) {
+    const int fr = e / FW, fc = e - fr * FW;
+    const long long gi = base + (long long)fr * L.P + fc;
+    const int8_t tg = tag[gi];
+    if (tg != TAG_FREE || dx[gi] != 0.0 || dy[gi] != 0.0) plain = 0;
+    if (fr >= 1 && fr <= TY && fc >= 1 && fc <= TX && tg >= TAG_BODY0)
+      bm |= 1ull << (tg - TAG_BODY0);
+  }
+  plain = __syncthreads_and(plain);
+  __shared__ unsigned long long s_bm[BLOCK / 64];
+  for (int off = 32; off > 0; off >>= 1) bm |= __shfl_xor(bm, off, 64);
+  if ((threadIdx.x & 63) == 0) s_bm[threadIdx.x >> 6] = bm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    tplain[t] = (uint8_t)plain;
+    tbody[t] = s_bm[0] | s_bm[1] | s_bm[2] | s_bm[3];
+  }
+}
+
+// Slots for tiles that own body nodes, numbered in tile order (single block).
+__global__ void k_assign_slots(int ntiles, const unsigned long long* __restrict__ tbody,
+                               int* __restrict__ tslot, int* __restrict__ nslots) {
+  __shared__ int s_scan[BLOCK];
+  __shared__ int s_base;
+  if (threadIdx.x == 0) s_base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < ntiles; c0 += BLOCK) {
+    const int t = c0 + threadIdx.x;
+    const int f = (t < ntiles && tbody[t] != 0ull) ? 1 : 0;
+    s_scan[threadIdx.x] = f;
+    __syncthreads();
+    for (int off = 1; off < BLOCK; off <<= 1) {
+      const int v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      s_scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (t < ntiles) tslot[t] = f ? s_base + s_scan[threadIdx.x] - 1 : -1;
+    __syncthreads();
+    if (threadIdx.x == BLOCK - 1) s_base += s_scan[BLOCK - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *nslots = s_base;
+}
+
+// w = g + T x as a full nodal vector (free: x, Dirichlet: g, body b: psi_b of the
+// current iterate).
+template <typename T>
+__global__ void k_form_w(long long n, const int8_t* __restrict__ tag,
+                         const double* __restrict__ x, const double* __restrict__ g,
+                         const DevState* __restrict__ st, T* __restrict__ w) {
+  const double* xb = st->xb[st->iters & 1];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int8_t tg = tag[e];
+    double v = 0.0;
+    if (tg == TAG_FREE)
+      v = x[e];
+    else if (tg == TAG_DIR)
+      v = g[e];
+    else if (tg >= TAG_BODY0)
+      v = xb[tg - TAG_BODY0];
+    w[e] = (T)v;
+  }
+}
+
+// r = -q at free nodes (q is zero elsewhere) when write_r; per-block partials of q.q.
+__global__ void __launch_bounds__(BLOCK) k_resid(long long n, const double* __restrict__ q,
+                                                 double* __restrict__ r, double* __restrict__ part,
+                                                 int write_r) {
+  __shared__ double s_red[BLOCK / 64];
+  double acc = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const double v = q[e];
+    if (write_r) r[e] = -v;
+    acc += v * v;
+  }
+  const double bs = block_sum(acc, s_red);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// Single block.  Body sums of the last plain apply, then
+// mode 0: initial CG state for x = 0 (rb = -qb, r.r, stopping threshold, p_b = 0 and
+//         r.r = 1 in the "previous" slot so that the first beta multiplies zeros);
+// mode 1: squared norm of the recomputed true residual.
+__global__ void __launch_bounds__(BLOCK) k_resid_finalize(const double* __restrict__ part,
+                                                          int G2, const double* __restrict__ bpart,
+                                                          const int* __restrict__ nslots,
+                                                          DevState* st, int nb, int mode,
+                                                          double rtol2) {
+  __shared__ double s_red[BLOCK / 64];
+  __shared__ double s_qb[MFP_MAX_BODIES];
+  body_sums(bpart, *nslots, nb, s_qb);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < G2; i += BLOCK) s += part[i];
+  s = block_sum(s, s_red);
+  if (threadIdx.x == 0) {
+    double rbr = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      st->qb[b] = s_qb[b];
+      rbr += s_qb[b] * s_qb[b];
+    }
+    if (mode == 0) {
+      for (int b = 0; b < nb; ++b) {
+        st->rb[0][b] = -s_qb[b];
+        st->pb[1][b] = 0.0;
+      }
+      st->rb_rr[0] = rbr;
+      st->rr[1] = 1.0;
+      st->rr0 = s + rbr;
+      st->rr_stop = rtol2 * (s + rbr);
+      st->iters = 0;
+      st->done = 0;
+    } else {
+      st->rr_true = s + rbr;
+    }
+  }
+}
+
+// Second half of CG iteration k: every block sums the apply's body slots and p.q
+// partials itself, forms alpha = r.r / p.Ap (breakdown stops the solve), block 0
+// advances the body unknowns, and all blocks stream x += alpha p, r -= alpha q with
+// per-block partials of the new r.r.  Two elements per thread and step.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_update(long long n, T* __restrict__ x,
+                                                  const T* __restrict__ p, T* __restrict__ r,
+                                                  const T* __restrict__ q,
+                                                  const double* __restrict__ part, int G,
+                                                  const double* __restrict__ bpart,
+                                                  const int* __restrict__ nslots,
+                                                  double* __restrict__ part2, DevState* st,
+                                                  int nb, long long k) {
+  using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
+  __shared__ double s_red[BLOCK / 64];
+  __shared__ double s_qb[MFP_MAX_BODIES];
+  if (st->done) return;
+  const long long n2 = n >> 1;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  T2* x2 = reinterpret_cast<T2*>(x);
+  T2* r2 = reinterpret_cast<T2*>(r);
+  const T2* p2 = reinterpret_cast<const T2*>(p);
+  const T2* q2 = reinterpret_cast<const T2*>(q);
+  // first operands in flight while the scalars are formed
+  T2 xv{}, pv{}, rv{}, qv{};
+  if (e < n2) {
+    xv = x2[e];
+    pv = p2[e];
+    rv = r2[e];
+    qv = q2[e];
+  }
+  const int cur = (int)(k & 1), nxt = cur ^ 1;
+  body_sums(bpart, *nslots, nb, s_qb);
+  double s = 0.0;
+  for (int i = threadIdx.x; i < G; i += BLOCK) s += part[i];
+  double pq = block_sum(s, s_red);
+  for (int b = 0; b < nb; ++b) pq += st->pb[cur][b] * s_qb[b];
+  if (!(pq > 0.0) || !isfinite(pq)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st->done = 2;
+      st->iters = k;
+      st->pq = pq;
+    }
+    return;
+  }
+  const double alpha_d = st->rr[cur] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double rbr = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      st->xb[nxt][b] = st->xb[cur][b] + alpha_d * st->pb[cur][b];
+      const double rbn = st->rb[cur][b] - alpha_d * s_qb[b];
+      st->rb[nxt][b] = rbn;
+      rbr += rbn * rbn;
+    }
+    st->rb_rr[nxt] = rbr;
+    st->alpha = alpha_d;
+    st->pq = pq;
+  }
+  const T alpha = (T)alpha_d;
+  double acc = 0.0;
+  for (; e < n2; e += stride) {
+    const long long en = e + stride;
+    T2 xn{}, pn{}, rn{}, qn{};
+    if (en < n2) {
+      xn = x2[en];
+      pn = p2[en];
+      rn = r2[en];
+      qn = q2[en];
+    }
+    T2 ro, xo;
+    ro.x = rv.x - alpha * qv.x;
+    ro.y = rv.y - alpha * qv.y;
+    xo.x = xv.x + alpha * pv.x;
+    xo.y = xv.y + alpha * pv.y;
+    x2[e] = xo;
+    r2[e] = ro;
+    acc += (double)ro.x * (double)ro.x + (double)ro.y * (double)ro.y;
+    xv = xn;
+    pv = pn;
+    rv = rn;
+    qv = qn;
+  }
+  const double bs = block_sum(acc, s_red);
+  if (threadIdx.x == 0) part2[blockIdx.x] = bs;
+}
+
+// psi (unpadded) from the padded unknowns; Q and CoPFI from the pair.
+__global__ void k_output(Layout L, int nx, int ny, const int8_t* __restrict__ tag,
+                         const double* __restrict__ x, const double* __restrict__ g,
+                         DevState* st, double* __restrict__ psi, int lo, int hi, double U,
+                         double ylo, double yhi) {
+  const long long nn = (long long)(nx + 1) * (ny + 1);
+  const double* xb = st->xb[st->iters & 1];
+  for (long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x; nd < nn;
+       nd += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(nd / (nx + 1)), i = (int)(nd - (long long)j * (nx + 1));
+    const long long e = (long long)(j + 1) * L.P + (i + 1);
+    const int8_t tg = tag[e];
+    psi[nd] = tg == TAG_FREE ? x[e] : tg == TAG_DIR ? g[e] : xb[tg - TAG_BODY0];
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && lo >= 0 && hi >= 0) {
+    st->Q = xb[hi] - xb[lo];
+    st->copfi = st->Q / (U * (yhi - ylo));
+  }
+}
+
+// Surface tangential velocity samples (section "Velocity Field and Surface
+// Tangential Velocity"): u_t = (psi_c - psi_b) / d_nc on each edge joining two nodes
+// snapped to the same body, in every active cell with a fluid node.  psi_c is the mean
+// nodal psi of the cell, d_nc the distance from the mean of its displaced nodes to the
+// line through the edge, theta the polar angle of the edge midpoint.  One block walks
+// the bodies in order and each body's cell box in cell-id order, so the output order
+// is (body, cell, local edge).
+struct SampleArgs {
+  int nx, ny, nb;
+  double x0, y0, hx, hy, hmax;
+  const mfp_circle* circ;
+  const int* boxes;  // per body: ci0, ci1, cj0, cj1 (cells)
+  const double* disp;
+  const int8_t* kind;
+  const int8_t* body;
+  const double* psi;
+  const DevState* st;
+  double* samples;
+  int8_t* sbody;
+  int cap;
+  int* count;
+};
+
+__global__ void __launch_bounds__(BLOCK) k_samples(SampleArgs a) {
+  __shared__ int s_scan[BLOCK];
+  __shared__ int s_base;
+  if (threadIdx.x == 0) s_base = 0;
+  __syncthreads();
+  const long long nn = (long long)(a.nx + 1) * (a.ny + 1);
+  for (int b = 0; b < a.nb; ++b) {
+    const int ci0 = a.boxes[4 * b], ci1 = a.boxes[4 * b + 1];
+    const int cj0 = a.boxes[4 * b + 2], cj1 = a.boxes[4 * b + 3];
+    const int bw = ci1 - ci0 + 1;
+    const long long total = (ci1 >= ci0 && cj1 >= cj0) ? (long long)bw * (cj1 - cj0 + 1) : 0;
+    const double cxb = a.circ[b].cx, cyb = a.circ[b].cy;
+    const double psib = a.st->xb[a.st->iters & 1][b];
+    for (long long c0 = 0; c0 < total; c0 += BLOCK) {
+      const long long c = c0 + threadIdx.x;
+      int cnt = 0;
+      double th[4], ut[4];
+      if (c < total) {
+        const int ci = ci0 + (int)(c % bw), cj = cj0 + (int)(c / bw);
+        const long long n0 = (long long)cj * (a.nx + 1) + ci;
+        const long long nd[4] = {n0, n0 + 1, n0 + a.nx + 2, n0 + a.nx + 1};
+        const int bb0 = a.body[nd[0]];
+        const bool inside = bb0 >= 0 && a.body[nd[1]] == bb0 && a.body[nd[2]] == bb0 &&
+                            a.body[nd[3]] == bb0;
+        bool fluid = false;
+        for (int k = 0; k < 4; ++k) fluid |= a.kind[nd[k]] == MFP_FLUID;
+        if (!inside && fluid) {
+          double X[4], Y[4], ps[4];
+          const int oi[4] = {0, 1, 1, 0}, oj[4] = {0, 0, 1, 1};
+          for (int k = 0; k < 4; ++k) {
+            X[k] = a.x0 + (double)(ci + oi[k]) * a.hx + a.disp[nd[k]];
+            Y[k] = a.y0 + (double)(cj + oj[k]) * a.hy + a.disp[nd[k] + nn];
+            ps[k] = a.psi[nd[k]];
+          }
+          const double gx = 0.25 * ((X[0] + X[1]) + (X[2] + X[3]));
+          const double gy = 0.25 * ((Y[0] + Y[1]) + (Y[2] + Y[3]));
+          const double psic = 0.25 * ((ps[0] + ps[1]) + (ps[2] + ps[3]));
+          for (int k = 0; k < 4; ++k) {
+            const int k2 = (k + 1) & 3;
+            if (a.kind[nd[k]] == MFP_SNAPPED && a.kind[nd[k2]] == MFP_SNAPPED &&
+                a.body[nd[k]] == b && a.body[nd[k2]] == b) {
+              const double ex = X[k2] - X[k], ey = Y[k2] - Y[k];
+              const double len = sqrt(ex * ex + ey * ey);
+              if (len > 1e-12 * a.hmax) {
+                const double dnc = fabs(ex * (gy - Y[k]) - ey * (gx - X[k])) / len;
+                const double mx = 0.5 * (X[k] + X[k2]), my = 0.5 * (Y[k] + Y[k2]);
+                th[cnt] = atan2(my - cyb, mx - cxb);
+                ut[cnt] = (psic - psib) / dnc;
+                ++cnt;
+              }
+            }
+          }
+        }
+      }
+      s_scan[threadIdx.x] = cnt;
+      __syncthreads();
+      for (int off = 1; off < BLOCK; off <<= 1) {
+        const int v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
+        __syncthreads();
+        s_scan[threadIdx.x] += v;
+        __syncthreads();
+      }
+      const int start = s_base + s_scan[threadIdx.x] - cnt;
+      for (int k = 0; k < cnt; ++k) {
+        const int o = start + k;
+        if (o < a.cap) {
+          a.samples[2 * o] = th[k];
+          a.samples[2 * o + 1] = ut[k];
+          a.sbody[o] = (int8_t)b;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x == BLOCK - 1) s_base += s_scan[BLOCK - 1];
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x == 0) *a.count = s_base;
+}
+
+// ---------------------------------------------------------------------------------
+// Workspace and host driver
+// ---------------------------------------------------------------------------------
+constexpr int GMAX = 2048;  // max blocks of the reduction kernels
+
+struct SolveWs {
+  Layout L;
+  int8_t* tag;
+  double *dx, *dy, *g, *x, *r, *p0, *p1, *q;
+  float *dxf, *dyf, *xf, *rf, *p0f, *p1f, *qf;
+  uint8_t* tplain;
+  unsigned long long* tbody;
+  int* tslot;
+  int* nslots;
+  double* part;
+  double* part2;
+  double* bpart;
+  DevState* st;
+  long long* nfree;
+  mfp_circle* circ;
+  int* boxes;
+  int* count;
+};
+
+static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base, SolveWs* out) {
+  Bump bp(base);
+  SolveWs w{};
+  w.L = make_layout(g->nx, g->ny);
+  const size_t n = (size_t)w.L.n;
+  const int nt = w.L.ntiles();
+  w.tag = bp.take<int8_t>(n);
+  w.dx = bp.take<double>(n);
+  w.dy = bp.take<double>(n);
+  w.g = bp.take<double>(n);
+  w.x = bp.take<double>(n);
+  w.r = bp.take<double>(n);
+  w.p0 = bp.take<double>(n);
+  w.p1 = bp.take<double>(n);
+  w.q = bp.take<double>(n);
+  if (precision != MFP_FP64) {
+    w.dxf = bp.take<float>(n);
+    w.dyf = bp.take<float>(n);
+    w.xf = bp.take<float>(n);
+    w.rf = bp.take<float>(n);
+    w.p0f = bp.take<float>(n);
+    w.p1f = bp.take<float>(n);
+    w.qf = bp.take<float>(n);
+  }
+  w.tplain = bp.take<uint8_t>(nt);
+  w.tbody = bp.take<unsigned long long>(nt);
+  w.tslot = bp.take<int>(nt);
+  w.nslots = bp.take<int>(1);
+  w.part = bp.take<double>(GMAX);
+  w.part2 = bp.take<double>(GMAX);
+  w.bpart = bp.take<double>((size_t)nt * (nb > 0 ? nb : 1));
+  w.st = bp.take<DevState>(1);
+  w.nfree = bp.take<long long>(1);
+  w.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
+  w.boxes = bp.take<int>(4 * (nb > 0 ? nb : 1));
+  w.count = bp.take<int>(1);
+  if (out) *out = w;
+  return bp.off + 256;
+}
+
+// Streaming kernels: about 8 elements per thread, at most 1024 blocks, so that the
+// next kernel's per-block reduction of these partials stays small.
+static int grid_blocks(long long n) {
+  long long b = (n + 8 * BLOCK - 1) / (8 * BLOCK);
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+// Apply: tiles per block chosen so that at most ~1024 blocks run; block count a
+// multiple of 8 (XCD-aware tile order).
+static int apply_blocks(int ntiles, int* tpb) {
+  int t = (ntiles + 1023) / 1024;
+  if (t < 1) t = 1;
+  int g = (ntiles + t - 1) / t;
+  g = (g + 7) & ~7;
+  *tpb = t;
+  return g;
+}
+
+template <typename T>
+static ApplyArgs<T> make_apply_args(const SolveWs& w, const mfp_grid& g, int nb, const T* dx,
+                                    const T* dy) {
+  ApplyArgs<T> a{};
+  a.P = w.L.P;
+  a.ntx = w.L.ntx;
+  a.ntiles = w.L.ntiles();
+  apply_blocks(a.ntiles, &a.tpb);
+  a.tag = w.tag;
+  a.dx = dx;
+  a.dy = dy;
+  a.tplain = w.tplain;
+  a.tbody = w.tbody;
+  a.tslot = w.tslot;
+  a.part = w.part;
+  a.bpart = w.bpart;
+  a.st = w.st;
+  a.nb = nb;
+  const double hx = grid_hx(g), hy = grid_hy(g);
+  const double rr = hy / hx, qq = hx / hy;
+  a.cC = (T)(4.0 / 3.0 * (rr + qq));
+  a.cE = (T)(-2.0 / 3.0 * rr + qq / 3.0);
+  a.cN = (T)(-2.0 / 3.0 * qq + rr / 3.0);
+  a.cD = (T)(-(rr + qq) / 6.0);
+  a.ry = (T)rr;
+  return a;
+}
+
+// Common setup: tags, scaled displacements, lifting, tile metadata.
+static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const double* disp,
+                 const int8_t* body, const mfp_flow* flow, int precision, const SolveWs& w,
+                 hipStream_t st) {
+  SetupArgs s{};
+  s.L = w.L;
+  s.nx = g.nx;
+  s.ny = g.ny;
+  s.x0 = g.x0;
+  s.y0 = g.y0;
+  s.hx = grid_hx(g);
+  s.hy = grid_hy(g);
+  s.inv_hx = 1.0 / s.hx;
+  s.U = flow ? flow->U : 0.0;
+  for (int k = 0; k < 4; ++k) s.bc[k] = flow ? flow->side_bc[k] : MFP_BC_NATURAL;
+  if (nb > 0 && circles_h) {
+    s.c0x = circles_h[0].cx;
+    s.c0y = circles_h[0].cy;
+    s.c0r = circles_h[0].r;
+  }
+  s.disp = disp;
+  s.body = body;
+  s.tag = w.tag;
+  s.dx = w.dx;
+  s.dy = w.dy;
+  s.dxf = precision != MFP_FP64 ? w.dxf : nullptr;
+  s.dyf = precision != MFP_FP64 ? w.dyf : nullptr;
+  s.g = w.g;
+  s.x = w.x;
+  s.r = w.r;
+  s.p0 = w.p0;
+  s.p1 = w.p1;
+  s.q = w.q;
+  s.nfree = w.nfree;
+  MFP_TRY_HIP(hipMemsetAsync(w.st, 0, sizeof(DevState), st));
+  MFP_TRY_HIP(hipMemsetAsync(w.nfree, 0, sizeof(long long), st));
+  k_setup<<<grid_blocks(w.L.n), BLOCK, 0, st>>>(s);
+  MFP_TRY_HIP(hipGetLastError());
+  k_tile_meta<<<w.L.ntiles(), BLOCK, 0, st>>>(w.L, w.tag, w.dx, w.dy, w.tplain, w.tbody);
+  MFP_TRY_HIP(hipGetLastError());
+  k_assign_slots<<<1, BLOCK, 0, st>>>(w.L.ntiles(), w.tbody, w.tslot, w.nslots);
+  MFP_TRY_HIP(hipGetLastError());
+  return MFP_OK;
+}
+
+}  // namespace mfp
+
+using namespace mfp;
+
+extern "C" size_t mfp_solve_workspace_size(const mfp_grid* grid, int32_t nbody,
+                                           int32_t precision) {
+  if (!grid || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES) return 0;
+  return solve_layout(grid, nbody, precision, nullptr, nullptr);
+}
+
+extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
+                                 const int8_t* body, int32_t precision, const void* p,
+                                 void* q, int32_t repeat, double* apply_ms_h, void* ws,
+                                 size_t ws_bytes, void* stream_) {
+  clear_error();
+  MFP_TRY(check_grid(grid));
+  if (!disp || !body || !p || !q || !ws || repeat < 1) {
+    set_error("NULL pointer or repeat < 1");
+    return MFP_E_ARG;
+  }
+  if (precision != MFP_FP64 && precision != MFP_FP32) {
+    set_error("precision must be MFP_FP64 or MFP_FP32");
+    return MFP_E_ARG;
+  }
+  const int nbmax = MFP_MAX_BODIES;
+  const size_t need = solve_layout(grid, nbmax, precision, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  SolveWs w;
+  solve_layout(grid, nbmax, precision, ws, &w);
+  const mfp_grid& g = *grid;
+  MFP_TRY(setup(g, nullptr, nbmax, disp, body, nullptr, precision, w, st));
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  const size_t esz = precision == MFP_FP64 ? sizeof(double) : sizeof(float);
+  void* src = precision == MFP_FP64 ? (void*)w.p0 : (void*)w.p0f;
+  void* dst = precision == MFP_FP64 ? (void*)w.q : (void*)w.qf;
+  // scatter p into the padded layout row by row
+  MFP_TRY_HIP(hipMemsetAsync(src, 0, esz * w.L.n, st));
+  MFP_TRY_HIP(hipMemcpy2DAsync((char*)src + esz * (w.L.P + 1), esz * w.L.P, p,
+                               esz * (g.nx + 1), esz * (g.nx + 1), g.ny + 1,
+                               hipMemcpyDeviceToDevice, st));
+  int tpb;
+  const int G = apply_blocks(w.L.ntiles(), &tpb);
+  hipEvent_t e0, e1;
+  MFP_TRY_HIP(hipEventCreate(&e0));
+  MFP_TRY_HIP(hipEventCreate(&e1));
+  MFP_TRY_HIP(hipEventRecord(e0, st));
+  for (int k = 0; k < repeat; ++k) {
+    if (precision == MFP_FP64) {
+      ApplyArgs<double> a = make_apply_args<double>(w, g, nbmax, w.dx, w.dy);
+      a.src = w.p0;
+      a.q = w.q;
+      a.write_all = 1;
+      k_apply<double, false><<<G, BLOCK, 0, st>>>(a);
+    } else {
+      ApplyArgs<float> a = make_apply_args<float>(w, g, nbmax, w.dxf, w.dyf);
+      a.src = w.p0f;
+      a.q = w.qf;
+      a.write_all = 1;
+      k_apply<float, false><<<G, BLOCK, 0, st>>>(a);
+    }
+    hipError_t le = hipGetLastError();
+    if (le != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      set_error("apply launch: %s", hipGetErrorString(le));
+      return MFP_E_HIP;
+    }
+  }
+  MFP_TRY_HIP(hipEventRecord(e1, st));
+  MFP_TRY_HIP(hipMemcpy2DAsync(q, esz * (g.nx + 1), (char*)dst + esz * (w.L.P + 1),
+                               esz * w.L.P, esz * (g.nx + 1), g.ny + 1,
+                               hipMemcpyDeviceToDevice, st));
+  MFP_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  MFP_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (apply_ms_h) *apply_ms_h = ms / repeat;
+  (void)nn;
+  return MFP_OK;
+}
+
+// Host loop of plain CG in FP64 on the prepared workspace.  Kernels are enqueued in
+// batches of `check_every` iterations; once the device sets its done flag the
+// remaining launches of the batch return immediately.  Returns the done code.
+static int cg_fp64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver_opts& o,
+                   hipStream_t st, long long* iters_out, long long* applies, double* apply_ms,
+                   long long* apply_samples) {
+  int tpb;
+  const int G = apply_blocks(w.L.ntiles(), &tpb);
+  const int G2 = grid_blocks(w.L.n);
+  double* pbuf[2] = {w.p0, w.p1};
+  const int every = o.check_every > 0 ? o.check_every : 50;
+  const int prof = o.profile_every > 0 ? o.profile_every : 0;
+  // event pairs for the sampled apply launches of one batch
+  const int nev = prof ? (every + prof - 1) / prof : 0;
+  hipEvent_t ev[2 * 64];
+  const int nev_c = nev > 64 ? 64 : nev;
+  for (int i = 0; i < 2 * nev_c; ++i) MFP_TRY_HIP(hipEventCreate(&ev[i]));
+  double tsum = 0.0;
+  long long tcnt = 0;
+  long long k = 0;
+  struct {
+    int done;
+    long long iters;
+  } hs{0, 0};
+  ApplyArgs<double> a = make_apply_args<double>(w, g, nb, w.dx, w.dy);
+  a.r = w.r;
+  a.q = w.q;
+  a.part2 = w.part2;
+  a.G2 = G2;
+  int status = MFP_OK;
+  while (true) {
+    int used = 0;
+    for (int m = 0; m < every; ++m, ++k) {
+      a.src = pbuf[k & 1];
+      a.pnew = pbuf[(k + 1) & 1];
+      a.k = k;
+      const bool timed = prof && (m % prof == 0) && used < nev_c;
+      if (timed) hipEventRecord(ev[2 * used], st);
+      k_apply<double, true><<<G, BLOCK, 0, st>>>(a);
+      if (timed) hipEventRecord(ev[2 * used + 1], st), ++used;
+      k_update<double><<<G2, BLOCK, 0, st>>>(w.L.n, w.x, pbuf[(k + 1) & 1], w.r, w.q, w.part,
+                                             G, w.bpart, w.nslots, w.part2, w.st, nb, k);
+    }
+    hipError_t le = hipGetLastError();
+    if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &w.st->done, sizeof(int),
+                                              hipMemcpyDeviceToHost, st);
+    if (le == hipSuccess) le = hipMemcpyAsync(&hs.iters, &w.st->iters, sizeof(long long),
+                                              hipMemcpyDeviceToHost, st);
+    if (le == hipSuccess) le = hipStreamSynchronize(st);
+    if (le != hipSuccess) {
+      set_error("CG loop: %s", hipGetErrorString(le));
+      status = MFP_E_HIP;
+      break;
+    }
+    // only launches that did work count (launches after convergence return at once)
+    const long long first = k - every;
+    for (int i = 0; i < used; ++i) {
+      const long long it = first + (long long)i * prof;
+      if (hs.done && it >= hs.iters) break;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
+        tsum += ms;
+        ++tcnt;
+      }
+    }
+    if (hs.done) break;
+  }
+  for (int i = 0; i < 2 * nev_c; ++i) hipEventDestroy(ev[i]);
+  if (status != MFP_OK) return status;
+  *iters_out = hs.iters;
+  *applies += hs.iters;
+  *apply_ms = tcnt ? tsum / tcnt : 0.0;
+  *apply_samples = tcnt;
+  return hs.done;
+}
+
+// b - A x in FP64 from the current iterate: w = g + T x, q = K w, r = -T^T q.
+// mode 0 (x = 0): also initialises the CG state; mode 1: records ||b - A x||^2.
+static int residual64(const mfp_grid& g, int nb, const SolveWs& w, hipStream_t st, int mode,
+                      double rtol) {
+  int tpb;
+  const int G = apply_blocks(w.L.ntiles(), &tpb);
+  const int G2 = grid_blocks(w.L.n);
+  k_form_w<double><<<G2, BLOCK, 0, st>>>(w.L.n, w.tag, w.x, w.g, w.st, w.p0);
+  ApplyArgs<double> a = make_apply_args<double>(w, g, nb, w.dx, w.dy);
+  a.src = w.p0;
+  a.q = w.q;
+  k_apply<double, false><<<G, BLOCK, 0, st>>>(a);
+  k_resid<<<G2, BLOCK, 0, st>>>(w.L.n, w.q, w.r, w.part2, mode == 0 ? 1 : 0);
+  k_resid_finalize<<<1, BLOCK, 0, st>>>(w.part2, G2, w.bpart, w.nslots, w.st, nb, mode,
+                                        rtol * rtol);
+  MFP_TRY_HIP(hipGetLastError());
+  if (mode == 0) MFP_TRY_HIP(hipMemsetAsync(w.p0, 0, sizeof(double) * w.L.n, st));
+  return MFP_OK;
+}
+
+extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                             const double* disp, const int8_t* kind, const int8_t* body,
+                             const mfp_flow* flow, const mfp_solver_opts* opts,
+                             int32_t pair_lo, int32_t pair_hi, double* psi, double* psi_b_h,
+                             double* Q_h, double* copfi_h, double* samples,
+                             int8_t* sample_body, int32_t sample_cap, int32_t* n_samples_h,
+                             mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream_) {
+  clear_error();
+  MFP_TRY(check_geometry(grid, circles_h, nbody));
+  if (!disp || !kind || !body || !flow || !opts || !psi || !ws) {
+    set_error("NULL argument");
+    return MFP_E_ARG;
+  }
+  if (nbody > 0 && !psi_b_h) {
+    set_error("psi_b_h is NULL");
+    return MFP_E_ARG;
+  }
+  for (int k = 0; k < 4; ++k)
+    if (flow->side_bc[k] < 0 || flow->side_bc[k] > 2) {
+      set_error("invalid side boundary code");
+      return MFP_E_ARG;
+    }
+  if (!std::isfinite(flow->U)) {
+    set_error("U is not finite");
+    return MFP_E_ARG;
+  }
+  if (opts->precision != MFP_FP64) {
+    set_error("precision %d not available in this entry point", opts->precision);
+    return MFP_E_ARG;
+  }
+  if (opts->psi0) {
+    set_error("warm start not supported");
+    return MFP_E_ARG;
+  }
+  if (!(opts->rtol > 0.0) || opts->kmax < 1) {
+    set_error("rtol must be > 0 and kmax >= 1");
+    return MFP_E_ARG;
+  }
+  if (pair_lo >= nbody || pair_hi >= nbody) {
+    set_error("pair index out of range");
+    return MFP_E_ARG;
+  }
+  if (sample_cap < 0 || (sample_cap > 0 && (!samples || !sample_body))) {
+    set_error("bad sample buffers");
+    return MFP_E_ARG;
+  }
+  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  SolveWs w;
+  solve_layout(grid, nbody, opts->precision, ws, &w);
+  const mfp_grid& g = *grid;
+  const int nb = nbody;
+  MFP_TRY(setup(g, circles_h, nb, disp, body, flow, opts->precision, w, st));
+  // kmax into the device state
+  long long kmax = opts->kmax;
+  MFP_TRY_HIP(hipMemcpyAsync(&w.st->kmax, &kmax, sizeof(long long), hipMemcpyHostToDevice, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));  // kmax is a stack value
+
+  hipEvent_t e0, e1;
+  MFP_TRY_HIP(hipEventCreate(&e0));
+  MFP_TRY_HIP(hipEventCreate(&e1));
+  MFP_TRY_HIP(hipEventRecord(e0, st));
+  long long applies = 0;
+  MFP_TRY(residual64(g, nb, w, st, 0, opts->rtol));
+  applies += 1;
+  long long iters = 0, apply_samples = 0;
+  double apply_ms = 0.0;
+  const int done = cg_fp64(g, nb, w, *opts, st, &iters, &applies, &apply_ms, &apply_samples);
+  if (done < 0) return done;
+  MFP_TRY_HIP(hipEventRecord(e1, st));
+  // true residual
+  MFP_TRY(residual64(g, nb, w, st, 1, opts->rtol));
+  applies += 1;
+  // outputs
+  double ylo = 0, yhi = 0;
+  if (pair_lo >= 0 && pair_hi >= 0) {
+    ylo = circles_h[pair_lo].cy;
+    yhi = circles_h[pair_hi].cy;
+  }
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  k_output<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, w.x, w.g, w.st, psi,
+                                               pair_lo, pair_hi, flow->U, ylo, yhi);
+  MFP_TRY_HIP(hipGetLastError());
+  int nsamp = 0;
+  if (nb > 0) {
+    int boxes[4 * MFP_MAX_BODIES];
+    for (int b = 0; b < nb; ++b) {
+      const Box bx = circle_box(g, circles_h[b], 1, 0, g.nx - 1, 0, g.ny - 1);
+      boxes[4 * b] = bx.i0;
+      boxes[4 * b + 1] = bx.i1;
+      boxes[4 * b + 2] = bx.j0;
+      boxes[4 * b + 3] = bx.j1;
+    }
+    MFP_TRY_HIP(hipMemcpyAsync(w.boxes, boxes, sizeof(int) * 4 * nb, hipMemcpyHostToDevice, st));
+    MFP_TRY_HIP(hipMemcpyAsync(w.circ, circles_h, sizeof(mfp_circle) * nb,
+                               hipMemcpyHostToDevice, st));
+    SampleArgs sa{};
+    sa.nx = g.nx;
+    sa.ny = g.ny;
+    sa.nb = nb;
+    sa.x0 = g.x0;
+    sa.y0 = g.y0;
+    sa.hx = grid_hx(g);
+    sa.hy = grid_hy(g);
+    sa.hmax = sa.hx > sa.hy ? sa.hx : sa.hy;
+    sa.circ = w.circ;
+    sa.boxes = w.boxes;
+    sa.disp = disp;
+    sa.kind = kind;
+    sa.body = body;
+    sa.psi = psi;
+    sa.st = w.st;
+    sa.samples = samples;
+    sa.sbody = sample_body;
+    sa.cap = sample_cap;
+    sa.count = w.count;
+    k_samples<<<1, BLOCK, 0, st>>>(sa);
+    MFP_TRY_HIP(hipGetLastError());
+    MFP_TRY_HIP(hipMemcpyAsync(&nsamp, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
+  }
+  DevState hsd;
+  MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+  long long nfree = 0;
+  MFP_TRY_HIP(hipMemcpyAsync(&nfree, w.nfree, sizeof(long long), hipMemcpyDeviceToHost, st));
+  std::vector<uint8_t> plain(w.L.ntiles());
+  MFP_TRY_HIP(hipMemcpyAsync(plain.data(), w.tplain, plain.size(), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  long long nplain = 0;
+  for (uint8_t v : plain) nplain += v;
+  float ms = 0.f;
+  hipEventElapsedTime(&ms, e0, e1);
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  for (int b = 0; b < nb; ++b) psi_b_h[b] = hsd.xb[hsd.iters & 1][b];
+  if (pair_lo >= 0 && pair_hi >= 0) {
+    if (Q_h) *Q_h = hsd.Q;
+    if (copfi_h) *copfi_h = hsd.copfi;
+  }
+  if (n_samples_h) *n_samples_h = nsamp;
+  if (stats_h) {
+    std::memset(stats_h, 0, sizeof(*stats_h));
+    stats_h->iters = hsd.iters;
+    stats_h->applies = applies;
+    stats_h->n_free = nfree;
+    stats_h->n_dof = nfree + nb;
+    stats_h->rnorm0 = std::sqrt(hsd.rr0);
+    stats_h->relres_true = hsd.rr0 > 0 ? std::sqrt(hsd.rr_true / hsd.rr0) : 0.0;
+    stats_h->solve_ms = ms;
+    stats_h->apply_ms = apply_ms;
+    stats_h->apply_samples = apply_samples;
+    stats_h->n_tiles = w.L.ntiles();
+    stats_h->n_plain_tiles = nplain;
+  }
+  if (done == 2) {
+    set_error("CG breakdown (p.Ap <= 0 or non-finite)");
+    return MFP_E_BREAKDOWN;
+  }
+  if (done == 3) {
+    set_error("kmax reached");
+    return MFP_W_NOCONV;
+  }
+  return MFP_OK;
+}

@@ -1,0 +1,101 @@
+"""The C-ABI library loads, exports every declared entry point, and its host-side
+logic (geometry checks, workspace sizing, argument errors) behaves without a GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import paper_2512_12232_amd as mfp
+    return mfp.load()
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "mfpsi.h")).read()
+    return sorted(set(re.findall(r"\b(mfp_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported(lib):
+    from paper_2512_12232_amd.binding import EXPORTS
+    names = declared_symbols()
+    assert names, "no declarations found"
+    assert sorted(EXPORTS) == names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_geometry_check_matches_oracle():
+    import paper_2512_12232_amd as mfp
+    rng = np.random.default_rng(11)
+    g = W.Grid(64, 32, -8.0, 8.0, -4.0, 4.0)
+    agree = 0
+    for _ in range(300):
+        nb = int(rng.integers(1, 4))
+        circles = [(float(rng.uniform(-8, 8)), float(rng.uniform(-4, 4)),
+                    float(rng.uniform(0.3, 2.0))) for _ in range(nb)]
+        try:
+            O.check_geometry(g, circles)
+            ok_oracle = True
+        except O.GeometryError:
+            ok_oracle = False
+        st = mfp.check_geometry(g, circles)
+        assert (st == 0) == ok_oracle, (circles, st, mfp.last_error())
+        agree += 1
+    assert agree == 300
+
+
+def test_workspace_sizes_and_argument_errors(lib):
+    import paper_2512_12232_amd as mfp
+    from paper_2512_12232_amd import binding as B
+    g = B.make_grid(W.Grid(1024, 512, -20, 20, -10, 10))
+    n64 = lib.mfp_solve_workspace_size(ctypes.byref(g), 5, B.FP64)
+    n32 = lib.mfp_solve_workspace_size(ctypes.byref(g), 5, B.FP32_IR)
+    assert n64 > 8 * 1025 * 513 * 8 and n32 > n64
+    assert lib.mfp_conform_workspace_size(ctypes.byref(g), 5) > 2 * 8 * 1025 * 513
+    # errors are reported before any device work
+    c = B.make_circles([(0, 0, 0.5), (0.5, 0, 0.5)])
+    st = lib.mfp_mesh_conform(ctypes.byref(g), c, 2, 200, None, None, None, None, 0, None)
+    assert st == B.MFP_E_GEOMETRY and "overlap" in mfp.last_error()
+    c = B.make_circles([(0, 0, 0.5)])
+    st = lib.mfp_mesh_conform(ctypes.byref(g), c, 1, 200, None, None, None, None, 0, None)
+    assert st == B.MFP_E_ARG
+    small = B.make_grid(W.Grid(1, 8, 0, 1, 0, 1))
+    assert lib.mfp_check_geometry(ctypes.byref(small), c, 0) == B.MFP_E_GEOMETRY
+
+
+def test_host_paths_reach_the_runtime_without_crashing(lib):
+    """On a machine without a GPU the entry points must get through their host-side
+    preparation and fail cleanly at the first HIP call (never crash)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("only meaningful without a device (pointers below are fake)")
+    from paper_2512_12232_amd import binding as B
+    g = B.make_grid(W.Grid(64, 64, -8, 8, -8, 8))
+    fake = ctypes.c_void_p(4096)
+    ms = ctypes.c_double(0)
+    big = 1 << 40
+    st = lib.mfp_element_apply(ctypes.byref(g), fake, fake, B.FP64, fake, fake, 1,
+                               ctypes.byref(ms), fake, big, None)
+    assert st == B.MFP_E_HIP
+    c = B.make_circles([(0, 0, 0.5)])
+    f = B.make_flow(W.Flow())
+    o = B.MfpSolverOpts(B.FP64, 1e-12, 100, 10, 1e-4, 10, None)
+    psib = (ctypes.c_double * 1)()
+    ns = ctypes.c_int32(0)
+    stats = B.MfpStats()
+    q = ctypes.c_double(0)
+    st = lib.mfp_psi_solve(ctypes.byref(g), c, 1, fake, fake, fake, ctypes.byref(f),
+                           ctypes.byref(o), 0, 0, fake, psib, ctypes.byref(q), ctypes.byref(q),
+                           fake, fake, 4, ctypes.byref(ns), ctypes.byref(stats), fake, big, None)
+    assert st == B.MFP_E_HIP
+    st = lib.mfp_mesh_conform(ctypes.byref(g), c, 1, 200, fake, fake, fake, fake, big, None)
+    assert st == B.MFP_E_HIP

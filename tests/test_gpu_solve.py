@@ -1,0 +1,95 @@
+"""GPU parity of the constrained psi solve against the oracle's direct solve.
+
+Tolerances (FP64 CG stopped at relative residual 1e-13): nodal psi relative L2
+error <= 1e-10, body values and CoPFI within 1e-10 absolute (psi is O(1..10)),
+surface samples: same count, order and bodies; theta within 1e-12, u_t within
+1e-8 relative to max|u_t| (u_t divides psi differences by d_nc ~ h).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import workloads as W
+from gpu_util import DEV, need_gpu, say
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "cyl64": W.single_cylinder(64),
+    "cyl64_exact_bc": W.single_cylinder(64, exact_bc=True),
+    "five96x48": W.five_cylinders(96, 48, 0.25, extent=(-6, 6, -3, 3)),
+    "five_ragged130x67": W.five_cylinders(130, 67, 0.4, extent=(-6.5, 6.5, -3.35, 3.35)),
+    "five_gap_lt_h_256x128": W.five_cylinders(256, 128, 0.05),
+    "channel_nobody_70x9": W.Case("channel", W.Grid(70, 9, 0.0, 7.0, 0.0, 0.9), []),
+}
+
+
+@pytest.fixture(scope="module")
+def mfp():
+    need_gpu()
+    import paper_2512_12232_amd as m
+    m.load()
+    return m
+
+
+def run_pair(mfp, c, rtol=1e-13, precision="fp64"):
+    say(f"[solve] {c.name} {precision}")
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=rtol,
+                        precision=precision, pair=c.pair)
+    mesh = O.conform(c.grid, c.circles, c.nsweeps)
+    ref = O.solve(mesh, c.flow)
+    return res, ref, mesh
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_solve_fp64_matches_oracle(mfp, name):
+    c = CASES[name]
+    res, ref, mesh = run_pair(mfp, c)
+    psi = res.psi.cpu().numpy()
+    err = np.linalg.norm(psi - ref.psi) / np.linalg.norm(ref.psi)
+    assert err <= 1e-10, err
+    assert res.stats["n_dof"] == ref.ndof
+    assert res.stats["relres_true"] <= 2e-13
+    if c.circles:
+        np.testing.assert_allclose(res.psi_b, ref.psi_b, rtol=0, atol=1e-10)
+    if c.pair[0] >= 0:
+        lo, hi = c.pair
+        Q, J = O.copfi(ref.psi_b, lo, hi, c.flow.U, c.circles[lo][1], c.circles[hi][1])
+        assert res.Q == pytest.approx(Q, abs=1e-10)
+        assert res.copfi == pytest.approx(J, abs=1e-10)
+    if c.circles:
+        th, ut, bb = O.surface_samples(mesh, ref.psi, ref.psi_b)
+        assert res.n_samples == len(th)
+        assert np.array_equal(res.sample_body.cpu().numpy(), bb)
+        np.testing.assert_allclose(res.theta.cpu().numpy(), th, rtol=0, atol=1e-12)
+        np.testing.assert_allclose(res.ut.cpu().numpy(), ut, rtol=0,
+                                   atol=1e-8 * np.abs(ut).max())
+
+
+def test_solve_deterministic(mfp):
+    c = CASES["five96x48"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, 200, device=DEV)
+    a = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12)
+    b = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12)
+    assert torch.equal(a.psi, b.psi) and a.psi_b == b.psi_b
+    assert a.stats["iters"] == b.stats["iters"]
+
+
+def test_kmax_gives_noconv_warning(mfp):
+    c = CASES["five96x48"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, 200, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12, kmax=5,
+                        check_every=2)
+    assert res.status == 1 and res.stats["iters"] == 5
+
+
+def test_symmetry_on_gpu(mfp):
+    """Mirror symmetry: bodies on y = 0 carry psi_b ~ 0, the pair opposite values."""
+    c = W.five_cylinders(256, 128, 0.3)
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, 200, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13)
+    pb = np.array(res.psi_b)
+    assert np.abs(pb[:3]).max() < 1e-9
+    assert abs(pb[3] + pb[4]) < 1e-9
