@@ -113,18 +113,43 @@ __device__ __forceinline__ void cell_apply(T ry, T dx0, T dx1, T dx2, T dx3, T d
   y3 = qt * ((Se - Sex) - (Sx + Sxe));
 }
 
+// Whole-wavefront lane shifts (DPP wave_shr:1 / wave_shl:1).  shr: lane i receives
+// lane i-1 (lane 0 receives 0); shl: lane i receives lane i+1 (lane 63 receives 0).
+// All 64 lanes must be active.
+__device__ __forceinline__ int dpp_shr1_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x138, 0xf, 0xf, false);
+}
+__device__ __forceinline__ int dpp_shl1_i(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, 0x130, 0xf, 0xf, false);
+}
+__device__ __forceinline__ double lane_shr(double v) {
+  const int lo = dpp_shr1_i(__double2loint(v)), hi = dpp_shr1_i(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_shl(double v) {
+  const int lo = dpp_shl1_i(__double2loint(v)), hi = dpp_shl1_i(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_shr(float v) {
+  return __int_as_float(dpp_shr1_i(__float_as_int(v)));
+}
+__device__ __forceinline__ float lane_shl(float v) {
+  return __int_as_float(dpp_shl1_i(__float_as_int(v)));
+}
+__device__ __forceinline__ int lane_shl(int v) { return dpp_shl1_i(v); }
+
 template <typename T>
 struct ApplyArgs {
-  int P, ntx, ntiles, tpb;       // pitch, tiles per row, tile count, tiles per block
+  int P, nstrip, ntasks, gpb;    // pitch, strips, tasks, task groups per block
   const int8_t* tag;
   const T* dx;                   // displacement / hx
   const T* dy;
-  const uint8_t* tplain;         // 1: constant-stencil tile
-  const unsigned long long* tbody;  // bodies among the tile's own nodes
-  const int* tslot;              // body-partial slot of the tile or -1
+  const uint8_t* tplain;         // per task, 1: constant-stencil task
+  const unsigned long long* tbody;  // per task: bodies among its owned nodes
+  const int* tslot;              // per task: body-partial slot or -1
   const T* src;                  // plain apply: p; fused: previous direction
   const T* r;                    // fused: residual
-  T* pnew;                       // fused: new direction (written at own nodes)
+  T* pnew;                       // fused: new direction (written at owned nodes)
   T* q;                          // K p at free nodes (all in-domain nodes if write_all)
   double* part;                  // per-block partial of p.q over free nodes
   double* bpart;                 // per-slot, per-body partial sums of K p
@@ -144,68 +169,68 @@ struct ApplyArgs {
 // results), forms beta = r_k.r_k / r_{k-1}.r_{k-1} and the body directions, stops
 // the solve when the tolerance, kmax or a non-finite value is reached, and then forms
 // p = r + beta p_old (body nodes p_b, Dirichlet nodes 0) before applying K.
-// There is no grid-wide synchronisation inside the kernel: partial sums go to
-// per-block slots that the next kernel reduces.
-template <typename T, bool FUSED>
+// No grid-wide synchronisation inside the kernel: partial sums go to per-block slots
+// that the next kernel reduces.
+//
+// Each wavefront processes whole tasks (64-column strip x HC rows).  The residual and
+// old-direction rows of a task are loaded into registers first (for a wave's first
+// task before the scalar reduction, so that the two latencies overlap).
+// Constant-stencil tasks evaluate the assembled 9-point stencil with lane shifts for
+// the horizontal neighbours.  Other tasks march over the HC+1 cell rows touching their
+// rows: lane c evaluates cell (c, j) from its own nodes and those of lane c+1 (shifted
+// in), keeps the cell's contributions to its own column and shifts the contributions
+// to column c+1 over; node (c, j) is complete once cell rows j-1 and j are done.
+template <typename T, bool FUSED, int HC>
 __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
-  __shared__ T s_p[FH][FW];
-  __shared__ T s_dx[FH][FW];
-  __shared__ T s_dy[FH][FW];
-  __shared__ int8_t s_tag[FH][FW];
-  __shared__ T s_c[4][CH][CW];
-  __shared__ double s_red[BLOCK / 64];
+  __shared__ double s_red[WAVES];
   __shared__ double s_pb[MFP_MAX_BODIES];
-
   const int tid = threadIdx.x;
-  if (FUSED && a.st->done) return;
+  const int lane = tid & 63, wv = tid >> 6;
   const int G = gridDim.x;
   // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs)
   const int vb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
-  const int t0 = vb * a.tpb;
-  const int t1 = min(t0 + a.tpb, a.ntiles);
   const long long P = a.P;
+  const bool owner = lane >= 1 && lane <= SW;
+  const int grp0 = vb * a.gpb, grp1 = (vb + 1) * a.gpb;
 
-  // Footprint values of the next tile are held in registers (NE per thread) so that
-  // its loads are in flight while the current tile is computed.
-  constexpr int NE = (FH * FW + BLOCK - 1) / BLOCK;
-  T ra[NE], rb[NE], rdx[NE], rdy[NE];
-  int8_t rtag[NE];
-  auto issue = [&](int t, bool plain) {
-    const int ty = t / a.ntx, tx = t - ty * a.ntx;
-    const long long base = (long long)(ty * TY) * P + tx * TX;
+  T ra[HC + 2], rs[HC + 2];  // residual and direction (or p) rows of the current task
+  auto fill = [&](int t) {
+    const int m = t % a.nstrip, kc = t / a.nstrip;
+    const long long base = (long long)(kc * HC) * P + (long long)m * SW + lane;
 #pragma unroll
-    for (int k = 0; k < NE; ++k) {
-      const int e = tid + k * BLOCK;
-      if (e < FH * FW) {
-        const int fr = e / FW, fc = e - fr * FW;
-        const long long gi = base + fr * P + fc;
-        rb[k] = a.src[gi];
-        if (FUSED) ra[k] = a.r[gi];
-        if (!plain) {
-          rtag[k] = a.tag[gi];
-          rdx[k] = a.dx[gi];
-          rdy[k] = a.dy[gi];
-        }
-      }
+    for (int r = 0; r < HC + 2; ++r) {
+      rs[r] = a.src[base + r * P];
+      if (FUSED) ra[r] = a.r[base + r * P];
     }
   };
-  bool plain_next = t0 < t1 ? a.tplain[t0] != 0 : true;
-  if (t0 < t1) issue(t0, plain_next);
+  int tfirst = grp0 * WAVES + wv;
+  const bool have_first = tfirst < a.ntasks;
+  if (have_first) fill(tfirst);
 
   T beta = (T)0;
   if (FUSED) {
     DevState* st = a.st;
     const int cur = (int)(a.k & 1), prv = cur ^ 1;
+    // every scalar this block needs is requested at once
+    const int done = st->done;
+    const double rb_rr = st->rb_rr[cur], rr_prv = st->rr[prv], rr_stop = st->rr_stop;
+    const long long kmax = st->kmax;
+    double rbv = 0.0, pbv = 0.0;
+    if (tid < a.nb) {
+      rbv = st->rb[cur][tid];
+      pbv = st->pb[prv][tid];
+    }
     double s = 0.0;
     for (int i = tid; i < a.G2; i += BLOCK) s += a.part2[i];
-    const double rrk = block_sum(s, s_red) + st->rb_rr[cur];
-    const double beta_d = rrk / st->rr[prv];
+    if (done) return;
+    const double rrk = block_sum(s, s_red) + rb_rr;
+    const double beta_d = rrk / rr_prv;
     int code = 0;
     if (!isfinite(rrk))
       code = 2;
-    else if (rrk <= st->rr_stop)
+    else if (rrk <= rr_stop)
       code = 1;
-    else if (a.k >= st->kmax)
+    else if (a.k >= kmax)
       code = 3;
     if (code) {
       if (blockIdx.x == 0 && tid == 0) {
@@ -216,7 +241,7 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
       return;
     }
     if (tid < a.nb) {
-      const double v = st->rb[cur][tid] + beta_d * st->pb[prv][tid];
+      const double v = rbv + beta_d * pbv;
       s_pb[tid] = v;
       if (blockIdx.x == 0) st->pb[cur][tid] = v;
     }
@@ -229,112 +254,108 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
   }
 
   double pq = 0.0;
-  for (int t = t0; t < t1; ++t) {
-    const int ty = t / a.ntx, tx = t - ty * a.ntx;
-    const long long base = (long long)(ty * TY) * P + tx * TX;
-    const bool plain = plain_next;
-    // registers -> LDS (forming the new direction on the way in the fused form)
+  double bacc = 0.0;  // lane b accumulates body b of the current task
+  for (int grp = grp0; grp < grp1; ++grp) {
+    const int t = grp * WAVES + wv;
+    if (t >= a.ntasks) break;
+    if (t != tfirst) fill(t);
+    const int m = t % a.nstrip, kc = t / a.nstrip;
+    // local row r = 0 .. HC+1 is internal row kc*HC + r; lane is internal column m*SW+lane
+    const long long base = (long long)(kc * HC) * P + (long long)m * SW + lane;
+    if (a.tplain[t]) {
+      T v[HC + 2];
 #pragma unroll
-    for (int k = 0; k < NE; ++k) {
-      const int e = tid + k * BLOCK;
-      if (e < FH * FW) {
-        const int fr = e / FW, fc = e - fr * FW;
-        T v;
-        if (FUSED) {
-          if (plain) {
-            v = ra[k] + beta * rb[k];
-          } else {
-            const int8_t tg = rtag[k];
-            v = tg == TAG_FREE ? ra[k] + beta * rb[k]
-                               : (tg >= TAG_BODY0 ? (T)s_pb[tg - TAG_BODY0] : (T)0);
-          }
-          if (fr >= 1 && fr <= TY && fc >= 1 && fc <= TX) a.pnew[base + fr * P + fc] = v;
-        } else {
-          v = rb[k];
-        }
-        s_p[fr][fc] = v;
-        if (!plain) {
-          s_tag[fr][fc] = rtag[k];
-          s_dx[fr][fc] = rdx[k];
-          s_dy[fr][fc] = rdy[k];
-        }
-      }
-    }
-    if (t + 1 < t1) {
-      plain_next = a.tplain[t + 1] != 0;
-      issue(t + 1, plain_next);
-    }
-    __syncthreads();
-    if (plain) {
+      for (int r = 0; r < HC + 2; ++r) v[r] = FUSED ? ra[r] + beta * rs[r] : rs[r];
 #pragma unroll
-      for (int k = 0; k < (TX * TY) / BLOCK; ++k) {
-        const int o = tid + k * BLOCK;
-        const int rr = 1 + o / TX, cc = 1 + (o % TX);
-        const T c = s_p[rr][cc];
-        const T v = a.cC * c + a.cE * (s_p[rr][cc - 1] + s_p[rr][cc + 1]) +
-                    a.cN * (s_p[rr - 1][cc] + s_p[rr + 1][cc]) +
-                    a.cD * ((s_p[rr - 1][cc - 1] + s_p[rr - 1][cc + 1]) +
-                            (s_p[rr + 1][cc - 1] + s_p[rr + 1][cc + 1]));
-        a.q[base + rr * P + cc] = v;
-        pq += (double)c * (double)v;
+      for (int r = 1; r <= HC; ++r) {
+        const long long gi = base + r * P;
+        const T cs = v[r - 1] + v[r + 1];
+        const T pl = lane_shr(v[r]), pr = lane_shl(v[r]);
+        const T csl = lane_shr(cs), csr = lane_shl(cs);
+        const T qv = a.cC * v[r] + a.cE * (pl + pr) + a.cN * cs + a.cD * (csl + csr);
+        if (owner) {
+          if (FUSED) a.pnew[gi] = v[r];
+          a.q[gi] = qv;
+          pq += (double)v[r] * (double)qv;
+        }
       }
     } else {
-      for (int c = tid; c < CH * CW; c += BLOCK) {
-        const int cr = c / CW, cc = c - cr * CW;
-        const int8_t g0 = s_tag[cr][cc], g1 = s_tag[cr][cc + 1], g2 = s_tag[cr + 1][cc + 1],
-                     g3 = s_tag[cr + 1][cc];
-        const bool halo = (g0 == TAG_HALO) | (g1 == TAG_HALO) | (g2 == TAG_HALO) | (g3 == TAG_HALO);
-        const bool inside = (g0 >= TAG_BODY0) & (g1 == g0) & (g2 == g0) & (g3 == g0);
-        T y0 = 0, y1 = 0, y2 = 0, y3 = 0;
-        if (!halo && !inside) {
-          cell_apply<T>(a.ry, s_dx[cr][cc], s_dx[cr][cc + 1], s_dx[cr + 1][cc + 1],
-                        s_dx[cr + 1][cc], s_dy[cr][cc], s_dy[cr][cc + 1],
-                        s_dy[cr + 1][cc + 1], s_dy[cr + 1][cc], s_p[cr][cc],
-                        s_p[cr][cc + 1], s_p[cr + 1][cc + 1], s_p[cr + 1][cc], y0, y1, y2,
-                        y3);
-        }
-        s_c[0][cr][cc] = y0;
-        s_c[1][cr][cc] = y1;
-        s_c[2][cr][cc] = y2;
-        s_c[3][cr][cc] = y3;
-      }
-      __syncthreads();
-      T sums[(TX * TY) / BLOCK];
-      int8_t tags[(TX * TY) / BLOCK];
-#pragma unroll
-      for (int k = 0; k < (TX * TY) / BLOCK; ++k) {
-        const int o = tid + k * BLOCK;
-        const int rr = 1 + o / TX, cc = 1 + (o % TX);
-        const T sum = (s_c[2][rr - 1][cc - 1] + s_c[3][rr - 1][cc]) +
-                      (s_c[1][rr][cc - 1] + s_c[0][rr][cc]);
-        const int8_t tg = s_tag[rr][cc];
-        const bool keep = (tg == TAG_FREE) || (a.write_all && tg != TAG_HALO);
-        a.q[base + rr * P + cc] = keep ? sum : (T)0;
-        if (tg == TAG_FREE) pq += (double)s_p[rr][cc] * (double)sum;
-        sums[k] = sum;
-        tags[k] = tg;
-      }
       const unsigned long long bm = a.tbody[t];
-      if (bm) {
-        const int slot = a.tslot[t];
-        for (int b = 0; b < a.nb; ++b) {
-          if (bm & (1ull << b)) {
-            double v = 0.0;
+      bacc = 0.0;
+      auto pval = [&](int8_t tg, int r) -> T {
+        if (!FUSED) return rs[r];
+        if (tg == TAG_FREE) return ra[r] + beta * rs[r];
+        if (tg >= TAG_BODY0) return (T)s_pb[tg - TAG_BODY0];
+        return (T)0;
+      };
+      // lower node row of the current cell row (own column and right neighbour)
+      int8_t g0 = a.tag[base];
+      T p0 = pval(g0, 0);
+      T x0 = a.dx[base], y0 = a.dy[base];
+      int8_t g1n = (int8_t)lane_shl((int)g0);
+      T p1n = lane_shl(p0), x1n = lane_shl(x0), y1n = lane_shl(y0);
+      T carry = (T)0;
 #pragma unroll
-            for (int k = 0; k < (TX * TY) / BLOCK; ++k)
-              if (tags[k] == TAG_BODY0 + b) v += (double)sums[k];
-            v = block_sum(v, s_red);
-            if (tid == 0) a.bpart[(long long)slot * a.nb + b] = v;
-          } else if (tid == 0) {
-            a.bpart[(long long)slot * a.nb + b] = 0.0;
+      for (int sr = 0; sr <= HC; ++sr) {
+        const long long gu = base + (sr + 1) * P;
+        const int8_t g3 = a.tag[gu];
+        const T p3 = pval(g3, sr + 1);
+        const T x3 = a.dx[gu], y3 = a.dy[gu];
+        const int8_t g2 = (int8_t)lane_shl((int)g3);
+        const T p2 = lane_shl(p3), x2 = lane_shl(x3), y2 = lane_shl(y3);
+        // cell (own column, row sr): nodes 0 = (c, sr), 1 = (c+1, sr), 2 = (c+1, sr+1),
+        // 3 = (c, sr+1)
+        const bool halo = (g0 == TAG_HALO) | (g1n == TAG_HALO) | (g2 == TAG_HALO) | (g3 == TAG_HALO);
+        const bool inside = (g0 >= TAG_BODY0) & (g1n == g0) & (g2 == g0) & (g3 == g0);
+        T c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+        if (!halo && !inside && lane < 63)
+          cell_apply<T>(a.ry, x0, x1n, x2, x3, y0, y1n, y2, y3, p0, p1n, p2, p3, c0, c1, c2,
+                        c3);
+        const T acc = carry + c0 + lane_shr(c1);
+        carry = c3 + lane_shr(c2);
+        if (sr >= 1) {
+          const long long gi = base + sr * P;
+          if (owner) {
+            if (FUSED) a.pnew[gi] = p0;
+            const bool keep = (g0 == TAG_FREE) || (a.write_all && g0 != TAG_HALO);
+            a.q[gi] = keep ? acc : (T)0;
+            if (g0 == TAG_FREE) pq += (double)p0 * (double)acc;
+          }
+          if (bm) {
+            unsigned long long rowb = __ballot(owner && g0 >= TAG_BODY0);
+            while (rowb) {
+              const int src = __ffsll((long long)rowb) - 1;
+              const int bt = __shfl((int)g0, src, 64);
+              const bool mine = owner && g0 == bt;
+              const double v = wave_sum(mine ? (double)acc : 0.0);
+              if (lane == bt - TAG_BODY0) bacc += v;
+              rowb &= ~__ballot(mine);
+            }
           }
         }
+        g0 = g3;
+        p0 = p3;
+        x0 = x3;
+        y0 = y3;
+        g1n = g2;
+        p1n = p2;
+        x1n = x2;
+        y1n = y2;
       }
+      if (bm && lane < a.nb) a.bpart[(long long)a.tslot[t] * a.nb + lane] = bacc;
     }
-    __syncthreads();
   }
   const double bsum = block_sum(pq, s_red);
   if (tid == 0) a.part[blockIdx.x] = bsum;
+}
+
+// Launch the apply for the layout's task height.
+template <typename T, bool FUSED>
+inline void launch_apply(int hc, int G, hipStream_t st, const ApplyArgs<T>& a) {
+  if (hc == 4)
+    k_apply<T, FUSED, 4><<<G, BLOCK, 0, st>>>(a);
+  else
+    k_apply<T, FUSED, 8><<<G, BLOCK, 0, st>>>(a);
 }
 
 // Per-body sums of the slot partials, into s_qb[0 .. nb); wave w handles bodies

@@ -61,33 +61,37 @@ struct Bump {
 
 // ---- padded node layout used by the solver ----------------------------------------
 // Node (i, j) of the (nx+1) x (ny+1) grid lives at index (j+1)*P + (i+1); a ring of
-// halo nodes (tag TAG_HALO, zero values) surrounds the domain and the pitch P is a
-// multiple of 64 so that each tile row starts on a 512-byte boundary.
-constexpr int TX = 64;        // tile width in nodes (one wavefront per row)
-constexpr int TY = 8;         // tile height in nodes
-constexpr int FW = TX + 2;    // footprint width (one halo column each side)
-constexpr int FH = TY + 2;    // footprint height
-constexpr int CW = TX + 1;    // cells touching a tile, per row
-constexpr int CH = TY + 1;    // rows of cells touching a tile
-constexpr int BLOCK = 256;
+// halo nodes (tag TAG_HALO, zero values) surrounds the domain.  The element apply
+// works on "tasks": one wavefront per strip of 64 node columns (lanes 0 and 63 are
+// halo columns shared with the neighbouring strips, lanes 1..62 own their column)
+// and a chunk of HC node rows, marching upward with the node data in registers.
+constexpr int SW = 62;        // owned node columns per strip
+constexpr int BLOCK = 256;    // 4 wavefronts, i.e. 4 tasks per block and step
+constexpr int WAVES = BLOCK / 64;
 
 struct Layout {
-  int nx, ny;     // cells
-  int ntx, nty;   // tiles
-  int P;          // pitch (nodes per padded row)
-  int rows;       // padded rows
-  long long n;    // P * rows
-  int ntiles() const { return ntx * nty; }
+  int nx, ny;       // cells
+  int hc;           // owned node rows per task (4 or 8)
+  int nstrip;       // strips of SW owned columns
+  int nchunk;       // chunks of hc owned rows
+  int P;            // pitch (nodes per padded row), multiple of 64
+  int rows;         // padded rows
+  long long n;      // P * rows
+  __host__ __device__ int ntasks() const { return nstrip * nchunk; }
 };
 
+// Short tasks (4 rows) on small grids give each SIMD at least two wavefronts; larger
+// grids use 8-row tasks (less halo re-reading).
 inline Layout make_layout(int nx, int ny) {
   Layout L;
   L.nx = nx;
   L.ny = ny;
-  L.ntx = (nx + 1 + TX - 1) / TX;
-  L.nty = (ny + 1 + TY - 1) / TY;
-  L.P = TX * (L.ntx + 1);
-  L.rows = TY * L.nty + 2;
+  L.nstrip = (nx + 1 + SW - 1) / SW;
+  const long long t8 = (long long)L.nstrip * ((ny + 1 + 7) / 8);
+  L.hc = t8 < 4096 ? 4 : 8;
+  L.nchunk = (ny + 1 + L.hc - 1) / L.hc;
+  L.P = (((L.nstrip - 1) * SW + 64) + 63) / 64 * 64;
+  L.rows = L.hc * L.nchunk + 2;
   L.n = (long long)L.P * L.rows;
   return L;
 }

@@ -108,32 +108,36 @@ __global__ void k_setup(SetupArgs a) {
   if (a.nfree && cnt) atomicAdd((unsigned long long*)a.nfree, (unsigned long long)cnt);
 }
 
-// Per tile: constant-stencil flag (footprint all free and undisplaced) and the set
-// of bodies among the tile's own nodes.  One block per tile.
-__global__ void k_tile_meta(Layout L, const int8_t* __restrict__ tag,
-                            const double* __restrict__ dx, const double* __restrict__ dy,
-                            uint8_t* __restrict__ tplain, unsigned long long* __restrict__ tbody) {
-  const int t = blockIdx.x;
-  const int ty = t / L.ntx, tx = t - ty * L.ntx;
-  const long long base = (long long)(ty * TY) * L.P + tx * TX;
+// Per task: constant-stencil flag (footprint of 64 columns x HC+2 rows all free and
+// undisplaced) and the set of bodies among the task's owned nodes.  One wavefront per
+// task.
+__global__ void __launch_bounds__(BLOCK) k_task_meta(Layout L, const int8_t* __restrict__ tag,
+                                                     const double* __restrict__ dx,
+                                                     const double* __restrict__ dy,
+                                                     uint8_t* __restrict__ tplain,
+                                                     unsigned long long* __restrict__ tbody) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * WAVES + (threadIdx.x >> 6);
+  if (t >= L.ntasks()) return;
+  const int m = t % L.nstrip, kc = t / L.nstrip;
+  const int HC = L.hc;
+  const long long base = (long long)(kc * HC) * L.P + (long long)m * SW + lane;
   int plain = 1;
   unsigned long long bm = 0;
-  for (int e = threadIdx.x; e < FH * FW; e += BLOCK) {
-    const int fr = e / FW, fc = e - fr * FW;
-    const long long gi = base + (long long)fr * L.P + fc;
+  for (int r = 0; r < HC + 2; ++r) {
+    const long long gi = base + (long long)r * L.P;
     const int8_t tg = tag[gi];
     if (tg != TAG_FREE || dx[gi] != 0.0 || dy[gi] != 0.0) plain = 0;
-    if (fr >= 1 && fr <= TY && fc >= 1 && fc <= TX && tg >= TAG_BODY0)
+    if (r >= 1 && r <= HC && lane >= 1 && lane <= SW && tg >= TAG_BODY0)
       bm |= 1ull << (tg - TAG_BODY0);
   }
-  plain = __syncthreads_and(plain);
-  __shared__ unsigned long long s_bm[BLOCK / 64];
-  for (int off = 32; off > 0; off >>= 1) bm |= __shfl_xor(bm, off, 64);
-  if ((threadIdx.x & 63) == 0) s_bm[threadIdx.x >> 6] = bm;
-  __syncthreads();
-  if (threadIdx.x == 0) {
+  for (int off = 32; off > 0; off >>= 1) {
+    bm |= __shfl_xor(bm, off, 64);
+    plain &= __shfl_xor(plain, off, 64);
+  }
+  if (lane == 0) {
     tplain[t] = (uint8_t)plain;
-    tbody[t] = s_bm[0] | s_bm[1] | s_bm[2] | s_bm[3];
+    tbody[t] = bm;
   }
 }
 
@@ -271,11 +275,15 @@ __global__ void __launch_bounds__(BLOCK) k_update(long long n, T* __restrict__ x
     qv = q2[e];
   }
   const int cur = (int)(k & 1), nxt = cur ^ 1;
-  body_sums(bpart, *nslots, nb, s_qb);
+  // every scalar this block needs is requested at once
+  const double rr_cur = st->rr[cur];
+  double pbv = 0.0;
+  if (threadIdx.x < nb) pbv = st->pb[cur][threadIdx.x];
   double s = 0.0;
   for (int i = threadIdx.x; i < G; i += BLOCK) s += part[i];
-  double pq = block_sum(s, s_red);
-  for (int b = 0; b < nb; ++b) pq += st->pb[cur][b] * s_qb[b];
+  body_sums(bpart, *nslots, nb, s_qb);
+  if (threadIdx.x < nb) s += pbv * s_qb[threadIdx.x];
+  const double pq = block_sum(s, s_red);
   if (!(pq > 0.0) || !isfinite(pq)) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       st->done = 2;
@@ -284,7 +292,7 @@ __global__ void __launch_bounds__(BLOCK) k_update(long long n, T* __restrict__ x
     }
     return;
   }
-  const double alpha_d = st->rr[cur] / pq;
+  const double alpha_d = rr_cur / pq;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     double rbr = 0.0;
     for (int b = 0; b < nb; ++b) {
@@ -476,7 +484,7 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   SolveWs w{};
   w.L = make_layout(g->nx, g->ny);
   const size_t n = (size_t)w.L.n;
-  const int nt = w.L.ntiles();
+  const int nt = w.L.ntasks();
   w.tag = bp.take<int8_t>(n);
   w.dx = bp.take<double>(n);
   w.dy = bp.take<double>(n);
@@ -520,14 +528,15 @@ static int grid_blocks(long long n) {
   return (int)b;
 }
 
-// Apply: tiles per block chosen so that at most ~1024 blocks run; block count a
-// multiple of 8 (XCD-aware tile order).
-static int apply_blocks(int ntiles, int* tpb) {
-  int t = (ntiles + 1023) / 1024;
+// Apply: groups of 4 tasks (one per wavefront); groups per block chosen so that at
+// most ~1024 blocks run; block count a multiple of 8 (XCD-aware task order).
+static int apply_blocks(int ntasks, int* gpb) {
+  const int groups = (ntasks + WAVES - 1) / WAVES;
+  int t = (groups + 1023) / 1024;
   if (t < 1) t = 1;
-  int g = (ntiles + t - 1) / t;
+  int g = (groups + t - 1) / t;
   g = (g + 7) & ~7;
-  *tpb = t;
+  *gpb = t;
   return g;
 }
 
@@ -536,9 +545,9 @@ static ApplyArgs<T> make_apply_args(const SolveWs& w, const mfp_grid& g, int nb,
                                     const T* dy) {
   ApplyArgs<T> a{};
   a.P = w.L.P;
-  a.ntx = w.L.ntx;
-  a.ntiles = w.L.ntiles();
-  apply_blocks(a.ntiles, &a.tpb);
+  a.nstrip = w.L.nstrip;
+  a.ntasks = w.L.ntasks();
+  apply_blocks(a.ntasks, &a.gpb);
   a.tag = w.tag;
   a.dx = dx;
   a.dy = dy;
@@ -597,9 +606,10 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   MFP_TRY_HIP(hipMemsetAsync(w.nfree, 0, sizeof(long long), st));
   k_setup<<<grid_blocks(w.L.n), BLOCK, 0, st>>>(s);
   MFP_TRY_HIP(hipGetLastError());
-  k_tile_meta<<<w.L.ntiles(), BLOCK, 0, st>>>(w.L, w.tag, w.dx, w.dy, w.tplain, w.tbody);
+  k_task_meta<<<(w.L.ntasks() + WAVES - 1) / WAVES, BLOCK, 0, st>>>(w.L, w.tag, w.dx, w.dy,
+                                                                     w.tplain, w.tbody);
   MFP_TRY_HIP(hipGetLastError());
-  k_assign_slots<<<1, BLOCK, 0, st>>>(w.L.ntiles(), w.tbody, w.tslot, w.nslots);
+  k_assign_slots<<<1, BLOCK, 0, st>>>(w.L.ntasks(), w.tbody, w.tslot, w.nslots);
   MFP_TRY_HIP(hipGetLastError());
   return MFP_OK;
 }
@@ -649,7 +659,7 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
                                esz * (g.nx + 1), esz * (g.nx + 1), g.ny + 1,
                                hipMemcpyDeviceToDevice, st));
   int tpb;
-  const int G = apply_blocks(w.L.ntiles(), &tpb);
+  const int G = apply_blocks(w.L.ntasks(), &tpb);
   hipEvent_t e0, e1;
   MFP_TRY_HIP(hipEventCreate(&e0));
   MFP_TRY_HIP(hipEventCreate(&e1));
@@ -660,18 +670,18 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
       a.src = w.p0;
       a.q = w.q;
       a.write_all = 1;
-      k_apply<double, false><<<G, BLOCK, 0, st>>>(a);
+      launch_apply<double, false>(w.L.hc, G, st, a);
     } else {
       ApplyArgs<float> a = make_apply_args<float>(w, g, nbmax, w.dxf, w.dyf);
       a.src = w.p0f;
       a.q = w.qf;
       a.write_all = 1;
-      k_apply<float, false><<<G, BLOCK, 0, st>>>(a);
+      launch_apply<float, false>(w.L.hc, G, st, a);
     }
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       set_error("apply launch: %s", hipGetErrorString(le));
       return MFP_E_HIP;
     }
@@ -683,8 +693,8 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
   MFP_TRY_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
   MFP_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (apply_ms_h) *apply_ms_h = ms / repeat;
   (void)nn;
   return MFP_OK;
@@ -697,7 +707,7 @@ static int cg_fp64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver
                    hipStream_t st, long long* iters_out, long long* applies, double* apply_ms,
                    long long* apply_samples) {
   int tpb;
-  const int G = apply_blocks(w.L.ntiles(), &tpb);
+  const int G = apply_blocks(w.L.ntasks(), &tpb);
   const int G2 = grid_blocks(w.L.n);
   double* pbuf[2] = {w.p0, w.p1};
   const int every = o.check_every > 0 ? o.check_every : 50;
@@ -727,9 +737,12 @@ static int cg_fp64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver
       a.pnew = pbuf[(k + 1) & 1];
       a.k = k;
       const bool timed = prof && (m % prof == 0) && used < nev_c;
-      if (timed) hipEventRecord(ev[2 * used], st);
-      k_apply<double, true><<<G, BLOCK, 0, st>>>(a);
-      if (timed) hipEventRecord(ev[2 * used + 1], st), ++used;
+      if (timed) (void)hipEventRecord(ev[2 * used], st);
+      launch_apply<double, true>(w.L.hc, G, st, a);
+      if (timed) {
+        (void)hipEventRecord(ev[2 * used + 1], st);
+        ++used;
+      }
       k_update<double><<<G2, BLOCK, 0, st>>>(w.L.n, w.x, pbuf[(k + 1) & 1], w.r, w.q, w.part,
                                              G, w.bpart, w.nslots, w.part2, w.st, nb, k);
     }
@@ -757,7 +770,7 @@ static int cg_fp64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver
     }
     if (hs.done) break;
   }
-  for (int i = 0; i < 2 * nev_c; ++i) hipEventDestroy(ev[i]);
+  for (int i = 0; i < 2 * nev_c; ++i) (void)hipEventDestroy(ev[i]);
   if (status != MFP_OK) return status;
   *iters_out = hs.iters;
   *applies += hs.iters;
@@ -771,13 +784,13 @@ static int cg_fp64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver
 static int residual64(const mfp_grid& g, int nb, const SolveWs& w, hipStream_t st, int mode,
                       double rtol) {
   int tpb;
-  const int G = apply_blocks(w.L.ntiles(), &tpb);
+  const int G = apply_blocks(w.L.ntasks(), &tpb);
   const int G2 = grid_blocks(w.L.n);
   k_form_w<double><<<G2, BLOCK, 0, st>>>(w.L.n, w.tag, w.x, w.g, w.st, w.p0);
   ApplyArgs<double> a = make_apply_args<double>(w, g, nb, w.dx, w.dy);
   a.src = w.p0;
   a.q = w.q;
-  k_apply<double, false><<<G, BLOCK, 0, st>>>(a);
+  launch_apply<double, false>(w.L.hc, G, st, a);
   k_resid<<<G2, BLOCK, 0, st>>>(w.L.n, w.q, w.r, w.part2, mode == 0 ? 1 : 0);
   k_resid_finalize<<<1, BLOCK, 0, st>>>(w.part2, G2, w.bpart, w.nslots, w.st, nb, mode,
                                         rtol * rtol);
@@ -914,15 +927,15 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
   long long nfree = 0;
   MFP_TRY_HIP(hipMemcpyAsync(&nfree, w.nfree, sizeof(long long), hipMemcpyDeviceToHost, st));
-  std::vector<uint8_t> plain(w.L.ntiles());
+  std::vector<uint8_t> plain(w.L.ntasks());
   MFP_TRY_HIP(hipMemcpyAsync(plain.data(), w.tplain, plain.size(), hipMemcpyDeviceToHost, st));
   MFP_TRY_HIP(hipStreamSynchronize(st));
   long long nplain = 0;
   for (uint8_t v : plain) nplain += v;
   float ms = 0.f;
-  hipEventElapsedTime(&ms, e0, e1);
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   for (int b = 0; b < nb; ++b) psi_b_h[b] = hsd.xb[hsd.iters & 1][b];
   if (pair_lo >= 0 && pair_hi >= 0) {
     if (Q_h) *Q_h = hsd.Q;
@@ -940,7 +953,7 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
     stats_h->solve_ms = ms;
     stats_h->apply_ms = apply_ms;
     stats_h->apply_samples = apply_samples;
-    stats_h->n_tiles = w.L.ntiles();
+    stats_h->n_tiles = w.L.ntasks();
     stats_h->n_plain_tiles = nplain;
   }
   if (done == 2) {
