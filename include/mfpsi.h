@@ -74,7 +74,8 @@ extern "C" {
 /* ---- solver precisions ------------------------------------------------------------ */
 #define MFP_FP64 0    /* FP64 vectors and FP64 element apply                           */
 #define MFP_FP32 1    /* FP32 vectors and apply; FP64 scalars and body sums            */
-#define MFP_FP32_IR 2 /* FP32 inner CG wrapped in FP64 iterative refinement            */
+#define MFP_FP32_IR 2 /* FP32 CG with FP64 residual recomputation and FP64 accumulation
+                         of the solution (iterative refinement, Krylov space kept)      */
 
 #define MFP_MAX_BODIES 64
 
@@ -97,8 +98,9 @@ typedef struct {
   double rtol;            /* stop when ||r_k|| <= rtol ||r_0|| (unknowns incl. bodies)  */
   int64_t kmax;           /* CG iteration cap (all inner iterations together)           */
   int32_t check_every;    /* host convergence poll period in iterations (>= 1)          */
-  double inner_rtol;      /* MFP_FP32_IR: relative tolerance of each inner FP32 solve   */
-  int32_t max_outer;      /* MFP_FP32_IR: cap on refinement steps                       */
+  double inner_rtol;      /* MFP_FP32_IR: residual reduction of the FP32 iteration between
+                             FP64 residual recomputations (0 < delta < 1; 0 -> 0.1)     */
+  int32_t max_outer;      /* MFP_FP32_IR: cap on FP64 residual recomputations (0 -> 1000) */
   const double* psi0;     /* optional DEVICE warm start (nodal psi, may be NULL)        */
   int32_t profile_every;  /* > 0: time every n-th apply launch with HIP events -> stats */
 } mfp_solver_opts;

@@ -192,7 +192,7 @@ class SolveResult:
 
 
 def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1e-12,
-              kmax=10 ** 7, check_every=64, inner_rtol=1e-4, max_outer=100, pair=(-1, -1),
+              kmax=10 ** 7, check_every=64, inner_rtol=0.1, max_outer=1000, pair=(-1, -1),
               sample_cap=None, ws: Optional[torch.Tensor] = None,
               allow_warn: bool = True, profile_every: int = 0) -> SolveResult:
     lib = load()

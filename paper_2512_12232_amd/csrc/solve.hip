@@ -204,15 +204,19 @@ __global__ void __launch_bounds__(BLOCK) k_resid(long long n, const double* __re
   if (threadIdx.x == 0) part[blockIdx.x] = bs;
 }
 
-// Single block.  Body sums of the last plain apply, then
-// mode 0: initial CG state for x = 0 (rb = -qb, r.r, stopping threshold, p_b = 0 and
-//         r.r = 1 in the "previous" slot so that the first beta multiplies zeros);
-// mode 1: squared norm of the recomputed true residual.
+// Single block.  Body sums of the last plain apply (q = K w, w = g + T x), then with
+// rr = ||b - A x||^2 = q.q over free nodes + sum_b qb^2:
+// mode 0: CG state for a start from the current iterate (x, xb of the current slot):
+//         rb = -qb, p_b = 0 and r.r = 1 in the "previous" slot so that the first
+//         direction is the residual; the first call also records rr0; the stopping
+//         threshold is stop_abs if positive, else rtol2 * rr0;
+// mode 1: record rr only (true residual at the end);
+// mode 2: record rr and rb = -qb (outer residual of iterative refinement).
 __global__ void __launch_bounds__(BLOCK) k_resid_finalize(const double* __restrict__ part,
                                                           int G2, const double* __restrict__ bpart,
                                                           const int* __restrict__ nslots,
                                                           DevState* st, int nb, int mode,
-                                                          double rtol2) {
+                                                          double rtol2, double stop_abs) {
   __shared__ double s_red[BLOCK / 64];
   __shared__ double s_qb[MFP_MAX_BODIES];
   body_sums(bpart, *nslots, nb, s_qb);
@@ -225,20 +229,119 @@ __global__ void __launch_bounds__(BLOCK) k_resid_finalize(const double* __restri
       st->qb[b] = s_qb[b];
       rbr += s_qb[b] * s_qb[b];
     }
+    const double rr = s + rbr;
+    st->rr_true = rr;
     if (mode == 0) {
+      const int it = (int)(st->iters & 1);
       for (int b = 0; b < nb; ++b) {
+        st->xb[0][b] = st->xb[it][b];
         st->rb[0][b] = -s_qb[b];
         st->pb[1][b] = 0.0;
       }
       st->rb_rr[0] = rbr;
       st->rr[1] = 1.0;
-      st->rr0 = s + rbr;
-      st->rr_stop = rtol2 * (s + rbr);
+      if (st->rr0 == 0.0) st->rr0 = rr;
+      st->rr_stop = stop_abs > 0.0 ? stop_abs : rtol2 * st->rr0;
       st->iters = 0;
       st->done = 0;
-    } else {
-      st->rr_true = s + rbr;
+    } else if (mode == 2) {
+      for (int b = 0; b < nb; ++b) st->rb[0][b] = -s_qb[b];
     }
+  }
+}
+
+// Inner (FP32) solve of A e = r for iterative refinement: r32 = r64 at every node
+// (zero away from free nodes), e = 0, previous direction 0, partials of r32.r32.
+__global__ void __launch_bounds__(BLOCK) k_inner_init(long long n, const double* __restrict__ r64,
+                                                      float* __restrict__ r32,
+                                                      float* __restrict__ e32,
+                                                      float* __restrict__ p32,
+                                                      double* __restrict__ part) {
+  __shared__ double s_red[BLOCK / 64];
+  double acc = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const float v = (float)r64[e];
+    r32[e] = v;
+    e32[e] = 0.f;
+    p32[e] = 0.f;
+    acc += (double)v * (double)v;
+  }
+  const double bs = block_sum(acc, s_red);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+}
+
+// Single block: inner CG state from the outer body residuals.
+__global__ void k_inner_finalize(const double* __restrict__ part, int G2, const DevState* outer,
+                                 DevState* in, int nb, double inner_rtol2, long long kmax) {
+  __shared__ double s_red[BLOCK / 64];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < G2; i += BLOCK) s += part[i];
+  s = block_sum(s, s_red);
+  if (threadIdx.x == 0) {
+    double rbr = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double v = outer->rb[0][b];
+      in->rb[0][b] = v;
+      in->xb[0][b] = 0.0;
+      in->pb[1][b] = 0.0;
+      rbr += v * v;
+    }
+    in->rb_rr[0] = rbr;
+    in->rr[1] = 1.0;
+    in->rr0 = s + rbr;
+    in->rr_stop = inner_rtol2 * (s + rbr);
+    in->iters = 0;
+    in->done = 0;
+    in->kmax = kmax;
+  }
+}
+
+// Reliable update of the mixed-precision solve: x64 += e32 (all nodes; only free
+// entries are ever read), e32 = 0, and the body corrections move from the inner
+// state (slot k&1) to the outer one.
+__global__ void k_ir_update(long long n, double* __restrict__ x64, float* __restrict__ e32,
+                            DevState* outer, DevState* in, int nb, int slot) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    x64[e] += (double)e32[e];
+    e32[e] = 0.f;
+  }
+  if (blockIdx.x == 0 && (int)threadIdx.x < nb) {
+    const int b = threadIdx.x;
+    outer->xb[outer->iters & 1][b] += in->xb[slot][b];
+    in->xb[slot][b] = 0.0;
+  }
+}
+
+// After a reliable update: the FP32 residual restarts from the FP64 one (r32 = r64,
+// partials of r32.r32 for the next iteration's reduction) and the inner body
+// residuals of slot k&1 take the FP64 values; the direction is kept.
+__global__ void __launch_bounds__(BLOCK) k_reliable_reset(long long n, const double* __restrict__ r64,
+                                                          float* __restrict__ r32,
+                                                          double* __restrict__ part,
+                                                          const DevState* outer, DevState* in,
+                                                          int nb, int slot, double delta2) {
+  __shared__ double s_red[BLOCK / 64];
+  double acc = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const float v = (float)r64[e];
+    r32[e] = v;
+    acc += (double)v * (double)v;
+  }
+  const double bs = block_sum(acc, s_red);
+  if (threadIdx.x == 0) part[blockIdx.x] = bs;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double rbr = 0.0;
+    for (int b = 0; b < nb; ++b) {
+      const double v = outer->rb[0][b];
+      in->rb[slot][b] = v;
+      rbr += v * v;
+    }
+    in->rb_rr[slot] = rbr;
+    in->rr_stop = delta2 * outer->rr_true;
+    in->done = 0;
   }
 }
 
@@ -473,6 +576,7 @@ struct SolveWs {
   double* part2;
   double* bpart;
   DevState* st;
+  DevState* st2;  // inner (FP32) solver state
   long long* nfree;
   mfp_circle* circ;
   int* boxes;
@@ -511,6 +615,7 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.part2 = bp.take<double>(GMAX);
   w.bpart = bp.take<double>((size_t)nt * (nb > 0 ? nb : 1));
   w.st = bp.take<DevState>(1);
+  w.st2 = bp.take<DevState>(1);
   w.nfree = bp.take<long long>(1);
   w.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
   w.boxes = bp.take<int>(4 * (nb > 0 ? nb : 1));
@@ -603,6 +708,13 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   s.q = w.q;
   s.nfree = w.nfree;
   MFP_TRY_HIP(hipMemsetAsync(w.st, 0, sizeof(DevState), st));
+  MFP_TRY_HIP(hipMemsetAsync(w.st2, 0, sizeof(DevState), st));
+  if (precision != MFP_FP64) {
+    // every padded entry of the FP32 vectors starts at zero (the apply writes owned
+    // nodes only)
+    for (float* f : {w.xf, w.rf, w.p0f, w.p1f, w.qf})
+      MFP_TRY_HIP(hipMemsetAsync(f, 0, sizeof(float) * w.L.n, st));
+  }
   MFP_TRY_HIP(hipMemsetAsync(w.nfree, 0, sizeof(long long), st));
   k_setup<<<grid_blocks(w.L.n), BLOCK, 0, st>>>(s);
   MFP_TRY_HIP(hipGetLastError());
@@ -700,35 +812,53 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
   return MFP_OK;
 }
 
-// Host loop of plain CG in FP64 on the prepared workspace.  Kernels are enqueued in
-// batches of `check_every` iterations; once the device sets its done flag the
-// remaining launches of the batch return immediately.  Returns the done code.
-static int cg_fp64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver_opts& o,
-                   hipStream_t st, long long* iters_out, long long* applies, double* apply_ms,
-                   long long* apply_samples) {
-  int tpb;
-  const int G = apply_blocks(w.L.ntasks(), &tpb);
+template <typename T>
+struct CgBufs {
+  T* x;
+  T* r;
+  T* p0;
+  T* p1;
+  T* q;
+  const T* dx;
+  const T* dy;
+  DevState* st;
+};
+
+struct CgCount {
+  long long iters = 0;     // iterations of the last run
+  long long applies = 0;   // applies over all runs
+  double tsum = 0.0;       // sampled apply durations (ms)
+  long long tcnt = 0;
+};
+
+// Host loop of CG on the prepared state (residual, direction 0, scalars): kernels are
+// enqueued in batches of `check_every` iterations; once the device sets its done flag
+// the remaining launches of the batch return immediately.  Returns the done code (1
+// converged, 2 breakdown, 3 kmax) or a negative status.
+template <typename T>
+static int cg_run(const mfp_grid& g, int nb, const SolveWs& w, const CgBufs<T>& B,
+                  const mfp_solver_opts& o, hipStream_t st, CgCount* cnt, long long k0 = 0) {
+  int gpb;
+  const int G = apply_blocks(w.L.ntasks(), &gpb);
   const int G2 = grid_blocks(w.L.n);
-  double* pbuf[2] = {w.p0, w.p1};
+  T* pbuf[2] = {B.p0, B.p1};
   const int every = o.check_every > 0 ? o.check_every : 50;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
-  // event pairs for the sampled apply launches of one batch
   const int nev = prof ? (every + prof - 1) / prof : 0;
   hipEvent_t ev[2 * 64];
   const int nev_c = nev > 64 ? 64 : nev;
   for (int i = 0; i < 2 * nev_c; ++i) MFP_TRY_HIP(hipEventCreate(&ev[i]));
-  double tsum = 0.0;
-  long long tcnt = 0;
-  long long k = 0;
+  long long k = k0;
   struct {
     int done;
     long long iters;
   } hs{0, 0};
-  ApplyArgs<double> a = make_apply_args<double>(w, g, nb, w.dx, w.dy);
-  a.r = w.r;
-  a.q = w.q;
+  ApplyArgs<T> a = make_apply_args<T>(w, g, nb, B.dx, B.dy);
+  a.r = B.r;
+  a.q = B.q;
   a.part2 = w.part2;
   a.G2 = G2;
+  a.st = B.st;
   int status = MFP_OK;
   while (true) {
     int used = 0;
@@ -738,18 +868,18 @@ static int cg_fp64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver
       a.k = k;
       const bool timed = prof && (m % prof == 0) && used < nev_c;
       if (timed) (void)hipEventRecord(ev[2 * used], st);
-      launch_apply<double, true>(w.L.hc, G, st, a);
+      launch_apply<T, true>(w.L.hc, G, st, a);
       if (timed) {
         (void)hipEventRecord(ev[2 * used + 1], st);
         ++used;
       }
-      k_update<double><<<G2, BLOCK, 0, st>>>(w.L.n, w.x, pbuf[(k + 1) & 1], w.r, w.q, w.part,
-                                             G, w.bpart, w.nslots, w.part2, w.st, nb, k);
+      k_update<T><<<G2, BLOCK, 0, st>>>(w.L.n, B.x, pbuf[(k + 1) & 1], B.r, B.q, w.part, G,
+                                        w.bpart, w.nslots, w.part2, B.st, nb, k);
     }
     hipError_t le = hipGetLastError();
-    if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &w.st->done, sizeof(int),
+    if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &B.st->done, sizeof(int),
                                               hipMemcpyDeviceToHost, st);
-    if (le == hipSuccess) le = hipMemcpyAsync(&hs.iters, &w.st->iters, sizeof(long long),
+    if (le == hipSuccess) le = hipMemcpyAsync(&hs.iters, &B.st->iters, sizeof(long long),
                                               hipMemcpyDeviceToHost, st);
     if (le == hipSuccess) le = hipStreamSynchronize(st);
     if (le != hipSuccess) {
@@ -764,39 +894,103 @@ static int cg_fp64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver
       if (hs.done && it >= hs.iters) break;
       float ms = 0.f;
       if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
-        tsum += ms;
-        ++tcnt;
+        cnt->tsum += ms;
+        ++cnt->tcnt;
       }
     }
     if (hs.done) break;
   }
   for (int i = 0; i < 2 * nev_c; ++i) (void)hipEventDestroy(ev[i]);
   if (status != MFP_OK) return status;
-  *iters_out = hs.iters;
-  *applies += hs.iters;
-  *apply_ms = tcnt ? tsum / tcnt : 0.0;
-  *apply_samples = tcnt;
+  cnt->iters = hs.iters;
+  cnt->applies += hs.iters - k0;
   return hs.done;
 }
 
-// b - A x in FP64 from the current iterate: w = g + T x, q = K w, r = -T^T q.
-// mode 0 (x = 0): also initialises the CG state; mode 1: records ||b - A x||^2.
+// b - A x in FP64 from the current iterate: w = g + T x, q = K w, r = -T^T q, then
+// k_resid_finalize in the given mode.
 static int residual64(const mfp_grid& g, int nb, const SolveWs& w, hipStream_t st, int mode,
-                      double rtol) {
-  int tpb;
-  const int G = apply_blocks(w.L.ntasks(), &tpb);
+                      double rtol, double stop_abs = 0.0) {
+  int gpb;
+  const int G = apply_blocks(w.L.ntasks(), &gpb);
   const int G2 = grid_blocks(w.L.n);
   k_form_w<double><<<G2, BLOCK, 0, st>>>(w.L.n, w.tag, w.x, w.g, w.st, w.p0);
   ApplyArgs<double> a = make_apply_args<double>(w, g, nb, w.dx, w.dy);
   a.src = w.p0;
   a.q = w.q;
   launch_apply<double, false>(w.L.hc, G, st, a);
-  k_resid<<<G2, BLOCK, 0, st>>>(w.L.n, w.q, w.r, w.part2, mode == 0 ? 1 : 0);
+  k_resid<<<G2, BLOCK, 0, st>>>(w.L.n, w.q, w.r, w.part2, mode != 1 ? 1 : 0);
   k_resid_finalize<<<1, BLOCK, 0, st>>>(w.part2, G2, w.bpart, w.nslots, w.st, nb, mode,
-                                        rtol * rtol);
+                                        rtol * rtol, stop_abs);
   MFP_TRY_HIP(hipGetLastError());
   if (mode == 0) MFP_TRY_HIP(hipMemsetAsync(w.p0, 0, sizeof(double) * w.L.n, st));
   return MFP_OK;
+}
+
+static int read_rr(const SolveWs& w, hipStream_t st, double* rr, double* rr0) {
+  double v[2];
+  MFP_TRY_HIP(hipMemcpyAsync(&v[0], &w.st->rr_true, sizeof(double), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipMemcpyAsync(&v[1], &w.st->rr0, sizeof(double), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  *rr = v[0];
+  *rr0 = v[1];
+  return MFP_OK;
+}
+
+// Mixed precision.  FP32 CG (FP32 vectors and element apply, FP64 scalars and body
+// sums) on the correction e, started from r32 = r64 = b - A x.  Each time the FP32
+// residual norm has dropped by `delta` since the last FP64 residual, x += e in FP64,
+// e = 0, the residual is recomputed with the FP64 apply and copied into r32, and the
+// CG iteration continues with its current direction.  MFP_FP32 runs one segment to
+// rtol and reports the FP64 residual.  Returns the final done code.
+static long long k0_cap(long long k) { return 2 * k > 2000 ? 2 * k : 2000; }
+
+static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver_opts& o,
+                       hipStream_t st, CgCount* cnt, long long* total_iters, long long* updates,
+                       bool* stagnated) {
+  const bool ir = o.precision == MFP_FP32_IR;
+  const double delta = ir ? (o.inner_rtol > 0 && o.inner_rtol < 1 ? o.inner_rtol : 0.1) : o.rtol;
+  const int max_upd = o.max_outer > 0 ? o.max_outer : 1000;
+  const int G2 = grid_blocks(w.L.n);
+  double rr = 0, rr0 = 0;
+  MFP_TRY(read_rr(w, st, &rr, &rr0));
+  if (rr <= o.rtol * o.rtol * rr0) return 1;
+  k_inner_init<<<G2, BLOCK, 0, st>>>(w.L.n, w.r, w.rf, w.xf, w.p0f, w.part2);
+  k_inner_finalize<<<1, BLOCK, 0, st>>>(w.part2, G2, w.st, w.st2, nb, delta * delta, o.kmax);
+  MFP_TRY_HIP(hipGetLastError());
+  CgBufs<float> B{w.xf, w.rf, w.p0f, w.p1f, w.qf, w.dxf, w.dyf, w.st2};
+  long long k = 0;
+  int code = 0;
+  while (true) {
+    // a segment may take at most max(2000, 2 x all iterations so far); one that does
+    // not reach its reduction within that is taken as FP32 stagnation
+    long long cap = ir ? k0_cap(k) : o.kmax;
+    long long kseg = k + cap < o.kmax ? k + cap : o.kmax;
+    MFP_TRY_HIP(hipMemcpyAsync(&w.st2->kmax, &kseg, sizeof(long long), hipMemcpyHostToDevice, st));
+    MFP_TRY_HIP(hipStreamSynchronize(st));
+    code = cg_run<float>(g, nb, w, B, o, st, cnt, k);
+    if (code < 0) return code;
+    const long long K = cnt->iters;
+    *total_iters = K;
+    // fold the correction into the FP64 iterate and recompute the true residual
+    k_ir_update<<<G2, BLOCK, 0, st>>>(w.L.n, w.x, w.xf, w.st, w.st2, nb, (int)(K & 1));
+    MFP_TRY_HIP(hipGetLastError());
+    MFP_TRY(residual64(g, nb, w, st, 2, o.rtol));
+    cnt->applies += 1;
+    ++*updates;
+    MFP_TRY(read_rr(w, st, &rr, &rr0));
+    if (rr <= o.rtol * o.rtol * rr0) return 1;
+    if (!ir) return code == 2 ? 2 : 3;
+    if (code == 3 && K >= o.kmax) return 3;
+    if (code != 1 || *updates >= max_upd) {
+      *stagnated = true;
+      return 0;
+    }
+    k_reliable_reset<<<G2, BLOCK, 0, st>>>(w.L.n, w.r, w.rf, w.part2, w.st, w.st2, nb,
+                                           (int)(K & 1), delta * delta);
+    MFP_TRY_HIP(hipGetLastError());
+    k = K;
+  }
 }
 
 extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
@@ -825,8 +1019,8 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
     set_error("U is not finite");
     return MFP_E_ARG;
   }
-  if (opts->precision != MFP_FP64) {
-    set_error("precision %d not available in this entry point", opts->precision);
+  if (opts->precision < MFP_FP64 || opts->precision > MFP_FP32_IR) {
+    set_error("unknown precision %d", opts->precision);
     return MFP_E_ARG;
   }
   if (opts->psi0) {
@@ -865,13 +1059,40 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   MFP_TRY_HIP(hipEventCreate(&e0));
   MFP_TRY_HIP(hipEventCreate(&e1));
   MFP_TRY_HIP(hipEventRecord(e0, st));
-  long long applies = 0;
+  CgCount cnt;
+  long long outer = 0, total_iters = 0;
+  int done = 1;
+  bool stagnated = false;
   MFP_TRY(residual64(g, nb, w, st, 0, opts->rtol));
-  applies += 1;
-  long long iters = 0, apply_samples = 0;
-  double apply_ms = 0.0;
-  const int done = cg_fp64(g, nb, w, *opts, st, &iters, &applies, &apply_ms, &apply_samples);
-  if (done < 0) return done;
+  cnt.applies += 1;
+  if (opts->precision == MFP_FP64) {
+    CgBufs<double> B{w.x, w.r, w.p0, w.p1, w.q, w.dx, w.dy, w.st};
+    done = cg_run<double>(g, nb, w, B, *opts, st, &cnt);
+    if (done < 0) return done;
+    total_iters = cnt.iters;
+  } else {
+    double rr = 0, rr0 = 0;
+    done = solve_mixed(g, nb, w, *opts, st, &cnt, &total_iters, &outer, &stagnated);
+    if (done < 0) return done;
+    if (opts->precision == MFP_FP32_IR && done == 0) {
+      // FP64 CG from the current iterate to the original target
+      stagnated = true;
+      MFP_TRY(read_rr(w, st, &rr, &rr0));
+      MFP_TRY(residual64(g, nb, w, st, 0, opts->rtol, opts->rtol * opts->rtol * rr0));
+      cnt.applies += 1;
+      long long left = opts->kmax - total_iters;
+      if (left < 1) left = 1;
+      MFP_TRY_HIP(hipMemcpyAsync(&w.st->kmax, &left, sizeof(long long), hipMemcpyHostToDevice, st));
+      MFP_TRY_HIP(hipStreamSynchronize(st));
+      CgBufs<double> B{w.x, w.r, w.p0, w.p1, w.q, w.dx, w.dy, w.st};
+      done = cg_run<double>(g, nb, w, B, *opts, st, &cnt);
+      if (done < 0) return done;
+      total_iters += cnt.iters;
+    }
+  }
+  const double apply_ms = cnt.tcnt ? cnt.tsum / cnt.tcnt : 0.0;
+  const long long apply_samples = cnt.tcnt;
+  long long applies = cnt.applies;
   MFP_TRY_HIP(hipEventRecord(e1, st));
   // true residual
   MFP_TRY(residual64(g, nb, w, st, 1, opts->rtol));
@@ -944,7 +1165,8 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   if (n_samples_h) *n_samples_h = nsamp;
   if (stats_h) {
     std::memset(stats_h, 0, sizeof(*stats_h));
-    stats_h->iters = hsd.iters;
+    stats_h->iters = total_iters;
+    stats_h->outer_iters = outer;
     stats_h->applies = applies;
     stats_h->n_free = nfree;
     stats_h->n_dof = nfree + nb;
@@ -960,9 +1182,13 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
     set_error("CG breakdown (p.Ap <= 0 or non-finite)");
     return MFP_E_BREAKDOWN;
   }
-  if (done == 3) {
-    set_error("kmax reached");
+  if (done == 3 || done == 0) {
+    set_error("kmax or the refinement cap reached before the tolerance");
     return MFP_W_NOCONV;
+  }
+  if (stagnated) {
+    set_error("FP32 refinement stagnated; finished with FP64 CG");
+    return MFP_W_STAGNATION;
   }
   return MFP_OK;
 }

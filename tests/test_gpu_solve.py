@@ -93,3 +93,44 @@ def test_symmetry_on_gpu(mfp):
     pb = np.array(res.psi_b)
     assert np.abs(pb[:3]).max() < 1e-9
     assert abs(pb[3] + pb[4]) < 1e-9
+
+
+IR_CASES = ["cyl64", "five96x48", "five_ragged130x67", "five_gap_lt_h_256x128"]
+
+
+@pytest.mark.parametrize("name", IR_CASES)
+def test_solve_fp32_refined_matches_oracle(mfp, name):
+    """FP32 element apply and vectors inside FP64 iterative refinement: psi relative
+    L2 error <= 1e-10 against the FP64 oracle."""
+    c = CASES[name]
+    res, ref, mesh = run_pair(mfp, c, rtol=1e-13, precision="fp32_ir")
+    assert res.status == 0, res.status
+    psi = res.psi.cpu().numpy()
+    err = np.linalg.norm(psi - ref.psi) / np.linalg.norm(ref.psi)
+    assert err <= 1e-10, err
+    assert res.stats["outer_iters"] >= 2
+    assert res.stats["relres_true"] <= 1e-13
+    np.testing.assert_allclose(res.psi_b, ref.psi_b, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("name", ["cyl64", "five96x48"])
+def test_solve_plain_fp32_within_1e_5(mfp, name):
+    c = CASES[name]
+    res, ref, mesh = run_pair(mfp, c, rtol=1e-6, precision="fp32")
+    psi = res.psi.cpu().numpy()
+    err = np.linalg.norm(psi - ref.psi) / np.linalg.norm(ref.psi)
+    assert err <= 1e-5, err
+
+
+def test_refinement_stagnation_falls_back_to_fp64(mfp):
+    """One allowed refinement step cannot reach 1e-13: the solver finishes with FP64
+    CG from the refined iterate and reports MFP_W_STAGNATION."""
+    c = CASES["five96x48"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, 200, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13,
+                        precision="fp32_ir", inner_rtol=1e-3, max_outer=1, pair=c.pair)
+    assert res.status == 2
+    mesh = O.conform(c.grid, c.circles, 200)
+    ref = O.solve(mesh, c.flow)
+    err = np.linalg.norm(res.psi.cpu().numpy() - ref.psi) / np.linalg.norm(ref.psi)
+    assert err <= 1e-10 and res.stats["relres_true"] <= 1e-13
