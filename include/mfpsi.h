@@ -101,7 +101,9 @@ typedef struct {
   double inner_rtol;      /* MFP_FP32_IR: residual reduction of the FP32 iteration between
                              FP64 residual recomputations (0 < delta < 1; 0 -> 0.1)     */
   int32_t max_outer;      /* MFP_FP32_IR: cap on FP64 residual recomputations (0 -> 1000) */
-  const double* psi0;     /* optional DEVICE warm start (nodal psi, may be NULL)        */
+  const double* psi0;     /* optional DEVICE warm start: nodal psi (free nodes) and the
+                             first node of each body (row-major) for psi_b; rtol is then
+                             relative to the residual of this start; may be NULL       */
   int32_t profile_every;  /* > 0: time every n-th apply launch with HIP events -> stats */
 } mfp_solver_opts;
 
@@ -188,6 +190,43 @@ int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbo
                   double* samples, int8_t* sample_body, int32_t sample_cap,
                   int32_t* n_samples_h, mfp_stats* stats_h,
                   void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for mfp_psi_grad. */
+size_t mfp_grad_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t precision);
+
+/* Adjoint of mfp_psi_solve with respect to the node displacements (the automated
+ * sensitivity analysis named in the paper's Conclusions as the next step).
+ * For a loss L(psi_b, CoPFI) with the node classification frozen:
+ *   adjoint solve   A lambda = dL/dy, A = T^T K T (the same symmetric operator, same
+ *                   solver and precision options), right-hand side non-zero only in
+ *                   the body rows: dL/dpsi_b = dL_dpsib_h[b] + dL_dcopfi dCoPFI/dpsi_b;
+ *   shape term      dL_ddisp = -d/dX [ lambda_full^T K(X) psi ] at every node
+ *                   (component-major like disp, device memory, overwritten);
+ *   explicit term   dL_dcentre_h[2b+1] (host, overwritten; x entries set to 0) holds
+ *                   dL_dcopfi times the derivative of CoPFI = Q / (U (cy_hi - cy_lo))
+ *                   with respect to the pair's centre heights.
+ * psi / psi_b_h are the outputs of mfp_psi_solve for the same inputs.  dL_dpsib_h may be
+ * NULL; pair indices < 0 or dL_dcopfi == 0 skip the CoPFI terms.  Add the mesh part
+ * with mfp_mesh_conform_grad. */
+int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                 const double* disp, const int8_t* kind, const int8_t* body,
+                 const mfp_flow* flow, const mfp_solver_opts* opts, const double* psi,
+                 const double* psi_b_h, const double* dL_dpsib_h, double dL_dcopfi,
+                 int32_t pair_lo, int32_t pair_hi, double* dL_ddisp, double* dL_dcentre_h,
+                 mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for mfp_mesh_conform_grad. */
+size_t mfp_conform_grad_workspace_size(const mfp_grid* grid, int32_t nbody);
+
+/* Adjoint of mfp_mesh_conform (frozen classification): given dL/d(disp) at every node
+ * (device, component-major), back-propagates through the nsweeps Jacobi sweeps
+ * (transposed sweeps) and the radial projection of the snapped nodes, and ADDS
+ * dL/d(cx_b, cy_b) to dL_dcentre_h[2b], [2b+1] and dL/dr_b to dL_dradius_h[b] (host;
+ * dL_dradius_h may be NULL).  kind/body are the outputs of mfp_mesh_conform. */
+int mfp_mesh_conform_grad(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                          int32_t nsweeps, const int8_t* kind, const int8_t* body,
+                          const double* dL_ddisp, double* dL_dcentre_h, double* dL_dradius_h,
+                          void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

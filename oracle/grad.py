@@ -142,6 +142,30 @@ def projection_jacobian(grid, circles, kind, body):
     return sel, bb, J
 
 
+def conform_grad(grid, circles, nsweeps, gX, kind_body=None):
+    """Back-propagate a gradient with respect to the final displacements (shape
+    (2, nodes)) through the sweeps and the projection: returns (dL/dc (nbody, 2),
+    dL/dr (nbody,)).  Radius: d(d0)/dr = u."""
+    kind, body = classify(grid, circles) if kind_body is None else kind_body
+    MT = sweep_matrix(grid, kind).T.tocsr()
+    gd0 = np.array(gX, dtype=float).reshape(2, -1).copy()
+    for _ in range(nsweeps):
+        gd0 = np.stack([MT @ gd0[0], MT @ gd0[1]])
+    sel, bb, Jp = projection_jacobian(grid, circles, kind, body)
+    v = np.stack([gd0[0][sel], gd0[1][sel]], axis=1)
+    gc = np.zeros((len(circles), 2))
+    np.add.at(gc, bb, np.einsum("mij,mi->mj", Jp, v))
+    X, Y = node_coords(grid)
+    cx = np.array([circles[b][0] for b in bb])
+    cy = np.array([circles[b][1] for b in bb])
+    dx = X.ravel()[sel] - cx
+    dy = Y.ravel()[sel] - cy
+    rho = np.sqrt(dx * dx + dy * dy)
+    gr = np.zeros(len(circles))
+    np.add.at(gr, bb, (dx * v[:, 0] + dy * v[:, 1]) / rho)
+    return gc, gr
+
+
 def adjoint_gradient(grid, circles, flow, pair, nsweeps=200):
     """Discrete adjoint of the frozen-topology map (see module docstring).
 
@@ -161,22 +185,13 @@ def adjoint_gradient(grid, circles, flow, pair, nsweeps=200):
     lam_full = sol.T @ lam
     # dJ/dX = -d(lam^T K(X) psi)/dX
     gX = -element_shape_gradient(mesh, lam_full, sol.psi)
-    # back through the sweeps
-    M = sweep_matrix(grid, mesh.kind)
-    MT = M.T.tocsr()
-    gd0 = gX.copy()
-    for _ in range(nsweeps):
-        gd0 = np.stack([MT @ gd0[0], MT @ gd0[1]])
-    sel, bb, Jp = projection_jacobian(grid, circles, mesh.kind, mesh.body)
-    v = np.stack([gd0[0][sel], gd0[1][sel]], axis=1)      # (m, 2)
-    contrib = np.einsum("mij,mi->mj", Jp, v)                # (dd0/dc)^T v
-    gc = np.zeros((len(circles), 2))
-    np.add.at(gc, bb, contrib)
+    # back through the sweeps and the projection
+    gc, _ = conform_grad(grid, circles, nsweeps, gX, (mesh.kind, mesh.body))
     # explicit dependence of CoPFI on y_lo, y_hi
     gc[hi, 1] += -J / (yhi - ylo)
     gc[lo, 1] += J / (yhi - ylo)
     gdelta = gc[hi, 1] - gc[lo, 1]
-    return gc, gdelta, dict(J=J, Q=Q, gX=gX, gd0=gd0, lam=lam_full, sol=sol, mesh=mesh)
+    return gc, gdelta, dict(J=J, Q=Q, gX=gX, lam=lam_full, sol=sol, mesh=mesh)
 
 
 def fd_gradient(grid, circles, flow, pair, nsweeps=200, step=1e-5, freeze=True):

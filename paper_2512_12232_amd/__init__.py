@@ -6,7 +6,10 @@ derived body stream-function values, surface velocities, inter-body flow rate
 and CoPFI.  All arithmetic runs in the library's HIP kernels.
 """
 from .binding import (MfpError, check_geometry, element_apply, last_error, load,
-                      mesh_conform, psi_solve, solve_workspace_size, EXPORTS)
+                      mesh_conform, mesh_conform_grad, psi_grad, psi_solve,
+                      solve_workspace_size, EXPORTS)
+from .autograd import CoPFIFunction, copfi
 
 __all__ = ["MfpError", "check_geometry", "element_apply", "last_error", "load",
-           "mesh_conform", "psi_solve", "solve_workspace_size", "EXPORTS"]
+           "mesh_conform", "mesh_conform_grad", "psi_grad", "psi_solve",
+           "solve_workspace_size", "EXPORTS", "CoPFIFunction", "copfi"]

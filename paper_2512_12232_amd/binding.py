@@ -30,6 +30,8 @@ _PREC = {"fp64": FP64, "fp32": FP32, "fp32_ir": FP32_IR}
 EXPORTS = [
     "mfp_last_error", "mfp_check_geometry", "mfp_conform_workspace_size",
     "mfp_mesh_conform", "mfp_solve_workspace_size", "mfp_element_apply", "mfp_psi_solve",
+    "mfp_grad_workspace_size", "mfp_psi_grad", "mfp_conform_grad_workspace_size",
+    "mfp_mesh_conform_grad",
 ]
 
 
@@ -92,6 +94,18 @@ def load(path: str = LIB_PATH):
         POINTER(MfpFlow), POINTER(MfpSolverOpts), c_int32, c_int32, c_void_p,
         POINTER(c_double), POINTER(c_double), POINTER(c_double), c_void_p, c_void_p, c_int32,
         POINTER(c_int32), POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
+    lib.mfp_grad_workspace_size.restype = c_size_t
+    lib.mfp_grad_workspace_size.argtypes = [POINTER(MfpGrid), c_int32, c_int32]
+    lib.mfp_psi_grad.argtypes = [
+        POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_void_p, c_void_p, c_void_p,
+        POINTER(MfpFlow), POINTER(MfpSolverOpts), c_void_p, POINTER(c_double), c_void_p,
+        c_double, c_int32, c_int32, c_void_p, POINTER(c_double), POINTER(MfpStats), c_void_p,
+        c_size_t, c_void_p]
+    lib.mfp_conform_grad_workspace_size.restype = c_size_t
+    lib.mfp_conform_grad_workspace_size.argtypes = [POINTER(MfpGrid), c_int32]
+    lib.mfp_mesh_conform_grad.argtypes = [
+        POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
+        POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p]
     _lib = lib
     return lib
 
@@ -194,7 +208,8 @@ class SolveResult:
 def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1e-12,
               kmax=10 ** 7, check_every=64, inner_rtol=0.1, max_outer=1000, pair=(-1, -1),
               sample_cap=None, ws: Optional[torch.Tensor] = None,
-              allow_warn: bool = True, profile_every: int = 0) -> SolveResult:
+              allow_warn: bool = True, profile_every: int = 0,
+              psi0: Optional[torch.Tensor] = None) -> SolveResult:
     lib = load()
     g = make_grid(grid)
     c = make_circles(circles)
@@ -202,7 +217,8 @@ def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
     f = make_flow(flow)
     prec = _PREC[precision]
     o = MfpSolverOpts(prec, float(rtol), int(kmax), int(check_every), float(inner_rtol),
-                      int(max_outer), None, int(profile_every))
+                      int(max_outer), _ptr(psi0) if psi0 is not None else None,
+                      int(profile_every))
     n = (g.nx + 1) * (g.ny + 1)
     dev = disp.device
     psi = torch.empty(n, dtype=torch.float64, device=dev)
@@ -232,3 +248,59 @@ def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
 def solve_workspace_size(grid, nbody: int, precision: str = "fp64") -> int:
     g = make_grid(grid)
     return load().mfp_solve_workspace_size(byref(g), int(nbody), _PREC[precision])
+
+
+def _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer):
+    return MfpSolverOpts(_PREC[precision], float(rtol), int(kmax), int(check_every),
+                         float(inner_rtol), int(max_outer), None, 0)
+
+
+def psi_grad(grid, circles, disp, kind, body, flow, psi, psi_b, *, dL_dpsib=None,
+             dL_dcopfi=0.0, pair=(-1, -1), precision="fp64", rtol=1e-12, kmax=10 ** 7,
+             check_every=64, inner_rtol=0.1, max_outer=1000):
+    """Adjoint solve + shape derivative.  Returns (dL_ddisp device tensor [2*nodes],
+    explicit dL/dcentre list of (dx, dy) per body, stats, status)."""
+    lib = load()
+    g = make_grid(grid)
+    c = make_circles(circles)
+    nb = len(circles)
+    f = make_flow(flow)
+    o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer)
+    n = (g.nx + 1) * (g.ny + 1)
+    dev = disp.device
+    out = torch.empty(2 * n, dtype=torch.float64, device=dev)
+    pb = (c_double * max(nb, 1))(*[float(v) for v in psi_b])
+    dpb = None
+    if dL_dpsib is not None:
+        dpb = (c_double * max(nb, 1))(*[float(v) for v in dL_dpsib])
+    dcen = (c_double * max(2 * nb, 1))()
+    st = MfpStats()
+    ws = workspace(lib.mfp_grad_workspace_size(byref(g), nb, _PREC[precision]), dev)
+    status = _check(lib.mfp_psi_grad(
+        byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o), _ptr(psi),
+        pb, dpb, float(dL_dcopfi), int(pair[0]), int(pair[1]), _ptr(out), dcen, byref(st),
+        _ptr(ws), ws.numel(), _stream()))
+    stats = {k: getattr(st, k) for k, _ in MfpStats._fields_}
+    return out, [(dcen[2 * b], dcen[2 * b + 1]) for b in range(nb)], stats, status
+
+
+def mesh_conform_grad(grid, circles, kind, body, dL_ddisp, nsweeps=200, dL_dcentre=None,
+                      dL_dradius=None):
+    """Adds the mesh part of the gradient; returns (dL_dcentre [(dx, dy)], dL_dradius)."""
+    lib = load()
+    g = make_grid(grid)
+    c = make_circles(circles)
+    nb = len(circles)
+    dcen = (c_double * max(2 * nb, 1))()
+    drad = (c_double * max(nb, 1))()
+    if dL_dcentre is not None:
+        for b, (gx, gy) in enumerate(dL_dcentre):
+            dcen[2 * b], dcen[2 * b + 1] = float(gx), float(gy)
+    if dL_dradius is not None:
+        for b, v in enumerate(dL_dradius):
+            drad[b] = float(v)
+    ws = workspace(lib.mfp_conform_grad_workspace_size(byref(g), nb), dL_ddisp.device)
+    _check(lib.mfp_mesh_conform_grad(byref(g), c, nb, int(nsweeps), _ptr(kind), _ptr(body),
+                                     _ptr(dL_ddisp), dcen, drad, _ptr(ws), ws.numel(),
+                                     _stream()))
+    return [(dcen[2 * b], dcen[2 * b + 1]) for b in range(nb)], [drad[b] for b in range(nb)]

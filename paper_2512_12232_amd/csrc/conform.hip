@@ -166,6 +166,72 @@ static Box union_box(const mfp_grid& g, const mfp_circle* c, int nb, int pad, in
   return u;
 }
 
+// Transposed Jacobi sweep (adjoint of k_jacobi_sweep): with upd(n) = fluid node off
+// the outer boundary, g_new[m] = [m fixed] g[m] + sum over update neighbours n of
+// w(n, m) g[n].
+__global__ void k_jacobi_sweep_T(int nx, int ny, int i0, int j0, int bw, int bh, double wx,
+                                 double wy, const int8_t* __restrict__ kind,
+                                 const double* __restrict__ src, double* __restrict__ dst) {
+  const long long nn = (long long)(nx + 1) * (ny + 1);
+  const int i = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  const int j = j0 + (int)blockIdx.y;
+  if (i >= i0 + bw || (int)blockIdx.y >= bh) return;
+  const long long n = (long long)j * (nx + 1) + i;
+  auto upd = [&](int ii, int jj) {
+    return ii >= 1 && ii <= nx - 1 && jj >= 1 && jj <= ny - 1 &&
+           kind[(long long)jj * (nx + 1) + ii] == MFP_FLUID;
+  };
+  const bool ue = upd(i + 1, j), uw = upd(i - 1, j), un = upd(i, j + 1), us = upd(i, j - 1);
+  const bool self = upd(i, j);
+  for (int c = 0; c < 2; ++c) {
+    const double* s = src + c * nn;
+    const double ge = ue ? s[n + 1] : 0.0, gw = uw ? s[n - 1] : 0.0;
+    const double gn = un ? s[n + nx + 1] : 0.0, gs = us ? s[n - nx - 1] : 0.0;
+    dst[n + c * nn] = (self ? 0.0 : s[n]) + (wx * (ge + gw) + wy * (gn + gs));
+  }
+}
+
+// One block per body: derivatives of the snapped displacements d0 = c + (r/rho)(x - c) - x
+// with respect to the centre (I - (r/rho)(I - u u^T), u = (x - c)/rho) and the radius
+// (u), applied to the incoming gradient and summed over the body's snapped nodes.
+__global__ void __launch_bounds__(BLOCK) k_project_grad(GridD g, const mfp_circle* __restrict__ circ,
+                                                        const int* __restrict__ boxes,
+                                                        const int8_t* __restrict__ kind,
+                                                        const int8_t* __restrict__ body,
+                                                        const double* __restrict__ gd,
+                                                        double* __restrict__ out) {
+  __shared__ double s_red[3][BLOCK / 64];
+  const int b = blockIdx.x;
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  const int i0 = boxes[4 * b], i1 = boxes[4 * b + 1], j0 = boxes[4 * b + 2], j1 = boxes[4 * b + 3];
+  const int bw = i1 - i0 + 1;
+  const long long total = (i1 >= i0 && j1 >= j0) ? (long long)bw * (j1 - j0 + 1) : 0;
+  const double cx = circ[b].cx, cy = circ[b].cy, r = circ[b].r;
+  double acx = 0.0, acy = 0.0, ar = 0.0;
+  for (long long e = threadIdx.x; e < total; e += BLOCK) {
+    const int i = i0 + (int)(e % bw), j = j0 + (int)(e / bw);
+    const long long n = (long long)j * (g.nx + 1) + i;
+    if (kind[n] != MFP_SNAPPED || body[n] != b) continue;
+    const double dx = (g.x0 + (double)i * g.hx) - cx, dy = (g.y0 + (double)j * g.hy) - cy;
+    const double rho = sqrt(dx * dx + dy * dy);
+    const double ux = dx / rho, uy = dy / rho, f = r / rho;
+    const double gx = gd[n], gy = gd[n + nn];
+    acx += (1.0 - f * (1.0 - ux * ux)) * gx + f * ux * uy * gy;
+    acy += f * ux * uy * gx + (1.0 - f * (1.0 - uy * uy)) * gy;
+    ar += ux * gx + uy * gy;
+  }
+  double v[3] = {acx, acy, ar};
+  for (int k = 0; k < 3; ++k) {
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+    if ((threadIdx.x & 63) == 0) s_red[k][threadIdx.x >> 6] = v[k];
+  }
+  __syncthreads();
+  if (threadIdx.x < 3) {
+    const int k = threadIdx.x;
+    out[3 * b + k] = (s_red[k][0] + s_red[k][1]) + (s_red[k][2] + s_red[k][3]);
+  }
+}
+
 struct ConformWs {
   mfp_circle* circ;
   double* tmp;  // second displacement buffer
@@ -267,6 +333,89 @@ extern "C" int mfp_mesh_conform(const mfp_grid* grid, const mfp_circle* circles_
   if (bad) {
     set_error("tangled mesh: an active cell has a non-positive Jacobian determinant");
     return MFP_E_TANGLED;
+  }
+  return MFP_OK;
+}
+
+extern "C" size_t mfp_conform_grad_workspace_size(const mfp_grid* grid, int32_t nbody) {
+  if (!grid || grid->nx < 2 || grid->ny < 2) return 0;
+  Bump bp(nullptr);
+  const size_t nn = (size_t)(grid->nx + 1) * (grid->ny + 1);
+  bp.take<double>(2 * nn);
+  bp.take<double>(2 * nn);
+  bp.take<mfp_circle>(nbody > 0 ? nbody : 1);
+  bp.take<int>(4 * (nbody > 0 ? nbody : 1));
+  bp.take<double>(3 * (nbody > 0 ? nbody : 1));
+  return bp.off + 256;
+}
+
+extern "C" int mfp_mesh_conform_grad(const mfp_grid* grid, const mfp_circle* circles_h,
+                                     int32_t nbody, int32_t nsweeps, const int8_t* kind,
+                                     const int8_t* body, const double* dL_ddisp,
+                                     double* dL_dcentre_h, double* dL_dradius_h, void* ws,
+                                     size_t ws_bytes, void* stream_) {
+  clear_error();
+  MFP_TRY(check_geometry(grid, circles_h, nbody));
+  if (nsweeps < 0 || !kind || !body || !dL_ddisp || !ws || (nbody > 0 && !dL_dcentre_h)) {
+    set_error("bad argument");
+    return MFP_E_ARG;
+  }
+  const size_t need = mfp_conform_grad_workspace_size(grid, nbody);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  if (nbody == 0) return MFP_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  const mfp_grid& g = *grid;
+  const GridD gd = to_dev(g);
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  Bump bp(ws);
+  double* A = bp.take<double>(2 * nn);
+  double* B = bp.take<double>(2 * nn);
+  mfp_circle* circ = bp.take<mfp_circle>(nbody);
+  int* boxes = bp.take<int>(4 * nbody);
+  double* out = bp.take<double>(3 * nbody);
+  int hbox[4 * MFP_MAX_BODIES];
+  for (int b = 0; b < nbody; ++b) {
+    const Box x = circle_box(g, circles_h[b], 1, 0, g.nx, 0, g.ny);
+    hbox[4 * b] = x.i0;
+    hbox[4 * b + 1] = x.i1;
+    hbox[4 * b + 2] = x.j0;
+    hbox[4 * b + 3] = x.j1;
+  }
+  MFP_TRY_HIP(hipMemcpyAsync(circ, circles_h, sizeof(mfp_circle) * nbody, hipMemcpyHostToDevice, st));
+  MFP_TRY_HIP(hipMemcpyAsync(boxes, hbox, sizeof(int) * 4 * nbody, hipMemcpyHostToDevice, st));
+  MFP_TRY_HIP(hipMemcpyAsync(A, dL_ddisp, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
+  MFP_TRY_HIP(hipMemcpyAsync(B, dL_ddisp, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
+  const double hx = gd.hx, hy = gd.hy;
+  const double sw = 2.0 * (hx * hx + hy * hy);
+  const double wx = (hy * hy) / sw, wy = (hx * hx) / sw;
+  // Transposed sweep s only needs nodes within nsweeps - s of a snapped node (the
+  // snapped values after the last sweep are all that is read).
+  double* a = A;
+  double* b = B;
+  for (int s = 1; s <= nsweeps; ++s) {
+    const Box bx = union_box(g, circles_h, nbody, nsweeps - s + 2, 1, g.nx - 1, 1, g.ny - 1);
+    if (!bx.empty()) {
+      const int bw = bx.i1 - bx.i0 + 1, bh = bx.j1 - bx.j0 + 1;
+      dim3 grd((bw + BLOCK - 1) / BLOCK, bh);
+      k_jacobi_sweep_T<<<grd, BLOCK, 0, st>>>(g.nx, g.ny, bx.i0, bx.j0, bw, bh, wx, wy, kind, a, b);
+      MFP_TRY_HIP(hipGetLastError());
+    }
+    double* t = a;
+    a = b;
+    b = t;
+  }
+  k_project_grad<<<nbody, BLOCK, 0, st>>>(gd, circ, boxes, kind, body, a, out);
+  MFP_TRY_HIP(hipGetLastError());
+  double hout[3 * MFP_MAX_BODIES];
+  MFP_TRY_HIP(hipMemcpyAsync(hout, out, sizeof(double) * 3 * nbody, hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  for (int k = 0; k < nbody; ++k) {
+    dL_dcentre_h[2 * k] += hout[3 * k];
+    dL_dcentre_h[2 * k + 1] += hout[3 * k + 1];
+    if (dL_dradius_h) dL_dradius_h[k] += hout[3 * k + 2];
   }
   return MFP_OK;
 }

@@ -109,6 +109,7 @@ struct DevState {
   double xb[2][MFP_MAX_BODIES];          // body unknowns of iterate k, slot k&1
   double rb[2][MFP_MAX_BODIES];          // body residuals of iterate k, slot k&1
   double qb[MFP_MAX_BODIES];             // body sums of the last plain apply
+  double bb[MFP_MAX_BODIES];             // extra right-hand side of the body rows (adjoint)
   double rr0, rr_stop, rr_final, rr_true;
   double alpha, beta, pq;
   double copfi, Q;

@@ -20,6 +20,7 @@
 #include <type_traits>
 #include <vector>
 
+#include "adjoint.h"
 #include "apply.h"
 
 namespace mfp {
@@ -224,10 +225,12 @@ __global__ void __launch_bounds__(BLOCK) k_resid_finalize(const double* __restri
   for (int i = threadIdx.x; i < G2; i += BLOCK) s += part[i];
   s = block_sum(s, s_red);
   if (threadIdx.x == 0) {
+    // body residuals: right-hand side of the body rows minus their sums of K w
     double rbr = 0.0;
     for (int b = 0; b < nb; ++b) {
       st->qb[b] = s_qb[b];
-      rbr += s_qb[b] * s_qb[b];
+      const double v = st->bb[b] - s_qb[b];
+      rbr += v * v;
     }
     const double rr = s + rbr;
     st->rr_true = rr;
@@ -235,7 +238,7 @@ __global__ void __launch_bounds__(BLOCK) k_resid_finalize(const double* __restri
       const int it = (int)(st->iters & 1);
       for (int b = 0; b < nb; ++b) {
         st->xb[0][b] = st->xb[it][b];
-        st->rb[0][b] = -s_qb[b];
+        st->rb[0][b] = st->bb[b] - s_qb[b];
         st->pb[1][b] = 0.0;
       }
       st->rb_rr[0] = rbr;
@@ -245,7 +248,7 @@ __global__ void __launch_bounds__(BLOCK) k_resid_finalize(const double* __restri
       st->iters = 0;
       st->done = 0;
     } else if (mode == 2) {
-      for (int b = 0; b < nb; ++b) st->rb[0][b] = -s_qb[b];
+      for (int b = 0; b < nb; ++b) st->rb[0][b] = st->bb[b] - s_qb[b];
     }
   }
 }
@@ -993,21 +996,48 @@ static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_so
   }
 }
 
-extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
-                             const double* disp, const int8_t* kind, const int8_t* body,
-                             const mfp_flow* flow, const mfp_solver_opts* opts,
-                             int32_t pair_lo, int32_t pair_hi, double* psi, double* psi_b_h,
-                             double* Q_h, double* copfi_h, double* samples,
-                             int8_t* sample_body, int32_t sample_cap, int32_t* n_samples_h,
-                             mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream_) {
-  clear_error();
-  MFP_TRY(check_geometry(grid, circles_h, nbody));
-  if (!disp || !kind || !body || !flow || !opts || !psi || !ws) {
-    set_error("NULL argument");
-    return MFP_E_ARG;
+// Warm start: body unknowns from the first node (row-major) of each body in psi0.
+__global__ void k_warm_xb(int nx, int ny, int nb, const int* __restrict__ boxes,
+                          const int8_t* __restrict__ body, const double* __restrict__ psi0,
+                          DevState* st) {
+  const int b = threadIdx.x;
+  if (b >= nb) return;
+  const int i0 = boxes[4 * b], i1 = boxes[4 * b + 1], j0 = boxes[4 * b + 2], j1 = boxes[4 * b + 3];
+  for (int j = j0; j <= j1; ++j)
+    for (int i = i0; i <= i1; ++i) {
+      const long long n = (long long)j * (nx + 1) + i;
+      if (body[n] == b) {
+        st->xb[0][b] = psi0[n];
+        return;
+      }
+    }
+}
+
+// x = psi0 at free nodes (padded layout).
+__global__ void k_warm_x(Layout L, int nx, int ny, const int8_t* __restrict__ tag,
+                         const double* __restrict__ psi0, double* __restrict__ x) {
+  const long long nn = (long long)(nx + 1) * (ny + 1);
+  for (long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x; nd < nn;
+       nd += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(nd / (nx + 1)), i = (int)(nd - (long long)j * (nx + 1));
+    const long long e = (long long)(j + 1) * L.P + (i + 1);
+    if (tag[e] == TAG_FREE) x[e] = psi0[nd];
   }
-  if (nbody > 0 && !psi_b_h) {
-    set_error("psi_b_h is NULL");
+}
+
+struct SolveInfo {
+  int done = 0;
+  bool stagnated = false;
+  long long iters = 0, outer = 0, applies = 0, apply_samples = 0;
+  double apply_ms = 0.0, solve_ms = 0.0;
+};
+
+static int check_solve_args(const mfp_grid* grid, const mfp_circle* circles_h, int nbody,
+                            const double* disp, const int8_t* kind, const int8_t* body,
+                            const mfp_flow* flow, const mfp_solver_opts* opts, const void* ws) {
+  MFP_TRY(check_geometry(grid, circles_h, nbody));
+  if (!disp || !kind || !body || !flow || !opts || !ws) {
+    set_error("NULL argument");
     return MFP_E_ARG;
   }
   for (int k = 0; k < 4; ++k)
@@ -1023,37 +1053,50 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
     set_error("unknown precision %d", opts->precision);
     return MFP_E_ARG;
   }
-  if (opts->psi0) {
-    set_error("warm start not supported");
-    return MFP_E_ARG;
-  }
   if (!(opts->rtol > 0.0) || opts->kmax < 1) {
     set_error("rtol must be > 0 and kmax >= 1");
     return MFP_E_ARG;
   }
-  if (pair_lo >= nbody || pair_hi >= nbody) {
-    set_error("pair index out of range");
-    return MFP_E_ARG;
+  return MFP_OK;
+}
+
+static void circle_boxes(const mfp_grid& g, const mfp_circle* c, int nb, int* boxes) {
+  for (int b = 0; b < nb; ++b) {
+    const Box bx = circle_box(g, c[b], 1, 0, g.nx - 1, 0, g.ny - 1);
+    boxes[4 * b] = bx.i0;
+    boxes[4 * b + 1] = bx.i1;
+    boxes[4 * b + 2] = bx.j0;
+    boxes[4 * b + 3] = bx.j1;
   }
-  if (sample_cap < 0 || (sample_cap > 0 && (!samples || !sample_body))) {
-    set_error("bad sample buffers");
-    return MFP_E_ARG;
-  }
-  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr);
-  if (ws_bytes < need) {
-    set_error("workspace too small: %zu < %zu", ws_bytes, need);
-    return MFP_E_WORKSPACE;
-  }
-  hipStream_t st = static_cast<hipStream_t>(stream_);
-  SolveWs w;
-  solve_layout(grid, nbody, opts->precision, ws, &w);
-  const mfp_grid& g = *grid;
-  const int nb = nbody;
+}
+
+// Setup, CG (FP64, or FP32 with FP64 refinement and FP64 fallback), true residual.
+// bb_h: extra right-hand side of the body rows (NULL: none); zero_g: homogeneous
+// Dirichlet data (adjoint).
+static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, const double* disp,
+                      const int8_t* body, const mfp_flow* flow, const mfp_solver_opts* opts,
+                      const double* bb_h, bool zero_g, const SolveWs& w, hipStream_t st,
+                      SolveInfo* info) {
   MFP_TRY(setup(g, circles_h, nb, disp, body, flow, opts->precision, w, st));
-  // kmax into the device state
+  if (zero_g) MFP_TRY_HIP(hipMemsetAsync(w.g, 0, sizeof(double) * w.L.n, st));
+  if (bb_h && nb > 0)
+    MFP_TRY_HIP(hipMemcpyAsync(w.st->bb, bb_h, sizeof(double) * nb, hipMemcpyHostToDevice, st));
   long long kmax = opts->kmax;
   MFP_TRY_HIP(hipMemcpyAsync(&w.st->kmax, &kmax, sizeof(long long), hipMemcpyHostToDevice, st));
-  MFP_TRY_HIP(hipStreamSynchronize(st));  // kmax is a stack value
+  if (nb > 0) {
+    int boxes[4 * MFP_MAX_BODIES];
+    circle_boxes(g, circles_h, nb, boxes);
+    MFP_TRY_HIP(hipMemcpyAsync(w.boxes, boxes, sizeof(int) * 4 * nb, hipMemcpyHostToDevice, st));
+    MFP_TRY_HIP(hipMemcpyAsync(w.circ, circles_h, sizeof(mfp_circle) * nb,
+                               hipMemcpyHostToDevice, st));
+  }
+  if (opts->psi0) {
+    const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+    k_warm_x<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, opts->psi0, w.x);
+    if (nb > 0) k_warm_xb<<<1, 64, 0, st>>>(g.nx, g.ny, nb, w.boxes, body, opts->psi0, w.st);
+    MFP_TRY_HIP(hipGetLastError());
+  }
+  MFP_TRY_HIP(hipStreamSynchronize(st));  // host-side staging buffers above
 
   hipEvent_t e0, e1;
   MFP_TRY_HIP(hipEventCreate(&e0));
@@ -1063,6 +1106,7 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   long long outer = 0, total_iters = 0;
   int done = 1;
   bool stagnated = false;
+  // rtol is relative to the residual of the starting iterate (zero, or psi0)
   MFP_TRY(residual64(g, nb, w, st, 0, opts->rtol));
   cnt.applies += 1;
   if (opts->precision == MFP_FP64) {
@@ -1090,14 +1134,100 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
       total_iters += cnt.iters;
     }
   }
-  const double apply_ms = cnt.tcnt ? cnt.tsum / cnt.tcnt : 0.0;
-  const long long apply_samples = cnt.tcnt;
-  long long applies = cnt.applies;
   MFP_TRY_HIP(hipEventRecord(e1, st));
-  // true residual
   MFP_TRY(residual64(g, nb, w, st, 1, opts->rtol));
-  applies += 1;
-  // outputs
+  cnt.applies += 1;
+  MFP_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  info->done = done;
+  info->stagnated = stagnated;
+  info->iters = total_iters;
+  info->outer = outer;
+  info->applies = cnt.applies;
+  info->apply_ms = cnt.tcnt ? cnt.tsum / cnt.tcnt : 0.0;
+  info->apply_samples = cnt.tcnt;
+  info->solve_ms = ms;
+  return MFP_OK;
+}
+
+static int finish_status(const SolveInfo& info) {
+  if (info.done == 2) {
+    set_error("CG breakdown (p.Ap <= 0 or non-finite)");
+    return MFP_E_BREAKDOWN;
+  }
+  if (info.done == 3 || info.done == 0) {
+    set_error("kmax or the refinement cap reached before the tolerance");
+    return MFP_W_NOCONV;
+  }
+  if (info.stagnated) {
+    set_error("FP32 refinement stagnated; finished with FP64 CG");
+    return MFP_W_STAGNATION;
+  }
+  return MFP_OK;
+}
+
+static int fill_stats(const SolveWs& w, const SolveInfo& info, int nb, const DevState& hsd,
+                      hipStream_t st, mfp_stats* stats_h) {
+  if (!stats_h) return MFP_OK;
+  long long nfree = 0;
+  MFP_TRY_HIP(hipMemcpyAsync(&nfree, w.nfree, sizeof(long long), hipMemcpyDeviceToHost, st));
+  std::vector<uint8_t> plain(w.L.ntasks());
+  MFP_TRY_HIP(hipMemcpyAsync(plain.data(), w.tplain, plain.size(), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  long long nplain = 0;
+  for (uint8_t v : plain) nplain += v;
+  std::memset(stats_h, 0, sizeof(*stats_h));
+  stats_h->iters = info.iters;
+  stats_h->outer_iters = info.outer;
+  stats_h->applies = info.applies;
+  stats_h->n_free = nfree;
+  stats_h->n_dof = nfree + nb;
+  stats_h->rnorm0 = std::sqrt(hsd.rr0);
+  stats_h->relres_true = hsd.rr0 > 0 ? std::sqrt(hsd.rr_true / hsd.rr0) : 0.0;
+  stats_h->solve_ms = info.solve_ms;
+  stats_h->apply_ms = info.apply_ms;
+  stats_h->apply_samples = info.apply_samples;
+  stats_h->n_tiles = w.L.ntasks();
+  stats_h->n_plain_tiles = nplain;
+  return MFP_OK;
+}
+
+extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                             const double* disp, const int8_t* kind, const int8_t* body,
+                             const mfp_flow* flow, const mfp_solver_opts* opts,
+                             int32_t pair_lo, int32_t pair_hi, double* psi, double* psi_b_h,
+                             double* Q_h, double* copfi_h, double* samples,
+                             int8_t* sample_body, int32_t sample_cap, int32_t* n_samples_h,
+                             mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream_) {
+  clear_error();
+  MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, kind, body, flow, opts, ws));
+  if (!psi || (nbody > 0 && !psi_b_h)) {
+    set_error("psi or psi_b_h is NULL");
+    return MFP_E_ARG;
+  }
+  if (pair_lo >= nbody || pair_hi >= nbody) {
+    set_error("pair index out of range");
+    return MFP_E_ARG;
+  }
+  if (sample_cap < 0 || (sample_cap > 0 && (!samples || !sample_body))) {
+    set_error("bad sample buffers");
+    return MFP_E_ARG;
+  }
+  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  SolveWs w;
+  solve_layout(grid, nbody, opts->precision, ws, &w);
+  const mfp_grid& g = *grid;
+  const int nb = nbody;
+  SolveInfo info;
+  MFP_TRY(solve_core(g, circles_h, nb, disp, body, flow, opts, nullptr, false, w, st, &info));
   double ylo = 0, yhi = 0;
   if (pair_lo >= 0 && pair_hi >= 0) {
     ylo = circles_h[pair_lo].cy;
@@ -1109,17 +1239,6 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   MFP_TRY_HIP(hipGetLastError());
   int nsamp = 0;
   if (nb > 0) {
-    int boxes[4 * MFP_MAX_BODIES];
-    for (int b = 0; b < nb; ++b) {
-      const Box bx = circle_box(g, circles_h[b], 1, 0, g.nx - 1, 0, g.ny - 1);
-      boxes[4 * b] = bx.i0;
-      boxes[4 * b + 1] = bx.i1;
-      boxes[4 * b + 2] = bx.j0;
-      boxes[4 * b + 3] = bx.j1;
-    }
-    MFP_TRY_HIP(hipMemcpyAsync(w.boxes, boxes, sizeof(int) * 4 * nb, hipMemcpyHostToDevice, st));
-    MFP_TRY_HIP(hipMemcpyAsync(w.circ, circles_h, sizeof(mfp_circle) * nb,
-                               hipMemcpyHostToDevice, st));
     SampleArgs sa{};
     sa.nx = g.nx;
     sa.ny = g.ny;
@@ -1146,49 +1265,94 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   }
   DevState hsd;
   MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
-  long long nfree = 0;
-  MFP_TRY_HIP(hipMemcpyAsync(&nfree, w.nfree, sizeof(long long), hipMemcpyDeviceToHost, st));
-  std::vector<uint8_t> plain(w.L.ntasks());
-  MFP_TRY_HIP(hipMemcpyAsync(plain.data(), w.tplain, plain.size(), hipMemcpyDeviceToHost, st));
   MFP_TRY_HIP(hipStreamSynchronize(st));
-  long long nplain = 0;
-  for (uint8_t v : plain) nplain += v;
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   for (int b = 0; b < nb; ++b) psi_b_h[b] = hsd.xb[hsd.iters & 1][b];
   if (pair_lo >= 0 && pair_hi >= 0) {
     if (Q_h) *Q_h = hsd.Q;
     if (copfi_h) *copfi_h = hsd.copfi;
   }
   if (n_samples_h) *n_samples_h = nsamp;
-  if (stats_h) {
-    std::memset(stats_h, 0, sizeof(*stats_h));
-    stats_h->iters = total_iters;
-    stats_h->outer_iters = outer;
-    stats_h->applies = applies;
-    stats_h->n_free = nfree;
-    stats_h->n_dof = nfree + nb;
-    stats_h->rnorm0 = std::sqrt(hsd.rr0);
-    stats_h->relres_true = hsd.rr0 > 0 ? std::sqrt(hsd.rr_true / hsd.rr0) : 0.0;
-    stats_h->solve_ms = ms;
-    stats_h->apply_ms = apply_ms;
-    stats_h->apply_samples = apply_samples;
-    stats_h->n_tiles = w.L.ntasks();
-    stats_h->n_plain_tiles = nplain;
+  MFP_TRY(fill_stats(w, info, nb, hsd, st, stats_h));
+  return finish_status(info);
+}
+
+extern "C" size_t mfp_grad_workspace_size(const mfp_grid* grid, int32_t nbody,
+                                          int32_t precision) {
+  if (!grid || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES) return 0;
+  Bump bp(nullptr);
+  bp.off = solve_layout(grid, nbody, precision, nullptr, nullptr);
+  const size_t nn = (size_t)(grid->nx + 1) * (grid->ny + 1);
+  bp.take<double>(nn);                                  // lambda (nodal)
+  bp.take<double>(8 * (size_t)grid->nx * grid->ny);     // per-cell shape derivatives
+  return bp.off + 256;
+}
+
+extern "C" int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                            const double* disp, const int8_t* kind, const int8_t* body,
+                            const mfp_flow* flow, const mfp_solver_opts* opts, const double* psi,
+                            const double* psi_b_h, const double* dL_dpsib_h, double dL_dcopfi,
+                            int32_t pair_lo, int32_t pair_hi, double* dL_ddisp,
+                            double* dL_dcentre_h, mfp_stats* stats_h, void* ws, size_t ws_bytes,
+                            void* stream_) {
+  clear_error();
+  MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, kind, body, flow, opts, ws));
+  if (!psi || !dL_ddisp || (nbody > 0 && (!psi_b_h || !dL_dcentre_h))) {
+    set_error("NULL argument");
+    return MFP_E_ARG;
   }
-  if (done == 2) {
-    set_error("CG breakdown (p.Ap <= 0 or non-finite)");
-    return MFP_E_BREAKDOWN;
+  const bool use_pair = pair_lo >= 0 && pair_hi >= 0 && dL_dcopfi != 0.0;
+  if (pair_lo >= nbody || pair_hi >= nbody || (use_pair && pair_lo == pair_hi)) {
+    set_error("bad pair");
+    return MFP_E_ARG;
   }
-  if (done == 3 || done == 0) {
-    set_error("kmax or the refinement cap reached before the tolerance");
-    return MFP_W_NOCONV;
+  if (!std::isfinite(dL_dcopfi)) {
+    set_error("dL_dcopfi is not finite");
+    return MFP_E_ARG;
   }
-  if (stagnated) {
-    set_error("FP32 refinement stagnated; finished with FP64 CG");
-    return MFP_W_STAGNATION;
+  const size_t need = mfp_grad_workspace_size(grid, nbody, opts->precision);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
   }
-  return MFP_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  SolveWs w;
+  Bump bp(ws);
+  bp.off = solve_layout(grid, nbody, opts->precision, ws, &w);
+  const mfp_grid& g = *grid;
+  const int nb = nbody;
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  double* lam = bp.take<double>(nn);
+  double* cg = bp.take<double>(8 * (size_t)g.nx * g.ny);
+  // adjoint right-hand side dJ/dpsi_b and the explicit dependence of CoPFI on the
+  // pair's centre heights
+  double rhs[MFP_MAX_BODIES] = {0};
+  for (int b = 0; b < nb; ++b) {
+    rhs[b] = dL_dpsib_h ? dL_dpsib_h[b] : 0.0;
+    dL_dcentre_h[2 * b] = 0.0;
+    dL_dcentre_h[2 * b + 1] = 0.0;
+  }
+  if (use_pair) {
+    const double dy = circles_h[pair_hi].cy - circles_h[pair_lo].cy;
+    const double den = flow->U * dy;
+    const double J = (psi_b_h[pair_hi] - psi_b_h[pair_lo]) / den;
+    rhs[pair_hi] += dL_dcopfi / den;
+    rhs[pair_lo] -= dL_dcopfi / den;
+    dL_dcentre_h[2 * pair_hi + 1] += -dL_dcopfi * J / dy;
+    dL_dcentre_h[2 * pair_lo + 1] += dL_dcopfi * J / dy;
+  }
+  SolveInfo info;
+  MFP_TRY(solve_core(g, circles_h, nb, disp, body, flow, opts, rhs, true, w, st, &info));
+  // lambda as a nodal vector (Dirichlet nodes 0, body nodes lambda_b)
+  k_output<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, w.x, w.g, w.st, lam, -1,
+                                               -1, 1.0, 0.0, 1.0);
+  const long long nc = (long long)g.nx * g.ny;
+  k_shape_grad_cells<<<grid_blocks(nc), BLOCK, 0, st>>>(g.nx, g.ny, grid_hx(g), grid_hy(g), body,
+                                                         disp, lam, psi, cg);
+  k_shape_grad_gather<<<grid_blocks(nn), BLOCK, 0, st>>>(g.nx, g.ny, cg, dL_ddisp);
+  MFP_TRY_HIP(hipGetLastError());
+  DevState hsd;
+  MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  MFP_TRY(fill_stats(w, info, nb, hsd, st, stats_h));
+  return finish_status(info);
 }

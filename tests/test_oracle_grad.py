@@ -79,3 +79,26 @@ def test_projection_jacobian_matches_complex_step():
             dd = np.imag(np.stack([d[0].ravel()[sel], d[1].ravel()[sel]], 1)) / 1e-30
             mine = np.where((bb == body)[:, None], J[:, :, comp], 0.0)
             np.testing.assert_allclose(dd, mine, atol=1e-14)
+
+
+def test_radius_derivative_matches_complex_step():
+    """conform_grad's radius term against complex step of the projection + sweeps."""
+    c = W.five_cylinders(96, 48, 0.5, extent=(-6, 6, -3, 3))
+    k, b = O.classify(c.grid, c.circles)
+    rng = np.random.default_rng(3)
+    gX = rng.normal(size=(2, c.grid.nodes))
+    gc, gr = G.conform_grad(c.grid, c.circles, 30, gX, (k, b))
+    for body in (0, 4):
+        cc = [list(map(complex, x)) for x in c.circles]
+        cc[body][2] += 1e-30j
+        d0 = O.snap_displacement(c.grid, [tuple(x) for x in cc], k, b)
+        d = O.smooth(c.grid, k, d0, 30)
+        val = np.imag((d.reshape(2, -1) * gX).sum()) / 1e-30
+        assert gr[body] == pytest.approx(val, rel=1e-11)
+        for comp in range(2):
+            cc = [list(map(complex, x)) for x in c.circles]
+            cc[body][comp] += 1e-30j
+            d0 = O.snap_displacement(c.grid, [tuple(x) for x in cc], k, b)
+            d = O.smooth(c.grid, k, d0, 30)
+            val = np.imag((d.reshape(2, -1) * gX).sum()) / 1e-30
+            assert gc[body, comp] == pytest.approx(val, rel=1e-11)
