@@ -81,6 +81,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="time every n-th apply launch with HIP events (0: off)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -93,6 +95,14 @@ def main():
     import paper_2512_12232_amd as mfp
 
     mfp.load()
+    if args.calibrate_copy:
+        a = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes": a.numel() * 8}), flush=True)
+        return
     case = W.five_cyl_1024()
     dev = "cuda:0"
     torch.cuda.set_device(0)

@@ -7,9 +7,9 @@ and CoPFI.  All arithmetic runs in the library's HIP kernels.
 """
 from .binding import (MfpError, check_geometry, element_apply, last_error, load,
                       mesh_conform, mesh_conform_grad, psi_grad, psi_solve,
-                      solve_workspace_size, EXPORTS)
+                      psi_solve_batched, solve_workspace_size, EXPORTS)
 from .autograd import CoPFIFunction, copfi
 
 __all__ = ["MfpError", "check_geometry", "element_apply", "last_error", "load",
-           "mesh_conform", "mesh_conform_grad", "psi_grad", "psi_solve",
+           "mesh_conform", "mesh_conform_grad", "psi_grad", "psi_solve", "psi_solve_batched",
            "solve_workspace_size", "EXPORTS", "CoPFIFunction", "copfi"]

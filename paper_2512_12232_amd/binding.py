@@ -31,7 +31,7 @@ EXPORTS = [
     "mfp_last_error", "mfp_check_geometry", "mfp_conform_workspace_size",
     "mfp_mesh_conform", "mfp_solve_workspace_size", "mfp_element_apply", "mfp_psi_solve",
     "mfp_grad_workspace_size", "mfp_psi_grad", "mfp_conform_grad_workspace_size",
-    "mfp_mesh_conform_grad",
+    "mfp_mesh_conform_grad", "mfp_batched_workspace_size", "mfp_psi_solve_batched",
 ]
 
 
@@ -59,6 +59,11 @@ class MfpStats(Structure):
                 ("n_dof", c_int64), ("n_free", c_int64), ("relres_true", c_double),
                 ("rnorm0", c_double), ("solve_ms", c_double), ("apply_ms", c_double),
                 ("apply_samples", c_int64), ("n_plain_tiles", c_int64), ("n_tiles", c_int64)]
+
+
+class MfpVariant(Structure):
+    _fields_ = [("grid", MfpGrid), ("disp", c_void_p), ("kind", c_void_p), ("body", c_void_p),
+                ("psi", c_void_p)]
 
 
 class MfpError(RuntimeError):
@@ -106,6 +111,12 @@ def load(path: str = LIB_PATH):
     lib.mfp_mesh_conform_grad.argtypes = [
         POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_int32, c_void_p, c_void_p, c_void_p,
         POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p]
+    lib.mfp_batched_workspace_size.restype = c_size_t
+    lib.mfp_batched_workspace_size.argtypes = [c_int32, POINTER(MfpVariant), c_int32, c_int32]
+    lib.mfp_psi_solve_batched.argtypes = [
+        c_int32, POINTER(MfpVariant), POINTER(MfpCircle), c_int32, POINTER(MfpFlow),
+        POINTER(MfpSolverOpts), c_int32, c_int32, c_int32, POINTER(c_double),
+        POINTER(c_double), POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
     _lib = lib
     return lib
 
@@ -304,3 +315,59 @@ def mesh_conform_grad(grid, circles, kind, body, dL_ddisp, nsweeps=200, dL_dcent
                                      _ptr(dL_ddisp), dcen, drad, _ptr(ws), ws.numel(),
                                      _stream()))
     return [(dcen[2 * b], dcen[2 * b + 1]) for b in range(nb)], [drad[b] for b in range(nb)]
+
+
+@dataclass
+class BatchResult:
+    psi: list            # device tensors (or None)
+    psi_b: list          # per system, list of nbody values
+    copfi: list
+    stats: list
+    status: int
+
+
+def psi_solve_batched(systems, flow, *, precision="fp32_ir", rtol=1e-10, kmax=10 ** 7,
+                      iters_per_launch=64, pair=(-1, -1), want_psi=False,
+                      ws: Optional[torch.Tensor] = None) -> BatchResult:
+    """systems: list of (grid, circles, disp, kind, body); all with the same number of
+    bodies.  One graph-replayed launch sequence for all of them."""
+    lib = load()
+    nvar = len(systems)
+    nb = len(systems[0][1])
+    vars_ = (MfpVariant * nvar)()
+    circ = (MfpCircle * max(1, nvar * nb))()
+    psis = []
+    for i, (grid, circles, disp, kind, body) in enumerate(systems):
+        assert len(circles) == nb
+        g = make_grid(grid)
+        psi = None
+        if want_psi:
+            psi = torch.empty((g.nx + 1) * (g.ny + 1), dtype=torch.float64, device=disp.device)
+        psis.append(psi)
+        vars_[i] = MfpVariant(g, c_void_p(disp.data_ptr()), c_void_p(kind.data_ptr()),
+                              c_void_p(body.data_ptr()), _ptr(psi) if psi is not None else None)
+        for b, (cx, cy, r) in enumerate(circles):
+            circ[i * nb + b] = MfpCircle(float(cx), float(cy), float(r))
+    f = make_flow(flow)
+    o = _opts(precision, rtol, kmax, 64, 0.1, 1000)
+    psib = (c_double * max(1, nvar * nb))()
+    cop = (c_double * nvar)()
+    st = (MfpStats * nvar)()
+    if ws is None:
+        ws = workspace(lib.mfp_batched_workspace_size(nvar, vars_, nb, _PREC[precision]),
+                       systems[0][2].device)
+    status = _check(lib.mfp_psi_solve_batched(
+        nvar, vars_, circ, nb, byref(f), byref(o), int(iters_per_launch), int(pair[0]),
+        int(pair[1]), psib, cop, st, _ptr(ws), ws.numel(), _stream()))
+    stats = [{k: getattr(st[i], k) for k, _ in MfpStats._fields_} for i in range(nvar)]
+    return BatchResult(psis, [[psib[i * nb + b] for b in range(nb)] for i in range(nvar)],
+                       [cop[i] for i in range(nvar)], stats, status)
+
+
+def batched_workspace_size(systems, precision="fp32_ir") -> int:
+    lib = load()
+    nvar = len(systems)
+    vars_ = (MfpVariant * nvar)()
+    for i, s in enumerate(systems):
+        vars_[i] = MfpVariant(make_grid(s[0]), None, None, None, None)
+    return lib.mfp_batched_workspace_size(nvar, vars_, len(systems[0][1]), _PREC[precision])

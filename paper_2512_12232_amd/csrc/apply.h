@@ -14,6 +14,8 @@
 // operator, a few ulp apart).
 #pragma once
 
+#include <hip/hip_ext.h>
+
 #include "mfp_internal.h"
 
 namespace mfp {
@@ -161,6 +163,11 @@ struct ApplyArgs {
   int write_all;
   T cC, cE, cN, cD;              // constant stencil (centre, east/west, north/south, diag)
   T ry;                          // hy / hx
+  int G;                         // blocks of this apply (batched launches)
+  int kdev;                      // fused: iteration index from st->ka, directions by parity
+  T* pbuf0;                      // kdev: direction buffers (iteration k reads k&1)
+  T* pbuf1;
+  const int* skip;               // plain apply: return at once when *skip != 0
 };
 
 // FUSED = false: q = K src.
@@ -181,14 +188,22 @@ struct ApplyArgs {
 // in), keeps the cell's contributions to its own column and shifts the contributions
 // to column c+1 over; node (c, j) is complete once cell rows j-1 and j are done.
 template <typename T, bool FUSED, int HC>
-__global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
-  __shared__ double s_red[WAVES];
-  __shared__ double s_pb[MFP_MAX_BODIES];
+__device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk, const int G,
+                                           double* s_red, double* s_pb) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int G = gridDim.x;
-  // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs)
-  const int vb = (blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3);
+  // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs;
+  // vblk and blockIdx.x agree modulo 8)
+  const int vb = (vblk & 7) * (G >> 3) + (vblk >> 3);
+  if (!FUSED && a.skip && *a.skip) return;
+  long long kk = a.k;
+  const T* src = a.src;
+  T* pnew = a.pnew;
+  if (FUSED && a.kdev) {
+    kk = a.st->ka;
+    src = (kk & 1) ? a.pbuf1 : a.pbuf0;
+    pnew = (kk & 1) ? a.pbuf0 : a.pbuf1;
+  }
   const long long P = a.P;
   const bool owner = lane >= 1 && lane <= SW;
   const int grp0 = vb * a.gpb, grp1 = (vb + 1) * a.gpb;
@@ -199,7 +214,7 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
     const long long base = (long long)(kc * HC) * P + (long long)m * SW + lane;
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
-      rs[r] = a.src[base + r * P];
+      rs[r] = src[base + r * P];
       if (FUSED) ra[r] = a.r[base + r * P];
     }
   };
@@ -210,7 +225,7 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
   T beta = (T)0;
   if (FUSED) {
     DevState* st = a.st;
-    const int cur = (int)(a.k & 1), prv = cur ^ 1;
+    const int cur = (int)(kk & 1), prv = cur ^ 1;
     // every scalar this block needs is requested at once
     const int done = st->done;
     const double rb_rr = st->rb_rr[cur], rr_prv = st->rr[prv], rr_stop = st->rr_stop;
@@ -230,12 +245,12 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
       code = 2;
     else if (rrk <= rr_stop)
       code = 1;
-    else if (a.k >= kmax)
+    else if (kk >= kmax)
       code = 3;
     if (code) {
-      if (blockIdx.x == 0 && tid == 0) {
+      if (vblk == 0 && tid == 0) {
         st->done = code;
-        st->iters = a.k;
+        st->iters = kk;
         st->rr_final = rrk;
       }
       return;
@@ -243,11 +258,12 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
     if (tid < a.nb) {
       const double v = rbv + beta_d * pbv;
       s_pb[tid] = v;
-      if (blockIdx.x == 0) st->pb[cur][tid] = v;
+      if (vblk == 0) st->pb[cur][tid] = v;
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    if (vblk == 0 && tid == 0) {
       st->rr[cur] = rrk;
       st->beta = beta_d;
+      st->ku = kk;
     }
     beta = (T)beta_d;
     __syncthreads();
@@ -274,7 +290,7 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
         const T csl = lane_shr(cs), csr = lane_shl(cs);
         const T qv = a.cC * v[r] + a.cE * (pl + pr) + a.cN * cs + a.cD * (csl + csr);
         if (owner) {
-          if (FUSED) a.pnew[gi] = v[r];
+          if (FUSED) pnew[gi] = v[r];
           a.q[gi] = qv;
           pq += (double)v[r] * (double)qv;
         }
@@ -316,7 +332,7 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
         if (sr >= 1) {
           const long long gi = base + sr * P;
           if (owner) {
-            if (FUSED) a.pnew[gi] = p0;
+            if (FUSED) pnew[gi] = p0;
             const bool keep = (g0 == TAG_FREE) || (a.write_all && g0 != TAG_HALO);
             a.q[gi] = keep ? acc : (T)0;
             if (g0 == TAG_FREE) pq += (double)p0 * (double)acc;
@@ -346,12 +362,41 @@ __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
     }
   }
   const double bsum = block_sum(pq, s_red);
-  if (tid == 0) a.part[blockIdx.x] = bsum;
+  if (tid == 0) a.part[vblk] = bsum;
 }
 
-// Launch the apply for the layout's task height.
+template <typename T, bool FUSED, int HC>
+__global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
+  __shared__ double s_red[WAVES];
+  __shared__ double s_pb[MFP_MAX_BODIES];
+  apply_core<T, FUSED, HC>(a, blockIdx.x, gridDim.x, s_red, s_pb);
+}
+
+// Many independent systems in one launch: block b works for system map[b].x as its
+// virtual block map[b].y (each system's blocks start at a multiple of 8).
+template <typename T, bool FUSED, int HC>
+__global__ void __launch_bounds__(BLOCK) k_apply_batch(const ApplyArgs<T>* __restrict__ args,
+                                                       const int2* __restrict__ map) {
+  __shared__ double s_red[WAVES];
+  __shared__ double s_pb[MFP_MAX_BODIES];
+  const int2 vm = map[blockIdx.x];
+  const ApplyArgs<T>& a = args[vm.x];
+  apply_core<T, FUSED, HC>(a, vm.y, a.G, s_red, s_pb);
+}
+
+// Launch the apply for the layout's task height.  With events, they are recorded by
+// the runtime at the start and end of this kernel's execution (hipExtLaunchKernel),
+// so their difference is the kernel's own duration.
 template <typename T, bool FUSED>
-inline void launch_apply(int hc, int G, hipStream_t st, const ApplyArgs<T>& a) {
+inline void launch_apply(int hc, int G, hipStream_t st, const ApplyArgs<T>& a,
+                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (e0) {
+    if (hc == 4)
+      hipExtLaunchKernelGGL(k_apply<T, FUSED, 4>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+    else
+      hipExtLaunchKernelGGL(k_apply<T, FUSED, 8>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+    return;
+  }
   if (hc == 4)
     k_apply<T, FUSED, 4><<<G, BLOCK, 0, st>>>(a);
   else

@@ -82,13 +82,13 @@ struct Layout {
 
 // Short tasks (4 rows) on small grids give each SIMD at least two wavefronts; larger
 // grids use 8-row tasks (less halo re-reading).
-inline Layout make_layout(int nx, int ny) {
+inline Layout make_layout(int nx, int ny, int hc_force = 0) {
   Layout L;
   L.nx = nx;
   L.ny = ny;
   L.nstrip = (nx + 1 + SW - 1) / SW;
   const long long t8 = (long long)L.nstrip * ((ny + 1 + 7) / 8);
-  L.hc = t8 < 4096 ? 4 : 8;
+  L.hc = hc_force ? hc_force : (t8 < 4096 ? 4 : 8);
   L.nchunk = (ny + 1 + L.hc - 1) / L.hc;
   L.P = (((L.nstrip - 1) * SW + 64) + 63) / 64 * 64;
   L.rows = L.hc * L.nchunk + 2;
@@ -115,6 +115,9 @@ struct DevState {
   double copfi, Q;
   long long iters;                       // index of the final iterate once done != 0
   long long kmax;
+  long long outer_count;                 // batched mixed solves: FP64 refinements so far
+  long long ka;                          // batched: index of the next apply's iteration
+  long long ku;                          // batched: index of the next update's iteration
   int done;                              // 0 running, 1 converged, 2 breakdown, 3 kmax
   int pad_;
 };

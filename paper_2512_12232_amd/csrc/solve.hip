@@ -348,30 +348,50 @@ __global__ void __launch_bounds__(BLOCK) k_reliable_reset(long long n, const dou
   }
 }
 
+template <typename T>
+struct UpdArgs {
+  long long n;
+  T* x;
+  const T* p;           // direction of this iteration (kdev: chosen by parity)
+  T* r;
+  const T* q;
+  const double* part;   // apply partials of p.q
+  int G;                // number of those
+  const double* bpart;  // apply body slots
+  const int* nslots;
+  double* part2;        // out: partials of r.r
+  DevState* st;
+  int nb;
+  long long k;
+  int G2;               // blocks of this update (batched launches)
+  int kdev;             // iteration index from st->ku, direction by parity
+  const T* pbuf0;
+  const T* pbuf1;
+};
+
 // Second half of CG iteration k: every block sums the apply's body slots and p.q
 // partials itself, forms alpha = r.r / p.Ap (breakdown stops the solve), block 0
 // advances the body unknowns, and all blocks stream x += alpha p, r -= alpha q with
 // per-block partials of the new r.r.  Two elements per thread and step.
 template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_update(long long n, T* __restrict__ x,
-                                                  const T* __restrict__ p, T* __restrict__ r,
-                                                  const T* __restrict__ q,
-                                                  const double* __restrict__ part, int G,
-                                                  const double* __restrict__ bpart,
-                                                  const int* __restrict__ nslots,
-                                                  double* __restrict__ part2, DevState* st,
-                                                  int nb, long long k) {
+__device__ __forceinline__ void update_core(const UpdArgs<T>& u, const int vblk, const int G2,
+                                            double* s_red, double* s_qb) {
   using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
-  __shared__ double s_red[BLOCK / 64];
-  __shared__ double s_qb[MFP_MAX_BODIES];
+  DevState* st = u.st;
   if (st->done) return;
-  const long long n2 = n >> 1;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  T2* x2 = reinterpret_cast<T2*>(x);
-  T2* r2 = reinterpret_cast<T2*>(r);
+  long long k = u.k;
+  const T* p = u.p;
+  if (u.kdev) {
+    k = st->ku;
+    p = ((k + 1) & 1) ? u.pbuf1 : u.pbuf0;
+  }
+  const long long n2 = u.n >> 1;
+  const long long stride = (long long)G2 * blockDim.x;
+  long long e = vblk * (long long)blockDim.x + threadIdx.x;
+  T2* x2 = reinterpret_cast<T2*>(u.x);
+  T2* r2 = reinterpret_cast<T2*>(u.r);
   const T2* p2 = reinterpret_cast<const T2*>(p);
-  const T2* q2 = reinterpret_cast<const T2*>(q);
+  const T2* q2 = reinterpret_cast<const T2*>(u.q);
   // first operands in flight while the scalars are formed
   T2 xv{}, pv{}, rv{}, qv{};
   if (e < n2) {
@@ -381,17 +401,18 @@ __global__ void __launch_bounds__(BLOCK) k_update(long long n, T* __restrict__ x
     qv = q2[e];
   }
   const int cur = (int)(k & 1), nxt = cur ^ 1;
+  const int nb = u.nb;
   // every scalar this block needs is requested at once
   const double rr_cur = st->rr[cur];
   double pbv = 0.0;
   if (threadIdx.x < nb) pbv = st->pb[cur][threadIdx.x];
   double s = 0.0;
-  for (int i = threadIdx.x; i < G; i += BLOCK) s += part[i];
-  body_sums(bpart, *nslots, nb, s_qb);
+  for (int i = threadIdx.x; i < u.G; i += BLOCK) s += u.part[i];
+  body_sums(u.bpart, *u.nslots, nb, s_qb);
   if (threadIdx.x < nb) s += pbv * s_qb[threadIdx.x];
   const double pq = block_sum(s, s_red);
   if (!(pq > 0.0) || !isfinite(pq)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (vblk == 0 && threadIdx.x == 0) {
       st->done = 2;
       st->iters = k;
       st->pq = pq;
@@ -399,7 +420,7 @@ __global__ void __launch_bounds__(BLOCK) k_update(long long n, T* __restrict__ x
     return;
   }
   const double alpha_d = rr_cur / pq;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (vblk == 0 && threadIdx.x == 0) {
     double rbr = 0.0;
     for (int b = 0; b < nb; ++b) {
       st->xb[nxt][b] = st->xb[cur][b] + alpha_d * st->pb[cur][b];
@@ -410,6 +431,7 @@ __global__ void __launch_bounds__(BLOCK) k_update(long long n, T* __restrict__ x
     st->rb_rr[nxt] = rbr;
     st->alpha = alpha_d;
     st->pq = pq;
+    st->ka = k + 1;
   }
   const T alpha = (T)alpha_d;
   double acc = 0.0;
@@ -436,7 +458,24 @@ __global__ void __launch_bounds__(BLOCK) k_update(long long n, T* __restrict__ x
     qv = qn;
   }
   const double bs = block_sum(acc, s_red);
-  if (threadIdx.x == 0) part2[blockIdx.x] = bs;
+  if (threadIdx.x == 0) u.part2[vblk] = bs;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_update(UpdArgs<T> u) {
+  __shared__ double s_red[BLOCK / 64];
+  __shared__ double s_qb[MFP_MAX_BODIES];
+  update_core<T>(u, blockIdx.x, gridDim.x, s_red, s_qb);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_update_batch(const UpdArgs<T>* __restrict__ args,
+                                                        const int2* __restrict__ map) {
+  __shared__ double s_red[BLOCK / 64];
+  __shared__ double s_qb[MFP_MAX_BODIES];
+  const int2 vm = map[blockIdx.x];
+  const UpdArgs<T>& u = args[vm.x];
+  update_core<T>(u, vm.y, u.G2, s_red, s_qb);
 }
 
 // psi (unpadded) from the padded unknowns; Q and CoPFI from the pair.
@@ -577,6 +616,7 @@ struct SolveWs {
   int* nslots;
   double* part;
   double* part2;
+  double* part3;  // batched refinement: partials of the FP64 residual
   double* bpart;
   DevState* st;
   DevState* st2;  // inner (FP32) solver state
@@ -586,10 +626,11 @@ struct SolveWs {
   int* count;
 };
 
-static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base, SolveWs* out) {
+static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base, SolveWs* out,
+                           int hc_force = 0) {
   Bump bp(base);
   SolveWs w{};
-  w.L = make_layout(g->nx, g->ny);
+  w.L = make_layout(g->nx, g->ny, hc_force);
   const size_t n = (size_t)w.L.n;
   const int nt = w.L.ntasks();
   w.tag = bp.take<int8_t>(n);
@@ -616,6 +657,7 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.nslots = bp.take<int>(1);
   w.part = bp.take<double>(GMAX);
   w.part2 = bp.take<double>(GMAX);
+  w.part3 = bp.take<double>(GMAX);
   w.bpart = bp.take<double>((size_t)nt * (nb > 0 ? nb : 1));
   w.st = bp.take<DevState>(1);
   w.st2 = bp.take<DevState>(1);
@@ -870,14 +912,27 @@ static int cg_run(const mfp_grid& g, int nb, const SolveWs& w, const CgBufs<T>& 
       a.pnew = pbuf[(k + 1) & 1];
       a.k = k;
       const bool timed = prof && (m % prof == 0) && used < nev_c;
-      if (timed) (void)hipEventRecord(ev[2 * used], st);
-      launch_apply<T, true>(w.L.hc, G, st, a);
       if (timed) {
-        (void)hipEventRecord(ev[2 * used + 1], st);
+        launch_apply<T, true>(w.L.hc, G, st, a, ev[2 * used], ev[2 * used + 1]);
         ++used;
+      } else {
+        launch_apply<T, true>(w.L.hc, G, st, a);
       }
-      k_update<T><<<G2, BLOCK, 0, st>>>(w.L.n, B.x, pbuf[(k + 1) & 1], B.r, B.q, w.part, G,
-                                        w.bpart, w.nslots, w.part2, B.st, nb, k);
+      UpdArgs<T> u{};
+      u.n = w.L.n;
+      u.x = B.x;
+      u.p = pbuf[(k + 1) & 1];
+      u.r = B.r;
+      u.q = B.q;
+      u.part = w.part;
+      u.G = G;
+      u.bpart = w.bpart;
+      u.nslots = w.nslots;
+      u.part2 = w.part2;
+      u.st = B.st;
+      u.nb = nb;
+      u.k = k;
+      k_update<T><<<G2, BLOCK, 0, st>>>(u);
     }
     hipError_t le = hipGetLastError();
     if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &B.st->done, sizeof(int),
@@ -1356,3 +1411,5 @@ extern "C" int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, i
   MFP_TRY(fill_stats(w, info, nb, hsd, st, stats_h));
   return finish_status(info);
 }
+
+#include "batch.h"
