@@ -47,9 +47,33 @@ def apply_bytes(case, disp, body):
     return 32 * n + 16 * moved + (boundary + bodies), moved
 
 
-def cpu_baseline(case, iters):
-    """The oracle's plain CG on the assembled reduced system, `iters` iterations,
-    one thread."""
+COUNTERS = os.path.join(ROOT, "profiles", "k_apply_fused_fp64_five_cyl_1024x512_counters.md")
+
+
+def traffic_from_profile():
+    """HBM bytes per fused-apply launch from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE passes (scaled by the copy-kernel calibration), or None when the
+    apply or solver source has changed since those counters were taken."""
+    import hashlib
+    try:
+        text = open(COUNTERS).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line
+                  and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "source_sha256_16"))
+    h = hashlib.sha256()
+    for f in ("apply.h", "solve.hip"):
+        with open(os.path.join(ROOT, "paper_2512_12232_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256_16", "").strip() != h.hexdigest()[:16]:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
+def cpu_baseline(case, seconds):
+    """The oracle's plain CG on the assembled reduced system, one thread, run for a
+    bounded number of iterations chosen from a short calibration run so that the
+    timed part takes about `seconds`."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -64,6 +88,10 @@ def cpu_baseline(case, iters):
     A = A.tocsr()
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
+        cg(A, b, rtol=1e-300, max_iters=50)
+        per_iter = (time.perf_counter() - t0) / 50
+        iters = max(100, int(seconds / per_iter))
+        t0 = time.perf_counter()
         _, k, _ = cg(A, b, rtol=1e-300, max_iters=iters)
         dt = time.perf_counter() - t0
     return {"value": ndof * k / dt, "unit": "DOF·iter/s", "cores": 1, "kind": "oracle",
@@ -72,13 +100,134 @@ def cpu_baseline(case, iters):
                       f"SpMV, 1 thread); assembly not timed; {dt:.1f} s"}
 
 
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _timed(fn, reps=1):
+    """Wall time of fn() (ms, best of reps) after one untimed call."""
+    out = fn()
+    _sync()
+    best = float("inf")
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        out = fn()
+        _sync()
+        best = min(best, time.perf_counter() - t0)
+    return out, 1e3 * best
+
+
+def mixed_precision(mfp, W):
+    """4096 x 2048 cells (delta 0.5): FP32 apply with FP64 refinement against plain
+    FP64 CG, both to relative residual 1e-10, and plain FP32 CG to 1e-6."""
+    case = W.five_cyl_4096()
+    disp, kind, body = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device="cuda:0")
+    out = {"workload": "five cylinders, 4096x2048 cells, delta 0.5, rtol 1e-10"}
+    res = {}
+    for prec, rtol in (("fp64", 1e-10), ("fp32_ir", 1e-10), ("fp32", 1e-6)):
+        r, ms = _timed(lambda: mfp.psi_solve(case.grid, case.circles, disp, kind, body,
+                                             case.flow, precision=prec, rtol=rtol,
+                                             pair=case.pair, sample_cap=0))
+        res[prec] = r
+        out[prec] = {"solve_ms": round(ms, 2), "iters": r.stats["iters"],
+                     "relres_true": r.stats["relres_true"], "rtol": rtol,
+                     "dof_iter_per_s": r.stats["n_dof"] * r.stats["iters"] / (ms * 1e-3)}
+    ref = res["fp64"].psi
+    for prec in ("fp32_ir", "fp32"):
+        d = res[prec].psi - ref
+        out[prec]["psi_rel_l2_vs_fp64"] = float(d.norm() / ref.norm())
+        out[prec]["max_abs_dpsi_b"] = max(abs(a - b) for a, b in
+                                          zip(res[prec].psi_b, res["fp64"].psi_b))
+        out[prec]["abs_dcopfi"] = abs(res[prec].copfi - res["fp64"].copfi)
+    out["fp32_ir_speedup_vs_fp64"] = out["fp64"]["solve_ms"] / out["fp32_ir"]["solve_ms"]
+    return out
+
+
+def adjoint_ratio(mfp, W):
+    """2048 x 1024 cells (delta 0.15): forward (mesh + FP64 solve to 1e-12 + outputs)
+    against backward (adjoint solve, shape derivative, transposed smoother,
+    projection) for dCoPFI/d(centres, delta)."""
+    case = W.five_cyl_2048_adjoint()
+    dev = "cuda:0"
+
+    def fwd():
+        d, k, b = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device=dev)
+        r = mfp.psi_solve(case.grid, case.circles, d, k, b, case.flow, rtol=1e-12,
+                          pair=case.pair, sample_cap=0)
+        return d, k, b, r
+
+    (d, k, b, r), fwd_ms = _timed(fwd, reps=2)
+
+    def bwd():
+        g, expl, st, _ = mfp.psi_grad(case.grid, case.circles, d, k, b, case.flow, r.psi,
+                                      r.psi_b, dL_dcopfi=1.0, pair=case.pair, rtol=1e-12)
+        dc, _ = mfp.mesh_conform_grad(case.grid, case.circles, k, b, g, case.nsweeps,
+                                      dL_dcentre=expl)
+        return dc, st
+
+    (dc, st), bwd_ms = _timed(bwd, reps=2)
+    return {"workload": "five cylinders, 2048x1024 cells, delta 0.15, rtol 1e-12",
+            "forward_ms": round(fwd_ms, 2), "backward_ms": round(bwd_ms, 2),
+            "ratio": bwd_ms / fwd_ms, "forward_iters": r.stats["iters"],
+            "adjoint_iters": st["iters"], "copfi": r.copfi,
+            "dcopfi_ddelta": dc[4][1] - dc[3][1]}
+
+
+def delta_sweep(mfp, W, count=256):
+    """256 seeded five-cylinder variants (delta ~ U[0.05, 2], 256x128 .. 1024x512
+    cells): one batched graph-replayed solve (FP32 apply + FP64 refinement, and plain
+    FP64) against the same systems solved one after another with the single-system
+    FP64 solver, all to relative residual 1e-10."""
+    cases = W.batch_variants(count, seed=0)
+    systems = []
+    for c in cases:
+        d, k, b = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device="cuda:0")
+        systems.append((c.grid, c.circles, d, k, b))
+    _sync()
+    flow, pair = cases[0].flow, cases[0].pair
+    out = {"workload": f"{count} five-cylinder variants, delta ~ U[0.05,2], "
+                       "256x128..1024x512 cells, rtol 1e-10",
+           "nodes": sum(c.grid.nodes for c in cases)}
+    res = {}
+    for prec in ("fp32_ir", "fp64"):
+        ws = mfp.binding.workspace(mfp.binding.batched_workspace_size(systems, prec), "cuda:0")
+        r, ms = _timed(lambda: mfp.psi_solve_batched(systems, flow, precision=prec,
+                                                     rtol=1e-10, pair=pair, ws=ws))
+        del ws
+        res[prec] = r
+        its = [s["iters"] for s in r.stats]
+        out["batched_" + prec] = {
+            "ms": round(ms, 1), "iters_mean": sum(its) / len(its), "iters_max": max(its),
+            "max_relres_true": max(s["relres_true"] for s in r.stats),
+            "dof_iter_per_s": sum(s["n_dof"] * s["iters"] for s in r.stats) / (ms * 1e-3)}
+
+    def seq():
+        return [mfp.psi_solve(g, c, d, k, b, flow, rtol=1e-10, pair=pair, sample_cap=0)
+                for g, c, d, k, b in systems]
+
+    rs, ms = _timed(seq)
+    out["sequential_fp64"] = {"ms": round(ms, 1), "dof_iter_per_s": sum(
+        r.stats["n_dof"] * r.stats["iters"] for r in rs) / (ms * 1e-3)}
+    for prec in ("fp32_ir", "fp64"):
+        b = out["batched_" + prec]
+        b["speedup_vs_sequential_fp64"] = out["sequential_fp64"]["ms"] / b["ms"]
+        b["max_abs_dcopfi_vs_sequential_fp64"] = max(
+            abs(x - r.copfi) for x, r in zip(res[prec].copfi, rs))
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--cpu-iters", type=int, default=1500)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="length of the timed oracle CG run on the host")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the 4096x2048 mixed-precision, adjoint and delta-sweep "
+                         "measurements")
     ap.add_argument("--profile-every", type=int, default=16,
                     help="time every n-th apply launch with HIP events (0: off)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -132,12 +281,17 @@ def main():
         achieved = nbytes / (ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": None, "kernel": "k_apply<double, fused>",
+                    "traffic": traffic_from_profile(), "kernel": "k_apply<double, fused>",
                     "launch_ms": round(ms, 5), "bytes_per_launch": nbytes,
                     "samples": int(sum(r.stats["apply_samples"] for _, _, r in outs))}
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(case, args.cpu_iters)
+        cpu = cpu_baseline(case, args.cpu_seconds)
+    extras = {}
+    if not args.no_extras:
+        extras["mixed_precision_4096x2048"] = mixed_precision(mfp, W)
+        extras["adjoint_2048x1024"] = adjoint_ratio(mfp, W)
+        extras["delta_sweep_256"] = delta_sweep(mfp, W)
     s = res.stats
     line = {
         "metric": METRIC,
@@ -165,6 +319,7 @@ def main():
         "plain_tile_frac": s["n_plain_tiles"] / max(1, s["n_tiles"]),
         "psi_b": res.psi_b,
         "copfi": res.copfi,
+        **extras,
     }
     print(json.dumps(line), flush=True)
 
