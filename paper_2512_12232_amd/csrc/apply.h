@@ -4,14 +4,15 @@
 // matrix with the element extract of the global vector and accumulates the element
 // results into the global vector; its element matrices are K_e = int (grad N)^T
 // (grad N) dOmega (section "Weak formulation").  Here the element matrix is never
-// stored: each workgroup owns a 64 x 8 tile of nodes, stages the tile plus a
-// one-node halo in LDS, evaluates K_e(X_e) p_e for every cell touching the tile with
-// the 2x2 Gauss rule from the node displacements, parks the four results of each
-// cell in LDS and lets every owned node gather the contributions of its four cells.
-// Each output is written exactly once, so no atomics and no colouring of the global
-// scatter are needed.  Tiles whose footprint holds only free, undisplaced nodes take
-// the assembled constant 9-point stencil of the rectangular cell instead (same
-// operator, a few ulp apart).
+// stored: each wavefront owns strips of 62 node columns (plus one halo column on
+// each side) and marches up them a few node rows at a time, evaluating K_e(X_e) p_e
+// for every cell touching its rows with the 2x2 Gauss rule from the node
+// displacements; the neighbour values a cell needs come from the adjacent lane
+// (DPP lane shifts) and from the rows already in registers.  Each output is written
+// exactly once, so no atomics and no colouring of the global scatter are needed.
+// Tasks whose footprint holds only free, undisplaced nodes take the assembled
+// constant 9-point stencil of the rectangular cell instead (same operator, a few ulp
+// apart).
 #pragma once
 
 #include <hip/hip_ext.h>
@@ -142,7 +143,10 @@ __device__ __forceinline__ int lane_shl(int v) { return dpp_shl1_i(v); }
 
 template <typename T>
 struct ApplyArgs {
-  int P, nstrip, ntasks, gpb;    // pitch, strips, tasks, task groups per block
+  int P, nstrip;                 // pitch, strips (task t = chunk * nstrip + strip)
+  const int4* segtab;            // work list: x = strip, y = first chunk | (length << 16),
+                                 // (z, w) = mask of constant-stencil tasks
+  int tabsize;                   // entries (a multiple of 4 G; empty entries have length 0)
   const int8_t* tag;
   const T* dx;                   // displacement / hx
   const T* dy;
@@ -179,9 +183,14 @@ struct ApplyArgs {
 // No grid-wide synchronisation inside the kernel: partial sums go to per-block slots
 // that the next kernel reduces.
 //
-// Each wavefront processes whole tasks (64-column strip x HC rows).  The residual and
-// old-direction rows of a task are loaded into registers first (for a wave's first
-// task before the scalar reduction, so that the two latencies overlap).
+// Work unit: a task is a 64-column strip x HC node rows; a wavefront takes a segment
+// of consecutive tasks of one strip from the work list (segments of about equal cost)
+// and marches upward through them.  The
+// two node rows that consecutive tasks share stay in registers, and the residual and
+// direction rows of the next task are requested before the current one is computed,
+// so every wavefront keeps a task's worth of loads in flight.  The first task's rows
+// and the segment's task flags are requested before the scalar reduction, so that
+// the two latencies overlap.
 // Constant-stencil tasks evaluate the assembled 9-point stencil with lane shifts for
 // the horizontal neighbours.  Other tasks march over the HC+1 cell rows touching their
 // rows: lane c evaluates cell (c, j) from its own nodes and those of lane c+1 (shifted
@@ -205,22 +214,58 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
     pnew = (kk & 1) ? a.pbuf0 : a.pbuf1;
   }
   const long long P = a.P;
+  const int nstrip = a.nstrip;
   const bool owner = lane >= 1 && lane <= SW;
-  const int grp0 = vb * a.gpb, grp1 = (vb + 1) * a.gpb;
+  const int W = G * WAVES;
 
-  T ra[HC + 2], rs[HC + 2];  // residual and direction (or p) rows of the current task
-  auto fill = [&](int t) {
-    const int m = t % a.nstrip, kc = t / a.nstrip;
-    const long long base = (long long)(kc * HC) * P + (long long)m * SW + lane;
+  // segment state: strip, chunk range, constant-stencil mask (bit i: task kc0 + i)
+  int s = vb * WAVES + wv;
+  int m = 0, kc0 = 0, kc1 = 0;
+  unsigned long long plain_mask = 0ull;
+  int fl_body = 0, slot_l = -1;                // this lane's task (kc0 + lane)
+  T f0s = 0, f1s = 0, f0r = 0, f1r = 0;        // rows 0, 1 of the segment's first task
+  T ns[HC], nr[HC];                            // rows 2..HC+1 of the next task
+  int8_t tg[HC + 2];                           // tags and displacements of the current
+  T ddx[HC + 2], ddy[HC + 2];                  // task (tasks that evaluate geometry)
+  auto load_geom = [&](long long base) {
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
-      rs[r] = src[base + r * P];
-      if (FUSED) ra[r] = a.r[base + r * P];
+      tg[r] = a.tag[base + r * P];
+      ddx[r] = a.dx[base + r * P];
+      ddy[r] = a.dy[base + r * P];
     }
   };
-  int tfirst = grp0 * WAVES + wv;
-  const bool have_first = tfirst < a.ntasks;
-  if (have_first) fill(tfirst);
+  auto seg_load = [&](int sg) {
+    const int4 e = a.segtab[sg];
+    m = e.x;
+    kc0 = e.y & 0xffff;
+    kc1 = kc0 + (e.y >> 16);
+    plain_mask = (unsigned long long)(unsigned)e.z | ((unsigned long long)(unsigned)e.w << 32);
+    if (kc1 <= kc0) return;
+    const int kcl = min(kc0 + lane, kc1 - 1);
+    const int tl = kcl * nstrip + m;
+    fl_body = a.tbody[tl] != 0ull;
+    slot_l = a.tslot[tl];
+    const long long base = (long long)(kc0 * HC) * P + (long long)m * SW + lane;
+    f0s = src[base];
+    f1s = src[base + P];
+    if (FUSED) {
+      f0r = a.r[base];
+      f1r = a.r[base + P];
+    }
+#pragma unroll
+    for (int r = 0; r < HC; ++r) {
+      ns[r] = src[base + (r + 2) * P];
+      if (FUSED) nr[r] = a.r[base + (r + 2) * P];
+    }
+    // the first task's geometry travels with its rows
+    if (!(plain_mask & 1ull)) load_geom(base);
+  };
+  bool loaded = false;
+  if (s < a.tabsize) {
+    seg_load(s);
+    loaded = true;
+  }
 
   T beta = (T)0;
   if (FUSED) {
@@ -235,10 +280,10 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
       rbv = st->rb[cur][tid];
       pbv = st->pb[prv][tid];
     }
-    double s = 0.0;
-    for (int i = tid; i < a.G2; i += BLOCK) s += a.part2[i];
+    double sacc = 0.0;
+    for (int i = tid; i < a.G2; i += BLOCK) sacc += a.part2[i];
     if (done) return;
-    const double rrk = block_sum(s, s_red) + rb_rr;
+    const double rrk = block_sum(sacc, s_red) + rb_rr;
     const double beta_d = rrk / rr_prv;
     int code = 0;
     if (!isfinite(rrk))
@@ -270,95 +315,123 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
   }
 
   double pq = 0.0;
-  double bacc = 0.0;  // lane b accumulates body b of the current task
-  for (int grp = grp0; grp < grp1; ++grp) {
-    const int t = grp * WAVES + wv;
-    if (t >= a.ntasks) break;
-    if (t != tfirst) fill(t);
-    const int m = t % a.nstrip, kc = t / a.nstrip;
-    // local row r = 0 .. HC+1 is internal row kc*HC + r; lane is internal column m*SW+lane
-    const long long base = (long long)(kc * HC) * P + (long long)m * SW + lane;
-    if (a.tplain[t]) {
-      T v[HC + 2];
+  for (; s < a.tabsize; s += W) {
+    if (!loaded) seg_load(s);  // later entries of this wavefront
+    loaded = false;
+    if (kc1 <= kc0) continue;
+    const unsigned long long body_mask = __ballot(fl_body != 0);
+    T v[HC + 2];  // input vector (fused: new direction) at rows 0..HC+1 of the task
+    // the fused form combines every row as at a free node and corrects the other
+    // nodes once their tags are known
+    v[0] = FUSED ? f0r + beta * f0s : f0s;
+    v[1] = FUSED ? f1r + beta * f1s : f1s;
+    for (int kc = kc0; kc < kc1; ++kc) {
+      const int it = kc - kc0;
+      const bool first = kc == kc0;
+      // local row r = 0 .. HC+1 is padded row kc*HC + r; lane is padded column m*SW+lane
+      const long long base = (long long)(kc * HC) * P + (long long)m * SW + lane;
+      const bool plain = (plain_mask >> it) & 1ull;
+      // rows 2..HC+1 arrived with the previous prefetch
 #pragma unroll
-      for (int r = 0; r < HC + 2; ++r) v[r] = FUSED ? ra[r] + beta * rs[r] : rs[r];
+      for (int r = 0; r < HC; ++r) v[r + 2] = FUSED ? nr[r] + beta * ns[r] : ns[r];
+      // requested before the next task's rows, so that waiting for them does not wait
+      // for the prefetch
+      if (!plain && !first) load_geom(base);
+      if (kc + 1 < kc1) {
+        // rows 2..HC+1 of the next task: padded rows (kc+1)*HC + 2 ..
 #pragma unroll
-      for (int r = 1; r <= HC; ++r) {
-        const long long gi = base + r * P;
-        const T cs = v[r - 1] + v[r + 1];
-        const T pl = lane_shr(v[r]), pr = lane_shl(v[r]);
-        const T csl = lane_shr(cs), csr = lane_shl(cs);
-        const T qv = a.cC * v[r] + a.cE * (pl + pr) + a.cN * cs + a.cD * (csl + csr);
-        if (owner) {
-          if (FUSED) pnew[gi] = v[r];
-          a.q[gi] = qv;
-          pq += (double)v[r] * (double)qv;
+        for (int r = 0; r < HC; ++r) {
+          ns[r] = src[base + (HC + 2 + r) * P];
+          if (FUSED) nr[r] = a.r[base + (HC + 2 + r) * P];
         }
       }
-    } else {
-      const unsigned long long bm = a.tbody[t];
-      bacc = 0.0;
-      auto pval = [&](int8_t tg, int r) -> T {
-        if (!FUSED) return rs[r];
-        if (tg == TAG_FREE) return ra[r] + beta * rs[r];
-        if (tg >= TAG_BODY0) return (T)s_pb[tg - TAG_BODY0];
-        return (T)0;
-      };
-      // lower node row of the current cell row (own column and right neighbour)
-      int8_t g0 = a.tag[base];
-      T p0 = pval(g0, 0);
-      T x0 = a.dx[base], y0 = a.dy[base];
-      int8_t g1n = (int8_t)lane_shl((int)g0);
-      T p1n = lane_shl(p0), x1n = lane_shl(x0), y1n = lane_shl(y0);
-      T carry = (T)0;
+      if (plain) {
 #pragma unroll
-      for (int sr = 0; sr <= HC; ++sr) {
-        const long long gu = base + (sr + 1) * P;
-        const int8_t g3 = a.tag[gu];
-        const T p3 = pval(g3, sr + 1);
-        const T x3 = a.dx[gu], y3 = a.dy[gu];
-        const int8_t g2 = (int8_t)lane_shl((int)g3);
-        const T p2 = lane_shl(p3), x2 = lane_shl(x3), y2 = lane_shl(y3);
-        // cell (own column, row sr): nodes 0 = (c, sr), 1 = (c+1, sr), 2 = (c+1, sr+1),
-        // 3 = (c, sr+1)
-        const bool halo = (g0 == TAG_HALO) | (g1n == TAG_HALO) | (g2 == TAG_HALO) | (g3 == TAG_HALO);
-        const bool inside = (g0 >= TAG_BODY0) & (g1n == g0) & (g2 == g0) & (g3 == g0);
-        T c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-        if (!halo && !inside && lane < 63)
-          cell_apply<T>(a.ry, x0, x1n, x2, x3, y0, y1n, y2, y3, p0, p1n, p2, p3, c0, c1, c2,
-                        c3);
-        const T acc = carry + c0 + lane_shr(c1);
-        carry = c3 + lane_shr(c2);
-        if (sr >= 1) {
-          const long long gi = base + sr * P;
+        for (int r = 1; r <= HC; ++r) {
+          const long long gi = base + r * P;
+          const T csum = v[r - 1] + v[r + 1];
+          const T pl = lane_shr(v[r]), pr = lane_shl(v[r]);
+          const T csl = lane_shr(csum), csr = lane_shl(csum);
+          const T qv = a.cC * v[r] + a.cE * (pl + pr) + a.cN * csum + a.cD * (csl + csr);
           if (owner) {
-            if (FUSED) pnew[gi] = p0;
-            const bool keep = (g0 == TAG_FREE) || (a.write_all && g0 != TAG_HALO);
-            a.q[gi] = keep ? acc : (T)0;
-            if (g0 == TAG_FREE) pq += (double)p0 * (double)acc;
+            if (FUSED) pnew[gi] = v[r];
+            a.q[gi] = qv;
+            pq += (double)v[r] * (double)qv;
           }
-          if (bm) {
-            unsigned long long rowb = __ballot(owner && g0 >= TAG_BODY0);
-            while (rowb) {
-              const int src = __ffsll((long long)rowb) - 1;
-              const int bt = __shfl((int)g0, src, 64);
-              const bool mine = owner && g0 == bt;
-              const double v = wave_sum(mine ? (double)acc : 0.0);
-              if (lane == bt - TAG_BODY0) bacc += v;
-              rowb &= ~__ballot(mine);
+        }
+      } else {
+        if (FUSED) {
+          // body nodes carry p_b, Dirichlet and halo nodes 0 (rows 0 and 1 of a later
+          // task were corrected as rows HC and HC+1 of the previous one)
+#pragma unroll
+          for (int r = 0; r < HC + 2; ++r) {
+            if (r < 2 && !first) continue;
+            const int8_t t = tg[r];
+            if (t >= TAG_BODY0)
+              v[r] = (T)s_pb[t - TAG_BODY0];
+            else if (t != TAG_FREE)
+              v[r] = (T)0;
+          }
+        }
+        const bool bm = (body_mask >> it) & 1ull;
+        const int slot = __shfl(slot_l, it, 64);
+        double bacc = 0.0;  // lane b accumulates body b of this task
+        // lower node row of the current cell row (own column and right neighbour)
+        int8_t g0 = tg[0];
+        T p0 = v[0], x0 = ddx[0], y0 = ddy[0];
+        int8_t g1n = (int8_t)lane_shl((int)g0);
+        T p1n = lane_shl(p0), x1n = lane_shl(x0), y1n = lane_shl(y0);
+        T carry = (T)0;
+#pragma unroll
+        for (int sr = 0; sr <= HC; ++sr) {
+          const int8_t g3 = tg[sr + 1];
+          const T p3 = v[sr + 1], x3 = ddx[sr + 1], y3 = ddy[sr + 1];
+          const int8_t g2 = (int8_t)lane_shl((int)g3);
+          const T p2 = lane_shl(p3), x2 = lane_shl(x3), y2 = lane_shl(y3);
+          // cell (own column, row sr): nodes 0 = (c, sr), 1 = (c+1, sr), 2 = (c+1, sr+1),
+          // 3 = (c, sr+1)
+          const bool halo =
+              (g0 == TAG_HALO) | (g1n == TAG_HALO) | (g2 == TAG_HALO) | (g3 == TAG_HALO);
+          const bool inside = (g0 >= TAG_BODY0) & (g1n == g0) & (g2 == g0) & (g3 == g0);
+          T c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+          if (!halo && !inside && lane < 63)
+            cell_apply<T>(a.ry, x0, x1n, x2, x3, y0, y1n, y2, y3, p0, p1n, p2, p3, c0, c1, c2,
+                          c3);
+          const T acc = carry + c0 + lane_shr(c1);
+          carry = c3 + lane_shr(c2);
+          if (sr >= 1) {
+            const long long gi = base + sr * P;
+            if (owner) {
+              if (FUSED) pnew[gi] = p0;
+              const bool keep = (g0 == TAG_FREE) || (a.write_all && g0 != TAG_HALO);
+              a.q[gi] = keep ? acc : (T)0;
+              if (g0 == TAG_FREE) pq += (double)p0 * (double)acc;
+            }
+            if (bm) {
+              unsigned long long rowb = __ballot(owner && g0 >= TAG_BODY0);
+              while (rowb) {
+                const int sl = __ffsll((long long)rowb) - 1;
+                const int bt = __shfl((int)g0, sl, 64);
+                const bool mine = owner && g0 == bt;
+                const double bv = wave_sum(mine ? (double)acc : 0.0);
+                if (lane == bt - TAG_BODY0) bacc += bv;
+                rowb &= ~__ballot(mine);
+              }
             }
           }
+          g0 = g3;
+          p0 = p3;
+          x0 = x3;
+          y0 = y3;
+          g1n = g2;
+          p1n = p2;
+          x1n = x2;
+          y1n = y2;
         }
-        g0 = g3;
-        p0 = p3;
-        x0 = x3;
-        y0 = y3;
-        g1n = g2;
-        p1n = p2;
-        x1n = x2;
-        y1n = y2;
+        if (bm && lane < a.nb) a.bpart[(long long)slot * a.nb + lane] = bacc;
       }
-      if (bm && lane < a.nb) a.bpart[(long long)a.tslot[t] * a.nb + lane] = bacc;
+      v[0] = v[HC];
+      v[1] = v[HC + 1];
     }
   }
   const double bsum = block_sum(pq, s_red);
@@ -404,13 +477,18 @@ inline void launch_apply(int hc, int G, hipStream_t st, const ApplyArgs<T>& a,
 }
 
 // Per-body sums of the slot partials, into s_qb[0 .. nb); wave w handles bodies
-// w, w+4, ...  Fixed order.
-__device__ __forceinline__ void body_sums(const double* __restrict__ bpart, int nslots, int nb,
+// w, w+4, ...  Fixed order.  The slot count is read together with the first 64 slots
+// of every body (the partial buffer always holds at least 64 slots), so the common
+// case costs one memory round trip.
+__device__ __forceinline__ void body_sums(const double* __restrict__ bpart,
+                                          const int* __restrict__ nslots_p, int nb,
                                           double* s_qb) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nslots = *nslots_p;
   for (int b = w; b < nb; b += BLOCK / 64) {
-    double v = 0.0;
-    for (int sl = lane; sl < nslots; sl += 64) v += bpart[(long long)sl * nb + b];
+    double v = bpart[(long long)lane * nb + b];
+    v = lane < nslots ? v : 0.0;
+    for (int sl = lane + 64; sl < nslots; sl += 64) v += bpart[(long long)sl * nb + b];
     v = wave_sum(v);
     if (lane == 0) s_qb[b] = v;
   }

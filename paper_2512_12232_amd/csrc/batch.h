@@ -112,7 +112,7 @@ __global__ void __launch_bounds__(BLOCK) k_b_fin(const BElem* __restrict__ bv, i
     if (threadIdx.x == 0) flags[blockIdx.x] = out->done;
     return;
   }
-  body_sums(b.bpart, *b.nslots, b.nb, s_qb);
+  body_sums(b.bpart, b.nslots, b.nb, s_qb);
   double s2 = 0.0, s3 = 0.0;
   for (int i = threadIdx.x; i < b.G2; i += BLOCK) {
     s2 += b.part2[i];
@@ -207,6 +207,10 @@ struct BatchPlan {
   size_t bytes = 0;
 };
 
+// Tasks per wavefront segment (on average, by cost) in batched applies: the launch
+// holds many systems, so segments are sized for the prefetch, not for residency.
+constexpr int BATCH_SEG = 4;
+
 static int batch_hc(int nvar, const mfp_variant* v) {
   int hc = 4;
   for (int i = 0; i < nvar; ++i)
@@ -233,8 +237,8 @@ static size_t batch_layout(int nvar, const mfp_variant* v, int nb, int precision
     char* b = bp.take<char>(sz);
     SolveWs w;
     solve_layout(&v[i].grid, nb, precision, b, &w, hc);
-    int gpb;
-    const int G = apply_blocks(w.L.ntasks(), &gpb);
+    w.sp = seg_plan(w.L, (w.L.ntasks() + BATCH_SEG - 1) / BATCH_SEG);
+    const int G = w.sp.G;
     const int G2 = grid_blocks(w.L.n);
     if (P) {
       P->w[i] = w;

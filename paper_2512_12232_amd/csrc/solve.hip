@@ -168,6 +168,93 @@ __global__ void k_assign_slots(int ntiles, const unsigned long long* __restrict_
   if (threadIdx.x == 0) *nslots = s_base;
 }
 
+// Apply work list.  The tasks of each strip are cut into segments of consecutive
+// chunks (one wavefront marches through one segment) so that every segment costs
+// about the same: a constant-stencil task counts 1, a task that evaluates its cells'
+// geometry GENERAL_COST (measured ratio of their run times).  The budget is the total
+// cost over `target` segments; a segment closes once it reaches the budget or 64
+// tasks, so a strip of cost c yields at most floor(c / budget) + 1 + nchunk / 64
+// segments and the whole list at most target + nstrip (1 + nchunk / 64) entries (the
+// host sizes the table by that bound).
+// Placement: wavefront w of a launch of W = 4 G wavefronts reads entries w, w + W, ...;
+// its work-group runs on XCD x for w in [x W/8, (x+1) W/8) (see apply_core).  The
+// segments, in strip order, are dealt to the 8 XCDs in contiguous runs of equal count,
+// each run filling its XCD's entries round by round, so neighbouring strips share an
+// L2 and every XCD gets the same share of the work.  Unused entries have length 0.
+// Entry: x = strip, y = first chunk | (length << 16), (z, w) = 64-bit mask of the
+// segment's constant-stencil tasks.  One block.
+constexpr int GENERAL_COST = 4;
+constexpr int SEG_MAX_STRIPS = 2048;
+
+__global__ void __launch_bounds__(1024) k_seg_plan(Layout L, const uint8_t* __restrict__ tplain,
+                                                   int target, int W, int tabsize,
+                                                   int4* __restrict__ segtab) {
+  __shared__ int s_off[SEG_MAX_STRIPS];
+  __shared__ long long s_red[1024 / 64];
+  __shared__ int s_budget, s_total;
+  const int nt = L.ntasks(), ns = L.nstrip, nc = L.nchunk;
+  for (int i = threadIdx.x; i < tabsize; i += blockDim.x) segtab[i] = make_int4(0, 0, 0, 0);
+  long long c = 0;
+  for (int t = threadIdx.x; t < nt; t += blockDim.x) c += tplain[t] ? 1 : GENERAL_COST;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) s_red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long tot = 0;
+    for (int i = 0; i < (int)(blockDim.x >> 6); ++i) tot += s_red[i];
+    long long b = (tot + target - 1) / target;
+    if (b < GENERAL_COST) b = GENERAL_COST;
+    s_budget = (int)(b < (1 << 30) ? b : (1 << 30));
+  }
+  __syncthreads();
+  const int budget = s_budget;
+  // with `first` >= 0, segment j (strip order, from `first`) goes to pos(j)
+  const int per = W / 8;  // entries per XCD and round
+  auto walk = [&](int m, int first, int total) -> int {
+    int cnt = 0, acc = 0, len = 0, kc0 = 0;
+    unsigned long long mask = 0ull;
+    for (int kc = 0; kc < nc; ++kc) {
+      const int pl = tplain[kc * ns + m];
+      acc += pl ? 1 : GENERAL_COST;
+      if (pl) mask |= 1ull << len;
+      ++len;
+      if (acc >= budget || len == 64 || kc == nc - 1) {
+        if (first >= 0) {
+          const int j = first + cnt;
+          const int q = total / 8, rem = total % 8;
+          // XCD x holds segments [x q + min(x, rem), ...)
+          const int x = j < rem * (q + 1) ? j / (q + 1) : rem + (j - rem * (q + 1)) / (q > 0 ? q : 1);
+          const int i = j - (x * q + (x < rem ? x : rem));
+          const long long pos = (long long)(i / per) * W + (long long)x * per + i % per;
+          if (pos < tabsize)
+            segtab[pos] = make_int4(m, kc0 | (len << 16), (int)(mask & 0xffffffffull),
+                                    (int)(mask >> 32));
+        }
+        ++cnt;
+        acc = 0;
+        len = 0;
+        mask = 0ull;
+        kc0 = kc + 1;
+      }
+    }
+    return cnt;
+  };
+  for (int m = threadIdx.x; m < ns; m += blockDim.x) s_off[m] = walk(m, -1, 0);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int acc = 0;
+    for (int m = 0; m < ns; ++m) {
+      const int v = s_off[m];
+      s_off[m] = acc;
+      acc += v;
+    }
+    s_total = acc;
+  }
+  __syncthreads();
+  const int total = s_total;
+  for (int m = threadIdx.x; m < ns; m += blockDim.x) walk(m, s_off[m], total);
+}
+
 // w = g + T x as a full nodal vector (free: x, Dirichlet: g, body b: psi_b of the
 // current iterate).
 template <typename T>
@@ -220,7 +307,7 @@ __global__ void __launch_bounds__(BLOCK) k_resid_finalize(const double* __restri
                                                           double rtol2, double stop_abs) {
   __shared__ double s_red[BLOCK / 64];
   __shared__ double s_qb[MFP_MAX_BODIES];
-  body_sums(bpart, *nslots, nb, s_qb);
+  body_sums(bpart, nslots, nb, s_qb);
   double s = 0.0;
   for (int i = threadIdx.x; i < G2; i += BLOCK) s += part[i];
   s = block_sum(s, s_red);
@@ -378,7 +465,6 @@ __device__ __forceinline__ void update_core(const UpdArgs<T>& u, const int vblk,
                                             double* s_red, double* s_qb) {
   using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
   DevState* st = u.st;
-  if (st->done) return;
   long long k = u.k;
   const T* p = u.p;
   if (u.kdev) {
@@ -403,12 +489,18 @@ __device__ __forceinline__ void update_core(const UpdArgs<T>& u, const int vblk,
   const int cur = (int)(k & 1), nxt = cur ^ 1;
   const int nb = u.nb;
   // every scalar this block needs is requested at once
+  const int done = st->done;
   const double rr_cur = st->rr[cur];
-  double pbv = 0.0;
-  if (threadIdx.x < nb) pbv = st->pb[cur][threadIdx.x];
+  double pbv = 0.0, xbv = 0.0, rbv = 0.0;
+  if (threadIdx.x < nb) {
+    pbv = st->pb[cur][threadIdx.x];
+    xbv = st->xb[cur][threadIdx.x];
+    rbv = st->rb[cur][threadIdx.x];
+  }
   double s = 0.0;
   for (int i = threadIdx.x; i < u.G; i += BLOCK) s += u.part[i];
-  body_sums(u.bpart, *u.nslots, nb, s_qb);
+  body_sums(u.bpart, u.nslots, nb, s_qb);
+  if (done) return;
   if (threadIdx.x < nb) s += pbv * s_qb[threadIdx.x];
   const double pq = block_sum(s, s_red);
   if (!(pq > 0.0) || !isfinite(pq)) {
@@ -420,18 +512,21 @@ __device__ __forceinline__ void update_core(const UpdArgs<T>& u, const int vblk,
     return;
   }
   const double alpha_d = rr_cur / pq;
-  if (vblk == 0 && threadIdx.x == 0) {
-    double rbr = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      st->xb[nxt][b] = st->xb[cur][b] + alpha_d * st->pb[cur][b];
-      const double rbn = st->rb[cur][b] - alpha_d * s_qb[b];
-      st->rb[nxt][b] = rbn;
-      rbr += rbn * rbn;
+  if (vblk == 0 && threadIdx.x < 64) {
+    // wavefront 0 of block 0 advances the body unknowns (nb <= 64)
+    double rbn = 0.0;
+    if (threadIdx.x < nb) {
+      st->xb[nxt][threadIdx.x] = xbv + alpha_d * pbv;
+      rbn = rbv - alpha_d * s_qb[threadIdx.x];
+      st->rb[nxt][threadIdx.x] = rbn;
     }
-    st->rb_rr[nxt] = rbr;
-    st->alpha = alpha_d;
-    st->pq = pq;
-    st->ka = k + 1;
+    const double rbr = wave_sum(rbn * rbn);
+    if (threadIdx.x == 0) {
+      st->rb_rr[nxt] = rbr;
+      st->alpha = alpha_d;
+      st->pq = pq;
+      st->ka = k + 1;
+    }
   }
   const T alpha = (T)alpha_d;
   double acc = 0.0;
@@ -605,8 +700,60 @@ __global__ void __launch_bounds__(BLOCK) k_samples(SampleArgs a) {
 // ---------------------------------------------------------------------------------
 constexpr int GMAX = 2048;  // max blocks of the reduction kernels
 
+// Wavefronts of k_apply<T, FUSED, hc> resident on the current device at once (0 when
+// the runtime cannot say).
+template <typename T, bool FUSED>
+static int apply_resident_waves(int hc) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  const void* f = hc == 4 ? reinterpret_cast<const void*>(&k_apply<T, FUSED, 4>)
+                          : reinterpret_cast<const void*>(&k_apply<T, FUSED, 8>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) != hipSuccess) return 0;
+  return per_cu * cus * WAVES;
+}
+
+// Segments for a single solve: about as many as the solve loop's fused apply keeps
+// resident, less the per-strip slack of the segment bound, so that the whole list runs
+// in one round of wavefronts.
+static int single_target(const Layout& L, int precision) {
+  const int wres = precision == MFP_FP64 ? apply_resident_waves<double, true>(L.hc)
+                                         : apply_resident_waves<float, true>(L.hc);
+  if (wres <= 0) return L.ntasks();
+  int t = wres - L.nstrip * (L.nchunk / 64 + 1);
+  if (t < wres / 2) t = wres / 2;
+  return t > 0 ? t : 1;
+}
+
+// Size of the apply work list for a segment target (see k_seg_plan) and the launch
+// that covers it: at most 1024 blocks, a multiple of 8 (XCD-aware order); with more
+// entries than wavefronts, each wavefront takes every W-th entry.
+struct SegPlan {
+  int target = 1, tabsize = 32, G = 8;
+};
+
+static SegPlan seg_plan(const Layout& L, int target) {
+  SegPlan p;
+  const long long nt = L.ntasks();
+  if (target < 1) target = 1;
+  long long cap = (long long)target + (long long)L.nstrip * (L.nchunk / 64 + 1);
+  if (cap > nt) cap = nt;
+  long long G = (cap + WAVES - 1) / WAVES;
+  G = (G + 7) & ~7LL;
+  if (G > 1024) G = 1024;
+  const long long W = WAVES * G;
+  // rounds so that every XCD's share, ceil(cap / 8), fits in its W/8 entries per round
+  const long long rounds = ((cap + 7) / 8 + W / 8 - 1) / (W / 8);
+  p.target = target;
+  p.tabsize = (int)(rounds * W);
+  p.G = (int)G;
+  return p;
+}
+
 struct SolveWs {
   Layout L;
+  SegPlan sp;     // apply work list and launch size
   int8_t* tag;
   double *dx, *dy, *g, *x, *r, *p0, *p1, *q;
   float *dxf, *dyf, *xf, *rf, *p0f, *p1f, *qf;
@@ -614,6 +761,7 @@ struct SolveWs {
   unsigned long long* tbody;
   int* tslot;
   int* nslots;
+  int4* segtab;   // apply work list (k_seg_plan)
   double* part;
   double* part2;
   double* part3;  // batched refinement: partials of the FP64 residual
@@ -655,17 +803,22 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.tbody = bp.take<unsigned long long>(nt);
   w.tslot = bp.take<int>(nt);
   w.nslots = bp.take<int>(1);
+  w.segtab = bp.take<int4>((size_t)nt + 4096);
   w.part = bp.take<double>(GMAX);
   w.part2 = bp.take<double>(GMAX);
   w.part3 = bp.take<double>(GMAX);
-  w.bpart = bp.take<double>((size_t)nt * (nb > 0 ? nb : 1));
+  // at least 64 slots: the body reductions read the first 64 before the slot count
+  w.bpart = bp.take<double>((size_t)(nt > 64 ? nt : 64) * (nb > 0 ? nb : 1));
   w.st = bp.take<DevState>(1);
   w.st2 = bp.take<DevState>(1);
   w.nfree = bp.take<long long>(1);
   w.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
   w.boxes = bp.take<int>(4 * (nb > 0 ? nb : 1));
   w.count = bp.take<int>(1);
-  if (out) *out = w;
+  if (out) {
+    if (base) w.sp = seg_plan(w.L, single_target(w.L, precision));
+    *out = w;
+  }
   return bp.off + 256;
 }
 
@@ -678,16 +831,15 @@ static int grid_blocks(long long n) {
   return (int)b;
 }
 
-// Apply: groups of 4 tasks (one per wavefront); groups per block chosen so that at
-// most ~1024 blocks run; block count a multiple of 8 (XCD-aware task order).
-static int apply_blocks(int ntasks, int* gpb) {
-  const int groups = (ntasks + WAVES - 1) / WAVES;
-  int t = (groups + 1023) / 1024;
-  if (t < 1) t = 1;
-  int g = (groups + t - 1) / t;
-  g = (g + 7) & ~7;
-  *gpb = t;
-  return g;
+// Streaming kernels of the single-system CG loop (update, residual, refinement):
+// about two elements per thread, so that each thread's operands are requested before
+// the block forms its scalars, and at most 1024 blocks, so that the next kernel's
+// reduction of the per-block partials stays small.
+static int loop_blocks(long long n) {
+  long long b = (n + 2 * BLOCK - 1) / (2 * BLOCK);
+  if (b > 1024) b = 1024;
+  if (b < 1) b = 1;
+  return (int)b;
 }
 
 template <typename T>
@@ -696,8 +848,9 @@ static ApplyArgs<T> make_apply_args(const SolveWs& w, const mfp_grid& g, int nb,
   ApplyArgs<T> a{};
   a.P = w.L.P;
   a.nstrip = w.L.nstrip;
-  a.ntasks = w.L.ntasks();
-  apply_blocks(a.ntasks, &a.gpb);
+  a.segtab = w.segtab;
+  a.tabsize = w.sp.tabsize;
+  a.G = w.sp.G;
   a.tag = w.tag;
   a.dx = dx;
   a.dy = dy;
@@ -752,6 +905,11 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   s.p1 = w.p1;
   s.q = w.q;
   s.nfree = w.nfree;
+  if (w.L.nstrip > SEG_MAX_STRIPS || w.L.nchunk > 0xffff) {
+    set_error("grid too large for the apply work list (nx <= %d, ny <= %d)",
+              SEG_MAX_STRIPS * SW - 1, 0xffff * 4 - 1);
+    return MFP_E_ARG;
+  }
   MFP_TRY_HIP(hipMemsetAsync(w.st, 0, sizeof(DevState), st));
   MFP_TRY_HIP(hipMemsetAsync(w.st2, 0, sizeof(DevState), st));
   if (precision != MFP_FP64) {
@@ -767,6 +925,9 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
                                                                      w.tplain, w.tbody);
   MFP_TRY_HIP(hipGetLastError());
   k_assign_slots<<<1, BLOCK, 0, st>>>(w.L.ntasks(), w.tbody, w.tslot, w.nslots);
+  MFP_TRY_HIP(hipGetLastError());
+  k_seg_plan<<<1, 1024, 0, st>>>(w.L, w.tplain, w.sp.target, WAVES * w.sp.G, w.sp.tabsize,
+                                 w.segtab);
   MFP_TRY_HIP(hipGetLastError());
   return MFP_OK;
 }
@@ -815,8 +976,6 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
   MFP_TRY_HIP(hipMemcpy2DAsync((char*)src + esz * (w.L.P + 1), esz * w.L.P, p,
                                esz * (g.nx + 1), esz * (g.nx + 1), g.ny + 1,
                                hipMemcpyDeviceToDevice, st));
-  int tpb;
-  const int G = apply_blocks(w.L.ntasks(), &tpb);
   hipEvent_t e0, e1;
   MFP_TRY_HIP(hipEventCreate(&e0));
   MFP_TRY_HIP(hipEventCreate(&e1));
@@ -827,13 +986,13 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
       a.src = w.p0;
       a.q = w.q;
       a.write_all = 1;
-      launch_apply<double, false>(w.L.hc, G, st, a);
+      launch_apply<double, false>(w.L.hc, w.sp.G, st, a);
     } else {
       ApplyArgs<float> a = make_apply_args<float>(w, g, nbmax, w.dxf, w.dyf);
       a.src = w.p0f;
       a.q = w.qf;
       a.write_all = 1;
-      launch_apply<float, false>(w.L.hc, G, st, a);
+      launch_apply<float, false>(w.L.hc, w.sp.G, st, a);
     }
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) {
@@ -883,9 +1042,8 @@ struct CgCount {
 template <typename T>
 static int cg_run(const mfp_grid& g, int nb, const SolveWs& w, const CgBufs<T>& B,
                   const mfp_solver_opts& o, hipStream_t st, CgCount* cnt, long long k0 = 0) {
-  int gpb;
-  const int G = apply_blocks(w.L.ntasks(), &gpb);
-  const int G2 = grid_blocks(w.L.n);
+  const int G = w.sp.G;
+  const int G2 = loop_blocks(w.L.n);
   T* pbuf[2] = {B.p0, B.p1};
   const int every = o.check_every > 0 ? o.check_every : 50;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
@@ -969,14 +1127,12 @@ static int cg_run(const mfp_grid& g, int nb, const SolveWs& w, const CgBufs<T>& 
 // k_resid_finalize in the given mode.
 static int residual64(const mfp_grid& g, int nb, const SolveWs& w, hipStream_t st, int mode,
                       double rtol, double stop_abs = 0.0) {
-  int gpb;
-  const int G = apply_blocks(w.L.ntasks(), &gpb);
-  const int G2 = grid_blocks(w.L.n);
+  const int G2 = loop_blocks(w.L.n);
   k_form_w<double><<<G2, BLOCK, 0, st>>>(w.L.n, w.tag, w.x, w.g, w.st, w.p0);
   ApplyArgs<double> a = make_apply_args<double>(w, g, nb, w.dx, w.dy);
   a.src = w.p0;
   a.q = w.q;
-  launch_apply<double, false>(w.L.hc, G, st, a);
+  launch_apply<double, false>(w.L.hc, w.sp.G, st, a);
   k_resid<<<G2, BLOCK, 0, st>>>(w.L.n, w.q, w.r, w.part2, mode != 1 ? 1 : 0);
   k_resid_finalize<<<1, BLOCK, 0, st>>>(w.part2, G2, w.bpart, w.nslots, w.st, nb, mode,
                                         rtol * rtol, stop_abs);
@@ -1009,7 +1165,7 @@ static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_so
   const bool ir = o.precision == MFP_FP32_IR;
   const double delta = ir ? (o.inner_rtol > 0 && o.inner_rtol < 1 ? o.inner_rtol : 0.1) : o.rtol;
   const int max_upd = o.max_outer > 0 ? o.max_outer : 1000;
-  const int G2 = grid_blocks(w.L.n);
+  const int G2 = loop_blocks(w.L.n);
   double rr = 0, rr0 = 0;
   MFP_TRY(read_rr(w, st, &rr, &rr0));
   if (rr <= o.rtol * o.rtol * rr0) return 1;
