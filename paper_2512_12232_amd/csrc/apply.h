@@ -141,6 +141,82 @@ __device__ __forceinline__ float lane_shl(float v) {
 }
 __device__ __forceinline__ int lane_shl(int v) { return dpp_shl1_i(v); }
 
+// ---- per-task building blocks --------------------------------------------------
+// A task is a 64-column strip x HC node rows; "rows" 0..HC+1 below are the task's
+// HC owned rows plus one halo row on each side, held one value per lane.
+
+// K v at rows 1..HC (qr[r-1]) of a task whose footprint is all free and undisplaced:
+// the assembled 9-point stencil, horizontal neighbours by lane shifts.
+template <typename T, int HC>
+__device__ __forceinline__ void stencil_task(T cC, T cE, T cN, T cD, const T (&v)[HC + 2],
+                                             T (&qr)[HC]) {
+#pragma unroll
+  for (int r = 1; r <= HC; ++r) {
+    const T csum = v[r - 1] + v[r + 1];
+    const T pl = lane_shr(v[r]), pr = lane_shl(v[r]);
+    const T csl = lane_shr(csum), csr = lane_shl(csum);
+    qr[r - 1] = cC * v[r] + cE * (pl + pr) + cN * csum + cD * (csl + csr);
+  }
+}
+
+// K v at rows 1..HC of any task: march over the HC+1 cell rows touching its rows.
+// Lane c evaluates cell (c, sr) from its own nodes and those of lane c+1 (shifted in),
+// keeps the cell's contributions to its own column and shifts the contributions to
+// column c+1 over; node row sr is complete once cell rows sr-1 and sr are done.
+// Cells with a halo node, and cells whose four nodes lie in one body, are skipped.
+template <typename T, int HC>
+__device__ __forceinline__ void march_task(T ry, int lane, const int8_t (&tg)[HC + 2],
+                                           const T (&v)[HC + 2], const T (&ddx)[HC + 2],
+                                           const T (&ddy)[HC + 2], T (&qr)[HC]) {
+  // lower node row of the current cell row (own column and right neighbour)
+  int8_t g0 = tg[0];
+  T p0 = v[0], x0 = ddx[0], y0 = ddy[0];
+  int8_t g1n = (int8_t)lane_shl((int)g0);
+  T p1n = lane_shl(p0), x1n = lane_shl(x0), y1n = lane_shl(y0);
+  T carry = (T)0;
+#pragma unroll
+  for (int sr = 0; sr <= HC; ++sr) {
+    const int8_t g3 = tg[sr + 1];
+    const T p3 = v[sr + 1], x3 = ddx[sr + 1], y3 = ddy[sr + 1];
+    const int8_t g2 = (int8_t)lane_shl((int)g3);
+    const T p2 = lane_shl(p3), x2 = lane_shl(x3), y2 = lane_shl(y3);
+    // cell (own column, row sr): nodes 0 = (c, sr), 1 = (c+1, sr), 2 = (c+1, sr+1),
+    // 3 = (c, sr+1)
+    const bool halo =
+        (g0 == TAG_HALO) | (g1n == TAG_HALO) | (g2 == TAG_HALO) | (g3 == TAG_HALO);
+    const bool inside = (g0 >= TAG_BODY0) & (g1n == g0) & (g2 == g0) & (g3 == g0);
+    T c0 = 0, c1 = 0, c2 = 0, c3 = 0;
+    if (!halo && !inside && lane < 63)
+      cell_apply<T>(ry, x0, x1n, x2, x3, y0, y1n, y2, y3, p0, p1n, p2, p3, c0, c1, c2, c3);
+    const T acc = carry + c0 + lane_shr(c1);
+    carry = c3 + lane_shr(c2);
+    if (sr >= 1) qr[sr - 1] = acc;
+    g0 = g3;
+    p0 = p3;
+    x0 = x3;
+    y0 = y3;
+    g1n = g2;
+    p1n = p2;
+    x1n = x2;
+    y1n = y2;
+  }
+}
+
+// Per-body sums of one node row: lane b of the wavefront accumulates the sum of `val`
+// over the owned nodes of body b in this row (fixed order).
+__device__ __forceinline__ void body_row(bool owner, int8_t g, double val, int lane,
+                                         double& bacc) {
+  unsigned long long rowb = __ballot(owner && g >= TAG_BODY0);
+  while (rowb) {
+    const int src = __ffsll((long long)rowb) - 1;
+    const int bt = __shfl((int)g, src, 64);
+    const bool mine = owner && g == bt;
+    const double bv = wave_sum(mine ? val : 0.0);
+    if (lane == bt - TAG_BODY0) bacc += bv;
+    rowb &= ~__ballot(mine);
+  }
+}
+
 template <typename T>
 struct ApplyArgs {
   int P, nstrip;                 // pitch, strips (task t = chunk * nstrip + strip)
@@ -345,20 +421,10 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
           if (FUSED) nr[r] = a.r[base + (HC + 2 + r) * P];
         }
       }
+      T qr[HC];
+      const bool bm = !plain && ((body_mask >> it) & 1ull);
       if (plain) {
-#pragma unroll
-        for (int r = 1; r <= HC; ++r) {
-          const long long gi = base + r * P;
-          const T csum = v[r - 1] + v[r + 1];
-          const T pl = lane_shr(v[r]), pr = lane_shl(v[r]);
-          const T csl = lane_shr(csum), csr = lane_shl(csum);
-          const T qv = a.cC * v[r] + a.cE * (pl + pr) + a.cN * csum + a.cD * (csl + csr);
-          if (owner) {
-            if (FUSED) pnew[gi] = v[r];
-            a.q[gi] = qv;
-            pq += (double)v[r] * (double)qv;
-          }
-        }
+        stencil_task<T, HC>(a.cC, a.cE, a.cN, a.cD, v, qr);
       } else {
         if (FUSED) {
           // body nodes carry p_b, Dirichlet and halo nodes 0 (rows 0 and 1 of a later
@@ -373,62 +439,25 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
               v[r] = (T)0;
           }
         }
-        const bool bm = (body_mask >> it) & 1ull;
-        const int slot = __shfl(slot_l, it, 64);
-        double bacc = 0.0;  // lane b accumulates body b of this task
-        // lower node row of the current cell row (own column and right neighbour)
-        int8_t g0 = tg[0];
-        T p0 = v[0], x0 = ddx[0], y0 = ddy[0];
-        int8_t g1n = (int8_t)lane_shl((int)g0);
-        T p1n = lane_shl(p0), x1n = lane_shl(x0), y1n = lane_shl(y0);
-        T carry = (T)0;
+        march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
+      }
+      double bacc = 0.0;  // lane b accumulates body b of this task
 #pragma unroll
-        for (int sr = 0; sr <= HC; ++sr) {
-          const int8_t g3 = tg[sr + 1];
-          const T p3 = v[sr + 1], x3 = ddx[sr + 1], y3 = ddy[sr + 1];
-          const int8_t g2 = (int8_t)lane_shl((int)g3);
-          const T p2 = lane_shl(p3), x2 = lane_shl(x3), y2 = lane_shl(y3);
-          // cell (own column, row sr): nodes 0 = (c, sr), 1 = (c+1, sr), 2 = (c+1, sr+1),
-          // 3 = (c, sr+1)
-          const bool halo =
-              (g0 == TAG_HALO) | (g1n == TAG_HALO) | (g2 == TAG_HALO) | (g3 == TAG_HALO);
-          const bool inside = (g0 >= TAG_BODY0) & (g1n == g0) & (g2 == g0) & (g3 == g0);
-          T c0 = 0, c1 = 0, c2 = 0, c3 = 0;
-          if (!halo && !inside && lane < 63)
-            cell_apply<T>(a.ry, x0, x1n, x2, x3, y0, y1n, y2, y3, p0, p1n, p2, p3, c0, c1, c2,
-                          c3);
-          const T acc = carry + c0 + lane_shr(c1);
-          carry = c3 + lane_shr(c2);
-          if (sr >= 1) {
-            const long long gi = base + sr * P;
-            if (owner) {
-              if (FUSED) pnew[gi] = p0;
-              const bool keep = (g0 == TAG_FREE) || (a.write_all && g0 != TAG_HALO);
-              a.q[gi] = keep ? acc : (T)0;
-              if (g0 == TAG_FREE) pq += (double)p0 * (double)acc;
-            }
-            if (bm) {
-              unsigned long long rowb = __ballot(owner && g0 >= TAG_BODY0);
-              while (rowb) {
-                const int sl = __ffsll((long long)rowb) - 1;
-                const int bt = __shfl((int)g0, sl, 64);
-                const bool mine = owner && g0 == bt;
-                const double bv = wave_sum(mine ? (double)acc : 0.0);
-                if (lane == bt - TAG_BODY0) bacc += bv;
-                rowb &= ~__ballot(mine);
-              }
-            }
-          }
-          g0 = g3;
-          p0 = p3;
-          x0 = x3;
-          y0 = y3;
-          g1n = g2;
-          p1n = p2;
-          x1n = x2;
-          y1n = y2;
+      for (int r = 1; r <= HC; ++r) {
+        const long long gi = base + r * P;
+        const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
+        const T qv = qr[r - 1];
+        if (owner) {
+          if (FUSED) pnew[gi] = v[r];
+          const bool keep = (g == TAG_FREE) || (a.write_all && g != TAG_HALO);
+          a.q[gi] = keep ? qv : (T)0;
+          if (g == TAG_FREE) pq += (double)v[r] * (double)qv;
         }
-        if (bm && lane < a.nb) a.bpart[(long long)slot * a.nb + lane] = bacc;
+        if (bm) body_row(owner, g, (double)qv, lane, bacc);
+      }
+      if (bm) {
+        const int slot = __shfl(slot_l, it, 64);  // whole wavefront active here
+        if (lane < a.nb) a.bpart[(long long)slot * a.nb + lane] = bacc;
       }
       v[0] = v[HC];
       v[1] = v[HC + 1];

@@ -80,15 +80,15 @@ struct Layout {
   __host__ __device__ int ntasks() const { return nstrip * nchunk; }
 };
 
-// Short tasks (4 rows) on small grids give each SIMD at least two wavefronts; larger
-// grids use 8-row tasks (less halo re-reading).
+// Tasks of 4 owned rows by default: consecutive tasks of a wavefront's segment share
+// their halo rows in registers, so taller tasks save little traffic and cost
+// registers (occupancy); hc_force = 8 selects 8-row tasks.
 inline Layout make_layout(int nx, int ny, int hc_force = 0) {
   Layout L;
   L.nx = nx;
   L.ny = ny;
   L.nstrip = (nx + 1 + SW - 1) / SW;
-  const long long t8 = (long long)L.nstrip * ((ny + 1 + 7) / 8);
-  L.hc = hc_force ? hc_force : (t8 < 4096 ? 4 : 8);
+  L.hc = hc_force == 8 ? 8 : 4;
   L.nchunk = (ny + 1 + L.hc - 1) / L.hc;
   L.P = (((L.nstrip - 1) * SW + 64) + 63) / 64 * 64;
   L.rows = L.hc * L.nchunk + 2;
@@ -112,6 +112,8 @@ struct DevState {
   double bb[MFP_MAX_BODIES];             // extra right-hand side of the body rows (adjoint)
   double rr0, rr_stop, rr_final, rr_true;
   double alpha, beta, pq;
+  double rr_prev;                        // one-kernel CG: |r|^2 before a restart (0: fresh)
+  double stop_rel;                       // one-kernel CG: threshold / start |r|^2 (0: use rr_stop)
   double copfi, Q;
   long long iters;                       // index of the final iterate once done != 0
   long long kmax;

@@ -9,11 +9,11 @@
 //   (A p)_free = (K p)_free and (A p)_b = sum over the nodes of body b of (K p)_n,
 // which is Algorithm 1's assembly of element results into r (interior nodes) and rb
 // (body DOFs), and p.Ap = sum_free p (Kp) + sum_b p_b (Ap)_b.
-// One CG iteration is two kernels:
+// A single solve runs one kernel per CG iteration (k_step, step.h).  The batched
+// solver runs two per iteration:
 //   k_apply<FUSED>  p = r + beta p_old (body nodes p_b), q = K p, partial p.q;
-//                   the last block finishes p.Ap, alpha and the body unknowns;
-//   k_update        x += alpha p, r -= alpha q, partial r.r; the last block finishes
-//                   r.r, beta, the convergence test and p_b = rb + beta p_b.
+//   k_update        alpha, x += alpha p, r -= alpha q, partial r.r;
+// each block of a kernel reduces the previous kernel's per-block partials itself.
 // Scalars never leave the device; the host polls a done flag every few iterations.
 #include <cmath>
 #include <cstring>
@@ -22,6 +22,7 @@
 
 #include "adjoint.h"
 #include "apply.h"
+#include "step.h"
 
 namespace mfp {
 
@@ -340,53 +341,6 @@ __global__ void __launch_bounds__(BLOCK) k_resid_finalize(const double* __restri
   }
 }
 
-// Inner (FP32) solve of A e = r for iterative refinement: r32 = r64 at every node
-// (zero away from free nodes), e = 0, previous direction 0, partials of r32.r32.
-__global__ void __launch_bounds__(BLOCK) k_inner_init(long long n, const double* __restrict__ r64,
-                                                      float* __restrict__ r32,
-                                                      float* __restrict__ e32,
-                                                      float* __restrict__ p32,
-                                                      double* __restrict__ part) {
-  __shared__ double s_red[BLOCK / 64];
-  double acc = 0.0;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
-    const float v = (float)r64[e];
-    r32[e] = v;
-    e32[e] = 0.f;
-    p32[e] = 0.f;
-    acc += (double)v * (double)v;
-  }
-  const double bs = block_sum(acc, s_red);
-  if (threadIdx.x == 0) part[blockIdx.x] = bs;
-}
-
-// Single block: inner CG state from the outer body residuals.
-__global__ void k_inner_finalize(const double* __restrict__ part, int G2, const DevState* outer,
-                                 DevState* in, int nb, double inner_rtol2, long long kmax) {
-  __shared__ double s_red[BLOCK / 64];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < G2; i += BLOCK) s += part[i];
-  s = block_sum(s, s_red);
-  if (threadIdx.x == 0) {
-    double rbr = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      const double v = outer->rb[0][b];
-      in->rb[0][b] = v;
-      in->xb[0][b] = 0.0;
-      in->pb[1][b] = 0.0;
-      rbr += v * v;
-    }
-    in->rb_rr[0] = rbr;
-    in->rr[1] = 1.0;
-    in->rr0 = s + rbr;
-    in->rr_stop = inner_rtol2 * (s + rbr);
-    in->iters = 0;
-    in->done = 0;
-    in->kmax = kmax;
-  }
-}
-
 // Reliable update of the mixed-precision solve: x64 += e32 (all nodes; only free
 // entries are ever read), e32 = 0, and the body corrections move from the inner
 // state (slot k&1) to the outer one.
@@ -401,37 +355,6 @@ __global__ void k_ir_update(long long n, double* __restrict__ x64, float* __rest
     const int b = threadIdx.x;
     outer->xb[outer->iters & 1][b] += in->xb[slot][b];
     in->xb[slot][b] = 0.0;
-  }
-}
-
-// After a reliable update: the FP32 residual restarts from the FP64 one (r32 = r64,
-// partials of r32.r32 for the next iteration's reduction) and the inner body
-// residuals of slot k&1 take the FP64 values; the direction is kept.
-__global__ void __launch_bounds__(BLOCK) k_reliable_reset(long long n, const double* __restrict__ r64,
-                                                          float* __restrict__ r32,
-                                                          double* __restrict__ part,
-                                                          const DevState* outer, DevState* in,
-                                                          int nb, int slot, double delta2) {
-  __shared__ double s_red[BLOCK / 64];
-  double acc = 0.0;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
-       e += (long long)gridDim.x * blockDim.x) {
-    const float v = (float)r64[e];
-    r32[e] = v;
-    acc += (double)v * (double)v;
-  }
-  const double bs = block_sum(acc, s_red);
-  if (threadIdx.x == 0) part[blockIdx.x] = bs;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    double rbr = 0.0;
-    for (int b = 0; b < nb; ++b) {
-      const double v = outer->rb[0][b];
-      in->rb[slot][b] = v;
-      rbr += v * v;
-    }
-    in->rb_rr[slot] = rbr;
-    in->rr_stop = delta2 * outer->rr_true;
-    in->done = 0;
   }
 }
 
@@ -556,12 +479,6 @@ __device__ __forceinline__ void update_core(const UpdArgs<T>& u, const int vblk,
   if (threadIdx.x == 0) u.part2[vblk] = bs;
 }
 
-template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_update(UpdArgs<T> u) {
-  __shared__ double s_red[BLOCK / 64];
-  __shared__ double s_qb[MFP_MAX_BODIES];
-  update_core<T>(u, blockIdx.x, gridDim.x, s_red, s_qb);
-}
 
 template <typename T>
 __global__ void __launch_bounds__(BLOCK) k_update_batch(const UpdArgs<T>* __restrict__ args,
@@ -700,26 +617,40 @@ __global__ void __launch_bounds__(BLOCK) k_samples(SampleArgs a) {
 // ---------------------------------------------------------------------------------
 constexpr int GMAX = 2048;  // max blocks of the reduction kernels
 
-// Wavefronts of k_apply<T, FUSED, hc> resident on the current device at once (0 when
-// the runtime cannot say).
-template <typename T, bool FUSED>
-static int apply_resident_waves(int hc) {
+// Wavefronts of the one-kernel CG iteration k_step<T, hc> resident on the current
+// device at once (0 when the runtime cannot say).
+template <typename T>
+static int step_resident_waves(int hc) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  const void* f = hc == 4 ? reinterpret_cast<const void*>(&k_apply<T, FUSED, 4>)
-                          : reinterpret_cast<const void*>(&k_apply<T, FUSED, 8>);
+  const void* f = hc == 4 ? reinterpret_cast<const void*>(&k_step<T, 4>)
+                          : reinterpret_cast<const void*>(&k_step<T, 8>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) != hipSuccess) return 0;
   return per_cu * cus * WAVES;
 }
 
-// Segments for a single solve: about as many as the solve loop's fused apply keeps
+// Blocks of the one-kernel iteration: as many as stay resident at once (so that no
+// second round of work-groups trails the first), at most one task per wavefront and at
+// most 1024 (the next launch reduces one partial per block); a multiple of 8.
+template <typename T>
+static int step_blocks(const Layout& L) {
+  const long long need = (((long long)L.ntasks() + WAVES - 1) / WAVES + 7) & ~7LL;
+  long long g = step_resident_waves<T>(L.hc) / WAVES;
+  g &= ~7LL;
+  if (g < 8) g = 8;
+  if (g > need) g = need;
+  if (g > 1024) g = 1024;
+  return (int)g;
+}
+
+// Segments for a single solve: about as many as the solve loop's kernel keeps
 // resident, less the per-strip slack of the segment bound, so that the whole list runs
 // in one round of wavefronts.
 static int single_target(const Layout& L, int precision) {
-  const int wres = precision == MFP_FP64 ? apply_resident_waves<double, true>(L.hc)
-                                         : apply_resident_waves<float, true>(L.hc);
+  const int wres = precision == MFP_FP64 ? step_resident_waves<double>(L.hc)
+                                         : step_resident_waves<float>(L.hc);
   if (wres <= 0) return L.ntasks();
   int t = wres - L.nstrip * (L.nchunk / 64 + 1);
   if (t < wres / 2) t = wres / 2;
@@ -756,7 +687,9 @@ struct SolveWs {
   SegPlan sp;     // apply work list and launch size
   int8_t* tag;
   double *dx, *dy, *g, *x, *r, *p0, *p1, *q;
+  double *r1, *q1;   // second residual / K p slots of the one-kernel iteration
   float *dxf, *dyf, *xf, *rf, *p0f, *p1f, *qf;
+  float *r1f, *q1f;
   uint8_t* tplain;
   unsigned long long* tbody;
   int* tslot;
@@ -766,6 +699,8 @@ struct SolveWs {
   double* part2;
   double* part3;  // batched refinement: partials of the FP64 residual
   double* bpart;
+  size_t bstride;   // per-slot body sums: parity slot 1 starts at bpart + bstride
+  double* spart;    // one-kernel iteration partials, 2 slots x 4 x GMAX
   DevState* st;
   DevState* st2;  // inner (FP32) solver state
   long long* nfree;
@@ -790,6 +725,8 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.p0 = bp.take<double>(n);
   w.p1 = bp.take<double>(n);
   w.q = bp.take<double>(n);
+  w.r1 = bp.take<double>(n);
+  w.q1 = bp.take<double>(n);
   if (precision != MFP_FP64) {
     w.dxf = bp.take<float>(n);
     w.dyf = bp.take<float>(n);
@@ -798,6 +735,8 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
     w.p0f = bp.take<float>(n);
     w.p1f = bp.take<float>(n);
     w.qf = bp.take<float>(n);
+    w.r1f = bp.take<float>(n);
+    w.q1f = bp.take<float>(n);
   }
   w.tplain = bp.take<uint8_t>(nt);
   w.tbody = bp.take<unsigned long long>(nt);
@@ -808,7 +747,9 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.part2 = bp.take<double>(GMAX);
   w.part3 = bp.take<double>(GMAX);
   // at least 64 slots: the body reductions read the first 64 before the slot count
-  w.bpart = bp.take<double>((size_t)(nt > 64 ? nt : 64) * (nb > 0 ? nb : 1));
+  w.bstride = (size_t)(nt > 64 ? nt : 64) * (nb > 0 ? nb : 1);
+  w.bpart = bp.take<double>(2 * w.bstride);
+  w.spart = bp.take<double>(2 * 4 * GMAX);
   w.st = bp.take<DevState>(1);
   w.st2 = bp.take<DevState>(1);
   w.nfree = bp.take<long long>(1);
@@ -905,8 +846,9 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   s.p1 = w.p1;
   s.q = w.q;
   s.nfree = w.nfree;
-  if (w.L.nstrip > SEG_MAX_STRIPS || w.L.nchunk > 0xffff) {
-    set_error("grid too large for the apply work list (nx <= %d, ny <= %d)",
+  if (w.L.nstrip > SEG_MAX_STRIPS || w.L.nchunk > 0xffff ||
+      (unsigned long long)w.L.n * sizeof(double) >= (1ull << 32)) {
+    set_error("grid too large (nx <= %d, ny <= %d, padded nodes < 2^29)",
               SEG_MAX_STRIPS * SW - 1, 0xffff * 4 - 1);
     return MFP_E_ARG;
   }
@@ -915,9 +857,10 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   if (precision != MFP_FP64) {
     // every padded entry of the FP32 vectors starts at zero (the apply writes owned
     // nodes only)
-    for (float* f : {w.xf, w.rf, w.p0f, w.p1f, w.qf})
+    for (float* f : {w.xf, w.rf, w.p0f, w.p1f, w.qf, w.r1f, w.q1f})
       MFP_TRY_HIP(hipMemsetAsync(f, 0, sizeof(float) * w.L.n, st));
   }
+  for (double* d : {w.r1, w.q1}) MFP_TRY_HIP(hipMemsetAsync(d, 0, sizeof(double) * w.L.n, st));
   MFP_TRY_HIP(hipMemsetAsync(w.nfree, 0, sizeof(long long), st));
   k_setup<<<grid_blocks(w.L.n), BLOCK, 0, st>>>(s);
   MFP_TRY_HIP(hipGetLastError());
@@ -1016,86 +959,110 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
   return MFP_OK;
 }
 
-template <typename T>
-struct CgBufs {
-  T* x;
-  T* r;
-  T* p0;
-  T* p1;
-  T* q;
-  const T* dx;
-  const T* dy;
-  DevState* st;
-};
-
 struct CgCount {
-  long long iters = 0;     // iterations of the last run
-  long long applies = 0;   // applies over all runs
-  double tsum = 0.0;       // sampled apply durations (ms)
+  long long iters = 0;     // index of the launch that stopped the last run
+  long long applies = 0;   // operator applications over all runs
+  double tsum = 0.0;       // sampled kernel durations (ms)
   long long tcnt = 0;
 };
 
-// Host loop of CG on the prepared state (residual, direction 0, scalars): kernels are
-// enqueued in batches of `check_every` iterations; once the device sets its done flag
-// the remaining launches of the batch return immediately.  Returns the done code (1
-// converged, 2 breakdown, 3 kmax) or a negative status.
+// Arguments of the one-kernel iteration over one set of vectors (FP64: w.r/r1, p0/p1,
+// q/q1, x; FP32: the float copies and the correction e in xf).
 template <typename T>
-static int cg_run(const mfp_grid& g, int nb, const SolveWs& w, const CgBufs<T>& B,
-                  const mfp_solver_opts& o, hipStream_t st, CgCount* cnt, long long k0 = 0) {
-  const int G = w.sp.G;
+static StepArgs<T> make_step_args(const SolveWs& w, const mfp_grid& g, int nb, const T* dx,
+                                  const T* dy, T* r0, T* r1, T* p0, T* p1, T* q0, T* q1,
+                                  T* x, DevState* st) {
+  StepArgs<T> a{};
+  a.P = w.L.P;
+  a.nstrip = w.L.nstrip;
+  a.nchunk = w.L.nchunk;
+  a.tplain = w.tplain;
+  a.tag = w.tag;
+  a.dx = dx;
+  a.dy = dy;
+  a.tbody = w.tbody;
+  a.tslot = w.tslot;
+  a.nslots = w.nslots;
+  a.r[0] = r0;
+  a.r[1] = r1;
+  a.p[0] = p0;
+  a.p[1] = p1;
+  a.q[0] = q0;
+  a.q[1] = q1;
+  a.x = x;
+  a.part[0] = w.spart;
+  a.part[1] = w.spart + 4 * GMAX;
+  a.bpart[0] = w.bpart;
+  a.bpart[1] = w.bpart + w.bstride;
+  a.st = st;
+  a.nb = nb;
+  const double hx = grid_hx(g), hy = grid_hy(g);
+  const double rr = hy / hx, qq = hx / hy;
+  a.cC = (T)(4.0 / 3.0 * (rr + qq));
+  a.cE = (T)(-2.0 / 3.0 * rr + qq / 3.0);
+  a.cN = (T)(-2.0 / 3.0 * qq + rr / 3.0);
+  a.cD = (T)(-(rr + qq) / 6.0);
+  a.ry = (T)rr;
+  return a;
+}
+
+// Start of a run at launch k0 (state of slot (k0-1)&1): the residual slot takes the
+// FP64 residual w.r (converted for FP32) with its partials, the body state comes from
+// the outer (FP64) state.  fresh: no previous direction; correction: the iterate is a
+// correction that starts at zero (inner FP32 solve); stop_rel > 0: threshold relative
+// to the start residual; kmax_abs: last launch index.
+template <typename T>
+static int step_start(const SolveWs& w, int nb, const StepArgs<T>& a, long long k0, bool fresh,
+                      bool correction, double stop_rel, long long kmax_abs, hipStream_t st,
+                      int* npart0) {
+  const int slot = (int)((k0 + 1) & 1);
   const int G2 = loop_blocks(w.L.n);
-  T* pbuf[2] = {B.p0, B.p1};
+  k_step_start<T><<<G2, BLOCK, 0, st>>>(w.L.n, w.r, a.r[slot], a.part[slot]);
+  k_step_bodies<<<1, 64, 0, st>>>(w.st, a.st, nb, slot, fresh ? 1 : 0, correction ? 1 : 0,
+                                  stop_rel, kmax_abs);
+  MFP_TRY_HIP(hipGetLastError());
+  *npart0 = G2;
+  return MFP_OK;
+}
+
+// Host loop of the one-kernel CG from launch k0: launches are enqueued in batches of
+// `check_every`; once the device has recorded an outcome the remaining launches of
+// the batch return immediately.  Afterwards the iterate takes the stopping launch's
+// alpha p.  Returns the done code (1 converged, 2 breakdown, 3 kmax) or a negative
+// status; cnt->iters is the stopping launch.
+template <typename T>
+static int step_run(const SolveWs& w, StepArgs<T> a, const mfp_solver_opts& o, hipStream_t st,
+                    CgCount* cnt, long long k0) {
+  const int G = step_blocks<T>(w.L);
   const int every = o.check_every > 0 ? o.check_every : 50;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
   const int nev = prof ? (every + prof - 1) / prof : 0;
   hipEvent_t ev[2 * 64];
   const int nev_c = nev > 64 ? 64 : nev;
   for (int i = 0; i < 2 * nev_c; ++i) MFP_TRY_HIP(hipEventCreate(&ev[i]));
-  long long k = k0;
+  long long j = k0;
   struct {
     int done;
     long long iters;
   } hs{0, 0};
-  ApplyArgs<T> a = make_apply_args<T>(w, g, nb, B.dx, B.dy);
-  a.r = B.r;
-  a.q = B.q;
-  a.part2 = w.part2;
-  a.G2 = G2;
-  a.st = B.st;
+  a.k0 = k0;
   int status = MFP_OK;
   while (true) {
     int used = 0;
-    for (int m = 0; m < every; ++m, ++k) {
-      a.src = pbuf[k & 1];
-      a.pnew = pbuf[(k + 1) & 1];
-      a.k = k;
+    for (int m = 0; m < every; ++m, ++j) {
+      a.j = j;
       const bool timed = prof && (m % prof == 0) && used < nev_c;
       if (timed) {
-        launch_apply<T, true>(w.L.hc, G, st, a, ev[2 * used], ev[2 * used + 1]);
+        launch_step<T>(w.L.hc, G, st, a, ev[2 * used], ev[2 * used + 1]);
         ++used;
       } else {
-        launch_apply<T, true>(w.L.hc, G, st, a);
+        launch_step<T>(w.L.hc, G, st, a);
       }
-      UpdArgs<T> u{};
-      u.n = w.L.n;
-      u.x = B.x;
-      u.p = pbuf[(k + 1) & 1];
-      u.r = B.r;
-      u.q = B.q;
-      u.part = w.part;
-      u.G = G;
-      u.bpart = w.bpart;
-      u.nslots = w.nslots;
-      u.part2 = w.part2;
-      u.st = B.st;
-      u.nb = nb;
-      u.k = k;
-      k_update<T><<<G2, BLOCK, 0, st>>>(u);
     }
     hipError_t le = hipGetLastError();
-    if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &B.st->done, sizeof(int),
+    if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &a.st->done, sizeof(int),
                                               hipMemcpyDeviceToHost, st);
-    if (le == hipSuccess) le = hipMemcpyAsync(&hs.iters, &B.st->iters, sizeof(long long),
+    if (le == hipSuccess) le = hipMemcpyAsync(&hs.iters, &a.st->iters, sizeof(long long),
                                               hipMemcpyDeviceToHost, st);
     if (le == hipSuccess) le = hipStreamSynchronize(st);
     if (le != hipSuccess) {
@@ -1103,8 +1070,8 @@ static int cg_run(const mfp_grid& g, int nb, const SolveWs& w, const CgBufs<T>& 
       status = MFP_E_HIP;
       break;
     }
-    // only launches that did work count (launches after convergence return at once)
-    const long long first = k - every;
+    // only launches that did work count (launches after the outcome return at once)
+    const long long first = j - every;
     for (int i = 0; i < used; ++i) {
       const long long it = first + (long long)i * prof;
       if (hs.done && it >= hs.iters) break;
@@ -1118,6 +1085,8 @@ static int cg_run(const mfp_grid& g, int nb, const SolveWs& w, const CgBufs<T>& 
   }
   for (int i = 0; i < 2 * nev_c; ++i) (void)hipEventDestroy(ev[i]);
   if (status != MFP_OK) return status;
+  k_finish<T><<<loop_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, a.x, a.p[(hs.iters + 1) & 1], a.st);
+  MFP_TRY_HIP(hipGetLastError());
   cnt->iters = hs.iters;
   cnt->applies += hs.iters - k0;
   return hs.done;
@@ -1151,12 +1120,23 @@ static int read_rr(const SolveWs& w, hipStream_t st, double* rr, double* rr0) {
   return MFP_OK;
 }
 
+// FP64 CG from the state that residual64 (mode 0) prepared: one run from launch 1.
+static int solve64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver_opts& o,
+                   hipStream_t st, CgCount* cnt, long long kmax = 0) {
+  StepArgs<double> a = make_step_args<double>(w, g, nb, w.dx, w.dy, w.r, w.r1, w.p0, w.p1,
+                                              w.q, w.q1, w.x, w.st);
+  const long long km = kmax > 0 ? kmax : o.kmax;
+  MFP_TRY(step_start<double>(w, nb, a, 1, true, false, 0.0, 1 + km, st, &a.npart0));
+  return step_run<double>(w, a, o, st, cnt, 1);
+}
+
 // Mixed precision.  FP32 CG (FP32 vectors and element apply, FP64 scalars and body
 // sums) on the correction e, started from r32 = r64 = b - A x.  Each time the FP32
 // residual norm has dropped by `delta` since the last FP64 residual, x += e in FP64,
-// e = 0, the residual is recomputed with the FP64 apply and copied into r32, and the
-// CG iteration continues with its current direction.  MFP_FP32 runs one segment to
-// rtol and reports the FP64 residual.  Returns the final done code.
+// e = 0, the residual is recomputed with the FP64 apply and replaces r32, and the
+// iteration restarts with its current direction (beta from the new residual).
+// MFP_FP32 runs one run to rtol and reports the FP64 residual.  Returns the final done
+// code (0: FP32 stagnation, continue in FP64).
 static long long k0_cap(long long k) { return 2 * k > 2000 ? 2 * k : 2000; }
 
 static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver_opts& o,
@@ -1169,25 +1149,25 @@ static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_so
   double rr = 0, rr0 = 0;
   MFP_TRY(read_rr(w, st, &rr, &rr0));
   if (rr <= o.rtol * o.rtol * rr0) return 1;
-  k_inner_init<<<G2, BLOCK, 0, st>>>(w.L.n, w.r, w.rf, w.xf, w.p0f, w.part2);
-  k_inner_finalize<<<1, BLOCK, 0, st>>>(w.part2, G2, w.st, w.st2, nb, delta * delta, o.kmax);
-  MFP_TRY_HIP(hipGetLastError());
-  CgBufs<float> B{w.xf, w.rf, w.p0f, w.p1f, w.qf, w.dxf, w.dyf, w.st2};
-  long long k = 0;
+  MFP_TRY_HIP(hipMemsetAsync(w.xf, 0, sizeof(float) * w.L.n, st));
+  StepArgs<float> a = make_step_args<float>(w, g, nb, w.dxf, w.dyf, w.rf, w.r1f, w.p0f, w.p1f,
+                                            w.qf, w.q1f, w.xf, w.st2);
+  long long k0 = 1;
+  bool fresh = true;
   int code = 0;
   while (true) {
-    // a segment may take at most max(2000, 2 x all iterations so far); one that does
-    // not reach its reduction within that is taken as FP32 stagnation
-    long long cap = ir ? k0_cap(k) : o.kmax;
-    long long kseg = k + cap < o.kmax ? k + cap : o.kmax;
-    MFP_TRY_HIP(hipMemcpyAsync(&w.st2->kmax, &kseg, sizeof(long long), hipMemcpyHostToDevice, st));
-    MFP_TRY_HIP(hipStreamSynchronize(st));
-    code = cg_run<float>(g, nb, w, B, o, st, cnt, k);
+    // a run may take at most max(2000, 2 x all iterations so far); one that does not
+    // reach its reduction within that is taken as FP32 stagnation
+    const long long cap = ir ? k0_cap(k0 - 1) : o.kmax;
+    long long kabs = k0 + cap;
+    if (kabs > 1 + o.kmax) kabs = 1 + o.kmax;
+    MFP_TRY(step_start<float>(w, nb, a, k0, fresh, true, delta * delta, kabs, st, &a.npart0));
+    code = step_run<float>(w, a, o, st, cnt, k0);
     if (code < 0) return code;
-    const long long K = cnt->iters;
-    *total_iters = K;
+    const long long J = cnt->iters;
+    *total_iters = J - 1;
     // fold the correction into the FP64 iterate and recompute the true residual
-    k_ir_update<<<G2, BLOCK, 0, st>>>(w.L.n, w.x, w.xf, w.st, w.st2, nb, (int)(K & 1));
+    k_ir_update<<<G2, BLOCK, 0, st>>>(w.L.n, w.x, w.xf, w.st, w.st2, nb, (int)(J & 1));
     MFP_TRY_HIP(hipGetLastError());
     MFP_TRY(residual64(g, nb, w, st, 2, o.rtol));
     cnt->applies += 1;
@@ -1195,15 +1175,13 @@ static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_so
     MFP_TRY(read_rr(w, st, &rr, &rr0));
     if (rr <= o.rtol * o.rtol * rr0) return 1;
     if (!ir) return code == 2 ? 2 : 3;
-    if (code == 3 && K >= o.kmax) return 3;
+    if (code == 3 && J - 1 >= o.kmax) return 3;
     if (code != 1 || *updates >= max_upd) {
       *stagnated = true;
       return 0;
     }
-    k_reliable_reset<<<G2, BLOCK, 0, st>>>(w.L.n, w.r, w.rf, w.part2, w.st, w.st2, nb,
-                                           (int)(K & 1), delta * delta);
-    MFP_TRY_HIP(hipGetLastError());
-    k = K;
+    fresh = false;
+    k0 = J;
   }
 }
 
@@ -1321,10 +1299,9 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
   MFP_TRY(residual64(g, nb, w, st, 0, opts->rtol));
   cnt.applies += 1;
   if (opts->precision == MFP_FP64) {
-    CgBufs<double> B{w.x, w.r, w.p0, w.p1, w.q, w.dx, w.dy, w.st};
-    done = cg_run<double>(g, nb, w, B, *opts, st, &cnt);
+    done = solve64(g, nb, w, *opts, st, &cnt);
     if (done < 0) return done;
-    total_iters = cnt.iters;
+    total_iters = cnt.iters - 1;
   } else {
     double rr = 0, rr0 = 0;
     done = solve_mixed(g, nb, w, *opts, st, &cnt, &total_iters, &outer, &stagnated);
@@ -1337,12 +1314,9 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
       cnt.applies += 1;
       long long left = opts->kmax - total_iters;
       if (left < 1) left = 1;
-      MFP_TRY_HIP(hipMemcpyAsync(&w.st->kmax, &left, sizeof(long long), hipMemcpyHostToDevice, st));
-      MFP_TRY_HIP(hipStreamSynchronize(st));
-      CgBufs<double> B{w.x, w.r, w.p0, w.p1, w.q, w.dx, w.dy, w.st};
-      done = cg_run<double>(g, nb, w, B, *opts, st, &cnt);
+      done = solve64(g, nb, w, *opts, st, &cnt, left);
       if (done < 0) return done;
-      total_iters += cnt.iters;
+      total_iters += cnt.iters - 1;
     }
   }
   MFP_TRY_HIP(hipEventRecord(e1, st));

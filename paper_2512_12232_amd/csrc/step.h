@@ -1,0 +1,395 @@
+// One conjugate-gradient iteration per kernel launch.
+//
+// The paper's Algorithm 1 runs the textbook CG loop: apply the operator to the
+// direction, alpha, update of the iterate and the residual, beta, new direction.  Done
+// as written that needs two grid-wide reductions per iteration (p.Ap before alpha,
+// r.r before beta), i.e. two kernels.  Here launch j does both halves for iteration j
+// with the same recurrences:
+//
+//   alpha_{j-1} = |r_{j-1}|^2 / p_{j-1}.Kp_{j-1}           (partials of launch j-1)
+//   x_j = x_{j-1} + alpha p_{j-1},   r_j = r_{j-1} - alpha Kp_{j-1}
+//   |r_j|^2 = |r_{j-1}|^2 - 2 alpha r_{j-1}.Kp_{j-1} + alpha^2 Kp_{j-1}.Kp_{j-1}
+//   beta_j = |r_j|^2 / |r_{j-1}|^2,  p_j = r_j + beta_j p_{j-1},  Kp_j
+//
+// with per-block partials of r_j.r_j, p_j.Kp_j, r_j.Kp_j and Kp_j.Kp_j for launch j+1.
+// Only |r_j|^2 inside beta_j (and the stopping test) comes from the expansion, over the
+// free nodes; alpha always uses the sum of the squares of the stored residual of the
+// previous launch, so the expansion's rounding never accumulates.  Body unknowns
+// (one per body, the multi-point constraint rows) follow the same recurrences as
+// scalars, their K p entries being the per-body sums of K p over the body's nodes.
+//
+// Every block needs r_j, p_j at the halo of its tasks, so it recomputes them there
+// from r_{j-1}, Kp_{j-1}, p_{j-1} (the same arithmetic as the owner); r, p and Kp are
+// therefore double-buffered by parity (launch j reads slot (j-1)&1 and writes j&1),
+// as are the partials and the per-body slot sums.  The iterate is read and written
+// at owned nodes only.
+//
+// Launch k0 starts (or restarts) a run: alpha = 0, |r_j|^2 is the exact sum of the
+// start residual (partials written by k_step_start), beta_j = |r_j|^2 / rr_prev with
+// rr_prev = 0 for a fresh start (direction p_{j-1} = 0) or, after a residual
+// replacement, the exact |r_{j-1}|^2 kept by the launch that stopped.
+//
+// A launch that finds |r_j|^2 <= the threshold, j >= kmax, a breakdown or a non-finite
+// value records the outcome (iterate index j, alpha) and returns; k_finish then adds
+// alpha p_{j-1} to the iterate.
+#pragma once
+
+#include "apply.h"
+
+namespace mfp {
+
+// Element at a 32-bit byte offset from a uniform base pointer (lets the compiler use
+// scalar-base + 32-bit vector-offset addressing; the solver's vectors are < 4 GiB).
+template <typename T>
+__device__ __forceinline__ T ld_at(const T* base, unsigned boff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ void st_at(T* base, unsigned boff, T v) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
+template <typename T>
+struct StepArgs {
+  int P, nstrip, nchunk;         // pitch, strips, chunks (task t = chunk * nstrip + strip)
+  const uint8_t* tplain;         // per task, 1: constant-stencil task
+  const int8_t* tag;
+  const T* dx;                   // displacement / hx
+  const T* dy;
+  const unsigned long long* tbody;
+  const int* tslot;
+  const int* nslots;
+  T* r[2];                       // residual, slot = iteration parity
+  T* p[2];                       // direction
+  T* q[2];                       // K p
+  T* x;                          // iterate (free nodes meaningful)
+  double* part[2];               // per-block partials: r.r, p.Kp, r.Kp, Kp.Kp
+  double* bpart[2];              // per-slot, per-body sums of K p
+  DevState* st;
+  int nb;
+  int npart0;                    // partials (blocks) written by the start kernel
+  long long k0;                  // start launch of this run
+  long long j;                   // this launch
+  T cC, cE, cN, cD;              // constant stencil
+  T ry;                          // hy / hx
+};
+
+// Work distribution: the launch keeps all its wavefronts resident; wavefront w takes
+// tasks w, w + W, w + 2W, ... (W wavefronts, tasks in strip-fastest order), so that at
+// any time the wavefronts of the chip cover a few contiguous bands of rows and each
+// XCD one contiguous part of every band (its L2 serves the halo rows and columns that
+// neighbouring tasks share).  Every task's rows, iterate rows and flags are requested
+// one task ahead (a task that evaluates geometry requests its tags and displacements
+// first and the next task's data after its cell march, which needs the registers).
+template <typename T, int HC>
+__device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, double* s_pb,
+                                          double* s_qb) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int G = gridDim.x, vblk = blockIdx.x;
+  // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs)
+  const int vb = (vblk & 7) * (G >> 3) + (vblk >> 3);
+  const unsigned P = (unsigned)a.P;
+  const int nstrip = a.nstrip;
+  const int ntask = nstrip * a.nchunk;
+  const bool owner = lane >= 1 && lane <= SW;
+  const int W = G * WAVES;
+  const long long j = a.j;
+  const int cur = (int)(j & 1), prv = cur ^ 1;
+  const bool start = j == a.k0;
+  const T* __restrict__ rp = a.r[prv];
+  const T* __restrict__ qp = a.q[prv];
+  const T* __restrict__ pp = a.p[prv];
+  T* __restrict__ rc = a.r[cur];
+  T* __restrict__ qc = a.q[cur];
+  T* __restrict__ pc = a.p[cur];
+  constexpr unsigned TS = sizeof(T);
+  const unsigned RB = P * TS;  // bytes per padded row of a T vector
+  // task t: rows 0..HC+1 are padded rows chunk*HC + r, lane is column strip*SW + lane
+  auto node0 = [&](int t) -> unsigned {
+    const int m = t % nstrip, kc = t / nstrip;
+    return (unsigned)(kc * HC) * P + (unsigned)(m * SW + lane);
+  };
+
+  // next task's data (requested one task ahead)
+  T nr[HC + 2], nq[HC + 2], np[HC + 2], nx[HC];
+  int n_plain = 1, n_body = 0, n_slot = -1;
+  auto fetch = [&](int t) {
+    const unsigned bo = node0(t) * TS;
+#pragma unroll
+    for (int r = 0; r < HC + 2; ++r) {
+      nr[r] = ld_at(rp, bo + r * RB);
+      nq[r] = ld_at(qp, bo + r * RB);
+      np[r] = ld_at(pp, bo + r * RB);
+    }
+#pragma unroll
+    for (int r = 0; r < HC; ++r) nx[r] = ld_at(a.x, bo + (r + 1) * RB);
+    n_plain = a.tplain[t];
+    n_body = a.tbody[t] != 0ull;
+    n_slot = a.tslot[t];
+  };
+  int t = vb * WAVES + wv;
+  if (t < ntask) fetch(t);
+
+  // ---- scalars of iteration j ----
+  DevState* st = a.st;
+  const int nb = a.nb;
+  const int done = st->done;
+  const double rr_stop = st->rr_stop, rr_prev_start = st->rr_prev, stop_rel = st->stop_rel;
+  const long long kmax = st->kmax;
+  double rbp = 0.0, pbp = 0.0, xbp = 0.0;  // lane b: body b of iteration j-1
+  if (lane < nb) {
+    rbp = st->rb[prv][lane];
+    pbp = st->pb[prv][lane];
+    xbp = st->xb[prv][lane];
+  }
+  const int npart = start ? a.npart0 : G;
+  const double* __restrict__ pt = a.part[prv];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+  for (int i = tid; i < npart; i += BLOCK) {
+    s0 += pt[4 * i];
+    s1 += pt[4 * i + 1];
+    s2 += pt[4 * i + 2];
+    s3 += pt[4 * i + 3];
+  }
+  body_sums(a.bpart[prv], a.nslots, nb, s_qb);
+  if (done) return;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+    s2 += __shfl_xor(s2, off, 64);
+    s3 += __shfl_xor(s3, off, 64);
+  }
+  if (lane == 0) {
+    s_red[4 * wv] = s0;
+    s_red[4 * wv + 1] = s1;
+    s_red[4 * wv + 2] = s2;
+    s_red[4 * wv + 3] = s3;
+  }
+  __syncthreads();
+  const double S_rr = (s_red[0] + s_red[4]) + (s_red[8] + s_red[12]);
+  const double S_pq = (s_red[1] + s_red[5]) + (s_red[9] + s_red[13]);
+  const double S_rq = (s_red[2] + s_red[6]) + (s_red[10] + s_red[14]);
+  const double S_qq = (s_red[3] + s_red[7]) + (s_red[11] + s_red[15]);
+  const double qb = (lane < nb && !start) ? s_qb[lane] : 0.0;
+  double alpha = 0.0, rr_prev, rr_j;
+  int code = 0;
+  if (start) {
+    rr_prev = rr_prev_start;
+  } else {
+    rr_prev = S_rr + wave_sum(rbp * rbp);
+    const double pq = S_pq + wave_sum(pbp * qb);
+    if (!(pq > 0.0) || !isfinite(pq)) code = 2;
+    alpha = code ? 0.0 : rr_prev / pq;
+  }
+  const double rbj = rbp - alpha * qb;
+  const double xbj = xbp + alpha * pbp;
+  const double b_rr = wave_sum(rbj * rbj);
+  if (start)
+    rr_j = S_rr + b_rr;
+  else
+    rr_j = (S_rr - 2.0 * alpha * S_rq + alpha * alpha * S_qq) + b_rr;
+  const double stop = (start && stop_rel > 0.0) ? stop_rel * rr_j : rr_stop;
+  if (!code) {
+    if (!isfinite(rr_j))
+      code = 2;
+    else if (rr_j <= stop)
+      code = 1;
+    else if (j >= kmax)
+      code = 3;
+  }
+  const double beta = rr_prev > 0.0 ? rr_j / rr_prev : 0.0;
+  const double pbj = rbj + beta * pbp;
+  if (vblk == 0 && wv == 0) {
+    if (lane < nb) {
+      st->rb[cur][lane] = rbj;
+      st->xb[cur][lane] = xbj;
+      if (!code) st->pb[cur][lane] = pbj;
+    }
+    if (lane == 0) {
+      st->alpha = alpha;
+      st->rr[cur] = rr_j;
+      if (start && stop_rel > 0.0) st->rr_stop = stop;
+      if (code) {
+        st->done = code;
+        st->iters = j;
+        st->rr_final = rr_j;
+        st->rr_prev = rr_prev;
+      } else {
+        st->beta = beta;
+      }
+    }
+  }
+  if (code) return;
+  if (wv == 0 && lane < nb) s_pb[lane] = pbj;
+  __syncthreads();
+  const T al = (T)alpha, be = (T)beta;
+
+  // ---- tasks ----
+  double prr = 0.0, ppq = 0.0, prq = 0.0, pqq = 0.0;
+  int8_t tg[HC + 2];
+  T ddx[HC + 2], ddy[HC + 2];
+  for (; t < ntask; t += W) {
+    const unsigned n0 = node0(t);
+    const unsigned bo = n0 * TS;
+    const bool plain = n_plain != 0;
+    const bool bm = !plain && n_body != 0;
+    const int slot = n_slot;
+    // r_j, p_j (as at a free node until corrected) and p_{j-1} at rows 0..HC+1
+    T rj[HC + 2], v[HC + 2], po[HC + 2], xo[HC];
+#pragma unroll
+    for (int r = 0; r < HC + 2; ++r) {
+      rj[r] = nr[r] - al * nq[r];
+      v[r] = rj[r] + be * np[r];
+      po[r] = np[r];
+    }
+#pragma unroll
+    for (int r = 0; r < HC; ++r) xo[r] = nx[r];
+    if (!plain) {
+#pragma unroll
+      for (int r = 0; r < HC + 2; ++r) {
+        tg[r] = ld_at(a.tag, n0 + r * P);
+        ddx[r] = ld_at(a.dx, bo + r * RB);
+        ddy[r] = ld_at(a.dy, bo + r * RB);
+      }
+    }
+    T qr[HC];
+    if (plain) {
+      if (t + W < ntask) fetch(t + W);
+      stencil_task<T, HC>(a.cC, a.cE, a.cN, a.cD, v, qr);
+    } else {
+      // body nodes carry p_b, Dirichlet and halo nodes 0; r is zero there
+#pragma unroll
+      for (int r = 0; r < HC + 2; ++r) {
+        const int8_t g = tg[r];
+        if (g >= TAG_BODY0)
+          v[r] = (T)s_pb[g - TAG_BODY0];
+        else if (g != TAG_FREE)
+          v[r] = (T)0;
+      }
+      march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
+      // requested after the cell march, which needs the registers
+      if (t + W < ntask) fetch(t + W);
+    }
+    double bacc = 0.0;
+#pragma unroll
+    for (int r = 1; r <= HC; ++r) {
+      const unsigned go = bo + r * RB;
+      const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
+      const T qv = (g == TAG_FREE) ? qr[r - 1] : (T)0;
+      if (owner) {
+        st_at(rc, go, rj[r]);
+        st_at(pc, go, v[r]);
+        st_at(qc, go, qv);
+        st_at(a.x, go, xo[r - 1] + al * po[r]);
+        if (g == TAG_FREE) {
+          const double rd = (double)rj[r], qd = (double)qv;
+          prr += rd * rd;
+          ppq += (double)v[r] * qd;
+          prq += rd * qd;
+          pqq += qd * qd;
+        }
+      }
+      if (bm) body_row(owner, g, (double)qr[r - 1], lane, bacc);
+    }
+    if (bm && lane < nb) a.bpart[cur][(long long)slot * nb + lane] = bacc;
+  }
+  // four block sums, fixed order
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    prr += __shfl_xor(prr, off, 64);
+    ppq += __shfl_xor(ppq, off, 64);
+    prq += __shfl_xor(prq, off, 64);
+    pqq += __shfl_xor(pqq, off, 64);
+  }
+  __syncthreads();  // s_red was read above by every thread
+  if (lane == 0) {
+    s_red[4 * wv] = prr;
+    s_red[4 * wv + 1] = ppq;
+    s_red[4 * wv + 2] = prq;
+    s_red[4 * wv + 3] = pqq;
+  }
+  __syncthreads();
+  if (tid < 4) {
+    a.part[cur][4 * vblk + tid] =
+        (s_red[tid] + s_red[4 + tid]) + (s_red[8 + tid] + s_red[12 + tid]);
+  }
+}
+
+template <typename T, int HC>
+__global__ void __launch_bounds__(BLOCK) k_step(StepArgs<T> a) {
+  __shared__ double s_red[4 * WAVES];
+  __shared__ double s_pb[MFP_MAX_BODIES];
+  __shared__ double s_qb[MFP_MAX_BODIES];
+  step_core<T, HC>(a, s_red, s_pb, s_qb);
+}
+
+template <typename T>
+inline void launch_step(int hc, int G, hipStream_t st, const StepArgs<T>& a,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (e0) {
+    if (hc == 4)
+      hipExtLaunchKernelGGL(k_step<T, 4>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+    else
+      hipExtLaunchKernelGGL(k_step<T, 8>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+    return;
+  }
+  if (hc == 4)
+    k_step<T, 4><<<G, BLOCK, 0, st>>>(a);
+  else
+    k_step<T, 8><<<G, BLOCK, 0, st>>>(a);
+}
+
+// Start (or restart after a residual replacement) of a run at launch k0: the
+// residual slot (k0-1)&1 takes r (converted from the FP64 residual when they
+// differ), and its per-block partials are (r.r, 0, 0, 0) in the step layout.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_step_start(long long n, const double* __restrict__ r64,
+                                                      T* __restrict__ rdst,
+                                                      double* __restrict__ part) {
+  __shared__ double s_red[BLOCK / 64];
+  double acc = 0.0;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const T v = (T)r64[e];
+    if ((const void*)rdst != (const void*)r64) rdst[e] = v;
+    acc += (double)v * (double)v;
+  }
+  const double bs = block_sum(acc, s_red);
+  if (threadIdx.x < 4) part[4 * blockIdx.x + threadIdx.x] = threadIdx.x == 0 ? bs : 0.0;
+}
+
+// Single block: body state of slot `slot` for a run start.  rb = the FP64 body
+// residuals of the outer state (slot 0), xb = 0 when the iterate is a correction
+// (inner solve) or kept otherwise; p_b = 0 and rr_prev = 0 for a fresh start, kept
+// for a restart; stop_rel > 0 sets the threshold relative to the start residual.
+__global__ void k_step_bodies(const DevState* outer, DevState* in, int nb, int slot,
+                              int fresh, int correction, double stop_rel, long long kmax) {
+  const int b = threadIdx.x;
+  if (b < nb) {
+    in->rb[slot][b] = outer->rb[0][b];
+    if (correction) in->xb[slot][b] = 0.0;
+    else if (in != outer) in->xb[slot][b] = outer->xb[0][b];
+    if (fresh) in->pb[slot][b] = 0.0;
+  }
+  if (b == 0) {
+    if (fresh) in->rr_prev = 0.0;
+    in->stop_rel = stop_rel;
+    in->kmax = kmax;
+    in->done = 0;
+  }
+}
+
+// x += alpha p_{j-1} for the launch j that stopped (alpha recorded by it).
+template <typename T>
+__global__ void k_finish(long long n, T* __restrict__ x, const T* __restrict__ p,
+                         const DevState* __restrict__ st) {
+  const T al = (T)st->alpha;
+  if (al == (T)0) return;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    x[e] += al * p[e];
+}
+
+}  // namespace mfp
