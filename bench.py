@@ -11,8 +11,9 @@ U = 1, psi = U y on inlet/bottom/top, natural outlet.
 
 Prints ONE JSON line.  value = sum over timed steps of N_dof x CG iterations,
 divided by the wall time of those steps (inputs resident on the GPU).  The
-roofline entry is for the dominant kernel, the fused direction-update + element
-apply, timed with HIP events inside the timed steps on the solver's stream.
+roofline entry is for the dominant kernel, the one-kernel CG iteration (element
+apply fused with the vector updates and dot products), timed with HIP events
+inside the timed steps on the solver's stream.
 The CPU baseline is the oracle's plain CG on its assembled sparse matrix, timed
 on a bounded number of iterations on this host.
 """
@@ -32,28 +33,27 @@ METRIC = "CG DOF·iter/s + matvec HBM GB/s (% peak); adjoint/forward time; err v
 HBM_PEAK_GBS = 8000.0
 
 
-def apply_bytes(case, disp, body):
-    """Algorithmic bytes of one fused apply launch: every node reads r and the old
-    direction and writes the new direction and K p (4 x 8 B); every node with a
-    non-zero displacement also reads it (2 x 8 B); every node that is not a free
-    fluid node is identified by its one-byte tag."""
-    import torch
+def step_bytes(case, disp, body):
+    """Algorithmic bytes of one launch of the one-kernel CG iteration: every node reads
+    the previous residual, direction, K p and iterate (4 x 8 B) and writes the new ones
+    (4 x 8 B); every node with a non-zero displacement also reads it (2 x 8 B); every
+    node that is not a free fluid node is identified by its one-byte tag."""
     n = case.grid.nodes
     d = disp.view(2, n)
     moved = int(((d[0] != 0) | (d[1] != 0)).sum().item())
     nx, ny = case.grid.nx, case.grid.ny
     boundary = 2 * (nx + 1) + 2 * (ny - 1)
     bodies = int((body >= 0).sum().item())
-    return 32 * n + 16 * moved + (boundary + bodies), moved
+    return 64 * n + 16 * moved + (boundary + bodies), moved
 
 
-COUNTERS = os.path.join(ROOT, "profiles", "k_apply_fused_fp64_five_cyl_1024x512_counters.md")
+COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp64_five_cyl_1024x512_counters.md")
 
 
 def traffic_from_profile():
-    """HBM bytes per fused-apply launch from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE passes (scaled by the copy-kernel calibration), or None when the
-    apply or solver source has changed since those counters were taken."""
+    """HBM bytes per launch of the CG iteration kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE passes (scaled by the copy-kernel calibration), or None
+    when the kernel or solver source has changed since those counters were taken."""
     import hashlib
     try:
         text = open(COUNTERS).read()
@@ -62,7 +62,7 @@ def traffic_from_profile():
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line
                   and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "source_sha256_16"))
     h = hashlib.sha256()
-    for f in ("apply.h", "solve.hip"):
+    for f in ("apply.h", "step.h", "solve.hip"):
         with open(os.path.join(ROOT, "paper_2512_12232_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if fields.get("source_sha256_16", "").strip() != h.hexdigest()[:16]:
@@ -274,14 +274,14 @@ def main():
     dof_iters = sum(r.stats["n_dof"] * r.stats["iters"] for _, _, r in outs)
     value = dof_iters / wall
     apply_ms = [r.stats["apply_ms"] for _, _, r in outs if r.stats["apply_samples"] > 0]
-    nbytes, moved = apply_bytes(case, disp, body)
+    nbytes, moved = step_bytes(case, disp, body)
     roofline = None
     if apply_ms:
         ms = sum(apply_ms) / len(apply_ms)
         achieved = nbytes / (ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic_from_profile(), "kernel": "k_apply<double, fused>",
+                    "traffic": traffic_from_profile(), "kernel": "k_step<double, 4>",
                     "launch_ms": round(ms, 5), "bytes_per_launch": nbytes,
                     "samples": int(sum(r.stats["apply_samples"] for _, _, r in outs))}
     cpu = None

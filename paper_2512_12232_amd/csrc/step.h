@@ -48,6 +48,20 @@ template <typename T>
 __device__ __forceinline__ void st_at(T* base, unsigned boff, T v) {
   *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
 }
+// Store of the iteration's vectors; STREAM: not kept in L2 (non-temporal).  For
+// working sets larger than the memory-side cache the streaming form measured ~11%
+// faster per iteration (the stores no longer evict the halo rows that neighbouring
+// tasks re-read); for smaller ones the cached form is faster (the next iteration
+// finds the data in cache).  A compile-time choice: with a run-time branch the
+// compiler merges the two stores and drops the hint.
+template <bool STREAM, typename T>
+__device__ __forceinline__ void st_vec(T* base, unsigned boff, T v) {
+  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
+  if constexpr (STREAM)
+    __builtin_nontemporal_store(v, p);
+  else
+    *p = v;
+}
 
 template <typename T>
 struct StepArgs {
@@ -68,6 +82,7 @@ struct StepArgs {
   DevState* st;
   int nb;
   int npart0;                    // partials (blocks) written by the start kernel
+  int stream;                    // 1: launch the streaming-store instance
   long long k0;                  // start launch of this run
   long long j;                   // this launch
   T cC, cE, cN, cD;              // constant stencil
@@ -81,7 +96,7 @@ struct StepArgs {
 // neighbouring tasks share).  Every task's rows, iterate rows and flags are requested
 // one task ahead (a task that evaluates geometry requests its tags and displacements
 // first and the next task's data after its cell march, which needs the registers).
-template <typename T, int HC>
+template <typename T, int HC, bool STREAM>
 __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, double* s_pb,
                                           double* s_qb) {
   const int tid = threadIdx.x;
@@ -279,10 +294,10 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
       const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
       const T qv = (g == TAG_FREE) ? qr[r - 1] : (T)0;
       if (owner) {
-        st_at(rc, go, rj[r]);
-        st_at(pc, go, v[r]);
-        st_at(qc, go, qv);
-        st_at(a.x, go, xo[r - 1] + al * po[r]);
+        st_vec<STREAM>(rc, go, rj[r]);
+        st_vec<STREAM>(pc, go, v[r]);
+        st_vec<STREAM>(qc, go, qv);
+        st_vec<STREAM>(a.x, go, xo[r - 1] + al * po[r]);
         if (g == TAG_FREE) {
           const double rd = (double)rj[r], qd = (double)qv;
           prr += rd * rd;
@@ -317,28 +332,29 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   }
 }
 
-template <typename T, int HC>
+template <typename T, int HC, bool STREAM>
 __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<T> a) {
   __shared__ double s_red[4 * WAVES];
   __shared__ double s_pb[MFP_MAX_BODIES];
   __shared__ double s_qb[MFP_MAX_BODIES];
-  step_core<T, HC>(a, s_red, s_pb, s_qb);
+  step_core<T, HC, STREAM>(a, s_red, s_pb, s_qb);
 }
 
+// Tasks of 4 node rows (the layout of a single solve).
 template <typename T>
-inline void launch_step(int hc, int G, hipStream_t st, const StepArgs<T>& a,
-                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+inline void launch_step(int G, hipStream_t st, const StepArgs<T>& a, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr) {
   if (e0) {
-    if (hc == 4)
-      hipExtLaunchKernelGGL(k_step<T, 4>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+    if (a.stream)
+      hipExtLaunchKernelGGL(k_step<T, 4, true>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
     else
-      hipExtLaunchKernelGGL(k_step<T, 8>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+      hipExtLaunchKernelGGL(k_step<T, 4, false>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
     return;
   }
-  if (hc == 4)
-    k_step<T, 4><<<G, BLOCK, 0, st>>>(a);
+  if (a.stream)
+    k_step<T, 4, true><<<G, BLOCK, 0, st>>>(a);
   else
-    k_step<T, 8><<<G, BLOCK, 0, st>>>(a);
+    k_step<T, 4, false><<<G, BLOCK, 0, st>>>(a);
 }
 
 // Start (or restart after a residual replacement) of a run at launch k0: the
