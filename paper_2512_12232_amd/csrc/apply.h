@@ -303,12 +303,13 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
   T ns[HC], nr[HC];                            // rows 2..HC+1 of the next task
   int8_t tg[HC + 2];                           // tags and displacements of the current
   T ddx[HC + 2], ddy[HC + 2];                  // task (tasks that evaluate geometry)
+  int shift = 0;  // this lane's read column minus its own column (halo lanes)
   auto load_geom = [&](long long base) {
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
-      tg[r] = a.tag[base + r * P];
-      ddx[r] = a.dx[base + r * P];
-      ddy[r] = a.dy[base + r * P];
+      tg[r] = a.tag[base + shift + r * P];
+      ddx[r] = a.dx[base + shift + r * P];
+      ddy[r] = a.dy[base + shift + r * P];
     }
   };
   auto seg_load = [&](int sg) {
@@ -322,17 +323,19 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
     const int tl = kcl * nstrip + m;
     fl_body = a.tbody[tl] != 0ull;
     slot_l = a.tslot[tl];
-    const long long base = (long long)(kc0 * HC) * P + (long long)m * SW + lane;
-    f0s = src[base];
-    f1s = src[base + P];
+    shift = halo_shift(lane, m, nstrip);
+    const long long base = (long long)(kc0 * HC) * P + (long long)m * 64 + lane;
+    const long long lb = base + shift;
+    f0s = src[lb];
+    f1s = src[lb + P];
     if (FUSED) {
-      f0r = a.r[base];
-      f1r = a.r[base + P];
+      f0r = a.r[lb];
+      f1r = a.r[lb + P];
     }
 #pragma unroll
     for (int r = 0; r < HC; ++r) {
-      ns[r] = src[base + (r + 2) * P];
-      if (FUSED) nr[r] = a.r[base + (r + 2) * P];
+      ns[r] = src[lb + (r + 2) * P];
+      if (FUSED) nr[r] = a.r[lb + (r + 2) * P];
     }
     // the first task's geometry travels with its rows
     if (!(plain_mask & 1ull)) load_geom(base);
@@ -404,8 +407,8 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
     for (int kc = kc0; kc < kc1; ++kc) {
       const int it = kc - kc0;
       const bool first = kc == kc0;
-      // local row r = 0 .. HC+1 is padded row kc*HC + r; lane is padded column m*SW+lane
-      const long long base = (long long)(kc * HC) * P + (long long)m * SW + lane;
+      // local row r = 0 .. HC+1 is padded row kc*HC + r; lane is padded column m*64+lane
+      const long long base = (long long)(kc * HC) * P + (long long)m * 64 + lane;
       const bool plain = (plain_mask >> it) & 1ull;
       // rows 2..HC+1 arrived with the previous prefetch
 #pragma unroll
@@ -417,8 +420,8 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
         // rows 2..HC+1 of the next task: padded rows (kc+1)*HC + 2 ..
 #pragma unroll
         for (int r = 0; r < HC; ++r) {
-          ns[r] = src[base + (HC + 2 + r) * P];
-          if (FUSED) nr[r] = a.r[base + (HC + 2 + r) * P];
+          ns[r] = src[base + shift + (HC + 2 + r) * P];
+          if (FUSED) nr[r] = a.r[base + shift + (HC + 2 + r) * P];
         }
       }
       T qr[HC];
@@ -447,12 +450,11 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
         const long long gi = base + r * P;
         const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
         const T qv = qr[r - 1];
-        if (owner) {
-          if (FUSED) pnew[gi] = v[r];
-          const bool keep = (g == TAG_FREE) || (a.write_all && g != TAG_HALO);
-          a.q[gi] = keep ? qv : (T)0;
-          if (g == TAG_FREE) pq += (double)v[r] * (double)qv;
-        }
+        // every lane stores (the padding lanes zeros): whole aligned rows
+        if (FUSED) pnew[gi] = owner ? v[r] : (T)0;
+        const bool keep = owner && ((g == TAG_FREE) || (a.write_all && g != TAG_HALO));
+        a.q[gi] = keep ? qv : (T)0;
+        if (owner && g == TAG_FREE) pq += (double)v[r] * (double)qv;
         if (bm) body_row(owner, g, (double)qv, lane, bacc);
       }
       if (bm) {

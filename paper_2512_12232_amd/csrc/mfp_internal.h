@@ -60,11 +60,16 @@ struct Bump {
 };
 
 // ---- padded node layout used by the solver ----------------------------------------
-// Node (i, j) of the (nx+1) x (ny+1) grid lives at index (j+1)*P + (i+1); a ring of
-// halo nodes (tag TAG_HALO, zero values) surrounds the domain.  The element apply
-// works on "tasks": one wavefront per strip of 64 node columns (lanes 0 and 63 are
-// halo columns shared with the neighbouring strips, lanes 1..62 own their column)
-// and a chunk of HC node rows, marching upward with the node data in registers.
+// Node columns are grouped in strips of SW = 62; strip m occupies the 64-column,
+// 512-byte-aligned block [64 m, 64 m + 63] of every padded row, its nodes at columns
+// 64 m + 1 .. 64 m + 62; columns 64 m and 64 m + 63 are padding (tag TAG_HALO, zero
+// in every vector).  Node (i, j) lives at (j+1) P + 64 (i / 62) + 1 + i % 62, with one
+// halo row below and at least one above the domain.  The element apply works on
+// "tasks": one wavefront per strip and chunk of HC node rows; lane l of strip m sits
+// at column 64 m + l, lanes 1..62 own their node, lanes 0 and 63 read the nodes just
+// left and right of the strip (at 64 m - 2 and 64 m + 65, see halo_shift) and store
+// zeros into the padding, so that every row store is one whole aligned 512-byte line
+// set.
 constexpr int SW = 62;        // owned node columns per strip
 constexpr int BLOCK = 256;    // 4 wavefronts, i.e. 4 tasks per block and step
 constexpr int WAVES = BLOCK / 64;
@@ -90,10 +95,30 @@ inline Layout make_layout(int nx, int ny, int hc_force = 0) {
   L.nstrip = (nx + 1 + SW - 1) / SW;
   L.hc = hc_force == 8 ? 8 : 4;
   L.nchunk = (ny + 1 + L.hc - 1) / L.hc;
-  L.P = (((L.nstrip - 1) * SW + 64) + 63) / 64 * 64;
+  L.P = 64 * L.nstrip;
   L.rows = L.hc * L.nchunk + 2;
   L.n = (long long)L.P * L.rows;
   return L;
+}
+
+// Padded index of node (i, j).
+__host__ __device__ inline long long node_index(const Layout& L, int i, int j) {
+  return (long long)(j + 1) * L.P + 64 * (i / SW) + 1 + (i % SW);
+}
+
+// Node column held at padded column col, or -1 for a padding column.
+__host__ __device__ inline int column_node(int col) {
+  const int l = col & 63;
+  return (l == 0 || l == 63) ? -1 : (col >> 6) * SW + l - 1;
+}
+
+// Column shift from lane's own column to the column it reads: lanes 0 and 63 read
+// the neighbouring strips' edge nodes (none beyond the first and last strip: there
+// they read their own padding, a halo node).
+__host__ __device__ inline int halo_shift(int lane, int m, int nstrip) {
+  if (lane == 0) return m > 0 ? -2 : 0;
+  if (lane == 63) return m + 1 < nstrip ? 2 : 0;
+  return 0;
 }
 
 // Internal node tags.

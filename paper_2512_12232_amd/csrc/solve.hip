@@ -67,7 +67,7 @@ __global__ void k_setup(SetupArgs a) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x) {
     const int row = (int)(e / a.L.P), col = (int)(e - (long long)row * a.L.P);
-    const int i = col - 1, j = row - 1;
+    const int i = column_node(col), j = row - 1;
     int8_t tg = TAG_HALO;
     double dxv = 0.0, dyv = 0.0, gv = 0.0;
     if (i >= 0 && i <= a.nx && j >= 0 && j <= a.ny) {
@@ -123,7 +123,8 @@ __global__ void __launch_bounds__(BLOCK) k_task_meta(Layout L, const int8_t* __r
   if (t >= L.ntasks()) return;
   const int m = t % L.nstrip, kc = t / L.nstrip;
   const int HC = L.hc;
-  const long long base = (long long)(kc * HC) * L.P + (long long)m * SW + lane;
+  const long long base =
+      (long long)(kc * HC) * L.P + (long long)m * 64 + lane + halo_shift(lane, m, L.nstrip);
   int plain = 1;
   unsigned long long bm = 0;
   for (int r = 0; r < HC + 2; ++r) {
@@ -140,6 +141,27 @@ __global__ void __launch_bounds__(BLOCK) k_task_meta(Layout L, const int8_t* __r
   if (lane == 0) {
     tplain[t] = (uint8_t)plain;
     tbody[t] = bm;
+  }
+}
+
+// Caller node vector (node (i, j) at j (nx+1) + i) to and from the padded layout.
+template <typename T>
+__global__ void k_to_padded(Layout L, const T* __restrict__ src, T* __restrict__ dst) {
+  const long long nn = (long long)(L.nx + 1) * (L.ny + 1);
+  for (long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x; nd < nn;
+       nd += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(nd / (L.nx + 1)), i = (int)(nd - (long long)j * (L.nx + 1));
+    dst[node_index(L, i, j)] = src[nd];
+  }
+}
+
+template <typename T>
+__global__ void k_from_padded(Layout L, const T* __restrict__ src, T* __restrict__ dst) {
+  const long long nn = (long long)(L.nx + 1) * (L.ny + 1);
+  for (long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x; nd < nn;
+       nd += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(nd / (L.nx + 1)), i = (int)(nd - (long long)j * (L.nx + 1));
+    dst[nd] = src[node_index(L, i, j)];
   }
 }
 
@@ -500,7 +522,7 @@ __global__ void k_output(Layout L, int nx, int ny, const int8_t* __restrict__ ta
   for (long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x; nd < nn;
        nd += (long long)gridDim.x * blockDim.x) {
     const int j = (int)(nd / (nx + 1)), i = (int)(nd - (long long)j * (nx + 1));
-    const long long e = (long long)(j + 1) * L.P + (i + 1);
+    const long long e = node_index(L, i, j);
     const int8_t tg = tag[e];
     psi[nd] = tg == TAG_FREE ? x[e] : tg == TAG_DIR ? g[e] : xb[tg - TAG_BODY0];
   }
@@ -913,11 +935,13 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
   const size_t esz = precision == MFP_FP64 ? sizeof(double) : sizeof(float);
   void* src = precision == MFP_FP64 ? (void*)w.p0 : (void*)w.p0f;
   void* dst = precision == MFP_FP64 ? (void*)w.q : (void*)w.qf;
-  // scatter p into the padded layout row by row
+  // scatter p into the padded layout
   MFP_TRY_HIP(hipMemsetAsync(src, 0, esz * w.L.n, st));
-  MFP_TRY_HIP(hipMemcpy2DAsync((char*)src + esz * (w.L.P + 1), esz * w.L.P, p,
-                               esz * (g.nx + 1), esz * (g.nx + 1), g.ny + 1,
-                               hipMemcpyDeviceToDevice, st));
+  if (precision == MFP_FP64)
+    k_to_padded<double><<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, (const double*)p, (double*)src);
+  else
+    k_to_padded<float><<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, (const float*)p, (float*)src);
+  MFP_TRY_HIP(hipGetLastError());
   hipEvent_t e0, e1;
   MFP_TRY_HIP(hipEventCreate(&e0));
   MFP_TRY_HIP(hipEventCreate(&e1));
@@ -945,16 +969,17 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
     }
   }
   MFP_TRY_HIP(hipEventRecord(e1, st));
-  MFP_TRY_HIP(hipMemcpy2DAsync(q, esz * (g.nx + 1), (char*)dst + esz * (w.L.P + 1),
-                               esz * w.L.P, esz * (g.nx + 1), g.ny + 1,
-                               hipMemcpyDeviceToDevice, st));
+  if (precision == MFP_FP64)
+    k_from_padded<double><<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, (const double*)dst, (double*)q);
+  else
+    k_from_padded<float><<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, (const float*)dst, (float*)q);
+  MFP_TRY_HIP(hipGetLastError());
   MFP_TRY_HIP(hipEventSynchronize(e1));
   float ms = 0.f;
   MFP_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (apply_ms_h) *apply_ms_h = ms / repeat;
-  (void)nn;
   return MFP_OK;
 }
 
@@ -1216,7 +1241,7 @@ __global__ void k_warm_x(Layout L, int nx, int ny, const int8_t* __restrict__ ta
   for (long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x; nd < nn;
        nd += (long long)gridDim.x * blockDim.x) {
     const int j = (int)(nd / (nx + 1)), i = (int)(nd - (long long)j * (nx + 1));
-    const long long e = (long long)(j + 1) * L.P + (i + 1);
+    const long long e = node_index(L, i, j);
     if (tag[e] == TAG_FREE) x[e] = psi0[nd];
   }
 }

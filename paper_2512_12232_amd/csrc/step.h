@@ -120,17 +120,19 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   T* __restrict__ pc = a.p[cur];
   constexpr unsigned TS = sizeof(T);
   const unsigned RB = P * TS;  // bytes per padded row of a T vector
-  // task t: rows 0..HC+1 are padded rows chunk*HC + r, lane is column strip*SW + lane
+  // task t: rows 0..HC+1 are padded rows chunk*HC + r, lane is column strip*64 + lane
+  // (it reads column strip*64 + lane + halo_shift)
   auto node0 = [&](int t) -> unsigned {
     const int m = t % nstrip, kc = t / nstrip;
-    return (unsigned)(kc * HC) * P + (unsigned)(m * SW + lane);
+    return (unsigned)(kc * HC) * P + (unsigned)(m * 64 + lane);
   };
+  auto shift_of = [&](int t) -> int { return halo_shift(lane, t % nstrip, nstrip); };
 
   // next task's data (requested one task ahead)
   T nr[HC + 2], nq[HC + 2], np[HC + 2], nx[HC];
   int n_plain = 1, n_body = 0, n_slot = -1;
   auto fetch = [&](int t) {
-    const unsigned bo = node0(t) * TS;
+    const unsigned bo = (unsigned)((int)node0(t) + shift_of(t)) * TS;
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
       nr[r] = ld_at(rp, bo + r * RB);
@@ -138,7 +140,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
       np[r] = ld_at(pp, bo + r * RB);
     }
 #pragma unroll
-    for (int r = 0; r < HC; ++r) nx[r] = ld_at(a.x, bo + (r + 1) * RB);
+    for (int r = 0; r < HC; ++r) nx[r] = ld_at(a.x, bo + (r + 1) * RB);  // halo lanes: unused
     n_plain = a.tplain[t];
     n_body = a.tbody[t] != 0ull;
     n_slot = a.tslot[t];
@@ -262,11 +264,12 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
 #pragma unroll
     for (int r = 0; r < HC; ++r) xo[r] = nx[r];
     if (!plain) {
+      const unsigned ln0 = (unsigned)((int)n0 + shift_of(t));
 #pragma unroll
       for (int r = 0; r < HC + 2; ++r) {
-        tg[r] = ld_at(a.tag, n0 + r * P);
-        ddx[r] = ld_at(a.dx, bo + r * RB);
-        ddy[r] = ld_at(a.dy, bo + r * RB);
+        tg[r] = ld_at(a.tag, ln0 + r * P);
+        ddx[r] = ld_at(a.dx, ln0 * TS + r * RB);
+        ddy[r] = ld_at(a.dy, ln0 * TS + r * RB);
       }
     }
     T qr[HC];
@@ -292,12 +295,13 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     for (int r = 1; r <= HC; ++r) {
       const unsigned go = bo + r * RB;
       const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
-      const T qv = (g == TAG_FREE) ? qr[r - 1] : (T)0;
+      const T qv = (owner && g == TAG_FREE) ? qr[r - 1] : (T)0;
+      // every lane stores (the padding lanes zeros): whole aligned rows
+      st_vec<STREAM>(rc, go, owner ? rj[r] : (T)0);
+      st_vec<STREAM>(pc, go, owner ? v[r] : (T)0);
+      st_vec<STREAM>(qc, go, qv);
+      st_vec<STREAM>(a.x, go, owner ? xo[r - 1] + al * po[r] : (T)0);
       if (owner) {
-        st_vec<STREAM>(rc, go, rj[r]);
-        st_vec<STREAM>(pc, go, v[r]);
-        st_vec<STREAM>(qc, go, qv);
-        st_vec<STREAM>(a.x, go, xo[r - 1] + al * po[r]);
         if (g == TAG_FREE) {
           const double rd = (double)rj[r], qd = (double)qv;
           prr += rd * rd;
