@@ -34,9 +34,11 @@ HBM_PEAK_GBS = 8000.0
 
 
 def step_bytes(case, disp, body):
-    """Algorithmic bytes of one launch of the one-kernel CG iteration: every node reads
-    the previous residual, direction, K p and iterate (4 x 8 B) and writes the new ones
-    (4 x 8 B); every node with a non-zero displacement also reads it (2 x 8 B); every
+    """Algorithmic bytes of one launch of the one-kernel CG iteration, averaged over the
+    two launch parities: every node reads the previous residual, direction and K p
+    (3 x 8 B) and writes the new ones (3 x 8 B); odd launches also read the iterate and
+    the direction before last and write the iterate (3 x 8 B), i.e. 12 B per launch on
+    average; every node with a non-zero displacement also reads it (2 x 8 B); every
     node that is not a free fluid node is identified by its one-byte tag."""
     n = case.grid.nodes
     d = disp.view(2, n)
@@ -44,7 +46,7 @@ def step_bytes(case, disp, body):
     nx, ny = case.grid.nx, case.grid.ny
     boundary = 2 * (nx + 1) + 2 * (ny - 1)
     bodies = int((body >= 0).sum().item())
-    return 64 * n + 16 * moved + (boundary + bodies), moved
+    return 60 * n + 16 * moved + (boundary + bodies), moved
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp64_five_cyl_1024x512_counters.md")
@@ -228,8 +230,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 4096x2048 mixed-precision, adjoint and delta-sweep "
                          "measurements")
-    ap.add_argument("--profile-every", type=int, default=16,
-                    help="time every n-th apply launch with HIP events (0: off)")
+    ap.add_argument("--profile-every", type=int, default=17,
+                    help="time every n-th iteration launch with HIP events (0: off; odd, "
+                         "so that both launch parities are sampled)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()

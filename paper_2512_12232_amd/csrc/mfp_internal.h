@@ -138,6 +138,7 @@ struct DevState {
   double rr0, rr_stop, rr_final, rr_true;
   double alpha, beta, pq;
   double rr_prev;                        // one-kernel CG: |r|^2 before a restart (0: fresh)
+  double alpha_hist[2];                  // one-kernel CG: alpha_{k-1} computed by launch k, slot k&1
   double stop_rel;                       // one-kernel CG: threshold / start |r|^2 (0: use rr_stop)
   double copfi, Q;
   long long iters;                       // index of the final iterate once done != 0

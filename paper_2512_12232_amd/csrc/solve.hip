@@ -647,7 +647,7 @@ static int step_resident_waves() {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  const void* f = reinterpret_cast<const void*>(&k_step<T, 4, false>);
+  const void* f = reinterpret_cast<const void*>(&k_step<T, 4, false, true>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) != hipSuccess) return 0;
   return per_cu * cus * WAVES;
 }
@@ -1117,7 +1117,7 @@ static int step_run(const SolveWs& w, StepArgs<T> a, const mfp_solver_opts& o, h
   }
   for (int i = 0; i < 2 * nev_c; ++i) (void)hipEventDestroy(ev[i]);
   if (status != MFP_OK) return status;
-  k_finish<T><<<loop_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, a.x, a.p[(hs.iters + 1) & 1], a.st);
+  k_finish<T><<<loop_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, a.x, a.p[0], a.p[1], a.st);
   MFP_TRY_HIP(hipGetLastError());
   cnt->iters = hs.iters;
   cnt->applies += hs.iters - k0;

@@ -22,7 +22,10 @@
 // from r_{j-1}, Kp_{j-1}, p_{j-1} (the same arithmetic as the owner); r, p and Kp are
 // therefore double-buffered by parity (launch j reads slot (j-1)&1 and writes j&1),
 // as are the partials and the per-body slot sums.  The iterate is read and written
-// at owned nodes only.
+// at owned nodes only, and only by odd launches, two directions at a time:
+// x_j = x_{j-2} + alpha_{j-2} p_{j-2} + alpha_{j-1} p_{j-1} (p_{j-2} is still in the
+// slot launch j overwrites; each owner reads it before writing p_j), which saves one
+// store stream in two launches.
 //
 // Launch k0 starts (or restarts) a run: alpha = 0, |r_j|^2 is the exact sum of the
 // start residual (partials written by k_step_start), beta_j = |r_j|^2 / rr_prev with
@@ -31,7 +34,7 @@
 //
 // A launch that finds |r_j|^2 <= the threshold, j >= kmax, a breakdown or a non-finite
 // value records the outcome (iterate index j, alpha) and returns; k_finish then adds
-// alpha p_{j-1} to the iterate.
+// the directions the iterate still lacks.
 #pragma once
 
 #include "apply.h"
@@ -96,7 +99,7 @@ struct StepArgs {
 // neighbouring tasks share).  Every task's rows, iterate rows and flags are requested
 // one task ahead (a task that evaluates geometry requests its tags and displacements
 // first and the next task's data after its cell march, which needs the registers).
-template <typename T, int HC, bool STREAM>
+template <typename T, int HC, bool STREAM, bool XUPD>
 __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, double* s_pb,
                                           double* s_qb) {
   const int tid = threadIdx.x;
@@ -129,7 +132,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   auto shift_of = [&](int t) -> int { return halo_shift(lane, t % nstrip, nstrip); };
 
   // next task's data (requested one task ahead)
-  T nr[HC + 2], nq[HC + 2], np[HC + 2], nx[HC];
+  T nr[HC + 2], nq[HC + 2], np[HC + 2], nx[HC], n2[HC];  // n2: p_{j-2} (XUPD)
   int n_plain = 1, n_body = 0, n_slot = -1;
   auto fetch = [&](int t) {
     const unsigned bo = (unsigned)((int)node0(t) + shift_of(t)) * TS;
@@ -139,8 +142,14 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
       nq[r] = ld_at(qp, bo + r * RB);
       np[r] = ld_at(pp, bo + r * RB);
     }
+    if (XUPD) {
+      // own rows only (halo lanes' values are unused)
 #pragma unroll
-    for (int r = 0; r < HC; ++r) nx[r] = ld_at(a.x, bo + (r + 1) * RB);  // halo lanes: unused
+      for (int r = 0; r < HC; ++r) {
+        nx[r] = ld_at(a.x, bo + (r + 1) * RB);
+        n2[r] = ld_at((const T*)pc, bo + (r + 1) * RB);
+      }
+    }
     n_plain = a.tplain[t];
     n_body = a.tbody[t] != 0ull;
     n_slot = a.tslot[t];
@@ -153,6 +162,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   const int nb = a.nb;
   const int done = st->done;
   const double rr_stop = st->rr_stop, rr_prev_start = st->rr_prev, stop_rel = st->stop_rel;
+  const double alpha2 = st->alpha_hist[prv];  // alpha_{j-2}
   const long long kmax = st->kmax;
   double rbp = 0.0, pbp = 0.0, xbp = 0.0;  // lane b: body b of iteration j-1
   if (lane < nb) {
@@ -226,6 +236,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     }
     if (lane == 0) {
       st->alpha = alpha;
+      st->alpha_hist[cur] = alpha;
       st->rr[cur] = rr_j;
       if (start && stop_rel > 0.0) st->rr_stop = stop;
       if (code) {
@@ -241,7 +252,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   if (code) return;
   if (wv == 0 && lane < nb) s_pb[lane] = pbj;
   __syncthreads();
-  const T al = (T)alpha, be = (T)beta;
+  const T al = (T)alpha, be = (T)beta, al2 = (T)alpha2;
 
   // ---- tasks ----
   double prr = 0.0, ppq = 0.0, prq = 0.0, pqq = 0.0;
@@ -254,15 +265,20 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     const bool bm = !plain && n_body != 0;
     const int slot = n_slot;
     // r_j, p_j (as at a free node until corrected) and p_{j-1} at rows 0..HC+1
-    T rj[HC + 2], v[HC + 2], po[HC + 2], xo[HC];
+    T rj[HC + 2], v[HC + 2], po[HC + 2], xo[HC], p2[HC];
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
       rj[r] = nr[r] - al * nq[r];
       v[r] = rj[r] + be * np[r];
       po[r] = np[r];
     }
+    if (XUPD) {
 #pragma unroll
-    for (int r = 0; r < HC; ++r) xo[r] = nx[r];
+      for (int r = 0; r < HC; ++r) {
+        xo[r] = nx[r];
+        p2[r] = n2[r];
+      }
+    }
     if (!plain) {
       const unsigned ln0 = (unsigned)((int)n0 + shift_of(t));
 #pragma unroll
@@ -300,7 +316,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
       st_vec<STREAM>(rc, go, owner ? rj[r] : (T)0);
       st_vec<STREAM>(pc, go, owner ? v[r] : (T)0);
       st_vec<STREAM>(qc, go, qv);
-      st_vec<STREAM>(a.x, go, owner ? xo[r - 1] + al * po[r] : (T)0);
+      if (XUPD) st_vec<STREAM>(a.x, go, owner ? (xo[r - 1] + al2 * p2[r - 1]) + al * po[r] : (T)0);
       if (owner) {
         if (g == TAG_FREE) {
           const double rd = (double)rj[r], qd = (double)qv;
@@ -336,29 +352,40 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   }
 }
 
-template <typename T, int HC, bool STREAM>
+template <typename T, int HC, bool STREAM, bool XUPD>
 __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<T> a) {
   __shared__ double s_red[4 * WAVES];
   __shared__ double s_pb[MFP_MAX_BODIES];
   __shared__ double s_qb[MFP_MAX_BODIES];
-  step_core<T, HC, STREAM>(a, s_red, s_pb, s_qb);
+  step_core<T, HC, STREAM, XUPD>(a, s_red, s_pb, s_qb);
 }
 
-// Tasks of 4 node rows (the layout of a single solve).
+// Tasks of 4 node rows (the layout of a single solve); odd launches update the
+// iterate.
+template <typename T, bool STREAM, bool XUPD>
+inline void launch_step_i(int G, hipStream_t st, const StepArgs<T>& a, hipEvent_t e0,
+                          hipEvent_t e1) {
+  if (e0)
+    hipExtLaunchKernelGGL(k_step<T, 4, STREAM, XUPD>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+  else
+    k_step<T, 4, STREAM, XUPD><<<G, BLOCK, 0, st>>>(a);
+}
+
 template <typename T>
 inline void launch_step(int G, hipStream_t st, const StepArgs<T>& a, hipEvent_t e0 = nullptr,
                         hipEvent_t e1 = nullptr) {
-  if (e0) {
-    if (a.stream)
-      hipExtLaunchKernelGGL(k_step<T, 4, true>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+  const bool xu = (a.j & 1) != 0;
+  if (a.stream) {
+    if (xu)
+      launch_step_i<T, true, true>(G, st, a, e0, e1);
     else
-      hipExtLaunchKernelGGL(k_step<T, 4, false>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
-    return;
+      launch_step_i<T, true, false>(G, st, a, e0, e1);
+  } else {
+    if (xu)
+      launch_step_i<T, false, true>(G, st, a, e0, e1);
+    else
+      launch_step_i<T, false, false>(G, st, a, e0, e1);
   }
-  if (a.stream)
-    k_step<T, 4, true><<<G, BLOCK, 0, st>>>(a);
-  else
-    k_step<T, 4, false><<<G, BLOCK, 0, st>>>(a);
 }
 
 // Start (or restart after a residual replacement) of a run at launch k0: the
@@ -394,6 +421,9 @@ __global__ void k_step_bodies(const DevState* outer, DevState* in, int nb, int s
     if (fresh) in->pb[slot][b] = 0.0;
   }
   if (b == 0) {
+    // no direction is pending in the iterate at a start
+    in->alpha_hist[0] = 0.0;
+    in->alpha_hist[1] = 0.0;
     if (fresh) in->rr_prev = 0.0;
     in->stop_rel = stop_rel;
     in->kmax = kmax;
@@ -401,15 +431,22 @@ __global__ void k_step_bodies(const DevState* outer, DevState* in, int nb, int s
   }
 }
 
-// x += alpha p_{j-1} for the launch j that stopped (alpha recorded by it).
+// The iterate after the launch J that stopped: x_J = x_{J-1} + alpha_{J-1} p_{J-1}.
+// If launch J-1 was odd, x holds x_{J-1}; otherwise it holds x_{J-2} and also lacks
+// alpha_{J-2} p_{J-2} (p_{J-2} is still in slot J&1: launch J wrote no direction).
 template <typename T>
-__global__ void k_finish(long long n, T* __restrict__ x, const T* __restrict__ p,
-                         const DevState* __restrict__ st) {
-  const T al = (T)st->alpha;
-  if (al == (T)0) return;
+__global__ void k_finish(long long n, T* __restrict__ x, const T* __restrict__ p0,
+                         const T* __restrict__ p1, const DevState* __restrict__ st) {
+  const long long J = st->iters;
+  const T a1 = (T)st->alpha;
+  const bool two = ((J - 1) & 1) == 0;
+  const T a2 = two ? (T)st->alpha_hist[(J - 1) & 1] : (T)0;
+  const T* pa = ((J - 1) & 1) ? p1 : p0;  // p_{J-1}
+  const T* pb = (J & 1) ? p1 : p0;        // p_{J-2}
+  if (a1 == (T)0 && a2 == (T)0) return;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
        e += (long long)gridDim.x * blockDim.x)
-    x[e] += al * p[e];
+    x[e] = (x[e] + a2 * pb[e]) + a1 * pa[e];
 }
 
 }  // namespace mfp
