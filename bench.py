@@ -33,20 +33,21 @@ METRIC = "CG DOF·iter/s + matvec HBM GB/s (% peak); adjoint/forward time; err v
 HBM_PEAK_GBS = 8000.0
 
 
-def step_bytes(case, disp, body):
+def step_bytes(case, disp, body, esz=8):
     """Algorithmic bytes of one launch of the one-kernel CG iteration, averaged over the
     two launch parities: every node reads the previous residual, direction and K p
     (3 x 8 B) and writes the new ones (3 x 8 B); odd launches also read the iterate and
     the direction before last and write the iterate (3 x 8 B), i.e. 12 B per launch on
     average; every node with a non-zero displacement also reads it (2 x 8 B); every
-    node that is not a free fluid node is identified by its one-byte tag."""
+    node that is not a free fluid node is identified by its one-byte tag.  esz = 4:
+    the FP32 iteration (4-byte vectors and displacements)."""
     n = case.grid.nodes
     d = disp.view(2, n)
     moved = int(((d[0] != 0) | (d[1] != 0)).sum().item())
     nx, ny = case.grid.nx, case.grid.ny
     boundary = 2 * (nx + 1) + 2 * (ny - 1)
     bodies = int((body >= 0).sum().item())
-    return 60 * n + 16 * moved + (boundary + bodies), moved
+    return (15 * esz * n) // 2 + 2 * esz * moved + (boundary + bodies), moved
 
 
 COUNTERS = os.path.join(ROOT, "profiles", "k_step_fp64_five_cyl_1024x512_counters.md")
@@ -127,14 +128,24 @@ def mixed_precision(mfp, W):
     disp, kind, body = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device="cuda:0")
     out = {"workload": "five cylinders, 4096x2048 cells, delta 0.5, rtol 1e-10"}
     res = {}
+    nbytes64, _ = step_bytes(case, disp, body)
+    nbytes32, _ = step_bytes(case, disp, body, esz=4)
     for prec, rtol in (("fp64", 1e-10), ("fp32_ir", 1e-10), ("fp32", 1e-6)):
         r, ms = _timed(lambda: mfp.psi_solve(case.grid, case.circles, disp, kind, body,
                                              case.flow, precision=prec, rtol=rtol,
-                                             pair=case.pair, sample_cap=0))
+                                             pair=case.pair, sample_cap=0, profile_every=17))
         res[prec] = r
         out[prec] = {"solve_ms": round(ms, 2), "iters": r.stats["iters"],
                      "relres_true": r.stats["relres_true"], "rtol": rtol,
                      "dof_iter_per_s": r.stats["n_dof"] * r.stats["iters"] / (ms * 1e-3)}
+        if r.stats["apply_samples"] > 0:
+            nbytes = nbytes64 if prec == "fp64" else nbytes32
+            kms = r.stats["apply_ms"]
+            out[prec]["roofline"] = {
+                "kernel": "k_step<%s, 4>" % ("double" if prec == "fp64" else "float"),
+                "launch_ms": round(kms, 5), "bytes_per_launch": nbytes,
+                "achieved_GBs": round(nbytes / (kms * 1e-3) / 1e9, 1),
+                "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     ref = res["fp64"].psi
     for prec in ("fp32_ir", "fp32"):
         d = res[prec].psi - ref
