@@ -508,14 +508,12 @@ inline void launch_apply(int hc, int G, hipStream_t st, const ApplyArgs<T>& a,
 }
 
 // Per-body sums of the slot partials, into s_qb[0 .. nb); wave w handles bodies
-// w, w+4, ...  Fixed order.  The slot count is read together with the first 64 slots
-// of every body (the partial buffer always holds at least 64 slots), so the common
-// case costs one memory round trip.
-__device__ __forceinline__ void body_sums(const double* __restrict__ bpart,
-                                          const int* __restrict__ nslots_p, int nb,
+// w, w+4, ...  Fixed order.  The first 64 slots of every body are requested at once
+// (the partial buffer always holds at least 64 slots), so the common case costs one
+// memory round trip.
+__device__ __forceinline__ void body_sums(const double* __restrict__ bpart, int nslots, int nb,
                                           double* s_qb) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int nslots = *nslots_p;
   for (int b = w; b < nb; b += BLOCK / 64) {
     double v = bpart[(long long)lane * nb + b];
     v = lane < nslots ? v : 0.0;
@@ -524,6 +522,12 @@ __device__ __forceinline__ void body_sums(const double* __restrict__ bpart,
     if (lane == 0) s_qb[b] = v;
   }
   __syncthreads();
+}
+
+__device__ __forceinline__ void body_sums(const double* __restrict__ bpart,
+                                          const int* __restrict__ nslots_p, int nb,
+                                          double* s_qb) {
+  body_sums(bpart, *nslots_p, nb, s_qb);
 }
 
 }  // namespace mfp

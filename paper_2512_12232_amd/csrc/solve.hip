@@ -715,6 +715,7 @@ struct SolveWs {
   unsigned long long* tbody;
   int* tslot;
   int* nslots;
+  mutable int nslots_h = 0;  // host copy of *nslots (read once after setup)
   int4* segtab;   // apply work list (k_seg_plan)
   double* part;
   double* part2;
@@ -990,13 +991,41 @@ struct CgCount {
   long long tcnt = 0;
 };
 
-// Arguments of the one-kernel iteration over one set of vectors (FP64: w.r/r1, p0/p1,
-// q/q1, x; FP32: the float copies and the correction e in xf).
+// The one-kernel iteration over one set of vectors (FP64: w.r/r1, p0/p1, q/q1, x;
+// FP32: the float copies and the correction e in xf): the fixed kernel arguments and
+// both parity slots of every double-buffered array; at(j) gives launch j's arguments.
 template <typename T>
-static StepArgs<T> make_step_args(const SolveWs& w, const mfp_grid& g, int nb, const T* dx,
-                                  const T* dy, T* r0, T* r1, T* p0, T* p1, T* q0, T* q1,
-                                  T* x, DevState* st) {
-  StepArgs<T> a{};
+struct StepRun {
+  StepArgs<T> a;
+  T* r[2];
+  T* p[2];
+  T* q[2];
+  double* part[2];
+  double* bpart[2];
+  StepArgs<T> at(long long j) const {
+    StepArgs<T> b = a;
+    const int c = (int)(j & 1), pv = c ^ 1;
+    b.j = j;
+    b.rp = r[pv];
+    b.qp = q[pv];
+    b.pp = p[pv];
+    b.rc = r[c];
+    b.qc = q[c];
+    b.pc = p[c];
+    b.part_p = part[pv];
+    b.part_c = part[c];
+    b.bpart_p = bpart[pv];
+    b.bpart_c = bpart[c];
+    return b;
+  }
+};
+
+template <typename T>
+static StepRun<T> make_step_run(const SolveWs& w, const mfp_grid& g, int nb, const T* dx,
+                                const T* dy, T* r0, T* r1, T* p0, T* p1, T* q0, T* q1, T* x,
+                                DevState* st) {
+  StepRun<T> s{};
+  StepArgs<T>& a = s.a;
   a.P = w.L.P;
   a.nstrip = w.L.nstrip;
   a.nchunk = w.L.nchunk;
@@ -1006,18 +1035,8 @@ static StepArgs<T> make_step_args(const SolveWs& w, const mfp_grid& g, int nb, c
   a.dy = dy;
   a.tbody = w.tbody;
   a.tslot = w.tslot;
-  a.nslots = w.nslots;
-  a.r[0] = r0;
-  a.r[1] = r1;
-  a.p[0] = p0;
-  a.p[1] = p1;
-  a.q[0] = q0;
-  a.q[1] = q1;
+  a.nslots = w.nslots_h;
   a.x = x;
-  a.part[0] = w.spart;
-  a.part[1] = w.spart + 4 * GMAX;
-  a.bpart[0] = w.bpart;
-  a.bpart[1] = w.bpart + w.bstride;
   a.st = st;
   a.nb = nb;
   // streaming stores once the iteration's seven vectors clearly exceed the 256 MiB
@@ -1031,7 +1050,17 @@ static StepArgs<T> make_step_args(const SolveWs& w, const mfp_grid& g, int nb, c
   a.cN = (T)(-2.0 / 3.0 * qq + rr / 3.0);
   a.cD = (T)(-(rr + qq) / 6.0);
   a.ry = (T)rr;
-  return a;
+  s.r[0] = r0;
+  s.r[1] = r1;
+  s.p[0] = p0;
+  s.p[1] = p1;
+  s.q[0] = q0;
+  s.q[1] = q1;
+  s.part[0] = w.spart;
+  s.part[1] = w.spart + 4 * GMAX;
+  s.bpart[0] = w.bpart;
+  s.bpart[1] = w.bpart + w.bstride;
+  return s;
 }
 
 // Start of a run at launch k0 (state of slot (k0-1)&1): the residual slot takes the
@@ -1040,13 +1069,13 @@ static StepArgs<T> make_step_args(const SolveWs& w, const mfp_grid& g, int nb, c
 // correction that starts at zero (inner FP32 solve); stop_rel > 0: threshold relative
 // to the start residual; kmax_abs: last launch index.
 template <typename T>
-static int step_start(const SolveWs& w, int nb, const StepArgs<T>& a, long long k0, bool fresh,
+static int step_start(const SolveWs& w, int nb, const StepRun<T>& a, long long k0, bool fresh,
                       bool correction, double stop_rel, long long kmax_abs, hipStream_t st,
                       int* npart0) {
   const int slot = (int)((k0 + 1) & 1);
   const int G2 = loop_blocks(w.L.n);
   k_step_start<T><<<G2, BLOCK, 0, st>>>(w.L.n, w.r, a.r[slot], a.part[slot]);
-  k_step_bodies<<<1, 64, 0, st>>>(w.st, a.st, nb, slot, fresh ? 1 : 0, correction ? 1 : 0,
+  k_step_bodies<<<1, 64, 0, st>>>(w.st, a.a.st, nb, slot, fresh ? 1 : 0, correction ? 1 : 0,
                                   stop_rel, kmax_abs);
   MFP_TRY_HIP(hipGetLastError());
   *npart0 = G2;
@@ -1059,7 +1088,7 @@ static int step_start(const SolveWs& w, int nb, const StepArgs<T>& a, long long 
 // alpha p.  Returns the done code (1 converged, 2 breakdown, 3 kmax) or a negative
 // status; cnt->iters is the stopping launch.
 template <typename T>
-static int step_run(const SolveWs& w, StepArgs<T> a, const mfp_solver_opts& o, hipStream_t st,
+static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, hipStream_t st,
                     CgCount* cnt, long long k0) {
   if (w.L.hc != 4) {
     set_error("internal: the CG iteration kernel needs 4-row tasks");
@@ -1077,12 +1106,12 @@ static int step_run(const SolveWs& w, StepArgs<T> a, const mfp_solver_opts& o, h
     int done;
     long long iters;
   } hs{0, 0};
-  a.k0 = k0;
+  run.a.k0 = k0;
   int status = MFP_OK;
   while (true) {
     int used = 0;
     for (int m = 0; m < every; ++m, ++j) {
-      a.j = j;
+      const StepArgs<T> a = run.at(j);
       const bool timed = prof && (m % prof == 0) && used < nev_c;
       if (timed) {
         launch_step<T>(G, st, a, ev[2 * used], ev[2 * used + 1]);
@@ -1092,9 +1121,9 @@ static int step_run(const SolveWs& w, StepArgs<T> a, const mfp_solver_opts& o, h
       }
     }
     hipError_t le = hipGetLastError();
-    if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &a.st->done, sizeof(int),
+    if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &run.a.st->done, sizeof(int),
                                               hipMemcpyDeviceToHost, st);
-    if (le == hipSuccess) le = hipMemcpyAsync(&hs.iters, &a.st->iters, sizeof(long long),
+    if (le == hipSuccess) le = hipMemcpyAsync(&hs.iters, &run.a.st->iters, sizeof(long long),
                                               hipMemcpyDeviceToHost, st);
     if (le == hipSuccess) le = hipStreamSynchronize(st);
     if (le != hipSuccess) {
@@ -1117,7 +1146,7 @@ static int step_run(const SolveWs& w, StepArgs<T> a, const mfp_solver_opts& o, h
   }
   for (int i = 0; i < 2 * nev_c; ++i) (void)hipEventDestroy(ev[i]);
   if (status != MFP_OK) return status;
-  k_finish<T><<<loop_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, a.x, a.p[0], a.p[1], a.st);
+  k_finish<T><<<loop_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, run.a.x, run.p[0], run.p[1], run.a.st);
   MFP_TRY_HIP(hipGetLastError());
   cnt->iters = hs.iters;
   cnt->applies += hs.iters - k0;
@@ -1155,10 +1184,10 @@ static int read_rr(const SolveWs& w, hipStream_t st, double* rr, double* rr0) {
 // FP64 CG from the state that residual64 (mode 0) prepared: one run from launch 1.
 static int solve64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver_opts& o,
                    hipStream_t st, CgCount* cnt, long long kmax = 0) {
-  StepArgs<double> a = make_step_args<double>(w, g, nb, w.dx, w.dy, w.r, w.r1, w.p0, w.p1,
+  StepRun<double> a = make_step_run<double>(w, g, nb, w.dx, w.dy, w.r, w.r1, w.p0, w.p1,
                                               w.q, w.q1, w.x, w.st);
   const long long km = kmax > 0 ? kmax : o.kmax;
-  MFP_TRY(step_start<double>(w, nb, a, 1, true, false, 0.0, 1 + km, st, &a.npart0));
+  MFP_TRY(step_start<double>(w, nb, a, 1, true, false, 0.0, 1 + km, st, &a.a.npart0));
   return step_run<double>(w, a, o, st, cnt, 1);
 }
 
@@ -1182,7 +1211,7 @@ static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_so
   MFP_TRY(read_rr(w, st, &rr, &rr0));
   if (rr <= o.rtol * o.rtol * rr0) return 1;
   MFP_TRY_HIP(hipMemsetAsync(w.xf, 0, sizeof(float) * w.L.n, st));
-  StepArgs<float> a = make_step_args<float>(w, g, nb, w.dxf, w.dyf, w.rf, w.r1f, w.p0f, w.p1f,
+  StepRun<float> a = make_step_run<float>(w, g, nb, w.dxf, w.dyf, w.rf, w.r1f, w.p0f, w.p1f,
                                             w.qf, w.q1f, w.xf, w.st2);
   long long k0 = 1;
   bool fresh = true;
@@ -1193,7 +1222,7 @@ static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_so
     const long long cap = ir ? k0_cap(k0 - 1) : o.kmax;
     long long kabs = k0 + cap;
     if (kabs > 1 + o.kmax) kabs = 1 + o.kmax;
-    MFP_TRY(step_start<float>(w, nb, a, k0, fresh, true, delta * delta, kabs, st, &a.npart0));
+    MFP_TRY(step_start<float>(w, nb, a, k0, fresh, true, delta * delta, kabs, st, &a.a.npart0));
     code = step_run<float>(w, a, o, st, cnt, k0);
     if (code < 0) return code;
     const long long J = cnt->iters;
@@ -1317,7 +1346,8 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
     if (nb > 0) k_warm_xb<<<1, 64, 0, st>>>(g.nx, g.ny, nb, w.boxes, body, opts->psi0, w.st);
     MFP_TRY_HIP(hipGetLastError());
   }
-  MFP_TRY_HIP(hipStreamSynchronize(st));  // host-side staging buffers above
+  MFP_TRY_HIP(hipMemcpyAsync(&w.nslots_h, w.nslots, sizeof(int), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));  // host-side staging buffers above, slot count
 
   hipEvent_t e0, e1;
   MFP_TRY_HIP(hipEventCreate(&e0));

@@ -75,13 +75,20 @@ struct StepArgs {
   const T* dy;
   const unsigned long long* tbody;
   const int* tslot;
-  const int* nslots;
-  T* r[2];                       // residual, slot = iteration parity
-  T* p[2];                       // direction
-  T* q[2];                       // K p
+  int nslots;                    // body-sum slots in use
+  // vectors of iteration j-1 (parity slot (j-1)&1) and j (slot j&1), chosen by the
+  // host for every launch so that no address depends on a loaded value
+  const T* rp;                   // residual
+  const T* qp;                   // K p
+  const T* pp;                   // direction
+  T* rc;
+  T* qc;
+  T* pc;
   T* x;                          // iterate (free nodes meaningful)
-  double* part[2];               // per-block partials: r.r, p.Kp, r.Kp, Kp.Kp
-  double* bpart[2];              // per-slot, per-body sums of K p
+  const double* part_p;          // per-block partials: r.r, p.Kp, r.Kp, Kp.Kp
+  double* part_c;
+  const double* bpart_p;         // per-slot, per-body sums of K p
+  double* bpart_c;
   DevState* st;
   int nb;
   int npart0;                    // partials (blocks) written by the start kernel
@@ -115,12 +122,12 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   const long long j = a.j;
   const int cur = (int)(j & 1), prv = cur ^ 1;
   const bool start = j == a.k0;
-  const T* __restrict__ rp = a.r[prv];
-  const T* __restrict__ qp = a.q[prv];
-  const T* __restrict__ pp = a.p[prv];
-  T* __restrict__ rc = a.r[cur];
-  T* __restrict__ qc = a.q[cur];
-  T* __restrict__ pc = a.p[cur];
+  const T* __restrict__ rp = a.rp;
+  const T* __restrict__ qp = a.qp;
+  const T* __restrict__ pp = a.pp;
+  T* __restrict__ rc = a.rc;
+  T* __restrict__ qc = a.qc;
+  T* __restrict__ pc = a.pc;
   constexpr unsigned TS = sizeof(T);
   const unsigned RB = P * TS;  // bytes per padded row of a T vector
   // task t: rows 0..HC+1 are padded rows chunk*HC + r, lane is column strip*64 + lane
@@ -158,8 +165,11 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   if (t < ntask) fetch(t);
 
   // ---- scalars of iteration j ----
+  // Everything they need is requested here, in one round trip: the state, lane b's
+  // body values, the previous launch's partials and its per-body slot sums (wave w:
+  // bodies w and w + 4 from the first 64 slots; more bodies or slots in a second pass).
   DevState* st = a.st;
-  const int nb = a.nb;
+  const int nb = a.nb, nsl = a.nslots;
   const int done = st->done;
   const double rr_stop = st->rr_stop, rr_prev_start = st->rr_prev, stop_rel = st->stop_rel;
   const double alpha2 = st->alpha_hist[prv];  // alpha_{j-2}
@@ -170,8 +180,15 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     pbp = st->pb[prv][lane];
     xbp = st->xb[prv][lane];
   }
+  const double* __restrict__ bq = a.bpart_p;
+  const int b0 = wv, b1 = wv + WAVES;
+  double q0 = 0.0, q1 = 0.0;  // slot sums of bodies b0, b1 (K p of iteration j-1)
+  if (!start && lane < nsl) {
+    if (b0 < nb) q0 = bq[(long long)lane * nb + b0];
+    if (b1 < nb) q1 = bq[(long long)lane * nb + b1];
+  }
   const int npart = start ? a.npart0 : G;
-  const double* __restrict__ pt = a.part[prv];
+  const double* __restrict__ pt = a.part_p;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int i = tid; i < npart; i += BLOCK) {
     s0 += pt[4 * i];
@@ -179,44 +196,83 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     s2 += pt[4 * i + 2];
     s3 += pt[4 * i + 3];
   }
-  body_sums(a.bpart[prv], a.nslots, nb, s_qb);
   if (done) return;
+  // the first task's geometry is requested now (its flag has arrived with the
+  // partials), so that it travels while the scalars are reduced
+  int8_t tg[HC + 2];
+  T ddx[HC + 2], ddy[HC + 2];
+  auto load_geom = [&](int tt) {
+    const unsigned ln0 = (unsigned)((int)node0(tt) + shift_of(tt));
+#pragma unroll
+    for (int r = 0; r < HC + 2; ++r) {
+      tg[r] = ld_at(a.tag, ln0 + r * P);
+      ddx[r] = ld_at(a.dx, ln0 * TS + r * RB);
+      ddy[r] = ld_at(a.dy, ln0 * TS + r * RB);
+    }
+  };
+  if (t < ntask && !n_plain) load_geom(t);
+  if (!start) {
+    for (int sl = lane + 64; sl < nsl; sl += 64) {
+      if (b0 < nb) q0 += bq[(long long)sl * nb + b0];
+      if (b1 < nb) q1 += bq[(long long)sl * nb + b1];
+    }
+  }
+  // wave sums, six independent chains
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     s0 += __shfl_xor(s0, off, 64);
     s1 += __shfl_xor(s1, off, 64);
     s2 += __shfl_xor(s2, off, 64);
     s3 += __shfl_xor(s3, off, 64);
+    q0 += __shfl_xor(q0, off, 64);
+    q1 += __shfl_xor(q1, off, 64);
   }
   if (lane == 0) {
     s_red[4 * wv] = s0;
     s_red[4 * wv + 1] = s1;
     s_red[4 * wv + 2] = s2;
     s_red[4 * wv + 3] = s3;
+    if (b0 < nb) s_qb[b0] = start ? 0.0 : q0;
+    if (b1 < nb) s_qb[b1] = start ? 0.0 : q1;
+  }
+  // bodies beyond 2 x WAVES (rare)
+  for (int b = wv + 2 * WAVES; b < nb; b += WAVES) {
+    double v = 0.0;
+    if (!start)
+      for (int sl = lane; sl < nsl; sl += 64) v += bq[(long long)sl * nb + b];
+    v = wave_sum(v);
+    if (lane == 0) s_qb[b] = v;
   }
   __syncthreads();
+  const double qb = lane < nb ? s_qb[lane] : 0.0;
+  // body parts of r.r and p.Kp, two independent chains
+  double brr = rbp * rbp, bpq = pbp * qb;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    brr += __shfl_xor(brr, off, 64);
+    bpq += __shfl_xor(bpq, off, 64);
+  }
   const double S_rr = (s_red[0] + s_red[4]) + (s_red[8] + s_red[12]);
   const double S_pq = (s_red[1] + s_red[5]) + (s_red[9] + s_red[13]);
   const double S_rq = (s_red[2] + s_red[6]) + (s_red[10] + s_red[14]);
   const double S_qq = (s_red[3] + s_red[7]) + (s_red[11] + s_red[15]);
-  const double qb = (lane < nb && !start) ? s_qb[lane] : 0.0;
-  double alpha = 0.0, rr_prev, rr_j;
+  double alpha = 0.0, rr_prev;
   int code = 0;
   if (start) {
     rr_prev = rr_prev_start;
   } else {
-    rr_prev = S_rr + wave_sum(rbp * rbp);
-    const double pq = S_pq + wave_sum(pbp * qb);
+    rr_prev = S_rr + brr;
+    const double pq = S_pq + bpq;
     if (!(pq > 0.0) || !isfinite(pq)) code = 2;
     alpha = code ? 0.0 : rr_prev / pq;
   }
   const double rbj = rbp - alpha * qb;
   const double xbj = xbp + alpha * pbp;
+  // the body part of |r_j|^2 is summed exactly: a body residual can drop by orders
+  // of magnitude in one iteration, where the expansion would cancel
   const double b_rr = wave_sum(rbj * rbj);
-  if (start)
-    rr_j = S_rr + b_rr;
-  else
-    rr_j = (S_rr - 2.0 * alpha * S_rq + alpha * alpha * S_qq) + b_rr;
+  const double rr_j =
+      start ? S_rr + b_rr : (S_rr - 2.0 * alpha * S_rq + alpha * alpha * S_qq) + b_rr;
   const double stop = (start && stop_rel > 0.0) ? stop_rel * rr_j : rr_stop;
   if (!code) {
     if (!isfinite(rr_j))
@@ -256,8 +312,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
 
   // ---- tasks ----
   double prr = 0.0, ppq = 0.0, prq = 0.0, pqq = 0.0;
-  int8_t tg[HC + 2];
-  T ddx[HC + 2], ddy[HC + 2];
+  bool first = true;
   for (; t < ntask; t += W) {
     const unsigned n0 = node0(t);
     const unsigned bo = n0 * TS;
@@ -279,15 +334,8 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
         p2[r] = n2[r];
       }
     }
-    if (!plain) {
-      const unsigned ln0 = (unsigned)((int)n0 + shift_of(t));
-#pragma unroll
-      for (int r = 0; r < HC + 2; ++r) {
-        tg[r] = ld_at(a.tag, ln0 + r * P);
-        ddx[r] = ld_at(a.dx, ln0 * TS + r * RB);
-        ddy[r] = ld_at(a.dy, ln0 * TS + r * RB);
-      }
-    }
+    if (!plain && !first) load_geom(t);
+    first = false;
     T qr[HC];
     if (plain) {
       if (t + W < ntask) fetch(t + W);
@@ -328,7 +376,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
       }
       if (bm) body_row(owner, g, (double)qr[r - 1], lane, bacc);
     }
-    if (bm && lane < nb) a.bpart[cur][(long long)slot * nb + lane] = bacc;
+    if (bm && lane < nb) a.bpart_c[(long long)slot * nb + lane] = bacc;
   }
   // four block sums, fixed order
 #pragma unroll
@@ -347,7 +395,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   }
   __syncthreads();
   if (tid < 4) {
-    a.part[cur][4 * vblk + tid] =
+    a.part_c[4 * vblk + tid] =
         (s_red[tid] + s_red[4 + tid]) + (s_red[8 + tid] + s_red[12 + tid]);
   }
 }
