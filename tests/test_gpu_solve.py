@@ -134,3 +134,72 @@ def test_refinement_stagnation_falls_back_to_fp64(mfp):
     ref = O.solve(mesh, c.flow)
     err = np.linalg.norm(res.psi.cpu().numpy() - ref.psi) / np.linalg.norm(ref.psi)
     assert err <= 1e-10 and res.stats["relres_true"] <= 1e-13
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 6, 17])
+def test_iterate_after_k_iterations_matches_textbook_cg(mfp, k):
+    """After exactly k iterations (kmax = k) the iterate equals k steps of the
+    oracle's textbook CG on the assembled reduced system.  Covers both launch
+    parities of the iteration kernel (the iterate is updated two directions at a
+    time) and the completion of the iterate after the stopping launch."""
+    from oracle.cg import cg
+    c = CASES["five_ragged130x67"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-30, kmax=k,
+                        check_every=4)
+    assert res.status == 1 and res.stats["iters"] == k
+    mesh = O.conform(c.grid, c.circles, c.nsweeps)
+    ref = O.solve(mesh, c.flow)
+    y, kk, _ = cg(ref.A, ref.b, rtol=0.0, max_iters=k)
+    assert kk == k
+    psi_k = ref.g + ref.T @ y
+    psi = res.psi.cpu().numpy()
+    err = np.linalg.norm(psi - psi_k) / np.linalg.norm(psi_k)
+    assert err <= 1e-11, err
+    np.testing.assert_allclose(res.psi_b, y[ref.nfree:], rtol=0, atol=1e-11)
+
+
+def test_refined_fp32_many_restarts(mfp):
+    """A loose inner reduction (0.5) forces many FP64 residual replacements, each a
+    restart of the iteration at an arbitrary launch parity with the direction kept."""
+    c = CASES["five_ragged130x67"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13,
+                        precision="fp32_ir", inner_rtol=0.5, pair=c.pair)
+    assert res.status == 0, res.status
+    assert res.stats["outer_iters"] >= 20
+    mesh = O.conform(c.grid, c.circles, c.nsweeps)
+    ref = O.solve(mesh, c.flow)
+    err = np.linalg.norm(res.psi.cpu().numpy() - ref.psi) / np.linalg.norm(ref.psi)
+    assert err <= 1e-10, err
+
+
+def test_full_size_4096x2048_equations_hold_on_samples(mfp):
+    """4096 x 2048 (8.4M nodes; the iteration's seven vectors exceed the memory-side
+    cache, so the streaming-store kernels run): the FP64 solution satisfies the
+    discrete equations of the oracle's mesh, row by row, at 4000 seeded free nodes
+    and in every body row (the sum of (K psi) over the body's nodes), and the layout's
+    mirror symmetry holds."""
+    c = W.five_cyl_4096()
+    say("[full size 4096x2048] GPU solve")
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-10,
+                        pair=c.pair, sample_cap=0)
+    assert res.status == 0 and res.stats["relres_true"] <= 1.5e-10
+    pb = np.array(res.psi_b)
+    assert np.abs(pb[:3]).max() < 1e-7 and abs(pb[3] + pb[4]) < 1e-7
+    psi = res.psi.cpu().numpy()
+    say("[full size 4096x2048] oracle mesh")
+    mesh = O.conform(c.grid, c.circles, c.nsweeps)
+    dmask = O.dirichlet_mask(c.grid, c.flow).ravel()
+    bflat = mesh.body.ravel()
+    free = np.flatnonzero((~dmask) & (bflat < 0))
+    rng = np.random.default_rng(7)
+    nodes = rng.choice(free, size=4000, replace=False)
+    kp = O.apply_at_nodes(mesh, psi, nodes)
+    scale = np.abs(psi).max()
+    # rows are O(1) combinations of psi; the global relative residual is 1e-10
+    assert np.abs(kp).max() <= 1e-7 * scale, np.abs(kp).max()
+    for b in range(len(c.circles)):
+        bn = np.flatnonzero(bflat == b)
+        assert abs(O.apply_at_nodes(mesh, psi, bn).sum()) <= 1e-7 * scale
