@@ -244,14 +244,16 @@ size_t mfp_batched_workspace_size(int32_t nvar, const mfp_variant* vars_h, int32
 
 /* Many independent solves of the same body layout on different meshes (the repeated
  * evaluations and design sweeps the paper's Practical Applications and Introduction
- * name), advanced together: every kernel launch covers all systems, a fixed block of
- * `iters_per_launch` iterations (0 -> 64) is captured once as a hipGraph and replayed
- * until every system has stopped.  circles_h holds nvar * nbody circles (system-major),
- * psi_b_h receives nvar * nbody values, copfi_h (may be NULL) nvar values, stats_h (may
- * be NULL) nvar entries.  opts->precision: MFP_FP64 (CG, each system stops on its own
- * residual) or MFP_FP32_IR (FP32 CG, after every captured block the FP32 correction is
- * folded into the FP64 iterate and the FP64 residual replaces the FP32 one; systems stop
- * on that FP64 residual).  Returns the worst status over the systems. */
+ * name), advanced together: every kernel launch covers all systems (one CG iteration
+ * each), a fixed block of `iters_per_launch` iterations (0 -> 64; rounded up to even) is
+ * captured once as a hipGraph and replayed until every system has stopped.  circles_h
+ * holds nvar * nbody circles (system-major), psi_b_h receives nvar * nbody values,
+ * copfi_h (may be NULL) nvar values, stats_h (may be NULL) nvar entries.
+ * opts->precision: MFP_FP64 (CG, each system stops on its own residual) or MFP_FP32_IR
+ * (FP32 CG; after every block, at most 256 iterations, the FP32 correction is folded
+ * into the FP64 iterate, the FP64 residual replaces the FP32 one and the iteration
+ * restarts from it with its last direction kept; systems stop on that FP64 residual).
+ * Returns the worst status over the systems. */
 int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h, const mfp_circle* circles_h,
                           int32_t nbody, const mfp_flow* flow, const mfp_solver_opts* opts,
                           int32_t iters_per_launch, int32_t pair_lo, int32_t pair_hi,

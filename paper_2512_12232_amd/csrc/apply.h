@@ -229,66 +229,41 @@ struct ApplyArgs {
   const uint8_t* tplain;         // per task, 1: constant-stencil task
   const unsigned long long* tbody;  // per task: bodies among its owned nodes
   const int* tslot;              // per task: body-partial slot or -1
-  const T* src;                  // plain apply: p; fused: previous direction
-  const T* r;                    // fused: residual
-  T* pnew;                       // fused: new direction (written at owned nodes)
+  const T* src;                  // p (zero at halo nodes)
   T* q;                          // K p at free nodes (all in-domain nodes if write_all)
   double* part;                  // per-block partial of p.q over free nodes
   double* bpart;                 // per-slot, per-body partial sums of K p
-  const double* part2;           // fused: per-block partials of r.r from the update
-  int G2;                        // fused: number of those partials
-  long long k;                   // fused: iteration index
-  DevState* st;
   int nb;
   int write_all;
   T cC, cE, cN, cD;              // constant stencil (centre, east/west, north/south, diag)
   T ry;                          // hy / hx
   int G;                         // blocks of this apply (batched launches)
-  int kdev;                      // fused: iteration index from st->ka, directions by parity
-  T* pbuf0;                      // kdev: direction buffers (iteration k reads k&1)
-  T* pbuf1;
-  const int* skip;               // plain apply: return at once when *skip != 0
+  const int* skip;               // return at once when *skip != 0
 };
 
-// FUSED = false: q = K src.
-// FUSED = true: one CG iteration's first half.  Every block reduces the previous
-// update's r.r partials itself (identical order in every block, so identical
-// results), forms beta = r_k.r_k / r_{k-1}.r_{k-1} and the body directions, stops
-// the solve when the tolerance, kmax or a non-finite value is reached, and then forms
-// p = r + beta p_old (body nodes p_b, Dirichlet nodes 0) before applying K.
-// No grid-wide synchronisation inside the kernel: partial sums go to per-block slots
-// that the next kernel reduces.
+// q = K src, with per-block partials of src.q over free nodes and per-slot body sums.
 //
 // Work unit: a task is a 64-column strip x HC node rows; a wavefront takes a segment
 // of consecutive tasks of one strip from the work list (segments of about equal cost)
 // and marches upward through them.  The
 // two node rows that consecutive tasks share stay in registers, and the residual and
 // direction rows of the next task are requested before the current one is computed,
-// so every wavefront keeps a task's worth of loads in flight.  The first task's rows
-// and the segment's task flags are requested before the scalar reduction, so that
-// the two latencies overlap.
+// so every wavefront keeps a task's worth of loads in flight.
 // Constant-stencil tasks evaluate the assembled 9-point stencil with lane shifts for
 // the horizontal neighbours.  Other tasks march over the HC+1 cell rows touching their
 // rows: lane c evaluates cell (c, j) from its own nodes and those of lane c+1 (shifted
 // in), keeps the cell's contributions to its own column and shifts the contributions
 // to column c+1 over; node (c, j) is complete once cell rows j-1 and j are done.
-template <typename T, bool FUSED, int HC>
+template <typename T, int HC>
 __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk, const int G,
-                                           double* s_red, double* s_pb) {
+                                           double* s_red) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs;
   // vblk and blockIdx.x agree modulo 8)
   const int vb = (vblk & 7) * (G >> 3) + (vblk >> 3);
-  if (!FUSED && a.skip && *a.skip) return;
-  long long kk = a.k;
+  if (a.skip && *a.skip) return;
   const T* src = a.src;
-  T* pnew = a.pnew;
-  if (FUSED && a.kdev) {
-    kk = a.st->ka;
-    src = (kk & 1) ? a.pbuf1 : a.pbuf0;
-    pnew = (kk & 1) ? a.pbuf0 : a.pbuf1;
-  }
   const long long P = a.P;
   const int nstrip = a.nstrip;
   const bool owner = lane >= 1 && lane <= SW;
@@ -299,8 +274,8 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
   int m = 0, kc0 = 0, kc1 = 0;
   unsigned long long plain_mask = 0ull;
   int fl_body = 0, slot_l = -1;                // this lane's task (kc0 + lane)
-  T f0s = 0, f1s = 0, f0r = 0, f1r = 0;        // rows 0, 1 of the segment's first task
-  T ns[HC], nr[HC];                            // rows 2..HC+1 of the next task
+  T f0s = 0, f1s = 0;                          // rows 0, 1 of the segment's first task
+  T ns[HC];                                    // rows 2..HC+1 of the next task
   int8_t tg[HC + 2];                           // tags and displacements of the current
   T ddx[HC + 2], ddy[HC + 2];                  // task (tasks that evaluate geometry)
   int shift = 0;  // this lane's read column minus its own column (halo lanes)
@@ -328,14 +303,9 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
     const long long lb = base + shift;
     f0s = src[lb];
     f1s = src[lb + P];
-    if (FUSED) {
-      f0r = a.r[lb];
-      f1r = a.r[lb + P];
-    }
 #pragma unroll
     for (int r = 0; r < HC; ++r) {
       ns[r] = src[lb + (r + 2) * P];
-      if (FUSED) nr[r] = a.r[lb + (r + 2) * P];
     }
     // the first task's geometry travels with its rows
     if (!(plain_mask & 1ull)) load_geom(base);
@@ -346,64 +316,15 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
     loaded = true;
   }
 
-  T beta = (T)0;
-  if (FUSED) {
-    DevState* st = a.st;
-    const int cur = (int)(kk & 1), prv = cur ^ 1;
-    // every scalar this block needs is requested at once
-    const int done = st->done;
-    const double rb_rr = st->rb_rr[cur], rr_prv = st->rr[prv], rr_stop = st->rr_stop;
-    const long long kmax = st->kmax;
-    double rbv = 0.0, pbv = 0.0;
-    if (tid < a.nb) {
-      rbv = st->rb[cur][tid];
-      pbv = st->pb[prv][tid];
-    }
-    double sacc = 0.0;
-    for (int i = tid; i < a.G2; i += BLOCK) sacc += a.part2[i];
-    if (done) return;
-    const double rrk = block_sum(sacc, s_red) + rb_rr;
-    const double beta_d = rrk / rr_prv;
-    int code = 0;
-    if (!isfinite(rrk))
-      code = 2;
-    else if (rrk <= rr_stop)
-      code = 1;
-    else if (kk >= kmax)
-      code = 3;
-    if (code) {
-      if (vblk == 0 && tid == 0) {
-        st->done = code;
-        st->iters = kk;
-        st->rr_final = rrk;
-      }
-      return;
-    }
-    if (tid < a.nb) {
-      const double v = rbv + beta_d * pbv;
-      s_pb[tid] = v;
-      if (vblk == 0) st->pb[cur][tid] = v;
-    }
-    if (vblk == 0 && tid == 0) {
-      st->rr[cur] = rrk;
-      st->beta = beta_d;
-      st->ku = kk;
-    }
-    beta = (T)beta_d;
-    __syncthreads();
-  }
-
   double pq = 0.0;
   for (; s < a.tabsize; s += W) {
     if (!loaded) seg_load(s);  // later entries of this wavefront
     loaded = false;
     if (kc1 <= kc0) continue;
     const unsigned long long body_mask = __ballot(fl_body != 0);
-    T v[HC + 2];  // input vector (fused: new direction) at rows 0..HC+1 of the task
-    // the fused form combines every row as at a free node and corrects the other
-    // nodes once their tags are known
-    v[0] = FUSED ? f0r + beta * f0s : f0s;
-    v[1] = FUSED ? f1r + beta * f1s : f1s;
+    T v[HC + 2];  // input vector at rows 0..HC+1 of the task
+    v[0] = f0s;
+    v[1] = f1s;
     for (int kc = kc0; kc < kc1; ++kc) {
       const int it = kc - kc0;
       const bool first = kc == kc0;
@@ -412,36 +333,20 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
       const bool plain = (plain_mask >> it) & 1ull;
       // rows 2..HC+1 arrived with the previous prefetch
 #pragma unroll
-      for (int r = 0; r < HC; ++r) v[r + 2] = FUSED ? nr[r] + beta * ns[r] : ns[r];
+      for (int r = 0; r < HC; ++r) v[r + 2] = ns[r];
       // requested before the next task's rows, so that waiting for them does not wait
       // for the prefetch
       if (!plain && !first) load_geom(base);
       if (kc + 1 < kc1) {
         // rows 2..HC+1 of the next task: padded rows (kc+1)*HC + 2 ..
 #pragma unroll
-        for (int r = 0; r < HC; ++r) {
-          ns[r] = src[base + shift + (HC + 2 + r) * P];
-          if (FUSED) nr[r] = a.r[base + shift + (HC + 2 + r) * P];
-        }
+        for (int r = 0; r < HC; ++r) ns[r] = src[base + shift + (HC + 2 + r) * P];
       }
       T qr[HC];
       const bool bm = !plain && ((body_mask >> it) & 1ull);
       if (plain) {
         stencil_task<T, HC>(a.cC, a.cE, a.cN, a.cD, v, qr);
       } else {
-        if (FUSED) {
-          // body nodes carry p_b, Dirichlet and halo nodes 0 (rows 0 and 1 of a later
-          // task were corrected as rows HC and HC+1 of the previous one)
-#pragma unroll
-          for (int r = 0; r < HC + 2; ++r) {
-            if (r < 2 && !first) continue;
-            const int8_t t = tg[r];
-            if (t >= TAG_BODY0)
-              v[r] = (T)s_pb[t - TAG_BODY0];
-            else if (t != TAG_FREE)
-              v[r] = (T)0;
-          }
-        }
         march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
       }
       double bacc = 0.0;  // lane b accumulates body b of this task
@@ -451,7 +356,6 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
         const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
         const T qv = qr[r - 1];
         // every lane stores (the padding lanes zeros): whole aligned rows
-        if (FUSED) pnew[gi] = owner ? v[r] : (T)0;
         const bool keep = owner && ((g == TAG_FREE) || (a.write_all && g != TAG_HALO));
         a.q[gi] = keep ? qv : (T)0;
         if (owner && g == TAG_FREE) pq += (double)v[r] * (double)qv;
@@ -469,42 +373,40 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
   if (tid == 0) a.part[vblk] = bsum;
 }
 
-template <typename T, bool FUSED, int HC>
+template <typename T, int HC>
 __global__ void __launch_bounds__(BLOCK) k_apply(ApplyArgs<T> a) {
   __shared__ double s_red[WAVES];
-  __shared__ double s_pb[MFP_MAX_BODIES];
-  apply_core<T, FUSED, HC>(a, blockIdx.x, gridDim.x, s_red, s_pb);
+  apply_core<T, HC>(a, blockIdx.x, gridDim.x, s_red);
 }
 
 // Many independent systems in one launch: block b works for system map[b].x as its
 // virtual block map[b].y (each system's blocks start at a multiple of 8).
-template <typename T, bool FUSED, int HC>
+template <typename T, int HC>
 __global__ void __launch_bounds__(BLOCK) k_apply_batch(const ApplyArgs<T>* __restrict__ args,
                                                        const int2* __restrict__ map) {
   __shared__ double s_red[WAVES];
-  __shared__ double s_pb[MFP_MAX_BODIES];
   const int2 vm = map[blockIdx.x];
   const ApplyArgs<T>& a = args[vm.x];
-  apply_core<T, FUSED, HC>(a, vm.y, a.G, s_red, s_pb);
+  apply_core<T, HC>(a, vm.y, a.G, s_red);
 }
 
 // Launch the apply for the layout's task height.  With events, they are recorded by
 // the runtime at the start and end of this kernel's execution (hipExtLaunchKernel),
 // so their difference is the kernel's own duration.
-template <typename T, bool FUSED>
+template <typename T>
 inline void launch_apply(int hc, int G, hipStream_t st, const ApplyArgs<T>& a,
                          hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (e0) {
     if (hc == 4)
-      hipExtLaunchKernelGGL(k_apply<T, FUSED, 4>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+      hipExtLaunchKernelGGL(k_apply<T, 4>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
     else
-      hipExtLaunchKernelGGL(k_apply<T, FUSED, 8>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+      hipExtLaunchKernelGGL(k_apply<T, 8>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
     return;
   }
   if (hc == 4)
-    k_apply<T, FUSED, 4><<<G, BLOCK, 0, st>>>(a);
+    k_apply<T, 4><<<G, BLOCK, 0, st>>>(a);
   else
-    k_apply<T, FUSED, 8><<<G, BLOCK, 0, st>>>(a);
+    k_apply<T, 8><<<G, BLOCK, 0, st>>>(a);
 }
 
 // Per-body sums of the slot partials, into s_qb[0 .. nb); wave w handles bodies

@@ -1,19 +1,27 @@
 // Batched solves: many independent meshes (a delta-sweep of the same layout, uneven
 // sizes) advanced together.  Part of solve.hip's translation unit.
 //
-// Every kernel covers all systems: its blocks are dealt to the systems in proportion
-// to their size through a block map (block b -> (system, virtual block)), and each
-// system's arguments come from a per-system table in device memory.  The CG iteration
-// index and the parity of the direction buffers live in each system's device state,
-// so the launch sequence of a fixed number of iterations is the same every time: it
-// is captured once as a hipGraph and replayed until every system has stopped.
-// Systems that have stopped return at the top of every kernel.
+// Every kernel covers all systems: its blocks are dealt to the systems through a block
+// map (block b -> (system, virtual block); each system's blocks start at a multiple of
+// 8, so the XCD-aware order of the single solve holds per system), and each system's
+// arguments come from a per-system table in device memory.  The CG iteration is the
+// one-kernel iteration of step.h: a replayed block of m launches (m even) reads its
+// first launch index from each system's device state (jbase), the launch's offset in
+// the block is a captured argument, so the launch sequence of a block is the same
+// every time: it is captured once as a hipGraph and replayed until every system has
+// stopped.  Systems that have stopped return at the top of every kernel.  jbase is odd
+// at every replay, so the launches that update the iterate (odd indices) are the same
+// captured launches every time.
 //
-// MFP_FP64: plain FP64 CG for every system (stopping on each system's own residual).
-// MFP_FP32_IR: FP32 CG for every system; after each captured block of iterations
-// the FP32 correction is folded into the FP64 iterate, the residual is recomputed
-// with the FP64 apply and replaces the FP32 residual (the direction is kept), and the
-// stopping test is made on that FP64 residual.
+// MFP_FP64: FP64 CG for every system (stopping on each system's own residual); a block
+// is an even number m of launches and jbase advances by m.
+// MFP_FP32_IR: FP32 CG for every system; a block is an odd number m of launches, so
+// that its last launch J is odd and the FP32 correction is complete after it.  The
+// correction is folded into the FP64 iterate, the residual is recomputed with the FP64
+// apply, the stopping test is made on that FP64 residual, and launch J is run again as
+// the first launch of the next block: a restart that forms p_J from the new residual
+// and p_{J-1} with beta = |r_new|^2 / |r_{J-1}|^2, as the single solve's residual
+// replacement does (jbase advances by m - 1).
 #pragma once
 
 namespace mfp {
@@ -26,12 +34,14 @@ struct BElem {
   const double* g;      // Dirichlet lifting
   double* w64;          // out: g + T x
   const double* q64;    // K w64
-  float* r32;           // mixed: out, FP32 residual
-  double* r64;          // FP64: out, residual
-  double* part2;        // out: partials of the new residual norm^2 (r32 or r64)
+  float* r32;           // mixed: out, FP32 residual (parity slot 0)
+  double* r64;          // FP64: out, residual (parity slot 0)
+  double* spart;        // out: iteration-layout partials of the new residual (slot 0)
   double* part3;        // out: partials of q64.q64
   const double* bpart;  // body slots of the last plain apply
   const int* nslots;
+  double* p64[2];       // FP64 directions by parity (completion of the iterate)
+  float* p32[2];        // FP32 directions by parity
   DevState* out;        // mixed: FP64 body unknowns, refinement state
   DevState* in;         // CG state
   int G2;
@@ -39,13 +49,14 @@ struct BElem {
 };
 
 // mode 0: w = g + T x (FP64 CG; body values of the current iterate);
-// mode 1: x += e32, e32 = 0, then w with body values out->xb[0] + in->xb[ka & 1].
+// mode 1: x += e32, e32 = 0, then w with body values out->xb[0] + in->xb[iters & 1]
+//         (the inner correction of the last launch).
 __global__ void __launch_bounds__(BLOCK) k_b_formw(const BElem* __restrict__ bv,
                                                    const int2* __restrict__ map, int mode) {
   const int2 vm = map[blockIdx.x];
   const BElem& b = bv[vm.x];
   if (mode == 1 && b.out->done) return;
-  const double* xbi = mode == 1 ? b.in->xb[b.in->ka & 1] : b.in->xb[b.in->iters & 1];
+  const double* xbi = b.in->xb[b.in->iters & 1];
   const double* xbo = b.out->xb[0];
   for (long long e = vm.y * (long long)BLOCK + threadIdx.x; e < b.n;
        e += (long long)b.G2 * BLOCK) {
@@ -67,10 +78,10 @@ __global__ void __launch_bounds__(BLOCK) k_b_formw(const BElem* __restrict__ bv,
   }
 }
 
-// mode 0 (FP64 start): r64 = -q64, partials of r64^2 into part2 (and part3);
-// mode 1 (mixed refinement): r32 = -q64 rounded, partials of r32^2 (part2) and
-//   q64^2 (part3);
-// mode 2 (FP64 true residual): partials of q64^2 into part3 only.
+// r = -K w at free nodes (K w is zero elsewhere), per-block partials of r.r in the
+// iteration layout (r.r, 0, 0, 0) in slot 0, and of (K w).(K w).
+// mode 0 (FP64 start): r64; mode 1 (mixed refinement): r32 (rounded); mode 2 (FP64
+// true residual): partials only.
 __global__ void __launch_bounds__(BLOCK) k_b_resid(const BElem* __restrict__ bv,
                                                    const int2* __restrict__ map, int mode) {
   __shared__ double s_red[BLOCK / 64];
@@ -93,16 +104,18 @@ __global__ void __launch_bounds__(BLOCK) k_b_resid(const BElem* __restrict__ bv,
   }
   const double s2 = block_sum(a2, s_red);
   const double s3 = block_sum(a3, s_red);
-  if (threadIdx.x == 0) {
-    b.part2[vm.y] = s2;
-    b.part3[vm.y] = s3;
-  }
+  if (threadIdx.x < 4 && mode != 2) b.spart[4 * vm.y + threadIdx.x] = threadIdx.x == 0 ? s2 : 0.0;
+  if (threadIdx.x == 0) b.part3[vm.y] = s3;
 }
 
-// One block per system.  mode 0: FP64 CG start; mode 1: mixed refinement (init
-// marks the first one); mode 2: FP64 true residual.  flags[v] = stop code.
+// One block per system; rr = |b - A x|^2 from the partials of (K w).(K w) and the body
+// rows.  mode 0: FP64 start (fresh run from launch 1); mode 1: mixed refinement (init
+// marks the first one): fold the body corrections, test the FP64 residual, and set up
+// the restart of the block's last launch J (in->iters); mode 2: FP64 true residual.
+// flags[v] = stop code.
 __global__ void __launch_bounds__(BLOCK) k_b_fin(const BElem* __restrict__ bv, int mode, int init,
-                                                 double rtol2, int* __restrict__ flags) {
+                                                 double rtol2, long long kmax_abs,
+                                                 int* __restrict__ flags) {
   __shared__ double s_red[BLOCK / 64];
   __shared__ double s_qb[MFP_MAX_BODIES];
   const BElem& b = bv[blockIdx.x];
@@ -113,12 +126,8 @@ __global__ void __launch_bounds__(BLOCK) k_b_fin(const BElem* __restrict__ bv, i
     return;
   }
   body_sums(b.bpart, b.nslots, b.nb, s_qb);
-  double s2 = 0.0, s3 = 0.0;
-  for (int i = threadIdx.x; i < b.G2; i += BLOCK) {
-    s2 += b.part2[i];
-    s3 += b.part3[i];
-  }
-  s2 = block_sum(s2, s_red);
+  double s3 = 0.0;
+  for (int i = threadIdx.x; i < b.G2; i += BLOCK) s3 += b.part3[i];
   s3 = block_sum(s3, s_red);
   if (threadIdx.x != 0) return;
   const int nb = b.nb;
@@ -127,38 +136,41 @@ __global__ void __launch_bounds__(BLOCK) k_b_fin(const BElem* __restrict__ bv, i
     const double v = in->bb[k] - s_qb[k];
     rbr += v * v;
   }
-  if (mode == 0) {
-    for (int k = 0; k < nb; ++k) {
-      in->rb[0][k] = in->bb[k] - s_qb[k];
-      in->pb[1][k] = 0.0;
-    }
-    in->rb_rr[0] = rbr;
-    in->rr[1] = 1.0;
-    in->rr0 = s2 + rbr;
-    in->rr_stop = rtol2 * in->rr0;
+  const double rr = s3 + rbr;
+  auto fresh = [&]() {
+    for (int k = 0; k < nb; ++k) in->pb[0][k] = 0.0;
+    in->rr_prev = 0.0;
+    in->stop_rel = 0.0;
+    in->alpha_hist[0] = in->alpha_hist[1] = 0.0;
+    in->jbase = 1;
+    in->k0 = 1;
     in->iters = 0;
-    in->ka = 0;
-    in->done = in->rr0 > 0.0 ? 0 : 1;
+    in->kmax = kmax_abs;
+  };
+  if (mode == 0) {
+    for (int k = 0; k < nb; ++k) in->rb[0][k] = in->bb[k] - s_qb[k];
+    fresh();
+    in->rr0 = rr;
+    in->rr_stop = rtol2 * rr;
+    in->done = rr > 0.0 ? 0 : 1;
     flags[blockIdx.x] = in->done;
     return;
   }
   if (mode == 2) {
-    in->rr_true = s3 + rbr;
+    in->rr_true = rr;
     return;
   }
   // mixed refinement: fold the body corrections, record the FP64 residual
-  const int slot = (int)(in->ka & 1);
+  const long long J = in->iters;
   for (int k = 0; k < nb; ++k) {
-    out->xb[0][k] += in->xb[slot][k];
-    in->xb[slot][k] = 0.0;
+    out->xb[0][k] += in->xb[J & 1][k];
+    in->xb[0][k] = 0.0;  // the correction restarts from zero
+    in->xb[1][k] = 0.0;
   }
-  const double rr = s3 + rbr;
   out->rr_true = rr;
   if (init) {
     out->rr0 = rr;
-    for (int k = 0; k < nb; ++k) in->pb[1][k] = 0.0;
-    in->rr[1] = 1.0;
-    in->ka = 0;
+    fresh();
     in->rr_stop = -1.0;  // the FP32 recursion never stops the solve by itself
     in->done = 0;
     out->outer_count = 0;
@@ -172,124 +184,193 @@ __global__ void __launch_bounds__(BLOCK) k_b_fin(const BElem* __restrict__ bv, i
     code = 1;
   else if (in->done)
     code = in->done;
+  out->iters = J;
   if (code) {
     out->done = code;
     in->done = code;
-    out->iters = in->ka;
     for (int k = 0; k < nb; ++k) out->xb[1][k] = out->xb[0][k];
+  } else if (init) {
+    for (int k = 0; k < nb; ++k) in->rb[0][k] = in->bb[k] - s_qb[k];
   } else {
-    for (int k = 0; k < nb; ++k) in->rb[slot][k] = in->bb[k] - s_qb[k];
-    in->rb_rr[slot] = rbr;
+    // launch J again as a start: it reads slot (J-1)&1, where the new residual has
+    // replaced r_{J-1} (k_b_resid) and p_{J-1} is kept
+    const int prv = (int)((J - 1) & 1);
+    for (int k = 0; k < nb; ++k) in->rb[prv][k] = in->bb[k] - s_qb[k];
+    in->k0 = J;
+    in->rr_prev = in->rr[prv];  // |r_{J-1}|^2
+    in->alpha_hist[0] = in->alpha_hist[1] = 0.0;  // no direction pending in e
   }
   flags[blockIdx.x] = out->done;
 }
 
-// FP64 CG: flags[v] = stop code of system v.
-__global__ void k_b_flags(const BElem* __restrict__ bv, int nvar, int* __restrict__ flags) {
+// The iterate after the last launch J of each system (see k_finish): J = the launch
+// that stopped, or jbase + off for a system still running (off = m - 1 inside a
+// replay, -1 after the replays), whose x lacks alpha_{J-1} p_{J-1} when J is even
+// (an odd J leaves it complete).  Block 0 of each system records J in iters.
+// mode 1: FP32 correction of a mixed solve.
+template <typename T>
+__global__ void __launch_bounds__(BLOCK) k_b_finish(const BElem* __restrict__ bv,
+                                                    const int2* __restrict__ map, int off,
+                                                    int mode) {
+  const int2 vm = map[blockIdx.x];
+  const BElem& b = bv[vm.x];
+  if (mode == 1 && b.out->done) return;
+  DevState* in = b.in;
+  const bool stopped = in->done != 0;
+  const long long J = stopped ? in->iters : in->jbase + off;
+  if (vm.y == 0 && threadIdx.x == 0) in->iters = J;  // same value if stopped
+  if (!stopped && (J & 1)) return;
+  T* x;
+  const T* p0;
+  const T* p1;
+  if constexpr (sizeof(T) == 8) {
+    x = b.x64;
+    p0 = b.p64[0];
+    p1 = b.p64[1];
+  } else {
+    x = b.e32;
+    p0 = b.p32[0];
+    p1 = b.p32[1];
+  }
+  const T a1 = (T)in->alpha;
+  const bool two = ((J - 1) & 1) == 0;
+  const T a2 = two ? (T)in->alpha_hist[(J - 1) & 1] : (T)0;
+  const T* pa = ((J - 1) & 1) ? p1 : p0;
+  const T* pb = (J & 1) ? p1 : p0;
+  for (long long e = vm.y * (long long)BLOCK + threadIdx.x; e < b.n;
+       e += (long long)b.G2 * BLOCK)
+    x[e] = (x[e] + a2 * pb[e]) + a1 * pa[e];
+}
+
+// End of a replayed block: next block's first launch (adv = m, or m - 1 when the
+// block's last launch is run again as a restart); FP64: flags[v] = stop code.
+__global__ void k_b_advance(const BElem* __restrict__ bv, int nvar, int adv, int fp64,
+                            int* __restrict__ flags) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v < nvar) flags[v] = bv[v].in->done;
+  if (v >= nvar) return;
+  DevState* in = bv[v].in;
+  if (!in->done) in->jbase += adv;
+  if (fp64) flags[v] = in->done;
 }
 
 struct BatchPlan {
-  int nvar = 0, nb = 0, hc = 4, precision = MFP_FP64;
+  int nvar = 0, nb = 0, precision = MFP_FP64;
   std::vector<SolveWs> w;
-  std::vector<int> G, G2;
-  int totG = 0, totG2 = 0;
-  ApplyArgs<float>* a32 = nullptr;
-  UpdArgs<float>* u32 = nullptr;
+  std::vector<int> G, G2, GS;   // blocks: residual apply, streaming kernels, iteration
+  int totG = 0, totG2 = 0, totGS = 0;
   ApplyArgs<double>* a64 = nullptr;   // plain FP64 apply (residuals)
-  ApplyArgs<double>* af64 = nullptr;  // fused FP64 apply (FP64 CG)
-  UpdArgs<double>* u64 = nullptr;
+  StepArgs<double>* s64 = nullptr;    // FP64 iteration
+  StepArgs<float>* s32 = nullptr;     // FP32 iteration
   BElem* be = nullptr;
   int2* amap = nullptr;
   int2* umap = nullptr;
+  int2* smap = nullptr;
   int* flags = nullptr;
   size_t bytes = 0;
 };
 
-// Tasks per wavefront segment (on average, by cost) in batched applies: the launch
-// holds many systems, so segments are sized for the prefetch, not for residency.
+// Tasks per wavefront segment (on average, by cost) in batched residual applies: the
+// launch holds many systems, so segments are sized for the prefetch, not for residency.
 constexpr int BATCH_SEG = 4;
+// Tasks per wavefront of the batched iteration (its launch holds many systems).
+constexpr int BATCH_TPW = 2;
 
-static int batch_hc(int nvar, const mfp_variant* v) {
-  int hc = 4;
-  for (int i = 0; i < nvar; ++i)
-    if (make_layout(v[i].grid.nx, v[i].grid.ny).hc == 8) hc = 8;
-  return hc;
+static int batch_step_blocks(const Layout& L) {
+  long long g = ((long long)L.ntasks() + WAVES * BATCH_TPW - 1) / (WAVES * BATCH_TPW);
+  g = (g + 7) & ~7LL;
+  if (g > 1024) g = 1024;
+  return (int)g;
 }
 
 static size_t batch_layout(int nvar, const mfp_variant* v, int nb, int precision, void* base,
                            BatchPlan* P) {
   Bump bp(base);
-  const int hc = batch_hc(nvar, v);
   if (P) {
     P->nvar = nvar;
     P->nb = nb;
-    P->hc = hc;
     P->precision = precision;
     P->w.resize(nvar);
     P->G.resize(nvar);
     P->G2.resize(nvar);
+    P->GS.resize(nvar);
   }
-  int totG = 0, totG2 = 0;
+  int totG = 0, totG2 = 0, totGS = 0;
   for (int i = 0; i < nvar; ++i) {
-    const size_t sz = solve_layout(&v[i].grid, nb, precision, nullptr, nullptr, hc);
+    const size_t sz = solve_layout(&v[i].grid, nb, precision, nullptr, nullptr);
     char* b = bp.take<char>(sz);
     SolveWs w;
-    solve_layout(&v[i].grid, nb, precision, b, &w, hc);
+    solve_layout(&v[i].grid, nb, precision, b, &w);
     w.sp = seg_plan(w.L, (w.L.ntasks() + BATCH_SEG - 1) / BATCH_SEG);
     const int G = w.sp.G;
     const int G2 = grid_blocks(w.L.n);
+    const int GS = batch_step_blocks(w.L);
     if (P) {
       P->w[i] = w;
       P->G[i] = G;
       P->G2[i] = G2;
+      P->GS[i] = GS;
     }
     totG += G;
     totG2 += G2;
+    totGS += GS;
   }
   if (P) {
     P->totG = totG;
     P->totG2 = totG2;
+    P->totGS = totGS;
   }
-  auto a32 = bp.take<ApplyArgs<float>>(nvar);
-  auto u32 = bp.take<UpdArgs<float>>(nvar);
   auto a64 = bp.take<ApplyArgs<double>>(nvar);
-  auto af64 = bp.take<ApplyArgs<double>>(nvar);
-  auto u64 = bp.take<UpdArgs<double>>(nvar);
+  auto s64 = bp.take<StepArgs<double>>(nvar);
+  auto s32 = bp.take<StepArgs<float>>(nvar);
   auto be = bp.take<BElem>(nvar);
   auto amap = bp.take<int2>(totG);
   auto umap = bp.take<int2>(totG2);
+  auto smap = bp.take<int2>(totGS);
   auto flags = bp.take<int>(nvar);
   if (P) {
-    P->a32 = a32;
-    P->u32 = u32;
     P->a64 = a64;
-    P->af64 = af64;
-    P->u64 = u64;
+    P->s64 = s64;
+    P->s32 = s32;
     P->be = be;
     P->amap = amap;
     P->umap = umap;
+    P->smap = smap;
     P->flags = flags;
     P->bytes = bp.off + 256;
   }
   return bp.off + 256;
 }
 
+// Arguments of a system's batched iteration: the single solve's arguments with the
+// parity slots filled in and the launch index taken from the device state.
 template <typename T>
-static void launch_apply_batch(int hc, int G, hipStream_t st, const ApplyArgs<T>* args,
-                               const int2* map, bool fused) {
-  if (hc == 4) {
-    if (fused)
-      k_apply_batch<T, true, 4><<<G, BLOCK, 0, st>>>(args, map);
-    else
-      k_apply_batch<T, false, 4><<<G, BLOCK, 0, st>>>(args, map);
-  } else {
-    if (fused)
-      k_apply_batch<T, true, 8><<<G, BLOCK, 0, st>>>(args, map);
-    else
-      k_apply_batch<T, false, 8><<<G, BLOCK, 0, st>>>(args, map);
+static StepArgs<T> batch_step_args(const SolveWs& w, const mfp_grid& g, int nb, int GS,
+                                   int npart0, const T* dx, const T* dy, T* r0, T* r1, T* p0,
+                                   T* p1, T* q0, T* q1, T* x, DevState* st) {
+  StepRun<T> run = make_step_run<T>(w, g, nb, dx, dy, r0, r1, p0, p1, q0, q1, x, st);
+  StepArgs<T> a = run.a;
+  a.kdev = 1;
+  a.G = GS;
+  a.stream = 0;
+  a.npart0 = npart0;
+  for (int s = 0; s < 2; ++s) {
+    a.rs[s] = run.r[s];
+    a.ps[s] = run.p[s];
+    a.qs[s] = run.q[s];
+    a.parts[s] = run.part[s];
+    a.bparts[s] = run.bpart[s];
   }
+  return a;
+}
+
+template <typename T>
+static void launch_step_batch(int G, hipStream_t st, const StepArgs<T>* args, const int2* map,
+                              int koff) {
+  // launch jbase + koff is odd (jbase is odd) for even koff: those update the iterate
+  if ((koff & 1) == 0)
+    k_step_batch<T, true><<<G, BLOCK, 0, st>>>(args, map, koff);
+  else
+    k_step_batch<T, false><<<G, BLOCK, 0, st>>>(args, map, koff);
 }
 
 }  // namespace mfp
@@ -340,95 +421,52 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   batch_layout(nvar, vars_h, nbody, opts->precision, ws, &P);
   const int nb = nbody;
   const bool mixed = opts->precision == MFP_FP32_IR;
-  const int m = iters_per_launch > 0 ? iters_per_launch : 64;
+  // launches per replay: FP64 an even number (jbase advances by m), mixed an odd one
+  // (its last launch is run again as the restart: jbase advances by m - 1), so that
+  // jbase stays odd and every replay has the same launch parities (the captured
+  // kernel instances depend on them)
+  int m = iters_per_launch > 0 ? iters_per_launch : 64;
+  m += m & 1;
+  // an unrefined FP32 run loses its accuracy (and can break down) after a few hundred
+  // iterations
+  if (mixed && m > 256) m = 256;
+  if (mixed) m += 1;
+  const int adv = mixed ? m - 1 : m;
   const double rtol2 = opts->rtol * opts->rtol;
 
   // per-system setup and argument tables
-  std::vector<ApplyArgs<float>> ha32(nvar);
-  std::vector<UpdArgs<float>> hu32(nvar);
-  std::vector<ApplyArgs<double>> ha64(nvar), haf64(nvar);
-  std::vector<UpdArgs<double>> hu64(nvar);
+  std::vector<ApplyArgs<double>> ha64(nvar);
+  std::vector<StepArgs<double>> hs64(nvar);
+  std::vector<StepArgs<float>> hs32(nvar);
   std::vector<BElem> hbe(nvar);
-  std::vector<int2> hamap, humap;
+  std::vector<int2> hamap, humap, hsmap;
   hamap.reserve(P.totG);
   humap.reserve(P.totG2);
+  hsmap.reserve(P.totGS);
+  const long long kmax_abs = 1 + opts->kmax;
   for (int i = 0; i < nvar; ++i) {
     const mfp_grid& g = vars_h[i].grid;
     const SolveWs& w = P.w[i];
     const mfp_circle* ci = circles_h + (size_t)i * nb;
     MFP_TRY(setup(g, ci, nb, vars_h[i].disp, vars_h[i].body, flow, opts->precision, w, st));
-    long long kmax = opts->kmax;
-    MFP_TRY_HIP(hipMemcpyAsync(&w.st->kmax, &kmax, sizeof(long long), hipMemcpyHostToDevice, st));
-    MFP_TRY_HIP(hipMemcpyAsync(&w.st2->kmax, &kmax, sizeof(long long), hipMemcpyHostToDevice, st));
-    MFP_TRY_HIP(hipStreamSynchronize(st));  // kmax is a stack value
-    const int G = P.G[i], G2 = P.G2[i];
+    MFP_TRY_HIP(hipMemcpyAsync(&w.nslots_h, w.nslots, sizeof(int), hipMemcpyDeviceToHost, st));
+    MFP_TRY_HIP(hipStreamSynchronize(st));  // slot count
+    const int G = P.G[i], G2 = P.G2[i], GS = P.GS[i];
     for (int b = 0; b < G; ++b) hamap.push_back(make_int2(i, b));
     for (int b = 0; b < G2; ++b) humap.push_back(make_int2(i, b));
+    for (int b = 0; b < GS; ++b) hsmap.push_back(make_int2(i, b));
     // plain FP64 apply on w (residuals)
     ApplyArgs<double> a = make_apply_args<double>(w, g, nb, w.dx, w.dy);
     a.src = w.p0;
     a.q = w.q;
-    a.G = G;
     a.skip = mixed ? &w.st->done : nullptr;
     ha64[i] = a;
-    // fused FP64 CG apply
-    ApplyArgs<double> af = make_apply_args<double>(w, g, nb, w.dx, w.dy);
-    af.r = w.r;
-    af.q = w.q;
-    af.part2 = w.part2;
-    af.G2 = G2;
-    af.G = G;
-    af.kdev = 1;
-    af.pbuf0 = w.p0;
-    af.pbuf1 = w.p1;
-    haf64[i] = af;
-    UpdArgs<double> u{};
-    u.n = w.L.n;
-    u.x = w.x;
-    u.r = w.r;
-    u.q = w.q;
-    u.part = w.part;
-    u.G = G;
-    u.bpart = w.bpart;
-    u.nslots = w.nslots;
-    u.part2 = w.part2;
-    u.st = w.st;
-    u.nb = nb;
-    u.G2 = G2;
-    u.kdev = 1;
-    u.pbuf0 = w.p0;
-    u.pbuf1 = w.p1;
-    hu64[i] = u;
-    if (mixed) {
-      ApplyArgs<float> a3 = make_apply_args<float>(w, g, nb, w.dxf, w.dyf);
-      a3.r = w.rf;
-      a3.q = w.qf;
-      a3.part2 = w.part2;
-      a3.G2 = G2;
-      a3.G = G;
-      a3.kdev = 1;
-      a3.pbuf0 = w.p0f;
-      a3.pbuf1 = w.p1f;
-      a3.st = w.st2;
-      ha32[i] = a3;
-      UpdArgs<float> u3{};
-      u3.n = w.L.n;
-      u3.x = w.xf;
-      u3.r = w.rf;
-      u3.q = w.qf;
-      u3.part = w.part;
-      u3.G = G;
-      u3.bpart = w.bpart;
-      u3.nslots = w.nslots;
-      u3.part2 = w.part2;
-      u3.st = w.st2;
-      u3.nb = nb;
-      u3.G2 = G2;
-      u3.kdev = 1;
-      u3.pbuf0 = w.p0f;
-      u3.pbuf1 = w.p1f;
-      hu32[i] = u3;
-    }
+    if (mixed)
+      hs32[i] = batch_step_args<float>(w, g, nb, GS, G2, w.dxf, w.dyf, w.rf, w.r1f, w.p0f, w.p1f,
+                                       w.qf, w.q1f, w.xf, w.st2);
+    else
+      hs64[i] = batch_step_args<double>(w, g, nb, GS, G2, w.dx, w.dy, w.r, w.r1, w.p0, w.p1, w.q,
+                                        w.q1, w.x, w.st);
     BElem be{};
     be.n = w.L.n;
     be.tag = w.tag;
@@ -439,10 +477,14 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
     be.q64 = w.q;
     be.r32 = mixed ? w.rf : nullptr;
     be.r64 = w.r;
-    be.part2 = w.part2;
+    be.spart = w.spart;
     be.part3 = w.part3;
     be.bpart = w.bpart;
     be.nslots = w.nslots;
+    be.p64[0] = w.p0;
+    be.p64[1] = w.p1;
+    be.p32[0] = mixed ? w.p0f : nullptr;
+    be.p32[1] = mixed ? w.p1f : nullptr;
     be.out = w.st;
     be.in = mixed ? w.st2 : w.st;
     be.G2 = G2;
@@ -450,15 +492,14 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
     hbe[i] = be;
   }
   MFP_TRY_HIP(hipMemcpyAsync(P.a64, ha64.data(), sizeof(ApplyArgs<double>) * nvar, hipMemcpyHostToDevice, st));
-  MFP_TRY_HIP(hipMemcpyAsync(P.af64, haf64.data(), sizeof(ApplyArgs<double>) * nvar, hipMemcpyHostToDevice, st));
-  MFP_TRY_HIP(hipMemcpyAsync(P.u64, hu64.data(), sizeof(UpdArgs<double>) * nvar, hipMemcpyHostToDevice, st));
-  if (mixed) {
-    MFP_TRY_HIP(hipMemcpyAsync(P.a32, ha32.data(), sizeof(ApplyArgs<float>) * nvar, hipMemcpyHostToDevice, st));
-    MFP_TRY_HIP(hipMemcpyAsync(P.u32, hu32.data(), sizeof(UpdArgs<float>) * nvar, hipMemcpyHostToDevice, st));
-  }
+  if (mixed)
+    MFP_TRY_HIP(hipMemcpyAsync(P.s32, hs32.data(), sizeof(StepArgs<float>) * nvar, hipMemcpyHostToDevice, st));
+  else
+    MFP_TRY_HIP(hipMemcpyAsync(P.s64, hs64.data(), sizeof(StepArgs<double>) * nvar, hipMemcpyHostToDevice, st));
   MFP_TRY_HIP(hipMemcpyAsync(P.be, hbe.data(), sizeof(BElem) * nvar, hipMemcpyHostToDevice, st));
   MFP_TRY_HIP(hipMemcpyAsync(P.amap, hamap.data(), sizeof(int2) * hamap.size(), hipMemcpyHostToDevice, st));
   MFP_TRY_HIP(hipMemcpyAsync(P.umap, humap.data(), sizeof(int2) * humap.size(), hipMemcpyHostToDevice, st));
+  MFP_TRY_HIP(hipMemcpyAsync(P.smap, hsmap.data(), sizeof(int2) * hsmap.size(), hipMemcpyHostToDevice, st));
   MFP_TRY_HIP(hipStreamSynchronize(st));  // host tables above
 
   hipEvent_t e0, e1;
@@ -467,13 +508,10 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   MFP_TRY_HIP(hipEventRecord(e0, st));
   // start: residual of x = 0 for every system
   k_b_formw<<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, mixed ? 1 : 0);
-  launch_apply_batch<double>(P.hc, P.totG, st, P.a64, P.amap, false);
+  k_apply_batch<double, 4><<<P.totG, BLOCK, 0, st>>>(P.a64, P.amap);
   k_b_resid<<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, mixed ? 1 : 0);
-  k_b_fin<<<nvar, BLOCK, 0, st>>>(P.be, mixed ? 1 : 0, 1, rtol2, P.flags);
+  k_b_fin<<<nvar, BLOCK, 0, st>>>(P.be, mixed ? 1 : 0, 1, rtol2, kmax_abs, P.flags);
   MFP_TRY_HIP(hipGetLastError());
-  if (!mixed)
-    for (int i = 0; i < nvar; ++i)
-      MFP_TRY_HIP(hipMemsetAsync(P.w[i].p0, 0, sizeof(double) * P.w[i].L.n, st));
 
   // capture m iterations (+ the FP64 refinement) once, replay until all systems stop
   hipStream_t cs;
@@ -484,22 +522,19 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   hipError_t he = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
   if (he == hipSuccess) {
     for (int k = 0; k < m; ++k) {
-      if (mixed) {
-        launch_apply_batch<float>(P.hc, P.totG, cs, P.a32, P.amap, true);
-        k_update_batch<float><<<P.totG2, BLOCK, 0, cs>>>(P.u32, P.umap);
-      } else {
-        launch_apply_batch<double>(P.hc, P.totG, cs, P.af64, P.amap, true);
-        k_update_batch<double><<<P.totG2, BLOCK, 0, cs>>>(P.u64, P.umap);
-      }
+      if (mixed)
+        launch_step_batch<float>(P.totGS, cs, P.s32, P.smap, k);
+      else
+        launch_step_batch<double>(P.totGS, cs, P.s64, P.smap, k);
     }
     if (mixed) {
+      k_b_finish<float><<<P.totG2, BLOCK, 0, cs>>>(P.be, P.umap, m - 1, 1);
       k_b_formw<<<P.totG2, BLOCK, 0, cs>>>(P.be, P.umap, 1);
-      launch_apply_batch<double>(P.hc, P.totG, cs, P.a64, P.amap, false);
+      k_apply_batch<double, 4><<<P.totG, BLOCK, 0, cs>>>(P.a64, P.amap);
       k_b_resid<<<P.totG2, BLOCK, 0, cs>>>(P.be, P.umap, 1);
-      k_b_fin<<<nvar, BLOCK, 0, cs>>>(P.be, 1, 0, rtol2, P.flags);
-    } else {
-      k_b_flags<<<(nvar + 255) / 256, 256, 0, cs>>>(P.be, nvar, P.flags);
+      k_b_fin<<<nvar, BLOCK, 0, cs>>>(P.be, 1, 0, rtol2, kmax_abs, P.flags);
     }
+    k_b_advance<<<(nvar + 255) / 256, 256, 0, cs>>>(P.be, nvar, adv, mixed ? 0 : 1, P.flags);
     he = hipStreamEndCapture(cs, &graph);
   }
   if (he == hipSuccess) he = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -509,7 +544,7 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   }
   std::vector<int> hflags(nvar, 0);
   long long launches = 0;
-  const long long max_launches = (opts->kmax + m - 1) / m + 1;
+  const long long max_launches = (opts->kmax + adv - 1) / adv + 1;
   while (status == MFP_OK) {
     he = hipGraphLaunch(exec, st);
     if (he == hipSuccess) he = hipMemcpyAsync(hflags.data(), P.flags, sizeof(int) * nvar, hipMemcpyDeviceToHost, st);
@@ -530,15 +565,16 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   if (status != MFP_OK) return status;
   MFP_TRY_HIP(hipEventRecord(e1, st));
   if (!mixed) {
-    // true residual of every system
+    // complete the iterates, then the true residual of every system
+    k_b_finish<double><<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, -1, 0);
     k_b_formw<<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, 0);
-    launch_apply_batch<double>(P.hc, P.totG, st, P.a64, P.amap, false);
+    k_apply_batch<double, 4><<<P.totG, BLOCK, 0, st>>>(P.a64, P.amap);
     k_b_resid<<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, 2);
-    k_b_fin<<<nvar, BLOCK, 0, st>>>(P.be, 2, 0, rtol2, P.flags);
+    k_b_fin<<<nvar, BLOCK, 0, st>>>(P.be, 2, 0, rtol2, kmax_abs, P.flags);
     MFP_TRY_HIP(hipGetLastError());
   }
   // outputs
-  std::vector<DevState> hs(nvar), hin(nvar);
+  std::vector<DevState> hs(nvar);
   for (int i = 0; i < nvar; ++i) {
     const mfp_grid& g = vars_h[i].grid;
     const SolveWs& w = P.w[i];
@@ -555,8 +591,6 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
                                                    ylo, yhi);
     }
     MFP_TRY_HIP(hipMemcpyAsync(&hs[i], w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
-    if (mixed)
-      MFP_TRY_HIP(hipMemcpyAsync(&hin[i], w.st2, sizeof(DevState), hipMemcpyDeviceToHost, st));
   }
   MFP_TRY_HIP(hipGetLastError());
   MFP_TRY_HIP(hipStreamSynchronize(st));
@@ -567,22 +601,24 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   int worst = MFP_OK;
   for (int i = 0; i < nvar; ++i) {
     const DevState& s = hs[i];
-    const long long it = s.iters;
-    const double* xb = s.xb[it & 1];
+    const long long J = s.iters;
+    const double* xb = s.xb[J & 1];
     for (int b = 0; b < nb; ++b) psi_b_h[(size_t)i * nb + b] = xb[b];
     if (copfi_h && pair_lo >= 0 && pair_hi >= 0) {
       const mfp_circle* ci = circles_h + (size_t)i * nb;
       copfi_h[i] = (xb[pair_hi] - xb[pair_lo]) / (flow->U * (ci[pair_hi].cy - ci[pair_lo].cy));
     }
-    const int code = mixed ? s.done : s.done;
+    const int code = s.done;
     if (code == 2) worst = MFP_E_BREAKDOWN;
     if ((code == 3 || code == 0) && worst == MFP_OK) worst = MFP_W_NOCONV;
     if (stats_h) {
       mfp_stats& o = stats_h[i];
       std::memset(&o, 0, sizeof(o));
-      o.iters = it;
+      // CG steps: launches 2..J (a restart runs launch J again, without a step)
+      o.iters = J > 1 ? J - 1 : 0;
       o.outer_iters = mixed ? s.outer_count : 0;
-      o.applies = it + (mixed ? s.outer_count + 1 : 2);
+      // element applies: the steps, the restarts and the FP64 residuals
+      o.applies = o.iters + (mixed ? 2 * s.outer_count + 1 : 2);
       o.rnorm0 = std::sqrt(s.rr0);
       o.relres_true = s.rr0 > 0 ? std::sqrt(s.rr_true / s.rr0) : 0.0;
       o.solve_ms = ms;

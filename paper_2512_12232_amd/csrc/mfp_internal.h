@@ -139,13 +139,13 @@ struct DevState {
   double alpha, beta, pq;
   double rr_prev;                        // one-kernel CG: |r|^2 before a restart (0: fresh)
   double alpha_hist[2];                  // one-kernel CG: alpha_{k-1} computed by launch k, slot k&1
+  long long jbase;                       // batched one-kernel CG: first launch of the replay
+  long long k0;                          // batched one-kernel CG: start launch of the run
   double stop_rel;                       // one-kernel CG: threshold / start |r|^2 (0: use rr_stop)
   double copfi, Q;
   long long iters;                       // index of the final iterate once done != 0
   long long kmax;
   long long outer_count;                 // batched mixed solves: FP64 refinements so far
-  long long ka;                          // batched: index of the next apply's iteration
-  long long ku;                          // batched: index of the next update's iteration
   int done;                              // 0 running, 1 converged, 2 breakdown, 3 kmax
   int pad_;
 };

@@ -9,12 +9,10 @@
 //   (A p)_free = (K p)_free and (A p)_b = sum over the nodes of body b of (K p)_n,
 // which is Algorithm 1's assembly of element results into r (interior nodes) and rb
 // (body DOFs), and p.Ap = sum_free p (Kp) + sum_b p_b (Ap)_b.
-// A single solve runs one kernel per CG iteration (k_step, step.h).  The batched
-// solver runs two per iteration:
-//   k_apply<FUSED>  p = r + beta p_old (body nodes p_b), q = K p, partial p.q;
-//   k_update        alpha, x += alpha p, r -= alpha q, partial r.r;
-// each block of a kernel reduces the previous kernel's per-block partials itself.
-// Scalars never leave the device; the host polls a done flag every few iterations.
+// Every solve runs one kernel per CG iteration (k_step, step.h; the batched solver
+// runs it for many systems per launch, batch.h); each block reduces the previous
+// launch's per-block partials itself.  Scalars never leave the device; the host polls
+// a done flag every few iterations.
 #include <cmath>
 #include <cstring>
 #include <type_traits>
@@ -380,138 +378,6 @@ __global__ void k_ir_update(long long n, double* __restrict__ x64, float* __rest
   }
 }
 
-template <typename T>
-struct UpdArgs {
-  long long n;
-  T* x;
-  const T* p;           // direction of this iteration (kdev: chosen by parity)
-  T* r;
-  const T* q;
-  const double* part;   // apply partials of p.q
-  int G;                // number of those
-  const double* bpart;  // apply body slots
-  const int* nslots;
-  double* part2;        // out: partials of r.r
-  DevState* st;
-  int nb;
-  long long k;
-  int G2;               // blocks of this update (batched launches)
-  int kdev;             // iteration index from st->ku, direction by parity
-  const T* pbuf0;
-  const T* pbuf1;
-};
-
-// Second half of CG iteration k: every block sums the apply's body slots and p.q
-// partials itself, forms alpha = r.r / p.Ap (breakdown stops the solve), block 0
-// advances the body unknowns, and all blocks stream x += alpha p, r -= alpha q with
-// per-block partials of the new r.r.  Two elements per thread and step.
-template <typename T>
-__device__ __forceinline__ void update_core(const UpdArgs<T>& u, const int vblk, const int G2,
-                                            double* s_red, double* s_qb) {
-  using T2 = typename std::conditional<sizeof(T) == 8, double2, float2>::type;
-  DevState* st = u.st;
-  long long k = u.k;
-  const T* p = u.p;
-  if (u.kdev) {
-    k = st->ku;
-    p = ((k + 1) & 1) ? u.pbuf1 : u.pbuf0;
-  }
-  const long long n2 = u.n >> 1;
-  const long long stride = (long long)G2 * blockDim.x;
-  long long e = vblk * (long long)blockDim.x + threadIdx.x;
-  T2* x2 = reinterpret_cast<T2*>(u.x);
-  T2* r2 = reinterpret_cast<T2*>(u.r);
-  const T2* p2 = reinterpret_cast<const T2*>(p);
-  const T2* q2 = reinterpret_cast<const T2*>(u.q);
-  // first operands in flight while the scalars are formed
-  T2 xv{}, pv{}, rv{}, qv{};
-  if (e < n2) {
-    xv = x2[e];
-    pv = p2[e];
-    rv = r2[e];
-    qv = q2[e];
-  }
-  const int cur = (int)(k & 1), nxt = cur ^ 1;
-  const int nb = u.nb;
-  // every scalar this block needs is requested at once
-  const int done = st->done;
-  const double rr_cur = st->rr[cur];
-  double pbv = 0.0, xbv = 0.0, rbv = 0.0;
-  if (threadIdx.x < nb) {
-    pbv = st->pb[cur][threadIdx.x];
-    xbv = st->xb[cur][threadIdx.x];
-    rbv = st->rb[cur][threadIdx.x];
-  }
-  double s = 0.0;
-  for (int i = threadIdx.x; i < u.G; i += BLOCK) s += u.part[i];
-  body_sums(u.bpart, u.nslots, nb, s_qb);
-  if (done) return;
-  if (threadIdx.x < nb) s += pbv * s_qb[threadIdx.x];
-  const double pq = block_sum(s, s_red);
-  if (!(pq > 0.0) || !isfinite(pq)) {
-    if (vblk == 0 && threadIdx.x == 0) {
-      st->done = 2;
-      st->iters = k;
-      st->pq = pq;
-    }
-    return;
-  }
-  const double alpha_d = rr_cur / pq;
-  if (vblk == 0 && threadIdx.x < 64) {
-    // wavefront 0 of block 0 advances the body unknowns (nb <= 64)
-    double rbn = 0.0;
-    if (threadIdx.x < nb) {
-      st->xb[nxt][threadIdx.x] = xbv + alpha_d * pbv;
-      rbn = rbv - alpha_d * s_qb[threadIdx.x];
-      st->rb[nxt][threadIdx.x] = rbn;
-    }
-    const double rbr = wave_sum(rbn * rbn);
-    if (threadIdx.x == 0) {
-      st->rb_rr[nxt] = rbr;
-      st->alpha = alpha_d;
-      st->pq = pq;
-      st->ka = k + 1;
-    }
-  }
-  const T alpha = (T)alpha_d;
-  double acc = 0.0;
-  for (; e < n2; e += stride) {
-    const long long en = e + stride;
-    T2 xn{}, pn{}, rn{}, qn{};
-    if (en < n2) {
-      xn = x2[en];
-      pn = p2[en];
-      rn = r2[en];
-      qn = q2[en];
-    }
-    T2 ro, xo;
-    ro.x = rv.x - alpha * qv.x;
-    ro.y = rv.y - alpha * qv.y;
-    xo.x = xv.x + alpha * pv.x;
-    xo.y = xv.y + alpha * pv.y;
-    x2[e] = xo;
-    r2[e] = ro;
-    acc += (double)ro.x * (double)ro.x + (double)ro.y * (double)ro.y;
-    xv = xn;
-    pv = pn;
-    rv = rn;
-    qv = qn;
-  }
-  const double bs = block_sum(acc, s_red);
-  if (threadIdx.x == 0) u.part2[vblk] = bs;
-}
-
-
-template <typename T>
-__global__ void __launch_bounds__(BLOCK) k_update_batch(const UpdArgs<T>* __restrict__ args,
-                                                        const int2* __restrict__ map) {
-  __shared__ double s_red[BLOCK / 64];
-  __shared__ double s_qb[MFP_MAX_BODIES];
-  const int2 vm = map[blockIdx.x];
-  const UpdArgs<T>& u = args[vm.x];
-  update_core<T>(u, vm.y, u.G2, s_red, s_qb);
-}
-
 // psi (unpadded) from the padded unknowns; Q and CoPFI from the pair.
 __global__ void k_output(Layout L, int nx, int ny, const int8_t* __restrict__ tag,
                          const double* __restrict__ x, const double* __restrict__ g,
@@ -822,7 +688,6 @@ static ApplyArgs<T> make_apply_args(const SolveWs& w, const mfp_grid& g, int nb,
   a.tslot = w.tslot;
   a.part = w.part;
   a.bpart = w.bpart;
-  a.st = w.st;
   a.nb = nb;
   const double hx = grid_hx(g), hy = grid_hy(g);
   const double rr = hy / hx, qq = hx / hy;
@@ -953,13 +818,13 @@ extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
       a.src = w.p0;
       a.q = w.q;
       a.write_all = 1;
-      launch_apply<double, false>(w.L.hc, w.sp.G, st, a);
+      launch_apply<double>(w.L.hc, w.sp.G, st, a);
     } else {
       ApplyArgs<float> a = make_apply_args<float>(w, g, nbmax, w.dxf, w.dyf);
       a.src = w.p0f;
       a.q = w.qf;
       a.write_all = 1;
-      launch_apply<float, false>(w.L.hc, w.sp.G, st, a);
+      launch_apply<float>(w.L.hc, w.sp.G, st, a);
     }
     hipError_t le = hipGetLastError();
     if (le != hipSuccess) {
@@ -1162,7 +1027,7 @@ static int residual64(const mfp_grid& g, int nb, const SolveWs& w, hipStream_t s
   ApplyArgs<double> a = make_apply_args<double>(w, g, nb, w.dx, w.dy);
   a.src = w.p0;
   a.q = w.q;
-  launch_apply<double, false>(w.L.hc, w.sp.G, st, a);
+  launch_apply<double>(w.L.hc, w.sp.G, st, a);
   k_resid<<<G2, BLOCK, 0, st>>>(w.L.n, w.q, w.r, w.part2, mode != 1 ? 1 : 0);
   k_resid_finalize<<<1, BLOCK, 0, st>>>(w.part2, G2, w.bpart, w.nslots, w.st, nb, mode,
                                         rtol * rtol, stop_abs);

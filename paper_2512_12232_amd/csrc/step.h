@@ -97,6 +97,16 @@ struct StepArgs {
   long long j;                   // this launch
   T cC, cE, cN, cD;              // constant stencil
   T ry;                          // hy / hx
+  // batched launches (kdev != 0): the launch index is st->jbase + the launch's offset in
+  // the replayed block and the start launch is st->k0; the parity slots below replace
+  // the per-launch pointers; G = this system's blocks
+  int kdev;
+  int G;
+  T* rs[2];
+  T* ps[2];
+  T* qs[2];
+  double* parts[2];
+  double* bparts[2];
 };
 
 // Work distribution: the launch keeps all its wavefronts resident; wavefront w takes
@@ -107,27 +117,47 @@ struct StepArgs {
 // one task ahead (a task that evaluates geometry requests its tags and displacements
 // first and the next task's data after its cell march, which needs the registers).
 template <typename T, int HC, bool STREAM, bool XUPD>
-__device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, double* s_pb,
+__device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, const int G,
+                                          const int koff, double* s_red, double* s_pb,
                                           double* s_qb) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const int G = gridDim.x, vblk = blockIdx.x;
-  // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs)
+  // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs;
+  // vblk and blockIdx.x agree modulo 8)
   const int vb = (vblk & 7) * (G >> 3) + (vblk >> 3);
   const unsigned P = (unsigned)a.P;
   const int nstrip = a.nstrip;
   const int ntask = nstrip * a.nchunk;
   const bool owner = lane >= 1 && lane <= SW;
   const int W = G * WAVES;
-  const long long j = a.j;
+  long long j = a.j, k0 = a.k0;
+  const T* rp = a.rp;
+  const T* qp = a.qp;
+  const T* pp = a.pp;
+  T* rc = a.rc;
+  T* qc = a.qc;
+  T* pc = a.pc;
+  const double* part_p = a.part_p;
+  double* part_c = a.part_c;
+  const double* bpart_p = a.bpart_p;
+  double* bpart_c = a.bpart_c;
+  if (a.kdev) {
+    j = a.st->jbase + koff;
+    k0 = a.st->k0;
+    const int c = (int)(j & 1), v = c ^ 1;
+    rp = a.rs[v];
+    qp = a.qs[v];
+    pp = a.ps[v];
+    rc = a.rs[c];
+    qc = a.qs[c];
+    pc = a.ps[c];
+    part_p = a.parts[v];
+    part_c = a.parts[c];
+    bpart_p = a.bparts[v];
+    bpart_c = a.bparts[c];
+  }
   const int cur = (int)(j & 1), prv = cur ^ 1;
-  const bool start = j == a.k0;
-  const T* __restrict__ rp = a.rp;
-  const T* __restrict__ qp = a.qp;
-  const T* __restrict__ pp = a.pp;
-  T* __restrict__ rc = a.rc;
-  T* __restrict__ qc = a.qc;
-  T* __restrict__ pc = a.pc;
+  const bool start = j == k0;
   constexpr unsigned TS = sizeof(T);
   const unsigned RB = P * TS;  // bytes per padded row of a T vector
   // task t: rows 0..HC+1 are padded rows chunk*HC + r, lane is column strip*64 + lane
@@ -180,7 +210,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     pbp = st->pb[prv][lane];
     xbp = st->xb[prv][lane];
   }
-  const double* __restrict__ bq = a.bpart_p;
+  const double* __restrict__ bq = bpart_p;
   const int b0 = wv, b1 = wv + WAVES;
   double q0 = 0.0, q1 = 0.0;  // slot sums of bodies b0, b1 (K p of iteration j-1)
   if (!start && lane < nsl) {
@@ -188,7 +218,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     if (b1 < nb) q1 = bq[(long long)lane * nb + b1];
   }
   const int npart = start ? a.npart0 : G;
-  const double* __restrict__ pt = a.part_p;
+  const double* __restrict__ pt = part_p;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int i = tid; i < npart; i += BLOCK) {
     s0 += pt[4 * i];
@@ -196,7 +226,6 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     s2 += pt[4 * i + 2];
     s3 += pt[4 * i + 3];
   }
-  if (done) return;
   // the first task's geometry is requested now (its flag has arrived with the
   // partials), so that it travels while the scalars are reduced
   int8_t tg[HC + 2];
@@ -234,6 +263,10 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     s_red[4 * wv + 3] = s3;
     if (b0 < nb) s_qb[b0] = start ? 0.0 : q0;
     if (b1 < nb) s_qb[b1] = start ? 0.0 : q1;
+    // the block leaves on wave 0's reading of the stop flag: the waves read it at
+    // different times, and block 0 may set it during this launch (a wave that left
+    // alone would leave its share of the block sums unwritten)
+    if (wv == 0) s_red[4 * WAVES] = done ? 1.0 : 0.0;
   }
   // bodies beyond 2 x WAVES (rare)
   for (int b = wv + 2 * WAVES; b < nb; b += WAVES) {
@@ -244,6 +277,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
     if (lane == 0) s_qb[b] = v;
   }
   __syncthreads();
+  if (s_red[4 * WAVES] != 0.0) return;  // stopped (the same decision in every wave)
   const double qb = lane < nb ? s_qb[lane] : 0.0;
   // body parts of r.r and p.Kp, two independent chains
   double brr = rbp * rbp, bpq = pbp * qb;
@@ -376,7 +410,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
       }
       if (bm) body_row(owner, g, (double)qr[r - 1], lane, bacc);
     }
-    if (bm && lane < nb) a.bpart_c[(long long)slot * nb + lane] = bacc;
+    if (bm && lane < nb) bpart_c[(long long)slot * nb + lane] = bacc;
   }
   // four block sums, fixed order
 #pragma unroll
@@ -395,17 +429,31 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, double* s_red, d
   }
   __syncthreads();
   if (tid < 4) {
-    a.part_c[4 * vblk + tid] =
+    part_c[4 * vblk + tid] =
         (s_red[tid] + s_red[4 + tid]) + (s_red[8 + tid] + s_red[12 + tid]);
   }
 }
 
 template <typename T, int HC, bool STREAM, bool XUPD>
 __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<T> a) {
-  __shared__ double s_red[4 * WAVES];
+  __shared__ double s_red[4 * WAVES + 1];
   __shared__ double s_pb[MFP_MAX_BODIES];
   __shared__ double s_qb[MFP_MAX_BODIES];
-  step_core<T, HC, STREAM, XUPD>(a, s_red, s_pb, s_qb);
+  step_core<T, HC, STREAM, XUPD>(a, blockIdx.x, gridDim.x, 0, s_red, s_pb, s_qb);
+}
+
+// Many independent systems in one launch: block b works for system map[b].x as its
+// virtual block map[b].y (each system's blocks start at a multiple of 8); koff is this
+// launch's offset in the replayed block of launches.
+template <typename T, bool XUPD>
+__global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restrict__ args,
+                                                      const int2* __restrict__ map, int koff) {
+  __shared__ double s_red[4 * WAVES + 1];
+  __shared__ double s_pb[MFP_MAX_BODIES];
+  __shared__ double s_qb[MFP_MAX_BODIES];
+  const int2 vm = map[blockIdx.x];
+  const StepArgs<T>& a = args[vm.x];
+  step_core<T, 4, false, XUPD>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
 }
 
 // Tasks of 4 node rows (the layout of a single solve); odd launches update the

@@ -83,3 +83,28 @@ def test_batched_sweep_sample_full_sizes(mfp):
         say(f"  system {i} {c.name}: iters {s['iters']} relres {s['relres_true']:.2e} "
             f"|dpsi_b| {d:.2e} copfi {res.copfi[i]:.9f} vs {single.copfi:.9f}")
         assert d <= 1e-6
+
+
+def test_batched_full_sweep_every_system_converges(mfp):
+    """The whole seeded delta-sweep (256 systems, 256x128 .. 1024x512) in one batch.
+    FP64: every system's FP64 true relative residual <= 2x the tolerance (a system's
+    blocks must agree on the launch that stops it; a block that ran on past it would
+    corrupt its tasks' iterate).  FP32 with FP64 refinement: every system converges in
+    at most 1.6x its FP64 iteration count plus one refinement block (a restart that lost
+    the last direction's conjugacy would take several times more)."""
+    cases = W.batch_variants(count=256, seed=0)
+    systems = meshes(mfp, cases)
+    r64 = mfp.psi_solve_batched(systems, cases[0].flow, precision="fp64", rtol=1e-10,
+                                pair=(3, 4))
+    assert r64.status == 0
+    worst = max(s["relres_true"] for s in r64.stats)
+    say(f"  fp64: worst relres {worst:.2e}")
+    assert worst <= 2e-10, [(i, s["relres_true"]) for i, s in enumerate(r64.stats)
+                            if s["relres_true"] > 2e-10]
+    r32 = mfp.psi_solve_batched(systems, cases[0].flow, precision="fp32_ir", rtol=1e-10,
+                                pair=(3, 4))
+    assert r32.status == 0
+    for i, (a, b) in enumerate(zip(r32.stats, r64.stats)):
+        assert a["relres_true"] <= 1.5e-10, (i, a["relres_true"])
+        assert a["iters"] <= 1.6 * b["iters"] + 64, (i, a["iters"], b["iters"])
+    np.testing.assert_allclose(r32.copfi, r64.copfi, rtol=0, atol=1e-7)
