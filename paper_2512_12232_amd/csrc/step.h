@@ -41,15 +41,22 @@
 
 namespace mfp {
 
+// Global memory.  The iteration kernel accesses its vectors through pointers of this
+// address space: pointers that a kernel loads from memory (the batched argument
+// tables) are otherwise generic, and every access through them becomes a flat
+// instruction (which also waits on the LDS counter).
+template <typename T>
+using gmem = __attribute__((address_space(1))) T;
+template <typename T>
+__device__ __forceinline__ gmem<T>* as_global(T* p) {
+  return (gmem<T>*)p;
+}
+
 // Element at a 32-bit byte offset from a uniform base pointer (lets the compiler use
 // scalar-base + 32-bit vector-offset addressing; the solver's vectors are < 4 GiB).
 template <typename T>
-__device__ __forceinline__ T ld_at(const T* base, unsigned boff) {
-  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
-}
-template <typename T>
-__device__ __forceinline__ void st_at(T* base, unsigned boff, T v) {
-  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff) = v;
+__device__ __forceinline__ T ld_at(const gmem<T>* base, unsigned boff) {
+  return *reinterpret_cast<const gmem<T>*>(reinterpret_cast<const gmem<char>*>(base) + boff);
 }
 // Store of the iteration's vectors; STREAM: not kept in L2 (non-temporal).  For
 // working sets larger than the memory-side cache the streaming form measured ~11%
@@ -58,8 +65,8 @@ __device__ __forceinline__ void st_at(T* base, unsigned boff, T v) {
 // finds the data in cache).  A compile-time choice: with a run-time branch the
 // compiler merges the two stores and drops the hint.
 template <bool STREAM, typename T>
-__device__ __forceinline__ void st_vec(T* base, unsigned boff, T v) {
-  T* p = reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
+__device__ __forceinline__ void st_vec(gmem<T>* base, unsigned boff, T v) {
+  gmem<T>* p = reinterpret_cast<gmem<T>*>(reinterpret_cast<gmem<char>*>(base) + boff);
   if constexpr (STREAM)
     __builtin_nontemporal_store(v, p);
   else
@@ -131,6 +138,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   const bool owner = lane >= 1 && lane <= SW;
   const int W = G * WAVES;
   long long j = a.j, k0 = a.k0;
+  gmem<DevState>* const st = as_global(a.st);
   const T* rp = a.rp;
   const T* qp = a.qp;
   const T* pp = a.pp;
@@ -142,20 +150,37 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   const double* bpart_p = a.bpart_p;
   double* bpart_c = a.bpart_c;
   if (a.kdev) {
-    j = a.st->jbase + koff;
-    k0 = a.st->k0;
-    const int c = (int)(j & 1), v = c ^ 1;
-    rp = a.rs[v];
-    qp = a.qs[v];
-    pp = a.ps[v];
-    rc = a.rs[c];
-    qc = a.qs[c];
-    pc = a.ps[c];
-    part_p = a.parts[v];
-    part_c = a.parts[c];
-    bpart_p = a.bparts[v];
-    bpart_c = a.bparts[c];
+    j = st->jbase + koff;
+    k0 = st->k0;
+    const bool c = (j & 1) != 0;  // selects, not indexing (keeps the table in registers)
+    rp = c ? a.rs[0] : a.rs[1];
+    qp = c ? a.qs[0] : a.qs[1];
+    pp = c ? a.ps[0] : a.ps[1];
+    rc = c ? a.rs[1] : a.rs[0];
+    qc = c ? a.qs[1] : a.qs[0];
+    pc = c ? a.ps[1] : a.ps[0];
+    part_p = c ? a.parts[0] : a.parts[1];
+    part_c = c ? a.parts[1] : a.parts[0];
+    bpart_p = c ? a.bparts[0] : a.bparts[1];
+    bpart_c = c ? a.bparts[1] : a.bparts[0];
   }
+  const gmem<T>* const rpg = as_global(rp);
+  const gmem<T>* const qpg = as_global(qp);
+  const gmem<T>* const ppg = as_global(pp);
+  gmem<T>* const rcg = as_global(rc);
+  gmem<T>* const qcg = as_global(qc);
+  gmem<T>* const pcg = as_global(pc);
+  const gmem<double>* const part_pg = as_global(part_p);
+  gmem<double>* const part_cg = as_global(part_c);
+  const gmem<double>* const bpart_pg = as_global(bpart_p);
+  gmem<double>* const bpart_cg = as_global(bpart_c);
+  gmem<T>* const xg = as_global(a.x);
+  const gmem<uint8_t>* const tplain = as_global(a.tplain);
+  const gmem<unsigned long long>* const tbody = as_global(a.tbody);
+  const gmem<int>* const tslot = as_global(a.tslot);
+  const gmem<int8_t>* const tagg = as_global(a.tag);
+  const gmem<T>* const dxg = as_global(a.dx);
+  const gmem<T>* const dyg = as_global(a.dy);
   const int cur = (int)(j & 1), prv = cur ^ 1;
   const bool start = j == k0;
   constexpr unsigned TS = sizeof(T);
@@ -175,21 +200,21 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     const unsigned bo = (unsigned)((int)node0(t) + shift_of(t)) * TS;
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
-      nr[r] = ld_at(rp, bo + r * RB);
-      nq[r] = ld_at(qp, bo + r * RB);
-      np[r] = ld_at(pp, bo + r * RB);
+      nr[r] = ld_at(rpg, bo + r * RB);
+      nq[r] = ld_at(qpg, bo + r * RB);
+      np[r] = ld_at(ppg, bo + r * RB);
     }
     if (XUPD) {
       // own rows only (halo lanes' values are unused)
 #pragma unroll
       for (int r = 0; r < HC; ++r) {
-        nx[r] = ld_at(a.x, bo + (r + 1) * RB);
-        n2[r] = ld_at((const T*)pc, bo + (r + 1) * RB);
+        nx[r] = ld_at(xg, bo + (r + 1) * RB);
+        n2[r] = ld_at((const gmem<T>*)pcg, bo + (r + 1) * RB);
       }
     }
-    n_plain = a.tplain[t];
-    n_body = a.tbody[t] != 0ull;
-    n_slot = a.tslot[t];
+    n_plain = tplain[t];
+    n_body = tbody[t] != 0ull;
+    n_slot = tslot[t];
   };
   int t = vb * WAVES + wv;
   if (t < ntask) fetch(t);
@@ -198,7 +223,6 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   // Everything they need is requested here, in one round trip: the state, lane b's
   // body values, the previous launch's partials and its per-body slot sums (wave w:
   // bodies w and w + 4 from the first 64 slots; more bodies or slots in a second pass).
-  DevState* st = a.st;
   const int nb = a.nb, nsl = a.nslots;
   const int done = st->done;
   const double rr_stop = st->rr_stop, rr_prev_start = st->rr_prev, stop_rel = st->stop_rel;
@@ -210,7 +234,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     pbp = st->pb[prv][lane];
     xbp = st->xb[prv][lane];
   }
-  const double* __restrict__ bq = bpart_p;
+  const gmem<double>* const bq = bpart_pg;
   const int b0 = wv, b1 = wv + WAVES;
   double q0 = 0.0, q1 = 0.0;  // slot sums of bodies b0, b1 (K p of iteration j-1)
   if (!start && lane < nsl) {
@@ -218,7 +242,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     if (b1 < nb) q1 = bq[(long long)lane * nb + b1];
   }
   const int npart = start ? a.npart0 : G;
-  const double* __restrict__ pt = part_p;
+  const gmem<double>* const pt = part_pg;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
   for (int i = tid; i < npart; i += BLOCK) {
     s0 += pt[4 * i];
@@ -234,9 +258,9 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     const unsigned ln0 = (unsigned)((int)node0(tt) + shift_of(tt));
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
-      tg[r] = ld_at(a.tag, ln0 + r * P);
-      ddx[r] = ld_at(a.dx, ln0 * TS + r * RB);
-      ddy[r] = ld_at(a.dy, ln0 * TS + r * RB);
+      tg[r] = ld_at(tagg, ln0 + r * P);
+      ddx[r] = ld_at(dxg, ln0 * TS + r * RB);
+      ddy[r] = ld_at(dyg, ln0 * TS + r * RB);
     }
   };
   if (t < ntask && !n_plain) load_geom(t);
@@ -395,10 +419,10 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
       const T qv = (owner && g == TAG_FREE) ? qr[r - 1] : (T)0;
       // every lane stores (the padding lanes zeros): whole aligned rows
-      st_vec<STREAM>(rc, go, owner ? rj[r] : (T)0);
-      st_vec<STREAM>(pc, go, owner ? v[r] : (T)0);
-      st_vec<STREAM>(qc, go, qv);
-      if (XUPD) st_vec<STREAM>(a.x, go, owner ? (xo[r - 1] + al2 * p2[r - 1]) + al * po[r] : (T)0);
+      st_vec<STREAM>(rcg, go, owner ? rj[r] : (T)0);
+      st_vec<STREAM>(pcg, go, owner ? v[r] : (T)0);
+      st_vec<STREAM>(qcg, go, qv);
+      if (XUPD) st_vec<STREAM>(xg, go, owner ? (xo[r - 1] + al2 * p2[r - 1]) + al * po[r] : (T)0);
       if (owner) {
         if (g == TAG_FREE) {
           const double rd = (double)rj[r], qd = (double)qv;
@@ -410,7 +434,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       }
       if (bm) body_row(owner, g, (double)qr[r - 1], lane, bacc);
     }
-    if (bm && lane < nb) bpart_c[(long long)slot * nb + lane] = bacc;
+    if (bm && lane < nb) bpart_cg[(long long)slot * nb + lane] = bacc;
   }
   // four block sums, fixed order
 #pragma unroll
@@ -429,7 +453,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   }
   __syncthreads();
   if (tid < 4) {
-    part_c[4 * vblk + tid] =
+    part_cg[4 * vblk + tid] =
         (s_red[tid] + s_red[4 + tid]) + (s_red[8 + tid] + s_red[12 + tid]);
   }
 }
