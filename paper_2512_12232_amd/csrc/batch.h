@@ -5,8 +5,8 @@
 // map (block b -> (system, virtual block); each system's blocks start at a multiple of
 // 8, so the XCD-aware order of the single solve holds per system), and each system's
 // arguments come from a per-system table in device memory.  The CG iteration is the
-// one-kernel iteration of step.h: a replayed block of m launches (m even) reads its
-// first launch index from each system's device state (jbase), the launch's offset in
+// one-kernel iteration of step.h: a replayed block of m launches reads its first
+// launch index from each system's device state (jbase), the launch's offset in
 // the block is a captured argument, so the launch sequence of a block is the same
 // every time: it is captured once as a hipGraph and replayed until every system has
 // stopped.  Systems that have stopped return at the top of every kernel.  jbase is odd
