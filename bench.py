@@ -141,8 +141,12 @@ def mixed_precision(mfp, W):
         if r.stats["apply_samples"] > 0:
             nbytes = nbytes64 if prec == "fp64" else nbytes32
             kms = r.stats["apply_ms"]
+            # task height of the solve's layout, from its task count (4-row tasks:
+            # strips of 62 node columns x chunks of 4 node rows)
+            tasks4 = -(-(case.grid.nx + 1) // 62) * -(-(case.grid.ny + 1) // 4)
+            hc = 4 if r.stats["n_tiles"] == tasks4 else 8
             out[prec]["roofline"] = {
-                "kernel": "k_step<%s, 4>" % ("double" if prec == "fp64" else "float"),
+                "kernel": "k_step<%s, %d>" % ("double" if prec == "fp64" else "float", hc),
                 "launch_ms": round(kms, 5), "bytes_per_launch": nbytes,
                 "achieved_GBs": round(nbytes / (kms * 1e-3) / 1e9, 1),
                 "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}

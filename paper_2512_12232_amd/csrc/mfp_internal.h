@@ -87,7 +87,8 @@ struct Layout {
 
 // Tasks of 4 owned rows by default: consecutive tasks of a wavefront's segment share
 // their halo rows in registers, so taller tasks save little traffic and cost
-// registers (occupancy); hc_force = 8 selects 8-row tasks.
+// registers (occupancy); hc_force = 8 selects 8-row tasks (FP32 solves of large
+// grids).
 inline Layout make_layout(int nx, int ny, int hc_force = 0) {
   Layout L;
   L.nx = nx;

@@ -508,12 +508,13 @@ constexpr int GMAX = 2048;  // max blocks of the reduction kernels
 // Wavefronts of the one-kernel CG iteration k_step<T, hc> resident on the current
 // device at once (0 when the runtime cannot say).
 template <typename T>
-static int step_resident_waves() {
+static int step_resident_waves(int hc = 4) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  const void* f = reinterpret_cast<const void*>(&k_step<T, 4, false, true>);
+  const void* f = hc == 8 ? reinterpret_cast<const void*>(&k_step<T, 8, false, true>)
+                          : reinterpret_cast<const void*>(&k_step<T, 4, false, true>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) != hipSuccess) return 0;
   return per_cu * cus * WAVES;
 }
@@ -524,7 +525,7 @@ static int step_resident_waves() {
 template <typename T>
 static int step_blocks(const Layout& L) {
   const long long need = (((long long)L.ntasks() + WAVES - 1) / WAVES + 7) & ~7LL;
-  long long g = step_resident_waves<T>() / WAVES;
+  long long g = step_resident_waves<T>(L.hc) / WAVES;
   g &= ~7LL;
   if (g < 8) g = 8;
   if (g > need) g = need;
@@ -536,8 +537,8 @@ static int step_blocks(const Layout& L) {
 // resident, less the per-strip slack of the segment bound, so that the whole list runs
 // in one round of wavefronts.
 static int single_target(const Layout& L, int precision) {
-  const int wres = precision == MFP_FP64 ? step_resident_waves<double>()
-                                         : step_resident_waves<float>();
+  const int wres = precision == MFP_FP64 ? step_resident_waves<double>(L.hc)
+                                         : step_resident_waves<float>(L.hc);
   if (wres <= 0) return L.ntasks();
   int t = wres - L.nstrip * (L.nchunk / 64 + 1);
   if (t < wres / 2) t = wres / 2;
@@ -596,6 +597,17 @@ struct SolveWs {
   int* boxes;
   int* count;
 };
+
+// Task height of a single solve's layout.  The FP32 iteration with 8-row tasks uses
+// about the registers of the FP64 one with 4-row tasks (two wavefronts per SIMD instead
+// of four) and has half the tasks: measured 56.8 vs 60.8 us per launch at 4096x2048,
+// but 17.0 vs 15.3 us at 1024x512, where 4-row tasks already give fewer tasks than
+// resident wavefronts.  So 8 rows for FP32 once the 4-row layout has at least 8192
+// tasks (twice the 4096 wavefronts of 4-row FP32 tasks that 256 CUs hold), else 4.
+static int solve_hc(const mfp_grid* g, int precision) {
+  if (precision != MFP_FP32 && precision != MFP_FP32_IR) return 4;
+  return make_layout(g->nx, g->ny).ntasks() >= 8192 ? 8 : 4;
+}
 
 static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base, SolveWs* out,
                            int hc_force = 0) {
@@ -769,7 +781,10 @@ using namespace mfp;
 extern "C" size_t mfp_solve_workspace_size(const mfp_grid* grid, int32_t nbody,
                                            int32_t precision) {
   if (!grid || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES) return 0;
-  return solve_layout(grid, nbody, precision, nullptr, nullptr);
+  // the solve's layout, and the element apply's (4-row tasks) for FP32
+  const size_t a = solve_layout(grid, nbody, precision, nullptr, nullptr, solve_hc(grid, precision));
+  const size_t b = solve_layout(grid, nbody, precision, nullptr, nullptr);
+  return a > b ? a : b;
 }
 
 extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
@@ -955,8 +970,8 @@ static int step_start(const SolveWs& w, int nb, const StepRun<T>& a, long long k
 template <typename T>
 static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, hipStream_t st,
                     CgCount* cnt, long long k0) {
-  if (w.L.hc != 4) {
-    set_error("internal: the CG iteration kernel needs 4-row tasks");
+  if (w.L.hc != 4 && w.L.hc != 8) {
+    set_error("internal: the CG iteration kernel needs 4- or 8-row tasks");
     return MFP_E_ARG;
   }
   const int G = step_blocks<T>(w.L);
@@ -979,10 +994,10 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
       const StepArgs<T> a = run.at(j);
       const bool timed = prof && (m % prof == 0) && used < nev_c;
       if (timed) {
-        launch_step<T>(G, st, a, ev[2 * used], ev[2 * used + 1]);
+        launch_step<T>(G, st, a, w.L.hc, ev[2 * used], ev[2 * used + 1]);
         ++used;
       } else {
-        launch_step<T>(G, st, a);
+        launch_step<T>(G, st, a, w.L.hc);
       }
     }
     hipError_t le = hipGetLastError();
@@ -1328,14 +1343,15 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
     set_error("bad sample buffers");
     return MFP_E_ARG;
   }
-  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr);
+  const int hc = solve_hc(grid, opts->precision);
+  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, hc);
   if (ws_bytes < need) {
     set_error("workspace too small: %zu < %zu", ws_bytes, need);
     return MFP_E_WORKSPACE;
   }
   hipStream_t st = static_cast<hipStream_t>(stream_);
   SolveWs w;
-  solve_layout(grid, nbody, opts->precision, ws, &w);
+  solve_layout(grid, nbody, opts->precision, ws, &w, hc);
   const mfp_grid& g = *grid;
   const int nb = nbody;
   SolveInfo info;

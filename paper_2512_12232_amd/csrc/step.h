@@ -480,32 +480,43 @@ __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restr
   step_core<T, 4, false, XUPD>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
 }
 
-// Tasks of 4 node rows (the layout of a single solve); odd launches update the
-// iterate.
-template <typename T, bool STREAM, bool XUPD>
+// Tasks of HC node rows (the layout's); odd launches update the iterate.
+template <typename T, int HC, bool STREAM, bool XUPD>
 inline void launch_step_i(int G, hipStream_t st, const StepArgs<T>& a, hipEvent_t e0,
                           hipEvent_t e1) {
   if (e0)
-    hipExtLaunchKernelGGL(k_step<T, 4, STREAM, XUPD>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+    hipExtLaunchKernelGGL(k_step<T, HC, STREAM, XUPD>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
   else
-    k_step<T, 4, STREAM, XUPD><<<G, BLOCK, 0, st>>>(a);
+    k_step<T, HC, STREAM, XUPD><<<G, BLOCK, 0, st>>>(a);
 }
 
-template <typename T>
-inline void launch_step(int G, hipStream_t st, const StepArgs<T>& a, hipEvent_t e0 = nullptr,
-                        hipEvent_t e1 = nullptr) {
+template <typename T, int HC>
+inline void launch_step_h(int G, hipStream_t st, const StepArgs<T>& a, hipEvent_t e0,
+                          hipEvent_t e1) {
   const bool xu = (a.j & 1) != 0;
   if (a.stream) {
     if (xu)
-      launch_step_i<T, true, true>(G, st, a, e0, e1);
+      launch_step_i<T, HC, true, true>(G, st, a, e0, e1);
     else
-      launch_step_i<T, true, false>(G, st, a, e0, e1);
+      launch_step_i<T, HC, true, false>(G, st, a, e0, e1);
   } else {
     if (xu)
-      launch_step_i<T, false, true>(G, st, a, e0, e1);
+      launch_step_i<T, HC, false, true>(G, st, a, e0, e1);
     else
-      launch_step_i<T, false, false>(G, st, a, e0, e1);
+      launch_step_i<T, HC, false, false>(G, st, a, e0, e1);
   }
+}
+
+// hc: the layout's task height, 4, or 8 for FP32 (FP32 8-row tasks use about as many
+// registers as FP64 4-row ones; FP64 8-row tasks would need 256 and run one wavefront
+// per SIMD).
+template <typename T>
+inline void launch_step(int G, hipStream_t st, const StepArgs<T>& a, int hc,
+                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+  if (hc == 8)
+    launch_step_h<T, 8>(G, st, a, e0, e1);
+  else
+    launch_step_h<T, 4>(G, st, a, e0, e1);
 }
 
 // Start (or restart after a residual replacement) of a run at launch k0: the

@@ -203,3 +203,43 @@ def test_full_size_4096x2048_equations_hold_on_samples(mfp):
     for b in range(len(c.circles)):
         bn = np.flatnonzero(bflat == b)
         assert abs(O.apply_at_nodes(mesh, psi, bn).sum()) <= 1e-7 * scale
+
+
+def test_fp32_eight_row_tasks_2048x1024(mfp):
+    """At 2048x1024 (8738 four-row tasks) the FP32 iteration runs 8-row tasks.  FP32 with
+    FP64 refinement to 1e-10 must satisfy the discrete equations of the oracle's mesh at
+    4000 seeded free nodes and in every body row, and agree with the FP64 solve; with one
+    refinement allowed it falls back to FP64 CG, here on the same 8-row layout, and must
+    then reach 1e-12 (x1.5: true against recursive residual)."""
+    c = W.five_cyl_2048_adjoint()
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    ref = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12, pair=c.pair,
+                        sample_cap=0)
+    assert ref.status == 0
+    ir = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-10,
+                       precision="fp32_ir", pair=c.pair, sample_cap=0)
+    assert ir.status == 0 and ir.stats["relres_true"] <= 1.5e-10
+    psi = ir.psi.cpu().numpy()
+    psi_ref = ref.psi.cpu().numpy()
+    d = np.linalg.norm(psi - psi_ref) / np.linalg.norm(psi_ref)
+    say(f"  fp32_ir: iters {ir.stats['iters']} relres {ir.stats['relres_true']:.2e} "
+        f"psi rel diff {d:.2e}")
+    assert d <= 1e-6
+    mesh = O.conform(c.grid, c.circles, c.nsweeps)
+    dmask = O.dirichlet_mask(c.grid, c.flow).ravel()
+    bflat = mesh.body.ravel()
+    free = np.flatnonzero((~dmask) & (bflat < 0))
+    nodes = np.random.default_rng(11).choice(free, size=4000, replace=False)
+    scale = np.abs(psi).max()
+    assert np.abs(O.apply_at_nodes(mesh, psi, nodes)).max() <= 1e-6 * scale
+    for b in range(len(c.circles)):
+        bn = np.flatnonzero(bflat == b)
+        assert abs(O.apply_at_nodes(mesh, psi, bn).sum()) <= 1e-6 * scale
+    fb = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12,
+                       precision="fp32_ir", inner_rtol=1e-3, max_outer=1, pair=c.pair,
+                       sample_cap=0)
+    # the true residual may exceed the recursive one that stopped the iteration a little
+    assert fb.status == 2 and fb.stats["relres_true"] <= 1.5e-12
+    d = np.linalg.norm(fb.psi.cpu().numpy() - psi_ref) / np.linalg.norm(psi_ref)
+    say(f"  fallback: relres {fb.stats['relres_true']:.2e} psi rel diff {d:.2e}")
+    assert d <= 1e-8
