@@ -150,8 +150,20 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   const double* bpart_p = a.bpart_p;
   double* bpart_c = a.bpart_c;
   if (a.kdev) {
-    j = st->jbase + koff;
-    k0 = st->k0;
+    // The launch index must arrive before any vector is requested (the parity slots
+    // depend on it), so the stop flag comes with it and a stopped system's blocks
+    // leave before they request anything.  One thread reads, the block decides
+    // together (see the stop decision below).
+    long long* const s_hdr = reinterpret_cast<long long*>(s_red + 4 * WAVES + 1);
+    if (tid == 0) {
+      s_hdr[0] = st->jbase;
+      s_hdr[1] = st->k0;
+      s_hdr[2] = st->done;
+    }
+    __syncthreads();
+    if (s_hdr[2] != 0) return;
+    j = s_hdr[0] + koff;
+    k0 = s_hdr[1];
     const bool c = (j & 1) != 0;  // selects, not indexing (keeps the table in registers)
     rp = c ? a.rs[0] : a.rs[1];
     qp = c ? a.qs[0] : a.qs[1];
@@ -460,7 +472,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
 
 template <typename T, int HC, bool STREAM, bool XUPD>
 __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<T> a) {
-  __shared__ double s_red[4 * WAVES + 1];
+  __shared__ double s_red[4 * WAVES + 4];  // + stop flag, launch header (batched)
   __shared__ double s_pb[MFP_MAX_BODIES];
   __shared__ double s_qb[MFP_MAX_BODIES];
   step_core<T, HC, STREAM, XUPD>(a, blockIdx.x, gridDim.x, 0, s_red, s_pb, s_qb);
@@ -472,7 +484,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<T> a) {
 template <typename T, bool XUPD>
 __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restrict__ args,
                                                       const int2* __restrict__ map, int koff) {
-  __shared__ double s_red[4 * WAVES + 1];
+  __shared__ double s_red[4 * WAVES + 4];  // + stop flag, launch header
   __shared__ double s_pb[MFP_MAX_BODIES];
   __shared__ double s_qb[MFP_MAX_BODIES];
   const int2 vm = map[blockIdx.x];
