@@ -97,7 +97,9 @@ typedef struct {
   int32_t precision;      /* MFP_FP64 / MFP_FP32 / MFP_FP32_IR                          */
   double rtol;            /* stop when ||r_k|| <= rtol ||r_0|| (unknowns incl. bodies)  */
   int64_t kmax;           /* CG iteration cap (all inner iterations together)           */
-  int32_t check_every;    /* host convergence poll period in iterations (>= 1)          */
+  int32_t check_every;    /* iterations per enqueued batch (0 -> 16); the host reads a
+                             batch's stop flag while the next batch runs, so an outcome
+                             costs at most one batch of launches that return at once    */
   double inner_rtol;      /* MFP_FP32_IR: residual reduction of the FP32 iteration between
                              FP64 residual recomputations (0 < delta < 1; 0 -> 0.1)     */
   int32_t max_outer;      /* MFP_FP32_IR: cap on FP64 residual recomputations (0 -> 1000) */

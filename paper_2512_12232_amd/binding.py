@@ -217,7 +217,7 @@ class SolveResult:
 
 
 def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1e-12,
-              kmax=10 ** 7, check_every=64, inner_rtol=0.1, max_outer=1000, pair=(-1, -1),
+              kmax=10 ** 7, check_every=16, inner_rtol=0.1, max_outer=1000, pair=(-1, -1),
               sample_cap=None, ws: Optional[torch.Tensor] = None,
               allow_warn: bool = True, profile_every: int = 0,
               psi0: Optional[torch.Tensor] = None) -> SolveResult:
@@ -268,7 +268,7 @@ def _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer):
 
 def psi_grad(grid, circles, disp, kind, body, flow, psi, psi_b, *, dL_dpsib=None,
              dL_dcopfi=0.0, pair=(-1, -1), precision="fp64", rtol=1e-12, kmax=10 ** 7,
-             check_every=64, inner_rtol=0.1, max_outer=1000):
+             check_every=16, inner_rtol=0.1, max_outer=1000):
     """Adjoint solve + shape derivative.  Returns (dL_ddisp device tensor [2*nodes],
     explicit dL/dcentre list of (dx, dy) per body, stats, status)."""
     lib = load()

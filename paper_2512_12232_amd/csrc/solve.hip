@@ -14,6 +14,7 @@
 // launch's per-block partials itself.  Scalars never leave the device; the host polls
 // a done flag every few iterations.
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <type_traits>
 #include <vector>
@@ -962,11 +963,36 @@ static int step_start(const SolveWs& w, int nb, const StepRun<T>& a, long long k
   return MFP_OK;
 }
 
-// Host loop of the one-kernel CG from launch k0: launches are enqueued in batches of
-// `check_every`; once the device has recorded an outcome the remaining launches of
-// the batch return immediately.  Afterwards the iterate takes the stopping launch's
-// alpha p.  Returns the done code (1 converged, 2 breakdown, 3 kmax) or a negative
-// status; cnt->iters is the stopping launch.
+// Host-visible copy of a solve's outcome: DevState from `iters` through `done`
+// (iters, kmax, outer_count, done), copied in one piece.
+struct OutcomeCopy {
+  long long iters, kmax, outer_count;
+  int done, pad_;
+};
+static_assert(offsetof(DevState, done) - offsetof(DevState, iters) ==
+                  offsetof(OutcomeCopy, done) - offsetof(OutcomeCopy, iters),
+              "DevState outcome fields must match OutcomeCopy");
+
+// Two outcome slots in pinned host memory per host thread, allocated on first use and
+// kept for the life of the process.
+static OutcomeCopy* outcome_slots() {
+  static thread_local OutcomeCopy* slots = nullptr;
+  if (!slots) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, 2 * sizeof(OutcomeCopy), hipHostMallocDefault) != hipSuccess)
+      return nullptr;
+    slots = static_cast<OutcomeCopy*>(p);
+  }
+  return slots;
+}
+
+// Host loop of the one-kernel CG from launch k0.  Launches are enqueued in batches of
+// `check_every` (0 -> 16); behind each batch the outcome fields travel to a pinned host
+// slot.  The host waits for a batch's outcome only after the next batch is enqueued,
+// so the device never drains between batches; an outcome is seen one batch late, and
+// the launches of the batch then in flight return at once.  Afterwards the iterate
+// takes the stopping launch's alpha p.  Returns the done code (1 converged, 2
+// breakdown, 3 kmax) or a negative status; cnt->iters is the stopping launch.
 template <typename T>
 static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, hipStream_t st,
                     CgCount* cnt, long long k0) {
@@ -974,63 +1000,100 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
     set_error("internal: the CG iteration kernel needs 4- or 8-row tasks");
     return MFP_E_ARG;
   }
+  OutcomeCopy* slots = outcome_slots();
+  if (!slots) {
+    set_error("pinned host memory for the convergence flag: allocation failed");
+    return MFP_E_HIP;
+  }
   const int G = step_blocks<T>(w.L);
-  const int every = o.check_every > 0 ? o.check_every : 50;
+  const int every = o.check_every > 0 ? o.check_every : 16;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
-  const int nev = prof ? (every + prof - 1) / prof : 0;
-  hipEvent_t ev[2 * 64];
-  const int nev_c = nev > 64 ? 64 : nev;
-  for (int i = 0; i < 2 * nev_c; ++i) MFP_TRY_HIP(hipEventCreate(&ev[i]));
-  long long j = k0;
-  struct {
-    int done;
-    long long iters;
-  } hs{0, 0};
-  run.a.k0 = k0;
+  // launches k0, k0 + prof, ... are timed (prof odd samples both launch parities)
+  const int nev = prof ? every / prof + 1 : 0;
+  const int nev_c = nev > 32 ? 32 : nev;
+  hipEvent_t ev[2][2 * 32], fev[2];
+  long long tj[2][32];  // launch index of each timed launch
+  int created = 0, fcreated = 0;
   int status = MFP_OK;
-  while (true) {
+  for (int s2 = 0; s2 < 2 && status == MFP_OK; ++s2) {
+    if (hipEventCreateWithFlags(&fev[s2], hipEventDisableTiming) != hipSuccess) status = MFP_E_HIP;
+    else ++fcreated;
+    for (int i = 0; i < 2 * nev_c && status == MFP_OK; ++i) {
+      if (hipEventCreate(&ev[s2][i]) != hipSuccess) status = MFP_E_HIP;
+      else ++created;
+    }
+  }
+  const char* state_bytes = reinterpret_cast<const char*>(run.a.st);
+  const size_t out_off = offsetof(DevState, iters);
+  const size_t out_len = offsetof(DevState, done) + sizeof(int) - out_off;
+  long long j = k0;
+  run.a.k0 = k0;
+  int slot = 0;
+  bool have_prev = false;
+  int used_prev = 0;
+  OutcomeCopy outcome{};
+  while (status == MFP_OK) {
     int used = 0;
     for (int m = 0; m < every; ++m, ++j) {
       const StepArgs<T> a = run.at(j);
-      const bool timed = prof && (m % prof == 0) && used < nev_c;
+      const bool timed = prof && ((j - k0) % prof == 0) && used < nev_c;
       if (timed) {
-        launch_step<T>(G, st, a, w.L.hc, ev[2 * used], ev[2 * used + 1]);
+        tj[slot][used] = j;
+        launch_step<T>(G, st, a, w.L.hc, ev[slot][2 * used], ev[slot][2 * used + 1]);
         ++used;
       } else {
         launch_step<T>(G, st, a, w.L.hc);
       }
     }
     hipError_t le = hipGetLastError();
-    if (le == hipSuccess) le = hipMemcpyAsync(&hs.done, &run.a.st->done, sizeof(int),
-                                              hipMemcpyDeviceToHost, st);
-    if (le == hipSuccess) le = hipMemcpyAsync(&hs.iters, &run.a.st->iters, sizeof(long long),
-                                              hipMemcpyDeviceToHost, st);
-    if (le == hipSuccess) le = hipStreamSynchronize(st);
+    if (le == hipSuccess)
+      le = hipMemcpyAsync(reinterpret_cast<char*>(&slots[slot]) + offsetof(OutcomeCopy, iters),
+                          state_bytes + out_off, out_len, hipMemcpyDeviceToHost, st);
+    if (le == hipSuccess) le = hipEventRecord(fev[slot], st);
+    if (le == hipSuccess && have_prev) le = hipEventSynchronize(fev[slot ^ 1]);
     if (le != hipSuccess) {
       set_error("CG loop: %s", hipGetErrorString(le));
       status = MFP_E_HIP;
       break;
     }
-    // only launches that did work count (launches after the outcome return at once)
-    const long long first = j - every;
-    for (int i = 0; i < used; ++i) {
-      const long long it = first + (long long)i * prof;
-      if (hs.done && it >= hs.iters) break;
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
-        cnt->tsum += ms;
-        ++cnt->tcnt;
+    if (have_prev) {
+      const OutcomeCopy prev = slots[slot ^ 1];
+      // only launches that did work count (launches after the outcome return at once)
+      for (int i = 0; i < used_prev; ++i) {
+        if (prev.done && tj[slot ^ 1][i] >= prev.iters) break;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[slot ^ 1][2 * i], ev[slot ^ 1][2 * i + 1]) == hipSuccess) {
+          cnt->tsum += ms;
+          ++cnt->tcnt;
+        }
+      }
+      if (prev.done) {
+        outcome = prev;
+        break;
       }
     }
-    if (hs.done) break;
+    have_prev = true;
+    used_prev = used;
+    slot ^= 1;
   }
-  for (int i = 0; i < 2 * nev_c; ++i) (void)hipEventDestroy(ev[i]);
+  // the batch still in flight (launches that return at once) ends before its events go
+  if (status == MFP_OK && hipEventSynchronize(fev[slot]) != hipSuccess) {
+    set_error("CG loop: event synchronisation failed");
+    status = MFP_E_HIP;
+  }
+  for (int s2 = 0; s2 < 2; ++s2) {
+    for (int i = 0; i < 2 * nev_c && created > 0; ++i, --created) (void)hipEventDestroy(ev[s2][i]);
+    if (fcreated > 0) {
+      (void)hipEventDestroy(fev[s2]);
+      --fcreated;
+    }
+  }
   if (status != MFP_OK) return status;
   k_finish<T><<<loop_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, run.a.x, run.p[0], run.p[1], run.a.st);
   MFP_TRY_HIP(hipGetLastError());
-  cnt->iters = hs.iters;
-  cnt->applies += hs.iters - k0;
-  return hs.done;
+  cnt->iters = outcome.iters;
+  cnt->applies += outcome.iters - k0;
+  return outcome.done;
 }
 
 // b - A x in FP64 from the current iterate: w = g + T x, q = K w, r = -T^T q, then
