@@ -243,3 +243,51 @@ def test_fp32_eight_row_tasks_2048x1024(mfp):
     d = np.linalg.norm(fb.psi.cpu().numpy() - psi_ref) / np.linalg.norm(psi_ref)
     say(f"  fallback: relres {fb.stats['relres_true']:.2e} psi rel diff {d:.2e}")
     assert d <= 1e-8
+
+
+def _reference_4096():
+    """The stored oracle solution of the 4096x2048 workload (header values and psi at the
+    stored nodes)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "five_cyl_4096x2048_reference.txt")
+    if not os.path.exists(path):
+        pytest.skip("reference not generated: run tests/golden/make_five_cyl_4096_reference.py")
+    meta, nodes, vals = {}, [], []
+    with open(path) as f:
+        for line in f:
+            if line.startswith("#"):
+                parts = line[1:].split()
+                if parts and parts[0] in ("psi_b", "copfi", "cg_iterations",
+                                          "true_relative_residual"):
+                    meta[parts[0]] = [float(v) for v in parts[1:]]
+                continue
+            n, v = line.split()
+            nodes.append(int(n))
+            vals.append(float(v))
+    return meta, np.array(nodes), np.array(vals)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_full_size_4096x2048_matches_oracle_reference(mfp, precision):
+    """The 4096x2048 workload against the oracle's own solution: its plain FP64 CG on the
+    assembled reduced system to a true relative residual <= 1e-13, stored with psi_b,
+    CoPFI and psi at 2000 seeded free nodes (tests/golden, written by the committed
+    script beside it).  GPU solves to 1e-12 (FP64, and FP32 with FP64 refinement on 8-row
+    tasks).  Both sides are iterative: they differ by the two residuals amplified by the
+    conditioning (about 1.6e6 here), so the bars are 5e-9 of max|psi| for psi and psi_b
+    and 5e-9 for CoPFI."""
+    meta, nodes, ref = _reference_4096()
+    c = W.five_cyl_4096()
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12,
+                        precision=precision, pair=c.pair, sample_cap=0)
+    assert res.status == 0 and res.stats["relres_true"] <= 1.5e-12
+    psi = res.psi.cpu().numpy()
+    scale = np.abs(psi).max()
+    dpsi = np.abs(psi[nodes] - ref).max() / scale
+    dpb = np.abs(np.array(res.psi_b) - np.array(meta["psi_b"])).max() / scale
+    dcop = abs(res.copfi - meta["copfi"][0])
+    say(f"  {precision}: iters {res.stats['iters']} relres {res.stats['relres_true']:.2e} "
+        f"max|dpsi|/max|psi| {dpsi:.2e} max|dpsi_b| {dpb:.2e} |dCoPFI| {dcop:.2e}")
+    assert dpsi <= 5e-9 and dpb <= 5e-9 and dcop <= 5e-9
