@@ -245,9 +245,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 4096x2048 mixed-precision, adjoint and delta-sweep "
                          "measurements")
-    ap.add_argument("--profile-every", type=int, default=17,
+    ap.add_argument("--profile-every", type=int, default=101,
                     help="time every n-th iteration launch with HIP events (0: off; odd, "
-                         "so that both launch parities are sampled)")
+                         "so that both launch parities are sampled; each timed launch "
+                         "leaves the device idle for a few microseconds, so sparsely)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy (counter calibration)")
     args = ap.parse_args()

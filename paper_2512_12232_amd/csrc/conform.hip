@@ -3,7 +3,7 @@
 //   k_classify      node -> body id by the FP64 test (x-cx)^2 + (y-cy)^2 <= r^2
 //   k_snap          body nodes with a fluid node among their eight neighbours are
 //                   moved radially onto their circle (d_ik = x_ik - x_gk); others deep
-//   k_jacobi_sweep  one Jacobi sweep d <- wx (d_E + d_W) + wy (d_N + d_S) of the
+//   k_jacobi_multi  up to 8 Jacobi sweeps d <- wx (d_E + d_W) + wy (d_N + d_S) of the
 //                   displacement Laplace problem on fluid nodes off the outer boundary
 //   k_tangle        Gauss-point Jacobian determinants of active cells must be > 0
 //
@@ -85,24 +85,66 @@ __global__ void k_snap(GridD g, const mfp_circle* __restrict__ circ,
   }
 }
 
-// One sweep over the box [i0,i1] x [j0,j1] (interior nodes only).
-__global__ void k_jacobi_sweep(int nx, int ny, int i0, int j0, int bw, int bh, double wx,
-                               double wy, const int8_t* __restrict__ kind,
-                               const double* __restrict__ src, double* __restrict__ dst) {
+// Up to JS Jacobi sweeps in one launch (temporal blocking).  A block takes one
+// displacement component of a JT_X x JT_Y tile of the last sweep's box, reads the tile
+// widened by JS nodes on every side into LDS, and runs the sweeps there: after s sweeps
+// the values are exact at least s nodes in from the region's edge, so the tile itself
+// is exact after JS.  Sweep s updates exactly the nodes the single sweep would (fluid
+// nodes in that sweep's box) with the same expression in the same order, so the
+// result is bit for bit that of the sweeps launched one by one.  Nodes outside a
+// sweep's box have not changed since the start (the boxes only grow) and are left as
+// they are, in LDS and in both global buffers.
+constexpr int JT_X = 64, JT_Y = 16, JS = 8;
+struct SweepBoxes {
+  int i0[JS], i1[JS], j0[JS], j1[JS];
+};
+
+__global__ void __launch_bounds__(BLOCK) k_jacobi_multi(int nx, int ny, int ns, SweepBoxes bx,
+                                                        double wx, double wy,
+                                                        const int8_t* __restrict__ kind,
+                                                        const double* __restrict__ src,
+                                                        double* __restrict__ dst) {
+  constexpr int RW = JT_X + 2 * JS, RH = JT_Y + 2 * JS;
+  __shared__ double buf[2][RW * RH];
+  __shared__ int8_t kd[RW * RH];
   const long long nn = (long long)(nx + 1) * (ny + 1);
-  const int i = i0 + (int)(blockIdx.x * blockDim.x + threadIdx.x);
-  const int j = j0 + (int)blockIdx.y;
-  if (i >= i0 + bw || (int)blockIdx.y >= bh) return;
-  const long long n = (long long)j * (nx + 1) + i;
-  const double* sx = src;
-  const double* sy = src + nn;
-  if (kind[n] == MFP_FLUID) {
-    const long long e = n + 1, w = n - 1, no = n + (nx + 1), so = n - (nx + 1);
-    dst[n] = wx * (sx[e] + sx[w]) + wy * (sx[no] + sx[so]);
-    dst[n + nn] = wx * (sy[e] + sy[w]) + wy * (sy[no] + sy[so]);
-  } else {
-    dst[n] = sx[n];
-    dst[n + nn] = sy[n];
+  const double* s = src + blockIdx.z * nn;
+  double* d = dst + blockIdx.z * nn;
+  const int last = ns - 1;
+  // region origin: tiles start at the last box's corner
+  const int gi0 = bx.i0[last] + (int)blockIdx.x * JT_X - JS;
+  const int gj0 = bx.j0[last] + (int)blockIdx.y * JT_Y - JS;
+  for (int e = threadIdx.x; e < RW * RH; e += BLOCK) {
+    const int i = gi0 + e % RW, j = gj0 + e / RW;
+    const bool in = i >= 0 && i <= nx && j >= 0 && j <= ny;
+    const long long n = (long long)j * (nx + 1) + i;
+    buf[0][e] = in ? s[n] : 0.0;
+    kd[e] = in ? kind[n] : (int8_t)-1;  // off the grid: never updated, never read by an update
+  }
+  __syncthreads();
+  int cur = 0;
+  for (int sw = 0; sw < ns; ++sw) {
+    const int bi0 = bx.i0[sw], bi1 = bx.i1[sw], bj0 = bx.j0[sw], bj1 = bx.j1[sw];
+    const double* a = buf[cur];
+    double* b = buf[cur ^ 1];
+    for (int e = threadIdx.x; e < RW * RH; e += BLOCK) {
+      const int li = e % RW, lj = e / RW;
+      const int i = gi0 + li, j = gj0 + lj;
+      double v = a[e];
+      if (li > sw && li < RW - 1 - sw && lj > sw && lj < RH - 1 - sw && i >= bi0 && i <= bi1 &&
+          j >= bj0 && j <= bj1 && kd[e] == MFP_FLUID)
+        v = wx * (a[e + 1] + a[e - 1]) + wy * (a[e + RW] + a[e - RW]);
+      b[e] = v;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const int bi0 = bx.i0[last], bi1 = bx.i1[last], bj0 = bx.j0[last], bj1 = bx.j1[last];
+  for (int e = threadIdx.x; e < JT_X * JT_Y; e += BLOCK) {
+    const int li = JS + e % JT_X, lj = JS + e / JT_X;
+    const int i = gi0 + li, j = gj0 + lj;
+    if (i >= bi0 && i <= bi1 && j >= bj0 && j <= bj1)
+      d[(long long)j * (nx + 1) + i] = buf[cur][lj * RW + li];
   }
 }
 
@@ -166,7 +208,7 @@ static Box union_box(const mfp_grid& g, const mfp_circle* c, int nb, int pad, in
   return u;
 }
 
-// Transposed Jacobi sweep (adjoint of k_jacobi_sweep): with upd(n) = fluid node off
+// Transposed Jacobi sweep (adjoint of one sweep of k_jacobi_multi): with upd(n) = fluid node off
 // the outer boundary, g_new[m] = [m fixed] g[m] + sum over update neighbours n of
 // w(n, m) g[n].
 __global__ void k_jacobi_sweep_T(int nx, int ny, int i0, int j0, int bw, int bh, double wx,
@@ -300,18 +342,32 @@ extern "C" int mfp_mesh_conform(const mfp_grid* grid, const mfp_circle* circles_
                                hipMemcpyDeviceToDevice, st));
     double* a = disp;
     double* b = w.tmp;
-    for (int k = 1; k <= nsweeps; ++k) {
-      const Box bx = union_box(g, circles_h, nbody, k + 1, 1, g.nx - 1, 1, g.ny - 1);
-      if (!bx.empty()) {
-        const int bw = bx.i1 - bx.i0 + 1, bh = bx.j1 - bx.j0 + 1;
-        dim3 grd((bw + BLOCK - 1) / BLOCK, bh);
-        k_jacobi_sweep<<<grd, BLOCK, 0, st>>>(g.nx, g.ny, bx.i0, bx.j0, bw, bh, wx, wy,
-                                              kind, a, b);
-        MFP_TRY_HIP(hipGetLastError());
+    // sweep k updates the fluid nodes of the circles' box widened by k + 1 nodes;
+    // up to JS sweeps per launch
+    for (int k = 1; k <= nsweeps;) {
+      SweepBoxes sb;
+      int ns = 0;
+      while (ns < JS && k + ns <= nsweeps) {
+        const Box bx = union_box(g, circles_h, nbody, k + ns + 1, 1, g.nx - 1, 1, g.ny - 1);
+        if (bx.empty()) break;
+        sb.i0[ns] = bx.i0;
+        sb.i1[ns] = bx.i1;
+        sb.j0[ns] = bx.j0;
+        sb.j1[ns] = bx.j1;
+        ++ns;
       }
+      if (ns == 0) {  // nothing to sweep (cannot happen for accepted geometry)
+        ++k;
+        continue;
+      }
+      const int bw = sb.i1[ns - 1] - sb.i0[ns - 1] + 1, bh = sb.j1[ns - 1] - sb.j0[ns - 1] + 1;
+      dim3 grd((bw + JT_X - 1) / JT_X, (bh + JT_Y - 1) / JT_Y, 2);
+      k_jacobi_multi<<<grd, BLOCK, 0, st>>>(g.nx, g.ny, ns, sb, wx, wy, kind, a, b);
+      MFP_TRY_HIP(hipGetLastError());
       double* t = a;
       a = b;
       b = t;
+      k += ns;
     }
     if (a != disp)
       MFP_TRY_HIP(hipMemcpyAsync(disp, a, sizeof(double) * 2 * nn,

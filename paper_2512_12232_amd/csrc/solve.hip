@@ -965,6 +965,8 @@ static int step_start(const SolveWs& w, int nb, const StepRun<T>& a, long long k
 
 // Host-visible copy of a solve's outcome: DevState from `iters` through `done`
 // (iters, kmax, outer_count, done), copied in one piece.
+// Host-visible copy of a solve's outcome: DevState from `iters` through `done`
+// (iters, kmax, outer_count, done), copied in one piece.
 struct OutcomeCopy {
   long long iters, kmax, outer_count;
   int done, pad_;
@@ -973,26 +975,40 @@ static_assert(offsetof(DevState, done) - offsetof(DevState, iters) ==
                   offsetof(OutcomeCopy, done) - offsetof(OutcomeCopy, iters),
               "DevState outcome fields must match OutcomeCopy");
 
-// Two outcome slots in pinned host memory per host thread, allocated on first use and
-// kept for the life of the process.
-static OutcomeCopy* outcome_slots() {
-  static thread_local OutcomeCopy* slots = nullptr;
-  if (!slots) {
+// Pinned host memory of a host thread's solves, allocated on first use and kept for
+// the life of the process: the stop code that the stopping launch writes (the host
+// polls it) and the outcome copy read at the end of a run.
+struct HostIo {
+  OutcomeCopy out;
+  int flag;
+};
+static HostIo* host_io(int** flag_dev) {
+  static thread_local HostIo* io = nullptr;
+  static thread_local int* dflag = nullptr;
+  if (!io) {
     void* p = nullptr;
-    if (hipHostMalloc(&p, 2 * sizeof(OutcomeCopy), hipHostMallocDefault) != hipSuccess)
+    if (hipHostMalloc(&p, sizeof(HostIo), hipHostMallocDefault) != hipSuccess) return nullptr;
+    void* d = nullptr;
+    if (hipHostGetDevicePointer(&d, &static_cast<HostIo*>(p)->flag, 0) != hipSuccess) {
+      (void)hipHostFree(p);
       return nullptr;
-    slots = static_cast<OutcomeCopy*>(p);
+    }
+    io = static_cast<HostIo*>(p);
+    dflag = static_cast<int*>(d);
   }
-  return slots;
+  *flag_dev = dflag;
+  return io;
 }
 
 // Host loop of the one-kernel CG from launch k0.  Launches are enqueued in batches of
-// `check_every` (0 -> 16); behind each batch the outcome fields travel to a pinned host
-// slot.  The host waits for a batch's outcome only after the next batch is enqueued,
-// so the device never drains between batches; an outcome is seen one batch late, and
-// the launches of the batch then in flight return at once.  Afterwards the iterate
-// takes the stopping launch's alpha p.  Returns the done code (1 converged, 2
-// breakdown, 3 kmax) or a negative status; cnt->iters is the stopping launch.
+// `check_every` (0 -> 16), each followed by an event.  The stopping launch writes its
+// stop code into pinned host memory as well; the host looks at it after a batch's
+// event has completed, and only once the next batch is enqueued, so the device never
+// drains between batches and no copy runs between them.  An outcome is seen at most
+// one batch late; the launches still in flight then return at once.  Afterwards the
+// outcome fields are copied once and the iterate takes the stopping launch's alpha p.
+// Returns the done code (1 converged, 2 breakdown, 3 kmax) or a negative status;
+// cnt->iters is the stopping launch.
 template <typename T>
 static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, hipStream_t st,
                     CgCount* cnt, long long k0) {
@@ -1000,11 +1016,14 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
     set_error("internal: the CG iteration kernel needs 4- or 8-row tasks");
     return MFP_E_ARG;
   }
-  OutcomeCopy* slots = outcome_slots();
-  if (!slots) {
-    set_error("pinned host memory for the convergence flag: allocation failed");
+  int* flag_dev = nullptr;
+  HostIo* io = host_io(&flag_dev);
+  if (!io) {
+    set_error("pinned host memory for the stop flag: allocation failed");
     return MFP_E_HIP;
   }
+  volatile int* flag = &io->flag;
+  *flag = 0;  // no launch of an earlier run is in flight (every run ends synchronised)
   const int G = step_blocks<T>(w.L);
   const int every = o.check_every > 0 ? o.check_every : 16;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
@@ -1013,6 +1032,7 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
   const int nev_c = nev > 32 ? 32 : nev;
   hipEvent_t ev[2][2 * 32], fev[2];
   long long tj[2][32];  // launch index of each timed launch
+  int used_n[2] = {0, 0};
   int created = 0, fcreated = 0;
   int status = MFP_OK;
   for (int s2 = 0; s2 < 2 && status == MFP_OK; ++s2) {
@@ -1023,15 +1043,26 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
       else ++created;
     }
   }
-  const char* state_bytes = reinterpret_cast<const char*>(run.a.st);
-  const size_t out_off = offsetof(DevState, iters);
-  const size_t out_len = offsetof(DevState, done) + sizeof(int) - out_off;
+  auto account = [&](int sl, long long stop) {
+    // only launches that did work count (launches after the outcome return at once)
+    for (int i = 0; i < used_n[sl]; ++i) {
+      if (tj[sl][i] >= stop) break;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, ev[sl][2 * i], ev[sl][2 * i + 1]) == hipSuccess) {
+        cnt->tsum += ms;
+        ++cnt->tcnt;
+      }
+    }
+    used_n[sl] = 0;
+  };
   long long j = k0;
   run.a.k0 = k0;
+  run.a.host_done = flag_dev;
+  const long long guard =
+      (o.kmax > 2000 + 2 * k0 ? o.kmax : 2000 + 2 * k0) + 2LL * every + 2;
   int slot = 0;
   bool have_prev = false;
-  int used_prev = 0;
-  OutcomeCopy outcome{};
+  int seen_slot = -1;  // batch after whose event the stop code was seen
   while (status == MFP_OK) {
     int used = 0;
     for (int m = 0; m < every; ++m, ++j) {
@@ -1045,10 +1076,8 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
         launch_step<T>(G, st, a, w.L.hc);
       }
     }
+    used_n[slot] = used;
     hipError_t le = hipGetLastError();
-    if (le == hipSuccess)
-      le = hipMemcpyAsync(reinterpret_cast<char*>(&slots[slot]) + offsetof(OutcomeCopy, iters),
-                          state_bytes + out_off, out_len, hipMemcpyDeviceToHost, st);
     if (le == hipSuccess) le = hipEventRecord(fev[slot], st);
     if (le == hipSuccess && have_prev) le = hipEventSynchronize(fev[slot ^ 1]);
     if (le != hipSuccess) {
@@ -1057,30 +1086,32 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
       break;
     }
     if (have_prev) {
-      const OutcomeCopy prev = slots[slot ^ 1];
-      // only launches that did work count (launches after the outcome return at once)
-      for (int i = 0; i < used_prev; ++i) {
-        if (prev.done && tj[slot ^ 1][i] >= prev.iters) break;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, ev[slot ^ 1][2 * i], ev[slot ^ 1][2 * i + 1]) == hipSuccess) {
-          cnt->tsum += ms;
-          ++cnt->tcnt;
-        }
-      }
-      if (prev.done) {
-        outcome = prev;
+      if (*flag != 0) {
+        seen_slot = slot ^ 1;
         break;
       }
+      account(slot ^ 1, j);  // entirely before the stop
+      // every run stops by its iteration cap; should the flag never show, the device
+      // state decides after the loop
+      if (j - k0 > guard) break;
     }
     have_prev = true;
-    used_prev = used;
     slot ^= 1;
   }
-  // the batch still in flight (launches that return at once) ends before its events go
-  if (status == MFP_OK && hipEventSynchronize(fev[slot]) != hipSuccess) {
-    set_error("CG loop: event synchronisation failed");
+  // the batch still in flight (launches that return at once) ends, then the outcome
+  hipError_t le = hipSuccess;
+  if (status == MFP_OK) le = hipEventSynchronize(fev[slot]);
+  if (status == MFP_OK && le == hipSuccess)
+    le = hipMemcpyAsync(&io->out, reinterpret_cast<const char*>(run.a.st) + offsetof(DevState, iters),
+                        offsetof(DevState, done) + sizeof(int) - offsetof(DevState, iters),
+                        hipMemcpyDeviceToHost, st);
+  if (status == MFP_OK && le == hipSuccess) le = hipStreamSynchronize(st);
+  if (status == MFP_OK && le != hipSuccess) {
+    set_error("CG loop: %s", hipGetErrorString(le));
     status = MFP_E_HIP;
   }
+  const OutcomeCopy outcome = io->out;
+  if (status == MFP_OK && seen_slot >= 0) account(seen_slot, outcome.iters);
   for (int s2 = 0; s2 < 2; ++s2) {
     for (int i = 0; i < 2 * nev_c && created > 0; ++i, --created) (void)hipEventDestroy(ev[s2][i]);
     if (fcreated > 0) {
@@ -1089,6 +1120,10 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
     }
   }
   if (status != MFP_OK) return status;
+  if (outcome.done == 0) {
+    set_error("internal: CG loop ended without an outcome");
+    return MFP_E_HIP;
+  }
   k_finish<T><<<loop_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, run.a.x, run.p[0], run.p[1], run.a.st);
   MFP_TRY_HIP(hipGetLastError());
   cnt->iters = outcome.iters;

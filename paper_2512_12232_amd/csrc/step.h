@@ -109,6 +109,7 @@ struct StepArgs {
   // the per-launch pointers; G = this system's blocks
   int kdev;
   int G;
+  int* host_done;                // single solve: stop code also written here (pinned host)
   T* rs[2];
   T* ps[2];
   T* qs[2];
@@ -370,6 +371,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
         st->iters = j;
         st->rr_final = rr_j;
         st->rr_prev = rr_prev;
+        if (a.host_done) *a.host_done = code;  // pinned host memory the host polls
       } else {
         st->beta = beta;
       }
