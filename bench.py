@@ -121,9 +121,10 @@ def _timed(fn, reps=1):
     return out, 1e3 * best
 
 
-def mixed_precision(mfp, W):
+def mixed_precision(mfp, W, kmax=10 ** 7):
     """4096 x 2048 cells (delta 0.5): FP32 apply with FP64 refinement against plain
-    FP64 CG, both to relative residual 1e-10, and plain FP32 CG to 1e-6."""
+    FP64 CG, both to relative residual 1e-10, and plain FP32 CG to 1e-6.  A small kmax
+    cuts every solve short (profiling runs: per-launch figures only)."""
     case = W.five_cyl_4096()
     disp, kind, body = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device="cuda:0")
     out = {"workload": "five cylinders, 4096x2048 cells, delta 0.5, rtol 1e-10"}
@@ -132,7 +133,7 @@ def mixed_precision(mfp, W):
     nbytes32, _ = step_bytes(case, disp, body, esz=4)
     for prec, rtol in (("fp64", 1e-10), ("fp32_ir", 1e-10), ("fp32", 1e-6)):
         r, ms = _timed(lambda: mfp.psi_solve(case.grid, case.circles, disp, kind, body,
-                                             case.flow, precision=prec, rtol=rtol,
+                                             case.flow, precision=prec, rtol=rtol, kmax=kmax,
                                              pair=case.pair, sample_cap=0, profile_every=17))
         res[prec] = r
         out[prec] = {"solve_ms": round(ms, 2), "iters": r.stats["iters"],
@@ -251,6 +252,12 @@ def main():
                          "leaves the device idle for a few microseconds, so sparsely)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy (counter calibration)")
+    ap.add_argument("--mixed-only", action="store_true",
+                    help="only run the 4096x2048 FP64 / FP32+refinement / FP32 comparison "
+                         "and print its JSON (for profiling that workload)")
+    ap.add_argument("--mixed-kmax", type=int, default=10 ** 7,
+                    help="with --mixed-only: iteration cap of every solve (short "
+                         "profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -270,6 +277,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"calibration": "copy", "bytes": a.numel() * 8}), flush=True)
+        return
+    if args.mixed_only:
+        print(json.dumps({"mixed_precision_4096x2048": mixed_precision(mfp, W, args.mixed_kmax)}),
+              flush=True)
         return
     case = W.five_cyl_1024()
     dev = "cuda:0"
