@@ -291,3 +291,32 @@ def test_full_size_4096x2048_matches_oracle_reference(mfp, precision):
     say(f"  {precision}: iters {res.stats['iters']} relres {res.stats['relres_true']:.2e} "
         f"max|dpsi|/max|psi| {dpsi:.2e} max|dpsi_b| {dpb:.2e} |dCoPFI| {dcop:.2e}")
     assert dpsi <= 5e-9 and dpb <= 5e-9 and dcop <= 5e-9
+
+
+def test_bench_workload_1024x512_matches_oracle_direct_solve(mfp):
+    """The benchmark's workload at its full size (1024x512, 520,722 unknowns) and in
+    the benchmark's configuration (FP64 to relative residual 1e-12, default batches)
+    against the oracle's direct sparse solve: nodal psi, psi_b, Q, CoPFI and every
+    surface sample.  At kappa ~ 1e5 a residual of 1e-12 allows relative errors up to
+    ~1e-7 in the worst case; measured: psi 1.0e-11, psi_b 1.8e-11, Q 3.5e-11, CoPFI
+    1.4e-11, u_t 6.8e-11 of max|u_t|.  Bars: 2e-10 on psi (relative L2) and on psi_b,
+    Q, CoPFI (absolute), 1e-8 of max|u_t| on u_t (it divides psi differences by d ~ h)."""
+    c = W.five_cyl_1024()
+    res, ref, mesh = run_pair(mfp, c, rtol=1e-12)
+    assert res.status == 0 and res.stats["relres_true"] <= 1.5e-12
+    assert res.stats["n_dof"] == ref.ndof
+    psi = res.psi.cpu().numpy()
+    err = np.linalg.norm(psi - ref.psi) / np.linalg.norm(ref.psi)
+    dpb = np.abs(np.array(res.psi_b) - ref.psi_b).max()
+    lo, hi = c.pair
+    Q, J = O.copfi(ref.psi_b, lo, hi, c.flow.U, c.circles[lo][1], c.circles[hi][1])
+    th, ut, bb = O.surface_samples(mesh, ref.psi, ref.psi_b)
+    dut = np.abs(res.ut.cpu().numpy() - ut).max() / np.abs(ut).max()
+    say(f"  psi rel err {err:.2e} max|dpsi_b| {dpb:.2e} |dQ| {abs(res.Q - Q):.2e} "
+        f"|dCoPFI| {abs(res.copfi - J):.2e} u_t {dut:.2e} ({len(th)} samples)")
+    assert err <= 2e-10 and dpb <= 2e-10
+    assert abs(res.Q - Q) <= 2e-10 and abs(res.copfi - J) <= 2e-10
+    assert res.n_samples == len(th)
+    assert np.array_equal(res.sample_body.cpu().numpy(), bb)
+    np.testing.assert_allclose(res.theta.cpu().numpy(), th, rtol=0, atol=1e-12)
+    assert dut <= 1e-8
