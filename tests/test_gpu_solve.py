@@ -273,24 +273,30 @@ def test_full_size_4096x2048_matches_oracle_reference(mfp, precision):
     """The 4096x2048 workload against the oracle's own solution: its plain FP64 CG on the
     assembled reduced system to a true relative residual <= 1e-13, stored with psi_b,
     CoPFI and psi at 2000 seeded free nodes (tests/golden, written by the committed
-    script beside it).  GPU solves to 1e-12 (FP64, and FP32 with FP64 refinement on 8-row
-    tasks).  Both sides are iterative: they differ by the two residuals amplified by the
-    conditioning (about 1.6e6 here), so the bars are 5e-9 of max|psi| for psi and psi_b
-    and 5e-9 for CoPFI."""
+    script beside it).  GPU solves to 1e-13, the FP64 floor (FP64, and FP32 with FP64
+    refinement on 8-row tasks).  Bars: relative L2 error of psi over the stored nodes
+    <= 1e-10 (the refined-FP32 target), psi_b and CoPFI within 1e-10 absolute (psi_b
+    is O(1)).  Measured: FP64 7.5e-12 / 3.0e-11 / 1.8e-11, FP32 + refinement
+    2.1e-11 / 6.3e-11 / 4.8e-12."""
     meta, nodes, ref = _reference_4096()
     c = W.five_cyl_4096()
     disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
-    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12,
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13,
                         precision=precision, pair=c.pair, sample_cap=0)
-    assert res.status == 0 and res.stats["relres_true"] <= 1.5e-12
+    # plain FP64 CG stops on its recursive residual, which at kappa ~ 1.6e6 drifts from
+    # the true one near 1e-13 (measured 2.4e-13); the refined solve replaces its
+    # residual with the FP64 one and stops on that
+    assert res.status == 0
+    assert res.stats["relres_true"] <= (3e-13 if precision == "fp64" else 1.5e-13)
     psi = res.psi.cpu().numpy()
-    scale = np.abs(psi).max()
-    dpsi = np.abs(psi[nodes] - ref).max() / scale
-    dpb = np.abs(np.array(res.psi_b) - np.array(meta["psi_b"])).max() / scale
+    rel = np.linalg.norm(psi[nodes] - ref) / np.linalg.norm(ref)
+    dmax = np.abs(psi[nodes] - ref).max() / np.abs(psi).max()
+    dpb = np.abs(np.array(res.psi_b) - np.array(meta["psi_b"])).max()
     dcop = abs(res.copfi - meta["copfi"][0])
     say(f"  {precision}: iters {res.stats['iters']} relres {res.stats['relres_true']:.2e} "
-        f"max|dpsi|/max|psi| {dpsi:.2e} max|dpsi_b| {dpb:.2e} |dCoPFI| {dcop:.2e}")
-    assert dpsi <= 5e-9 and dpb <= 5e-9 and dcop <= 5e-9
+        f"psi rel L2 {rel:.2e} max|dpsi|/max|psi| {dmax:.2e} max|dpsi_b| {dpb:.2e} "
+        f"|dCoPFI| {dcop:.2e}")
+    assert rel <= 1e-10 and dpb <= 1e-10 and dcop <= 1e-10
 
 
 def test_bench_workload_1024x512_matches_oracle_direct_solve(mfp):
