@@ -99,3 +99,31 @@ def test_host_paths_reach_the_runtime_without_crashing(lib):
     assert st == B.MFP_E_HIP
     st = lib.mfp_mesh_conform(ctypes.byref(g), c, 1, 200, fake, fake, fake, fake, big, None)
     assert st == B.MFP_E_HIP
+
+
+def test_grid_size_limit_is_reported_before_device_work(lib):
+    """The solver's layout limits (at most 2048 strips of 62 node columns, 65535 chunks
+    of 4 node rows, padded vectors < 4 GiB): one past the column limit is rejected with
+    MFP_E_ARG before any device call; the largest accepted width gets past the check
+    (on a machine without a device it then fails at the first HIP call)."""
+    import torch
+    from paper_2512_12232_amd import binding as B
+    import paper_2512_12232_amd as mfp
+    fake = ctypes.c_void_p(4096)
+    c = B.make_circles([(0, 0, 0.5)])
+    f = B.make_flow(W.Flow())
+    o = B.MfpSolverOpts(B.FP64, 1e-12, 100, 10, 1e-4, 10, None)
+    psib = (ctypes.c_double * 1)()
+    ns = ctypes.c_int32(0)
+    stats = B.MfpStats()
+    q = ctypes.c_double(0)
+
+    def solve(nx):
+        g = B.make_grid(W.Grid(nx, 100, -nx * 0.01, nx * 0.01, -1, 1))
+        return lib.mfp_psi_solve(ctypes.byref(g), c, 1, fake, fake, fake, ctypes.byref(f),
+                                 ctypes.byref(o), 0, 0, fake, psib, ctypes.byref(q),
+                                 ctypes.byref(q), fake, fake, 4, ctypes.byref(ns),
+                                 ctypes.byref(stats), fake, 1 << 44, None)
+    assert solve(2048 * 62) == B.MFP_E_ARG and "grid too large" in mfp.last_error()
+    if not torch.cuda.is_available():
+        assert solve(2048 * 62 - 1) == B.MFP_E_HIP
