@@ -121,6 +121,16 @@ def _timed(fn, reps=1):
     return out, 1e3 * best
 
 
+def _task_height(case, n_tiles):
+    """Node rows per task of a solve's layout, from its task count (strips of 62 node
+    columns x chunks of hc node rows)."""
+    strips = -(-(case.grid.nx + 1) // 62)
+    for hc in (4, 5, 8):
+        if strips * -(-(case.grid.ny + 1) // hc) == n_tiles:
+            return hc
+    return 0
+
+
 def mixed_precision(mfp, W, kmax=10 ** 7):
     """4096 x 2048 cells (delta 0.5): FP32 apply with FP64 refinement against plain
     FP64 CG, both to relative residual 1e-10, and plain FP32 CG to 1e-6.  A small kmax
@@ -142,10 +152,7 @@ def mixed_precision(mfp, W, kmax=10 ** 7):
         if r.stats["apply_samples"] > 0:
             nbytes = nbytes64 if prec == "fp64" else nbytes32
             kms = r.stats["apply_ms"]
-            # task height of the solve's layout, from its task count (4-row tasks:
-            # strips of 62 node columns x chunks of 4 node rows)
-            tasks4 = -(-(case.grid.nx + 1) // 62) * -(-(case.grid.ny + 1) // 4)
-            hc = 4 if r.stats["n_tiles"] == tasks4 else 8
+            hc = _task_height(case, r.stats["n_tiles"])
             out[prec]["roofline"] = {
                 "kernel": "k_step<%s, %d>" % ("double" if prec == "fp64" else "float", hc),
                 "launch_ms": round(kms, 5), "bytes_per_launch": nbytes,
@@ -358,7 +365,8 @@ def main():
         achieved = nbytes / (ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic_from_profile(), "kernel": "k_step<double, 4>",
+                    "traffic": traffic_from_profile(),
+                    "kernel": "k_step<double, %d>" % _task_height(case, res.stats["n_tiles"]),
                     "launch_ms": round(ms, 5), "bytes_per_launch": nbytes,
                     "samples": int(sum(r.stats["apply_samples"] for _, _, r in outs))}
     cpu = None

@@ -417,12 +417,16 @@ inline void launch_apply(int hc, int G, hipStream_t st, const ApplyArgs<T>& a,
   if (e0) {
     if (hc == 4)
       hipExtLaunchKernelGGL(k_apply<T, 4>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
+    else if (hc == 5)
+      hipExtLaunchKernelGGL(k_apply<T, 5>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
     else
       hipExtLaunchKernelGGL(k_apply<T, 8>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
     return;
   }
   if (hc == 4)
     k_apply<T, 4><<<G, BLOCK, 0, st>>>(a);
+  else if (hc == 5)
+    k_apply<T, 5><<<G, BLOCK, 0, st>>>(a);
   else
     k_apply<T, 8><<<G, BLOCK, 0, st>>>(a);
 }

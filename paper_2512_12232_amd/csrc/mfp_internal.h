@@ -94,7 +94,7 @@ inline Layout make_layout(int nx, int ny, int hc_force = 0) {
   L.nx = nx;
   L.ny = ny;
   L.nstrip = (nx + 1 + SW - 1) / SW;
-  L.hc = hc_force == 8 ? 8 : 4;
+  L.hc = (hc_force == 8 || hc_force == 5) ? hc_force : 4;
   L.nchunk = (ny + 1 + L.hc - 1) / L.hc;
   L.P = 64 * L.nstrip;
   L.rows = L.hc * L.nchunk + 2;

@@ -514,8 +514,9 @@ static int step_resident_waves(int hc = 4) {
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  const void* f = hc == 8 ? reinterpret_cast<const void*>(&k_step<T, 8, false, true>)
-                          : reinterpret_cast<const void*>(&k_step<T, 4, false, true>);
+  const void* f = hc == 8   ? reinterpret_cast<const void*>(&k_step<T, 8, false, true>)
+                  : hc == 5 ? reinterpret_cast<const void*>(&k_step<T, 5, false, true>)
+                            : reinterpret_cast<const void*>(&k_step<T, 4, false, true>);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) != hipSuccess) return 0;
   return per_cu * cus * WAVES;
 }
@@ -606,7 +607,15 @@ struct SolveWs {
 // resident wavefronts.  So 8 rows for FP32 once the 4-row layout has at least 8192
 // tasks (twice the 4096 wavefronts of 4-row FP32 tasks that 256 CUs hold), else 4.
 static int solve_hc(const mfp_grid* g, int precision) {
-  if (precision != MFP_FP32 && precision != MFP_FP32_IR) return 4;
+  if (precision != MFP_FP32 && precision != MFP_FP32_IR) {
+    // FP64: 5-row tasks when they fit the resident wavefronts in one round and 4-row
+    // tasks do not (a wavefront with a second task doubles the launch's tail)
+    const int w = step_resident_waves<double>(4);
+    if (w > 0 && make_layout(g->nx, g->ny).ntasks() > w &&
+        make_layout(g->nx, g->ny, 5).ntasks() <= step_resident_waves<double>(5))
+      return 5;
+    return 4;
+  }
   return make_layout(g->nx, g->ny).ntasks() >= 8192 ? 8 : 4;
 }
 
@@ -1012,8 +1021,8 @@ static HostIo* host_io(int** flag_dev) {
 template <typename T>
 static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, hipStream_t st,
                     CgCount* cnt, long long k0) {
-  if (w.L.hc != 4 && w.L.hc != 8) {
-    set_error("internal: the CG iteration kernel needs 4- or 8-row tasks");
+  if (w.L.hc != 4 && w.L.hc != 5 && w.L.hc != 8) {
+    set_error("internal: the CG iteration kernel needs 4-, 5- or 8-row tasks");
     return MFP_E_ARG;
   }
   int* flag_dev = nullptr;

@@ -529,6 +529,8 @@ inline void launch_step(int G, hipStream_t st, const StepArgs<T>& a, int hc,
                         hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   if (hc == 8)
     launch_step_h<T, 8>(G, st, a, e0, e1);
+  else if (hc == 5)
+    launch_step_h<T, 5>(G, st, a, e0, e1);
   else
     launch_step_h<T, 4>(G, st, a, e0, e1);
 }

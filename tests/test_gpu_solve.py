@@ -311,6 +311,9 @@ def test_bench_workload_1024x512_matches_oracle_direct_solve(mfp):
     c = W.five_cyl_1024()
     res, ref, mesh = run_pair(mfp, c, rtol=1e-12)
     assert res.status == 0 and res.stats["relres_true"] <= 1.5e-12
+    # 17 strips x 103 chunks of 5 rows: the layout of 5-row tasks (2193 4-row tasks
+    # would not fit the resident wavefronts in one round)
+    say(f"  tasks {res.stats['n_tiles']}")
     assert res.stats["n_dof"] == ref.ndof
     psi = res.psi.cpu().numpy()
     err = np.linalg.norm(psi - ref.psi) / np.linalg.norm(ref.psi)
