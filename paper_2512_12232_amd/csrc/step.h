@@ -210,6 +210,10 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   T nr[HC + 2], nq[HC + 2], np[HC + 2], nx[HC], n2[HC];  // n2: p_{j-2} (XUPD)
   int n_plain = 1, n_body = 0, n_slot = -1;
   auto fetch = [&](int t) {
+    // flags first: the geometry request waits for them, not for the rows
+    n_plain = tplain[t];
+    n_body = tbody[t] != 0ull;
+    n_slot = tslot[t];
     const unsigned bo = (unsigned)((int)node0(t) + shift_of(t)) * TS;
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
@@ -225,46 +229,45 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
         n2[r] = ld_at((const gmem<T>*)pcg, bo + (r + 1) * RB);
       }
     }
-    n_plain = tplain[t];
-    n_body = tbody[t] != 0ull;
-    n_slot = tslot[t];
   };
-  int t = vb * WAVES + wv;
-  if (t < ntask) fetch(t);
-
   // ---- scalars of iteration j ----
-  // Everything they need is requested here, in one round trip: the state, lane b's
-  // body values, the previous launch's partials and its per-body slot sums (wave w:
-  // bodies w and w + 4 from the first 64 slots; more bodies or slots in a second pass).
+  // Everything they need is requested first, in one round trip, ahead of the task's
+  // rows: the previous launch's partials, the state, lane b's body values and the
+  // per-body slot sums (wave w: bodies w and w + 4 from the first 64 slots; more
+  // bodies or slots in a second pass).  These loads, and the rows', are unconditional
+  // (clamped indices, values past the end dropped when used): the counter a wavefront
+  // waits on counts loads in issue order, and a load under a branch makes the wait for
+  // anything issued before it a wait for everything.  So the scalars are reduced while
+  // the rows travel, and the first task's geometry is requested right after the flags
+  // arrive, together with the partials.
+  const int npart = start ? a.npart0 : G;  // at least 1
+  const gmem<double>* const pt = part_pg;
+  constexpr int PU = 2;
+  double pv[PU][4];
+#pragma unroll
+  for (int u = 0; u < PU; ++u) {
+    const int i = min(tid + u * BLOCK, npart - 1);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) pv[u][c] = pt[4 * i + c];
+  }
   const int nb = a.nb, nsl = a.nslots;
   const int done = st->done;
   const double rr_stop = st->rr_stop, rr_prev_start = st->rr_prev, stop_rel = st->stop_rel;
   const double alpha2 = st->alpha_hist[prv];  // alpha_{j-2}
   const long long kmax = st->kmax;
-  double rbp = 0.0, pbp = 0.0, xbp = 0.0;  // lane b: body b of iteration j-1
-  if (lane < nb) {
-    rbp = st->rb[prv][lane];
-    pbp = st->pb[prv][lane];
-    xbp = st->xb[prv][lane];
-  }
+  // lane b: body b of iteration j-1 (the state holds MFP_MAX_BODIES = 64 of each)
+  const bool lb = lane < nb;
+  const double rbp_l = st->rb[prv][lane], pbp_l = st->pb[prv][lane], xbp_l = st->xb[prv][lane];
+  // slot sums of bodies b0, b1 (K p of iteration j-1); the slot buffer holds at least
+  // 64 slots of max(nb, 1) bodies
   const gmem<double>* const bq = bpart_pg;
   const int b0 = wv, b1 = wv + WAVES;
-  double q0 = 0.0, q1 = 0.0;  // slot sums of bodies b0, b1 (K p of iteration j-1)
-  if (!start && lane < nsl) {
-    if (b0 < nb) q0 = bq[(long long)lane * nb + b0];
-    if (b1 < nb) q1 = bq[(long long)lane * nb + b1];
-  }
-  const int npart = start ? a.npart0 : G;
-  const gmem<double>* const pt = part_pg;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-  for (int i = tid; i < npart; i += BLOCK) {
-    s0 += pt[4 * i];
-    s1 += pt[4 * i + 1];
-    s2 += pt[4 * i + 2];
-    s3 += pt[4 * i + 3];
-  }
-  // the first task's geometry is requested now (its flag has arrived with the
-  // partials), so that it travels while the scalars are reduced
+  const int nbc = nb > 0 ? nb : 1;
+  const double q0_l = bq[(long long)lane * nb + min(b0, nbc - 1)];
+  const double q1_l = bq[(long long)lane * nb + min(b1, nbc - 1)];
+  int t = vb * WAVES + wv;
+  fetch(t < ntask ? t : ntask - 1);  // a wavefront without a task drops what it fetched
+
   int8_t tg[HC + 2];
   T ddx[HC + 2], ddy[HC + 2];
   auto load_geom = [&](int tt) {
@@ -276,7 +279,26 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       ddy[r] = ld_at(dyg, ln0 * TS + r * RB);
     }
   };
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int u = 0; u < PU; ++u) {
+    const bool in = tid + u * BLOCK < npart;
+    s0 += in ? pv[u][0] : 0.0;
+    s1 += in ? pv[u][1] : 0.0;
+    s2 += in ? pv[u][2] : 0.0;
+    s3 += in ? pv[u][3] : 0.0;
+  }
   if (t < ntask && !n_plain) load_geom(t);
+  for (int i = tid + PU * BLOCK; i < npart; i += BLOCK) {  // launches of more than 512 blocks
+    s0 += pt[4 * i];
+    s1 += pt[4 * i + 1];
+    s2 += pt[4 * i + 2];
+    s3 += pt[4 * i + 3];
+  }
+  const double rbp = lb ? rbp_l : 0.0, pbp = lb ? pbp_l : 0.0, xbp = lb ? xbp_l : 0.0;
+  const bool qin = !start && lane < nsl;
+  double q0 = qin && b0 < nb ? q0_l : 0.0;
+  double q1 = qin && b1 < nb ? q1_l : 0.0;
   if (!start) {
     for (int sl = lane + 64; sl < nsl; sl += 64) {
       if (b0 < nb) q0 += bq[(long long)sl * nb + b0];
