@@ -306,15 +306,12 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     }
   }
   // wave sums, six independent chains
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    s0 += __shfl_xor(s0, off, 64);
-    s1 += __shfl_xor(s1, off, 64);
-    s2 += __shfl_xor(s2, off, 64);
-    s3 += __shfl_xor(s3, off, 64);
-    q0 += __shfl_xor(q0, off, 64);
-    q1 += __shfl_xor(q1, off, 64);
-  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  s2 = wave_sum(s2);
+  s3 = wave_sum(s3);
+  q0 = wave_sum(q0);
+  q1 = wave_sum(q1);
   if (lane == 0) {
     s_red[4 * wv] = s0;
     s_red[4 * wv + 1] = s1;
@@ -339,12 +336,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   if (s_red[4 * WAVES] != 0.0) return;  // stopped (the same decision in every wave)
   const double qb = lane < nb ? s_qb[lane] : 0.0;
   // body parts of r.r and p.Kp, two independent chains
-  double brr = rbp * rbp, bpq = pbp * qb;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    brr += __shfl_xor(brr, off, 64);
-    bpq += __shfl_xor(bpq, off, 64);
-  }
+  const double brr = wave_sum(rbp * rbp), bpq = wave_sum(pbp * qb);
   const double S_rr = (s_red[0] + s_red[4]) + (s_red[8] + s_red[12]);
   const double S_pq = (s_red[1] + s_red[5]) + (s_red[9] + s_red[13]);
   const double S_rq = (s_red[2] + s_red[6]) + (s_red[10] + s_red[14]);
@@ -473,13 +465,10 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     if (bm && lane < nb) bpart_cg[(long long)slot * nb + lane] = bacc;
   }
   // four block sums, fixed order
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    prr += __shfl_xor(prr, off, 64);
-    ppq += __shfl_xor(ppq, off, 64);
-    prq += __shfl_xor(prq, off, 64);
-    pqq += __shfl_xor(pqq, off, 64);
-  }
+  prr = wave_sum(prr);
+  ppq = wave_sum(ppq);
+  prq = wave_sum(prq);
+  pqq = wave_sum(pqq);
   __syncthreads();  // s_red was read above by every thread
   if (lane == 0) {
     s_red[4 * wv] = prr;
