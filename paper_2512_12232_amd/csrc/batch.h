@@ -351,7 +351,7 @@ static StepArgs<T> batch_step_args(const SolveWs& w, const mfp_grid& g, int nb, 
   StepArgs<T> a = run.a;
   a.kdev = 1;
   a.G = GS;
-  a.stream = 0;
+  a.stream = 1;  // k_step_batch stores streaming
   a.npart0 = npart0;
   for (int s = 0; s < 2; ++s) {
     a.rs[s] = run.r[s];
