@@ -144,7 +144,7 @@ def mixed_precision(mfp, W, kmax=10 ** 7):
     for prec, rtol in (("fp64", 1e-10), ("fp32_ir", 1e-10), ("fp32", 1e-6)):
         r, ms = _timed(lambda: mfp.psi_solve(case.grid, case.circles, disp, kind, body,
                                              case.flow, precision=prec, rtol=rtol, kmax=kmax,
-                                             pair=case.pair, sample_cap=0, profile_every=17))
+                                             pair=case.pair, sample_cap=0, profile_every=1))
         res[prec] = r
         out[prec] = {"solve_ms": round(ms, 2), "iters": r.stats["iters"],
                      "relres_true": r.stats["relres_true"], "rtol": rtol,
@@ -300,10 +300,10 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the 4096x2048 mixed-precision, adjoint and delta-sweep "
                          "measurements")
-    ap.add_argument("--profile-every", type=int, default=101,
-                    help="time every n-th iteration launch with HIP events (0: off; odd, "
-                         "so that both launch parities are sampled; each timed launch "
-                         "leaves the device idle for a few microseconds, so sparsely)")
+    ap.add_argument("--profile-every", type=int, default=1,
+                    help="time every n-th batch of iteration launches with HIP events "
+                         "(0: off); a batch is timed between the events that end it and "
+                         "the batch before it, which the host loop records anyway")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a 256 MiB device-to-device copy (counter calibration)")
     ap.add_argument("--mixed-only", action="store_true",
@@ -357,11 +357,12 @@ def main():
     disp, body, res = outs[-1]
     dof_iters = sum(r.stats["n_dof"] * r.stats["iters"] for _, _, r in outs)
     value = dof_iters / wall
-    apply_ms = [r.stats["apply_ms"] for _, _, r in outs if r.stats["apply_samples"] > 0]
+    timed = [(r.stats["apply_ms"], r.stats["apply_samples"]) for _, _, r in outs
+             if r.stats["apply_samples"] > 0]
     nbytes, moved = step_bytes(case, disp, body)
     roofline = None
-    if apply_ms:
-        ms = sum(apply_ms) / len(apply_ms)
+    if timed:
+        ms = sum(m * n for m, n in timed) / sum(n for _, n in timed)
         achieved = nbytes / (ms * 1e-3) / 1e9
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

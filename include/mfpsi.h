@@ -106,7 +106,9 @@ typedef struct {
   const double* psi0;     /* optional DEVICE warm start: nodal psi (free nodes) and the
                              first node of each body (row-major) for psi_b; rtol is then
                              relative to the residual of this start; may be NULL       */
-  int32_t profile_every;  /* > 0: time every n-th apply launch with HIP events -> stats */
+  int32_t profile_every;  /* > 0: time every n-th batch of iteration launches with HIP
+                             events (between the events that end it and the batch
+                             before it) -> stats.apply_ms                              */
 } mfp_solver_opts;
 
 typedef struct {
@@ -118,7 +120,7 @@ typedef struct {
   double relres_true;     /* ||b - A x|| / ||b - A x0|| recomputed in FP64 at the end   */
   double rnorm0;          /* ||b - A x0||                                               */
   double solve_ms;        /* device time of the iteration phase (HIP events)            */
-  double apply_ms;        /* mean duration of one apply launch (profile_every > 0)      */
+  double apply_ms;        /* mean time per iteration launch in the timed batches        */
   int64_t apply_samples;  /* launches behind apply_ms                                   */
   int64_t n_plain_tiles;  /* 64x8 node tiles on the constant-stencil path               */
   int64_t n_tiles;        /* all node tiles                                             */

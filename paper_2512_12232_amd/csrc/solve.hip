@@ -1020,6 +1020,9 @@ static HostIo* host_io(int** flag_dev) {
 // drains between batches and no copy runs between them.  An outcome is seen at most
 // one batch late; the launches still in flight then return at once.  Afterwards the
 // outcome fields are copied once and the iterate takes the stopping launch's alpha p.
+// With profile_every = n > 0, every n-th batch that ends before the stop is timed
+// between the events that end it and the batch before it (nothing else runs on the
+// stream in between), and its mean per launch enters cnt.
 // Returns the done code (1 converged, 2 breakdown, 3 kmax) or a negative status;
 // cnt->iters is the stopping launch.
 template <typename T>
@@ -1040,80 +1043,54 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
   const int G = step_blocks<T>(w.L);
   const int every = o.check_every > 0 ? o.check_every : 16;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
-  // launches k0, k0 + prof, ... are timed (prof odd samples both launch parities)
-  const int nev = prof ? every / prof + 1 : 0;
-  const int nev_c = nev > 32 ? 32 : nev;
-  hipEvent_t ev[2][2 * 32], fev[2];
-  long long tj[2][32];  // launch index of each timed launch
-  int used_n[2] = {0, 0};
-  int created = 0, fcreated = 0;
+  // ev[b % NE] marks the end of batch b - 1 (ev[0]: the start of batch 0); an event is
+  // re-recorded three batches after it was last read
+  constexpr int NE = 4;
+  hipEvent_t ev[NE];
+  int created = 0;
   int status = MFP_OK;
-  for (int s2 = 0; s2 < 2 && status == MFP_OK; ++s2) {
-    if (hipEventCreateWithFlags(&fev[s2], hipEventDisableTiming) != hipSuccess) status = MFP_E_HIP;
-    else ++fcreated;
-    for (int i = 0; i < 2 * nev_c && status == MFP_OK; ++i) {
-      if (hipEventCreate(&ev[s2][i]) != hipSuccess) status = MFP_E_HIP;
-      else ++created;
-    }
+  for (int i = 0; i < NE && status == MFP_OK; ++i) {
+    if (hipEventCreateWithFlags(&ev[i], prof ? hipEventDefault : hipEventDisableTiming) !=
+        hipSuccess)
+      status = MFP_E_HIP;
+    else
+      ++created;
   }
-  auto account = [&](int sl, long long stop) {
-    // only launches that did work count (launches after the outcome return at once)
-    for (int i = 0; i < used_n[sl]; ++i) {
-      if (tj[sl][i] >= stop) break;
-      float ms = 0.f;
-      if (hipEventElapsedTime(&ms, ev[sl][2 * i], ev[sl][2 * i + 1]) == hipSuccess) {
-        cnt->tsum += ms;
-        ++cnt->tcnt;
-      }
-    }
-    used_n[sl] = 0;
-  };
   long long j = k0;
   run.a.k0 = k0;
   run.a.host_done = flag_dev;
   const long long guard =
       (o.kmax > 2000 + 2 * k0 ? o.kmax : 2000 + 2 * k0) + 2LL * every + 2;
-  int slot = 0;
-  bool have_prev = false;
-  int seen_slot = -1;  // batch after whose event the stop code was seen
+  long long b = 0;  // batch being enqueued
+  if (status == MFP_OK && hipEventRecord(ev[0], st) != hipSuccess) status = MFP_E_HIP;
   while (status == MFP_OK) {
-    int used = 0;
-    for (int m = 0; m < every; ++m, ++j) {
-      const StepArgs<T> a = run.at(j);
-      const bool timed = prof && ((j - k0) % prof == 0) && used < nev_c;
-      if (timed) {
-        tj[slot][used] = j;
-        launch_step<T>(G, st, a, w.L.hc, ev[slot][2 * used], ev[slot][2 * used + 1]);
-        ++used;
-      } else {
-        launch_step<T>(G, st, a, w.L.hc);
-      }
-    }
-    used_n[slot] = used;
+    for (int m = 0; m < every; ++m, ++j) launch_step<T>(G, st, run.at(j), w.L.hc);
     hipError_t le = hipGetLastError();
-    if (le == hipSuccess) le = hipEventRecord(fev[slot], st);
-    if (le == hipSuccess && have_prev) le = hipEventSynchronize(fev[slot ^ 1]);
+    if (le == hipSuccess) le = hipEventRecord(ev[(b + 1) % NE], st);
+    if (le == hipSuccess && b > 0) le = hipEventSynchronize(ev[b % NE]);  // batch b - 1
     if (le != hipSuccess) {
       set_error("CG loop: %s", hipGetErrorString(le));
       status = MFP_E_HIP;
       break;
     }
-    if (have_prev) {
-      if (*flag != 0) {
-        seen_slot = slot ^ 1;
-        break;
+    if (b > 0) {
+      if (*flag != 0) break;  // batch b - 1 held the stopping launch
+      if (prof && (b - 1) % prof == 0) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, ev[(b - 1) % NE], ev[b % NE]) == hipSuccess) {
+          cnt->tsum += ms;
+          cnt->tcnt += every;
+        }
       }
-      account(slot ^ 1, j);  // entirely before the stop
       // every run stops by its iteration cap; should the flag never show, the device
       // state decides after the loop
       if (j - k0 > guard) break;
     }
-    have_prev = true;
-    slot ^= 1;
+    ++b;
   }
   // the batch still in flight (launches that return at once) ends, then the outcome
   hipError_t le = hipSuccess;
-  if (status == MFP_OK) le = hipEventSynchronize(fev[slot]);
+  if (status == MFP_OK) le = hipEventSynchronize(ev[(b + 1) % NE]);
   if (status == MFP_OK && le == hipSuccess)
     le = hipMemcpyAsync(&io->out, reinterpret_cast<const char*>(run.a.st) + offsetof(DevState, iters),
                         offsetof(DevState, done) + sizeof(int) - offsetof(DevState, iters),
@@ -1124,14 +1101,7 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
     status = MFP_E_HIP;
   }
   const OutcomeCopy outcome = io->out;
-  if (status == MFP_OK && seen_slot >= 0) account(seen_slot, outcome.iters);
-  for (int s2 = 0; s2 < 2; ++s2) {
-    for (int i = 0; i < 2 * nev_c && created > 0; ++i, --created) (void)hipEventDestroy(ev[s2][i]);
-    if (fcreated > 0) {
-      (void)hipEventDestroy(fev[s2]);
-      --fcreated;
-    }
-  }
+  for (int i = 0; i < created; ++i) (void)hipEventDestroy(ev[i]);
   if (status != MFP_OK) return status;
   if (outcome.done == 0) {
     set_error("internal: CG loop ended without an outcome");
