@@ -509,45 +509,36 @@ __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restr
   step_core<T, 4, true, XUPD>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
 }
 
-// Tasks of HC node rows (the layout's); odd launches update the iterate.
-template <typename T, int HC, bool STREAM, bool XUPD>
-inline void launch_step_i(int G, hipStream_t st, const StepArgs<T>& a, hipEvent_t e0,
-                          hipEvent_t e1) {
-  if (e0)
-    hipExtLaunchKernelGGL(k_step<T, HC, STREAM, XUPD>, dim3(G), dim3(BLOCK), 0, st, e0, e1, 0, a);
-  else
-    k_step<T, HC, STREAM, XUPD><<<G, BLOCK, 0, st>>>(a);
-}
-
+// Tasks of HC node rows (the layout's); odd launches update the iterate; a.stream
+// selects the streaming-store instance.
 template <typename T, int HC>
-inline void launch_step_h(int G, hipStream_t st, const StepArgs<T>& a, hipEvent_t e0,
-                          hipEvent_t e1) {
+inline void launch_step_h(int G, hipStream_t st, const StepArgs<T>& a) {
   const bool xu = (a.j & 1) != 0;
   if (a.stream) {
     if (xu)
-      launch_step_i<T, HC, true, true>(G, st, a, e0, e1);
+      k_step<T, HC, true, true><<<G, BLOCK, 0, st>>>(a);
     else
-      launch_step_i<T, HC, true, false>(G, st, a, e0, e1);
+      k_step<T, HC, true, false><<<G, BLOCK, 0, st>>>(a);
   } else {
     if (xu)
-      launch_step_i<T, HC, false, true>(G, st, a, e0, e1);
+      k_step<T, HC, false, true><<<G, BLOCK, 0, st>>>(a);
     else
-      launch_step_i<T, HC, false, false>(G, st, a, e0, e1);
+      k_step<T, HC, false, false><<<G, BLOCK, 0, st>>>(a);
   }
 }
 
-// hc: the layout's task height, 4, or 8 for FP32 (FP32 8-row tasks use about as many
-// registers as FP64 4-row ones; FP64 8-row tasks would need 256 and run one wavefront
-// per SIMD).
+// hc: the layout's task height: 4; 5 for FP64 where 4-row tasks would outnumber the
+// resident wavefronts and 5-row ones do not; 8 for large FP32 layouts (FP32 8-row
+// tasks use about as many registers as FP64 4-row ones; FP64 8-row tasks would need
+// 256 and run one wavefront per SIMD).
 template <typename T>
-inline void launch_step(int G, hipStream_t st, const StepArgs<T>& a, int hc,
-                        hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
+inline void launch_step(int G, hipStream_t st, const StepArgs<T>& a, int hc) {
   if (hc == 8)
-    launch_step_h<T, 8>(G, st, a, e0, e1);
+    launch_step_h<T, 8>(G, st, a);
   else if (hc == 5)
-    launch_step_h<T, 5>(G, st, a, e0, e1);
+    launch_step_h<T, 5>(G, st, a);
   else
-    launch_step_h<T, 4>(G, st, a, e0, e1);
+    launch_step_h<T, 4>(G, st, a);
 }
 
 // Start (or restart after a residual replacement) of a run at launch k0: the

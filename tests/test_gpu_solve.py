@@ -85,6 +85,31 @@ def test_kmax_gives_noconv_warning(mfp):
     assert res.status == 1 and res.stats["iters"] == 5
 
 
+def test_batch_timing_counts_whole_batches_before_the_stop(mfp):
+    """profile_every > 0: whole batches of check_every launches that end before the
+    stopping launch are timed; their mean per launch fits the iteration phase, and
+    timing changes neither the iterate nor the count."""
+    c = W.five_cylinders(256, 128, 0.3)
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, 200, device=DEV)
+    a = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12,
+                      check_every=8)
+    t = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12,
+                      check_every=8, profile_every=1)
+    it = t.stats["iters"]
+    n = t.stats["apply_samples"]
+    say(f"[timing] iters {it} samples {n} per launch {t.stats['apply_ms'] * 1e3:.2f} us "
+        f"phase {t.stats['solve_ms']:.3f} ms")
+    assert a.stats["apply_samples"] == 0
+    assert torch.equal(a.psi, t.psi) and a.stats["iters"] == it
+    assert n > 0 and n % 8 == 0
+    assert it - 2 * 8 <= n <= it  # the stopping batch and the run's first launch aside
+    assert 0.0 < t.stats["apply_ms"] * n <= t.stats["solve_ms"]
+    # every third batch only
+    e = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12,
+                      check_every=8, profile_every=3)
+    assert 0 < e.stats["apply_samples"] <= (n + 2 * 8) // 3 + 8
+
+
 def test_symmetry_on_gpu(mfp):
     """Mirror symmetry: bodies on y = 0 carry psi_b ~ 0, the pair opposite values."""
     c = W.five_cylinders(256, 128, 0.3)
