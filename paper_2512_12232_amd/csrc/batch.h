@@ -272,8 +272,12 @@ struct BatchPlan {
 // Tasks per wavefront segment (on average, by cost) in batched residual applies: the
 // launch holds many systems, so segments are sized for the prefetch, not for residency.
 constexpr int BATCH_SEG = 4;
-// Tasks per wavefront of the batched iteration (its launch holds many systems).
-constexpr int BATCH_TPW = 2;
+// Tasks per wavefront of the batched iteration (its launch holds many systems, far more
+// wavefronts than are resident).  Each wavefront's scalar phase (partials in, block
+// sums, barriers) is a fixed latency, spread over its tasks; measured on the 256-system
+// sweep (FP64 / FP32 + refinement, ms): 1 task 1647 / 1076, 2: 1424 / 929,
+// 4: 1297 / 896, 8: 1286 / 910.
+constexpr int BATCH_TPW = 4;
 
 static int batch_step_blocks(const Layout& L) {
   long long g = ((long long)L.ntasks() + WAVES * BATCH_TPW - 1) / (WAVES * BATCH_TPW);
