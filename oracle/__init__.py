@@ -20,6 +20,9 @@ Body-Conforming Grids"):
   post-processing (surface tangential velocity, Q_54, CoPFI);
 * ``grad``  -- derivatives of CoPFI with respect to body centres and the gap
   ratio by complex step, by a discrete adjoint and by finite differences;
+* ``potential`` -- the velocity potential phi on the same mesh (section
+  "Governing Equation": the flow net's other family of curves), solved
+  directly;
 * ``cg``    -- a plain conjugate-gradient loop on the assembled matrix (CPU
   timing baseline).
 
@@ -33,6 +36,7 @@ from .fem import (element_stiffness, element_coords, assemble, apply_at_nodes,
                   rectangle_stiffness)
 from .solve import (dirichlet_mask, dirichlet_values, dof_numbering,
                     reduced_system, solve, surface_samples, copfi, Solution)
+from .potential import in_domain, phi_solve, cell_velocity, PhiSolution
 
 __all__ = [
     "FLUID", "SNAPPED", "DEEP", "GeometryError", "spacing", "node_coords",
@@ -41,5 +45,5 @@ __all__ = [
     "element_stiffness", "element_coords", "assemble", "apply_at_nodes",
     "rectangle_stiffness", "dirichlet_mask", "dirichlet_values",
     "dof_numbering", "reduced_system", "solve", "surface_samples", "copfi",
-    "Solution",
+    "Solution", "in_domain", "phi_solve", "cell_velocity", "PhiSolution",
 ]

@@ -25,7 +25,8 @@ Readings applied here:
 
 * boundary data: a side with code 1 carries psi = U y, code 2 carries the
   isolated-cylinder stream function psi = U (y - cy)(1 - a^2 / rho^2) about
-  body 0, code 0 is natural.  A corner node is Dirichlet if either adjacent
+  body 0, code 0 is natural (codes 3 and 4 are the potential's: U x and the
+  isolated-cylinder potential U (x - cx)(1 + a^2 / rho^2), see ``potential``).  A corner node is Dirichlet if either adjacent
   side is; its value comes from the bottom/top side when that side is
   Dirichlet, otherwise from the left/right side;
 * the surface tangential velocity (section "Velocity Field and Surface
@@ -54,6 +55,7 @@ from .mesh import SNAPPED, FLUID, node_coords, spacing, cell_nodes, active_cells
 from .fem import assemble
 
 BC_NATURAL, BC_DIRICHLET_UY, BC_DIRICHLET_CYL = 0, 1, 2
+BC_DIRICHLET_UX, BC_DIRICHLET_CYLPHI = 3, 4
 
 
 def dirichlet_mask(grid, flow):
@@ -79,6 +81,13 @@ def _side_value(code, X, Y, flow, circles):
         dx, dy = X - cx, Y - cy
         rho2 = dx * dx + dy * dy
         return flow.U * dy * (1.0 - a * a / rho2)
+    if code == BC_DIRICHLET_UX:
+        return flow.U * X
+    if code == BC_DIRICHLET_CYLPHI:
+        cx, cy, a = circles[0]
+        dx, dy = X - cx, Y - cy
+        rho2 = dx * dx + dy * dy
+        return flow.U * dx * (1.0 + a * a / rho2)
     return np.zeros_like(X)
 
 

@@ -26,6 +26,8 @@ import numpy as np
 BC_NATURAL = 0        # natural (zero normal derivative of psi): free nodes
 BC_DIRICHLET_UY = 1   # psi = U * y
 BC_DIRICHLET_CYL = 2  # psi = U (y - cy)(1 - a^2 / rho^2) about circle 0
+BC_DIRICHLET_UX = 3   # phi = U * x (velocity potential of the free stream)
+BC_DIRICHLET_CYLPHI = 4  # phi = U (x - cx)(1 + a^2 / rho^2) about circle 0
 
 SIDE_L, SIDE_R, SIDE_B, SIDE_T = 0, 1, 2, 3
 
@@ -94,6 +96,17 @@ def five_cylinders(nx: int, ny: int, delta: float,
     return Case(f"five{nx}x{ny}_d{delta:g}", g, circles,
                 Flow(U, (BC_DIRICHLET_UY, BC_NATURAL, BC_DIRICHLET_UY, BC_DIRICHLET_UY)),
                 pair=(3, 4), delta=delta)
+
+
+def potential_flow(case: Case, exact_bc: bool = False) -> Case:
+    """The same geometry with the boundary data of the velocity-potential problem:
+    phi = U x on the inlet and outlet, natural (no flow through) on the walls;
+    exact_bc=True: the isolated-cylinder potential about circle 0 on all four
+    sides.  The body surfaces are natural boundaries in either case."""
+    bc = (BC_DIRICHLET_CYLPHI,) * 4 if exact_bc else (BC_DIRICHLET_UX, BC_DIRICHLET_UX,
+                                                       BC_NATURAL, BC_NATURAL)
+    return Case("phi_" + case.name, case.grid, case.circles, Flow(case.flow.U, bc),
+                case.nsweeps, case.pair, case.delta)
 
 
 def validation_cylinder(n: int = 64) -> Case:
