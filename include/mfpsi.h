@@ -13,6 +13,9 @@
  *                      Constraint Enforcement", Algorithm 1 (appendix), "Velocity Field
  *                      and Surface Tangential Velocity", and the CoPFI definition of
  *                      "Effect of Gap Ratio";
+ *   mfp_phi_solve      section "Governing Equation": the velocity potential phi
+ *                      (u = grad phi, Laplace equation), whose contours and those of
+ *                      psi form the flow net, on the same mesh and operator;
  *   mfp_element_apply  the matrix-free element product of Algorithm 1 on its own;
  *   mfp_psi_grad / mfp_mesh_conform_grad
  *                      the adjoint of that map (the automated sensitivity analysis named
@@ -67,9 +70,11 @@ extern "C" {
 #define MFP_DEEP 2    /* body node with no fluid neighbour: stays put                    */
 
 /* ---- side boundary conditions (side order: left, right, bottom, top) -------------- */
-#define MFP_BC_NATURAL 0       /* zero normal derivative of psi: nodes stay unknowns     */
+#define MFP_BC_NATURAL 0       /* zero normal derivative of the field: nodes stay unknowns */
 #define MFP_BC_DIRICHLET_UY 1  /* psi = U * y                                            */
 #define MFP_BC_DIRICHLET_CYL 2 /* psi = U (y-cy)(1 - a^2/rho^2) about circle 0 (tests)   */
+#define MFP_BC_DIRICHLET_UX 3  /* phi = U * x (free-stream potential)                    */
+#define MFP_BC_DIRICHLET_CYLPHI 4 /* phi = U (x-cx)(1 + a^2/rho^2) about circle 0 (tests) */
 
 /* ---- solver precisions ------------------------------------------------------------ */
 #define MFP_FP64 0    /* FP64 vectors and FP64 element apply                           */
@@ -194,6 +199,28 @@ int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbo
                   double* samples, int8_t* sample_body, int32_t sample_cap,
                   int32_t* n_samples_h, mfp_stats* stats_h,
                   void* ws, size_t ws_bytes, void* stream);
+
+/* Velocity-potential solve on a conformed mesh (section "Governing Equation": the
+ * velocity is also grad phi, phi satisfies the Laplace equation, and the contours of
+ * phi and psi form the flow net), with the operator, solver and options of
+ * mfp_psi_solve.  The paper gives no boundary conditions for phi; these are the
+ * potential-flow ones:
+ *   - sides flagged Dirichlet in `flow` carry their value (for the channel:
+ *     MFP_BC_DIRICHLET_UX on inlet and outlet), natural sides (the walls) and every
+ *     body surface have zero normal velocity (natural boundaries);
+ *   - no body constraint: every node of an active cell (a cell whose four nodes are
+ *     not all in one body) that is not Dirichlet is an unknown, body nodes included;
+ *     nodes of no active cell lie inside a body and carry no equation.
+ * Arguments as for mfp_psi_solve (same workspace size query, mfp_solve_workspace_size
+ * with this nbody and precision).  Output:
+ *   phi      device double[(nx+1)(ny+1)]: nodal potential, NaN at nodes of no active
+ *            cell;
+ *   stats_h  host (may be NULL); n_dof = n_free = the number of unknowns.
+ * Returns MFP_W_NOCONV if kmax was reached, MFP_E_BREAKDOWN on CG breakdown. */
+int mfp_phi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                  const double* disp, const int8_t* kind, const int8_t* body,
+                  const mfp_flow* flow, const mfp_solver_opts* opts, double* phi,
+                  mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for mfp_psi_grad. */
 size_t mfp_grad_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t precision);

@@ -32,6 +32,7 @@ EXPORTS = [
     "mfp_mesh_conform", "mfp_solve_workspace_size", "mfp_element_apply", "mfp_psi_solve",
     "mfp_grad_workspace_size", "mfp_psi_grad", "mfp_conform_grad_workspace_size",
     "mfp_mesh_conform_grad", "mfp_batched_workspace_size", "mfp_psi_solve_batched",
+    "mfp_phi_solve",
 ]
 
 
@@ -99,6 +100,10 @@ def load(path: str = LIB_PATH):
         POINTER(MfpFlow), POINTER(MfpSolverOpts), c_int32, c_int32, c_void_p,
         POINTER(c_double), POINTER(c_double), POINTER(c_double), c_void_p, c_void_p, c_int32,
         POINTER(c_int32), POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
+    lib.mfp_phi_solve.argtypes = [
+        POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_void_p, c_void_p, c_void_p,
+        POINTER(MfpFlow), POINTER(MfpSolverOpts), c_void_p, POINTER(MfpStats), c_void_p,
+        c_size_t, c_void_p]
     lib.mfp_grad_workspace_size.restype = c_size_t
     lib.mfp_grad_workspace_size.argtypes = [POINTER(MfpGrid), c_int32, c_int32]
     lib.mfp_psi_grad.argtypes = [
@@ -254,6 +259,40 @@ def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
     return SolveResult(psi, [psib[k] for k in range(nb)], Q.value, cop.value,
                        samples[0:2 * m:2], samples[1:2 * m:2], sbody[:m], ns.value, stats,
                        status)
+
+
+@dataclass
+class PhiResult:
+    phi: torch.Tensor    # nodal potential (NaN at nodes of no active cell)
+    stats: dict
+    status: int
+
+
+def phi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1e-12,
+              kmax=10 ** 7, check_every=16, inner_rtol=0.1, max_outer=1000,
+              ws: Optional[torch.Tensor] = None, allow_warn: bool = True,
+              profile_every: int = 0) -> PhiResult:
+    """Velocity potential on the conformed mesh (mfp_phi_solve): ``flow`` gives the
+    Dirichlet sides (e.g. phi = U x on inlet and outlet), bodies and the other sides
+    are natural boundaries."""
+    lib = load()
+    g = make_grid(grid)
+    c = make_circles(circles)
+    nb = len(circles)
+    f = make_flow(flow)
+    prec = _PREC[precision]
+    o = MfpSolverOpts(prec, float(rtol), int(kmax), int(check_every), float(inner_rtol),
+                      int(max_outer), None, int(profile_every))
+    n = (g.nx + 1) * (g.ny + 1)
+    dev = disp.device
+    phi = torch.empty(n, dtype=torch.float64, device=dev)
+    st = MfpStats()
+    if ws is None:
+        ws = workspace(lib.mfp_solve_workspace_size(byref(g), nb, prec), dev)
+    status = _check(lib.mfp_phi_solve(
+        byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o), _ptr(phi),
+        byref(st), _ptr(ws), ws.numel(), _stream()), allow_warn)
+    return PhiResult(phi, {k: getattr(st, k) for k, _ in MfpStats._fields_}, status)
 
 
 def solve_workspace_size(grid, nbody: int, precision: str = "fp64") -> int:

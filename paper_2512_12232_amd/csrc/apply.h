@@ -221,7 +221,7 @@ __device__ __forceinline__ void march_task(T ry, int lane, const int8_t (&tg)[HC
     // 3 = (c, sr+1)
     const bool halo =
         (g0 == TAG_HALO) | (g1n == TAG_HALO) | (g2 == TAG_HALO) | (g3 == TAG_HALO);
-    const bool inside = (g0 >= TAG_BODY0) & (g1n == g0) & (g2 == g0) & (g3 == g0);
+    const bool inside = tag_body(g0) & (g1n == g0) & (g2 == g0) & (g3 == g0);
     T c0 = 0, c1 = 0, c2 = 0, c3 = 0;
     if (!halo && !inside && lane < 63)
       cell_apply<T>(ry, x0, x1n, x2, x3, y0, y1n, y2, y3, p0, p1n, p2, p3, c0, c1, c2, c3);
@@ -392,10 +392,11 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
         const long long gi = base + r * P;
         const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
         const T qv = qr[r - 1];
+        const bool fr = tag_own(g);  // free (the potential's body nodes too)
         // every lane stores (the padding lanes zeros): whole aligned rows
-        const bool keep = owner && ((g == TAG_FREE) || (a.write_all && g != TAG_HALO));
+        const bool keep = owner && (fr || (a.write_all && g != TAG_HALO));
         a.q[gi] = keep ? qv : (T)0;
-        if (owner && g == TAG_FREE) pq += (double)v[r] * (double)qv;
+        if (owner && fr) pq += (double)v[r] * (double)qv;
         if (bm) body_row(owner, g, (double)qv, lane, bacc);
       }
       if (bm) {

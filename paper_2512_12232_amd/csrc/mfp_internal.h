@@ -122,8 +122,15 @@ __host__ __device__ inline int halo_shift(int lane, int m, int nstrip) {
   return 0;
 }
 
-// Internal node tags.
+// Internal node tags.  For the stream function the nodes of body b carry
+// TAG_BODY0 + b and stand for the one unknown psi_b.  For the velocity potential they
+// carry -1 - b: unknowns of their own (no body constraint) whose tag still names the
+// body, so that cells inside a body stay inactive.  Hence tag <= TAG_FREE: a node that
+// is its own unknown; (uint8_t)tag >= TAG_BODY0: a body node of either kind.
 enum : int8_t { TAG_FREE = 0, TAG_DIR = 1, TAG_HALO = 2, TAG_BODY0 = 3 };
+__host__ __device__ inline int8_t tag_potential_body(int b) { return (int8_t)(-1 - b); }
+__host__ __device__ inline bool tag_own(int8_t g) { return g <= TAG_FREE; }
+__host__ __device__ inline bool tag_body(int8_t g) { return (uint8_t)g >= (uint8_t)TAG_BODY0; }
 
 // Device-resident solver scalars.  Quantities that a kernel reads for iteration k
 // while its block 0 writes the value for the next iteration are double-buffered by

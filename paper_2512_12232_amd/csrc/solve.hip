@@ -32,6 +32,7 @@ struct SetupArgs {
   double U;
   int bc[4];
   double c0x, c0y, c0r;          // circle 0 (cylinder boundary data)
+  int phi;                       // velocity potential: body nodes are unknowns of their own
   const double* disp;            // caller displacement (unpadded)
   const int8_t* kind;
   const int8_t* body;
@@ -51,12 +52,29 @@ struct SetupArgs {
 
 __device__ double side_value(int code, double x, double y, const SetupArgs& a) {
   if (code == MFP_BC_DIRICHLET_UY) return a.U * y;
-  if (code == MFP_BC_DIRICHLET_CYL) {
+  if (code == MFP_BC_DIRICHLET_UX) return a.U * x;
+  if (code == MFP_BC_DIRICHLET_CYL || code == MFP_BC_DIRICHLET_CYLPHI) {
     const double dx = x - a.c0x, dy = y - a.c0y;
     const double rho2 = dx * dx + dy * dy;
-    return a.U * dy * (1.0 - a.c0r * a.c0r / rho2);
+    const double k = a.c0r * a.c0r / rho2;
+    return code == MFP_BC_DIRICHLET_CYL ? a.U * dy * (1.0 - k) : a.U * dx * (1.0 + k);
   }
   return 0.0;
+}
+
+// Whether node (i, j) belongs to an active cell (a cell whose four nodes do not all
+// lie in one body): the domain of the velocity potential.
+__device__ bool node_in_domain(const int8_t* __restrict__ body, int nx, int ny, int i, int j) {
+  for (int cj = j - 1; cj <= j; ++cj) {
+    for (int ci = i - 1; ci <= i; ++ci) {
+      if (ci < 0 || cj < 0 || ci >= nx || cj >= ny) continue;
+      const long long n0 = (long long)cj * (nx + 1) + ci;
+      const int b0 = body[n0];
+      if (b0 < 0 || body[n0 + 1] != b0 || body[n0 + nx + 1] != b0 || body[n0 + nx + 2] != b0)
+        return true;
+    }
+  }
+  return false;
 }
 
 __global__ void k_setup(SetupArgs a) {
@@ -77,7 +95,8 @@ __global__ void k_setup(SetupArgs a) {
       const bool bot = j == 0 && a.bc[2] != MFP_BC_NATURAL;
       const bool top = j == a.ny && a.bc[3] != MFP_BC_NATURAL;
       if (b >= 0) {
-        tg = (int8_t)(TAG_BODY0 + b);
+        tg = a.phi ? tag_potential_body(b) : (int8_t)(TAG_BODY0 + b);
+        if (a.phi && node_in_domain(a.body, a.nx, a.ny, i, j)) ++cnt;
       } else if (left || right || bot || top) {
         tg = TAG_DIR;
         const double x = a.x0 + (double)i * a.hx, y = a.y0 + (double)j * a.hy;
@@ -110,8 +129,8 @@ __global__ void k_setup(SetupArgs a) {
 }
 
 // Per task: constant-stencil flag (footprint of 64 columns x HC+2 rows all free and
-// undisplaced) and the set of bodies among the task's owned nodes.  One wavefront per
-// task.
+// undisplaced) and the set of bodies among the task's owned nodes (none for the
+// potential).  One wavefront per task.
 __global__ void __launch_bounds__(BLOCK) k_task_meta(Layout L, const int8_t* __restrict__ tag,
                                                      const double* __restrict__ dx,
                                                      const double* __restrict__ dy,
@@ -130,6 +149,7 @@ __global__ void __launch_bounds__(BLOCK) k_task_meta(Layout L, const int8_t* __r
     const long long gi = base + (long long)r * L.P;
     const int8_t tg = tag[gi];
     if (tg != TAG_FREE || dx[gi] != 0.0 || dy[gi] != 0.0) plain = 0;
+    // (the potential's body tags are negative: no body constraint)
     if (r >= 1 && r <= HC && lane >= 1 && lane <= SW && tg >= TAG_BODY0)
       bm |= 1ull << (tg - TAG_BODY0);
   }
@@ -278,7 +298,7 @@ __global__ void __launch_bounds__(1024) k_seg_plan(Layout L, const uint8_t* __re
 }
 
 // w = g + T x as a full nodal vector (free: x, Dirichlet: g, body b: psi_b of the
-// current iterate).
+// current iterate; the potential's body nodes, negative tags: x).
 template <typename T>
 __global__ void k_form_w(long long n, const int8_t* __restrict__ tag,
                          const double* __restrict__ x, const double* __restrict__ g,
@@ -288,7 +308,7 @@ __global__ void k_form_w(long long n, const int8_t* __restrict__ tag,
        e += (long long)gridDim.x * blockDim.x) {
     const int8_t tg = tag[e];
     double v = 0.0;
-    if (tg == TAG_FREE)
+    if (tag_own(tg))
       v = x[e];
     else if (tg == TAG_DIR)
       v = g[e];
@@ -396,6 +416,28 @@ __global__ void k_output(Layout L, int nx, int ny, const int8_t* __restrict__ ta
   if (blockIdx.x == 0 && threadIdx.x == 0 && lo >= 0 && hi >= 0) {
     st->Q = xb[hi] - xb[lo];
     st->copfi = st->Q / (U * (yhi - ylo));
+  }
+}
+
+// The potential (unpadded): unknowns from x, Dirichlet nodes from g, NaN at nodes of no
+// active cell (inside a body).
+__global__ void k_output_phi(Layout L, int nx, int ny, const int8_t* __restrict__ tag,
+                             const int8_t* __restrict__ body, const double* __restrict__ x,
+                             const double* __restrict__ g, double* __restrict__ phi) {
+  const long long nn = (long long)(nx + 1) * (ny + 1);
+  for (long long nd = blockIdx.x * (long long)blockDim.x + threadIdx.x; nd < nn;
+       nd += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(nd / (nx + 1)), i = (int)(nd - (long long)j * (nx + 1));
+    const long long e = node_index(L, i, j);
+    const int8_t tg = tag[e];
+    double v;
+    if (tg == TAG_DIR)
+      v = g[e];
+    else if (tg < TAG_FREE && !node_in_domain(body, nx, ny, i, j))
+      v = __builtin_nan("");
+    else
+      v = x[e];
+    phi[nd] = v;
   }
 }
 
@@ -598,6 +640,7 @@ struct SolveWs {
   mfp_circle* circ;
   int* boxes;
   int* count;
+  int phi = 0;    // velocity-potential solve: body nodes are unknowns, no body constraint
 };
 
 // Task height of a single solve's layout.  The FP32 iteration with 8-row tasks uses
@@ -724,7 +767,7 @@ static ApplyArgs<T> make_apply_args(const SolveWs& w, const mfp_grid& g, int nb,
 // Common setup: tags, scaled displacements, lifting, tile metadata.
 static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const double* disp,
                  const int8_t* body, const mfp_flow* flow, int precision, const SolveWs& w,
-                 hipStream_t st) {
+                 hipStream_t st, const mfp_circle* bc_circle = nullptr) {
   SetupArgs s{};
   s.L = w.L;
   s.nx = g.nx;
@@ -736,10 +779,12 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   s.inv_hx = 1.0 / s.hx;
   s.U = flow ? flow->U : 0.0;
   for (int k = 0; k < 4; ++k) s.bc[k] = flow ? flow->side_bc[k] : MFP_BC_NATURAL;
-  if (nb > 0 && circles_h) {
-    s.c0x = circles_h[0].cx;
-    s.c0y = circles_h[0].cy;
-    s.c0r = circles_h[0].r;
+  // circle 0 for the isolated-cylinder boundary data (the potential passes it alone)
+  const mfp_circle* c0 = bc_circle ? bc_circle : (nb > 0 ? circles_h : nullptr);
+  if (c0) {
+    s.c0x = c0->cx;
+    s.c0y = c0->cy;
+    s.c0r = c0->r;
   }
   s.disp = disp;
   s.body = body;
@@ -755,6 +800,7 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   s.p1 = w.p1;
   s.q = w.q;
   s.nfree = w.nfree;
+  s.phi = w.phi;
   if (w.L.nstrip > SEG_MAX_STRIPS || w.L.nchunk > 0xffff ||
       (unsigned long long)w.L.n * sizeof(double) >= (1ull << 32)) {
     set_error("grid too large (nx <= %d, ny <= %d, padded nodes < 2^29)",
@@ -1232,7 +1278,7 @@ __global__ void k_warm_x(Layout L, int nx, int ny, const int8_t* __restrict__ ta
        nd += (long long)gridDim.x * blockDim.x) {
     const int j = (int)(nd / (nx + 1)), i = (int)(nd - (long long)j * (nx + 1));
     const long long e = node_index(L, i, j);
-    if (tag[e] == TAG_FREE) x[e] = psi0[nd];
+    if (tag_own(tag[e])) x[e] = psi0[nd];
   }
 }
 
@@ -1252,7 +1298,7 @@ static int check_solve_args(const mfp_grid* grid, const mfp_circle* circles_h, i
     return MFP_E_ARG;
   }
   for (int k = 0; k < 4; ++k)
-    if (flow->side_bc[k] < 0 || flow->side_bc[k] > 2) {
+    if (flow->side_bc[k] < MFP_BC_NATURAL || flow->side_bc[k] > MFP_BC_DIRICHLET_CYLPHI) {
       set_error("invalid side boundary code");
       return MFP_E_ARG;
     }
@@ -1287,8 +1333,8 @@ static void circle_boxes(const mfp_grid& g, const mfp_circle* c, int nb, int* bo
 static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, const double* disp,
                       const int8_t* body, const mfp_flow* flow, const mfp_solver_opts* opts,
                       const double* bb_h, bool zero_g, const SolveWs& w, hipStream_t st,
-                      SolveInfo* info) {
-  MFP_TRY(setup(g, circles_h, nb, disp, body, flow, opts->precision, w, st));
+                      SolveInfo* info, const mfp_circle* bc_circle = nullptr) {
+  MFP_TRY(setup(g, circles_h, nb, disp, body, flow, opts->precision, w, st, bc_circle));
   if (zero_g) MFP_TRY_HIP(hipMemsetAsync(w.g, 0, sizeof(double) * w.L.n, st));
   if (bb_h && nb > 0)
     MFP_TRY_HIP(hipMemcpyAsync(w.st->bb, bb_h, sizeof(double) * nb, hipMemcpyHostToDevice, st));
@@ -1482,6 +1528,41 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   }
   if (n_samples_h) *n_samples_h = nsamp;
   MFP_TRY(fill_stats(w, info, nb, hsd, st, stats_h));
+  return finish_status(info);
+}
+
+extern "C" int mfp_phi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                             const double* disp, const int8_t* kind, const int8_t* body,
+                             const mfp_flow* flow, const mfp_solver_opts* opts, double* phi,
+                             mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream_) {
+  clear_error();
+  MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, kind, body, flow, opts, ws));
+  if (!phi) {
+    set_error("phi is NULL");
+    return MFP_E_ARG;
+  }
+  const int hc = solve_hc(grid, opts->precision);
+  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, hc);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  SolveWs w;
+  solve_layout(grid, nbody, opts->precision, ws, &w, hc);
+  w.phi = 1;
+  const mfp_grid& g = *grid;
+  // no body constraint (nb = 0); circle 0 only gives MFP_BC_DIRICHLET_CYLPHI its data
+  SolveInfo info;
+  MFP_TRY(solve_core(g, nullptr, 0, disp, body, flow, opts, nullptr, false, w, st, &info,
+                     nbody > 0 ? circles_h : nullptr));
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  k_output_phi<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, body, w.x, w.g, phi);
+  MFP_TRY_HIP(hipGetLastError());
+  DevState hsd;
+  MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  MFP_TRY(fill_stats(w, info, 0, hsd, st, stats_h));
   return finish_status(info);
 }
 

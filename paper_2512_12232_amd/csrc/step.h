@@ -427,13 +427,14 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       if (t + W < ntask) fetch(t + W);
       stencil_task<T, HC>(a.cC, a.cE, a.cN, a.cD, v, qr);
     } else {
-      // body nodes carry p_b, Dirichlet and halo nodes 0; r is zero there
+      // body nodes carry p_b, Dirichlet and halo nodes 0 (r is zero there); the
+      // potential's body nodes (negative tags) keep their own p
 #pragma unroll
       for (int r = 0; r < HC + 2; ++r) {
         const int8_t g = tg[r];
         if (g >= TAG_BODY0)
           v[r] = (T)s_pb[g - TAG_BODY0];
-        else if (g != TAG_FREE)
+        else if (g > TAG_FREE)
           v[r] = (T)0;
       }
       march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
@@ -445,14 +446,15 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     for (int r = 1; r <= HC; ++r) {
       const unsigned go = bo + r * RB;
       const int8_t g = plain ? (int8_t)TAG_FREE : tg[r];
-      const T qv = (owner && g == TAG_FREE) ? qr[r - 1] : (T)0;
+      const bool fr = tag_own(g);  // free (the potential's body nodes too)
+      const T qv = (owner && fr) ? qr[r - 1] : (T)0;
       // every lane stores (the padding lanes zeros): whole aligned rows
       st_vec<STREAM>(rcg, go, owner ? rj[r] : (T)0);
       st_vec<STREAM>(pcg, go, owner ? v[r] : (T)0);
       st_vec<STREAM>(qcg, go, qv);
       if (XUPD) st_vec<STREAM>(xg, go, owner ? (xo[r - 1] + al2 * p2[r - 1]) + al * po[r] : (T)0);
       if (owner) {
-        if (g == TAG_FREE) {
+        if (fr) {
           const double rd = (double)rj[r], qd = (double)qv;
           prr += rd * rd;
           ppq += (double)v[r] * qd;
