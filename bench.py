@@ -246,6 +246,33 @@ def adjoint_ratio(mfp, W):
             "dcopfi_ddelta": dc[4][1] - dc[3][1]}
 
 
+def potential_solve(mfp, W):
+    """The velocity potential of the benchmark workload (1024 x 512 cells, five
+    cylinders): phi = U x on inlet and outlet, natural walls and bodies, FP64 CG to
+    1e-12 on the same mesh, with the iteration kernel's roofline (same algorithmic
+    bytes per launch as the stream function's: the same vectors, displacements and
+    tags)."""
+    case = W.potential_flow(W.five_cyl_1024())
+    dev = "cuda:0"
+    d, k, b = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device=dev)
+    r, ms = _timed(lambda: mfp.phi_solve(case.grid, case.circles, d, k, b, case.flow,
+                                         rtol=1e-12, profile_every=1), reps=2)
+    s = r.stats
+    nbytes, _ = step_bytes(case, d, b)
+    out = {"workload": "five cylinders, 1024x512 cells, delta 0.25; phi = U x on inlet and "
+                       "outlet, natural walls and bodies; FP64 CG to 1e-12",
+           "solve_ms": round(ms, 2), "iters": s["iters"], "n_dof": s["n_dof"],
+           "relres_true": s["relres_true"],
+           "dof_iter_per_s": s["n_dof"] * s["iters"] / (ms * 1e-3)}
+    if s["apply_samples"] > 0:
+        kms = s["apply_ms"]
+        out["roofline"] = {"kernel": "k_step<double, %d>" % _task_height(case, s["n_tiles"]),
+                           "launch_ms": round(kms, 5), "bytes_per_launch": nbytes,
+                           "achieved_GBs": round(nbytes / (kms * 1e-3) / 1e9, 1),
+                           "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    return out
+
+
 def delta_sweep(mfp, W, count=256):
     """256 seeded five-cylinder variants (delta ~ U[0.05, 2], 256x128 .. 1024x512
     cells): one batched graph-replayed solve (FP32 apply + FP64 refinement, and plain
@@ -377,6 +404,7 @@ def main():
     if not args.no_extras:
         extras["mixed_precision_4096x2048"] = mixed_precision(mfp, W)
         extras["adjoint_2048x1024"] = adjoint_ratio(mfp, W)
+        extras["potential_1024x512"] = potential_solve(mfp, W)
         extras["delta_sweep_256"] = delta_sweep(mfp, W)
     s = res.stats
     line = {
