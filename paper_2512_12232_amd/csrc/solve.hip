@@ -1,5 +1,6 @@
 // Constrained stream-function solve: setup, conjugate-gradient kernels and the
-// host drivers of mfp_psi_solve and mfp_element_apply.
+// host drivers of mfp_psi_solve, mfp_phi_solve (the velocity potential: body nodes
+// as unknowns of their own, see the tags in mfp_internal.h) and mfp_element_apply.
 //
 // Unknowns (section "Matrix-Free Conjugate Gradient with Multiple Constraint
 // Enforcement"): free nodes plus one value psi_b per body, N_dof = N_int + N_N + N_b.
