@@ -23,6 +23,8 @@ Body-Conforming Grids"):
 * ``potential`` -- the velocity potential phi on the same mesh (section
   "Governing Equation": the flow net's other family of curves), solved
   directly;
+* ``sweep`` -- the cubic fit of CoPFI over the gap ratio (section "Effect of
+  Gap Ratio");
 * ``cg``    -- a plain conjugate-gradient loop on the assembled matrix (CPU
   timing baseline).
 
@@ -37,6 +39,7 @@ from .fem import (element_stiffness, element_coords, assemble, apply_at_nodes,
 from .solve import (dirichlet_mask, dirichlet_values, dof_numbering,
                     reduced_system, solve, surface_samples, copfi, Solution)
 from .potential import in_domain, phi_solve, cell_velocity, PhiSolution
+from .sweep import cubic_fit
 
 __all__ = [
     "FLUID", "SNAPPED", "DEEP", "GeometryError", "spacing", "node_coords",
@@ -45,5 +48,5 @@ __all__ = [
     "element_stiffness", "element_coords", "assemble", "apply_at_nodes",
     "rectangle_stiffness", "dirichlet_mask", "dirichlet_values",
     "dof_numbering", "reduced_system", "solve", "surface_samples", "copfi",
-    "Solution", "in_domain", "phi_solve", "cell_velocity", "PhiSolution",
+    "Solution", "in_domain", "phi_solve", "cell_velocity", "PhiSolution", "cubic_fit",
 ]
