@@ -16,6 +16,8 @@
  *   mfp_phi_solve      section "Governing Equation": the velocity potential phi
  *                      (u = grad phi, Laplace equation), whose contours and those of
  *                      psi form the flow net, on the same mesh and operator;
+ *   mfp_cubic_fit      the cubic fit of CoPFI over the gap ratio ("Effect of Gap
+ *                      Ratio");
  *   mfp_element_apply  the matrix-free element product of Algorithm 1 on its own;
  *   mfp_psi_grad / mfp_mesh_conform_grad
  *                      the adjoint of that map (the automated sensitivity analysis named
@@ -221,6 +223,16 @@ int mfp_phi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbo
                   const double* disp, const int8_t* kind, const int8_t* body,
                   const mfp_flow* flow, const mfp_solver_opts* opts, double* phi,
                   mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream);
+
+/* Cubic least-squares fit of a gap-ratio sweep (section "Effect of Gap Ratio" fits
+ * CoPFI as a cubic in delta and reports R^2 and the mean square error):
+ *   y ~ coef_h[0] x^3 + coef_h[1] x^2 + coef_h[2] x + coef_h[3]   (ordinary least
+ *   squares, Householder QR), r2_h = 1 - SS_res / SS_tot, mse_h = SS_res / n.
+ * x_h, y_h: HOST double[n] (e.g. delta and the copfi_h of mfp_psi_solve_batched),
+ * n >= 4; coef_h host double[4]; r2_h, mse_h may be NULL.  Host arithmetic only.
+ * Returns MFP_E_ARG for n < 4, a non-finite value or fewer than 4 distinct x. */
+int mfp_cubic_fit(const double* x_h, const double* y_h, int32_t n, double* coef_h,
+                  double* r2_h, double* mse_h);
 
 /* Workspace bytes for mfp_psi_grad. */
 size_t mfp_grad_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t precision);

@@ -32,7 +32,7 @@ EXPORTS = [
     "mfp_mesh_conform", "mfp_solve_workspace_size", "mfp_element_apply", "mfp_psi_solve",
     "mfp_grad_workspace_size", "mfp_psi_grad", "mfp_conform_grad_workspace_size",
     "mfp_mesh_conform_grad", "mfp_batched_workspace_size", "mfp_psi_solve_batched",
-    "mfp_phi_solve",
+    "mfp_phi_solve", "mfp_cubic_fit",
 ]
 
 
@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH):
         POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_void_p, c_void_p, c_void_p,
         POINTER(MfpFlow), POINTER(MfpSolverOpts), c_void_p, POINTER(MfpStats), c_void_p,
         c_size_t, c_void_p]
+    lib.mfp_cubic_fit.argtypes = [POINTER(c_double), POINTER(c_double), c_int32,
+                                  POINTER(c_double), POINTER(c_double), POINTER(c_double)]
     lib.mfp_grad_workspace_size.restype = c_size_t
     lib.mfp_grad_workspace_size.argtypes = [POINTER(MfpGrid), c_int32, c_int32]
     lib.mfp_psi_grad.argtypes = [
@@ -293,6 +295,21 @@ def phi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
         byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o), _ptr(phi),
         byref(st), _ptr(ws), ws.numel(), _stream()), allow_warn)
     return PhiResult(phi, {k: getattr(st, k) for k, _ in MfpStats._fields_}, status)
+
+
+def cubic_fit(x: Sequence[float], y: Sequence[float]):
+    """Least-squares cubic y ~ c3 x^3 + c2 x^2 + c1 x + c0 (mfp_cubic_fit), e.g. CoPFI
+    over the gap ratio of a sweep.  Returns ((c3, c2, c1, c0), R^2, MSE)."""
+    n = len(x)
+    if len(y) != n:
+        raise ValueError("x and y differ in length")
+    xa = (c_double * max(n, 1))(*[float(v) for v in x])
+    ya = (c_double * max(n, 1))(*[float(v) for v in y])
+    c = (c_double * 4)()
+    r2 = c_double(0.0)
+    mse = c_double(0.0)
+    _check(load().mfp_cubic_fit(xa, ya, n, c, byref(r2), byref(mse)), False)
+    return (c[0], c[1], c[2], c[3]), r2.value, mse.value
 
 
 def solve_workspace_size(grid, nbody: int, precision: str = "fp64") -> int:

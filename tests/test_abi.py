@@ -127,3 +127,27 @@ def test_grid_size_limit_is_reported_before_device_work(lib):
     assert solve(2048 * 62) == B.MFP_E_ARG and "grid too large" in mfp.last_error()
     if not torch.cuda.is_available():
         assert solve(2048 * 62 - 1) == B.MFP_E_HIP
+
+
+def test_cubic_fit_matches_the_oracle():
+    """mfp_cubic_fit (host code of the library, no device work) against the oracle's
+    least-squares cubic: Table 1 of the paper, and a noisy seeded sweep of 256 gap
+    ratios; errors in x (fewer than 4 distinct values) are reported."""
+    import oracle as O
+    import paper_2512_12232_amd as m
+    t = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "table1_gap_ratio.txt"),
+                   comments="#")
+    rng = np.random.default_rng(11)
+    x = rng.uniform(0.05, 2.0, 256)
+    y = 0.8 * x ** 3 - 1.4 * x ** 2 + 2.2 * x - 0.2 + rng.normal(0.0, 1e-3, x.size)
+    for xs, ys in ((t[:, 0], t[:, 5]), (x, y)):
+        c, r2, mse = m.cubic_fit(xs, ys)
+        co, r2o, mseo = O.cubic_fit(xs, ys)
+        np.testing.assert_allclose(c, co, rtol=1e-10, atol=1e-12)
+        assert r2 == pytest.approx(r2o, abs=1e-12) and mse == pytest.approx(mseo, rel=1e-8)
+    assert tuple(round(v, 5) for v in m.cubic_fit(t[:, 0], t[:, 5])[0]) == \
+        (0.80417, -1.38561, 2.21409, -0.22171)
+    with pytest.raises(m.MfpError):
+        m.cubic_fit([1.0, 1.0, 2.0, 2.0, 3.0], [0.0, 1.0, 2.0, 3.0, 4.0])
+    with pytest.raises(m.MfpError):
+        m.cubic_fit([1.0, 2.0, 3.0], [0.0, 1.0, 2.0])
