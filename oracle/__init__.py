@@ -23,6 +23,8 @@ Body-Conforming Grids"):
 * ``potential`` -- the velocity potential phi on the same mesh (section
   "Governing Equation": the flow net's other family of curves), solved
   directly;
+* ``contour`` -- contour lines of a nodal field (flow net, stagnation
+  streamlines) by marching squares on the conformed mesh;
 * ``sweep`` -- the cubic fit of CoPFI over the gap ratio (section "Effect of
   Gap Ratio");
 * ``cg``    -- a plain conjugate-gradient loop on the assembled matrix (CPU
@@ -40,6 +42,7 @@ from .solve import (dirichlet_mask, dirichlet_values, dof_numbering,
                     reduced_system, solve, surface_samples, copfi, Solution)
 from .potential import in_domain, phi_solve, cell_velocity, PhiSolution
 from .sweep import cubic_fit
+from .contour import contour
 
 __all__ = [
     "FLUID", "SNAPPED", "DEEP", "GeometryError", "spacing", "node_coords",
@@ -49,4 +52,5 @@ __all__ = [
     "rectangle_stiffness", "dirichlet_mask", "dirichlet_values",
     "dof_numbering", "reduced_system", "solve", "surface_samples", "copfi",
     "Solution", "in_domain", "phi_solve", "cell_velocity", "PhiSolution", "cubic_fit",
+    "contour",
 ]
