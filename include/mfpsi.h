@@ -18,6 +18,8 @@
  *                      psi form the flow net, on the same mesh and operator;
  *   mfp_cubic_fit      the cubic fit of CoPFI over the gap ratio ("Effect of Gap
  *                      Ratio");
+ *   mfp_contour        contour lines of psi or phi: the flow net and the stagnation
+ *                      streamlines of the transverse cylinders ("Effect of Gap Ratio");
  *   mfp_element_apply  the matrix-free element product of Algorithm 1 on its own;
  *   mfp_psi_grad / mfp_mesh_conform_grad
  *                      the adjoint of that map (the automated sensitivity analysis named
@@ -233,6 +235,30 @@ int mfp_phi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbo
  * Returns MFP_E_ARG for n < 4, a non-finite value or fewer than 4 distinct x. */
 int mfp_cubic_fit(const double* x_h, const double* y_h, int32_t n, double* coef_h,
                   double* r2_h, double* mse_h);
+
+/* Workspace bytes for mfp_contour. */
+size_t mfp_contour_workspace_size(const mfp_grid* grid);
+
+/* Contour line field = level on the conformed mesh: the flow net (contours of psi and
+ * phi, section "Governing Equation") and the stagnation streamlines psi = psi_b of the
+ * transverse cylinders (section "Effect of Gap Ratio").  The paper does not say how its
+ * lines were drawn; marching squares over the active cells, in the displaced node
+ * coordinates X = background + disp: a node is above the level when field >= level;
+ * on each cell edge a -> b (node order (i,j), (i+1,j), (i+1,j+1), (i,j+1); edges 0-1,
+ * 1-2, 2-3, 3-0) whose end nodes differ, the crossing is X_a + t (X_b - X_a),
+ * t = (level - f_a) / (f_b - f_a); two crossings make one segment (lower edge first),
+ * four (a saddle) two, paired by the mean of the four values (on node 0's side: edges
+ * 0,1 then 2,3, else 3,0 then 1,2).  Cells inside a body (all four nodes in one body)
+ * or with a non-finite value (phi outside the domain) give none.
+ *   field   device double[(nx+1)(ny+1)] (e.g. psi of mfp_psi_solve, phi of
+ *           mfp_phi_solve); disp, body as for the solvers;
+ *   seg     device double[4*cap]: (x0, y0, x1, y1) per segment, ordered by cell id
+ *           j nx + i, then as above; only the first cap are written;
+ *   n_seg_h host: number of segments that exist (may exceed cap).
+ * Synchronises the stream (to read the count). */
+int mfp_contour(const mfp_grid* grid, const double* disp, const int8_t* body,
+                const double* field, double level, double* seg, int64_t cap,
+                int64_t* n_seg_h, void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for mfp_psi_grad. */
 size_t mfp_grad_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t precision);

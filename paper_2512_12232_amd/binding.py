@@ -32,7 +32,7 @@ EXPORTS = [
     "mfp_mesh_conform", "mfp_solve_workspace_size", "mfp_element_apply", "mfp_psi_solve",
     "mfp_grad_workspace_size", "mfp_psi_grad", "mfp_conform_grad_workspace_size",
     "mfp_mesh_conform_grad", "mfp_batched_workspace_size", "mfp_psi_solve_batched",
-    "mfp_phi_solve", "mfp_cubic_fit",
+    "mfp_phi_solve", "mfp_cubic_fit", "mfp_contour_workspace_size", "mfp_contour",
 ]
 
 
@@ -106,6 +106,11 @@ def load(path: str = LIB_PATH):
         c_size_t, c_void_p]
     lib.mfp_cubic_fit.argtypes = [POINTER(c_double), POINTER(c_double), c_int32,
                                   POINTER(c_double), POINTER(c_double), POINTER(c_double)]
+    lib.mfp_contour_workspace_size.restype = c_size_t
+    lib.mfp_contour_workspace_size.argtypes = [POINTER(MfpGrid)]
+    lib.mfp_contour.argtypes = [POINTER(MfpGrid), c_void_p, c_void_p, c_void_p, c_double,
+                                c_void_p, c_int64, POINTER(c_int64), c_void_p, c_size_t,
+                                c_void_p]
     lib.mfp_grad_workspace_size.restype = c_size_t
     lib.mfp_grad_workspace_size.argtypes = [POINTER(MfpGrid), c_int32, c_int32]
     lib.mfp_psi_grad.argtypes = [
@@ -310,6 +315,26 @@ def cubic_fit(x: Sequence[float], y: Sequence[float]):
     mse = c_double(0.0)
     _check(load().mfp_cubic_fit(xa, ya, n, c, byref(r2), byref(mse)), False)
     return (c[0], c[1], c[2], c[3]), r2.value, mse.value
+
+
+def contour(grid, disp: torch.Tensor, body: torch.Tensor, field: torch.Tensor, level: float,
+            cap: Optional[int] = None) -> torch.Tensor:
+    """Contour line field = level (mfp_contour): (k, 4) device tensor of segments
+    (x0, y0, x1, y1) in cell order.  cap None: all of them (counted first)."""
+    lib = load()
+    g = make_grid(grid)
+    dev = field.device
+    ws = workspace(lib.mfp_contour_workspace_size(byref(g)), dev)
+    n = c_int64(0)
+    if cap is None:
+        _check(lib.mfp_contour(byref(g), _ptr(disp), _ptr(body), _ptr(field), float(level),
+                               None, 0, byref(n), _ptr(ws), ws.numel(), _stream()), False)
+        cap = n.value
+    seg = torch.empty(max(4 * cap, 4), dtype=torch.float64, device=dev)
+    _check(lib.mfp_contour(byref(g), _ptr(disp), _ptr(body), _ptr(field), float(level),
+                           _ptr(seg), int(cap), byref(n), _ptr(ws), ws.numel(), _stream()),
+           False)
+    return seg[:4 * min(cap, n.value)].view(-1, 4)
 
 
 def solve_workspace_size(grid, nbody: int, precision: str = "fp64") -> int:
