@@ -313,7 +313,30 @@ def delta_sweep(mfp, W, count=256):
         b["speedup_vs_sequential_fp64"] = out["sequential_fp64"]["ms"] / b["ms"]
         b["max_abs_dcopfi_vs_sequential_fp64"] = max(
             abs(x - r.copfi) for x, r in zip(res[prec].copfi, rs))
+    # the paper's post-processing of a gap-ratio study: cubic fit of CoPFI(delta)
+    coef, r2, mse = mfp.cubic_fit([c.delta for c in cases], list(res["fp32_ir"].copfi))
+    out["copfi_cubic_fit"] = {"coef_d3_d2_d1_d0": [round(v, 6) for v in coef], "r2": r2,
+                              "mse": mse}
     return out
+
+
+def streamlines(mfp, W):
+    """Stagnation streamlines psi = psi_4 and psi = psi_5 of the benchmark workload
+    (1024 x 512): mfp_contour on the FP64 solution, timed (both lines, ms)."""
+    case = W.five_cyl_1024()
+    dev = "cuda:0"
+    d, k, b = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device=dev)
+    r = mfp.psi_solve(case.grid, case.circles, d, k, b, case.flow, rtol=1e-12,
+                      pair=case.pair, sample_cap=0)
+
+    def lines():
+        return [mfp.contour(case.grid, d, b, r.psi, r.psi_b[q]) for q in (3, 4)]
+
+    segs, ms = _timed(lines, reps=3)
+    return {"workload": "five cylinders, 1024x512 cells; contours psi = psi_4, psi_5",
+            "ms": round(ms, 3), "segments": [int(s.shape[0]) for s in segs],
+            "lengths": [round(float((s[:, 2:] - s[:, :2]).norm(dim=1).sum()), 4)
+                        for s in segs]}
 
 
 def main():
@@ -405,6 +428,7 @@ def main():
         extras["mixed_precision_4096x2048"] = mixed_precision(mfp, W)
         extras["adjoint_2048x1024"] = adjoint_ratio(mfp, W)
         extras["potential_1024x512"] = potential_solve(mfp, W)
+        extras["stagnation_streamlines_1024x512"] = streamlines(mfp, W)
         extras["delta_sweep_256"] = delta_sweep(mfp, W)
     s = res.stats
     line = {
