@@ -122,17 +122,31 @@ __global__ void __launch_bounds__(BLOCK) k_jacobi_multi(int nx, int ny, int ns, 
     kd[e] = in ? kind[n] : (int8_t)-1;  // off the grid: never updated, never read by an update
   }
   __syncthreads();
+  // each thread keeps the same NE region entries in every sweep: their coordinates and
+  // node kinds are worked out once
+  static_assert(RW * RH % BLOCK == 0, "whole region entries per thread");
+  constexpr int NE = RW * RH / BLOCK;
+  int eli[NE], elj[NE];
+  bool efl[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = (int)threadIdx.x + k * BLOCK;
+    eli[k] = e % RW;
+    elj[k] = e / RW;
+    efl[k] = kd[e] == MFP_FLUID;
+  }
   int cur = 0;
   for (int sw = 0; sw < ns; ++sw) {
-    const int bi0 = bx.i0[sw], bi1 = bx.i1[sw], bj0 = bx.j0[sw], bj1 = bx.j1[sw];
+    // box of sweep sw in region coordinates, cut to the entries it can update
+    const int li0 = max(bx.i0[sw] - gi0, sw + 1), li1 = min(bx.i1[sw] - gi0, RW - 2 - sw);
+    const int lj0 = max(bx.j0[sw] - gj0, sw + 1), lj1 = min(bx.j1[sw] - gj0, RH - 2 - sw);
     const double* a = buf[cur];
     double* b = buf[cur ^ 1];
-    for (int e = threadIdx.x; e < RW * RH; e += BLOCK) {
-      const int li = e % RW, lj = e / RW;
-      const int i = gi0 + li, j = gj0 + lj;
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = (int)threadIdx.x + k * BLOCK;
       double v = a[e];
-      if (li > sw && li < RW - 1 - sw && lj > sw && lj < RH - 1 - sw && i >= bi0 && i <= bi1 &&
-          j >= bj0 && j <= bj1 && kd[e] == MFP_FLUID)
+      if (efl[k] && eli[k] >= li0 && eli[k] <= li1 && elj[k] >= lj0 && elj[k] <= lj1)
         v = wx * (a[e + 1] + a[e - 1]) + wy * (a[e + RW] + a[e - RW]);
       b[e] = v;
     }
