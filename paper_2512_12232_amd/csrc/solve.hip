@@ -446,9 +446,11 @@ __global__ void k_output_phi(Layout L, int nx, int ny, const int8_t* __restrict_
 // Tangential Velocity"): u_t = (psi_c - psi_b) / d_nc on each edge joining two nodes
 // snapped to the same body, in every active cell with a fluid node.  psi_c is the mean
 // nodal psi of the cell, d_nc the distance from the mean of its displaced nodes to the
-// line through the edge, theta the polar angle of the edge midpoint.  One block walks
-// the bodies in order and each body's cell box in cell-id order, so the output order
-// is (body, cell, local edge).
+// line through the edge, theta the polar angle of the edge midpoint.  The items are the
+// cells of every body's box, body after body and in cell-id order within a box; three
+// passes (samples per block, one block scanning the block counts, a write pass that
+// recounts and scans within its block) keep the output order (body, cell, local edge)
+// without atomics.
 struct SampleArgs {
   int nx, ny, nb;
   double x0, y0, hx, hy, hmax;
@@ -463,85 +465,136 @@ struct SampleArgs {
   int8_t* sbody;
   int cap;
   int* count;
+  long long items;                        // cells of all boxes, body after body
+  long long first[MFP_MAX_BODIES + 1];    // first item of each body's box
+  int* boff;                              // per block: sample count, then offset
 };
 
-__global__ void __launch_bounds__(BLOCK) k_samples(SampleArgs a) {
-  __shared__ int s_scan[BLOCK];
-  __shared__ int s_base;
-  if (threadIdx.x == 0) s_base = 0;
-  __syncthreads();
+constexpr int SMP_ITEMS = 4;                     // consecutive items per thread
+constexpr int SMP_CHUNK = BLOCK * SMP_ITEMS;     // items per block
+constexpr int SMP_MAX_BLOCKS = 1 << 16;          // up to 2^26 box cells
+
+// Samples of item it (body b, cell c of its box in cell-id order), in edge order;
+// (theta, u_t) into th/ut when they are non-null.  Returns the count (0..4).
+__device__ int item_samples(const SampleArgs& a, long long it, int* bout, double* th,
+                            double* ut) {
+  int b = 0;
+  while (b + 1 < a.nb && it >= a.first[b + 1]) ++b;
+  *bout = b;
+  const long long c = it - a.first[b];
+  const int ci0 = a.boxes[4 * b], ci1 = a.boxes[4 * b + 1];
+  const int cj0 = a.boxes[4 * b + 2];
+  const int bw = ci1 - ci0 + 1;
+  const int ci = ci0 + (int)(c % bw), cj = cj0 + (int)(c / bw);
   const long long nn = (long long)(a.nx + 1) * (a.ny + 1);
-  for (int b = 0; b < a.nb; ++b) {
-    const int ci0 = a.boxes[4 * b], ci1 = a.boxes[4 * b + 1];
-    const int cj0 = a.boxes[4 * b + 2], cj1 = a.boxes[4 * b + 3];
-    const int bw = ci1 - ci0 + 1;
-    const long long total = (ci1 >= ci0 && cj1 >= cj0) ? (long long)bw * (cj1 - cj0 + 1) : 0;
-    const double cxb = a.circ[b].cx, cyb = a.circ[b].cy;
-    const double psib = a.st->xb[a.st->iters & 1][b];
-    for (long long c0 = 0; c0 < total; c0 += BLOCK) {
-      const long long c = c0 + threadIdx.x;
-      int cnt = 0;
-      double th[4], ut[4];
-      if (c < total) {
-        const int ci = ci0 + (int)(c % bw), cj = cj0 + (int)(c / bw);
-        const long long n0 = (long long)cj * (a.nx + 1) + ci;
-        const long long nd[4] = {n0, n0 + 1, n0 + a.nx + 2, n0 + a.nx + 1};
-        const int bb0 = a.body[nd[0]];
-        const bool inside = bb0 >= 0 && a.body[nd[1]] == bb0 && a.body[nd[2]] == bb0 &&
-                            a.body[nd[3]] == bb0;
-        bool fluid = false;
-        for (int k = 0; k < 4; ++k) fluid |= a.kind[nd[k]] == MFP_FLUID;
-        if (!inside && fluid) {
-          double X[4], Y[4], ps[4];
-          const int oi[4] = {0, 1, 1, 0}, oj[4] = {0, 0, 1, 1};
-          for (int k = 0; k < 4; ++k) {
-            X[k] = a.x0 + (double)(ci + oi[k]) * a.hx + a.disp[nd[k]];
-            Y[k] = a.y0 + (double)(cj + oj[k]) * a.hy + a.disp[nd[k] + nn];
-            ps[k] = a.psi[nd[k]];
-          }
-          const double gx = 0.25 * ((X[0] + X[1]) + (X[2] + X[3]));
-          const double gy = 0.25 * ((Y[0] + Y[1]) + (Y[2] + Y[3]));
-          const double psic = 0.25 * ((ps[0] + ps[1]) + (ps[2] + ps[3]));
-          for (int k = 0; k < 4; ++k) {
-            const int k2 = (k + 1) & 3;
-            if (a.kind[nd[k]] == MFP_SNAPPED && a.kind[nd[k2]] == MFP_SNAPPED &&
-                a.body[nd[k]] == b && a.body[nd[k2]] == b) {
-              const double ex = X[k2] - X[k], ey = Y[k2] - Y[k];
-              const double len = sqrt(ex * ex + ey * ey);
-              if (len > 1e-12 * a.hmax) {
-                const double dnc = fabs(ex * (gy - Y[k]) - ey * (gx - X[k])) / len;
-                const double mx = 0.5 * (X[k] + X[k2]), my = 0.5 * (Y[k] + Y[k2]);
-                th[cnt] = atan2(my - cyb, mx - cxb);
-                ut[cnt] = (psic - psib) / dnc;
-                ++cnt;
-              }
-            }
-          }
+  const long long n0 = (long long)cj * (a.nx + 1) + ci;
+  const long long nd[4] = {n0, n0 + 1, n0 + a.nx + 2, n0 + a.nx + 1};
+  const int bb0 = a.body[nd[0]];
+  const bool inside =
+      bb0 >= 0 && a.body[nd[1]] == bb0 && a.body[nd[2]] == bb0 && a.body[nd[3]] == bb0;
+  bool fluid = false;
+  for (int k = 0; k < 4; ++k) fluid |= a.kind[nd[k]] == MFP_FLUID;
+  if (inside || !fluid) return 0;
+  double X[4], Y[4], ps[4];
+  const int oi[4] = {0, 1, 1, 0}, oj[4] = {0, 0, 1, 1};
+  for (int k = 0; k < 4; ++k) {
+    X[k] = a.x0 + (double)(ci + oi[k]) * a.hx + a.disp[nd[k]];
+    Y[k] = a.y0 + (double)(cj + oj[k]) * a.hy + a.disp[nd[k] + nn];
+    ps[k] = a.psi[nd[k]];
+  }
+  const double gx = 0.25 * ((X[0] + X[1]) + (X[2] + X[3]));
+  const double gy = 0.25 * ((Y[0] + Y[1]) + (Y[2] + Y[3]));
+  const double psic = 0.25 * ((ps[0] + ps[1]) + (ps[2] + ps[3]));
+  const double psib = a.st->xb[a.st->iters & 1][b];
+  int cnt = 0;
+  for (int k = 0; k < 4; ++k) {
+    const int k2 = (k + 1) & 3;
+    if (a.kind[nd[k]] == MFP_SNAPPED && a.kind[nd[k2]] == MFP_SNAPPED && a.body[nd[k]] == b &&
+        a.body[nd[k2]] == b) {
+      const double ex = X[k2] - X[k], ey = Y[k2] - Y[k];
+      const double len = sqrt(ex * ex + ey * ey);
+      if (len > 1e-12 * a.hmax) {
+        if (th) {
+          const double dnc = fabs(ex * (gy - Y[k]) - ey * (gx - X[k])) / len;
+          const double mx = 0.5 * (X[k] + X[k2]), my = 0.5 * (Y[k] + Y[k2]);
+          th[cnt] = atan2(my - a.circ[b].cy, mx - a.circ[b].cx);
+          ut[cnt] = (psic - psib) / dnc;
         }
+        ++cnt;
       }
-      s_scan[threadIdx.x] = cnt;
-      __syncthreads();
-      for (int off = 1; off < BLOCK; off <<= 1) {
-        const int v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
-        __syncthreads();
-        s_scan[threadIdx.x] += v;
-        __syncthreads();
-      }
-      const int start = s_base + s_scan[threadIdx.x] - cnt;
-      for (int k = 0; k < cnt; ++k) {
-        const int o = start + k;
-        if (o < a.cap) {
-          a.samples[2 * o] = th[k];
-          a.samples[2 * o + 1] = ut[k];
-          a.sbody[o] = (int8_t)b;
-        }
-      }
-      __syncthreads();
-      if (threadIdx.x == BLOCK - 1) s_base += s_scan[BLOCK - 1];
-      __syncthreads();
     }
   }
-  if (threadIdx.x == 0) *a.count = s_base;
+  return cnt;
+}
+
+// Exclusive scan of one int per thread over the block; *sum gets the block total.
+__device__ int block_exscan_int(int v, int* s_scan, int* sum) {
+  const int tid = threadIdx.x;
+  s_scan[tid] = v;
+  __syncthreads();
+  for (int off = 1; off < BLOCK; off <<= 1) {
+    const int u = tid >= off ? s_scan[tid - off] : 0;
+    __syncthreads();
+    s_scan[tid] += u;
+    __syncthreads();
+  }
+  const int incl = s_scan[tid];
+  *sum = s_scan[BLOCK - 1];
+  __syncthreads();
+  return incl - v;
+}
+
+// Pass 1: samples per block of SMP_CHUNK items.
+__global__ void __launch_bounds__(BLOCK) k_samples_count(SampleArgs a) {
+  __shared__ int s_scan[BLOCK];
+  const long long i0 = (long long)blockIdx.x * SMP_CHUNK + (long long)threadIdx.x * SMP_ITEMS;
+  int cnt = 0, b;
+  for (int q = 0; q < SMP_ITEMS; ++q)
+    if (i0 + q < a.items) cnt += item_samples(a, i0 + q, &b, nullptr, nullptr);
+  int sum;
+  (void)block_exscan_int(cnt, s_scan, &sum);
+  if (threadIdx.x == 0) a.boff[blockIdx.x] = sum;
+}
+
+// Pass 2 (one block): block counts -> offsets; the total into *count.
+__global__ void __launch_bounds__(BLOCK) k_samples_scan(SampleArgs a, int nblk) {
+  __shared__ int s_scan[BLOCK];
+  const int per = (nblk + BLOCK - 1) / BLOCK;
+  const int b0 = threadIdx.x * per;
+  int loc = 0;
+  for (int k = 0; k < per; ++k)
+    if (b0 + k < nblk) loc += a.boff[b0 + k];
+  int sum;
+  int off = block_exscan_int(loc, s_scan, &sum);
+  for (int k = 0; k < per; ++k)
+    if (b0 + k < nblk) {
+      const int c = a.boff[b0 + k];
+      a.boff[b0 + k] = off;
+      off += c;
+    }
+  if (threadIdx.x == 0) *a.count = sum;
+}
+
+// Pass 3: every block writes its samples from its offset, in item and edge order.
+__global__ void __launch_bounds__(BLOCK) k_samples_write(SampleArgs a) {
+  __shared__ int s_scan[BLOCK];
+  const long long i0 = (long long)blockIdx.x * SMP_CHUNK + (long long)threadIdx.x * SMP_ITEMS;
+  int cnt = 0, b;
+  for (int q = 0; q < SMP_ITEMS; ++q)
+    if (i0 + q < a.items) cnt += item_samples(a, i0 + q, &b, nullptr, nullptr);
+  int sum;
+  int o = a.boff[blockIdx.x] + block_exscan_int(cnt, s_scan, &sum);
+  for (int q = 0; q < SMP_ITEMS; ++q) {
+    if (i0 + q >= a.items) break;
+    double th[4], ut[4];
+    const int k = item_samples(a, i0 + q, &b, th, ut);
+    for (int s = 0; s < k; ++s, ++o)
+      if (o < a.cap) {
+        a.samples[2 * o] = th[s];
+        a.samples[2 * o + 1] = ut[s];
+        a.sbody[o] = (int8_t)b;
+      }
+  }
 }
 
 // ---------------------------------------------------------------------------------
@@ -641,6 +694,8 @@ struct SolveWs {
   mfp_circle* circ;
   int* boxes;
   int* count;
+  int* sboff;     // surface samples: per-block counts / offsets
+  int sboff_n = 0;
   int phi = 0;    // velocity-potential solve: body nodes are unknowns, no body constraint
 };
 
@@ -710,6 +765,13 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
   w.boxes = bp.take<int>(4 * (nb > 0 ? nb : 1));
   w.count = bp.take<int>(1);
+  {
+    // surface samples: at most nb boxes of at most nx ny cells each
+    const long long items = (long long)(nb > 0 ? nb : 0) * g->nx * g->ny;
+    const long long blk = (items + SMP_CHUNK - 1) / SMP_CHUNK + 1;
+    w.sboff_n = (int)(blk < SMP_MAX_BLOCKS ? blk : SMP_MAX_BLOCKS);
+    w.sboff = bp.take<int>((size_t)w.sboff_n);
+  }
   if (out) {
     if (base) w.sp = seg_plan(w.L, single_target(w.L, precision));
     *out = w;
@@ -1515,7 +1577,28 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
     sa.sbody = sample_body;
     sa.cap = sample_cap;
     sa.count = w.count;
-    k_samples<<<1, BLOCK, 0, st>>>(sa);
+    int hb[4 * MFP_MAX_BODIES];
+    circle_boxes(g, circles_h, nb, hb);
+    sa.items = 0;
+    for (int q = 0; q < nb; ++q) {
+      sa.first[q] = sa.items;
+      if (hb[4 * q + 1] >= hb[4 * q] && hb[4 * q + 3] >= hb[4 * q + 2])
+        sa.items += (long long)(hb[4 * q + 1] - hb[4 * q] + 1) * (hb[4 * q + 3] - hb[4 * q + 2] + 1);
+    }
+    sa.first[nb] = sa.items;
+    const long long nblk = (sa.items + SMP_CHUNK - 1) / SMP_CHUNK;
+    if (nblk > w.sboff_n) {
+      set_error("internal: too many sample cells");
+      return MFP_E_ARG;
+    }
+    sa.boff = w.sboff;
+    if (nblk > 0) {
+      k_samples_count<<<(unsigned)nblk, BLOCK, 0, st>>>(sa);
+      k_samples_scan<<<1, BLOCK, 0, st>>>(sa, (int)nblk);
+      k_samples_write<<<(unsigned)nblk, BLOCK, 0, st>>>(sa);
+    } else {
+      MFP_TRY_HIP(hipMemsetAsync(w.count, 0, sizeof(int), st));
+    }
     MFP_TRY_HIP(hipGetLastError());
     MFP_TRY_HIP(hipMemcpyAsync(&nsamp, w.count, sizeof(int), hipMemcpyDeviceToHost, st));
   }
