@@ -151,3 +151,38 @@ def test_cubic_fit_matches_the_oracle():
         m.cubic_fit([1.0, 1.0, 2.0, 2.0, 3.0], [0.0, 1.0, 2.0, 3.0, 4.0])
     with pytest.raises(m.MfpError):
         m.cubic_fit([1.0, 2.0, 3.0], [0.0, 1.0, 2.0])
+
+
+def test_potential_and_contour_reject_bad_arguments_before_device_work(lib):
+    """Argument errors of mfp_phi_solve and mfp_contour come back as MFP_E_ARG or
+    MFP_E_WORKSPACE before any device call (the pointers below are never touched)."""
+    from paper_2512_12232_amd import binding as B
+    import paper_2512_12232_amd as mfp
+    fake = ctypes.c_void_p(4096)
+    g = B.make_grid(W.Grid(64, 32, -4, 4, -2, 2))
+    c = B.make_circles([(0, 0, 0.5)])
+    o = B.MfpSolverOpts(B.FP64, 1e-12, 100, 16, 0.1, 10, None)
+    stats = B.MfpStats()
+    bad = B.make_flow(W.Flow(1.0, (W.BC_DIRICHLET_UX, 5, 0, 0)))
+    assert lib.mfp_phi_solve(ctypes.byref(g), c, 1, fake, fake, fake, ctypes.byref(bad),
+                             ctypes.byref(o), fake, ctypes.byref(stats), fake, 1 << 40,
+                             None) == B.MFP_E_ARG
+    assert "boundary code" in mfp.last_error()
+    good = B.make_flow(W.potential_flow(W.single_cylinder(64)).flow)
+    assert lib.mfp_phi_solve(ctypes.byref(g), c, 1, fake, fake, fake, ctypes.byref(good),
+                             ctypes.byref(o), None, ctypes.byref(stats), fake, 1 << 40,
+                             None) == B.MFP_E_ARG
+    assert lib.mfp_phi_solve(ctypes.byref(g), c, 1, fake, fake, fake, ctypes.byref(good),
+                             ctypes.byref(o), fake, ctypes.byref(stats), fake, 16,
+                             None) == B.MFP_E_WORKSPACE
+    n = ctypes.c_int64(-1)
+    ws = lib.mfp_contour_workspace_size(ctypes.byref(g))
+    assert ws > 0
+    assert lib.mfp_contour(ctypes.byref(g), fake, fake, None, 0.0, fake, 4, ctypes.byref(n),
+                           fake, ws, None) == B.MFP_E_ARG
+    assert lib.mfp_contour(ctypes.byref(g), fake, fake, fake, float("nan"), fake, 4,
+                           ctypes.byref(n), fake, ws, None) == B.MFP_E_ARG
+    assert lib.mfp_contour(ctypes.byref(g), fake, fake, fake, 0.0, None, 4, ctypes.byref(n),
+                           fake, ws, None) == B.MFP_E_ARG
+    assert lib.mfp_contour(ctypes.byref(g), fake, fake, fake, 0.0, fake, 4, ctypes.byref(n),
+                           fake, ws - 1, None) == B.MFP_E_WORKSPACE
