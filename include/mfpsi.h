@@ -216,7 +216,8 @@ int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbo
  *     not all in one body) that is not Dirichlet is an unknown, body nodes included;
  *     nodes of no active cell lie inside a body and carry no equation.
  * Arguments as for mfp_psi_solve (same workspace size query, mfp_solve_workspace_size
- * with this nbody and precision).  Output:
+ * with this nbody and precision); opts->psi0, if set, is a nodal warm start for phi
+ * (its values at the unknowns are used, others ignored).  Output:
  *   phi      device double[(nx+1)(ny+1)]: nodal potential, NaN at nodes of no active
  *            cell;
  *   stats_h  host (may be NULL); n_dof = n_free = the number of unknowns.

@@ -278,10 +278,11 @@ class PhiResult:
 def phi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1e-12,
               kmax=10 ** 7, check_every=16, inner_rtol=0.1, max_outer=1000,
               ws: Optional[torch.Tensor] = None, allow_warn: bool = True,
-              profile_every: int = 0) -> PhiResult:
+              profile_every: int = 0, phi0: Optional[torch.Tensor] = None) -> PhiResult:
     """Velocity potential on the conformed mesh (mfp_phi_solve): ``flow`` gives the
     Dirichlet sides (e.g. phi = U x on inlet and outlet), bodies and the other sides
-    are natural boundaries."""
+    are natural boundaries.  phi0: optional nodal warm start (device doubles; its
+    values at the unknowns are used, NaN elsewhere is ignored)."""
     lib = load()
     g = make_grid(grid)
     c = make_circles(circles)
@@ -289,7 +290,8 @@ def phi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
     f = make_flow(flow)
     prec = _PREC[precision]
     o = MfpSolverOpts(prec, float(rtol), int(kmax), int(check_every), float(inner_rtol),
-                      int(max_outer), None, int(profile_every))
+                      int(max_outer), _ptr(phi0) if phi0 is not None else None,
+                      int(profile_every))
     n = (g.nx + 1) * (g.ny + 1)
     dev = disp.device
     phi = torch.empty(n, dtype=torch.float64, device=dev)

@@ -102,3 +102,19 @@ def test_phi_bench_workload_1024x512_matches_oracle_direct_solve(mfp):
     err = _compare(res, ref, 2e-10)
     say(f"  1024x512 phi: iters {res.stats['iters']} rel L2 {err:.2e} "
         f"unknowns {res.stats['n_dof']}")
+
+
+def test_phi_warm_start_from_its_solution(mfp):
+    """A warm start from the converged potential (psi0 of the options: its values at
+    the unknowns, body nodes included) starts at the solution's residual, so a
+    tolerance relative to it is met at once, and the result stays within 1e-12."""
+    c = CASES["five96x48"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    a = mfp.phi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13)
+    b = mfp.phi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13,
+                      phi0=a.phi.clone(), kmax=50)
+    assert b.stats["rnorm0"] < 1e-10 * a.stats["rnorm0"]
+    pa, pb = a.phi.cpu().numpy(), b.phi.cpu().numpy()
+    dom = ~np.isnan(pa)
+    np.testing.assert_array_equal(np.isnan(pb), ~dom)
+    assert np.abs(pa[dom] - pb[dom]).max() <= 1e-12 * np.abs(pa[dom]).max()
