@@ -240,6 +240,11 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   // anything issued before it a wait for everything.  So the scalars are reduced while
   // the rows travel, and the first task's geometry is requested right after the flags
   // arrive, together with the partials.
+  // The scalar phase (inputs in, wavefront sums, the block barrier, alpha and beta) runs
+  // at raised wave priority: the SIMD's other wavefront, already in its task, yields to
+  // it, so the block reaches its barrier sooner (1024x512: 13.73 -> 13.29 us per launch;
+  // 4096x2048 unchanged).  Back to normal priority for the task.
+  __builtin_amdgcn_s_setprio(3);
   const int npart = start ? a.npart0 : G;  // at least 1
   const gmem<double>* const pt = part_pg;
   constexpr int PU = 2;
@@ -395,6 +400,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   if (wv == 0 && lane < nb) s_pb[lane] = pbj;
   __syncthreads();
   const T al = (T)alpha, be = (T)beta, al2 = (T)alpha2;
+  __builtin_amdgcn_s_setprio(0);
 
   // ---- tasks ----
   double prr = 0.0, ppq = 0.0, prq = 0.0, pqq = 0.0;
