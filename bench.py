@@ -232,7 +232,7 @@ def adjoint_ratio(mfp, W):
     (d, k, b, r), fwd_ms = _timed(fwd, reps=2)
 
     def bwd():
-        g, expl, st, _ = mfp.psi_grad(case.grid, case.circles, d, k, b, case.flow, r.psi,
+        g, expl, st, _, _ = mfp.psi_grad(case.grid, case.circles, d, k, b, case.flow, r.psi,
                                       r.psi_b, dL_dcopfi=1.0, pair=case.pair, rtol=1e-12)
         dc, _ = mfp.mesh_conform_grad(case.grid, case.circles, k, b, g, case.nsweeps,
                                       dL_dcentre=expl)

@@ -104,7 +104,7 @@ typedef struct {
 
 typedef struct {
   int32_t precision;      /* MFP_FP64 / MFP_FP32 / MFP_FP32_IR                          */
-  double rtol;            /* stop when ||r_k|| <= rtol ||r_0|| (unknowns incl. bodies)  */
+  double rtol;            /* stop when ||r_k|| <= rtol ||b|| (unknowns incl. bodies)    */
   int64_t kmax;           /* CG iteration cap (all inner iterations together)           */
   int32_t check_every;    /* iterations per enqueued batch (0 -> 16); the host reads a
                              batch's stop flag while the next batch runs, so an outcome
@@ -113,11 +113,19 @@ typedef struct {
                              FP64 residual recomputations (0 < delta < 1; 0 -> 0.1)     */
   int32_t max_outer;      /* MFP_FP32_IR: cap on FP64 residual recomputations (0 -> 1000) */
   const double* psi0;     /* optional DEVICE warm start: nodal psi (free nodes) and the
-                             first node of each body (row-major) for psi_b; rtol is then
-                             relative to the residual of this start; may be NULL       */
+                             first node of each body (row-major) for psi_b; may be NULL.
+                             rtol stays relative to ||b|| (the residual of a zero start),
+                             so a better start means fewer iterations to the same target,
+                             unless rtol_from_start is set                             */
   int32_t profile_every;  /* > 0: time every n-th batch of iteration launches with HIP
                              events (between the events that end it and the batch
                              before it) -> stats.apply_ms                              */
+  int32_t estimate_kappa; /* != 0: fill stats.kappa_est (see mfp_stats); costs one copy
+                             of the CG scalars to the host and a host eigenvalue search */
+  int32_t rtol_from_start;/* != 0 with psi0: stop at rtol ||b - A psi0|| instead (a
+                             correction solve: from a nearby solution, e.g. one step of a
+                             parameter sweep or a finite difference, this reaches an
+                             absolute accuracy below what rtol ||b|| allows)            */
 } mfp_solver_opts;
 
 typedef struct {
@@ -126,13 +134,29 @@ typedef struct {
   int64_t applies;        /* element-operator applications (all precisions)             */
   int64_t n_dof;          /* N_int + N_N + N_b                                          */
   int64_t n_free;         /* N_int + N_N                                                */
-  double relres_true;     /* ||b - A x|| / ||b - A x0|| recomputed in FP64 at the end   */
-  double rnorm0;          /* ||b - A x0||                                               */
+  double relres_true;     /* ||b - A x|| / ||b|| recomputed in FP64 at the end          */
+  double rnorm0;          /* ||b|| (the residual of a zero start)                       */
   double solve_ms;        /* device time of the iteration phase (HIP events)            */
   double apply_ms;        /* mean time per iteration launch in the timed batches        */
   int64_t apply_samples;  /* launches behind apply_ms                                   */
-  int64_t n_plain_tiles;  /* 64x8 node tiles on the constant-stencil path               */
-  int64_t n_tiles;        /* all node tiles                                             */
+  int64_t n_plain_tiles;  /* tasks (node tiles) on the constant-stencil path             */
+  int64_t n_tiles;        /* all tasks                                                  */
+  int64_t inner_iters;    /* MFP_FP32 / MFP_FP32_IR: FP32 iterations among `iters`      */
+  /* Condition estimate (opts.estimate_kappa): the CG step lengths alpha_k and direction
+   * factors beta_k of Algorithm 1 define the Lanczos tridiagonal T of A on the Krylov
+   * space of the right-hand side (T_11 = 1/alpha_1, T_kk = 1/alpha_k + beta_k/alpha_(k-1),
+   * T_k,k-1 = sqrt(beta_k)/alpha_(k-1)); its extreme eigenvalues (Ritz values, found by
+   * Sturm bisection on the host) approach the extreme eigenvalues of A on that space.
+   * kappa_est = ritz_max / ritz_min.  A lower bound on cond_2(A): eigenvectors the
+   * right-hand side barely touches show late or not before the stop (for a mirror-
+   * symmetric layout b is odd in y, and only rounding reaches the even eigenvectors,
+   * that of lambda_min among them).  Taken from the last CG run (FP32 runs for the
+   * refined solve, joined
+   * across its residual replacements), at most the first 16384 iterations; 0 when not
+   * requested or fewer than 2 iterations ran.                                        */
+  double kappa_est;
+  double ritz_min, ritz_max;
+  int64_t kappa_steps;    /* order of T                                                 */
 } mfp_stats;
 
 /* Message for the last non-zero status returned on this thread ("" if none). */
@@ -180,7 +204,7 @@ int mfp_element_apply(const mfp_grid* grid, const double* disp, const int8_t* bo
  * Unknowns: free nodes (interior and natural-boundary nodes) plus one psi_b per body
  * (all of a body's nodes tied to it); Dirichlet sides prescribed by `flow`.  Solves
  * A y = b with A = T^T K T, b = -T^T K g by conjugate gradients (Algorithm 1), to
- * ||r_k|| <= rtol ||r_0||.
+ * ||r_k|| <= rtol ||b|| (= rtol ||r_0|| from the default zero start).
  * Outputs:
  *   psi         device double[(nx+1)(ny+1)]: nodal psi (body nodes carry psi_b);
  *   psi_b_h     host double[nbody];
@@ -194,7 +218,9 @@ int mfp_element_apply(const mfp_grid* grid, const double* disp, const int8_t* bo
  *   sample_body device int8[sample_cap];
  *   n_samples_h host: number of samples that exist (may exceed sample_cap);
  *   stats_h     host (may be NULL).
- * Returns MFP_W_NOCONV if kmax was reached, MFP_E_BREAKDOWN on CG breakdown. */
+ * Returns MFP_W_NOCONV if kmax was reached, MFP_E_BREAKDOWN on CG breakdown (p.Ap <= 0
+ * or a non-finite value, e.g. from a non-finite warm start; every kernel still ends
+ * normally), MFP_E_ARG for a non-finite U or bad arguments (before any device work). */
 int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
                   const double* disp, const int8_t* kind, const int8_t* body,
                   const mfp_flow* flow, const mfp_solver_opts* opts,
@@ -274,16 +300,22 @@ size_t mfp_grad_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t prec
  *                   (component-major like disp, device memory, overwritten);
  *   explicit term   dL_dcentre_h[2b+1] (host, overwritten; x entries set to 0) holds
  *                   dL_dcopfi times the derivative of CoPFI = Q / (U (cy_hi - cy_lo))
- *                   with respect to the pair's centre heights.
+ *                   with respect to the pair's centre heights;
+ *   free stream     dL_dU_h (host, may be NULL): dL/dU.  Every side datum is U times a
+ *                   fixed function, so b = U b1 and y = U y1; the adjoint identity
+ *                   lambda^T db/dU = (dL/dy)^T y / U, less the explicit U in CoPFI's
+ *                   denominator, gives sum_b dL_dpsib_h[b] psi_b[b] / U (CoPFI itself
+ *                   does not depend on U).
  * psi / psi_b_h are the outputs of mfp_psi_solve for the same inputs.  dL_dpsib_h may be
- * NULL; pair indices < 0 or dL_dcopfi == 0 skip the CoPFI terms.  Add the mesh part
- * with mfp_mesh_conform_grad. */
+ * NULL; pair indices < 0 or dL_dcopfi == 0 skip the CoPFI terms.  opts->psi0 is ignored
+ * (the adjoint solve always starts from zero; a forward warm start would not fit its
+ * right-hand side).  Add the mesh part with mfp_mesh_conform_grad. */
 int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
                  const double* disp, const int8_t* kind, const int8_t* body,
                  const mfp_flow* flow, const mfp_solver_opts* opts, const double* psi,
                  const double* psi_b_h, const double* dL_dpsib_h, double dL_dcopfi,
                  int32_t pair_lo, int32_t pair_hi, double* dL_ddisp, double* dL_dcentre_h,
-                 mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream);
+                 double* dL_dU_h, mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for mfp_mesh_conform_grad. */
 size_t mfp_conform_grad_workspace_size(const mfp_grid* grid, int32_t nbody);

@@ -28,7 +28,9 @@ Body-Conforming Grids"):
 * ``sweep`` -- the cubic fit of CoPFI over the gap ratio (section "Effect of
   Gap Ratio");
 * ``cg``    -- a plain conjugate-gradient loop on the assembled matrix (CPU
-  timing baseline).
+  timing baseline);
+* ``spectrum`` -- extreme eigenvalues of the reduced operator (condition number)
+  and the Ritz extremes of the Lanczos process from a right-hand side.
 
 Readings of passages where the paper is silent or ambiguous are listed in the
 module docstrings where they are applied.
@@ -43,6 +45,7 @@ from .solve import (dirichlet_mask, dirichlet_values, dof_numbering,
 from .potential import in_domain, phi_solve, cell_velocity, PhiSolution
 from .sweep import cubic_fit
 from .contour import contour
+from .spectrum import condition_number, lanczos_extremes
 
 __all__ = [
     "FLUID", "SNAPPED", "DEEP", "GeometryError", "spacing", "node_coords",
@@ -52,5 +55,5 @@ __all__ = [
     "rectangle_stiffness", "dirichlet_mask", "dirichlet_values",
     "dof_numbering", "reduced_system", "solve", "surface_samples", "copfi",
     "Solution", "in_domain", "phi_solve", "cell_velocity", "PhiSolution", "cubic_fit",
-    "contour",
+    "contour", "condition_number", "lanczos_extremes",
 ]

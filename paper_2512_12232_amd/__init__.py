@@ -5,13 +5,17 @@ circles, the multi-point-constrained conjugate-gradient solve for psi, and the
 derived body stream-function values, surface velocities, inter-body flow rate
 and CoPFI; the velocity potential phi on the same mesh (the flow net).  All arithmetic runs in the library's HIP kernels.
 """
-from .binding import (MfpError, check_geometry, contour, cubic_fit, element_apply,
+from .binding import (MFP_OK, MFP_W_NOCONV, MFP_W_STAGNATION, MFP_E_ARG, MFP_E_HIP,
+                      MFP_E_GEOMETRY, MFP_E_TANGLED, MFP_E_BREAKDOWN, MFP_E_WORKSPACE,
+                      MfpError, check_geometry, contour, cubic_fit, element_apply,
                       last_error, load,
                       mesh_conform, mesh_conform_grad, phi_solve, psi_grad, psi_solve,
                       psi_solve_batched, solve_workspace_size, EXPORTS)
 from .autograd import CoPFIFunction, copfi
 
-__all__ = ["MfpError", "check_geometry", "contour", "cubic_fit", "element_apply", "last_error", "load",
+__all__ = ["MFP_OK", "MFP_W_NOCONV", "MFP_W_STAGNATION", "MFP_E_ARG", "MFP_E_HIP",
+           "MFP_E_GEOMETRY", "MFP_E_TANGLED", "MFP_E_BREAKDOWN", "MFP_E_WORKSPACE",
+           "MfpError", "check_geometry", "contour", "cubic_fit", "element_apply", "last_error", "load",
            "mesh_conform", "mesh_conform_grad", "phi_solve", "psi_grad", "psi_solve",
            "psi_solve_batched",
            "solve_workspace_size", "EXPORTS", "CoPFIFunction", "copfi"]

@@ -52,14 +52,17 @@ class MfpFlow(Structure):
 class MfpSolverOpts(Structure):
     _fields_ = [("precision", c_int32), ("rtol", c_double), ("kmax", c_int64),
                 ("check_every", c_int32), ("inner_rtol", c_double), ("max_outer", c_int32),
-                ("psi0", c_void_p), ("profile_every", c_int32)]
+                ("psi0", c_void_p), ("profile_every", c_int32), ("estimate_kappa", c_int32),
+                ("rtol_from_start", c_int32)]
 
 
 class MfpStats(Structure):
     _fields_ = [("iters", c_int64), ("outer_iters", c_int64), ("applies", c_int64),
                 ("n_dof", c_int64), ("n_free", c_int64), ("relres_true", c_double),
                 ("rnorm0", c_double), ("solve_ms", c_double), ("apply_ms", c_double),
-                ("apply_samples", c_int64), ("n_plain_tiles", c_int64), ("n_tiles", c_int64)]
+                ("apply_samples", c_int64), ("n_plain_tiles", c_int64), ("n_tiles", c_int64),
+                ("inner_iters", c_int64), ("kappa_est", c_double), ("ritz_min", c_double),
+                ("ritz_max", c_double), ("kappa_steps", c_int64)]
 
 
 class MfpVariant(Structure):
@@ -116,8 +119,8 @@ def load(path: str = LIB_PATH):
     lib.mfp_psi_grad.argtypes = [
         POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_void_p, c_void_p, c_void_p,
         POINTER(MfpFlow), POINTER(MfpSolverOpts), c_void_p, POINTER(c_double), c_void_p,
-        c_double, c_int32, c_int32, c_void_p, POINTER(c_double), POINTER(MfpStats), c_void_p,
-        c_size_t, c_void_p]
+        c_double, c_int32, c_int32, c_void_p, POINTER(c_double), POINTER(c_double),
+        POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
     lib.mfp_conform_grad_workspace_size.restype = c_size_t
     lib.mfp_conform_grad_workspace_size.argtypes = [POINTER(MfpGrid), c_int32]
     lib.mfp_mesh_conform_grad.argtypes = [
@@ -232,7 +235,8 @@ def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
               kmax=10 ** 7, check_every=16, inner_rtol=0.1, max_outer=1000, pair=(-1, -1),
               sample_cap=None, ws: Optional[torch.Tensor] = None,
               allow_warn: bool = True, profile_every: int = 0,
-              psi0: Optional[torch.Tensor] = None) -> SolveResult:
+              psi0: Optional[torch.Tensor] = None, estimate_kappa: bool = False,
+              rtol_from_start: bool = False) -> SolveResult:
     lib = load()
     g = make_grid(grid)
     c = make_circles(circles)
@@ -241,7 +245,7 @@ def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
     prec = _PREC[precision]
     o = MfpSolverOpts(prec, float(rtol), int(kmax), int(check_every), float(inner_rtol),
                       int(max_outer), _ptr(psi0) if psi0 is not None else None,
-                      int(profile_every))
+                      int(profile_every), int(bool(estimate_kappa)), int(bool(rtol_from_start)))
     n = (g.nx + 1) * (g.ny + 1)
     dev = disp.device
     psi = torch.empty(n, dtype=torch.float64, device=dev)
@@ -278,7 +282,8 @@ class PhiResult:
 def phi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1e-12,
               kmax=10 ** 7, check_every=16, inner_rtol=0.1, max_outer=1000,
               ws: Optional[torch.Tensor] = None, allow_warn: bool = True,
-              profile_every: int = 0, phi0: Optional[torch.Tensor] = None) -> PhiResult:
+              profile_every: int = 0, phi0: Optional[torch.Tensor] = None,
+              estimate_kappa: bool = False, rtol_from_start: bool = False) -> PhiResult:
     """Velocity potential on the conformed mesh (mfp_phi_solve): ``flow`` gives the
     Dirichlet sides (e.g. phi = U x on inlet and outlet), bodies and the other sides
     are natural boundaries.  phi0: optional nodal warm start (device doubles; its
@@ -291,7 +296,7 @@ def phi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
     prec = _PREC[precision]
     o = MfpSolverOpts(prec, float(rtol), int(kmax), int(check_every), float(inner_rtol),
                       int(max_outer), _ptr(phi0) if phi0 is not None else None,
-                      int(profile_every))
+                      int(profile_every), int(bool(estimate_kappa)), int(bool(rtol_from_start)))
     n = (g.nx + 1) * (g.ny + 1)
     dev = disp.device
     phi = torch.empty(n, dtype=torch.float64, device=dev)
@@ -344,22 +349,23 @@ def solve_workspace_size(grid, nbody: int, precision: str = "fp64") -> int:
     return load().mfp_solve_workspace_size(byref(g), int(nbody), _PREC[precision])
 
 
-def _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer):
+def _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa=False):
     return MfpSolverOpts(_PREC[precision], float(rtol), int(kmax), int(check_every),
-                         float(inner_rtol), int(max_outer), None, 0)
+                         float(inner_rtol), int(max_outer), None, 0, int(bool(estimate_kappa)), 0)
 
 
 def psi_grad(grid, circles, disp, kind, body, flow, psi, psi_b, *, dL_dpsib=None,
              dL_dcopfi=0.0, pair=(-1, -1), precision="fp64", rtol=1e-12, kmax=10 ** 7,
-             check_every=16, inner_rtol=0.1, max_outer=1000):
+             check_every=16, inner_rtol=0.1, max_outer=1000, allow_warn=True,
+             estimate_kappa=False):
     """Adjoint solve + shape derivative.  Returns (dL_ddisp device tensor [2*nodes],
-    explicit dL/dcentre list of (dx, dy) per body, stats, status)."""
+    explicit dL/dcentre list of (dx, dy) per body, stats, status, dL/dU)."""
     lib = load()
     g = make_grid(grid)
     c = make_circles(circles)
     nb = len(circles)
     f = make_flow(flow)
-    o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer)
+    o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa)
     n = (g.nx + 1) * (g.ny + 1)
     dev = disp.device
     out = torch.empty(2 * n, dtype=torch.float64, device=dev)
@@ -368,14 +374,16 @@ def psi_grad(grid, circles, disp, kind, body, flow, psi, psi_b, *, dL_dpsib=None
     if dL_dpsib is not None:
         dpb = (c_double * max(nb, 1))(*[float(v) for v in dL_dpsib])
     dcen = (c_double * max(2 * nb, 1))()
+    dU = c_double(0.0)
     st = MfpStats()
     ws = workspace(lib.mfp_grad_workspace_size(byref(g), nb, _PREC[precision]), dev)
     status = _check(lib.mfp_psi_grad(
         byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o), _ptr(psi),
-        pb, dpb, float(dL_dcopfi), int(pair[0]), int(pair[1]), _ptr(out), dcen, byref(st),
-        _ptr(ws), ws.numel(), _stream()))
+        pb, dpb, float(dL_dcopfi), int(pair[0]), int(pair[1]), _ptr(out), dcen, byref(dU),
+        byref(st), _ptr(ws), ws.numel(), _stream()), allow_warn)
     stats = {k: getattr(st, k) for k, _ in MfpStats._fields_}
-    return out, [(dcen[2 * b], dcen[2 * b + 1]) for b in range(nb)], stats, status
+    return (out, [(dcen[2 * b], dcen[2 * b + 1]) for b in range(nb)], stats, status,
+            dU.value)
 
 
 def mesh_conform_grad(grid, circles, kind, body, dL_ddisp, nsweeps=200, dL_dcentre=None,

@@ -1,9 +1,9 @@
 // Matrix-free Q1 element operator on the padded node layout.
 //
-// The paper's Algorithm 1 (appendix) loops over elements, multiplies each element
-// matrix with the element extract of the global vector and accumulates the element
-// results into the global vector; its element matrices are K_e = int (grad N)^T
-// (grad N) dOmega (section "Weak formulation").  Here the element matrix is never
+// Algorithm 1 (appendix) forms K p cell by cell: each cell's 4x4 matrix
+// K_e = int (grad N)^T (grad N) dOmega (section "Weak formulation") acts on the cell's
+// four nodal values, and the four results are summed into the nodes they belong to.
+// Here the element matrix is never
 // stored: each wavefront owns strips of 62 node columns (plus one halo column on
 // each side) and marches up them a few node rows at a time, evaluating K_e(X_e) p_e
 // for every cell touching its rows with the 2x2 Gauss rule from the node

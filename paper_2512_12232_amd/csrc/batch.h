@@ -621,6 +621,7 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
       // CG steps: launches 2..J (a restart runs launch J again, without a step)
       o.iters = J > 1 ? J - 1 : 0;
       o.outer_iters = mixed ? s.outer_count : 0;
+      o.inner_iters = mixed ? o.iters : 0;
       // element applies: the steps, the restarts and the FP64 residuals
       o.applies = o.iters + (mixed ? 2 * s.outer_count + 1 : 2);
       o.rnorm0 = std::sqrt(s.rr0);

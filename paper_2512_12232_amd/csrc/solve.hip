@@ -601,6 +601,8 @@ __global__ void __launch_bounds__(BLOCK) k_samples_write(SampleArgs a) {
 // Workspace and host driver
 // ---------------------------------------------------------------------------------
 constexpr int GMAX = 2048;  // max blocks of the reduction kernels
+// Launches whose CG scalars are kept for the condition estimate (256 KiB).
+constexpr long long HIST_CAP = 16384;
 
 // Wavefronts of the one-kernel CG iteration k_step<T, hc> resident on the current
 // device at once (0 when the runtime cannot say).
@@ -688,6 +690,7 @@ struct SolveWs {
   double* bpart;
   size_t bstride;   // per-slot body sums: parity slot 1 starts at bpart + bstride
   double* spart;    // one-kernel iteration partials, 2 slots x 4 x GMAX
+  double* hist;     // CG scalars per launch (alpha_{j-1}, beta_j), HIST_CAP launches
   DevState* st;
   DevState* st2;  // inner (FP32) solver state
   long long* nfree;
@@ -759,6 +762,7 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.bstride = (size_t)(nt > 64 ? nt : 64) * (nb > 0 ? nb : 1);
   w.bpart = bp.take<double>(2 * w.bstride);
   w.spart = bp.take<double>(2 * 4 * GMAX);
+  w.hist = bp.take<double>(2 * (size_t)HIST_CAP);
   w.st = bp.take<DevState>(1);
   w.st2 = bp.take<DevState>(1);
   w.nfree = bp.take<long long>(1);
@@ -1256,6 +1260,8 @@ static int solve64(const mfp_grid& g, int nb, const SolveWs& w, const mfp_solver
                    hipStream_t st, CgCount* cnt, long long kmax = 0) {
   StepRun<double> a = make_step_run<double>(w, g, nb, w.dx, w.dy, w.r, w.r1, w.p0, w.p1,
                                               w.q, w.q1, w.x, w.st);
+  a.a.hist = w.hist;
+  a.a.hist_cap = HIST_CAP;
   const long long km = kmax > 0 ? kmax : o.kmax;
   MFP_TRY(step_start<double>(w, nb, a, 1, true, false, 0.0, 1 + km, st, &a.a.npart0));
   return step_run<double>(w, a, o, st, cnt, 1);
@@ -1283,6 +1289,8 @@ static int solve_mixed(const mfp_grid& g, int nb, const SolveWs& w, const mfp_so
   MFP_TRY_HIP(hipMemsetAsync(w.xf, 0, sizeof(float) * w.L.n, st));
   StepRun<float> a = make_step_run<float>(w, g, nb, w.dxf, w.dyf, w.rf, w.r1f, w.p0f, w.p1f,
                                             w.qf, w.q1f, w.xf, w.st2);
+  a.a.hist = w.hist;
+  a.a.hist_cap = HIST_CAP;
   long long k0 = 1;
   bool fresh = true;
   int code = 0;
@@ -1348,9 +1356,86 @@ __global__ void k_warm_x(Layout L, int nx, int ny, const int8_t* __restrict__ ta
 struct SolveInfo {
   int done = 0;
   bool stagnated = false;
-  long long iters = 0, outer = 0, applies = 0, apply_samples = 0;
+  long long iters = 0, inner = 0, outer = 0, applies = 0, apply_samples = 0;
   double apply_ms = 0.0, solve_ms = 0.0;
+  double kappa = 0.0, ritz_min = 0.0, ritz_max = 0.0;
+  long long kappa_steps = 0;
 };
+
+// Number of eigenvalues below x of the symmetric tridiagonal with diagonal d[0..m) and
+// squared off-diagonals e2[1..m) (e2[k] couples k-1 and k): the sign changes of the
+// Sturm sequence of leading-minor ratios.
+static int sturm_count(const std::vector<double>& d, const std::vector<double>& e2, double x,
+                       double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  for (size_t k = 0;;) {
+    if (std::fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+    if (++k >= d.size()) break;
+    q = (d[k] - x) - e2[k] / q;
+  }
+  return cnt;
+}
+
+// Condition estimate from the CG scalars of one run (section "Matrix-Free Conjugate
+// Gradient..." / Algorithm 1: alpha = r.r / p.Ap, beta = r_new.r_new / r.r).  CG on A
+// is the Lanczos process on A started from the first residual; its tridiagonal T has
+//   T_11 = 1/alpha_1,  T_kk = 1/alpha_k + beta_k/alpha_(k-1),
+//   T_k,k-1 = sqrt(beta_k)/alpha_(k-1)
+// (alpha_k: step along p_k; beta_k: p_k = r_k + beta_k p_(k-1)).  hist holds launch j's
+// (alpha_(j-1), beta_j) at [2j], [2j+1] for j = 1..J (2J + 2 entries); J is the last
+// launch kept, so T has order J-1, cut at the first step length that is not positive
+// and finite.  Extreme eigenvalues by bisection from the Gershgorin interval.
+static void lanczos_kappa(const std::vector<double>& hist, long long J, SolveInfo* info) {
+  const long long m = J - 1;
+  if ((long long)hist.size() < 2 * (J + 1)) return;
+  std::vector<double> d, e2;
+  for (long long k = 1; k <= m; ++k) {
+    const double ak = hist[2 * (k + 1)];  // alpha_k, formed by launch k+1
+    if (!(ak > 0.0) || !std::isfinite(ak)) break;
+    if (k == 1) {
+      d.push_back(1.0 / ak);
+      e2.push_back(0.0);
+    } else {
+      const double ap = hist[2 * k], bk = hist[2 * k + 1];  // alpha_(k-1), beta_k
+      if (!(bk >= 0.0) || !std::isfinite(bk)) break;
+      d.push_back(1.0 / ak + bk / ap);
+      e2.push_back(bk / (ap * ap));
+    }
+  }
+  const size_t n = d.size();
+  if (n < 2) return;
+  double lo = d[0], hi = d[0], emax = 0.0;
+  for (size_t k = 0; k < n; ++k) {
+    const double r = (k > 0 ? std::sqrt(e2[k]) : 0.0) + (k + 1 < n ? std::sqrt(e2[k + 1]) : 0.0);
+    lo = std::fmin(lo, d[k] - r);
+    hi = std::fmax(hi, d[k] + r);
+    emax = std::fmax(emax, e2[k]);
+  }
+  const double pivmin = 1e-300 * std::fmax(1.0, emax);
+  const double span = hi - lo;
+  lo -= 1e-12 * span;
+  hi += 1e-12 * span;
+  // smallest: count(x) >= 1 iff x > lambda_min; largest: count(x) == n iff x > lambda_max
+  double a = lo, b = hi;
+  for (int it = 0; it < 200 && b - a > 1e-13 * std::fabs(b); ++it) {
+    const double c = 0.5 * (a + b);
+    (sturm_count(d, e2, c, pivmin) >= 1 ? b : a) = c;
+  }
+  const double lmin = 0.5 * (a + b);
+  a = lo;
+  b = hi;
+  for (int it = 0; it < 200 && b - a > 1e-13 * std::fabs(b); ++it) {
+    const double c = 0.5 * (a + b);
+    (sturm_count(d, e2, c, pivmin) >= (int)n ? b : a) = c;
+  }
+  const double lmax = 0.5 * (a + b);
+  info->ritz_min = lmin;
+  info->ritz_max = lmax;
+  info->kappa = lmin > 0.0 ? lmax / lmin : 0.0;
+  info->kappa_steps = (long long)n;
+}
 
 static int check_solve_args(const mfp_grid* grid, const mfp_circle* circles_h, int nbody,
                             const double* disp, const int8_t* kind, const int8_t* body,
@@ -1410,12 +1495,6 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
     MFP_TRY_HIP(hipMemcpyAsync(w.circ, circles_h, sizeof(mfp_circle) * nb,
                                hipMemcpyHostToDevice, st));
   }
-  if (opts->psi0) {
-    const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
-    k_warm_x<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, opts->psi0, w.x);
-    if (nb > 0) k_warm_xb<<<1, 64, 0, st>>>(g.nx, g.ny, nb, w.boxes, body, opts->psi0, w.st);
-    MFP_TRY_HIP(hipGetLastError());
-  }
   MFP_TRY_HIP(hipMemcpyAsync(&w.nslots_h, w.nslots, sizeof(int), hipMemcpyDeviceToHost, st));
   MFP_TRY_HIP(hipStreamSynchronize(st));  // host-side staging buffers above, slot count
 
@@ -1427,9 +1506,23 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
   long long outer = 0, total_iters = 0;
   int done = 1;
   bool stagnated = false;
-  // rtol is relative to the residual of the starting iterate (zero, or psi0)
-  MFP_TRY(residual64(g, nb, w, st, 0, opts->rtol));
-  cnt.applies += 1;
+  // rtol is relative to ||b||, the residual of the zero iterate, which the first call
+  // records; a warm start then replaces the iterate and the state is formed again
+  // from its residual (the threshold stays rtol ||b||).  With rtol_from_start the
+  // warm start's residual is the first one recorded, and the reference.
+  if (!opts->psi0 || !opts->rtol_from_start) {
+    MFP_TRY(residual64(g, nb, w, st, 0, opts->rtol));
+    cnt.applies += 1;
+  }
+  if (opts->psi0) {
+    const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+    k_warm_x<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, opts->psi0, w.x);
+    if (nb > 0) k_warm_xb<<<1, 64, 0, st>>>(g.nx, g.ny, nb, w.boxes, body, opts->psi0, w.st);
+    MFP_TRY_HIP(hipGetLastError());
+    MFP_TRY(residual64(g, nb, w, st, 0, opts->rtol));
+    cnt.applies += 1;
+  }
+  long long inner = 0;
   if (opts->precision == MFP_FP64) {
     done = solve64(g, nb, w, *opts, st, &cnt);
     if (done < 0) return done;
@@ -1438,6 +1531,7 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
     double rr = 0, rr0 = 0;
     done = solve_mixed(g, nb, w, *opts, st, &cnt, &total_iters, &outer, &stagnated);
     if (done < 0) return done;
+    inner = total_iters;
     if (opts->precision == MFP_FP32_IR && done == 0) {
       // FP64 CG from the current iterate to the original target
       stagnated = true;
@@ -1459,9 +1553,19 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
   (void)hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
+  if (opts->estimate_kappa && cnt.iters > 2) {
+    // launches 1..J hold their scalars at [2j], [2j+1] (those below HIST_CAP)
+    const long long J = cnt.iters < HIST_CAP - 1 ? cnt.iters : HIST_CAP - 1;
+    std::vector<double> hist(2 * (size_t)(J + 1));
+    MFP_TRY_HIP(hipMemcpyAsync(hist.data(), w.hist, sizeof(double) * hist.size(),
+                               hipMemcpyDeviceToHost, st));
+    MFP_TRY_HIP(hipStreamSynchronize(st));
+    lanczos_kappa(hist, J, info);
+  }
   info->done = done;
   info->stagnated = stagnated;
   info->iters = total_iters;
+  info->inner = inner;
   info->outer = outer;
   info->applies = cnt.applies;
   info->apply_ms = cnt.tcnt ? cnt.tsum / cnt.tcnt : 0.0;
@@ -1509,6 +1613,11 @@ static int fill_stats(const SolveWs& w, const SolveInfo& info, int nb, const Dev
   stats_h->apply_samples = info.apply_samples;
   stats_h->n_tiles = w.L.ntasks();
   stats_h->n_plain_tiles = nplain;
+  stats_h->inner_iters = info.inner;
+  stats_h->kappa_est = info.kappa;
+  stats_h->ritz_min = info.ritz_min;
+  stats_h->ritz_max = info.ritz_max;
+  stats_h->kappa_steps = info.kappa_steps;
   return MFP_OK;
 }
 
@@ -1666,8 +1775,8 @@ extern "C" int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, i
                             const mfp_flow* flow, const mfp_solver_opts* opts, const double* psi,
                             const double* psi_b_h, const double* dL_dpsib_h, double dL_dcopfi,
                             int32_t pair_lo, int32_t pair_hi, double* dL_ddisp,
-                            double* dL_dcentre_h, mfp_stats* stats_h, void* ws, size_t ws_bytes,
-                            void* stream_) {
+                            double* dL_dcentre_h, double* dL_dU_h, mfp_stats* stats_h, void* ws,
+                            size_t ws_bytes, void* stream_) {
   clear_error();
   MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, kind, body, flow, opts, ws));
   if (!psi || !dL_ddisp || (nbody > 0 && (!psi_b_h || !dL_dcentre_h))) {
@@ -1714,8 +1823,21 @@ extern "C" int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, i
     dL_dcentre_h[2 * pair_hi + 1] += -dL_dcopfi * J / dy;
     dL_dcentre_h[2 * pair_lo + 1] += dL_dcopfi * J / dy;
   }
+  // free stream: y = U y1, so with A lambda = dL/dy, lambda^T db/dU = (dL/dy)^T y / U;
+  // the explicit U in CoPFI's denominator cancels the pair's part of it
+  if (dL_dU_h) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += rhs[b] * psi_b_h[b];
+    if (use_pair)
+      s -= dL_dcopfi * (psi_b_h[pair_hi] - psi_b_h[pair_lo]) /
+           (flow->U * (circles_h[pair_hi].cy - circles_h[pair_lo].cy));
+    *dL_dU_h = flow->U != 0.0 ? s / flow->U : 0.0;
+  }
+  // the adjoint starts from zero whatever the caller's options say
+  mfp_solver_opts ao = *opts;
+  ao.psi0 = nullptr;
   SolveInfo info;
-  MFP_TRY(solve_core(g, circles_h, nb, disp, body, flow, opts, rhs, true, w, st, &info));
+  MFP_TRY(solve_core(g, circles_h, nb, disp, body, flow, &ao, rhs, true, w, st, &info));
   // lambda as a nodal vector (Dirichlet nodes 0, body nodes lambda_b)
   k_output<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, w.x, w.g, w.st, lam, -1,
                                                -1, 1.0, 0.0, 1.0);

@@ -110,6 +110,8 @@ struct StepArgs {
   int kdev;
   int G;
   int* host_done;                // single solve: stop code also written here (pinned host)
+  double* hist;                  // single solve, may be NULL: hist[2j] = alpha_{j-1} and
+  long long hist_cap;            // hist[2j+1] = beta_j as launch j forms them (j < hist_cap)
   T* rs[2];
   T* ps[2];
   T* qs[2];
@@ -381,6 +383,12 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       if (!code) st->pb[cur][lane] = pbj;
     }
     if (lane == 0) {
+      // the CG scalars, for the Lanczos condition estimate (a restart launch has no
+      // step length, a stopping one forms no direction)
+      if (a.hist && j < a.hist_cap) {
+        if (!start) a.hist[2 * j] = alpha;
+        if (!code) a.hist[2 * j + 1] = beta;
+      }
       st->alpha = alpha;
       st->alpha_hist[cur] = alpha;
       st->rr[cur] = rr_j;

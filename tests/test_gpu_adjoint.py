@@ -3,9 +3,12 @@ oracle: the shape term against the oracle's per-element complex-step derivative,
 the mesh back-propagation against the oracle's transposed sweep matrix, and the
 full CoPFI gradient against complex step through the whole oracle pipeline (the
 frozen-topology derivative) within 1e-7 of max|grad| (the stated bar is 1e-6
-relative to finite differences).  At the full 2048x1024 size: the mirror-symmetry
-identities and central finite differences of warm-started GPU solves.
+relative to finite differences).  At the full 2048x1024 size: the oracle's
+discrete-adjoint gradient stored in tests/golden, the mirror-symmetry identities
+and central finite differences of warm-started GPU solves.
 """
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -16,6 +19,8 @@ from oracle import grad as G
 from gpu_util import DEV, need_gpu, say
 
 pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 SMALL = W.five_cylinders(96, 48, 0.5, extent=(-6, 6, -3, 3))
 SMALL_GAP = W.five_cylinders(130, 67, 0.1, extent=(-6.5, 6.5, -3.35, 3.35))
@@ -39,7 +44,7 @@ def gpu_forward(mfp, c, rtol=1e-13):
 def test_shape_term_matches_oracle(mfp, c):
     say(f"[adjoint shape] {c.name}")
     disp, kind, body, res = gpu_forward(mfp, c)
-    gX, explicit, stats, status = mfp.psi_grad(c.grid, c.circles, disp, kind, body, c.flow,
+    gX, explicit, stats, status, _ = mfp.psi_grad(c.grid, c.circles, disp, kind, body, c.flow,
                                                res.psi, res.psi_b, dL_dcopfi=1.0,
                                                pair=c.pair, rtol=1e-13)
     assert status == 0
@@ -94,11 +99,29 @@ def test_fp32_refined_adjoint(mfp):
                                atol=1e-7 * np.abs(gc).max())
 
 
-def test_full_size_symmetry_and_fd(mfp):
-    """2048x1024, delta = 0.15: dJ/dy of the axis bodies vanish, the pair's y
-    derivatives are opposite, x derivatives of the pair equal; dJ/d(delta) equals a
-    central difference (step 1e-5) of GPU solves warm-started from the base solution
-    with an unchanged node classification."""
+def read_gradient_golden():
+    """tests/golden/five_cyl_2048x1024_gradient.txt (oracle discrete adjoint, written
+    by make_five_cyl_2048_gradient.py): ({key: values}, grad (5, 2))."""
+    hdr, rows = {}, []
+    with open(os.path.join(HERE, "golden", "five_cyl_2048x1024_gradient.txt")) as f:
+        for line in f:
+            if line.startswith("#"):
+                parts = line[1:].split()
+                if parts and parts[0] in ("psi_b", "copfi", "dcopfi_ddelta"):
+                    hdr[parts[0]] = np.array([float(v) for v in parts[1:]])
+                continue
+            b, gx, gy = line.split()
+            rows.append((float(gx), float(gy)))
+    return hdr, np.array(rows)
+
+
+def test_full_size_gradient_matches_oracle_and_fd(mfp):
+    """2048x1024, delta = 0.15: all 10 centre derivatives and dJ/d(delta) within
+    1e-6 max|grad J| of the oracle's discrete-adjoint gradient of the same workload
+    (direct sparse-LU solves, tests/golden); dJ/dy of the axis bodies vanish, the
+    pair's y derivatives are opposite, x derivatives of the pair equal; dJ/d(delta)
+    equals a central difference (step 1e-5) of GPU correction solves warm-started
+    from the base solution with an unchanged node classification."""
     c = W.five_cyl_2048_adjoint()
     say("[adjoint full size] forward")
     delta = torch.tensor(c.delta, dtype=torch.float64, requires_grad=True)
@@ -118,6 +141,13 @@ def test_full_size_symmetry_and_fd(mfp):
     assert g[3, 0] == pytest.approx(g[4, 0], rel=1e-6, abs=1e-9 * scale)
     gd = float(delta.grad)
     assert gd == pytest.approx(g[4, 1] - g[3, 1], rel=1e-12)
+    hdr, gref = read_gradient_golden()
+    bar = 1e-6 * np.abs(gref).max()
+    say(f"  vs oracle: centres max {np.abs(g - gref).max():.3e}, delta "
+        f"{abs(gd - hdr['dcopfi_ddelta'][0]):.3e} (bar {bar:.2e})")
+    np.testing.assert_allclose(g, gref, rtol=0, atol=bar)
+    assert abs(gd - hdr["dcopfi_ddelta"][0]) <= bar
+    assert float(J) == pytest.approx(hdr["copfi"][0], abs=1e-10)
     # finite differences of delta with warm-started solves
     say("[adjoint full size] finite differences")
     disp0, kind0, body0 = mfp.mesh_conform(c.grid, c.circles, 200, device=DEV)
@@ -133,7 +163,7 @@ def test_full_size_symmetry_and_fd(mfp):
         disp, kind, body = mfp.mesh_conform(c.grid, cc, 200, device=DEV)
         assert torch.equal(kind, kind0) and torch.equal(body, body0)
         r = mfp.psi_solve(c.grid, cc, disp, kind, body, c.flow, rtol=1e-10, pair=c.pair,
-                          psi0=res0.psi)
+                          psi0=res0.psi, rtol_from_start=True)
         vals.append(r.copfi)
     fd = (vals[0] - vals[1]) / (2 * h)
     assert fd == pytest.approx(gd, rel=1e-6)

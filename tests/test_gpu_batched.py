@@ -61,9 +61,10 @@ def test_batched_matches_single_and_oracle(mfp, precision):
         ref = O.solve(mesh, c.flow)
         psi = res.psi[i].cpu().numpy()
         err = np.linalg.norm(psi - ref.psi) / np.linalg.norm(ref.psi)
+        dmax = np.abs(psi - ref.psi).max() / np.abs(ref.psi).max()
         say(f"  system {i} {c.name}: iters {s['iters']} outer {s['outer_iters']} "
-            f"relres {s['relres_true']:.2e} err {err:.2e}")
-        assert err <= 1e-9, (i, err)
+            f"relres {s['relres_true']:.2e} err {err:.2e} node max {dmax:.2e}")
+        assert err <= 1e-9 and dmax <= 1e-9, (i, err, dmax)
 
 
 def test_batched_sweep_sample_full_sizes(mfp):

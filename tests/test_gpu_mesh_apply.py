@@ -73,7 +73,7 @@ def test_mesh_nsweeps_zero_and_odd(mfp):
         assert np.array_equal(disp.cpu().numpy(), ref.disp.reshape(-1)), ns
 
 
-def test_tangled_and_geometry_errors(mfp):
+def test_overlapping_circles_rejected(mfp):
     g = W.Grid(64, 64, -8, 8, -8, 8)
     with pytest.raises(mfp.MfpError) as e:
         mfp.mesh_conform(g, [(0, 0, 1.0), (1.5, 0, 1.0)], 200, device=DEV)

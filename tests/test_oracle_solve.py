@@ -184,6 +184,28 @@ def test_surface_velocity_converges_to_formula_on_exact_field():
     assert out[1] < out[0] / 4
 
 
+def test_surface_velocity_magnitude_against_analytic_cylinder():
+    """u_t's magnitude against the analytic surface speed of the isolated
+    cylinder, u_t = 2 U sin(theta) (section "Validation" compares with it;
+    section "Velocity Field and Surface Tangential Velocity" defines u_t).
+    The exact stream function on the box sides removes the truncation of the
+    far field, so what remains is discretisation error: the least-squares scale
+    of u_t against 2 U sin(theta) tends to 1 and the rms difference falls under
+    refinement.  A wrong d_nc or psi_c definition (a factor, a wrong centroid)
+    fails this even though it would pass the same-formula comparison above."""
+    scale, rms = [], []
+    for n in (256, 512):
+        _, sol, mesh = _cyl_error(n)
+        th, ut, _ = O.surface_samples(mesh, sol.psi, sol.psi_b)
+        ref = 2.0 * np.sin(th)
+        scale.append(float(ut @ ref) / float(ref @ ref))
+        rms.append(float(np.sqrt(np.mean((ut - ref) ** 2))))
+    assert abs(scale[1] - 1.0) < 0.02
+    assert abs(scale[1] - 1.0) < abs(scale[0] - 1.0)
+    assert rms[1] < 0.5 * rms[0]
+    assert rms[1] < 0.1
+
+
 def test_table1_internal_arithmetic():
     """CoPFI = (psi5 - psi4)/(U (y5 - y4)) reproduces the printed Q54 / delta in
     the paper's units (U = 2 m/s, domain height 0.5 m, centre distance

@@ -98,6 +98,19 @@ def five_cylinders(nx: int, ny: int, delta: float,
                 pair=(3, 4), delta=delta)
 
 
+def five_cylinders_asymmetric(nx: int, ny: int, extent=(-20.0, 20.0, -10.0, 10.0)) -> Case:
+    """The five-cylinder layout moved off every symmetry: the streamwise cylinders
+    off the axis, the transverse pair shifted apart in x and in y (D = 1).  Used
+    where the right-hand side must have weight on every eigenvector of the operator
+    (condition estimates)."""
+    circles = [(-3.0, 0.2, 0.5), (0.0, -0.15, 0.5), (3.0, 0.3, 0.5), (0.35, -1.3, 0.5),
+               (-0.3, 1.4, 0.5)]
+    g = Grid(nx, ny, *extent)
+    return Case(f"five_asym{nx}x{ny}", g, circles,
+                Flow(1.0, (BC_DIRICHLET_UY, BC_NATURAL, BC_DIRICHLET_UY, BC_DIRICHLET_UY)),
+                pair=(3, 4))
+
+
 def potential_flow(case: Case, exact_bc: bool = False) -> Case:
     """The same geometry with the boundary data of the velocity-potential problem:
     phi = U x on the inlet and outlet, natural (no flow through) on the walls;
