@@ -200,6 +200,27 @@ int mfp_element_apply(const mfp_grid* grid, const double* disp, const int8_t* bo
                       int32_t precision, const void* p, void* q, int32_t repeat,
                       double* apply_ms_h, void* ws, size_t ws_bytes, void* stream);
 
+/* Scratch of mfp_element_apply_noalloc: one file-scope device array per GPU. */
+#define MFP_NOALLOC_SCRATCH_BYTES (32u * 1024u * 1024u)
+
+/* mfp_element_apply without allocation, for callers that cannot allocate device or
+ * pinned memory: code being captured into a HIP graph, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same product q = K p (same kernels, same result bit for bit)
+ * with no workspace argument, no timing and no repeat: its scratch is a file-scope
+ * device array of MFP_NOALLOC_SCRATCH_BYTES (32 MiB) that each GPU the library runs on
+ * holds until the process ends; its address is looked up once per device.  Tags,
+ * displacements, the padded input and output and the task tables take about 33 bytes
+ * per padded node (FP64 and FP32), so grids up to about 1e6 nodes fit (1300 x 650
+ * cells do, 1390 x 695 do not); larger grids return MFP_E_WORKSPACE before any device
+ * work.  Calls no hipMalloc, hipFree, event or other
+ * allocating routine, clears what must start at zero with kernels (no memset), and does
+ * not synchronise: the work is enqueued on `stream` and q is valid once it completes.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.
+ * Arguments as for mfp_element_apply. */
+int mfp_element_apply_noalloc(const mfp_grid* grid, const double* disp, const int8_t* body,
+                              int32_t precision, const void* p, void* q, void* stream);
+
 /* Constrained stream-function solve on a conformed mesh.
  * Unknowns: free nodes (interior and natural-boundary nodes) plus one psi_b per body
  * (all of a body's nodes tied to it); Dirichlet sides prescribed by `flow`.  Solves

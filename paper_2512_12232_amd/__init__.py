@@ -8,6 +8,7 @@ and CoPFI; the velocity potential phi on the same mesh (the flow net).  All arit
 from .binding import (MFP_OK, MFP_W_NOCONV, MFP_W_STAGNATION, MFP_E_ARG, MFP_E_HIP,
                       MFP_E_GEOMETRY, MFP_E_TANGLED, MFP_E_BREAKDOWN, MFP_E_WORKSPACE,
                       MfpError, check_geometry, contour, cubic_fit, element_apply,
+                      element_apply_noalloc,
                       last_error, load,
                       mesh_conform, mesh_conform_grad, phi_solve, psi_grad, psi_solve,
                       psi_solve_batched, solve_workspace_size, EXPORTS)
@@ -15,7 +16,8 @@ from .autograd import CoPFIFunction, copfi
 
 __all__ = ["MFP_OK", "MFP_W_NOCONV", "MFP_W_STAGNATION", "MFP_E_ARG", "MFP_E_HIP",
            "MFP_E_GEOMETRY", "MFP_E_TANGLED", "MFP_E_BREAKDOWN", "MFP_E_WORKSPACE",
-           "MfpError", "check_geometry", "contour", "cubic_fit", "element_apply", "last_error", "load",
+           "MfpError", "check_geometry", "contour", "cubic_fit", "element_apply",
+           "element_apply_noalloc", "last_error", "load",
            "mesh_conform", "mesh_conform_grad", "phi_solve", "psi_grad", "psi_solve",
            "psi_solve_batched",
            "solve_workspace_size", "EXPORTS", "CoPFIFunction", "copfi"]

@@ -33,6 +33,7 @@ EXPORTS = [
     "mfp_grad_workspace_size", "mfp_psi_grad", "mfp_conform_grad_workspace_size",
     "mfp_mesh_conform_grad", "mfp_batched_workspace_size", "mfp_psi_solve_batched",
     "mfp_phi_solve", "mfp_cubic_fit", "mfp_contour_workspace_size", "mfp_contour",
+    "mfp_element_apply_noalloc",
 ]
 
 
@@ -98,6 +99,8 @@ def load(path: str = LIB_PATH):
     lib.mfp_element_apply.argtypes = [POINTER(MfpGrid), c_void_p, c_void_p, c_int32, c_void_p,
                                       c_void_p, c_int32, POINTER(c_double), c_void_p, c_size_t,
                                       c_void_p]
+    lib.mfp_element_apply_noalloc.argtypes = [POINTER(MfpGrid), c_void_p, c_void_p, c_int32,
+                                              c_void_p, c_void_p, c_void_p]
     lib.mfp_psi_solve.argtypes = [
         POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_void_p, c_void_p, c_void_p,
         POINTER(MfpFlow), POINTER(MfpSolverOpts), c_int32, c_int32, c_void_p,
@@ -215,6 +218,22 @@ def element_apply(grid, disp: torch.Tensor, body: torch.Tensor, p: torch.Tensor,
     _check(lib.mfp_element_apply(byref(g), _ptr(disp), _ptr(body), prec, _ptr(p), _ptr(q),
                                  int(repeat), byref(ms), _ptr(ws), ws.numel(), _stream()))
     return q, ms.value
+
+
+def element_apply_noalloc(grid, disp: torch.Tensor, body: torch.Tensor, p: torch.Tensor,
+                          precision: str = "fp64", q: Optional[torch.Tensor] = None):
+    """q = K p through mfp_element_apply_noalloc (no workspace: the library's static
+    scratch).  q: optional preallocated output of p's dtype and size."""
+    lib = load()
+    g = make_grid(grid)
+    prec = _PREC[precision]
+    dt = torch.float64 if prec == FP64 else torch.float32
+    p = p.to(dt).contiguous()
+    if q is None:
+        q = torch.empty_like(p)
+    _check(lib.mfp_element_apply_noalloc(byref(g), _ptr(disp), _ptr(body), prec, _ptr(p),
+                                         _ptr(q), _stream()))
+    return q
 
 
 @dataclass

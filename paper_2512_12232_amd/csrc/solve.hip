@@ -17,6 +17,7 @@
 #include <cmath>
 #include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 #include <vector>
 
@@ -1851,6 +1852,183 @@ extern "C" int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, i
   MFP_TRY_HIP(hipStreamSynchronize(st));
   MFP_TRY(fill_stats(w, info, nb, hsd, st, stats_h));
   return finish_status(info);
+}
+
+// ---------------------------------------------------------------------------------
+// Element apply without allocation (mfp_element_apply_noalloc)
+// ---------------------------------------------------------------------------------
+namespace mfp {
+
+// The entry point's scratch: a file-scope device array, one copy per GPU, kept until
+// the process ends.  Host code never passes its name to a kernel (in host code it is
+// a stand-in, not a device address): the address comes from hipGetSymbolAddress, once
+// per device, with that device current.
+constexpr size_t NOALLOC_BYTES = (size_t)MFP_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+// Address of the current device's scratch (resolved on the first call on a device).
+static int scratch_address(void** out) {
+  int dev = 0;
+  MFP_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+    set_error("device %d beyond the %d devices the scratch table covers", dev,
+              NOALLOC_MAX_DEVICES);
+    return MFP_E_ARG;
+  }
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      set_error("hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+      return MFP_E_HIP;
+    }
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return MFP_OK;
+}
+
+template <typename T>
+__global__ void k_zero(long long n, T* __restrict__ v) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    v[e] = (T)0;
+}
+
+// What the element apply needs and nothing else: tags, displacements / hx (FP64,
+// and FP32 copies for an FP32 apply), the padded input and output, the task metadata
+// and the work list (no body unknowns: the product is the full nodal K p).
+static size_t noalloc_layout(const mfp_grid* g, int precision, void* base, SolveWs* out) {
+  Bump bp(base);
+  SolveWs w{};
+  w.L = make_layout(g->nx, g->ny);
+  const size_t n = (size_t)w.L.n;
+  const int nt = w.L.ntasks();
+  const size_t esz = precision == MFP_FP64 ? sizeof(double) : sizeof(float);
+  w.tag = bp.take<int8_t>(n);
+  w.dx = bp.take<double>(n);
+  w.dy = bp.take<double>(n);
+  if (precision != MFP_FP64) {
+    w.dxf = bp.take<float>(n);
+    w.dyf = bp.take<float>(n);
+  }
+  char* src = bp.take<char>(n * esz);
+  char* dst = bp.take<char>(n * esz);
+  w.tplain = bp.take<uint8_t>(nt);
+  w.tbody = bp.take<unsigned long long>(nt);
+  w.tslot = bp.take<int>(nt);
+  w.nslots = bp.take<int>(1);
+  w.segtab = bp.take<int4>((size_t)nt + 4096);
+  w.part = bp.take<double>(GMAX);
+  w.bstride = 64;
+  w.bpart = bp.take<double>(2 * w.bstride);
+  if (precision == MFP_FP64) {
+    w.p0 = reinterpret_cast<double*>(src);
+    w.q = reinterpret_cast<double*>(dst);
+  } else {
+    w.p0f = reinterpret_cast<float*>(src);
+    w.qf = reinterpret_cast<float*>(dst);
+  }
+  if (out) {
+    if (base) w.sp = seg_plan(w.L, single_target(w.L, precision));
+    *out = w;
+  }
+  return bp.off + 256;
+}
+
+}  // namespace mfp
+
+extern "C" int mfp_element_apply_noalloc(const mfp_grid* grid, const double* disp,
+                                         const int8_t* body, int32_t precision, const void* p,
+                                         void* q, void* stream_) {
+  clear_error();
+  MFP_TRY(check_grid(grid));
+  if (!disp || !body || !p || !q) {
+    set_error("NULL pointer");
+    return MFP_E_ARG;
+  }
+  if (precision != MFP_FP64 && precision != MFP_FP32) {
+    set_error("precision must be MFP_FP64 or MFP_FP32");
+    return MFP_E_ARG;
+  }
+  const size_t need = noalloc_layout(grid, precision, nullptr, nullptr);
+  if (need > NOALLOC_BYTES) {
+    set_error("grid %dx%d needs %zu bytes of scratch, above the %zu of the allocation-free "
+              "entry point: use mfp_element_apply with a workspace", grid->nx, grid->ny, need,
+              NOALLOC_BYTES);
+    return MFP_E_WORKSPACE;
+  }
+  const mfp_grid& g = *grid;
+  {
+    const Layout L = make_layout(g.nx, g.ny);
+    if (L.nstrip > SEG_MAX_STRIPS || L.nchunk > 0xffff) {
+      set_error("grid too large");
+      return MFP_E_ARG;
+    }
+  }
+  void* base = nullptr;
+  MFP_TRY(scratch_address(&base));
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  SolveWs w;
+  noalloc_layout(grid, precision, base, &w);
+  // tags and scaled displacements (k_setup writes every padded entry), task metadata
+  // and the work list
+  SetupArgs s{};
+  s.L = w.L;
+  s.nx = g.nx;
+  s.ny = g.ny;
+  s.x0 = g.x0;
+  s.y0 = g.y0;
+  s.hx = grid_hx(g);
+  s.hy = grid_hy(g);
+  s.inv_hx = 1.0 / s.hx;
+  for (int k = 0; k < 4; ++k) s.bc[k] = MFP_BC_NATURAL;
+  s.disp = disp;
+  s.body = body;
+  s.tag = w.tag;
+  s.dx = w.dx;
+  s.dy = w.dy;
+  s.dxf = w.dxf;
+  s.dyf = w.dyf;
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  // the padded input is zero off the nodes (halo rows and padding columns): cleared by a
+  // kernel on every call (the array keeps the last call's contents)
+  if (precision == MFP_FP64) {
+    k_zero<double><<<grid_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, w.p0);
+    k_to_padded<double><<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, (const double*)p, w.p0);
+  } else {
+    k_zero<float><<<grid_blocks(w.L.n), BLOCK, 0, st>>>(w.L.n, w.p0f);
+    k_to_padded<float><<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, (const float*)p, w.p0f);
+  }
+  k_setup<<<grid_blocks(w.L.n), BLOCK, 0, st>>>(s);
+  k_task_meta<<<(w.L.ntasks() + WAVES - 1) / WAVES, BLOCK, 0, st>>>(w.L, w.tag, w.dx, w.dy,
+                                                                     w.tplain, w.tbody);
+  k_assign_slots<<<1, BLOCK, 0, st>>>(w.L.ntasks(), w.tbody, w.tslot, w.nslots);
+  k_seg_plan<<<1, 1024, 0, st>>>(w.L, w.tplain, w.sp.target, WAVES * w.sp.G, w.sp.tabsize,
+                                 w.segtab);
+  MFP_TRY_HIP(hipGetLastError());
+  if (precision == MFP_FP64) {
+    ApplyArgs<double> a = make_apply_args<double>(w, g, 0, w.dx, w.dy);
+    a.src = w.p0;
+    a.q = w.q;
+    a.write_all = 1;
+    launch_apply<double>(w.L.hc, w.sp.G, st, a);
+    k_from_padded<double><<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, w.q, (double*)q);
+  } else {
+    ApplyArgs<float> a = make_apply_args<float>(w, g, 0, w.dxf, w.dyf);
+    a.src = w.p0f;
+    a.q = w.qf;
+    a.write_all = 1;
+    launch_apply<float>(w.L.hc, w.sp.G, st, a);
+    k_from_padded<float><<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, w.qf, (float*)q);
+  }
+  MFP_TRY_HIP(hipGetLastError());
+  return MFP_OK;
 }
 
 #include "batch.h"
