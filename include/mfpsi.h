@@ -126,6 +126,20 @@ typedef struct {
                              correction solve: from a nearby solution, e.g. one step of a
                              parameter sweep or a finite difference, this reaches an
                              absolute accuracy below what rtol ||b|| allows)            */
+  /* Schedule of the iteration kernel; 0 = automatic: the entry for this device, grid
+   * and precision in the tuning cache named by the environment variable
+   * MFP_TUNE_CACHE (written by the package's tuner), else built-in rules.  The
+   * result does not depend on the schedule beyond rounding.                          */
+  int32_t task_rows;      /* node rows per task: 4, 5 or 8                              */
+  int32_t element_mode;   /* 1: element geometry on the fly from the displacements every
+                             iteration; 2: each distorted cell's element matrix evaluated
+                             once per solve (same 2x2 Gauss rule) and its six
+                             off-diagonal entries read by the iteration (more bytes, far
+                             fewer operations)                                          */
+  int32_t store_mode;     /* 1: cached vector stores; 2: streaming (non-temporal) stores */
+  int32_t launch_blocks;  /* work-groups per iteration launch (multiple of 8, <= 1024)  */
+  int32_t batch_tasks_per_wave; /* mfp_psi_solve_batched: tasks per wavefront of the
+                             batched iteration (1..64; its launch holds many systems)   */
 } mfp_solver_opts;
 
 typedef struct {
@@ -185,8 +199,14 @@ int mfp_mesh_conform(const mfp_grid* grid, const mfp_circle* circles_h, int32_t 
                      int32_t nsweeps, double* disp, int8_t* kind, int8_t* body,
                      void* ws, size_t ws_bytes, void* stream);
 
-/* Workspace bytes for mfp_psi_solve / mfp_element_apply with this precision. */
+/* Workspace bytes for mfp_psi_solve / mfp_phi_solve / mfp_element_apply with this
+ * precision and the automatic schedule (see mfp_solver_opts). */
 size_t mfp_solve_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t precision);
+
+/* Workspace bytes for a solve with these options (precision and any explicit schedule
+ * fields); 0 for invalid options. */
+size_t mfp_solve_workspace_size_opts(const mfp_grid* grid, int32_t nbody,
+                                     const mfp_solver_opts* opts);
 
 /* Matrix-free element product q = K p (Algorithm 1's element loop, section "Weak
  * formulation": K_e = int (grad N)^T (grad N) dOmega, bilinear quads, 2x2 Gauss),
@@ -361,14 +381,18 @@ typedef struct {
   double* psi;
 } mfp_variant;
 
-/* Workspace bytes for mfp_psi_solve_batched. */
+/* Workspace bytes for mfp_psi_solve_batched (automatic schedule), and for these options
+ * (precision, element_mode, batch_tasks_per_wave; 0 for invalid options). */
 size_t mfp_batched_workspace_size(int32_t nvar, const mfp_variant* vars_h, int32_t nbody,
                                   int32_t precision);
+size_t mfp_batched_workspace_size_opts(int32_t nvar, const mfp_variant* vars_h, int32_t nbody,
+                                       const mfp_solver_opts* opts);
 
 /* Many independent solves of the same body layout on different meshes (the repeated
  * evaluations and design sweeps the paper's Practical Applications and Introduction
  * name), advanced together: every kernel launch covers all systems (one CG iteration
- * each), a fixed block of `iters_per_launch` iterations (0 -> 64; rounded up to even) is
+ * each), a fixed block of `iters_per_launch` iterations (0 -> the tuning cache's value,
+ * else 64; rounded up to even) is
  * captured once as a hipGraph and replayed until every system has stopped.  circles_h
  * holds nvar * nbody circles (system-major), psi_b_h receives nvar * nbody values,
  * copfi_h (may be NULL) nvar values, stats_h (may be NULL) nvar entries.
@@ -376,6 +400,8 @@ size_t mfp_batched_workspace_size(int32_t nvar, const mfp_variant* vars_h, int32
  * (FP32 CG; after every block, at most 256 iterations, the FP32 correction is folded
  * into the FP64 iterate, the FP64 residual replaces the FP32 one and the iteration
  * restarts from it with its last direction kept; systems stop on that FP64 residual).
+ * Schedule: 4-row tasks; opts->element_mode and opts->batch_tasks_per_wave (or the
+ * tuning cache's batched entry) choose the element mode and the tasks per wavefront.
  * Returns the worst status over the systems. */
 int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h, const mfp_circle* circles_h,
                           int32_t nbody, const mfp_flow* flow, const mfp_solver_opts* opts,

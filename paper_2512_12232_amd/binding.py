@@ -33,7 +33,8 @@ EXPORTS = [
     "mfp_grad_workspace_size", "mfp_psi_grad", "mfp_conform_grad_workspace_size",
     "mfp_mesh_conform_grad", "mfp_batched_workspace_size", "mfp_psi_solve_batched",
     "mfp_phi_solve", "mfp_cubic_fit", "mfp_contour_workspace_size", "mfp_contour",
-    "mfp_element_apply_noalloc",
+    "mfp_element_apply_noalloc", "mfp_solve_workspace_size_opts",
+    "mfp_batched_workspace_size_opts",
 ]
 
 
@@ -54,7 +55,22 @@ class MfpSolverOpts(Structure):
     _fields_ = [("precision", c_int32), ("rtol", c_double), ("kmax", c_int64),
                 ("check_every", c_int32), ("inner_rtol", c_double), ("max_outer", c_int32),
                 ("psi0", c_void_p), ("profile_every", c_int32), ("estimate_kappa", c_int32),
-                ("rtol_from_start", c_int32)]
+                ("rtol_from_start", c_int32), ("task_rows", c_int32), ("element_mode", c_int32),
+                ("store_mode", c_int32), ("launch_blocks", c_int32),
+                ("batch_tasks_per_wave", c_int32)]
+
+
+SCHEDULE_KEYS = ("task_rows", "element_mode", "store_mode", "launch_blocks",
+                 "batch_tasks_per_wave")
+
+
+def _set_schedule(o: "MfpSolverOpts", schedule: Optional[dict]) -> "MfpSolverOpts":
+    """Explicit schedule fields of the iteration kernel (0 or missing = automatic)."""
+    for k, v in (schedule or {}).items():
+        if k not in SCHEDULE_KEYS:
+            raise ValueError(f"unknown schedule field {k!r}")
+        setattr(o, k, int(v))
+    return o
 
 
 class MfpStats(Structure):
@@ -96,6 +112,9 @@ def load(path: str = LIB_PATH):
                                      c_void_p, c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     lib.mfp_solve_workspace_size.restype = c_size_t
     lib.mfp_solve_workspace_size.argtypes = [POINTER(MfpGrid), c_int32, c_int32]
+    lib.mfp_solve_workspace_size_opts.restype = c_size_t
+    lib.mfp_solve_workspace_size_opts.argtypes = [POINTER(MfpGrid), c_int32,
+                                                  POINTER(MfpSolverOpts)]
     lib.mfp_element_apply.argtypes = [POINTER(MfpGrid), c_void_p, c_void_p, c_int32, c_void_p,
                                       c_void_p, c_int32, POINTER(c_double), c_void_p, c_size_t,
                                       c_void_p]
@@ -131,6 +150,9 @@ def load(path: str = LIB_PATH):
         POINTER(c_double), POINTER(c_double), c_void_p, c_size_t, c_void_p]
     lib.mfp_batched_workspace_size.restype = c_size_t
     lib.mfp_batched_workspace_size.argtypes = [c_int32, POINTER(MfpVariant), c_int32, c_int32]
+    lib.mfp_batched_workspace_size_opts.restype = c_size_t
+    lib.mfp_batched_workspace_size_opts.argtypes = [c_int32, POINTER(MfpVariant), c_int32,
+                                                    POINTER(MfpSolverOpts)]
     lib.mfp_psi_solve_batched.argtypes = [
         c_int32, POINTER(MfpVariant), POINTER(MfpCircle), c_int32, POINTER(MfpFlow),
         POINTER(MfpSolverOpts), c_int32, c_int32, c_int32, POINTER(c_double),
@@ -255,7 +277,7 @@ def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
               sample_cap=None, ws: Optional[torch.Tensor] = None,
               allow_warn: bool = True, profile_every: int = 0,
               psi0: Optional[torch.Tensor] = None, estimate_kappa: bool = False,
-              rtol_from_start: bool = False) -> SolveResult:
+              rtol_from_start: bool = False, schedule: Optional[dict] = None) -> SolveResult:
     lib = load()
     g = make_grid(grid)
     c = make_circles(circles)
@@ -265,6 +287,7 @@ def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
     o = MfpSolverOpts(prec, float(rtol), int(kmax), int(check_every), float(inner_rtol),
                       int(max_outer), _ptr(psi0) if psi0 is not None else None,
                       int(profile_every), int(bool(estimate_kappa)), int(bool(rtol_from_start)))
+    _set_schedule(o, schedule)
     n = (g.nx + 1) * (g.ny + 1)
     dev = disp.device
     psi = torch.empty(n, dtype=torch.float64, device=dev)
@@ -278,7 +301,7 @@ def psi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
     ns = c_int32(0)
     st = MfpStats()
     if ws is None:
-        ws = workspace(lib.mfp_solve_workspace_size(byref(g), nb, prec), dev)
+        ws = workspace(lib.mfp_solve_workspace_size_opts(byref(g), nb, byref(o)), dev)
     status = _check(lib.mfp_psi_solve(
         byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o),
         int(pair[0]), int(pair[1]), _ptr(psi), psib, byref(Q), byref(cop), _ptr(samples),
@@ -302,7 +325,8 @@ def phi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
               kmax=10 ** 7, check_every=16, inner_rtol=0.1, max_outer=1000,
               ws: Optional[torch.Tensor] = None, allow_warn: bool = True,
               profile_every: int = 0, phi0: Optional[torch.Tensor] = None,
-              estimate_kappa: bool = False, rtol_from_start: bool = False) -> PhiResult:
+              estimate_kappa: bool = False, rtol_from_start: bool = False,
+              schedule: Optional[dict] = None) -> PhiResult:
     """Velocity potential on the conformed mesh (mfp_phi_solve): ``flow`` gives the
     Dirichlet sides (e.g. phi = U x on inlet and outlet), bodies and the other sides
     are natural boundaries.  phi0: optional nodal warm start (device doubles; its
@@ -316,12 +340,13 @@ def phi_solve(grid, circles, disp, kind, body, flow, *, precision="fp64", rtol=1
     o = MfpSolverOpts(prec, float(rtol), int(kmax), int(check_every), float(inner_rtol),
                       int(max_outer), _ptr(phi0) if phi0 is not None else None,
                       int(profile_every), int(bool(estimate_kappa)), int(bool(rtol_from_start)))
+    _set_schedule(o, schedule)
     n = (g.nx + 1) * (g.ny + 1)
     dev = disp.device
     phi = torch.empty(n, dtype=torch.float64, device=dev)
     st = MfpStats()
     if ws is None:
-        ws = workspace(lib.mfp_solve_workspace_size(byref(g), nb, prec), dev)
+        ws = workspace(lib.mfp_solve_workspace_size_opts(byref(g), nb, byref(o)), dev)
     status = _check(lib.mfp_phi_solve(
         byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o), _ptr(phi),
         byref(st), _ptr(ws), ws.numel(), _stream()), allow_warn)
@@ -368,15 +393,17 @@ def solve_workspace_size(grid, nbody: int, precision: str = "fp64") -> int:
     return load().mfp_solve_workspace_size(byref(g), int(nbody), _PREC[precision])
 
 
-def _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa=False):
-    return MfpSolverOpts(_PREC[precision], float(rtol), int(kmax), int(check_every),
-                         float(inner_rtol), int(max_outer), None, 0, int(bool(estimate_kappa)), 0)
+def _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa=False,
+          schedule=None):
+    o = MfpSolverOpts(_PREC[precision], float(rtol), int(kmax), int(check_every),
+                      float(inner_rtol), int(max_outer), None, 0, int(bool(estimate_kappa)), 0)
+    return _set_schedule(o, schedule)
 
 
 def psi_grad(grid, circles, disp, kind, body, flow, psi, psi_b, *, dL_dpsib=None,
              dL_dcopfi=0.0, pair=(-1, -1), precision="fp64", rtol=1e-12, kmax=10 ** 7,
              check_every=16, inner_rtol=0.1, max_outer=1000, allow_warn=True,
-             estimate_kappa=False):
+             estimate_kappa=False, schedule=None):
     """Adjoint solve + shape derivative.  Returns (dL_ddisp device tensor [2*nodes],
     explicit dL/dcentre list of (dx, dy) per body, stats, status, dL/dU)."""
     lib = load()
@@ -384,7 +411,8 @@ def psi_grad(grid, circles, disp, kind, body, flow, psi, psi_b, *, dL_dpsib=None
     c = make_circles(circles)
     nb = len(circles)
     f = make_flow(flow)
-    o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa)
+    o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa,
+              schedule)
     n = (g.nx + 1) * (g.ny + 1)
     dev = disp.device
     out = torch.empty(2 * n, dtype=torch.float64, device=dev)
@@ -395,7 +423,10 @@ def psi_grad(grid, circles, disp, kind, body, flow, psi, psi_b, *, dL_dpsib=None
     dcen = (c_double * max(2 * nb, 1))()
     dU = c_double(0.0)
     st = MfpStats()
-    ws = workspace(lib.mfp_grad_workspace_size(byref(g), nb, _PREC[precision]), dev)
+    # an explicit schedule can need more solver workspace than the automatic one
+    extra = max(0, lib.mfp_solve_workspace_size_opts(byref(g), nb, byref(o)) -
+                lib.mfp_solve_workspace_size(byref(g), nb, _PREC[precision]))
+    ws = workspace(lib.mfp_grad_workspace_size(byref(g), nb, _PREC[precision]) + extra, dev)
     status = _check(lib.mfp_psi_grad(
         byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o), _ptr(psi),
         pb, dpb, float(dL_dcopfi), int(pair[0]), int(pair[1]), _ptr(out), dcen, byref(dU),
@@ -437,8 +468,9 @@ class BatchResult:
 
 
 def psi_solve_batched(systems, flow, *, precision="fp32_ir", rtol=1e-10, kmax=10 ** 7,
-                      iters_per_launch=64, pair=(-1, -1), want_psi=False,
-                      ws: Optional[torch.Tensor] = None) -> BatchResult:
+                      iters_per_launch=0, pair=(-1, -1), want_psi=False,
+                      ws: Optional[torch.Tensor] = None,
+                      schedule: Optional[dict] = None) -> BatchResult:
     """systems: list of (grid, circles, disp, kind, body); all with the same number of
     bodies.  One graph-replayed launch sequence for all of them."""
     lib = load()
@@ -459,12 +491,12 @@ def psi_solve_batched(systems, flow, *, precision="fp32_ir", rtol=1e-10, kmax=10
         for b, (cx, cy, r) in enumerate(circles):
             circ[i * nb + b] = MfpCircle(float(cx), float(cy), float(r))
     f = make_flow(flow)
-    o = _opts(precision, rtol, kmax, 64, 0.1, 1000)
+    o = _opts(precision, rtol, kmax, 64, 0.1, 1000, schedule=schedule)
     psib = (c_double * max(1, nvar * nb))()
     cop = (c_double * nvar)()
     st = (MfpStats * nvar)()
     if ws is None:
-        ws = workspace(lib.mfp_batched_workspace_size(nvar, vars_, nb, _PREC[precision]),
+        ws = workspace(lib.mfp_batched_workspace_size_opts(nvar, vars_, nb, byref(o)),
                        systems[0][2].device)
     status = _check(lib.mfp_psi_solve_batched(
         nvar, vars_, circ, nb, byref(f), byref(o), int(iters_per_launch), int(pair[0]),
@@ -474,10 +506,11 @@ def psi_solve_batched(systems, flow, *, precision="fp32_ir", rtol=1e-10, kmax=10
                        [cop[i] for i in range(nvar)], stats, status)
 
 
-def batched_workspace_size(systems, precision="fp32_ir") -> int:
+def batched_workspace_size(systems, precision="fp32_ir", schedule=None) -> int:
     lib = load()
     nvar = len(systems)
     vars_ = (MfpVariant * nvar)()
     for i, s in enumerate(systems):
         vars_[i] = MfpVariant(make_grid(s[0]), None, None, None, None)
-    return lib.mfp_batched_workspace_size(nvar, vars_, len(systems[0][1]), _PREC[precision])
+    o = _opts(precision, 1e-10, 1, 64, 0.1, 1000, schedule=schedule)
+    return lib.mfp_batched_workspace_size_opts(nvar, vars_, len(systems[0][1]), byref(o))

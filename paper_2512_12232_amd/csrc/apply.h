@@ -239,6 +239,136 @@ __device__ __forceinline__ void march_task(T ry, int lane, const int8_t (&tg)[HC
   }
 }
 
+// ---- element matrices evaluated once per solve ---------------------------------
+// A cell's K_e is symmetric with zero row sums (K_e applied to a constant is zero),
+// so its six off-diagonal entries determine it: (K_e p)_a = sum_{b != a} k_ab (p_b - p_a).
+// For tasks that evaluate geometry, the iteration can read those six numbers per cell
+// instead of rebuilding the Jacobians from the displacements every iteration: the
+// same 2x2 Gauss rule (cell_apply) evaluates them once per solve, in FP64.  A task's
+// slab holds cell rows 0..HC (the rows touching its node rows) x the six entries
+// (k01, k02, k03, k12, k13, k23) x 64 lanes, lane-contiguous; lane c holds cell
+// (c, row) between node columns c and c+1, lane 63 and cells with a halo node or
+// inside a body hold zeros (they contribute nothing).
+constexpr int KCOEF = 6;
+
+template <int HC>
+__host__ __device__ constexpr int kslab() { return (HC + 1) * KCOEF * 64; }
+
+// The six off-diagonal entries of one cell's K_e: its columns are K_e applied to the
+// unit vectors.
+__device__ __forceinline__ void cell_coefficients(double ry, double x0, double x1, double x2,
+                                                  double x3, double y0, double y1, double y2,
+                                                  double y3, double (&k)[KCOEF]) {
+  double c0, c1, c2, c3;
+  cell_apply<double>(ry, x0, x1, x2, x3, y0, y1, y2, y3, 0.0, 1.0, 0.0, 0.0, c0, c1, c2, c3);
+  k[0] = c0;  // k01
+  cell_apply<double>(ry, x0, x1, x2, x3, y0, y1, y2, y3, 0.0, 0.0, 1.0, 0.0, c0, c1, c2, c3);
+  k[1] = c0;  // k02
+  k[3] = c1;  // k12
+  cell_apply<double>(ry, x0, x1, x2, x3, y0, y1, y2, y3, 0.0, 0.0, 0.0, 1.0, c0, c1, c2, c3);
+  k[2] = c0;  // k03
+  k[4] = c1;  // k13
+  k[5] = c2;  // k23
+}
+
+// K v at rows 1..HC from the task's stored element entries kc[cell row][entry] (the
+// march of march_task with the cell product in difference form).
+template <typename T, int HC>
+__device__ __forceinline__ void march_task_stored(const T (&v)[HC + 2], const T (&kc)[HC + 1][KCOEF],
+                                                  T (&qr)[HC]) {
+  T p0 = v[0];
+  T p1 = lane_shl(p0);
+  T carry = (T)0;
+#pragma unroll
+  for (int sr = 0; sr <= HC; ++sr) {
+    const T p3 = v[sr + 1];
+    const T p2 = lane_shl(p3);
+    const T d01 = p1 - p0, d02 = p2 - p0, d03 = p3 - p0;
+    const T d12 = p2 - p1, d13 = p3 - p1, d23 = p3 - p2;
+    const T k01 = kc[sr][0], k02 = kc[sr][1], k03 = kc[sr][2];
+    const T k12 = kc[sr][3], k13 = kc[sr][4], k23 = kc[sr][5];
+    const T c0 = (k01 * d01 + k02 * d02) + k03 * d03;
+    const T c1 = (k12 * d12 + k13 * d13) - k01 * d01;
+    const T c2 = k23 * d23 - (k02 * d02 + k12 * d12);
+    const T c3 = -((k03 * d03 + k13 * d13) + k23 * d23);
+    const T acc = carry + c0 + lane_shr(c1);
+    carry = c3 + lane_shr(c2);
+    if (sr >= 1) qr[sr - 1] = acc;
+    p0 = p3;
+    p1 = p2;
+  }
+}
+
+// Element entries of every geometry task (tgeo[t] = its slab, -1 for constant-stencil
+// tasks): one wavefront per task, geometry from the FP64 displacements / hx.
+template <typename T, int HC>
+__global__ void __launch_bounds__(256) k_elem_coef(Layout L, double ry,
+                                                   const int8_t* __restrict__ tag,
+                                                   const double* __restrict__ dx,
+                                                   const double* __restrict__ dy,
+                                                   const int* __restrict__ tgeo,
+                                                   T* __restrict__ kcoef) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (t >= L.ntasks()) return;
+  const int s = tgeo[t];
+  if (s < 0) return;  // uniform over the wavefront
+  const int m = t % L.nstrip, kc = t / L.nstrip;
+  const long long base =
+      (long long)(kc * HC) * L.P + (long long)m * 64 + lane + halo_shift(lane, m, L.nstrip);
+  int8_t g0 = tag[base];
+  double x0 = dx[base], y0 = dy[base];
+  int8_t g1 = (int8_t)lane_shl((int)g0);
+  double x1 = lane_shl(x0), y1 = lane_shl(y0);
+  T* out = kcoef + (size_t)s * kslab<HC>();
+  for (int sr = 0; sr <= HC; ++sr) {
+    const long long gi = base + (long long)(sr + 1) * L.P;
+    const int8_t g3 = tag[gi];
+    const double x3 = dx[gi], y3 = dy[gi];
+    const int8_t g2 = (int8_t)lane_shl((int)g3);
+    const double x2 = lane_shl(x3), y2 = lane_shl(y3);
+    const bool halo =
+        (g0 == TAG_HALO) | (g1 == TAG_HALO) | (g2 == TAG_HALO) | (g3 == TAG_HALO);
+    const bool inside = tag_body(g0) & (g1 == g0) & (g2 == g0) & (g3 == g0);
+    double k[KCOEF] = {0, 0, 0, 0, 0, 0};
+    if (!halo && !inside && lane < 63) cell_coefficients(ry, x0, x1, x2, x3, y0, y1, y2, y3, k);
+#pragma unroll
+    for (int e = 0; e < KCOEF; ++e) out[(sr * KCOEF + e) * 64 + lane] = (T)k[e];
+    g0 = g3;
+    x0 = x3;
+    y0 = y3;
+    g1 = g2;
+    x1 = x2;
+    y1 = y2;
+  }
+}
+
+// Slabs for the geometry tasks, numbered in task order (single block).
+__global__ void k_assign_geo(int ntiles, const uint8_t* __restrict__ tplain,
+                             int* __restrict__ tgeo, int* __restrict__ ngeo) {
+  __shared__ int s_scan[256];
+  __shared__ int s_base;
+  if (threadIdx.x == 0) s_base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < ntiles; c0 += 256) {
+    const int t = c0 + threadIdx.x;
+    const int f = (t < ntiles && !tplain[t]) ? 1 : 0;
+    s_scan[threadIdx.x] = f;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const int v = threadIdx.x >= off ? s_scan[threadIdx.x - off] : 0;
+      __syncthreads();
+      s_scan[threadIdx.x] += v;
+      __syncthreads();
+    }
+    if (t < ntiles) tgeo[t] = f ? s_base + s_scan[threadIdx.x] - 1 : -1;
+    __syncthreads();
+    if (threadIdx.x == 255) s_base += s_scan[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *ngeo = s_base;
+}
+
 // Per-body sums of one node row: lane b of the wavefront accumulates the sum of `val`
 // over the owned nodes of body b in this row (fixed order).
 __device__ __forceinline__ void body_row(bool owner, int8_t g, double val, int lane,

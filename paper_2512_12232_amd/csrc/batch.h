@@ -279,15 +279,49 @@ constexpr int BATCH_SEG = 4;
 // 4: 1297 / 896, 8: 1286 / 910.
 constexpr int BATCH_TPW = 4;
 
-static int batch_step_blocks(const Layout& L) {
-  long long g = ((long long)L.ntasks() + WAVES * BATCH_TPW - 1) / (WAVES * BATCH_TPW);
+// Schedule of a batched solve: tasks per wavefront and the element mode (stored
+// entries or geometry on the fly) of every system; 4-row tasks throughout.
+struct BatchSchedule {
+  int tpw = BATCH_TPW;
+  int kst = 0;
+  int ipl = 0;  // launches per replayed block when the caller passes 0 (0: 64)
+};
+
+// Built-in rule, then the tuning cache's batched entry (grid 0 x 0: one entry covers
+// every batch of this precision on this device), then the caller's explicit fields.
+static int resolve_batch_schedule(int precision, const mfp_solver_opts* o, BatchSchedule* out) {
+  BatchSchedule bs;
+  TuneEntry e;
+  mfp_grid any{};
+  if (tuned_entry(&any, precision, 1, &e)) {
+    if (e.tasks_per_wave >= 1 && e.tasks_per_wave <= 64) bs.tpw = e.tasks_per_wave;
+    if (e.element_mode == 1 || e.element_mode == 2) bs.kst = e.element_mode == 2;
+    if (e.iters_per_launch >= 2 && e.iters_per_launch <= 1024) bs.ipl = e.iters_per_launch;
+  }
+  if (o) {
+    if (o->element_mode < 0 || o->element_mode > 2 || o->batch_tasks_per_wave < 0 ||
+        o->batch_tasks_per_wave > 64) {
+      set_error("invalid batched schedule: element_mode 0..2, batch_tasks_per_wave 0..64");
+      return MFP_E_ARG;
+    }
+    if (o->element_mode) bs.kst = o->element_mode == 2;
+    if (o->batch_tasks_per_wave) bs.tpw = o->batch_tasks_per_wave;
+  }
+  *out = bs;
+  return MFP_OK;
+}
+
+static int batch_step_blocks(const Layout& L, int tpw) {
+  long long g = ((long long)L.ntasks() + WAVES * tpw - 1) / (WAVES * tpw);
   g = (g + 7) & ~7LL;
   if (g > 1024) g = 1024;
   return (int)g;
 }
 
 static size_t batch_layout(int nvar, const mfp_variant* v, int nb, int precision, void* base,
-                           BatchPlan* P) {
+                           BatchPlan* P, const BatchSchedule& bs) {
+  Schedule sc;  // 4-row tasks
+  sc.kst = bs.kst;
   Bump bp(base);
   if (P) {
     P->nvar = nvar;
@@ -300,14 +334,14 @@ static size_t batch_layout(int nvar, const mfp_variant* v, int nb, int precision
   }
   int totG = 0, totG2 = 0, totGS = 0;
   for (int i = 0; i < nvar; ++i) {
-    const size_t sz = solve_layout(&v[i].grid, nb, precision, nullptr, nullptr);
+    const size_t sz = solve_layout(&v[i].grid, nb, precision, nullptr, nullptr, &sc);
     char* b = bp.take<char>(sz);
     SolveWs w;
-    solve_layout(&v[i].grid, nb, precision, b, &w);
+    solve_layout(&v[i].grid, nb, precision, b, &w, &sc);
     w.sp = seg_plan(w.L, (w.L.ntasks() + BATCH_SEG - 1) / BATCH_SEG);
     const int G = w.sp.G;
     const int G2 = grid_blocks(w.L.n);
-    const int GS = batch_step_blocks(w.L);
+    const int GS = batch_step_blocks(w.L, bs.tpw);
     if (P) {
       P->w[i] = w;
       P->G[i] = G;
@@ -369,22 +403,38 @@ static StepArgs<T> batch_step_args(const SolveWs& w, const mfp_grid& g, int nb, 
 
 template <typename T>
 static void launch_step_batch(int G, hipStream_t st, const StepArgs<T>* args, const int2* map,
-                              int koff) {
+                              int koff, int kst) {
   // launch jbase + koff is odd (jbase is odd) for even koff: those update the iterate
-  if ((koff & 1) == 0)
-    k_step_batch<T, true><<<G, BLOCK, 0, st>>>(args, map, koff);
-  else
-    k_step_batch<T, false><<<G, BLOCK, 0, st>>>(args, map, koff);
+  if (kst) {
+    if ((koff & 1) == 0)
+      k_step_batch<T, true, true><<<G, BLOCK, 0, st>>>(args, map, koff);
+    else
+      k_step_batch<T, false, true><<<G, BLOCK, 0, st>>>(args, map, koff);
+  } else {
+    if ((koff & 1) == 0)
+      k_step_batch<T, true, false><<<G, BLOCK, 0, st>>>(args, map, koff);
+    else
+      k_step_batch<T, false, false><<<G, BLOCK, 0, st>>>(args, map, koff);
+  }
 }
 
 }  // namespace mfp
 
-extern "C" size_t mfp_batched_workspace_size(int32_t nvar, const mfp_variant* vars_h,
-                                             int32_t nbody, int32_t precision) {
-  if (nvar < 1 || !vars_h || nbody < 0 || nbody > MFP_MAX_BODIES) return 0;
+extern "C" size_t mfp_batched_workspace_size_opts(int32_t nvar, const mfp_variant* vars_h,
+                                                  int32_t nbody, const mfp_solver_opts* opts) {
+  if (nvar < 1 || !vars_h || !opts || nbody < 0 || nbody > MFP_MAX_BODIES) return 0;
   for (int i = 0; i < nvar; ++i)
     if (vars_h[i].grid.nx < 2 || vars_h[i].grid.ny < 2) return 0;
-  return mfp::batch_layout(nvar, vars_h, nbody, precision, nullptr, nullptr);
+  mfp::BatchSchedule bs;
+  if (mfp::resolve_batch_schedule(opts->precision, opts, &bs) != MFP_OK) return 0;
+  return mfp::batch_layout(nvar, vars_h, nbody, opts->precision, nullptr, nullptr, bs);
+}
+
+extern "C" size_t mfp_batched_workspace_size(int32_t nvar, const mfp_variant* vars_h,
+                                             int32_t nbody, int32_t precision) {
+  mfp_solver_opts o{};
+  o.precision = precision;
+  return mfp_batched_workspace_size_opts(nvar, vars_h, nbody, &o);
 }
 
 extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
@@ -415,21 +465,23 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
     MFP_TRY(check_solve_args(&vars_h[i].grid, circles_h + (size_t)i * nbody, nbody,
                              vars_h[i].disp, vars_h[i].kind, vars_h[i].body, flow, opts, ws));
   }
-  const size_t need = batch_layout(nvar, vars_h, nbody, opts->precision, nullptr, nullptr);
+  BatchSchedule bs;
+  MFP_TRY(resolve_batch_schedule(opts->precision, opts, &bs));
+  const size_t need = batch_layout(nvar, vars_h, nbody, opts->precision, nullptr, nullptr, bs);
   if (ws_bytes < need) {
     set_error("workspace too small: %zu < %zu", ws_bytes, need);
     return MFP_E_WORKSPACE;
   }
   hipStream_t st = static_cast<hipStream_t>(stream_);
   BatchPlan P;
-  batch_layout(nvar, vars_h, nbody, opts->precision, ws, &P);
+  batch_layout(nvar, vars_h, nbody, opts->precision, ws, &P, bs);
   const int nb = nbody;
   const bool mixed = opts->precision == MFP_FP32_IR;
   // launches per replay: FP64 an even number (jbase advances by m), mixed an odd one
   // (its last launch is run again as the restart: jbase advances by m - 1), so that
   // jbase stays odd and every replay has the same launch parities (the captured
   // kernel instances depend on them)
-  int m = iters_per_launch > 0 ? iters_per_launch : 64;
+  int m = iters_per_launch > 0 ? iters_per_launch : (bs.ipl > 0 ? bs.ipl : 64);
   m += m & 1;
   // an unrefined FP32 run loses its accuracy (and can break down) after a few hundred
   // iterations
@@ -527,9 +579,9 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   if (he == hipSuccess) {
     for (int k = 0; k < m; ++k) {
       if (mixed)
-        launch_step_batch<float>(P.totGS, cs, P.s32, P.smap, k);
+        launch_step_batch<float>(P.totGS, cs, P.s32, P.smap, k, bs.kst);
       else
-        launch_step_batch<double>(P.totGS, cs, P.s64, P.smap, k);
+        launch_step_batch<double>(P.totGS, cs, P.s64, P.smap, k, bs.kst);
     }
     if (mixed) {
       k_b_finish<float><<<P.totG2, BLOCK, 0, cs>>>(P.be, P.umap, m - 1, 1);

@@ -14,10 +14,17 @@
 // runs it for many systems per launch, batch.h); each block reduces the previous
 // launch's per-block partials itself.  Scalars never leave the device; the host polls
 // a done flag every few iterations.
+#include <dlfcn.h>
+#include <sys/stat.h>
+
 #include <cmath>
+#include <cstdlib>
 #include <cstddef>
 #include <cstring>
+#include <fstream>
 #include <mutex>
+#include <sstream>
+#include <string>
 #include <type_traits>
 #include <vector>
 
@@ -608,14 +615,18 @@ constexpr long long HIST_CAP = 16384;
 // Wavefronts of the one-kernel CG iteration k_step<T, hc> resident on the current
 // device at once (0 when the runtime cannot say).
 template <typename T>
-static int step_resident_waves(int hc = 4) {
+static int step_resident_waves(int hc = 4, int kst = 0) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  const void* f = hc == 8   ? reinterpret_cast<const void*>(&k_step<T, 8, false, true>)
-                  : hc == 5 ? reinterpret_cast<const void*>(&k_step<T, 5, false, true>)
-                            : reinterpret_cast<const void*>(&k_step<T, 4, false, true>);
+  const void* f =
+      kst ? (hc == 8   ? reinterpret_cast<const void*>(&k_step<T, 8, false, true, true>)
+             : hc == 5 ? reinterpret_cast<const void*>(&k_step<T, 5, false, true, true>)
+                       : reinterpret_cast<const void*>(&k_step<T, 4, false, true, true>))
+          : (hc == 8   ? reinterpret_cast<const void*>(&k_step<T, 8, false, true, false>)
+             : hc == 5 ? reinterpret_cast<const void*>(&k_step<T, 5, false, true, false>)
+                       : reinterpret_cast<const void*>(&k_step<T, 4, false, true, false>));
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, BLOCK, 0) != hipSuccess) return 0;
   return per_cu * cus * WAVES;
 }
@@ -624,9 +635,9 @@ static int step_resident_waves(int hc = 4) {
 // second round of work-groups trails the first), at most one task per wavefront and at
 // most 1024 (the next launch reduces one partial per block); a multiple of 8.
 template <typename T>
-static int step_blocks(const Layout& L) {
+static int step_blocks(const Layout& L, int kst = 0, int forced = 0) {
   const long long need = (((long long)L.ntasks() + WAVES - 1) / WAVES + 7) & ~7LL;
-  long long g = step_resident_waves<T>(L.hc) / WAVES;
+  long long g = forced > 0 ? forced : step_resident_waves<T>(L.hc, kst) / WAVES;
   g &= ~7LL;
   if (g < 8) g = 8;
   if (g > need) g = need;
@@ -671,6 +682,17 @@ static SegPlan seg_plan(const Layout& L, int target) {
   return p;
 }
 
+// Schedule of the one-kernel iteration of a single solve.
+struct Schedule {
+  int hc = 4;       // node rows per task: 4, 5 or 8
+  int kst = 0;      // 1: the geometry tasks read stored element entries (k_elem_coef)
+  int stream = -1;  // -1: by working-set size; 0: cached stores; 1: streaming stores
+  int blocks = 0;   // blocks per launch; 0: as many as stay resident
+};
+
+// Values per task slab of stored element entries (cell rows x entries x lanes).
+inline size_t kslab_rows(int hc) { return (size_t)(hc + 1) * KCOEF * 64; }
+
 struct SolveWs {
   Layout L;
   SegPlan sp;     // apply work list and launch size
@@ -701,6 +723,11 @@ struct SolveWs {
   int* sboff;     // surface samples: per-block counts / offsets
   int sboff_n = 0;
   int phi = 0;    // velocity-potential solve: body nodes are unknowns, no body constraint
+  Schedule sc;    // the iteration's schedule (task rows, element mode, stores, blocks)
+  int* tgeo = nullptr;      // stored element entries: per task its slab or -1
+  int* ngeo = nullptr;      // number of slabs in use
+  double* kc64 = nullptr;   // slabs for an FP64 iteration
+  float* kc32 = nullptr;    // slabs for an FP32 iteration
 };
 
 // Task height of a single solve's layout.  The FP32 iteration with 8-row tasks uses
@@ -722,11 +749,121 @@ static int solve_hc(const mfp_grid* g, int precision) {
   return make_layout(g->nx, g->ny).ntasks() >= 8192 ? 8 : 4;
 }
 
+// ---- tuning cache ----------------------------------------------------------------
+// A text file: the one named by MFP_TUNE_CACHE, else tune_cache.txt beside this
+// library (MFP_TUNE_CACHE=none: no cache, built-in rules only).  One entry per line
+// (written by the package's tuner, '#' starts a comment):
+//   arch nx ny precision batched task_rows element_mode store_mode launch_blocks
+//        tasks_per_wave iters_per_launch
+// with the fields of mfp_solver_opts (0 = automatic) and, for batched entries, the
+// batched solver's tasks per wavefront and launches per replayed block.  Read again
+// whenever the file's modification time changes.
+struct TuneEntry {
+  std::string arch;
+  int nx = 0, ny = 0, precision = 0, batched = 0;
+  int task_rows = 0, element_mode = 0, store_mode = 0, launch_blocks = 0;
+  int tasks_per_wave = 0, iters_per_launch = 0;
+};
+
+static std::mutex g_tune_mu;
+
+static std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return "";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+static std::string tune_cache_path() {
+  const char* env = std::getenv("MFP_TUNE_CACHE");
+  if (env) return (!*env || std::strcmp(env, "none") == 0) ? std::string() : std::string(env);
+  Dl_info info;
+  if (!dladdr(reinterpret_cast<const void*>(&tune_cache_path), &info) || !info.dli_fname)
+    return "";
+  std::string lib = info.dli_fname;
+  const size_t sl = lib.rfind('/');
+  return (sl == std::string::npos ? std::string(".") : lib.substr(0, sl)) + "/tune_cache.txt";
+}
+
+// The cache entry for this device, grid, precision and solver kind (false if none).
+static bool tuned_entry(const mfp_grid* g, int precision, int batched, TuneEntry* out) {
+  const std::string path_s = tune_cache_path();
+  if (path_s.empty()) return false;
+  const char* path = path_s.c_str();
+  static std::vector<TuneEntry> entries;
+  static std::string loaded_path, arch;
+  static long long loaded_mtime = -1;
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  struct stat sb;
+  if (stat(path, &sb) != 0) return false;
+  const long long mt = (long long)sb.st_mtime * 1000000000LL + (long long)sb.st_mtim.tv_nsec;
+  if (loaded_path != path || mt != loaded_mtime) {
+    entries.clear();
+    std::ifstream f(path);
+    std::string line;
+    while (std::getline(f, line)) {
+      const size_t h = line.find('#');
+      if (h != std::string::npos) line.resize(h);
+      std::istringstream is(line);
+      TuneEntry e;
+      if (is >> e.arch >> e.nx >> e.ny >> e.precision >> e.batched >> e.task_rows >>
+          e.element_mode >> e.store_mode >> e.launch_blocks >> e.tasks_per_wave >>
+          e.iters_per_launch)
+        entries.push_back(e);
+    }
+    loaded_path = path;
+    loaded_mtime = mt;
+  }
+  if (arch.empty()) arch = device_arch();
+  for (auto it = entries.rbegin(); it != entries.rend(); ++it)  // the last entry wins
+    if (it->arch == arch && it->nx == g->nx && it->ny == g->ny &&
+        it->precision == precision && it->batched == batched) {
+      *out = *it;
+      return true;
+    }
+  return false;
+}
+
+// Schedule fields (0 = automatic) applied over sc; false for a value out of range.
+static bool apply_schedule_fields(int task_rows, int element_mode, int store_mode,
+                                  int launch_blocks, Schedule* sc) {
+  if (task_rows != 0 && task_rows != 4 && task_rows != 5 && task_rows != 8) return false;
+  if (element_mode < 0 || element_mode > 2 || store_mode < 0 || store_mode > 2) return false;
+  if (launch_blocks < 0 || launch_blocks > 1024 || (launch_blocks & 7) != 0) return false;
+  if (task_rows) sc->hc = task_rows;
+  if (element_mode) sc->kst = element_mode == 2 ? 1 : 0;
+  if (store_mode) sc->stream = store_mode == 2 ? 1 : 0;
+  if (launch_blocks) sc->blocks = launch_blocks;
+  return true;
+}
+
+// Built-in rules, then the tuning cache, then the caller's explicit fields.
+static int resolve_schedule(const mfp_grid* g, int precision, const mfp_solver_opts* o,
+                            Schedule* out) {
+  Schedule sc;
+  sc.hc = solve_hc(g, precision);
+  TuneEntry e;
+  if (tuned_entry(g, precision, 0, &e))
+    (void)apply_schedule_fields(e.task_rows, e.element_mode, e.store_mode, e.launch_blocks, &sc);
+  if (o && !apply_schedule_fields(o->task_rows, o->element_mode, o->store_mode,
+                                  o->launch_blocks, &sc)) {
+    set_error("invalid schedule: task_rows 0/4/5/8, element_mode and store_mode 0..2, "
+              "launch_blocks a multiple of 8 up to 1024");
+    return MFP_E_ARG;
+  }
+  *out = sc;
+  return MFP_OK;
+}
+
 static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base, SolveWs* out,
-                           int hc_force = 0) {
+                           const Schedule* sched = nullptr) {
   Bump bp(base);
   SolveWs w{};
-  w.L = make_layout(g->nx, g->ny, hc_force);
+  if (sched) w.sc = *sched;
+  w.L = make_layout(g->nx, g->ny, w.sc.hc);
   const size_t n = (size_t)w.L.n;
   const int nt = w.L.ntasks();
   w.tag = bp.take<int8_t>(n);
@@ -770,6 +907,16 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
   w.boxes = bp.take<int>(4 * (nb > 0 ? nb : 1));
   w.count = bp.take<int>(1);
+  if (w.sc.kst) {
+    // every task could be a geometry task
+    w.tgeo = bp.take<int>(nt);
+    w.ngeo = bp.take<int>(1);
+    const size_t slabs = (size_t)nt * kslab_rows(w.L.hc);
+    if (precision == MFP_FP64)
+      w.kc64 = bp.take<double>(slabs);
+    else
+      w.kc32 = bp.take<float>(slabs);
+  }
   {
     // surface samples: at most nb boxes of at most nx ny cells each
     const long long items = (long long)(nb > 0 ? nb : 0) * g->nx * g->ny;
@@ -830,6 +977,29 @@ static ApplyArgs<T> make_apply_args(const SolveWs& w, const mfp_grid& g, int nb,
   a.cD = (T)(-(rr + qq) / 6.0);
   a.ry = (T)rr;
   return a;
+}
+
+// Stored element entries for the geometry tasks (Schedule::kst): slabs numbered in
+// task order, each cell's K_e by the 2x2 Gauss rule from the FP64 displacements,
+// kept in the precision of the iteration.
+template <typename T>
+static void launch_elem_coef(const SolveWs& w, double ry, T* kc, hipStream_t st) {
+  const int nb = (w.L.ntasks() + WAVES - 1) / WAVES;
+  if (w.L.hc == 8)
+    k_elem_coef<T, 8><<<nb, BLOCK, 0, st>>>(w.L, ry, w.tag, w.dx, w.dy, w.tgeo, kc);
+  else if (w.L.hc == 5)
+    k_elem_coef<T, 5><<<nb, BLOCK, 0, st>>>(w.L, ry, w.tag, w.dx, w.dy, w.tgeo, kc);
+  else
+    k_elem_coef<T, 4><<<nb, BLOCK, 0, st>>>(w.L, ry, w.tag, w.dx, w.dy, w.tgeo, kc);
+}
+
+static int element_entries(const mfp_grid& g, const SolveWs& w, hipStream_t st) {
+  k_assign_geo<<<1, 256, 0, st>>>(w.L.ntasks(), w.tplain, w.tgeo, w.ngeo);
+  const double ry = grid_hy(g) / grid_hx(g);
+  if (w.kc64) launch_elem_coef<double>(w, ry, w.kc64, st);
+  if (w.kc32) launch_elem_coef<float>(w, ry, w.kc32, st);
+  MFP_TRY_HIP(hipGetLastError());
+  return MFP_OK;
 }
 
 // Common setup: tags, scaled displacements, lifting, tile metadata.
@@ -895,6 +1065,7 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   k_seg_plan<<<1, 1024, 0, st>>>(w.L, w.tplain, w.sp.target, WAVES * w.sp.G, w.sp.tabsize,
                                  w.segtab);
   MFP_TRY_HIP(hipGetLastError());
+  if (w.sc.kst) MFP_TRY(element_entries(g, w, st));
   return MFP_OK;
 }
 
@@ -902,13 +1073,23 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
 
 using namespace mfp;
 
+extern "C" size_t mfp_solve_workspace_size_opts(const mfp_grid* grid, int32_t nbody,
+                                                const mfp_solver_opts* opts) {
+  if (!grid || !opts || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES)
+    return 0;
+  Schedule sc;
+  if (resolve_schedule(grid, opts->precision, opts, &sc) != MFP_OK) return 0;
+  // the solve's layout, and the element apply's (4-row tasks, geometry on the fly)
+  const size_t a = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, &sc);
+  const size_t b = solve_layout(grid, nbody, opts->precision, nullptr, nullptr);
+  return a > b ? a : b;
+}
+
 extern "C" size_t mfp_solve_workspace_size(const mfp_grid* grid, int32_t nbody,
                                            int32_t precision) {
-  if (!grid || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES) return 0;
-  // the solve's layout, and the element apply's (4-row tasks) for FP32
-  const size_t a = solve_layout(grid, nbody, precision, nullptr, nullptr, solve_hc(grid, precision));
-  const size_t b = solve_layout(grid, nbody, precision, nullptr, nullptr);
-  return a > b ? a : b;
+  mfp_solver_opts o{};
+  o.precision = precision;
+  return mfp_solve_workspace_size_opts(grid, nbody, &o);
 }
 
 extern "C" int mfp_element_apply(const mfp_grid* grid, const double* disp,
@@ -1051,6 +1232,17 @@ static StepRun<T> make_step_run(const SolveWs& w, const mfp_grid& g, int nb, con
   // 118 MB cached stores are 13% and 15% faster).
   const double vbytes = 7.0 * (double)w.L.n * sizeof(T);
   a.stream = (vbytes > 320.0 * 1024 * 1024 || vbytes <= 32.0 * 1024 * 1024) ? 1 : 0;
+  if (w.sc.stream >= 0) a.stream = w.sc.stream;
+  // stored element entries of this precision, if the schedule keeps them
+  const T* kc = nullptr;
+  if constexpr (sizeof(T) == sizeof(double))
+    kc = reinterpret_cast<const T*>(w.kc64);
+  else
+    kc = reinterpret_cast<const T*>(w.kc32);
+  if (w.sc.kst && kc) {
+    a.kcoef = kc;
+    a.tgeo = w.tgeo;
+  }
   const double hx = grid_hx(g), hy = grid_hy(g);
   const double rr = hy / hx, qq = hx / hy;
   a.cC = (T)(4.0 / 3.0 * (rr + qq));
@@ -1154,7 +1346,7 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
   }
   volatile int* flag = &io->flag;
   *flag = 0;  // no launch of an earlier run is in flight (every run ends synchronised)
-  const int G = step_blocks<T>(w.L);
+  const int G = step_blocks<T>(w.L, run.a.kcoef ? 1 : 0, w.sc.blocks);
   const int every = o.check_every > 0 ? o.check_every : 16;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
   // ev[b % NE] marks the end of batch b - 1 (ev[0]: the start of batch 0); an event is
@@ -1643,15 +1835,16 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
     set_error("bad sample buffers");
     return MFP_E_ARG;
   }
-  const int hc = solve_hc(grid, opts->precision);
-  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, hc);
+  Schedule sc;
+  MFP_TRY(resolve_schedule(grid, opts->precision, opts, &sc));
+  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, &sc);
   if (ws_bytes < need) {
     set_error("workspace too small: %zu < %zu", ws_bytes, need);
     return MFP_E_WORKSPACE;
   }
   hipStream_t st = static_cast<hipStream_t>(stream_);
   SolveWs w;
-  solve_layout(grid, nbody, opts->precision, ws, &w, hc);
+  solve_layout(grid, nbody, opts->precision, ws, &w, &sc);
   const mfp_grid& g = *grid;
   const int nb = nbody;
   SolveInfo info;
@@ -1735,15 +1928,16 @@ extern "C" int mfp_phi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
     set_error("phi is NULL");
     return MFP_E_ARG;
   }
-  const int hc = solve_hc(grid, opts->precision);
-  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, hc);
+  Schedule sc;
+  MFP_TRY(resolve_schedule(grid, opts->precision, opts, &sc));
+  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, &sc);
   if (ws_bytes < need) {
     set_error("workspace too small: %zu < %zu", ws_bytes, need);
     return MFP_E_WORKSPACE;
   }
   hipStream_t st = static_cast<hipStream_t>(stream_);
   SolveWs w;
-  solve_layout(grid, nbody, opts->precision, ws, &w, hc);
+  solve_layout(grid, nbody, opts->precision, ws, &w, &sc);
   w.phi = 1;
   const mfp_grid& g = *grid;
   // no body constraint (nb = 0); circle 0 only gives MFP_BC_DIRICHLET_CYLPHI its data
@@ -1760,15 +1954,23 @@ extern "C" int mfp_phi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   return finish_status(info);
 }
 
-extern "C" size_t mfp_grad_workspace_size(const mfp_grid* grid, int32_t nbody,
-                                          int32_t precision) {
+static size_t grad_workspace(const mfp_grid* grid, int32_t nbody, const mfp_solver_opts* o) {
   if (!grid || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES) return 0;
+  Schedule sc;
+  if (resolve_schedule(grid, o->precision, o, &sc) != MFP_OK) return 0;
   Bump bp(nullptr);
-  bp.off = solve_layout(grid, nbody, precision, nullptr, nullptr);
+  bp.off = solve_layout(grid, nbody, o->precision, nullptr, nullptr, &sc);
   const size_t nn = (size_t)(grid->nx + 1) * (grid->ny + 1);
   bp.take<double>(nn);                                  // lambda (nodal)
   bp.take<double>(8 * (size_t)grid->nx * grid->ny);     // per-cell shape derivatives
   return bp.off + 256;
+}
+
+extern "C" size_t mfp_grad_workspace_size(const mfp_grid* grid, int32_t nbody,
+                                          int32_t precision) {
+  mfp_solver_opts o{};
+  o.precision = precision;
+  return grad_workspace(grid, nbody, &o);
 }
 
 extern "C" int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
@@ -1793,7 +1995,9 @@ extern "C" int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, i
     set_error("dL_dcopfi is not finite");
     return MFP_E_ARG;
   }
-  const size_t need = mfp_grad_workspace_size(grid, nbody, opts->precision);
+  Schedule sc;
+  MFP_TRY(resolve_schedule(grid, opts->precision, opts, &sc));
+  const size_t need = grad_workspace(grid, nbody, opts);
   if (ws_bytes < need) {
     set_error("workspace too small: %zu < %zu", ws_bytes, need);
     return MFP_E_WORKSPACE;
@@ -1801,7 +2005,7 @@ extern "C" int mfp_psi_grad(const mfp_grid* grid, const mfp_circle* circles_h, i
   hipStream_t st = static_cast<hipStream_t>(stream_);
   SolveWs w;
   Bump bp(ws);
-  bp.off = solve_layout(grid, nbody, opts->precision, ws, &w);
+  bp.off = solve_layout(grid, nbody, opts->precision, ws, &w, &sc);
   const mfp_grid& g = *grid;
   const int nb = nbody;
   const long long nn = (long long)(g.nx + 1) * (g.ny + 1);

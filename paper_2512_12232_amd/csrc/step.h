@@ -112,6 +112,8 @@ struct StepArgs {
   int* host_done;                // single solve: stop code also written here (pinned host)
   double* hist;                  // single solve, may be NULL: hist[2j] = alpha_{j-1} and
   long long hist_cap;            // hist[2j+1] = beta_j as launch j forms them (j < hist_cap)
+  const T* kcoef;                // stored element entries (KST instances): slab per task
+  const int* tgeo;               // per task: its slab, -1 for constant-stencil tasks
   T* rs[2];
   T* ps[2];
   T* qs[2];
@@ -126,7 +128,7 @@ struct StepArgs {
 // neighbouring tasks share).  Every task's rows, iterate rows and flags are requested
 // one task ahead (a task that evaluates geometry requests its tags and displacements
 // first and the next task's data after its cell march, which needs the registers).
-template <typename T, int HC, bool STREAM, bool XUPD>
+template <typename T, int HC, bool STREAM, bool XUPD, bool KST>
 __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, const int G,
                                           const int koff, double* s_red, double* s_pb,
                                           double* s_qb) {
@@ -210,12 +212,14 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
 
   // next task's data (requested one task ahead)
   T nr[HC + 2], nq[HC + 2], np[HC + 2], nx[HC], n2[HC];  // n2: p_{j-2} (XUPD)
-  int n_plain = 1, n_body = 0, n_slot = -1;
+  int n_plain = 1, n_body = 0, n_slot = -1, n_geo = 0;
+  const gmem<int>* const tgeo = as_global(a.tgeo);
   auto fetch = [&](int t) {
     // flags first: the geometry request waits for them, not for the rows
     n_plain = tplain[t];
     n_body = tbody[t] != 0ull;
     n_slot = tslot[t];
+    if (KST) n_geo = tgeo[t];
     const unsigned bo = (unsigned)((int)node0(t) + shift_of(t)) * TS;
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
@@ -277,13 +281,25 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
 
   int8_t tg[HC + 2];
   T ddx[HC + 2], ddy[HC + 2];
-  auto load_geom = [&](int tt) {
+  T kc[HC + 1][KCOEF];  // KST: the task's stored element entries
+  const gmem<T>* const kcg = as_global(a.kcoef);
+  // tags, and either the displacements (geometry on the fly) or the element entries
+  auto load_geom = [&](int tt, int slab) {
     const unsigned ln0 = (unsigned)((int)node0(tt) + shift_of(tt));
 #pragma unroll
-    for (int r = 0; r < HC + 2; ++r) {
-      tg[r] = ld_at(tagg, ln0 + r * P);
-      ddx[r] = ld_at(dxg, ln0 * TS + r * RB);
-      ddy[r] = ld_at(dyg, ln0 * TS + r * RB);
+    for (int r = 0; r < HC + 2; ++r) tg[r] = ld_at(tagg, ln0 + r * P);
+    if constexpr (KST) {
+      const unsigned kb = ((unsigned)slab * (unsigned)kslab<HC>() + (unsigned)lane) * TS;
+#pragma unroll
+      for (int r = 0; r <= HC; ++r)
+#pragma unroll
+        for (int e = 0; e < KCOEF; ++e) kc[r][e] = ld_at(kcg, kb + (r * KCOEF + e) * 64 * TS);
+    } else {
+#pragma unroll
+      for (int r = 0; r < HC + 2; ++r) {
+        ddx[r] = ld_at(dxg, ln0 * TS + r * RB);
+        ddy[r] = ld_at(dyg, ln0 * TS + r * RB);
+      }
     }
   };
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -295,7 +311,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     s2 += in ? pv[u][2] : 0.0;
     s3 += in ? pv[u][3] : 0.0;
   }
-  if (t < ntask && !n_plain) load_geom(t);
+  if (t < ntask && !n_plain) load_geom(t, n_geo);
   for (int i = tid + PU * BLOCK; i < npart; i += BLOCK) {  // launches of more than 512 blocks
     s0 += pt[4 * i];
     s1 += pt[4 * i + 1];
@@ -419,6 +435,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     const bool plain = n_plain != 0;
     const bool bm = !plain && n_body != 0;
     const int slot = n_slot;
+    const int geo = n_geo;
     // r_j, p_j (as at a free node until corrected) and p_{j-1} at rows 0..HC+1
     T rj[HC + 2], v[HC + 2], po[HC + 2], xo[HC], p2[HC];
 #pragma unroll
@@ -434,7 +451,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
         p2[r] = n2[r];
       }
     }
-    if (!plain && !first) load_geom(t);
+    if (!plain && !first) load_geom(t, geo);
     first = false;
     T qr[HC];
     if (plain) {
@@ -451,7 +468,10 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
         else if (g > TAG_FREE)
           v[r] = (T)0;
       }
-      march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
+      if constexpr (KST)
+        march_task_stored<T, HC>(v, kc, qr);
+      else
+        march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
       // requested after the cell march, which needs the registers
       if (t + W < ntask) fetch(t + W);
     }
@@ -501,18 +521,18 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   }
 }
 
-template <typename T, int HC, bool STREAM, bool XUPD>
+template <typename T, int HC, bool STREAM, bool XUPD, bool KST>
 __global__ void __launch_bounds__(BLOCK) k_step(StepArgs<T> a) {
   __shared__ double s_red[4 * WAVES + 4];  // + stop flag, launch header (batched)
   __shared__ double s_pb[MFP_MAX_BODIES];
   __shared__ double s_qb[MFP_MAX_BODIES + 4 * WAVES];  // + final block sums
-  step_core<T, HC, STREAM, XUPD>(a, blockIdx.x, gridDim.x, 0, s_red, s_pb, s_qb);
+  step_core<T, HC, STREAM, XUPD, KST>(a, blockIdx.x, gridDim.x, 0, s_red, s_pb, s_qb);
 }
 
 // Many independent systems in one launch: block b works for system map[b].x as its
 // virtual block map[b].y (each system's blocks start at a multiple of 8); koff is this
 // launch's offset in the replayed block of launches.
-template <typename T, bool XUPD>
+template <typename T, bool XUPD, bool KST>
 __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restrict__ args,
                                                       const int2* __restrict__ map, int koff) {
   __shared__ double s_red[4 * WAVES + 4];  // + stop flag, launch header
@@ -522,25 +542,33 @@ __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restr
   const StepArgs<T>& a = args[vm.x];
   // streaming stores: the systems' vectors together exceed the memory-side cache
   // (measured on a 256-system sweep: 2% faster than cached stores)
-  step_core<T, 4, true, XUPD>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
+  step_core<T, 4, true, XUPD, KST>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
 }
 
 // Tasks of HC node rows (the layout's); odd launches update the iterate; a.stream
-// selects the streaming-store instance.
-template <typename T, int HC>
-inline void launch_step_h(int G, hipStream_t st, const StepArgs<T>& a) {
+// selects the streaming-store instance, a.kcoef the stored-element-entry one.
+template <typename T, int HC, bool KST>
+inline void launch_step_k(int G, hipStream_t st, const StepArgs<T>& a) {
   const bool xu = (a.j & 1) != 0;
   if (a.stream) {
     if (xu)
-      k_step<T, HC, true, true><<<G, BLOCK, 0, st>>>(a);
+      k_step<T, HC, true, true, KST><<<G, BLOCK, 0, st>>>(a);
     else
-      k_step<T, HC, true, false><<<G, BLOCK, 0, st>>>(a);
+      k_step<T, HC, true, false, KST><<<G, BLOCK, 0, st>>>(a);
   } else {
     if (xu)
-      k_step<T, HC, false, true><<<G, BLOCK, 0, st>>>(a);
+      k_step<T, HC, false, true, KST><<<G, BLOCK, 0, st>>>(a);
     else
-      k_step<T, HC, false, false><<<G, BLOCK, 0, st>>>(a);
+      k_step<T, HC, false, false, KST><<<G, BLOCK, 0, st>>>(a);
   }
+}
+
+template <typename T, int HC>
+inline void launch_step_h(int G, hipStream_t st, const StepArgs<T>& a) {
+  if (a.kcoef)
+    launch_step_k<T, HC, true>(G, st, a);
+  else
+    launch_step_k<T, HC, false>(G, st, a);
 }
 
 // hc: the layout's task height: 4; 5 for FP64 where 4-row tasks would outnumber the

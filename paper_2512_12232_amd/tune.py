@@ -1,0 +1,256 @@
+"""Offline tuner of the iteration schedule: python -m paper_2512_12232_amd.tune
+
+The one-kernel CG iteration has a few schedule choices that do not change the
+result beyond rounding but change its speed with the grid, the precision and the
+share of distorted cells:
+
+* task_rows      node rows per task (4, 5 or 8): registers against tasks per launch;
+* element_mode   1: each distorted cell's geometry (2x2 Gauss) recomputed every
+                 iteration from the displacements; 2: its element matrix evaluated
+                 once per solve and its six off-diagonal entries read every iteration;
+* store_mode     1: cached vector stores; 2: streaming (non-temporal) stores;
+* launch_blocks  work-groups per launch (0: as many as stay resident);
+* batched solves: tasks per wavefront, element mode and launches per replayed
+  block (iters_per_launch).
+
+The tuner times complete solves of a representative workload for candidate
+schedules with the library's own event timing (the iteration phase,
+stats["solve_ms"]; best of `reps`), searching one choice at a time from the
+built-in rules, checks that every candidate returns the same body values as the
+built-in schedule, and writes the fastest as one line per (device architecture,
+grid, precision, solver kind) into the tuning cache the library reads: the file
+named by MFP_TUNE_CACHE, else tune_cache.txt beside libmfpsi.so.  Batched entries
+use grid 0 x 0: one entry covers every batch of that precision.
+
+Usage (on the GPU):
+  python -m paper_2512_12232_amd.tune --grids 1024x512,2048x1024,4096x2048 \\
+      --precisions fp64,fp32_ir --batched fp32_ir,fp64 --out <cache file>
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_CACHE = os.path.join(PKG, "tune_cache.txt")
+FIELDS = ("task_rows", "element_mode", "store_mode", "launch_blocks")
+
+
+def _five_cylinders(nx, ny, delta=0.25):
+    """Five-cylinder channel layout (D = 1 on [-20, 20] x [-10, 10]), the paper's
+    multi-body configuration: three streamwise cylinders and a transverse pair."""
+    yc = 1.0 + delta
+    circles = [(-3.0, 0.0, 0.5), (0.0, 0.0, 0.5), (3.0, 0.0, 0.5), (0.0, -yc, 0.5),
+               (0.0, yc, 0.5)]
+
+    class G:
+        pass
+    g = G()
+    g.nx, g.ny, g.x0, g.x1, g.y0, g.y1 = nx, ny, -20.0, 20.0, -10.0, 10.0
+
+    class F:
+        U = 1.0
+        side_bc = (B.BC_DIRICHLET_UY, B.BC_NATURAL, B.BC_DIRICHLET_UY, B.BC_DIRICHLET_UY)
+    return g, circles, F()
+
+
+def _arch() -> str:
+    name = torch.cuda.get_device_properties(0).gcnArchName
+    return name.split(":")[0]
+
+
+def _no_cache():
+    """Context: the library's built-in rules only (tuning cache switched off)."""
+    class _Ctx:
+        def __enter__(self):
+            self.old = os.environ.get("MFP_TUNE_CACHE")
+            os.environ["MFP_TUNE_CACHE"] = "none"
+
+        def __exit__(self, *exc):
+            if self.old is None:
+                del os.environ["MFP_TUNE_CACHE"]
+            else:
+                os.environ["MFP_TUNE_CACHE"] = self.old
+    return _Ctx()
+
+
+def time_single(mesh, grid, circles, flow, precision, rtol, schedule, reps):
+    disp, kind, body = mesh
+    best, res = float("inf"), None
+    for _ in range(reps):
+        r = B.psi_solve(grid, circles, disp, kind, body, flow, rtol=rtol, precision=precision,
+                        pair=(3, 4), sample_cap=0, schedule=schedule)
+        if r.status not in (B.MFP_OK, B.MFP_W_STAGNATION):
+            return float("inf"), r
+        if r.stats["solve_ms"] < best:
+            best, res = r.stats["solve_ms"], r
+    return best, res
+
+
+def tune_single(nx, ny, precision, rtol, reps=2, log=print):
+    grid, circles, flow = _five_cylinders(nx, ny)
+    mesh = B.mesh_conform(grid, circles, 200, device="cuda:0")
+    with _no_cache():
+        t_def, ref = time_single(mesh, grid, circles, flow, precision, rtol, None, reps)
+    log(f"  built-in rules: {t_def:.3f} ms ({ref.stats['iters']} iterations)")
+    rows = (4, 5) if precision == "fp64" else (4, 5, 8)
+
+    def ok(r):
+        return r is not None and np.abs(np.array(r.psi_b) - np.array(ref.psi_b)).max() <= 1e-7
+
+    best = {"task_rows": 0, "element_mode": 0, "store_mode": 0, "launch_blocks": 0}
+    t_best = float("inf")
+    with _no_cache():
+        for tr in rows:
+            for em in (1, 2):
+                cand = dict(best, task_rows=tr, element_mode=em)
+                t, r = time_single(mesh, grid, circles, flow, precision, rtol, cand, reps)
+                log(f"  {cand}: {t:.3f} ms")
+                if ok(r) and t < t_best:
+                    best, t_best = cand, t
+        for sm in (1, 2):
+            cand = dict(best, store_mode=sm)
+            t, r = time_single(mesh, grid, circles, flow, precision, rtol, cand, reps)
+            log(f"  {cand}: {t:.3f} ms")
+            if ok(r) and t < t_best:
+                best, t_best = cand, t
+        for lb in (256, 512, 1024):
+            cand = dict(best, launch_blocks=lb)
+            t, r = time_single(mesh, grid, circles, flow, precision, rtol, cand, reps)
+            log(f"  {cand}: {t:.3f} ms")
+            if ok(r) and t < t_best:
+                best, t_best = cand, t
+    return best, t_best, t_def
+
+
+def _sweep_systems(count, seed):
+    rng = np.random.default_rng(seed)
+    deltas = rng.uniform(0.05, 2.0, size=count)
+    nxs = 2 * rng.integers(128, 513, size=count)
+    out = []
+    for nx, d in zip(nxs, deltas):
+        grid, circles, flow = _five_cylinders(int(nx), int(nx) // 2, float(d))
+        disp, kind, body = B.mesh_conform(grid, circles, 200, device="cuda:0")
+        out.append((grid, circles, disp, kind, body))
+    return out, flow
+
+
+def time_batched(systems, flow, precision, schedule, ipl, reps):
+    best = float("inf")
+    res = None
+    for _ in range(reps):
+        r = B.psi_solve_batched(systems, flow, precision=precision, rtol=1e-10, pair=(3, 4),
+                                iters_per_launch=ipl, schedule=schedule)
+        if r.status != B.MFP_OK:
+            return float("inf"), r
+        t = r.stats[0]["solve_ms"]
+        if t < best:
+            best, res = t, r
+    return best, res
+
+
+def tune_batched(precision, count=256, seed=0, reps=2, log=print):
+    systems, flow = _sweep_systems(count, seed)
+    with _no_cache():
+        t_def, ref = time_batched(systems, flow, precision, None, 0, reps)
+    log(f"  built-in rules: {t_def:.1f} ms")
+
+    def ok(r):
+        return r is not None and np.abs(np.array(r.copfi) - np.array(ref.copfi)).max() <= 1e-7
+
+    best = {"element_mode": 0, "batch_tasks_per_wave": 0}
+    best_ipl, t_best = 0, float("inf")
+    with _no_cache():
+        for em in (1, 2):
+            for tpw in (1, 2, 4, 8):
+                cand = dict(best, element_mode=em, batch_tasks_per_wave=tpw)
+                t, r = time_batched(systems, flow, precision, cand, best_ipl, reps)
+                log(f"  {cand}: {t:.1f} ms")
+                if ok(r) and t < t_best:
+                    best, t_best = cand, t
+        for ipl in (32, 128):
+            t, r = time_batched(systems, flow, precision, best, ipl, reps)
+            log(f"  {best} iters_per_launch {ipl}: {t:.1f} ms")
+            if ok(r) and t < t_best:
+                best_ipl, t_best = ipl, t
+    return best, best_ipl, t_best, t_def
+
+
+def write_entries(path, entries, note):
+    """Replace the entries with the same key, keep the others."""
+    keep = []
+    keys = {tuple(e[:5]) for e in entries}
+    if os.path.exists(path):
+        with open(path) as f:
+            for line in f:
+                body = line.split("#")[0].split()
+                if len(body) >= 11 and (body[0], int(body[1]), int(body[2]), int(body[3]),
+                                        int(body[4])) in keys:
+                    continue
+                if line.strip() and not line.startswith("#"):
+                    keep.append(line.rstrip("\n"))
+    with open(path, "w") as f:
+        f.write("# arch nx ny precision batched task_rows element_mode store_mode "
+                "launch_blocks tasks_per_wave iters_per_launch\n")
+        f.write(f"# {note}\n")
+        for line in keep:
+            f.write(line + "\n")
+        for e in entries:
+            f.write(" ".join(str(v) for v in e[:11]) + (f"  # {e[11]}" if len(e) > 11 else "")
+                    + "\n")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--grids", default="1024x512,2048x1024,4096x2048")
+    ap.add_argument("--precisions", default="fp64,fp32_ir")
+    ap.add_argument("--batched", default="fp32_ir,fp64")
+    ap.add_argument("--count", type=int, default=256)
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--out", default=os.environ.get("MFP_TUNE_CACHE", DEFAULT_CACHE))
+    ap.add_argument("--json", default="")
+    a = ap.parse_args(argv)
+    B.load()
+    arch = _arch()
+    prec_code = {"fp64": B.FP64, "fp32": B.FP32, "fp32_ir": B.FP32_IR}
+    entries, report = [], []
+    t0 = time.time()
+    for gs in [g for g in a.grids.split(",") if g]:
+        nx, ny = (int(v) for v in gs.split("x"))
+        for prec in [p for p in a.precisions.split(",") if p]:
+            rtol = 1e-12 if nx * ny <= 2048 * 1024 else 1e-10
+            print(f"[tune] {gs} {prec} rtol {rtol:g}", flush=True)
+            best, t_best, t_def = tune_single(nx, ny, prec, rtol, a.reps,
+                                              log=lambda s: print(s, flush=True))
+            entries.append([arch, nx, ny, prec_code[prec], 0, best["task_rows"],
+                            best["element_mode"], best["store_mode"], best["launch_blocks"], 0,
+                            0, f"{t_best:.3f} ms vs built-in {t_def:.3f} ms"])
+            report.append(dict(grid=gs, precision=prec, schedule=best, tuned_ms=t_best,
+                               builtin_ms=t_def))
+    for prec in [p for p in a.batched.split(",") if p]:
+        print(f"[tune] batched {prec} ({a.count} systems)", flush=True)
+        best, ipl, t_best, t_def = tune_batched(prec, a.count, 0, a.reps,
+                                                log=lambda s: print(s, flush=True))
+        entries.append([arch, 0, 0, prec_code[prec], 1, 0, best["element_mode"], 0, 0,
+                        best["batch_tasks_per_wave"], ipl,
+                        f"{t_best:.1f} ms vs built-in {t_def:.1f} ms"])
+        report.append(dict(grid="batched", precision=prec, schedule=dict(best, iters_per_launch=ipl),
+                           tuned_ms=t_best, builtin_ms=t_def))
+    write_entries(a.out, entries, f"python -m paper_2512_12232_amd.tune {' '.join(argv or sys.argv[1:])}"
+                                  f" ({time.time() - t0:.0f} s)")
+    print(f"[tune] wrote {len(entries)} entries to {a.out}", flush=True)
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump(report, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

@@ -147,7 +147,7 @@ def test_full_size_gradient_matches_oracle_and_fd(mfp):
         f"{abs(gd - hdr['dcopfi_ddelta'][0]):.3e} (bar {bar:.2e})")
     np.testing.assert_allclose(g, gref, rtol=0, atol=bar)
     assert abs(gd - hdr["dcopfi_ddelta"][0]) <= bar
-    assert float(J) == pytest.approx(hdr["copfi"][0], abs=1e-10)
+    assert float(J.detach()) == pytest.approx(hdr["copfi"][0], abs=1e-10)
     # finite differences of delta with warm-started solves
     say("[adjoint full size] finite differences")
     disp0, kind0, body0 = mfp.mesh_conform(c.grid, c.circles, 200, device=DEV)

@@ -372,3 +372,80 @@ def test_bench_workload_1024x512_matches_oracle_direct_solve(mfp):
     assert np.array_equal(res.sample_body.cpu().numpy(), bb)
     np.testing.assert_allclose(res.theta.cpu().numpy(), th, rtol=0, atol=1e-12)
     assert dut <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["cyl64", "five96x48", "five_ragged130x67",
+                                  "five_gap_lt_h_256x128"])
+@pytest.mark.parametrize("precision,rows", [("fp64", 4), ("fp64", 5), ("fp32_ir", 4),
+                                            ("fp32_ir", 8)])
+def test_stored_element_entries_match_oracle(mfp, name, precision, rows):
+    """Element mode 2 (each distorted cell's K_e evaluated once per solve, its six
+    off-diagonal entries read by the iteration): the same bars against the oracle."""
+    c = CASES[name]
+    say(f"[stored entries] {name} {precision} rows {rows}")
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13,
+                        precision=precision, pair=c.pair,
+                        schedule={"task_rows": rows, "element_mode": 2})
+    assert res.status == 0
+    mesh = O.conform(c.grid, c.circles, c.nsweeps)
+    ref = O.solve(mesh, c.flow)
+    psi = res.psi.cpu().numpy()
+    err = np.linalg.norm(psi - ref.psi) / np.linalg.norm(ref.psi)
+    assert err <= 1e-10 and node_max_err(psi, ref.psi) <= 1e-10, err
+    assert res.stats["relres_true"] <= 2e-13
+    np.testing.assert_allclose(res.psi_b, ref.psi_b, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 6, 17])
+def test_stored_entries_iterate_after_k_iterations(mfp, k):
+    """With stored element entries the first k iterations still equal the oracle's
+    textbook CG (both launch parities)."""
+    from oracle.cg import cg
+    c = CASES["five_ragged130x67"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-30, kmax=k,
+                        check_every=4, schedule={"element_mode": 2, "task_rows": 5})
+    assert res.status == 1 and res.stats["iters"] == k
+    mesh = O.conform(c.grid, c.circles, c.nsweeps)
+    ref = O.solve(mesh, c.flow)
+    y, _, _ = cg(ref.A, ref.b, rtol=0.0, max_iters=k)
+    psi_k = ref.g + ref.T @ y
+    err = np.linalg.norm(res.psi.cpu().numpy() - psi_k) / np.linalg.norm(psi_k)
+    assert err <= 1e-11, err
+
+
+def test_schedule_fields_validated(mfp):
+    c = CASES["five96x48"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    for bad in ({"task_rows": 6}, {"element_mode": 3}, {"launch_blocks": 12},
+                {"store_mode": -1}):
+        with pytest.raises(mfp.MfpError) as e:
+            mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-10,
+                          schedule=bad, ws=torch.empty(1 << 26, dtype=torch.uint8,
+                                                       device=DEV))
+        assert e.value.status == mfp.MFP_E_ARG
+
+
+def test_tuning_cache_entry_selects_the_schedule(mfp, tmp_path, monkeypatch):
+    """An entry of the tuning cache (MFP_TUNE_CACHE) sets the schedule of solves on its
+    grid and precision (visible in the task count: 8-row tasks), MFP_TUNE_CACHE=none
+    restores the built-in rules, and both give the same solution to the solver's
+    tolerance."""
+    c = CASES["five96x48"]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    path = tmp_path / "cache.txt"
+    path.write_text(f"# test\n{arch} {c.grid.nx} {c.grid.ny} 0 0 8 2 1 0 0 0\n")
+    monkeypatch.setenv("MFP_TUNE_CACHE", "none")
+    a = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13)
+    monkeypatch.setenv("MFP_TUNE_CACHE", str(path))
+    b = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13)
+    strips = -(-(c.grid.nx + 1) // 62)
+    assert a.stats["n_tiles"] == strips * -(-(c.grid.ny + 1) // 4)
+    assert b.stats["n_tiles"] == strips * -(-(c.grid.ny + 1) // 8)
+    np.testing.assert_allclose(b.psi_b, a.psi_b, rtol=0, atol=1e-10)
+    # an explicit field of the options wins over the cache
+    e = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13,
+                      schedule={"task_rows": 5})
+    assert e.stats["n_tiles"] == strips * -(-(c.grid.ny + 1) // 5)
