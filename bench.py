@@ -73,10 +73,29 @@ def traffic_from_profile():
     return int(fields["traffic_bytes_per_launch"])
 
 
+def host_info():
+    """CPU model and the cores this process may use on the benchmark host."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(case, seconds):
     """The oracle's plain CG on the assembled reduced system, one thread, run for a
     bounded number of iterations chosen from a short calibration run so that the
-    timed part takes about `seconds`."""
+    timed part takes about `seconds`; and the oracle's time to solution by sparse LU
+    (assembly, factorisation and solve: oracle.solve), whose solution is returned for
+    the error figures."""
     import numpy as np
     from threadpoolctl import threadpool_limits
 
@@ -97,10 +116,61 @@ def cpu_baseline(case, seconds):
         t0 = time.perf_counter()
         _, k, _ = cg(A, b, rtol=1e-300, max_iters=iters)
         dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sol = oracle.solve(mesh, case.flow)
+        t_lu = time.perf_counter() - t0
     return {"value": ndof * k / dt, "unit": "DOF·iter/s", "cores": 1, "kind": "oracle",
             "sample": f"{k} iterations of the oracle's plain FP64 CG on the assembled "
                       f"reduced CSR system of the same workload ({ndof} DOF, scipy.sparse "
-                      f"SpMV, 1 thread); assembly not timed; {dt:.1f} s"}
+                      f"SpMV, 1 thread); assembly not timed; {dt:.1f} s",
+            "splu_time_to_solution_s": round(t_lu, 2),
+            "splu_note": "oracle.solve: assembly, SuperLU factorisation and solve, 1 thread",
+            "host": host_info()}, mesh, sol
+
+
+def errors_vs_oracle(case, res, mesh, sol, kappa):
+    """The GPU result of the benchmark workload against the oracle's direct solve:
+    psi (relative L2 over all nodes, and the largest nodal difference relative to
+    max|psi|), psi_b, Q, CoPFI and u_t (relative to max|u_t|), each stated beside the
+    condition number (the GPU's Lanczos estimate from this solve's CG scalars and the
+    oracle's extreme eigenvalues of the reduced operator)."""
+    import numpy as np
+
+    import oracle
+    from oracle.spectrum import condition_number
+    psi = res.psi.cpu().numpy()
+    lo, hi = case.pair
+    Q, J = oracle.copfi(sol.psi_b, lo, hi, case.flow.U, case.circles[lo][1], case.circles[hi][1])
+    th, ut, _ = oracle.surface_samples(mesh, sol.psi, sol.psi_b)
+    t0 = time.perf_counter()
+    lmin, lmax, kap = condition_number(sol.A)
+    return {"psi_rel_l2": float(np.linalg.norm(psi - sol.psi) / np.linalg.norm(sol.psi)),
+            "psi_node_max_rel": float(np.abs(psi - sol.psi).max() / np.abs(sol.psi).max()),
+            "psi_b_max_abs": float(np.abs(np.array(res.psi_b) - sol.psi_b).max()),
+            "Q_abs": abs(res.Q - Q), "copfi_abs": abs(res.copfi - J),
+            "u_t_max_rel": float(np.abs(res.ut.cpu().numpy() - ut).max() / np.abs(ut).max()),
+            "kappa_gpu_lanczos": kappa,
+            "kappa_oracle": {"lambda_min": lmin, "lambda_max": lmax, "kappa": kap,
+                             "seconds": round(time.perf_counter() - t0, 1),
+                             "note": "ARPACK on the assembled reduced matrix (largest "
+                                     "eigenvalue, and shift-invert about 0 for the "
+                                     "smallest)"},
+            "note": "the Lanczos estimate sees the eigenvectors the odd (mirror-symmetric) "
+                    "right-hand side reaches; the oracle's kappa is the whole operator's"}
+
+
+def potential_vs_oracle(case_phi, phi, mesh):
+    """The GPU potential against the oracle's direct solve of the same problem."""
+    import numpy as np
+
+    import oracle
+    ref = oracle.phi_solve(mesh, case_phi.flow)
+    p = phi.cpu().numpy()
+    dom = ~np.isnan(ref.phi)
+    return {"phi_rel_l2": float(np.linalg.norm(p[dom] - ref.phi[dom]) / np.linalg.norm(ref.phi[dom])),
+            "phi_node_max_rel": float(np.abs(p[dom] - ref.phi[dom]).max()
+                                      / np.abs(ref.phi[dom]).max()),
+            "nan_pattern_equal": bool(np.array_equal(np.isnan(p), ~dom))}
 
 
 def _sync():
@@ -158,6 +228,11 @@ def mixed_precision(mfp, W, kmax=10 ** 7):
                 "launch_ms": round(kms, 5), "bytes_per_launch": nbytes,
                 "achieved_GBs": round(nbytes / (kms * 1e-3) / 1e9, 1),
                 "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    # condition estimate of this operator from an FP64 solve's CG scalars (untimed)
+    rk = mfp.psi_solve(case.grid, case.circles, disp, kind, body, case.flow, rtol=1e-10,
+                       pair=case.pair, sample_cap=0, estimate_kappa=True)
+    out["kappa_gpu_lanczos"] = {"kappa": rk.stats["kappa_est"], "ritz_min": rk.stats["ritz_min"],
+                                "ritz_max": rk.stats["ritz_max"], "steps": rk.stats["kappa_steps"]}
     ref = res["fp64"].psi
     for prec in ("fp32_ir", "fp32"):
         d = res[prec].psi - ref
@@ -195,10 +270,13 @@ def mixed_precision(mfp, W, kmax=10 ** 7):
 
 
 def _oracle_reference_4096():
-    """The stored oracle solution of the 4096x2048 workload (tests/golden: CG on the
-    assembled system to a true relative residual <= 1e-13), or None."""
+    """The stored oracle solution of the 4096x2048 workload (tests/golden): the refined
+    one (residuals in extended precision, FP64 CG corrections) when present, else the
+    plain CG one (true relative residual <= 1e-13); None if neither exists."""
     import numpy as np
-    path = os.path.join(ROOT, "tests", "golden", "five_cyl_4096x2048_reference.txt")
+    path = os.path.join(ROOT, "tests", "golden", "five_cyl_4096x2048_refined.txt")
+    if not os.path.exists(path):
+        path = os.path.join(ROOT, "tests", "golden", "five_cyl_4096x2048_reference.txt")
     if not os.path.exists(path):
         return None
     psi_b, copfi, rows = None, None, []
@@ -239,11 +317,91 @@ def adjoint_ratio(mfp, W):
         return dc, st
 
     (dc, st), bwd_ms = _timed(bwd, reps=2)
-    return {"workload": "five cylinders, 2048x1024 cells, delta 0.15, rtol 1e-12",
-            "forward_ms": round(fwd_ms, 2), "backward_ms": round(bwd_ms, 2),
-            "ratio": bwd_ms / fwd_ms, "forward_iters": r.stats["iters"],
-            "adjoint_iters": st["iters"], "copfi": r.copfi,
-            "dcopfi_ddelta": dc[4][1] - dc[3][1]}
+    out = {"workload": "five cylinders, 2048x1024 cells, delta 0.15, rtol 1e-12",
+           "forward_ms": round(fwd_ms, 2), "backward_ms": round(bwd_ms, 2),
+           "ratio": bwd_ms / fwd_ms, "forward_iters": r.stats["iters"],
+           "adjoint_iters": st["iters"], "copfi": r.copfi,
+           "dcopfi_ddelta": dc[4][1] - dc[3][1]}
+    gold = _gradient_golden()
+    if gold is not None:
+        hdr, gref = gold
+        g = [[float(v) for v in row] for row in dc]
+        scale = max(abs(v) for row in gref for v in row)
+        err = max(abs(g[b][k] - gref[b][k]) for b in range(5) for k in range(2))
+        out["vs_oracle_gradient"] = {
+            "max_abs_err_centres": err, "abs_err_ddelta": abs(out["dcopfi_ddelta"] -
+                                                               hdr["dcopfi_ddelta"]),
+            "max_abs_grad": scale, "rel_to_max_grad": err / scale,
+            "source": "tests/golden/five_cyl_2048x1024_gradient.txt (oracle discrete "
+                      "adjoint, sparse LU)"}
+    return out
+
+
+def _gradient_golden():
+    """The oracle's gradient of the 2048x1024 workload (tests/golden), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "five_cyl_2048x1024_gradient.txt")
+    if not os.path.exists(path):
+        return None
+    hdr, rows = {}, []
+    for line in open(path):
+        if line.startswith("#"):
+            parts = line[1:].split()
+            if parts and parts[0] in ("copfi", "dcopfi_ddelta"):
+                hdr[parts[0]] = float(parts[1])
+            continue
+        _, gx, gy = line.split()
+        rows.append((float(gx), float(gy)))
+    return hdr, rows
+
+
+def autotune_effect(mfp, W):
+    """Tuned schedule (the package's tuning cache) against the built-in rules
+    (MFP_TUNE_CACHE=none) on the workloads the cache was tuned on: 1024x512 (the
+    benchmark's) and 2048x1024 to rtol 1e-12, 4096x2048 to 1e-10, each in FP64 and
+    FP32 + refinement, and the 256-variant batched sweep in FP32 + refinement.
+    Iteration-phase times (ms, best of two)."""
+    import numpy as np
+    out = {}
+
+    def both(fn):
+        old = os.environ.get("MFP_TUNE_CACHE")
+        res = {}
+        for label, val in (("builtin", "none"), ("tuned", None)):
+            if val is None:
+                os.environ.pop("MFP_TUNE_CACHE", None)
+            else:
+                os.environ["MFP_TUNE_CACHE"] = val
+            res[label] = min(fn() for _ in range(2))
+        if old is None:
+            os.environ.pop("MFP_TUNE_CACHE", None)
+        else:
+            os.environ["MFP_TUNE_CACHE"] = old
+        res["speedup"] = res["builtin"] / res["tuned"]
+        return res
+
+    for case, prec, rtol, key in ((W.five_cyl_1024(), "fp64", 1e-12, "1024x512_fp64"),
+                                  (W.five_cyl_1024(), "fp32_ir", 1e-12, "1024x512_fp32_ir"),
+                                  (W.five_cyl_2048_adjoint(), "fp64", 1e-12, "2048x1024_fp64"),
+                                  (W.five_cyl_2048_adjoint(), "fp32_ir", 1e-12,
+                                   "2048x1024_fp32_ir"),
+                                  (W.five_cyl_4096(), "fp64", 1e-10, "4096x2048_fp64"),
+                                  (W.five_cyl_4096(), "fp32_ir", 1e-10, "4096x2048_fp32_ir")):
+        d, k, b = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device="cuda:0")
+        out[key] = both(lambda: mfp.psi_solve(case.grid, case.circles, d, k, b, case.flow,
+                                              rtol=rtol, precision=prec, pair=case.pair,
+                                              sample_cap=0).stats["solve_ms"])
+    cases = W.batch_variants(256, seed=0)
+    systems = []
+    for c in cases:
+        d, k, b = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device="cuda:0")
+        systems.append((c.grid, c.circles, d, k, b))
+    out["sweep256_fp32_ir"] = both(lambda: mfp.psi_solve_batched(
+        systems, cases[0].flow, precision="fp32_ir", rtol=1e-10,
+        pair=cases[0].pair).stats[0]["solve_ms"])
+    for v in out.values():
+        for kk in ("builtin", "tuned"):
+            v[kk] = round(float(np.float64(v[kk])), 3)
+    return out
 
 
 def potential_solve(mfp, W):
@@ -257,6 +415,7 @@ def potential_solve(mfp, W):
     d, k, b = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device=dev)
     r, ms = _timed(lambda: mfp.phi_solve(case.grid, case.circles, d, k, b, case.flow,
                                          rtol=1e-12, profile_every=1), reps=2)
+    potential_solve.last = (case, r.phi)
     s = r.stats
     nbytes, _ = step_bytes(case, d, b)
     out = {"workload": "five cylinders, 1024x512 cells, delta 0.25; phi = U x on inlet and "
@@ -420,9 +579,13 @@ def main():
                     "kernel": "k_step<double, %d>" % _task_height(case, res.stats["n_tiles"]),
                     "launch_ms": round(ms, 5), "bytes_per_launch": nbytes,
                     "samples": int(sum(r.stats["apply_samples"] for _, _, r in outs))}
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(case, args.cpu_seconds)
+    # condition estimate of the benchmark solve from its CG scalars (an extra,
+    # untimed solve of the same system)
+    dk, kk, bk = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device=dev)
+    rk = mfp.psi_solve(case.grid, case.circles, dk, kk, bk, case.flow, rtol=1e-12,
+                       pair=case.pair, sample_cap=0, estimate_kappa=True)
+    kappa = {"kappa": rk.stats["kappa_est"], "ritz_min": rk.stats["ritz_min"],
+             "ritz_max": rk.stats["ritz_max"], "steps": rk.stats["kappa_steps"]}
     extras = {}
     if not args.no_extras:
         extras["mixed_precision_4096x2048"] = mixed_precision(mfp, W)
@@ -430,6 +593,15 @@ def main():
         extras["potential_1024x512"] = potential_solve(mfp, W)
         extras["stagnation_streamlines_1024x512"] = streamlines(mfp, W)
         extras["delta_sweep_256"] = delta_sweep(mfp, W)
+        extras["autotune"] = autotune_effect(mfp, W)
+    cpu = None
+    vs_oracle = {"kappa_gpu_lanczos": kappa}
+    if not args.no_cpu_baseline:
+        cpu, mesh_o, sol_o = cpu_baseline(case, args.cpu_seconds)
+        vs_oracle = errors_vs_oracle(case, res, mesh_o, sol_o, kappa)
+        if "potential_1024x512" in extras:
+            pc, phi = potential_solve.last
+            extras["potential_1024x512"]["vs_oracle"] = potential_vs_oracle(pc, phi, mesh_o)
     s = res.stats
     line = {
         "metric": METRIC,
@@ -451,6 +623,7 @@ def main():
                    "n_dof": s["n_dof"], "nodes": case.grid.nodes, "moved_nodes": moved},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "vs_oracle": vs_oracle,
         "iters": s["iters"],
         "solve_ms": s["solve_ms"],
         "relres_true": s["relres_true"],

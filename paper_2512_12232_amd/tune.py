@@ -16,7 +16,8 @@ share of distorted cells:
 The tuner times complete solves of a representative workload for candidate
 schedules with the library's own event timing (the iteration phase,
 stats["solve_ms"]; best of `reps`), searching one choice at a time from the
-built-in rules, checks that every candidate returns the same body values as the
+built-in rules (a candidate must be 2% faster than the incumbent, which starts as the
+built-in schedule), checks that every candidate returns the same body values as the
 built-in schedule, and writes the fastest as one line per (device architecture,
 grid, precision, solver kind) into the tuning cache the library reads: the file
 named by MFP_TUNE_CACHE, else tune_cache.txt beside libmfpsi.so.  Batched entries
@@ -42,6 +43,9 @@ from . import binding as B
 PKG = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_CACHE = os.path.join(PKG, "tune_cache.txt")
 FIELDS = ("task_rows", "element_mode", "store_mode", "launch_blocks")
+# a candidate replaces the incumbent (first the built-in schedule) only if it is at
+# least 2% faster: run-to-run noise of a whole solve is about 1%
+MARGIN = 0.98
 
 
 def _five_cylinders(nx, ny, delta=0.25):
@@ -106,27 +110,28 @@ def tune_single(nx, ny, precision, rtol, reps=2, log=print):
     def ok(r):
         return r is not None and np.abs(np.array(r.psi_b) - np.array(ref.psi_b)).max() <= 1e-7
 
+    # the built-in schedule is the incumbent; a candidate must beat it by MARGIN
     best = {"task_rows": 0, "element_mode": 0, "store_mode": 0, "launch_blocks": 0}
-    t_best = float("inf")
+    t_best = t_def
     with _no_cache():
         for tr in rows:
             for em in (1, 2):
                 cand = dict(best, task_rows=tr, element_mode=em)
                 t, r = time_single(mesh, grid, circles, flow, precision, rtol, cand, reps)
                 log(f"  {cand}: {t:.3f} ms")
-                if ok(r) and t < t_best:
+                if ok(r) and t < MARGIN * t_best:
                     best, t_best = cand, t
         for sm in (1, 2):
             cand = dict(best, store_mode=sm)
             t, r = time_single(mesh, grid, circles, flow, precision, rtol, cand, reps)
             log(f"  {cand}: {t:.3f} ms")
-            if ok(r) and t < t_best:
+            if ok(r) and t < MARGIN * t_best:
                 best, t_best = cand, t
         for lb in (256, 512, 1024):
             cand = dict(best, launch_blocks=lb)
             t, r = time_single(mesh, grid, circles, flow, precision, rtol, cand, reps)
             log(f"  {cand}: {t:.3f} ms")
-            if ok(r) and t < t_best:
+            if ok(r) and t < MARGIN * t_best:
                 best, t_best = cand, t
     return best, t_best, t_def
 
@@ -167,19 +172,19 @@ def tune_batched(precision, count=256, seed=0, reps=2, log=print):
         return r is not None and np.abs(np.array(r.copfi) - np.array(ref.copfi)).max() <= 1e-7
 
     best = {"element_mode": 0, "batch_tasks_per_wave": 0}
-    best_ipl, t_best = 0, float("inf")
+    best_ipl, t_best = 0, t_def
     with _no_cache():
         for em in (1, 2):
             for tpw in (1, 2, 4, 8):
                 cand = dict(best, element_mode=em, batch_tasks_per_wave=tpw)
                 t, r = time_batched(systems, flow, precision, cand, best_ipl, reps)
                 log(f"  {cand}: {t:.1f} ms")
-                if ok(r) and t < t_best:
+                if ok(r) and t < MARGIN * t_best:
                     best, t_best = cand, t
         for ipl in (32, 128):
             t, r = time_batched(systems, flow, precision, best, ipl, reps)
             log(f"  {best} iters_per_launch {ipl}: {t:.1f} ms")
-            if ok(r) and t < t_best:
+            if ok(r) and t < MARGIN * t_best:
                 best_ipl, t_best = ipl, t
     return best, best_ipl, t_best, t_def
 
@@ -214,7 +219,7 @@ def main(argv=None):
     ap.add_argument("--precisions", default="fp64,fp32_ir")
     ap.add_argument("--batched", default="fp32_ir,fp64")
     ap.add_argument("--count", type=int, default=256)
-    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--out", default=os.environ.get("MFP_TUNE_CACHE", DEFAULT_CACHE))
     ap.add_argument("--json", default="")
     a = ap.parse_args(argv)
