@@ -30,7 +30,10 @@ Body-Conforming Grids"):
 * ``cg``    -- a plain conjugate-gradient loop on the assembled matrix (CPU
   timing baseline);
 * ``spectrum`` -- extreme eigenvalues of the reduced operator (condition number)
-  and the Ritz extremes of the Lanczos process from a right-hand side.
+  and the Ritz extremes of the Lanczos process from a right-hand side;
+* ``mixed`` -- the paper's own mesher with mixed cells (grid points moved onto the
+  body along grid lines, node splitting, triangles, pentagons cut into a triangle
+  and a quadrilateral) and the stream-function solve on it (P1 and Q1 elements).
 
 Readings of passages where the paper is silent or ambiguous are listed in the
 module docstrings where they are applied.
