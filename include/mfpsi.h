@@ -21,6 +21,9 @@
  *   mfp_contour        contour lines of psi or phi: the flow net and the stagnation
  *                      streamlines of the transverse cylinders ("Effect of Gap Ratio");
  *   mfp_element_apply  the matrix-free element product of Algorithm 1 on its own;
+ *   mfp_mixed_*        the mixed-cell variant of the body-conforming grid (cut points
+ *                      on the grid lines, triangles and quadrilaterals) with its
+ *                      element product and constrained solve;
  *   mfp_psi_grad / mfp_mesh_conform_grad
  *                      the adjoint of that map (the automated sensitivity analysis named
  *                      in the Conclusions as the next step).
@@ -408,6 +411,93 @@ int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h, const mfp_cir
                           int32_t iters_per_launch, int32_t pair_lo, int32_t pair_hi,
                           double* psi_b_h, double* copfi_h, mfp_stats* stats_h, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* ---- mixed-cell mesh ---------------------------------------------------------------
+ * The mesh of section "Body-Conforming Grid Generation" that keeps the grid lines:
+ * each grid edge joining a node inside a body to a fluid node is cut where it crosses
+ * the circle (cut point I + t (O - I) with |I + t (O - I) - c| = r, t in [0, 1), I the
+ * inside end, O the fluid end); inside nodes leave the mesh; every cut cell becomes the
+ * polygon of its fluid corners and cut points walked counter-clockwise from corner
+ * (i, j): a triangle (one fluid corner), a quadrilateral (two) or a pentagon (three),
+ * the pentagon split into the triangle (P_a, C1, C2) and the quadrilateral
+ * (P_a, C2, C3, P_b), P_a the cut point after the inside corner, C1..C3 the fluid
+ * corners that follow, P_b the cut point before it.  A triangle whose two cut points
+ * lie within 1e-12 max(hx, hy) of each other (max norm) has no area and is not meshed.
+ * Fluid nodes are then moved by `nsweeps` Jacobi sweeps of the displacement (weights
+ * as for mfp_mesh_conform, start 0, outer-boundary nodes fixed) in which an inside
+ * neighbour contributes its cut point's displacement P - I.  Cells with corners in two
+ * bodies, grid edges joining two bodies and cells whose inside and fluid corners
+ * alternate are rejected (MFP_E_GEOMETRY).
+ * Mixed-node numbering: background nodes j (nx+1) + i (inside ones unused), then the
+ * cut points, numbered in edge order: horizontal edges (edge j nx + i joins (i, j) and
+ * (i+1, j)), then vertical ones (edge (ny+1) nx + j (nx+1) + i joins (i, j), (i, j+1)).
+ * Elements are numbered cell by cell (cell j nx + i), a pentagon's triangle first.
+ * Every floating-point expression of the mesh is evaluated without fused
+ * multiply-add, so the mesh is reproducible bit for bit. */
+typedef struct {
+  /* caller-owned device arrays, sizes in elements */
+  double* disp;          /* 2 (nx+1)(ny+1): displacements of background nodes (x, then y) */
+  int8_t* body;          /* (nx+1)(ny+1): body of each background node, -1 fluid           */
+  int32_t* hpt;          /* (ny+1) nx: cut point of each horizontal edge, -1 none          */
+  int32_t* vpt;          /* ny (nx+1): cut point of each vertical edge, -1 none            */
+  int32_t* cell_first;   /* nx ny + 1: first element of each cell, then the element count  */
+  double* pxy;           /* 2 cap_points: (x, y) of each cut point                          */
+  int8_t* pbody;         /* cap_points: body of each cut point                              */
+  int32_t* pedge;        /* cap_points: grid edge of each cut point                         */
+  int32_t* elem;         /* 4 cap_elems: mixed node ids, counter-clockwise, -1 past nne     */
+  int8_t* nne;           /* cap_elems: 3 (triangle) or 4 (quadrilateral)                    */
+  int64_t cap_points;    /* capacity of pxy / pbody / pedge (may be 0)                      */
+  int64_t cap_elems;     /* capacity of elem / nne (may be 0)                               */
+  int64_t n_points;      /* out: cut points                                                 */
+  int64_t n_elems;       /* out: elements                                                   */
+  int64_t n_tri;         /* out: triangles among them                                       */
+} mfp_mixed_mesh_t;
+
+/* Workspace bytes for mfp_mixed_mesh (0 for an invalid grid or body count). */
+size_t mfp_mixed_workspace_size(const mfp_grid* grid, int32_t nbody);
+
+/* Builds the mixed-cell mesh into *m.  disp, body, hpt, vpt and cell_first are always
+ * written; the cut points and elements are copied up to cap_points / cap_elems (the
+ * counts are reported in full, so a first call with zero capacities sizes a second).
+ * Synchronises `stream`.  MFP_E_GEOMETRY as mfp_check_geometry and for the mesh
+ * rejections above (message names which). */
+int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                   int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
+                   void* stream);
+
+/* Workspace bytes for mfp_mixed_element_apply / mfp_mixed_psi_solve on a mixed mesh of
+ * n_points cut points and n_elems elements. */
+size_t mfp_mixed_solve_workspace_size(const mfp_grid* grid, int64_t n_points, int64_t n_elems,
+                                      int32_t nbody);
+
+/* q = K p on the mixed mesh (section "Weak formulation": P1 triangles exactly, Q1
+ * quadrilaterals with 2x2 Gauss points, summed over the elements), p and q device
+ * double[(nx+1)(ny+1) + n_points] in mixed-node numbering; nodes in no element get 0.
+ * The element matrices are evaluated once per call into the workspace; the product is
+ * a gather (each node sums its rows of the elements of the cells around it in a fixed
+ * order), so it is deterministic.  `repeat` >= 1 launches the product that many times;
+ * apply_ms_h (may be NULL) receives the mean product time in milliseconds.
+ * Synchronises `stream`. */
+int mfp_mixed_element_apply(const mfp_grid* grid, const mfp_mixed_mesh_t* m, const double* p,
+                            double* q, int32_t repeat, double* apply_ms_h, void* ws,
+                            size_t ws_bytes, void* stream);
+
+/* Constrained stream-function solve on the mixed mesh (Algorithm 1, FP64 only): the
+ * unknowns are the fluid nodes of some element that lie on no Dirichlet side, plus one
+ * psi_b per body shared by all its cut points; Dirichlet sides as in mfp_psi_solve.
+ * CG on A y = b, A = T^T K T, b = -T^T K g, to ||r|| <= rtol ||b||, with the scalars
+ * kept on the device (the host reads the stop flag every opts->check_every
+ * iterations, 32 if 0).  psi: device double[(nx+1)(ny+1) + n_points]: the free
+ * values, the Dirichlet values, psi_b at the cut points and 0 at unused nodes (inside
+ * nodes, fluid nodes in no element).  psi_b_h, Q_h, copfi_h, stats_h as in
+ * mfp_psi_solve (stats: iters, applies, n_free, n_dof, rnorm0, relres_true,
+ * solve_ms).  Other opts fields are ignored.  Returns MFP_W_NOCONV, MFP_E_BREAKDOWN
+ * as mfp_psi_solve; MFP_E_ARG for a precision other than MFP_FP64. */
+int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                        const mfp_mixed_mesh_t* m, const mfp_flow* flow,
+                        const mfp_solver_opts* opts, int32_t pair_lo, int32_t pair_hi,
+                        double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
+                        mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

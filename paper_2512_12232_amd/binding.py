@@ -34,7 +34,8 @@ EXPORTS = [
     "mfp_mesh_conform_grad", "mfp_batched_workspace_size", "mfp_psi_solve_batched",
     "mfp_phi_solve", "mfp_cubic_fit", "mfp_contour_workspace_size", "mfp_contour",
     "mfp_element_apply_noalloc", "mfp_solve_workspace_size_opts",
-    "mfp_batched_workspace_size_opts",
+    "mfp_batched_workspace_size_opts", "mfp_mixed_workspace_size", "mfp_mixed_mesh",
+    "mfp_mixed_solve_workspace_size", "mfp_mixed_element_apply", "mfp_mixed_psi_solve",
 ]
 
 
@@ -85,6 +86,14 @@ class MfpStats(Structure):
 class MfpVariant(Structure):
     _fields_ = [("grid", MfpGrid), ("disp", c_void_p), ("kind", c_void_p), ("body", c_void_p),
                 ("psi", c_void_p)]
+
+
+class MfpMixedMesh(Structure):
+    _fields_ = [("disp", c_void_p), ("body", c_void_p), ("hpt", c_void_p), ("vpt", c_void_p),
+                ("cell_first", c_void_p), ("pxy", c_void_p), ("pbody", c_void_p),
+                ("pedge", c_void_p), ("elem", c_void_p), ("nne", c_void_p),
+                ("cap_points", c_int64), ("cap_elems", c_int64), ("n_points", c_int64),
+                ("n_elems", c_int64), ("n_tri", c_int64)]
 
 
 class MfpError(RuntimeError):
@@ -157,6 +166,19 @@ def load(path: str = LIB_PATH):
         c_int32, POINTER(MfpVariant), POINTER(MfpCircle), c_int32, POINTER(MfpFlow),
         POINTER(MfpSolverOpts), c_int32, c_int32, c_int32, POINTER(c_double),
         POINTER(c_double), POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
+    lib.mfp_mixed_workspace_size.restype = c_size_t
+    lib.mfp_mixed_workspace_size.argtypes = [POINTER(MfpGrid), c_int32]
+    lib.mfp_mixed_mesh.argtypes = [POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_int32,
+                                   POINTER(MfpMixedMesh), c_void_p, c_size_t, c_void_p]
+    lib.mfp_mixed_solve_workspace_size.restype = c_size_t
+    lib.mfp_mixed_solve_workspace_size.argtypes = [POINTER(MfpGrid), c_int64, c_int64, c_int32]
+    lib.mfp_mixed_element_apply.argtypes = [POINTER(MfpGrid), POINTER(MfpMixedMesh), c_void_p,
+                                            c_void_p, c_int32, POINTER(c_double), c_void_p,
+                                            c_size_t, c_void_p]
+    lib.mfp_mixed_psi_solve.argtypes = [
+        POINTER(MfpGrid), POINTER(MfpCircle), c_int32, POINTER(MfpMixedMesh), POINTER(MfpFlow),
+        POINTER(MfpSolverOpts), c_int32, c_int32, c_void_p, POINTER(c_double),
+        POINTER(c_double), POINTER(c_double), POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
     _lib = lib
     return lib
 
@@ -514,3 +536,121 @@ def batched_workspace_size(systems, precision="fp32_ir", schedule=None) -> int:
         vars_[i] = MfpVariant(make_grid(s[0]), None, None, None, None)
     o = _opts(precision, 1e-10, 1, 64, 0.1, 1000, schedule=schedule)
     return lib.mfp_batched_workspace_size_opts(nvar, vars_, len(systems[0][1]), byref(o))
+
+
+@dataclass
+class MixedMesh:
+    """Device arrays of a mixed-cell mesh (see mfp_mixed_mesh_t)."""
+    grid: object
+    circles: list
+    disp: torch.Tensor        # 2 nodes f64 (x, then y)
+    body: torch.Tensor        # nodes i8
+    hpt: torch.Tensor         # (ny+1) nx i32
+    vpt: torch.Tensor         # ny (nx+1) i32
+    cell_first: torch.Tensor  # nx ny + 1 i32
+    pxy: torch.Tensor         # (n_points, 2) f64
+    pbody: torch.Tensor       # n_points i8
+    pedge: torch.Tensor       # n_points i32
+    elem: torch.Tensor        # (n_elems, 4) i32
+    nne: torch.Tensor         # n_elems i8
+    n_tri: int
+
+    @property
+    def n_points(self) -> int:
+        return int(self.pbody.numel())
+
+    @property
+    def n_elems(self) -> int:
+        return int(self.nne.numel())
+
+    @property
+    def n_nodes(self) -> int:
+        return (self.grid.nx + 1) * (self.grid.ny + 1) + self.n_points
+
+    def c_struct(self) -> MfpMixedMesh:
+        return MfpMixedMesh(_ptr(self.disp), _ptr(self.body), _ptr(self.hpt), _ptr(self.vpt),
+                            _ptr(self.cell_first), _ptr(self.pxy), _ptr(self.pbody),
+                            _ptr(self.pedge), _ptr(self.elem), _ptr(self.nne), self.n_points,
+                            self.n_elems, self.n_points, self.n_elems, self.n_tri)
+
+
+def mixed_mesh(grid, circles, nsweeps: int = 200, device="cuda") -> MixedMesh:
+    """Mixed-cell mesh: a sizing call (zero capacities), then the filling call."""
+    lib = load()
+    g = make_grid(grid)
+    c = make_circles(circles)
+    nb = len(circles)
+    n = (g.nx + 1) * (g.ny + 1)
+    disp = torch.empty(2 * n, dtype=torch.float64, device=device)
+    body = torch.empty(n, dtype=torch.int8, device=device)
+    hpt = torch.empty((g.ny + 1) * g.nx, dtype=torch.int32, device=device)
+    vpt = torch.empty(g.ny * (g.nx + 1), dtype=torch.int32, device=device)
+    first = torch.empty(g.nx * g.ny + 1, dtype=torch.int32, device=device)
+    ws = workspace(lib.mfp_mixed_workspace_size(byref(g), nb), device)
+    m = MfpMixedMesh(_ptr(disp), _ptr(body), _ptr(hpt), _ptr(vpt), _ptr(first))
+    _check(lib.mfp_mixed_mesh(byref(g), c, nb, int(nsweeps), byref(m), _ptr(ws), ws.numel(),
+                              _stream()))
+    npts, nel = m.n_points, m.n_elems
+    pxy = torch.empty((max(npts, 1), 2), dtype=torch.float64, device=device)
+    pbody = torch.empty(max(npts, 1), dtype=torch.int8, device=device)
+    pedge = torch.empty(max(npts, 1), dtype=torch.int32, device=device)
+    elem = torch.empty((max(nel, 1), 4), dtype=torch.int32, device=device)
+    nne = torch.empty(max(nel, 1), dtype=torch.int8, device=device)
+    m.pxy, m.pbody, m.pedge = _ptr(pxy), _ptr(pbody), _ptr(pedge)
+    m.elem, m.nne = _ptr(elem), _ptr(nne)
+    m.cap_points, m.cap_elems = npts, nel
+    _check(lib.mfp_mixed_mesh(byref(g), c, nb, int(nsweeps), byref(m), _ptr(ws), ws.numel(),
+                              _stream()))
+    return MixedMesh(grid, list(circles), disp, body, hpt, vpt, first, pxy[:npts],
+                     pbody[:npts], pedge[:npts], elem[:nel], nne[:nel], int(m.n_tri))
+
+
+def mixed_element_apply(mm: MixedMesh, p: torch.Tensor, repeat: int = 1):
+    """q = K p on the mixed mesh (mixed-node numbering).  Returns (q, mean ms)."""
+    lib = load()
+    g = make_grid(mm.grid)
+    p = p.to(torch.float64).contiguous()
+    if p.numel() != mm.n_nodes:
+        raise ValueError(f"p has {p.numel()} values, the mesh {mm.n_nodes} nodes")
+    q = torch.empty_like(p)
+    m = mm.c_struct()
+    ws = workspace(lib.mfp_mixed_solve_workspace_size(byref(g), mm.n_points, mm.n_elems, 0),
+                   p.device)
+    ms = c_double(0.0)
+    _check(lib.mfp_mixed_element_apply(byref(g), byref(m), _ptr(p), _ptr(q), int(repeat),
+                                       byref(ms), _ptr(ws), ws.numel(), _stream()))
+    return q, ms.value
+
+
+@dataclass
+class MixedSolveResult:
+    psi: torch.Tensor   # mixed-node values
+    psi_b: list
+    Q: float
+    copfi: float
+    stats: dict
+    status: int
+
+
+def mixed_psi_solve(mm: MixedMesh, flow, *, rtol=1e-12, kmax=10 ** 7, check_every=32,
+                    pair=(-1, -1), allow_warn: bool = True) -> MixedSolveResult:
+    lib = load()
+    g = make_grid(mm.grid)
+    c = make_circles(mm.circles)
+    nb = len(mm.circles)
+    f = make_flow(flow)
+    o = _opts("fp64", rtol, kmax, check_every, 0.1, 1000)
+    dev = mm.disp.device
+    psi = torch.empty(mm.n_nodes, dtype=torch.float64, device=dev)
+    psib = (c_double * max(nb, 1))()
+    Q = c_double(float("nan"))
+    cop = c_double(float("nan"))
+    st = MfpStats()
+    m = mm.c_struct()
+    ws = workspace(lib.mfp_mixed_solve_workspace_size(byref(g), mm.n_points, mm.n_elems, nb),
+                   dev)
+    status = _check(lib.mfp_mixed_psi_solve(
+        byref(g), c, nb, byref(m), byref(f), byref(o), int(pair[0]), int(pair[1]), _ptr(psi),
+        psib, byref(Q), byref(cop), byref(st), _ptr(ws), ws.numel(), _stream()), allow_warn)
+    stats = {k: getattr(st, k) for k, _ in MfpStats._fields_}
+    return MixedSolveResult(psi, [psib[k] for k in range(nb)], Q.value, cop.value, stats, status)

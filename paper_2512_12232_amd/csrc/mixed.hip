@@ -1,0 +1,1228 @@
+// The paper's mixed-cell mesh on the GPU and the stream-function solve on it
+// (section "Body-Conforming Grid Generation": grid points just inside a body moved
+// onto it along grid lines, node splitting, triangles and pentagons, pentagons cut
+// into a triangle and a quadrilateral; section "Weak formulation": element
+// matrices of triangles and quadrilaterals; Algorithm 1: CG with the body values as
+// constrained unknowns).
+//
+// Mesh (one thread per node, edge or cell; no atomics in what is written):
+//   k_mx_classify   node -> body by (x-cx)^2 + (y-cy)^2 <= r^2 in FP64
+//   k_mx_edge_flags an edge joining an inside and a fluid node is cut (flag 1);
+//                   an edge joining two bodies is an error
+//   (scan)          cut points numbered in edge order: horizontal edges, then vertical
+//   k_mx_cut        the cut point I + t (O - I), |I - c + t (O - I)| = r, t in [0, 1)
+//   k_mx_sweep      Jacobi sweeps of the displacement on fluid nodes; an inside
+//                   neighbour contributes its cut point's displacement P - I
+//   k_mx_cell_count elements per cell (0, 1 or 2), errors for cells touching two bodies
+//                   or with alternating corners
+//   (scan)          elements numbered in cell order
+//   k_mx_cells      the polygon of each cell: fluid corners and cut points walked
+//                   counter-clockwise from corner (i, j); pentagons split from the cut
+//                   point after the inside corner; slivers (two cut points within
+//                   1e-12 h, max norm) not meshed
+// Apply: element matrices (P1 triangles exactly, Q1 quadrilaterals by 2x2 Gauss)
+// evaluated once per call into the workspace (the paper stores them); q = K p is a
+// gather: every mixed node sums, in a fixed order, its rows of the elements of the
+// (at most four) cells around it, so the result is deterministic and no scatter or
+// atomic is needed.
+//
+// Mixed-node numbering: background nodes j (nx+1) + i (inside ones unused), then
+// the cut points.  Every floating-point expression of the mesh is evaluated without
+// contraction into fused multiply-adds (same rounding as a plain IEEE evaluation).
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "mfp_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace mfp {
+namespace mixed {
+
+constexpr int MB = 256;  // threads per block
+constexpr int SCAN_CH = MB * 8;  // flags per block of the scans
+constexpr double SLIVER = 1e-12;
+
+struct G {
+  int nx, ny;
+  double x0, y0, hx, hy;
+  __host__ __device__ long long nn() const { return (long long)(nx + 1) * (ny + 1); }
+  __host__ __device__ long long nh() const { return (long long)(ny + 1) * nx; }
+  __host__ __device__ long long nv() const { return (long long)ny * (nx + 1); }
+  __host__ __device__ long long nc() const { return (long long)nx * ny; }
+};
+
+__device__ __forceinline__ double node_x(const G& g, int i) { return g.x0 + (double)i * g.hx; }
+__device__ __forceinline__ double node_y(const G& g, int j) { return g.y0 + (double)j * g.hy; }
+
+static int blocks_for(long long n) {
+  long long b = (n + MB - 1) / MB;
+  if (b > 65535) b = 65535;
+  return (int)(b < 1 ? 1 : b);
+}
+
+// ---- exclusive scan of int flags: out[k] = sum of in[0..k), out[n] = total ----------
+__global__ void k_scan_block_sums(const int* __restrict__ in, long long n, int* __restrict__ bs) {
+  __shared__ int s[MB];
+  const long long b0 = (long long)blockIdx.x * SCAN_CH;
+  int acc = 0;
+  for (int k = 0; k < 8; ++k) {
+    const long long i = b0 + (long long)threadIdx.x * 8 + k;
+    if (i < n) acc += in[i];
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = MB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bs[blockIdx.x] = s[0];
+}
+
+// single block: exclusive scan of the block sums in place, total in bs[nb]
+__global__ void k_scan_sums(int* __restrict__ bs, int nb) {
+  __shared__ int s[MB];
+  __shared__ int base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  for (int c0 = 0; c0 < nb; c0 += MB) {
+    const int i = c0 + threadIdx.x;
+    const int v = i < nb ? bs[i] : 0;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < MB; off <<= 1) {
+      const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+      __syncthreads();
+      s[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < nb) bs[i] = base + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == MB - 1) base += s[MB - 1];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bs[nb] = base;
+}
+
+__global__ void k_scan_write(const int* __restrict__ in, long long n, const int* __restrict__ bs,
+                             int nb, int* __restrict__ out) {
+  __shared__ int s[MB];
+  const long long b0 = (long long)blockIdx.x * SCAN_CH;
+  int v[8];
+  int acc = 0;
+  for (int k = 0; k < 8; ++k) {
+    const long long i = b0 + (long long)threadIdx.x * 8 + k;
+    v[k] = i < n ? in[i] : 0;
+    acc += v[k];
+  }
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 1; off < MB; off <<= 1) {
+    const int t = threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += t;
+    __syncthreads();
+  }
+  int run = bs[blockIdx.x] + s[threadIdx.x] - acc;
+  for (int k = 0; k < 8; ++k) {
+    const long long i = b0 + (long long)threadIdx.x * 8 + k;
+    if (i < n) out[i] = run;
+    run += v[k];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = bs[nb];
+}
+
+static int scan_blocks(long long n) { return (int)((n + SCAN_CH - 1) / SCAN_CH); }
+
+static int exclusive_scan(const int* in, long long n, int* bs, int* out, hipStream_t st) {
+  const int nb = scan_blocks(n < 1 ? 1 : n);
+  k_scan_block_sums<<<nb, MB, 0, st>>>(in, n, bs);
+  k_scan_sums<<<1, MB, 0, st>>>(bs, nb);
+  k_scan_write<<<nb, MB, 0, st>>>(in, n, bs, nb, out);
+  MFP_TRY_HIP(hipGetLastError());
+  return MFP_OK;
+}
+
+// ---- mesh -----------------------------------------------------------------------------
+__global__ void k_mx_classify(G g, const mfp_circle* __restrict__ circ, int nb,
+                              int8_t* __restrict__ body) {
+  const long long nn = g.nn();
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(n / (g.nx + 1)), i = (int)(n - (long long)j * (g.nx + 1));
+    const double x = node_x(g, i), y = node_y(g, j);
+    int b_in = -1;
+    for (int b = 0; b < nb; ++b) {
+      const double dx = x - circ[b].cx, dy = y - circ[b].cy;
+      if (dx * dx + dy * dy <= circ[b].r * circ[b].r) b_in = b;
+    }
+    body[n] = (int8_t)b_in;
+  }
+}
+
+// Edge e: horizontal (i,j)-(i+1,j) for e < nh (e = j nx + i), vertical (i,j)-(i,j+1)
+// for e = nh + j (nx+1) + i.  Ends a (lower-left) and c.
+__device__ __forceinline__ void edge_ends(const G& g, long long e, int& ia, int& ja, int& ic,
+                                          int& jc) {
+  const long long nh = g.nh();
+  if (e < nh) {
+    ja = (int)(e / g.nx);
+    ia = (int)(e - (long long)ja * g.nx);
+    ic = ia + 1;
+    jc = ja;
+  } else {
+    const long long v = e - nh;
+    ja = (int)(v / (g.nx + 1));
+    ia = (int)(v - (long long)ja * (g.nx + 1));
+    ic = ia;
+    jc = ja + 1;
+  }
+}
+
+__global__ void k_mx_edge_flags(G g, const int8_t* __restrict__ body, int* __restrict__ flag,
+                                int* __restrict__ err) {
+  const long long ne = g.nh() + g.nv();
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
+       e += (long long)gridDim.x * blockDim.x) {
+    int ia, ja, ic, jc;
+    edge_ends(g, e, ia, ja, ic, jc);
+    const int ba = body[(long long)ja * (g.nx + 1) + ia];
+    const int bc = body[(long long)jc * (g.nx + 1) + ic];
+    if (ba >= 0 && bc >= 0 && ba != bc) err[0] = 1;  // an edge joining two bodies
+    flag[e] = (ba >= 0) != (bc >= 0) ? 1 : 0;
+  }
+}
+
+// t in [0, 1) with |u + t v| = r (|u| <= r < |u + v|): the oracle's expression.
+__device__ __forceinline__ double edge_root(double ux, double uy, double vx, double vy, double r) {
+  const double vv = vx * vx + vy * vy;
+  const double uv = ux * vx + uy * vy;
+  const double uu = ux * ux + uy * uy;
+  return (-uv + sqrt(uv * uv - vv * (uu - r * r))) / vv;
+}
+
+__global__ void k_mx_cut(G g, const mfp_circle* __restrict__ circ, const int8_t* __restrict__ body,
+                         const int* __restrict__ flag, const int* __restrict__ off,
+                         int* __restrict__ hpt, int* __restrict__ vpt, double* __restrict__ pxy,
+                         int8_t* __restrict__ pbody, int* __restrict__ pedge, long long cap) {
+  const long long nh = g.nh(), ne = nh + g.nv();
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int k = flag[e] ? off[e] : -1;
+    if (e < nh)
+      hpt[e] = k;
+    else
+      vpt[e - nh] = k;
+    if (k < 0 || k >= cap) continue;
+    int ia, ja, ic, jc;
+    edge_ends(g, e, ia, ja, ic, jc);
+    const int ba = body[(long long)ja * (g.nx + 1) + ia];
+    const bool a_in = ba >= 0;
+    const int ii = a_in ? ia : ic, ji = a_in ? ja : jc;  // inside end
+    const int io = a_in ? ic : ia, jo = a_in ? jc : ja;  // fluid end
+    const int b = a_in ? ba : body[(long long)jc * (g.nx + 1) + ic];
+    const double xi = node_x(g, ii), yi = node_y(g, ji);
+    const double vx = node_x(g, io) - xi, vy = node_y(g, jo) - yi;
+    const double t = edge_root(xi - circ[b].cx, yi - circ[b].cy, vx, vy, circ[b].r);
+    pxy[2 * k] = xi + t * vx;
+    pxy[2 * k + 1] = yi + t * vy;
+    pbody[k] = (int8_t)b;
+    pedge[k] = (int)e;
+  }
+}
+
+// Displacement of an inside neighbour (in, jn) seen from a fluid node across edge e's
+// cut point k: P - X_in.
+__device__ __forceinline__ void cut_disp(const G& g, const double* __restrict__ pxy, int k, int in,
+                                         int jn, double& dx, double& dy) {
+  dx = pxy[2 * k] - node_x(g, in);
+  dy = pxy[2 * k + 1] - node_y(g, jn);
+}
+
+__global__ void k_mx_sweep(G g, double wx, double wy, const int8_t* __restrict__ body,
+                           const int* __restrict__ hpt, const int* __restrict__ vpt,
+                           const double* __restrict__ pxy, const double* __restrict__ din,
+                           double* __restrict__ dout) {
+  const long long nn = g.nn();
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(n / (g.nx + 1)), i = (int)(n - (long long)j * (g.nx + 1));
+    double ox = din[n], oy = din[n + nn];
+    if (body[n] < 0 && i > 0 && i < g.nx && j > 0 && j < g.ny) {
+      double ex, ey, wxx, wyy, nx_, ny_, sx, sy;
+      const long long nE = n + 1, nW = n - 1, nN = n + g.nx + 1, nS = n - g.nx - 1;
+      if (body[nE] >= 0)
+        cut_disp(g, pxy, hpt[(long long)j * g.nx + i], i + 1, j, ex, ey);
+      else {
+        ex = din[nE];
+        ey = din[nE + nn];
+      }
+      if (body[nW] >= 0)
+        cut_disp(g, pxy, hpt[(long long)j * g.nx + i - 1], i - 1, j, wxx, wyy);
+      else {
+        wxx = din[nW];
+        wyy = din[nW + nn];
+      }
+      if (body[nN] >= 0)
+        cut_disp(g, pxy, vpt[(long long)j * (g.nx + 1) + i], i, j + 1, nx_, ny_);
+      else {
+        nx_ = din[nN];
+        ny_ = din[nN + nn];
+      }
+      if (body[nS] >= 0)
+        cut_disp(g, pxy, vpt[(long long)(j - 1) * (g.nx + 1) + i], i, j - 1, sx, sy);
+      else {
+        sx = din[nS];
+        sy = din[nS + nn];
+      }
+      ox = wx * (ex + wxx) + wy * (nx_ + sx);
+      oy = wx * (ey + wyy) + wy * (ny_ + sy);
+    }
+    dout[n] = ox;
+    dout[n + nn] = oy;
+  }
+}
+
+// Cut point index of the edge from CCW corner k to corner k+1 of cell (i, j).
+__device__ __forceinline__ int cell_edge_point(const G& g, const int* __restrict__ hpt,
+                                               const int* __restrict__ vpt, int i, int j, int k) {
+  if (k == 0) return hpt[(long long)j * g.nx + i];
+  if (k == 1) return vpt[(long long)j * (g.nx + 1) + i + 1];
+  if (k == 2) return hpt[(long long)(j + 1) * g.nx + i];
+  return vpt[(long long)j * (g.nx + 1) + i];
+}
+
+// Elements of cell (i, j) (0, 1 or 2); with `out` non-null, their node lists.
+__device__ int cell_elements(const G& g, const int8_t* __restrict__ body,
+                             const int* __restrict__ hpt, const int* __restrict__ vpt,
+                             const double* __restrict__ pxy, int i, int j, int* err,
+                             int (*out)[4], int* nne) {
+  const long long nn = g.nn();
+  const long long c0 = (long long)j * (g.nx + 1) + i;
+  const long long ids[4] = {c0, c0 + 1, c0 + g.nx + 2, c0 + g.nx + 1};
+  int bb[4];
+  bool ins[4];
+  int nf = 0, bfirst = -1;
+  bool two = false;
+  for (int k = 0; k < 4; ++k) {
+    bb[k] = body[ids[k]];
+    ins[k] = bb[k] >= 0;
+    if (!ins[k]) ++nf;
+    if (ins[k]) {
+      if (bfirst < 0) bfirst = bb[k];
+      else if (bb[k] != bfirst) two = true;
+    }
+  }
+  if (nf == 4) {
+    if (out) {
+      for (int k = 0; k < 4; ++k) out[0][k] = (int)ids[k];
+      nne[0] = 4;
+    }
+    return 1;
+  }
+  if (two) {
+    if (err) err[1] = 1;
+    return 0;
+  }
+  if (nf == 0) return 0;
+  int changes = 0;
+  for (int k = 0; k < 4; ++k) changes += ins[k] != ins[(k + 1) & 3];
+  if (changes != 2) {
+    if (err) err[2] = 1;
+    return 0;
+  }
+  if (nf == 1) {
+    // triangle: the fluid corner and the cut points on its two edges, CCW from corner 0
+    int poly[3], np_ = 0;
+    int pts[2], npt = 0;
+    for (int k = 0; k < 4; ++k) {
+      if (!ins[k]) poly[np_++] = (int)ids[k];
+      if (ins[k] != ins[(k + 1) & 3]) {
+        const int q = cell_edge_point(g, hpt, vpt, i, j, k);
+        pts[npt++] = q;
+        poly[np_++] = (int)(nn + q);
+      }
+    }
+    const double hmax = g.hx > g.hy ? g.hx : g.hy;
+    const double gx = fabs(pxy[2 * pts[0]] - pxy[2 * pts[1]]);
+    const double gy = fabs(pxy[2 * pts[0] + 1] - pxy[2 * pts[1] + 1]);
+    const double gap = gx > gy ? gx : gy;
+    if (!(gap >= SLIVER * hmax)) return 0;  // a sliver (max-norm gap below 1e-12 h)
+    if (out) {
+      for (int k = 0; k < 3; ++k) out[0][k] = poly[k];
+      out[0][3] = -1;
+      nne[0] = 3;
+    }
+    return 1;
+  }
+  if (nf == 2) {
+    if (out) {
+      int np_ = 0;
+      for (int k = 0; k < 4; ++k) {
+        if (!ins[k]) out[0][np_++] = (int)ids[k];
+        if (ins[k] != ins[(k + 1) & 3])
+          out[0][np_++] = (int)(nn + cell_edge_point(g, hpt, vpt, i, j, k));
+      }
+      nne[0] = 4;
+    }
+    return 1;
+  }
+  // pentagon: split at the cut point after the inside corner
+  if (out) {
+    int kin = 0;
+    while (!ins[kin]) ++kin;
+    const int pa = (int)(nn + cell_edge_point(g, hpt, vpt, i, j, kin));
+    const int pb = (int)(nn + cell_edge_point(g, hpt, vpt, i, j, (kin + 3) & 3));
+    const int c1 = (int)ids[(kin + 1) & 3], c2 = (int)ids[(kin + 2) & 3], c3 = (int)ids[(kin + 3) & 3];
+    out[0][0] = pa;
+    out[0][1] = c1;
+    out[0][2] = c2;
+    out[0][3] = -1;
+    nne[0] = 3;
+    out[1][0] = pa;
+    out[1][1] = c2;
+    out[1][2] = c3;
+    out[1][3] = pb;
+    nne[1] = 4;
+  }
+  return 2;
+}
+
+__global__ void k_mx_cell_count(G g, const int8_t* __restrict__ body, const int* __restrict__ hpt,
+                                const int* __restrict__ vpt, const double* __restrict__ pxy,
+                                int* __restrict__ cnt, int* __restrict__ err) {
+  const long long nc = g.nc();
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < nc;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(c / g.nx), i = (int)(c - (long long)j * g.nx);
+    cnt[c] = cell_elements(g, body, hpt, vpt, pxy, i, j, err, nullptr, nullptr);
+  }
+}
+
+__global__ void k_mx_cells(G g, const int8_t* __restrict__ body, const int* __restrict__ hpt,
+                           const int* __restrict__ vpt, const double* __restrict__ pxy,
+                           const int* __restrict__ first, int* __restrict__ elem,
+                           int8_t* __restrict__ nne, long long cap) {
+  const long long nc = g.nc();
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < nc;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(c / g.nx), i = (int)(c - (long long)j * g.nx);
+    int out[2][4];
+    int nl[2];
+    const int m = cell_elements(g, body, hpt, vpt, pxy, i, j, nullptr, out, nl);
+    for (int q = 0; q < m; ++q) {
+      const long long e = (long long)first[c] + q;
+      if (e >= cap) break;
+      for (int k = 0; k < 4; ++k) elem[4 * e + k] = out[q][k];
+      nne[e] = (int8_t)nl[q];
+    }
+  }
+}
+
+// ---- element matrices and the apply ---------------------------------------------------
+__device__ __forceinline__ void node_xy(const G& g, const double* __restrict__ disp,
+                                        const double* __restrict__ pxy, long long n, double& x,
+                                        double& y) {
+  const long long nn = g.nn();
+  if (n < nn) {
+    const int j = (int)(n / (g.nx + 1)), i = (int)(n - (long long)j * (g.nx + 1));
+    x = node_x(g, i) + disp[n];
+    y = node_y(g, j) + disp[n + nn];
+  } else {
+    x = pxy[2 * (n - nn)];
+    y = pxy[2 * (n - nn) + 1];
+  }
+}
+
+}  // namespace mixed
+}  // namespace mfp
+
+#pragma clang fp contract(fast)
+
+namespace mfp {
+namespace mixed {
+
+// K_e of element e, row-major 4 x 4 (triangles: leading 3 x 3, rest zero).
+// Triangle (P1): K_ab = (b_a b_b + c_a c_b) / (4 A), b_a = y_(a+1) - y_(a+2),
+// c_a = x_(a+2) - x_(a+1), 2A = sum b_a x_a.  Quadrilateral (Q1, 2x2 Gauss, points
+// +-1/sqrt(3)): K_ab = sum_g det J (grad N_a . grad N_b).
+__global__ void k_mx_kmat(G g, long long ne, const int* __restrict__ elem,
+                          const int8_t* __restrict__ nne, const double* __restrict__ disp,
+                          const double* __restrict__ pxy, double* __restrict__ K) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < ne;
+       e += (long long)gridDim.x * blockDim.x) {
+    double x[4], y[4];
+    const int m = nne[e];
+    for (int a = 0; a < m; ++a) node_xy(g, disp, pxy, elem[4 * e + a], x[a], y[a]);
+    double k[16];
+    for (int q = 0; q < 16; ++q) k[q] = 0.0;
+    if (m == 3) {
+      double b[3], c[3];
+      for (int a = 0; a < 3; ++a) {
+        const int a1 = (a + 1) % 3, a2 = (a + 2) % 3;
+        b[a] = y[a1] - y[a2];
+        c[a] = x[a2] - x[a1];
+      }
+      const double twoA = b[0] * x[0] + b[1] * x[1] + b[2] * x[2];
+      const double s = 1.0 / (2.0 * twoA);
+      for (int a = 0; a < 3; ++a)
+        for (int d = 0; d < 3; ++d) k[4 * a + d] = (b[a] * b[d] + c[a] * c[d]) * s;
+    } else {
+      const double xa[4] = {-1.0, 1.0, 1.0, -1.0}, ea[4] = {-1.0, -1.0, 1.0, 1.0};
+      const double gp = 0.57735026918962576451;
+      for (int q = 0; q < 4; ++q) {
+        const double xi = xa[q] * gp, eta = ea[q] * gp;
+        double dxi[4], deta[4];
+        double j11 = 0, j12 = 0, j21 = 0, j22 = 0;
+        for (int a = 0; a < 4; ++a) {
+          dxi[a] = 0.25 * xa[a] * (1.0 + ea[a] * eta);
+          deta[a] = 0.25 * ea[a] * (1.0 + xa[a] * xi);
+          j11 += dxi[a] * x[a];
+          j12 += dxi[a] * y[a];
+          j21 += deta[a] * x[a];
+          j22 += deta[a] * y[a];
+        }
+        const double det = j11 * j22 - j12 * j21;
+        const double inv = 1.0 / det;
+        double gx[4], gy[4];
+        for (int a = 0; a < 4; ++a) {
+          gx[a] = (j22 * dxi[a] - j12 * deta[a]) * inv;
+          gy[a] = (-j21 * dxi[a] + j11 * deta[a]) * inv;
+        }
+        for (int a = 0; a < 4; ++a)
+          for (int d = 0; d < 4; ++d) k[4 * a + d] += det * (gx[a] * gx[d] + gy[a] * gy[d]);
+      }
+    }
+    for (int q = 0; q < 16; ++q) K[16 * e + q] = k[q];
+  }
+}
+
+// Cells around mixed node n (up to four, in a fixed order; -1 when absent).
+__device__ __forceinline__ void node_cells(const G& g, const int* __restrict__ pedge, long long n,
+                                           long long (&cells)[4]) {
+  const long long nn = g.nn();
+  for (int k = 0; k < 4; ++k) cells[k] = -1;
+  if (n < nn) {
+    const int j = (int)(n / (g.nx + 1)), i = (int)(n - (long long)j * (g.nx + 1));
+    int k = 0;
+    for (int cj = j - 1; cj <= j; ++cj)
+      for (int ci = i - 1; ci <= i; ++ci, ++k)
+        if (ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny) cells[k] = (long long)cj * g.nx + ci;
+  } else {
+    const long long e = pedge[n - nn];
+    int ia, ja, ic, jc;
+    edge_ends(g, e, ia, ja, ic, jc);
+    if (e < g.nh()) {  // horizontal edge: cells below and above
+      if (ja - 1 >= 0) cells[0] = (long long)(ja - 1) * g.nx + ia;
+      if (ja < g.ny) cells[1] = (long long)ja * g.nx + ia;
+    } else {           // vertical edge: cells left and right
+      if (ia - 1 >= 0) cells[0] = (long long)ja * g.nx + ia - 1;
+      if (ia < g.nx) cells[1] = (long long)ja * g.nx + ia;
+    }
+  }
+}
+
+// q[n] = (K p)[n] for every mixed node (nodes in no element: 0).
+__global__ void k_mx_apply(G g, long long ntot, const int* __restrict__ pedge,
+                           const int* __restrict__ first, const int* __restrict__ elem,
+                           const int8_t* __restrict__ nne, const double* __restrict__ K,
+                           const double* __restrict__ p, double* __restrict__ q) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
+       n += (long long)gridDim.x * blockDim.x) {
+    long long cells[4];
+    node_cells(g, pedge, n, cells);
+    double acc = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      if (cells[k] < 0) continue;
+      for (int e = first[cells[k]]; e < first[cells[k] + 1]; ++e) {
+        const int m = nne[e];
+        int a = -1;
+        for (int t = 0; t < m; ++t)
+          if (elem[4 * e + t] == n) a = t;
+        if (a < 0) continue;
+        double s = 0.0;
+        for (int t = 0; t < m; ++t) s += K[16 * e + 4 * a + t] * p[elem[4 * e + t]];
+        acc += s;
+      }
+    }
+    q[n] = acc;
+  }
+}
+
+}  // namespace mixed
+}  // namespace mfp
+
+// ---- constrained CG on the mixed mesh ----------------------------------------------------
+namespace mfp {
+namespace mixed {
+
+// Mixed-node tags: free fluid node, Dirichlet fluid node, unused (inside a body), or
+// TAG_B0 + b for the cut points of body b (one unknown psi_b each).
+enum : int8_t { MT_FREE = 0, MT_DIR = 1, MT_UNUSED = 2, MT_B0 = 3 };
+
+struct MixState {
+  double rr, rr0, rr_stop, alpha, beta, pq;
+  double xb[MFP_MAX_BODIES], rb[MFP_MAX_BODIES], pb[MFP_MAX_BODIES], qb[MFP_MAX_BODIES];
+  long long iters, kmax;
+  int done, pad_;
+};
+
+__device__ double mx_side_value(int code, double x, double y, double U, double cx, double cy,
+                                double a) {
+  if (code == MFP_BC_DIRICHLET_UY) return U * y;
+  if (code == MFP_BC_DIRICHLET_UX) return U * x;
+  if (code == MFP_BC_DIRICHLET_CYL || code == MFP_BC_DIRICHLET_CYLPHI) {
+    const double dx = x - cx, dy = y - cy;
+    const double k = a * a / (dx * dx + dy * dy);
+    return code == MFP_BC_DIRICHLET_CYL ? U * dy * (1.0 - k) : U * dx * (1.0 + k);
+  }
+  return 0.0;
+}
+
+struct TagArgs {
+  G g;
+  int bc[4];
+  double U, cx, cy, a;
+  long long npts;
+};
+
+// Whether background node n is a vertex of an element of one of its four cells.
+__device__ bool node_used(const G& g, const int* __restrict__ first, const int* __restrict__ elem,
+                          const int8_t* __restrict__ nne, long long n) {
+  long long cells[4];
+  node_cells(g, nullptr, n, cells);
+  for (int k = 0; k < 4; ++k) {
+    if (cells[k] < 0) continue;
+    for (int e = first[cells[k]]; e < first[cells[k] + 1]; ++e)
+      for (int t = 0; t < nne[e]; ++t)
+        if (elem[4 * e + t] == n) return true;
+  }
+  return false;
+}
+
+// Tags and lifting values: Dirichlet nodes are the fluid nodes of the Dirichlet
+// sides (bottom and top win at corners); fluid nodes in no element and inside nodes
+// are unused (value 0).
+__global__ void k_mx_tags(TagArgs t, const int8_t* __restrict__ body,
+                          const int8_t* __restrict__ pbody, const int* __restrict__ first,
+                          const int* __restrict__ elem, const int8_t* __restrict__ nne,
+                          int8_t* __restrict__ tag, double* __restrict__ gv) {
+  const G& g = t.g;
+  const long long nn = g.nn(), ntot = nn + t.npts;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
+       n += (long long)gridDim.x * blockDim.x) {
+    int8_t tg;
+    double v = 0.0;
+    if (n >= nn) {
+      tg = (int8_t)(MT_B0 + pbody[n - nn]);
+    } else if (body[n] >= 0) {
+      tg = MT_UNUSED;
+    } else {
+      const int j = (int)(n / (g.nx + 1)), i = (int)(n - (long long)j * (g.nx + 1));
+      const bool left = i == 0 && t.bc[0] != MFP_BC_NATURAL;
+      const bool right = i == g.nx && t.bc[1] != MFP_BC_NATURAL;
+      const bool bot = j == 0 && t.bc[2] != MFP_BC_NATURAL;
+      const bool top = j == g.ny && t.bc[3] != MFP_BC_NATURAL;
+      if (left || right || bot || top) {
+        tg = MT_DIR;
+        const int code = bot ? t.bc[2] : top ? t.bc[3] : left ? t.bc[0] : t.bc[1];
+        v = mx_side_value(code, node_x(g, i), node_y(g, j), t.U, t.cx, t.cy, t.a);
+      } else {
+        tg = node_used(g, first, elem, nne, n) ? MT_FREE : MT_UNUSED;
+      }
+    }
+    tag[n] = tg;
+    gv[n] = v;
+  }
+}
+
+// Block sums (fixed order): v over one block of 256 threads.
+__device__ __forceinline__ double mx_block_sum(double v, double* s) {
+  s[threadIdx.x] = v;
+  __syncthreads();
+  for (int off = MB / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double r = s[0];
+  __syncthreads();
+  return r;
+}
+
+// Per-block partials of p.q over free nodes and of q over each body's cut points:
+// part[blk * (1 + nb) + 0] and [.. + 1 + b].
+__global__ void k_mx_partials(long long ntot, int nb, const int8_t* __restrict__ tag,
+                              const double* __restrict__ p, const double* __restrict__ q,
+                              double* __restrict__ part, const MixState* st, int use_p) {
+  __shared__ double s[MB];
+  if (st && st->done) return;
+  double pq = 0.0;
+  double qb[MFP_MAX_BODIES];
+  for (int b = 0; b < nb; ++b) qb[b] = 0.0;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int8_t tg = tag[n];
+    if (tg == MT_FREE) pq += (use_p ? p[n] : q[n]) * q[n];
+    else if (tg >= MT_B0) qb[tg - MT_B0] += q[n];
+  }
+  const double t0 = mx_block_sum(pq, s);
+  if (threadIdx.x == 0) part[blockIdx.x * (1 + nb)] = t0;
+  for (int b = 0; b < nb; ++b) {
+    const double tb = mx_block_sum(qb[b], s);
+    if (threadIdx.x == 0) part[blockIdx.x * (1 + nb) + 1 + b] = tb;
+  }
+}
+
+// Single block: body sums of the partials into st->qb, and the sum of column 0.
+__device__ double mx_reduce(const double* __restrict__ part, int nblk, int nb, MixState* st,
+                            double* s) {
+  double t = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += MB) t += part[k * (1 + nb)];
+  const double tot = mx_block_sum(t, s);
+  for (int b = 0; b < nb; ++b) {
+    double u = 0.0;
+    for (int k = threadIdx.x; k < nblk; k += MB) u += part[k * (1 + nb) + 1 + b];
+    const double ub = mx_block_sum(u, s);
+    if (threadIdx.x == 0) st->qb[b] = ub;
+  }
+  return tot;
+}
+
+// Start: partials of the lifting's K g give r = -q (free) and rb = -sum q (bodies).
+__global__ void k_mx_start(long long ntot, int nb, const int8_t* __restrict__ tag,
+                           const double* __restrict__ q, double* __restrict__ r,
+                           double* __restrict__ p, double* __restrict__ x) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int8_t tg = tag[n];
+    const double v = tg == MT_FREE ? -q[n] : 0.0;
+    r[n] = v;
+    p[n] = v;
+    x[n] = 0.0;
+  }
+}
+
+__global__ void k_mx_start_state(const double* __restrict__ part, int nblk, int nb,
+                                 MixState* st, double rtol2, long long kmax) {
+  __shared__ double s[MB];
+  // r.r over free nodes (column 0 holds q.q there, r = -q) and the body residuals
+  const double rr_free = mx_reduce(part, nblk, nb, st, s);
+  if (threadIdx.x == 0) {
+    double rr = rr_free;
+    for (int b = 0; b < nb; ++b) {
+      const double v = -st->qb[b];
+      st->rb[b] = v;
+      st->pb[b] = v;
+      st->xb[b] = 0.0;
+      rr += v * v;
+    }
+    st->rr = rr;
+    st->rr0 = rr;
+    st->rr_stop = rtol2 * rr;
+    st->iters = 0;
+    st->kmax = kmax;
+    st->done = rr > 0.0 ? 0 : 1;
+  }
+}
+
+// p at the cut points from the body directions, zero at Dirichlet and unused nodes.
+__global__ void k_mx_bodies_to_p(long long ntot, const int8_t* __restrict__ tag,
+                                 double* __restrict__ p, const MixState* st) {
+  if (st->done) return;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int8_t tg = tag[n];
+    if (tg >= MT_B0) p[n] = st->pb[tg - MT_B0];
+    else if (tg != MT_FREE) p[n] = 0.0;
+  }
+}
+
+__global__ void k_mx_alpha(const double* __restrict__ part, int nblk, int nb, MixState* st) {
+  __shared__ double s[MB];
+  if (st->done) return;
+  const double pq_free = mx_reduce(part, nblk, nb, st, s);
+  if (threadIdx.x == 0) {
+    double pq = pq_free;
+    for (int b = 0; b < nb; ++b) pq += st->pb[b] * st->qb[b];
+    st->pq = pq;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+      st->done = 2;
+      return;
+    }
+    const double al = st->rr / pq;
+    st->alpha = al;
+    for (int b = 0; b < nb; ++b) {
+      st->xb[b] += al * st->pb[b];
+      st->rb[b] -= al * st->qb[b];
+    }
+  }
+}
+
+__global__ void k_mx_update(long long ntot, const int8_t* __restrict__ tag,
+                            const double* __restrict__ p, const double* __restrict__ q,
+                            double* __restrict__ x, double* __restrict__ r,
+                            double* __restrict__ part, const MixState* st) {
+  __shared__ double s[MB];
+  if (st->done) return;
+  const double al = st->alpha;
+  double rr = 0.0;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
+       n += (long long)gridDim.x * blockDim.x) {
+    if (tag[n] != MT_FREE) continue;
+    x[n] += al * p[n];
+    const double rv = r[n] - al * q[n];
+    r[n] = rv;
+    rr += rv * rv;
+  }
+  const double t = mx_block_sum(rr, s);
+  if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
+__global__ void k_mx_beta(const double* __restrict__ part, int nblk, int nb, MixState* st) {
+  __shared__ double s[MB];
+  if (st->done) return;
+  double t = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += MB) t += part[k];
+  const double rr_free = mx_block_sum(t, s);
+  if (threadIdx.x == 0) {
+    double rr = rr_free;
+    for (int b = 0; b < nb; ++b) rr += st->rb[b] * st->rb[b];
+    const double be = rr / st->rr;
+    st->beta = be;
+    st->rr = rr;
+    st->iters += 1;
+    for (int b = 0; b < nb; ++b) st->pb[b] = st->rb[b] + be * st->pb[b];
+    if (!isfinite(rr)) st->done = 2;
+    else if (rr <= st->rr_stop) st->done = 1;
+    else if (st->iters >= st->kmax) st->done = 3;
+  }
+}
+
+__global__ void k_mx_dir(long long ntot, const int8_t* __restrict__ tag,
+                         const double* __restrict__ r, double* __restrict__ p,
+                         const MixState* st) {
+  // runs once more after the stopping step: harmless (p is not used afterwards)
+  const double be = st->beta;
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int8_t tg = tag[n];
+    if (tg == MT_FREE) p[n] = r[n] + be * p[n];
+    else if (tg >= MT_B0) p[n] = st->pb[tg - MT_B0];
+    else p[n] = 0.0;
+  }
+}
+
+// psi over the mixed nodes: free x, Dirichlet g, cut points psi_b, unused 0.
+__global__ void k_mx_output(long long ntot, const int8_t* __restrict__ tag,
+                            const double* __restrict__ x,
+                            const double* __restrict__ gv, const MixState* st,
+                            double* __restrict__ psi) {
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
+       n += (long long)gridDim.x * blockDim.x) {
+    const int8_t tg = tag[n];
+    double v;
+    if (tg == MT_FREE) v = x[n];
+    else if (tg == MT_DIR) v = gv[n];
+    else if (tg >= MT_B0) v = st->xb[tg - MT_B0];
+    else v = 0.0;
+    psi[n] = v;
+  }
+}
+
+// ---- host side ---------------------------------------------------------------------------
+static G to_g(const mfp_grid& g) {
+  G d;
+  d.nx = g.nx;
+  d.ny = g.ny;
+  d.x0 = g.x0;
+  d.y0 = g.y0;
+  d.hx = grid_hx(g);
+  d.hy = grid_hy(g);
+  return d;
+}
+
+struct MeshWs {
+  int* eflag;       // nh + nv
+  int* eoff;        // nh + nv + 1
+  int* ccnt;        // nc
+  int* bsum;        // scan blocks + 1
+  double* pxy;      // 2 (nh + nv)
+  int8_t* pbody;    // nh + nv
+  int* pedge;       // nh + nv
+  int* elem;        // 4 * 2 nc
+  int8_t* nne;      // 2 nc
+  double* dtmp;     // 2 nn
+  mfp_circle* circ;
+  int* err;         // 4 flags
+};
+
+static size_t mesh_layout(const mfp_grid* gr, int nb, void* base, MeshWs* w) {
+  Bump bp(base);
+  const G g = to_g(*gr);
+  const long long ne = g.nh() + g.nv(), nc = g.nc();
+  MeshWs m{};
+  m.eflag = bp.take<int>(ne);
+  m.eoff = bp.take<int>(ne + 1);
+  m.ccnt = bp.take<int>(nc);
+  const long long mx = ne > nc ? ne : nc;
+  m.bsum = bp.take<int>(scan_blocks(mx) + 2);
+  m.pxy = bp.take<double>(2 * ne);
+  m.pbody = bp.take<int8_t>(ne);
+  m.pedge = bp.take<int>(ne);
+  m.elem = bp.take<int>(8 * nc);
+  m.nne = bp.take<int8_t>(2 * nc);
+  m.dtmp = bp.take<double>(2 * g.nn());
+  m.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
+  m.err = bp.take<int>(4);
+  if (w) *w = m;
+  return bp.off + 256;
+}
+
+}  // namespace mixed
+}  // namespace mfp
+
+using namespace mfp;
+using namespace mfp::mixed;
+
+extern "C" size_t mfp_mixed_workspace_size(const mfp_grid* grid, int32_t nbody) {
+  if (!grid || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES) return 0;
+  return mesh_layout(grid, nbody, nullptr, nullptr);
+}
+
+extern "C" int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                              int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
+                              void* stream_) {
+  clear_error();
+  MFP_TRY(check_geometry(grid, circles_h, nbody));
+  if (!m || !ws || !m->disp || !m->body || !m->hpt || !m->vpt || !m->cell_first ||
+      nsweeps < 0 || m->cap_points < 0 || m->cap_elems < 0 ||
+      (m->cap_points > 0 && (!m->pxy || !m->pbody || !m->pedge)) ||
+      (m->cap_elems > 0 && (!m->elem || !m->nne))) {
+    set_error("bad mesh arrays, capacities or nsweeps");
+    return MFP_E_ARG;
+  }
+  const size_t need = mesh_layout(grid, nbody, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  MeshWs w;
+  mesh_layout(grid, nbody, ws, &w);
+  const G g = to_g(*grid);
+  const long long nn = g.nn(), nh = g.nh(), ne = nh + g.nv(), nc = g.nc();
+  if (nbody > 0)
+    MFP_TRY_HIP(hipMemcpyAsync(w.circ, circles_h, sizeof(mfp_circle) * nbody,
+                               hipMemcpyHostToDevice, st));
+  MFP_TRY_HIP(hipMemsetAsync(w.err, 0, 4 * sizeof(int), st));
+  k_mx_classify<<<blocks_for(nn), MB, 0, st>>>(g, w.circ, nbody, m->body);
+  k_mx_edge_flags<<<blocks_for(ne), MB, 0, st>>>(g, m->body, w.eflag, w.err);
+  MFP_TRY_HIP(hipGetLastError());
+  MFP_TRY(exclusive_scan(w.eflag, ne, w.bsum, w.eoff, st));
+  k_mx_cut<<<blocks_for(ne), MB, 0, st>>>(g, w.circ, m->body, w.eflag, w.eoff, m->hpt, m->vpt,
+                                          w.pxy, w.pbody, w.pedge, ne);
+  MFP_TRY_HIP(hipGetLastError());
+  // sweeps, ping-pong between the caller's array and the workspace
+  MFP_TRY_HIP(hipMemsetAsync(m->disp, 0, sizeof(double) * 2 * nn, st));
+  const double hx = g.hx, hy = g.hy;
+  const double s = 2.0 * (hx * hx + hy * hy);
+  const double wx = (hy * hy) / s, wy = (hx * hx) / s;
+  double* a = m->disp;
+  double* b = w.dtmp;
+  for (int k = 0; k < nsweeps; ++k) {
+    k_mx_sweep<<<blocks_for(nn), MB, 0, st>>>(g, wx, wy, m->body, m->hpt, m->vpt, w.pxy, a, b);
+    double* t = a;
+    a = b;
+    b = t;
+  }
+  MFP_TRY_HIP(hipGetLastError());
+  if (a != m->disp)
+    MFP_TRY_HIP(hipMemcpyAsync(m->disp, a, sizeof(double) * 2 * nn, hipMemcpyDeviceToDevice, st));
+  k_mx_cell_count<<<blocks_for(nc), MB, 0, st>>>(g, m->body, m->hpt, m->vpt, w.pxy, w.ccnt, w.err);
+  MFP_TRY_HIP(hipGetLastError());
+  MFP_TRY(exclusive_scan(w.ccnt, nc, w.bsum, m->cell_first, st));
+  k_mx_cells<<<blocks_for(nc), MB, 0, st>>>(g, m->body, m->hpt, m->vpt, w.pxy, m->cell_first,
+                                            w.elem, w.nne, 2 * nc);
+  MFP_TRY_HIP(hipGetLastError());
+  int err[4];
+  int counts[2];
+  MFP_TRY_HIP(hipMemcpyAsync(err, w.err, sizeof(err), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipMemcpyAsync(&counts[0], w.eoff + ne, sizeof(int), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipMemcpyAsync(&counts[1], m->cell_first + nc, sizeof(int), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  if (err[0] || err[1] || err[2]) {
+    set_error(err[0] ? "a grid edge joins two bodies"
+                     : err[1] ? "a cell touches two bodies"
+                              : "inside and fluid corners alternate in a cell");
+    return MFP_E_GEOMETRY;
+  }
+  m->n_points = counts[0];
+  m->n_elems = counts[1];
+  const long long np_ = counts[0] < m->cap_points ? counts[0] : m->cap_points;
+  const long long nel = counts[1] < m->cap_elems ? counts[1] : m->cap_elems;
+  if (np_ > 0) {
+    MFP_TRY_HIP(hipMemcpyAsync(m->pxy, w.pxy, sizeof(double) * 2 * np_, hipMemcpyDeviceToDevice, st));
+    MFP_TRY_HIP(hipMemcpyAsync(m->pbody, w.pbody, np_, hipMemcpyDeviceToDevice, st));
+    MFP_TRY_HIP(hipMemcpyAsync(m->pedge, w.pedge, sizeof(int) * np_, hipMemcpyDeviceToDevice, st));
+  }
+  if (nel > 0) {
+    MFP_TRY_HIP(hipMemcpyAsync(m->elem, w.elem, sizeof(int) * 4 * nel, hipMemcpyDeviceToDevice, st));
+    MFP_TRY_HIP(hipMemcpyAsync(m->nne, w.nne, nel, hipMemcpyDeviceToDevice, st));
+  }
+  // triangles among the elements
+  std::vector<int8_t> hn((size_t)counts[1]);
+  if (counts[1] > 0)
+    MFP_TRY_HIP(hipMemcpyAsync(hn.data(), w.nne, hn.size(), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  long long ntri = 0;
+  for (int8_t v : hn) ntri += v == 3;
+  m->n_tri = ntri;
+  return MFP_OK;
+}
+
+namespace mfp {
+namespace mixed {
+
+struct SolveMx {
+  double* K;      // 16 per element
+  int8_t* tag;    // per mixed node
+  double *g, *x, *r, *p, *q;
+  double* part;   // partials
+  MixState* st;
+  int nblk;       // blocks of the reductions
+};
+
+static int red_blocks(long long n) {
+  long long b = (n + 8 * MB - 1) / (8 * MB);
+  if (b > 1024) b = 1024;
+  return (int)(b < 1 ? 1 : b);
+}
+
+static size_t solve_layout_mx(long long ntot, long long nel, int nb, void* base, SolveMx* out) {
+  Bump bp(base);
+  SolveMx s{};
+  s.K = bp.take<double>(16 * (size_t)nel);
+  s.tag = bp.take<int8_t>(ntot);
+  s.g = bp.take<double>(ntot);
+  s.x = bp.take<double>(ntot);
+  s.r = bp.take<double>(ntot);
+  s.p = bp.take<double>(ntot);
+  s.q = bp.take<double>(ntot);
+  s.nblk = red_blocks(ntot);
+  s.part = bp.take<double>((size_t)s.nblk * (1 + (nb > 0 ? nb : 1)));
+  s.st = bp.take<MixState>(1);
+  if (out) *out = s;
+  return bp.off + 256;
+}
+
+static int check_mesh_arg(const mfp_grid* grid, const mfp_mixed_mesh_t* m) {
+  MFP_TRY(check_grid(grid));
+  if (!m || !m->disp || !m->body || !m->cell_first || m->n_points < 0 || m->n_elems < 0 ||
+      m->n_points > m->cap_points || m->n_elems > m->cap_elems ||
+      (m->n_points > 0 && (!m->pxy || !m->pbody || !m->pedge)) ||
+      (m->n_elems > 0 && (!m->elem || !m->nne))) {
+    set_error("mixed mesh arrays missing or counts above their capacities");
+    return MFP_E_ARG;
+  }
+  return MFP_OK;
+}
+
+static void launch_kmat(const G& g, const mfp_mixed_mesh_t* m, double* K, hipStream_t st) {
+  k_mx_kmat<<<blocks_for(m->n_elems), MB, 0, st>>>(g, m->n_elems, m->elem, m->nne, m->disp,
+                                                     m->pxy, K);
+}
+
+static void launch_apply_mx(const G& g, const mfp_mixed_mesh_t* m, const double* K,
+                            const double* p, double* q, hipStream_t st) {
+  const long long ntot = g.nn() + m->n_points;
+  k_mx_apply<<<blocks_for(ntot), MB, 0, st>>>(g, ntot, m->pedge, m->cell_first, m->elem, m->nne,
+                                               K, p, q);
+}
+
+}  // namespace mixed
+}  // namespace mfp
+
+extern "C" size_t mfp_mixed_solve_workspace_size(const mfp_grid* grid, int64_t n_points,
+                                                 int64_t n_elems, int32_t nbody) {
+  if (!grid || grid->nx < 2 || grid->ny < 2 || n_points < 0 || n_elems < 0 || nbody < 0 ||
+      nbody > MFP_MAX_BODIES)
+    return 0;
+  const G g = to_g(*grid);
+  return solve_layout_mx(g.nn() + n_points, n_elems, nbody, nullptr, nullptr);
+}
+
+extern "C" int mfp_mixed_element_apply(const mfp_grid* grid, const mfp_mixed_mesh_t* m,
+                                       const double* p, double* q, int32_t repeat,
+                                       double* apply_ms_h, void* ws, size_t ws_bytes,
+                                       void* stream_) {
+  clear_error();
+  MFP_TRY(check_mesh_arg(grid, m));
+  if (!p || !q || !ws || repeat < 1) {
+    set_error("NULL pointer or repeat < 1");
+    return MFP_E_ARG;
+  }
+  const G g = to_g(*grid);
+  const size_t need = solve_layout_mx(g.nn() + m->n_points, m->n_elems, 0, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  SolveMx s;
+  solve_layout_mx(g.nn() + m->n_points, m->n_elems, 0, ws, &s);
+  launch_kmat(g, m, s.K, st);
+  MFP_TRY_HIP(hipGetLastError());
+  hipEvent_t e0, e1;
+  MFP_TRY_HIP(hipEventCreate(&e0));
+  MFP_TRY_HIP(hipEventCreate(&e1));
+  MFP_TRY_HIP(hipEventRecord(e0, st));
+  for (int k = 0; k < repeat; ++k) launch_apply_mx(g, m, s.K, p, q, st);
+  MFP_TRY_HIP(hipEventRecord(e1, st));
+  const hipError_t le = hipGetLastError();
+  float ms = 0.f;
+  hipError_t se = hipEventSynchronize(e1);
+  if (se == hipSuccess) se = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (le != hipSuccess || se != hipSuccess) {
+    set_error("mixed apply: %s", hipGetErrorString(le != hipSuccess ? le : se));
+    return MFP_E_HIP;
+  }
+  if (apply_ms_h) *apply_ms_h = ms / repeat;
+  return MFP_OK;
+}
+
+extern "C" int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h,
+                                   int32_t nbody, const mfp_mixed_mesh_t* m,
+                                   const mfp_flow* flow, const mfp_solver_opts* opts,
+                                   int32_t pair_lo, int32_t pair_hi, double* psi,
+                                   double* psi_b_h, double* Q_h, double* copfi_h,
+                                   mfp_stats* stats_h, void* ws, size_t ws_bytes,
+                                   void* stream_) {
+  clear_error();
+  MFP_TRY(check_geometry(grid, circles_h, nbody));
+  MFP_TRY(check_mesh_arg(grid, m));
+  if (!flow || !opts || !psi || !ws || (nbody > 0 && !psi_b_h)) {
+    set_error("NULL argument");
+    return MFP_E_ARG;
+  }
+  if (!std::isfinite(flow->U) || !(opts->rtol > 0.0) || opts->kmax < 1 ||
+      opts->precision != MFP_FP64 || pair_lo >= nbody || pair_hi >= nbody) {
+    set_error("U finite, rtol > 0, kmax >= 1, MFP_FP64 and pair indices below nbody");
+    return MFP_E_ARG;
+  }
+  for (int k = 0; k < 4; ++k)
+    if (flow->side_bc[k] < MFP_BC_NATURAL || flow->side_bc[k] > MFP_BC_DIRICHLET_CYLPHI) {
+      set_error("invalid side boundary code");
+      return MFP_E_ARG;
+    }
+  const G g = to_g(*grid);
+  const long long nn = g.nn(), ntot = nn + m->n_points;
+  const size_t need = solve_layout_mx(ntot, m->n_elems, nbody, nullptr, nullptr);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  SolveMx s;
+  solve_layout_mx(ntot, m->n_elems, nbody, ws, &s);
+  const int nb = nbody;
+  TagArgs ta{};
+  ta.g = g;
+  for (int k = 0; k < 4; ++k) ta.bc[k] = flow->side_bc[k];
+  ta.U = flow->U;
+  if (nbody > 0) {
+    ta.cx = circles_h[0].cx;
+    ta.cy = circles_h[0].cy;
+    ta.a = circles_h[0].r;
+  }
+  ta.npts = m->n_points;
+  const int GB = blocks_for(ntot);
+  k_mx_tags<<<GB, MB, 0, st>>>(ta, m->body, m->pbody, m->cell_first, m->elem, m->nne, s.tag,
+                               s.g);
+  launch_kmat(g, m, s.K, st);
+  // r = -K g at free nodes, rb = -sum of K g over each body's cut points
+  launch_apply_mx(g, m, s.K, s.g, s.q, st);
+  k_mx_partials<<<s.nblk, MB, 0, st>>>(ntot, nb, s.tag, s.q, s.q, s.part, nullptr, 0);
+  k_mx_start<<<GB, MB, 0, st>>>(ntot, nb, s.tag, s.q, s.r, s.p, s.x);
+  k_mx_start_state<<<1, MB, 0, st>>>(s.part, s.nblk, nb, s.st, opts->rtol * opts->rtol,
+                                     opts->kmax);
+  k_mx_bodies_to_p<<<GB, MB, 0, st>>>(ntot, s.tag, s.p, s.st);
+  MFP_TRY_HIP(hipGetLastError());
+  hipEvent_t e0, e1;
+  MFP_TRY_HIP(hipEventCreate(&e0));
+  MFP_TRY_HIP(hipEventCreate(&e1));
+  MFP_TRY_HIP(hipEventRecord(e0, st));
+  const int every = opts->check_every > 0 ? opts->check_every : 32;
+  int done = 0;
+  long long launched = 0;
+  while (true) {
+    for (int k = 0; k < every; ++k) {
+      launch_apply_mx(g, m, s.K, s.p, s.q, st);
+      k_mx_partials<<<s.nblk, MB, 0, st>>>(ntot, nb, s.tag, s.p, s.q, s.part, s.st, 1);
+      k_mx_alpha<<<1, MB, 0, st>>>(s.part, s.nblk, nb, s.st);
+      k_mx_update<<<s.nblk, MB, 0, st>>>(ntot, s.tag, s.p, s.q, s.x, s.r, s.part, s.st);
+      k_mx_beta<<<1, MB, 0, st>>>(s.part, s.nblk, nb, s.st);
+      k_mx_dir<<<GB, MB, 0, st>>>(ntot, s.tag, s.r, s.p, s.st);
+    }
+    launched += every;
+    MFP_TRY_HIP(hipGetLastError());
+    MFP_TRY_HIP(hipMemcpyAsync(&done, &s.st->done, sizeof(int), hipMemcpyDeviceToHost, st));
+    MFP_TRY_HIP(hipStreamSynchronize(st));
+    if (done || launched > opts->kmax + every) break;
+  }
+  MFP_TRY_HIP(hipEventRecord(e1, st));
+  // output and the true residual from it
+  k_mx_output<<<GB, MB, 0, st>>>(ntot, s.tag, s.x, s.g, s.st, psi);
+  launch_apply_mx(g, m, s.K, psi, s.q, st);
+  k_mx_partials<<<s.nblk, MB, 0, st>>>(ntot, nb, s.tag, s.q, s.q, s.part, nullptr, 0);
+  MFP_TRY_HIP(hipGetLastError());
+  MixState hs;
+  std::vector<double> part((size_t)s.nblk * (1 + (nb > 0 ? nb : 1)));
+  MFP_TRY_HIP(hipMemcpyAsync(&hs, s.st, sizeof(MixState), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipMemcpyAsync(part.data(), s.part, sizeof(double) * part.size(),
+                             hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipEventSynchronize(e1));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  double rr = 0.0;
+  for (int k = 0; k < s.nblk; ++k) rr += part[(size_t)k * (1 + nb)];
+  for (int b = 0; b < nb; ++b) {
+    double qb = 0.0;
+    for (int k = 0; k < s.nblk; ++k) qb += part[(size_t)k * (1 + nb) + 1 + b];
+    rr += qb * qb;
+  }
+  for (int b = 0; b < nb; ++b) psi_b_h[b] = hs.xb[b];
+  if (pair_lo >= 0 && pair_hi >= 0) {
+    const double Q = hs.xb[pair_hi] - hs.xb[pair_lo];
+    if (Q_h) *Q_h = Q;
+    if (copfi_h) *copfi_h = Q / (flow->U * (circles_h[pair_hi].cy - circles_h[pair_lo].cy));
+  }
+  if (stats_h) {
+    std::vector<int8_t> tg((size_t)ntot);
+    MFP_TRY_HIP(hipMemcpy(tg.data(), s.tag, tg.size(), hipMemcpyDeviceToHost));
+    long long nfree = 0;
+    for (int8_t v : tg) nfree += v == MT_FREE;
+    std::memset(stats_h, 0, sizeof(*stats_h));
+    stats_h->iters = hs.iters;
+    stats_h->applies = hs.iters + 2;
+    stats_h->n_free = nfree;
+    stats_h->n_dof = nfree + nb;
+    stats_h->rnorm0 = std::sqrt(hs.rr0);
+    stats_h->relres_true = hs.rr0 > 0 ? std::sqrt(rr / hs.rr0) : 0.0;
+    stats_h->solve_ms = ms;
+  }
+  if (hs.done == 2) {
+    set_error("CG breakdown (p.Ap <= 0 or non-finite)");
+    return MFP_E_BREAKDOWN;
+  }
+  if (hs.done != 1) {
+    set_error("kmax reached before the tolerance");
+    return MFP_W_NOCONV;
+  }
+  return MFP_OK;
+}

@@ -143,6 +143,24 @@ def test_pentagon_split_rule():
     assert list(mm.elem_nodes[els[1]]) == [pa, c2, c3, pb]
 
 
+def test_element_matrix_rounding():
+    """The FP64 element matrices against the same integrals in extended precision:
+    within 1e-13 of the element's largest entry (the bar the GPU apply is held to
+    rests on this)."""
+    case = W.five_cylinders_asymmetric(120, 60, extent=(-6, 6, -3, 3))
+    mm = M.mixed_mesh(case.grid, case.circles, 200)
+    K = M.element_matrices(mm)
+    x, y = mm.coords()
+    xl, yl = x.astype(np.longdouble), y.astype(np.longdouble)
+    quad = mm.elem_nne == 4
+    n4 = mm.elem_nodes[quad]
+    Kl = O.element_stiffness(xl[n4], yl[n4])
+    me = np.abs(K[quad]).max(axis=(1, 2))
+    rel = (np.abs(K[quad] - Kl).max(axis=(1, 2)) / me).astype(float)
+    assert rel.max() < 1e-13
+    assert rel.max() > 0.0  # extended precision really was used
+
+
 def test_dense_elementwise_assembly_and_solve():
     """A tiny mesh: the reduced matrix assembled element by element into a dense
     array (written out here, no sparse code) and solved with numpy gives the same
