@@ -466,9 +466,10 @@ int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nb
                    void* stream);
 
 /* Workspace bytes for mfp_mixed_element_apply / mfp_mixed_psi_solve on a mixed mesh of
- * n_points cut points and n_elems elements. */
+ * n_points cut points and n_elems elements with these solver options (NULL: FP64 and
+ * the automatic schedule); 0 for invalid arguments. */
 size_t mfp_mixed_solve_workspace_size(const mfp_grid* grid, int64_t n_points, int64_t n_elems,
-                                      int32_t nbody);
+                                      int32_t nbody, const mfp_solver_opts* opts);
 
 /* q = K p on the mixed mesh (section "Weak formulation": P1 triangles exactly, Q1
  * quadrilaterals with 2x2 Gauss points, summed over the elements), p and q device
@@ -482,17 +483,19 @@ int mfp_mixed_element_apply(const mfp_grid* grid, const mfp_mixed_mesh_t* m, con
                             double* q, int32_t repeat, double* apply_ms_h, void* ws,
                             size_t ws_bytes, void* stream);
 
-/* Constrained stream-function solve on the mixed mesh (Algorithm 1, FP64 only): the
- * unknowns are the fluid nodes of some element that lie on no Dirichlet side, plus one
- * psi_b per body shared by all its cut points; Dirichlet sides as in mfp_psi_solve.
- * CG on A y = b, A = T^T K T, b = -T^T K g, to ||r|| <= rtol ||b||, with the scalars
- * kept on the device (the host reads the stop flag every opts->check_every
- * iterations, 32 if 0).  psi: device double[(nx+1)(ny+1) + n_points]: the free
- * values, the Dirichlet values, psi_b at the cut points and 0 at unused nodes (inside
- * nodes, fluid nodes in no element).  psi_b_h, Q_h, copfi_h, stats_h as in
- * mfp_psi_solve (stats: iters, applies, n_free, n_dof, rnorm0, relres_true,
- * solve_ms).  Other opts fields are ignored.  Returns MFP_W_NOCONV, MFP_E_BREAKDOWN
- * as mfp_psi_solve; MFP_E_ARG for a precision other than MFP_FP64. */
+/* Constrained stream-function solve on the mixed mesh (Algorithm 1): the unknowns are
+ * the fluid nodes on no Dirichlet side plus one psi_b per body, shared by all its cut
+ * points; Dirichlet sides as in mfp_psi_solve.  A y = b with A = T^T K T, b = -T^T K g.
+ * Every element lies in one grid cell and the inside corners of a cut cell are tied
+ * to the same psi_b as its cut points, so A is also the sum of 4 x 4 corner matrices,
+ * one per cell (a cut cell's elements condensed onto its corners): the solve runs the
+ * one-kernel CG of mfp_psi_solve on those matrices as stored element entries, with the
+ * same options (precisions MFP_FP64, MFP_FP32, MFP_FP32_IR; tolerance, schedule fields
+ * except element_mode, which is always the stored form; no warm start: psi0 must be
+ * NULL) and the same statistics (n_free counts every fluid node off the Dirichlet
+ * sides).  psi: device double[(nx+1)(ny+1) + n_points]: free values, Dirichlet values,
+ * psi_b at the cut points and 0 at the inside nodes.  psi_b_h, Q_h, copfi_h, stats_h
+ * as in mfp_psi_solve.  Synchronises `stream`.  Returns as mfp_psi_solve. */
 int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
                         const mfp_mixed_mesh_t* m, const mfp_flow* flow,
                         const mfp_solver_opts* opts, int32_t pair_lo, int32_t pair_hi,

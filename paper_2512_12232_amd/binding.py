@@ -171,7 +171,8 @@ def load(path: str = LIB_PATH):
     lib.mfp_mixed_mesh.argtypes = [POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_int32,
                                    POINTER(MfpMixedMesh), c_void_p, c_size_t, c_void_p]
     lib.mfp_mixed_solve_workspace_size.restype = c_size_t
-    lib.mfp_mixed_solve_workspace_size.argtypes = [POINTER(MfpGrid), c_int64, c_int64, c_int32]
+    lib.mfp_mixed_solve_workspace_size.argtypes = [POINTER(MfpGrid), c_int64, c_int64, c_int32,
+                                                   POINTER(MfpSolverOpts)]
     lib.mfp_mixed_element_apply.argtypes = [POINTER(MfpGrid), POINTER(MfpMixedMesh), c_void_p,
                                             c_void_p, c_int32, POINTER(c_double), c_void_p,
                                             c_size_t, c_void_p]
@@ -614,8 +615,8 @@ def mixed_element_apply(mm: MixedMesh, p: torch.Tensor, repeat: int = 1):
         raise ValueError(f"p has {p.numel()} values, the mesh {mm.n_nodes} nodes")
     q = torch.empty_like(p)
     m = mm.c_struct()
-    ws = workspace(lib.mfp_mixed_solve_workspace_size(byref(g), mm.n_points, mm.n_elems, 0),
-                   p.device)
+    ws = workspace(lib.mfp_mixed_solve_workspace_size(byref(g), mm.n_points, mm.n_elems, 0,
+                                                      None), p.device)
     ms = c_double(0.0)
     _check(lib.mfp_mixed_element_apply(byref(g), byref(m), _ptr(p), _ptr(q), int(repeat),
                                        byref(ms), _ptr(ws), ws.numel(), _stream()))
@@ -632,14 +633,17 @@ class MixedSolveResult:
     status: int
 
 
-def mixed_psi_solve(mm: MixedMesh, flow, *, rtol=1e-12, kmax=10 ** 7, check_every=32,
-                    pair=(-1, -1), allow_warn: bool = True) -> MixedSolveResult:
+def mixed_psi_solve(mm: MixedMesh, flow, *, precision="fp64", rtol=1e-12, kmax=10 ** 7,
+                    check_every=16, inner_rtol=0.1, max_outer=1000, pair=(-1, -1),
+                    estimate_kappa: bool = False, schedule: Optional[dict] = None,
+                    allow_warn: bool = True) -> MixedSolveResult:
     lib = load()
     g = make_grid(mm.grid)
     c = make_circles(mm.circles)
     nb = len(mm.circles)
     f = make_flow(flow)
-    o = _opts("fp64", rtol, kmax, check_every, 0.1, 1000)
+    o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa,
+              schedule)
     dev = mm.disp.device
     psi = torch.empty(mm.n_nodes, dtype=torch.float64, device=dev)
     psib = (c_double * max(nb, 1))()
@@ -647,8 +651,8 @@ def mixed_psi_solve(mm: MixedMesh, flow, *, rtol=1e-12, kmax=10 ** 7, check_ever
     cop = c_double(float("nan"))
     st = MfpStats()
     m = mm.c_struct()
-    ws = workspace(lib.mfp_mixed_solve_workspace_size(byref(g), mm.n_points, mm.n_elems, nb),
-                   dev)
+    ws = workspace(lib.mfp_mixed_solve_workspace_size(byref(g), mm.n_points, mm.n_elems, nb,
+                                                      byref(o)), dev)
     status = _check(lib.mfp_mixed_psi_solve(
         byref(g), c, nb, byref(m), byref(f), byref(o), int(pair[0]), int(pair[1]), _ptr(psi),
         psib, byref(Q), byref(cop), byref(st), _ptr(ws), ws.numel(), _stream()), allow_warn)

@@ -18,46 +18,9 @@
 #include <hip/hip_ext.h>
 
 #include "mfp_internal.h"
+#include "reduce.h"
 
 namespace mfp {
-
-// A double moved across lanes by one DPP pattern (lanes of rows outside ROWS get 0).
-template <int CTRL, int ROWS>
-__device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xf, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xf, false);
-  return __hiloint2double(hi, lo);
-}
-
-// Sum over the wavefront; every lane receives the same total.  All 64 lanes must be
-// active.  DPP steps within each row of 16 lanes (quad swaps, half-row and row
-// mirrors: every lane then holds its row's sum), then the row sums are combined
-// towards lane 63 with the row broadcasts, (r0 + r1) + (r2 + r3), and lane 63's value
-// is read out.  A fixed order, so results are reproducible; each step is a register
-// move instead of the round trip through the LDS crossbar that a shuffle takes.
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_move<0xB1, 0xf>(v);   // quad_perm [1, 0, 3, 2]
-  v += dpp_move<0x4E, 0xf>(v);   // quad_perm [2, 3, 0, 1]
-  v += dpp_move<0x141, 0xf>(v);  // row_half_mirror
-  v += dpp_move<0x140, 0xf>(v);  // row_mirror
-  v += dpp_move<0x142, 0xa>(v);  // row_bcast:15 into rows 1 and 3
-  v += dpp_move<0x143, 0xc>(v);  // row_bcast:31 into rows 2 and 3
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  return __hiloint2double(hi, lo);
-}
-
-// Sum over a 256-thread block; every thread receives the total.  Fixed reduction
-// order, so results are reproducible run to run.
-__device__ __forceinline__ double block_sum(double v, double* s_red) {
-  v = wave_sum(v);
-  const int tid = threadIdx.x;
-  __syncthreads();
-  if ((tid & 63) == 0) s_red[tid >> 6] = v;
-  __syncthreads();
-  const double t = (s_red[0] + s_red[1]) + (s_red[2] + s_red[3]);
-  return t;
-}
 
 template <typename T>
 __device__ __forceinline__ T fast_rcp(T x);
@@ -343,6 +306,35 @@ __global__ void __launch_bounds__(256) k_elem_coef(Layout L, double ry,
   }
 }
 
+// Element entries of every geometry task copied from a per-cell table of six entries
+// per cell, entry-major (tab[e nx ny + j nx + i] for cell (i, j), corners counter-
+// clockwise from node (i, j)): for meshes whose cells are not plain bilinear
+// quadrilaterals of the displaced nodes.  Lane c's cell lies between its node column
+// and the next lane's; lanes and rows without a cell of the grid get zeros.
+template <typename T, int HC>
+__global__ void __launch_bounds__(256) k_cells_to_slab(Layout L, const double* __restrict__ tab,
+                                                       const int* __restrict__ tgeo,
+                                                       T* __restrict__ kcoef) {
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (t >= L.ntasks()) return;
+  const int s = tgeo[t];
+  if (s < 0) return;  // uniform over the wavefront
+  const int m = t % L.nstrip, kc = t / L.nstrip;
+  const int ci = column_node(m * 64 + lane + halo_shift(lane, m, L.nstrip));
+  const bool col_ok = lane < 63 && ci >= 0 && ci < L.nx;
+  const long long nc = (long long)L.nx * L.ny;
+  T* out = kcoef + (size_t)s * kslab<HC>();
+  for (int sr = 0; sr <= HC; ++sr) {
+    const int cj = kc * HC + sr - 1;
+    const bool ok = col_ok && cj >= 0 && cj < L.ny;
+    const long long c = ok ? (long long)cj * L.nx + ci : 0;
+#pragma unroll
+    for (int e = 0; e < KCOEF; ++e)
+      out[(sr * KCOEF + e) * 64 + lane] = ok ? (T)tab[e * nc + c] : (T)0;
+  }
+}
+
 // Slabs for the geometry tasks, numbered in task order (single block).
 __global__ void k_assign_geo(int ntiles, const uint8_t* __restrict__ tplain,
                              int* __restrict__ tgeo, int* __restrict__ ngeo) {
@@ -406,6 +398,8 @@ struct ApplyArgs {
   T ry;                          // hy / hx
   int G;                         // blocks of this apply (batched launches)
   const int* skip;               // return at once when *skip != 0
+  const T* kcoef;                // non-null: geometry tasks read stored element entries
+  const int* tgeo;               // per task: its slab of kcoef, -1 for constant-stencil tasks
 };
 
 // q = K src, with per-block partials of src.q over free nodes and per-slot body sums.
@@ -513,6 +507,14 @@ __device__ __forceinline__ void apply_core(const ApplyArgs<T>& a, const int vblk
       const bool bm = !plain && ((body_mask >> it) & 1ull);
       if (plain) {
         stencil_task<T, HC>(a.cC, a.cE, a.cN, a.cD, v, qr);
+      } else if (a.kcoef) {
+        T kcv[HC + 1][KCOEF];
+        const T* kb = a.kcoef + (size_t)a.tgeo[kc * nstrip + m] * kslab<HC>() + lane;
+#pragma unroll
+        for (int r = 0; r <= HC; ++r)
+#pragma unroll
+          for (int e = 0; e < KCOEF; ++e) kcv[r][e] = kb[(r * KCOEF + e) * 64];
+        march_task_stored<T, HC>(v, kcv, qr);
       } else {
         march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
       }

@@ -45,6 +45,20 @@ struct Box {
 Box circle_box(const mfp_grid& g, const mfp_circle& c, int pad, int ilo, int ihi, int jlo,
                int jhi);
 
+// ---- constrained solve with caller-given element entries (solve.hip) ---------------
+// The single-system solve (as mfp_psi_solve, FP64, FP32 or FP32 + FP64 refinement) on
+// an operator given cell by cell: cellcoef holds, entry-major, the six off-diagonal
+// entries (k01, k02, k03, k12, k13, k23) of each cell's 4 x 4 matrix in the corner
+// order (i, j), (i+1, j), (i+1, j+1), (i, j+1), rows summing to zero.  Nodes with
+// body[n] = b >= 0 are tied to psi_b; psi receives the background-node values (tied
+// nodes psi_b).  disp only marks the cells that are not plain rectangles.
+size_t psi_solve_cells_workspace(const mfp_grid* grid, int nbody, const mfp_solver_opts* opts);
+int psi_solve_cells(const mfp_grid* grid, const mfp_circle* circles_h, int nbody,
+                    const double* disp, const int8_t* body, const double* cellcoef,
+                    const mfp_flow* flow, const mfp_solver_opts* opts, int pair_lo,
+                    int pair_hi, double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
+                    mfp_stats* stats_h, void* ws, size_t ws_bytes, hipStream_t st);
+
 // ---- workspace bump allocator ----------------------------------------------------
 struct Bump {
   char* base;     // may be nullptr when only measuring

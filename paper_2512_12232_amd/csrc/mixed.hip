@@ -34,6 +34,7 @@
 #include <vector>
 
 #include "mfp_internal.h"
+#include "reduce.h"
 
 #pragma clang fp contract(off)
 
@@ -523,310 +524,200 @@ __device__ __forceinline__ void node_cells(const G& g, const int* __restrict__ p
   }
 }
 
-// q[n] = (K p)[n] for every mixed node (nodes in no element: 0).
-__global__ void k_mx_apply(G g, long long ntot, const int* __restrict__ pedge,
-                           const int* __restrict__ first, const int* __restrict__ elem,
-                           const int8_t* __restrict__ nne, const double* __restrict__ K,
-                           const double* __restrict__ p, double* __restrict__ q) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
-       n += (long long)gridDim.x * blockDim.x) {
-    long long cells[4];
-    node_cells(g, pedge, n, cells);
-    double acc = 0.0;
-    for (int k = 0; k < 4; ++k) {
-      if (cells[k] < 0) continue;
-      for (int e = first[cells[k]]; e < first[cells[k] + 1]; ++e) {
+// Cell kinds for the product: no element (inside a body), the plain quadrilateral
+// of a cell with four fluid corners (its six distinct off-diagonal entries stored),
+// or a cut cell (its elements' full matrices read through the element lists).
+enum : int8_t { CK_NONE = 0, CK_QUAD = 1, CK_CUT = 2 };
+
+// Index of the off-diagonal entry (a, b) of a quadrilateral among its six.
+__device__ __forceinline__ int pair_index(int a, int b) {
+  const int lo = a < b ? a : b, hi = a < b ? b : a;
+  return lo == 0 ? hi - 1 : lo == 1 ? hi + 1 : 5;
+}
+
+__global__ void k_mx_cellcoef(G g, const int8_t* __restrict__ body, const int* __restrict__ first,
+                              const int* __restrict__ elem, const int8_t* __restrict__ nne,
+                              const double* __restrict__ K, int8_t* __restrict__ ckind,
+                              double* __restrict__ kc) {
+  const long long nc = g.nc(), nn = g.nn();
+  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < nc;
+       c += (long long)gridDim.x * blockDim.x) {
+    const int e0 = first[c], e1 = first[c + 1];
+    int8_t kind = CK_NONE;
+    if (e1 - e0 == 1 && nne[e0] == 4 && elem[4 * e0] < nn && elem[4 * e0 + 1] < nn &&
+        elem[4 * e0 + 2] < nn && elem[4 * e0 + 3] < nn)
+      kind = CK_QUAD;
+    else if (e1 > e0)
+      kind = CK_CUT;
+    ckind[c] = kind;
+    double k[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (kind == CK_QUAD) {
+      const double* ke = K + 16 * (long long)e0;
+      k[0] = ke[1];
+      k[1] = ke[2];
+      k[2] = ke[3];
+      k[3] = ke[6];
+      k[4] = ke[7];
+      k[5] = ke[11];
+    } else if (kind == CK_CUT) {
+      // the cell's matrix on its four corners: a cut point (value psi_b) goes to the
+      // first inside corner, since every inside corner carries psi_b too
+      const int j = (int)(c / g.nx), i = (int)(c - (long long)j * g.nx);
+      const long long c0 = (long long)j * (g.nx + 1) + i;
+      const long long ids[4] = {c0, c0 + 1, c0 + g.nx + 2, c0 + g.nx + 1};
+      int kin = 0;
+      while (kin < 3 && body[ids[kin]] < 0) ++kin;
+      for (int e = e0; e < e1; ++e) {
         const int m = nne[e];
-        int a = -1;
-        for (int t = 0; t < m; ++t)
-          if (elem[4 * e + t] == n) a = t;
-        if (a < 0) continue;
-        double s = 0.0;
-        for (int t = 0; t < m; ++t) s += K[16 * e + 4 * a + t] * p[elem[4 * e + t]];
-        acc += s;
+        int corner[4];
+        for (int t = 0; t < m; ++t) {
+          const long long id = elem[4 * e + t];
+          int a = kin;
+          for (int q = 0; q < 4; ++q)
+            if (ids[q] == id) a = q;
+          corner[t] = a;
+        }
+        const double* ke = K + 16 * (long long)e;
+        for (int s = 0; s < m; ++s)
+          for (int t = s + 1; t < m; ++t) {
+            const int a = corner[s], b = corner[t];
+            if (a != b) k[pair_index(a, b)] += ke[4 * s + t];
+          }
       }
     }
-    q[n] = acc;
+    for (int q = 0; q < 6; ++q) kc[q * nc + c] = k[q];
   }
+}
+
+// Values of the vector K acts on (background nodes and cut points alike).
+struct PlainVec {
+  const double* p;
+  __device__ __forceinline__ double bg(long long m) const { return p[m]; }
+  __device__ __forceinline__ double cut(long long m) const { return p[m]; }
+};
+struct ApplyMx {
+  G g;
+  long long ntot;
+  const int8_t* ckind;
+  const double* kc;     // 6 nc, coefficient-major
+  const int* first;
+  const int* elem;
+  const int8_t* nne;
+  const double* K;
+  const int* pedge;
+};
+
+// Row n of K v over the elements of cut cell c (the element's full matrix).
+template <class V>
+__device__ double cut_cell_row(const ApplyMx& a, long long c, long long n, const V& v) {
+  const long long nn = a.g.nn();
+  double acc = 0.0;
+  for (int e = a.first[c]; e < a.first[c + 1]; ++e) {
+    const int m = a.nne[e];
+    int ids[4];
+    int loc = -1;
+    for (int t = 0; t < 4; ++t) {
+      ids[t] = a.elem[4 * e + t];
+      if (t < m && ids[t] == n) loc = t;
+    }
+    if (loc < 0) continue;
+    const double* kr = a.K + 16 * (long long)e + 4 * loc;
+    double s = 0.0;
+    for (int t = 0; t < m; ++t) s += kr[t] * (ids[t] < nn ? v.bg(ids[t]) : v.cut(ids[t]));
+    acc += s;
+  }
+  return acc;
+}
+
+// (K v)[n].  Background node (i, j): its four cells in the order (i-1, j-1), (i, j-1),
+// (i-1, j), (i, j); a plain quadrilateral in difference form sum_b k_ab (v_b - v_a)
+// (its rows sum to zero), a cut cell through its element lists.  Cut point: the two
+// cells on either side of its edge.
+template <class V>
+__device__ __forceinline__ double apply_row(const ApplyMx& a, long long n, double vn,
+                                            const V& v) {
+  const G& g = a.g;
+  const long long nn = g.nn();
+  if (n >= nn) {
+    long long cells[4];
+    node_cells(g, a.pedge, n, cells);
+    double acc = 0.0;
+    for (int k = 0; k < 2; ++k)
+      if (cells[k] >= 0 && a.ckind[cells[k]] == CK_CUT) acc += cut_cell_row(a, cells[k], n, v);
+    return acc;
+  }
+  const int W = g.nx + 1;
+  const int j = (int)(n / W), i = (int)(n - (long long)j * W);
+  const long long nc = g.nc();
+  // the 3 x 3 neighbourhood, only where a cell can use it
+  double P[3][3];
+  for (int dy = 0; dy < 3; ++dy)
+    for (int dx = 0; dx < 3; ++dx) {
+      const int ii = i + dx - 1, jj = j + dy - 1;
+      P[dy][dx] = (ii >= 0 && ii <= g.nx && jj >= 0 && jj <= g.ny)
+                      ? (dx == 1 && dy == 1 ? vn : v.bg(n + (long long)(dy - 1) * W + (dx - 1)))
+                      : 0.0;
+    }
+  double acc = 0.0;
+  for (int k = 0; k < 4; ++k) {
+    const int ci = i - 1 + (k & 1), cj = j - 1 + (k >> 1);
+    if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) continue;
+    const long long c = (long long)cj * g.nx + ci;
+    const int8_t kind = a.ckind[c];
+    if (kind == CK_QUAD) {
+      // corner a of node (i, j) in cell (ci, cj); corners CCW from (ci, cj)
+      const int ox = i - ci, oy = j - cj;
+      const int ca = oy == 0 ? ox : 3 - ox;
+      const int cx[4] = {0, 1, 1, 0}, cy[4] = {0, 0, 1, 1};
+      for (int b = 0; b < 4; ++b) {
+        if (b == ca) continue;
+        const double vb = P[cj - j + 1 + cy[b]][ci - i + 1 + cx[b]];
+        acc += a.kc[pair_index(ca, b) * nc + c] * (vb - vn);
+      }
+    } else if (kind == CK_CUT) {
+      acc += cut_cell_row(a, c, n, v);
+    }
+  }
+  return acc;
+}
+
+__global__ void __launch_bounds__(MB) k_mx_apply(ApplyMx a, const double* __restrict__ p,
+                                                 double* __restrict__ q) {
+  const PlainVec v{p};
+  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < a.ntot;
+       n += (long long)gridDim.x * blockDim.x)
+    q[n] = apply_row(a, n, p[n], v);
 }
 
 }  // namespace mixed
 }  // namespace mfp
 
-// ---- constrained CG on the mixed mesh ----------------------------------------------------
+// ---- constrained solve on the mixed mesh ------------------------------------------------
+// The constrained system A = T^T K T ties every cut point of body b to psi_b.  Every
+// element lies in one background cell, and the inside corners of a cut cell are tied
+// to the same psi_b, so T^T K T is also the sum over background cells of 4 x 4 corner
+// matrices: a cut cell's elements condensed onto its corners (fluid corners keep their
+// rows and columns, cut points are added to an inside corner).  The solve is then the
+// one-kernel CG of the bilinear mesh reading those corner matrices as its stored
+// element entries.
 namespace mfp {
 namespace mixed {
 
-// Mixed-node tags: free fluid node, Dirichlet fluid node, unused (inside a body), or
-// TAG_B0 + b for the cut points of body b (one unknown psi_b each).
-enum : int8_t { MT_FREE = 0, MT_DIR = 1, MT_UNUSED = 2, MT_B0 = 3 };
-
-struct MixState {
-  double rr, rr0, rr_stop, alpha, beta, pq;
-  double xb[MFP_MAX_BODIES], rb[MFP_MAX_BODIES], pb[MFP_MAX_BODIES], qb[MFP_MAX_BODIES];
-  long long iters, kmax;
-  int done, pad_;
+struct PsiB {
+  double v[MFP_MAX_BODIES];
 };
 
-__device__ double mx_side_value(int code, double x, double y, double U, double cx, double cy,
-                                double a) {
-  if (code == MFP_BC_DIRICHLET_UY) return U * y;
-  if (code == MFP_BC_DIRICHLET_UX) return U * x;
-  if (code == MFP_BC_DIRICHLET_CYL || code == MFP_BC_DIRICHLET_CYLPHI) {
-    const double dx = x - cx, dy = y - cy;
-    const double k = a * a / (dx * dx + dy * dy);
-    return code == MFP_BC_DIRICHLET_CYL ? U * dy * (1.0 - k) : U * dx * (1.0 + k);
-  }
-  return 0.0;
-}
-
-struct TagArgs {
-  G g;
-  int bc[4];
-  double U, cx, cy, a;
-  long long npts;
-};
-
-// Whether background node n is a vertex of an element of one of its four cells.
-__device__ bool node_used(const G& g, const int* __restrict__ first, const int* __restrict__ elem,
-                          const int8_t* __restrict__ nne, long long n) {
-  long long cells[4];
-  node_cells(g, nullptr, n, cells);
-  for (int k = 0; k < 4; ++k) {
-    if (cells[k] < 0) continue;
-    for (int e = first[cells[k]]; e < first[cells[k] + 1]; ++e)
-      for (int t = 0; t < nne[e]; ++t)
-        if (elem[4 * e + t] == n) return true;
-  }
-  return false;
-}
-
-// Tags and lifting values: Dirichlet nodes are the fluid nodes of the Dirichlet
-// sides (bottom and top win at corners); fluid nodes in no element and inside nodes
-// are unused (value 0).
-__global__ void k_mx_tags(TagArgs t, const int8_t* __restrict__ body,
-                          const int8_t* __restrict__ pbody, const int* __restrict__ first,
-                          const int* __restrict__ elem, const int8_t* __restrict__ nne,
-                          int8_t* __restrict__ tag, double* __restrict__ gv) {
-  const G& g = t.g;
-  const long long nn = g.nn(), ntot = nn + t.npts;
+// psi at the mixed nodes from the solve's background values: inside nodes 0 (they are
+// no mesh nodes), cut points psi_b.
+__global__ void k_mx_psi_out(G g, long long npts, const int8_t* __restrict__ body,
+                             const int8_t* __restrict__ pbody, PsiB pb, double* __restrict__ psi) {
+  const long long nn = g.nn(), ntot = nn + npts;
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
        n += (long long)gridDim.x * blockDim.x) {
-    int8_t tg;
-    double v = 0.0;
-    if (n >= nn) {
-      tg = (int8_t)(MT_B0 + pbody[n - nn]);
-    } else if (body[n] >= 0) {
-      tg = MT_UNUSED;
-    } else {
-      const int j = (int)(n / (g.nx + 1)), i = (int)(n - (long long)j * (g.nx + 1));
-      const bool left = i == 0 && t.bc[0] != MFP_BC_NATURAL;
-      const bool right = i == g.nx && t.bc[1] != MFP_BC_NATURAL;
-      const bool bot = j == 0 && t.bc[2] != MFP_BC_NATURAL;
-      const bool top = j == g.ny && t.bc[3] != MFP_BC_NATURAL;
-      if (left || right || bot || top) {
-        tg = MT_DIR;
-        const int code = bot ? t.bc[2] : top ? t.bc[3] : left ? t.bc[0] : t.bc[1];
-        v = mx_side_value(code, node_x(g, i), node_y(g, j), t.U, t.cx, t.cy, t.a);
-      } else {
-        tg = node_used(g, first, elem, nne, n) ? MT_FREE : MT_UNUSED;
-      }
-    }
-    tag[n] = tg;
-    gv[n] = v;
-  }
-}
-
-// Block sums (fixed order): v over one block of 256 threads.
-__device__ __forceinline__ double mx_block_sum(double v, double* s) {
-  s[threadIdx.x] = v;
-  __syncthreads();
-  for (int off = MB / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
-    __syncthreads();
-  }
-  const double r = s[0];
-  __syncthreads();
-  return r;
-}
-
-// Per-block partials of p.q over free nodes and of q over each body's cut points:
-// part[blk * (1 + nb) + 0] and [.. + 1 + b].
-__global__ void k_mx_partials(long long ntot, int nb, const int8_t* __restrict__ tag,
-                              const double* __restrict__ p, const double* __restrict__ q,
-                              double* __restrict__ part, const MixState* st, int use_p) {
-  __shared__ double s[MB];
-  if (st && st->done) return;
-  double pq = 0.0;
-  double qb[MFP_MAX_BODIES];
-  for (int b = 0; b < nb; ++b) qb[b] = 0.0;
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
-       n += (long long)gridDim.x * blockDim.x) {
-    const int8_t tg = tag[n];
-    if (tg == MT_FREE) pq += (use_p ? p[n] : q[n]) * q[n];
-    else if (tg >= MT_B0) qb[tg - MT_B0] += q[n];
-  }
-  const double t0 = mx_block_sum(pq, s);
-  if (threadIdx.x == 0) part[blockIdx.x * (1 + nb)] = t0;
-  for (int b = 0; b < nb; ++b) {
-    const double tb = mx_block_sum(qb[b], s);
-    if (threadIdx.x == 0) part[blockIdx.x * (1 + nb) + 1 + b] = tb;
-  }
-}
-
-// Single block: body sums of the partials into st->qb, and the sum of column 0.
-__device__ double mx_reduce(const double* __restrict__ part, int nblk, int nb, MixState* st,
-                            double* s) {
-  double t = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += MB) t += part[k * (1 + nb)];
-  const double tot = mx_block_sum(t, s);
-  for (int b = 0; b < nb; ++b) {
-    double u = 0.0;
-    for (int k = threadIdx.x; k < nblk; k += MB) u += part[k * (1 + nb) + 1 + b];
-    const double ub = mx_block_sum(u, s);
-    if (threadIdx.x == 0) st->qb[b] = ub;
-  }
-  return tot;
-}
-
-// Start: partials of the lifting's K g give r = -q (free) and rb = -sum q (bodies).
-__global__ void k_mx_start(long long ntot, int nb, const int8_t* __restrict__ tag,
-                           const double* __restrict__ q, double* __restrict__ r,
-                           double* __restrict__ p, double* __restrict__ x) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
-       n += (long long)gridDim.x * blockDim.x) {
-    const int8_t tg = tag[n];
-    const double v = tg == MT_FREE ? -q[n] : 0.0;
-    r[n] = v;
-    p[n] = v;
-    x[n] = 0.0;
-  }
-}
-
-__global__ void k_mx_start_state(const double* __restrict__ part, int nblk, int nb,
-                                 MixState* st, double rtol2, long long kmax) {
-  __shared__ double s[MB];
-  // r.r over free nodes (column 0 holds q.q there, r = -q) and the body residuals
-  const double rr_free = mx_reduce(part, nblk, nb, st, s);
-  if (threadIdx.x == 0) {
-    double rr = rr_free;
-    for (int b = 0; b < nb; ++b) {
-      const double v = -st->qb[b];
-      st->rb[b] = v;
-      st->pb[b] = v;
-      st->xb[b] = 0.0;
-      rr += v * v;
-    }
-    st->rr = rr;
-    st->rr0 = rr;
-    st->rr_stop = rtol2 * rr;
-    st->iters = 0;
-    st->kmax = kmax;
-    st->done = rr > 0.0 ? 0 : 1;
-  }
-}
-
-// p at the cut points from the body directions, zero at Dirichlet and unused nodes.
-__global__ void k_mx_bodies_to_p(long long ntot, const int8_t* __restrict__ tag,
-                                 double* __restrict__ p, const MixState* st) {
-  if (st->done) return;
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
-       n += (long long)gridDim.x * blockDim.x) {
-    const int8_t tg = tag[n];
-    if (tg >= MT_B0) p[n] = st->pb[tg - MT_B0];
-    else if (tg != MT_FREE) p[n] = 0.0;
-  }
-}
-
-__global__ void k_mx_alpha(const double* __restrict__ part, int nblk, int nb, MixState* st) {
-  __shared__ double s[MB];
-  if (st->done) return;
-  const double pq_free = mx_reduce(part, nblk, nb, st, s);
-  if (threadIdx.x == 0) {
-    double pq = pq_free;
-    for (int b = 0; b < nb; ++b) pq += st->pb[b] * st->qb[b];
-    st->pq = pq;
-    if (!(pq > 0.0) || !isfinite(pq)) {
-      st->done = 2;
-      return;
-    }
-    const double al = st->rr / pq;
-    st->alpha = al;
-    for (int b = 0; b < nb; ++b) {
-      st->xb[b] += al * st->pb[b];
-      st->rb[b] -= al * st->qb[b];
-    }
-  }
-}
-
-__global__ void k_mx_update(long long ntot, const int8_t* __restrict__ tag,
-                            const double* __restrict__ p, const double* __restrict__ q,
-                            double* __restrict__ x, double* __restrict__ r,
-                            double* __restrict__ part, const MixState* st) {
-  __shared__ double s[MB];
-  if (st->done) return;
-  const double al = st->alpha;
-  double rr = 0.0;
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
-       n += (long long)gridDim.x * blockDim.x) {
-    if (tag[n] != MT_FREE) continue;
-    x[n] += al * p[n];
-    const double rv = r[n] - al * q[n];
-    r[n] = rv;
-    rr += rv * rv;
-  }
-  const double t = mx_block_sum(rr, s);
-  if (threadIdx.x == 0) part[blockIdx.x] = t;
-}
-
-__global__ void k_mx_beta(const double* __restrict__ part, int nblk, int nb, MixState* st) {
-  __shared__ double s[MB];
-  if (st->done) return;
-  double t = 0.0;
-  for (int k = threadIdx.x; k < nblk; k += MB) t += part[k];
-  const double rr_free = mx_block_sum(t, s);
-  if (threadIdx.x == 0) {
-    double rr = rr_free;
-    for (int b = 0; b < nb; ++b) rr += st->rb[b] * st->rb[b];
-    const double be = rr / st->rr;
-    st->beta = be;
-    st->rr = rr;
-    st->iters += 1;
-    for (int b = 0; b < nb; ++b) st->pb[b] = st->rb[b] + be * st->pb[b];
-    if (!isfinite(rr)) st->done = 2;
-    else if (rr <= st->rr_stop) st->done = 1;
-    else if (st->iters >= st->kmax) st->done = 3;
-  }
-}
-
-__global__ void k_mx_dir(long long ntot, const int8_t* __restrict__ tag,
-                         const double* __restrict__ r, double* __restrict__ p,
-                         const MixState* st) {
-  // runs once more after the stopping step: harmless (p is not used afterwards)
-  const double be = st->beta;
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
-       n += (long long)gridDim.x * blockDim.x) {
-    const int8_t tg = tag[n];
-    if (tg == MT_FREE) p[n] = r[n] + be * p[n];
-    else if (tg >= MT_B0) p[n] = st->pb[tg - MT_B0];
-    else p[n] = 0.0;
-  }
-}
-
-// psi over the mixed nodes: free x, Dirichlet g, cut points psi_b, unused 0.
-__global__ void k_mx_output(long long ntot, const int8_t* __restrict__ tag,
-                            const double* __restrict__ x,
-                            const double* __restrict__ gv, const MixState* st,
-                            double* __restrict__ psi) {
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < ntot;
-       n += (long long)gridDim.x * blockDim.x) {
-    const int8_t tg = tag[n];
-    double v;
-    if (tg == MT_FREE) v = x[n];
-    else if (tg == MT_DIR) v = gv[n];
-    else if (tg >= MT_B0) v = st->xb[tg - MT_B0];
-    else v = 0.0;
-    psi[n] = v;
+    if (n >= nn)
+      psi[n] = pb.v[pbody[n - nn]];
+    else if (body[n] >= 0)
+      psi[n] = 0.0;
   }
 }
 
@@ -985,33 +876,22 @@ namespace mfp {
 namespace mixed {
 
 struct SolveMx {
-  double* K;      // 16 per element
-  int8_t* tag;    // per mixed node
-  double *g, *x, *r, *p, *q;
-  double* part;   // partials
-  MixState* st;
-  int nblk;       // blocks of the reductions
+  double* K;       // 16 per element
+  double* kc;      // 6 per cell, entry-major (corner matrices)
+  int8_t* ckind;   // per cell
+  void* solve_ws;  // the constrained solve's own workspace
+  size_t solve_bytes;
 };
 
-static int red_blocks(long long n) {
-  long long b = (n + 8 * MB - 1) / (8 * MB);
-  if (b > 1024) b = 1024;
-  return (int)(b < 1 ? 1 : b);
-}
-
-static size_t solve_layout_mx(long long ntot, long long nel, int nb, void* base, SolveMx* out) {
+static size_t solve_layout_mx(const G& g, long long nel, size_t solve_bytes, void* base,
+                              SolveMx* out) {
   Bump bp(base);
   SolveMx s{};
   s.K = bp.take<double>(16 * (size_t)nel);
-  s.tag = bp.take<int8_t>(ntot);
-  s.g = bp.take<double>(ntot);
-  s.x = bp.take<double>(ntot);
-  s.r = bp.take<double>(ntot);
-  s.p = bp.take<double>(ntot);
-  s.q = bp.take<double>(ntot);
-  s.nblk = red_blocks(ntot);
-  s.part = bp.take<double>((size_t)s.nblk * (1 + (nb > 0 ? nb : 1)));
-  s.st = bp.take<MixState>(1);
+  s.kc = bp.take<double>(6 * (size_t)g.nc());
+  s.ckind = bp.take<int8_t>(g.nc());
+  s.solve_ws = bp.take<char>(solve_bytes);
+  s.solve_bytes = solve_bytes;
   if (out) *out = s;
   return bp.off + 256;
 }
@@ -1028,28 +908,39 @@ static int check_mesh_arg(const mfp_grid* grid, const mfp_mixed_mesh_t* m) {
   return MFP_OK;
 }
 
-static void launch_kmat(const G& g, const mfp_mixed_mesh_t* m, double* K, hipStream_t st) {
+// Element matrices of every element, then the per-cell kinds and corner matrices;
+// returns the product's arguments.
+static ApplyMx setup_apply(const G& g, const mfp_mixed_mesh_t* m, const SolveMx& s,
+                           hipStream_t st) {
   k_mx_kmat<<<blocks_for(m->n_elems), MB, 0, st>>>(g, m->n_elems, m->elem, m->nne, m->disp,
-                                                     m->pxy, K);
-}
-
-static void launch_apply_mx(const G& g, const mfp_mixed_mesh_t* m, const double* K,
-                            const double* p, double* q, hipStream_t st) {
-  const long long ntot = g.nn() + m->n_points;
-  k_mx_apply<<<blocks_for(ntot), MB, 0, st>>>(g, ntot, m->pedge, m->cell_first, m->elem, m->nne,
-                                               K, p, q);
+                                                     m->pxy, s.K);
+  k_mx_cellcoef<<<blocks_for(g.nc()), MB, 0, st>>>(g, m->body, m->cell_first, m->elem, m->nne,
+                                                   s.K, s.ckind, s.kc);
+  ApplyMx a;
+  a.g = g;
+  a.ntot = g.nn() + m->n_points;
+  a.ckind = s.ckind;
+  a.kc = s.kc;
+  a.first = m->cell_first;
+  a.elem = m->elem;
+  a.nne = m->nne;
+  a.K = s.K;
+  a.pedge = m->pedge;
+  return a;
 }
 
 }  // namespace mixed
 }  // namespace mfp
 
 extern "C" size_t mfp_mixed_solve_workspace_size(const mfp_grid* grid, int64_t n_points,
-                                                 int64_t n_elems, int32_t nbody) {
+                                                 int64_t n_elems, int32_t nbody,
+                                                 const mfp_solver_opts* opts) {
   if (!grid || grid->nx < 2 || grid->ny < 2 || n_points < 0 || n_elems < 0 || nbody < 0 ||
       nbody > MFP_MAX_BODIES)
     return 0;
-  const G g = to_g(*grid);
-  return solve_layout_mx(g.nn() + n_points, n_elems, nbody, nullptr, nullptr);
+  const size_t sb = psi_solve_cells_workspace(grid, nbody, opts);
+  if (sb == 0) return 0;
+  return solve_layout_mx(to_g(*grid), n_elems, sb, nullptr, nullptr);
 }
 
 extern "C" int mfp_mixed_element_apply(const mfp_grid* grid, const mfp_mixed_mesh_t* m,
@@ -1063,21 +954,22 @@ extern "C" int mfp_mixed_element_apply(const mfp_grid* grid, const mfp_mixed_mes
     return MFP_E_ARG;
   }
   const G g = to_g(*grid);
-  const size_t need = solve_layout_mx(g.nn() + m->n_points, m->n_elems, 0, nullptr, nullptr);
+  const long long ntot = g.nn() + m->n_points;
+  const size_t need = solve_layout_mx(g, m->n_elems, 0, nullptr, nullptr);
   if (ws_bytes < need) {
     set_error("workspace too small: %zu < %zu", ws_bytes, need);
     return MFP_E_WORKSPACE;
   }
   hipStream_t st = static_cast<hipStream_t>(stream_);
   SolveMx s;
-  solve_layout_mx(g.nn() + m->n_points, m->n_elems, 0, ws, &s);
-  launch_kmat(g, m, s.K, st);
+  solve_layout_mx(g, m->n_elems, 0, ws, &s);
+  const ApplyMx a = setup_apply(g, m, s, st);
   MFP_TRY_HIP(hipGetLastError());
   hipEvent_t e0, e1;
   MFP_TRY_HIP(hipEventCreate(&e0));
   MFP_TRY_HIP(hipEventCreate(&e1));
   MFP_TRY_HIP(hipEventRecord(e0, st));
-  for (int k = 0; k < repeat; ++k) launch_apply_mx(g, m, s.K, p, q, st);
+  for (int k = 0; k < repeat; ++k) k_mx_apply<<<blocks_for(ntot), MB, 0, st>>>(a, p, q);
   MFP_TRY_HIP(hipEventRecord(e1, st));
   const hipError_t le = hipGetLastError();
   float ms = 0.f;
@@ -1107,122 +999,40 @@ extern "C" int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circl
     set_error("NULL argument");
     return MFP_E_ARG;
   }
-  if (!std::isfinite(flow->U) || !(opts->rtol > 0.0) || opts->kmax < 1 ||
-      opts->precision != MFP_FP64 || pair_lo >= nbody || pair_hi >= nbody) {
-    set_error("U finite, rtol > 0, kmax >= 1, MFP_FP64 and pair indices below nbody");
+  if (opts->psi0) {
+    set_error("no warm start on the mixed mesh");
     return MFP_E_ARG;
   }
-  for (int k = 0; k < 4; ++k)
-    if (flow->side_bc[k] < MFP_BC_NATURAL || flow->side_bc[k] > MFP_BC_DIRICHLET_CYLPHI) {
-      set_error("invalid side boundary code");
-      return MFP_E_ARG;
-    }
   const G g = to_g(*grid);
-  const long long nn = g.nn(), ntot = nn + m->n_points;
-  const size_t need = solve_layout_mx(ntot, m->n_elems, nbody, nullptr, nullptr);
+  const size_t sb = psi_solve_cells_workspace(grid, nbody, opts);
+  if (sb == 0) {
+    set_error("invalid solver options");
+    return MFP_E_ARG;
+  }
+  const size_t need = solve_layout_mx(g, m->n_elems, sb, nullptr, nullptr);
   if (ws_bytes < need) {
     set_error("workspace too small: %zu < %zu", ws_bytes, need);
     return MFP_E_WORKSPACE;
   }
   hipStream_t st = static_cast<hipStream_t>(stream_);
   SolveMx s;
-  solve_layout_mx(ntot, m->n_elems, nbody, ws, &s);
-  const int nb = nbody;
-  TagArgs ta{};
-  ta.g = g;
-  for (int k = 0; k < 4; ++k) ta.bc[k] = flow->side_bc[k];
-  ta.U = flow->U;
-  if (nbody > 0) {
-    ta.cx = circles_h[0].cx;
-    ta.cy = circles_h[0].cy;
-    ta.a = circles_h[0].r;
-  }
-  ta.npts = m->n_points;
-  const int GB = blocks_for(ntot);
-  k_mx_tags<<<GB, MB, 0, st>>>(ta, m->body, m->pbody, m->cell_first, m->elem, m->nne, s.tag,
-                               s.g);
-  launch_kmat(g, m, s.K, st);
-  // r = -K g at free nodes, rb = -sum of K g over each body's cut points
-  launch_apply_mx(g, m, s.K, s.g, s.q, st);
-  k_mx_partials<<<s.nblk, MB, 0, st>>>(ntot, nb, s.tag, s.q, s.q, s.part, nullptr, 0);
-  k_mx_start<<<GB, MB, 0, st>>>(ntot, nb, s.tag, s.q, s.r, s.p, s.x);
-  k_mx_start_state<<<1, MB, 0, st>>>(s.part, s.nblk, nb, s.st, opts->rtol * opts->rtol,
-                                     opts->kmax);
-  k_mx_bodies_to_p<<<GB, MB, 0, st>>>(ntot, s.tag, s.p, s.st);
+  solve_layout_mx(g, m->n_elems, sb, ws, &s);
+  (void)setup_apply(g, m, s, st);
   MFP_TRY_HIP(hipGetLastError());
-  hipEvent_t e0, e1;
-  MFP_TRY_HIP(hipEventCreate(&e0));
-  MFP_TRY_HIP(hipEventCreate(&e1));
-  MFP_TRY_HIP(hipEventRecord(e0, st));
-  const int every = opts->check_every > 0 ? opts->check_every : 32;
-  int done = 0;
-  long long launched = 0;
-  while (true) {
-    for (int k = 0; k < every; ++k) {
-      launch_apply_mx(g, m, s.K, s.p, s.q, st);
-      k_mx_partials<<<s.nblk, MB, 0, st>>>(ntot, nb, s.tag, s.p, s.q, s.part, s.st, 1);
-      k_mx_alpha<<<1, MB, 0, st>>>(s.part, s.nblk, nb, s.st);
-      k_mx_update<<<s.nblk, MB, 0, st>>>(ntot, s.tag, s.p, s.q, s.x, s.r, s.part, s.st);
-      k_mx_beta<<<1, MB, 0, st>>>(s.part, s.nblk, nb, s.st);
-      k_mx_dir<<<GB, MB, 0, st>>>(ntot, s.tag, s.r, s.p, s.st);
-    }
-    launched += every;
-    MFP_TRY_HIP(hipGetLastError());
-    MFP_TRY_HIP(hipMemcpyAsync(&done, &s.st->done, sizeof(int), hipMemcpyDeviceToHost, st));
-    MFP_TRY_HIP(hipStreamSynchronize(st));
-    if (done || launched > opts->kmax + every) break;
+  // background-node values first (the mixed numbering starts with them)
+  std::vector<double> pb((size_t)(nbody > 0 ? nbody : 1));
+  const int rc = psi_solve_cells(grid, circles_h, nbody, m->disp, m->body, s.kc, flow, opts,
+                                 pair_lo, pair_hi, psi, pb.data(), Q_h, copfi_h, stats_h,
+                                 s.solve_ws, s.solve_bytes, st);
+  if (rc < 0) return rc;
+  PsiB hb{};
+  for (int b = 0; b < nbody; ++b) {
+    hb.v[b] = pb[b];
+    psi_b_h[b] = pb[b];
   }
-  MFP_TRY_HIP(hipEventRecord(e1, st));
-  // output and the true residual from it
-  k_mx_output<<<GB, MB, 0, st>>>(ntot, s.tag, s.x, s.g, s.st, psi);
-  launch_apply_mx(g, m, s.K, psi, s.q, st);
-  k_mx_partials<<<s.nblk, MB, 0, st>>>(ntot, nb, s.tag, s.q, s.q, s.part, nullptr, 0);
+  const long long ntot = g.nn() + m->n_points;
+  k_mx_psi_out<<<blocks_for(ntot), MB, 0, st>>>(g, m->n_points, m->body, m->pbody, hb, psi);
   MFP_TRY_HIP(hipGetLastError());
-  MixState hs;
-  std::vector<double> part((size_t)s.nblk * (1 + (nb > 0 ? nb : 1)));
-  MFP_TRY_HIP(hipMemcpyAsync(&hs, s.st, sizeof(MixState), hipMemcpyDeviceToHost, st));
-  MFP_TRY_HIP(hipMemcpyAsync(part.data(), s.part, sizeof(double) * part.size(),
-                             hipMemcpyDeviceToHost, st));
-  MFP_TRY_HIP(hipEventSynchronize(e1));
-  float ms = 0.f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   MFP_TRY_HIP(hipStreamSynchronize(st));
-  double rr = 0.0;
-  for (int k = 0; k < s.nblk; ++k) rr += part[(size_t)k * (1 + nb)];
-  for (int b = 0; b < nb; ++b) {
-    double qb = 0.0;
-    for (int k = 0; k < s.nblk; ++k) qb += part[(size_t)k * (1 + nb) + 1 + b];
-    rr += qb * qb;
-  }
-  for (int b = 0; b < nb; ++b) psi_b_h[b] = hs.xb[b];
-  if (pair_lo >= 0 && pair_hi >= 0) {
-    const double Q = hs.xb[pair_hi] - hs.xb[pair_lo];
-    if (Q_h) *Q_h = Q;
-    if (copfi_h) *copfi_h = Q / (flow->U * (circles_h[pair_hi].cy - circles_h[pair_lo].cy));
-  }
-  if (stats_h) {
-    std::vector<int8_t> tg((size_t)ntot);
-    MFP_TRY_HIP(hipMemcpy(tg.data(), s.tag, tg.size(), hipMemcpyDeviceToHost));
-    long long nfree = 0;
-    for (int8_t v : tg) nfree += v == MT_FREE;
-    std::memset(stats_h, 0, sizeof(*stats_h));
-    stats_h->iters = hs.iters;
-    stats_h->applies = hs.iters + 2;
-    stats_h->n_free = nfree;
-    stats_h->n_dof = nfree + nb;
-    stats_h->rnorm0 = std::sqrt(hs.rr0);
-    stats_h->relres_true = hs.rr0 > 0 ? std::sqrt(rr / hs.rr0) : 0.0;
-    stats_h->solve_ms = ms;
-  }
-  if (hs.done == 2) {
-    set_error("CG breakdown (p.Ap <= 0 or non-finite)");
-    return MFP_E_BREAKDOWN;
-  }
-  if (hs.done != 1) {
-    set_error("kmax reached before the tolerance");
-    return MFP_W_NOCONV;
-  }
-  return MFP_OK;
+  return rc;
 }

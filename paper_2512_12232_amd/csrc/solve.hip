@@ -688,6 +688,8 @@ struct Schedule {
   int kst = 0;      // 1: the geometry tasks read stored element entries (k_elem_coef)
   int stream = -1;  // -1: by working-set size; 0: cached stores; 1: streaming stores
   int blocks = 0;   // blocks per launch; 0: as many as stay resident
+  int cells = 0;    // 1: the stored entries come from a caller's per-cell table (FP64
+                    //    slabs kept for the residuals in every precision)
 };
 
 // Values per task slab of stored element entries (cell rows x entries x lanes).
@@ -728,6 +730,7 @@ struct SolveWs {
   int* ngeo = nullptr;      // number of slabs in use
   double* kc64 = nullptr;   // slabs for an FP64 iteration
   float* kc32 = nullptr;    // slabs for an FP32 iteration
+  const double* cellcoef = nullptr;  // per-cell element entries given by the caller
 };
 
 // Task height of a single solve's layout.  The FP32 iteration with 8-row tasks uses
@@ -912,10 +915,8 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
     w.tgeo = bp.take<int>(nt);
     w.ngeo = bp.take<int>(1);
     const size_t slabs = (size_t)nt * kslab_rows(w.L.hc);
-    if (precision == MFP_FP64)
-      w.kc64 = bp.take<double>(slabs);
-    else
-      w.kc32 = bp.take<float>(slabs);
+    if (precision == MFP_FP64 || w.sc.cells) w.kc64 = bp.take<double>(slabs);
+    if (precision != MFP_FP64) w.kc32 = bp.take<float>(slabs);
   }
   {
     // surface samples: at most nb boxes of at most nx ny cells each
@@ -976,6 +977,14 @@ static ApplyArgs<T> make_apply_args(const SolveWs& w, const mfp_grid& g, int nb,
   a.cN = (T)(-2.0 / 3.0 * qq + rr / 3.0);
   a.cD = (T)(-(rr + qq) / 6.0);
   a.ry = (T)rr;
+  if (w.cellcoef) {
+    // element entries from a per-cell table: the product has no geometry to rebuild
+    if constexpr (sizeof(T) == sizeof(double))
+      a.kcoef = reinterpret_cast<const T*>(w.kc64);
+    else
+      a.kcoef = reinterpret_cast<const T*>(w.kc32);
+    a.tgeo = w.tgeo;
+  }
   return a;
 }
 
@@ -993,8 +1002,25 @@ static void launch_elem_coef(const SolveWs& w, double ry, T* kc, hipStream_t st)
     k_elem_coef<T, 4><<<nb, BLOCK, 0, st>>>(w.L, ry, w.tag, w.dx, w.dy, w.tgeo, kc);
 }
 
+template <typename T>
+static void launch_cells_to_slab(const SolveWs& w, T* kc, hipStream_t st) {
+  const int nb = (w.L.ntasks() + WAVES - 1) / WAVES;
+  if (w.L.hc == 8)
+    k_cells_to_slab<T, 8><<<nb, BLOCK, 0, st>>>(w.L, w.cellcoef, w.tgeo, kc);
+  else if (w.L.hc == 5)
+    k_cells_to_slab<T, 5><<<nb, BLOCK, 0, st>>>(w.L, w.cellcoef, w.tgeo, kc);
+  else
+    k_cells_to_slab<T, 4><<<nb, BLOCK, 0, st>>>(w.L, w.cellcoef, w.tgeo, kc);
+}
+
 static int element_entries(const mfp_grid& g, const SolveWs& w, hipStream_t st) {
   k_assign_geo<<<1, 256, 0, st>>>(w.L.ntasks(), w.tplain, w.tgeo, w.ngeo);
+  if (w.cellcoef) {
+    if (w.kc64) launch_cells_to_slab<double>(w, w.kc64, st);
+    if (w.kc32) launch_cells_to_slab<float>(w, w.kc32, st);
+    MFP_TRY_HIP(hipGetLastError());
+    return MFP_OK;
+  }
   const double ry = grid_hy(g) / grid_hx(g);
   if (w.kc64) launch_elem_coef<double>(w, ry, w.kc64, st);
   if (w.kc32) launch_elem_coef<float>(w, ry, w.kc32, st);
@@ -1917,6 +1943,69 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   MFP_TRY(fill_stats(w, info, nb, hsd, st, stats_h));
   return finish_status(info);
 }
+
+namespace mfp {
+
+// Schedule of a solve whose element entries come from a per-cell table: the stored
+// form for every geometry task, the rest as for any solve.
+static int cells_schedule(const mfp_grid* grid, const mfp_solver_opts* opts, Schedule* sc) {
+  MFP_TRY(resolve_schedule(grid, opts ? opts->precision : MFP_FP64, opts, sc));
+  sc->kst = 1;
+  sc->cells = 1;
+  return MFP_OK;
+}
+
+size_t psi_solve_cells_workspace(const mfp_grid* grid, int nbody, const mfp_solver_opts* opts) {
+  Schedule sc;
+  if (cells_schedule(grid, opts, &sc) != MFP_OK) return 0;
+  return solve_layout(grid, nbody, opts ? opts->precision : MFP_FP64, nullptr, nullptr, &sc);
+}
+
+int psi_solve_cells(const mfp_grid* grid, const mfp_circle* circles_h, int nbody,
+                    const double* disp, const int8_t* body, const double* cellcoef,
+                    const mfp_flow* flow, const mfp_solver_opts* opts, int pair_lo,
+                    int pair_hi, double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
+                    mfp_stats* stats_h, void* ws, size_t ws_bytes, hipStream_t st) {
+  MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, body, body, flow, opts, ws));
+  if (!psi || !cellcoef || (nbody > 0 && !psi_b_h) || pair_lo >= nbody || pair_hi >= nbody) {
+    set_error("NULL argument or pair index out of range");
+    return MFP_E_ARG;
+  }
+  Schedule sc;
+  MFP_TRY(cells_schedule(grid, opts, &sc));
+  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, &sc);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  SolveWs w;
+  solve_layout(grid, nbody, opts->precision, ws, &w, &sc);
+  w.cellcoef = cellcoef;
+  const mfp_grid& g = *grid;
+  SolveInfo info;
+  MFP_TRY(solve_core(g, circles_h, nbody, disp, body, flow, opts, nullptr, false, w, st, &info));
+  double ylo = 0, yhi = 0;
+  if (pair_lo >= 0 && pair_hi >= 0) {
+    ylo = circles_h[pair_lo].cy;
+    yhi = circles_h[pair_hi].cy;
+  }
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  k_output<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, w.x, w.g, w.st, psi,
+                                               pair_lo, pair_hi, flow->U, ylo, yhi);
+  MFP_TRY_HIP(hipGetLastError());
+  DevState hsd;
+  MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < nbody; ++b) psi_b_h[b] = hsd.xb[hsd.iters & 1][b];
+  if (pair_lo >= 0 && pair_hi >= 0) {
+    if (Q_h) *Q_h = hsd.Q;
+    if (copfi_h) *copfi_h = hsd.copfi;
+  }
+  MFP_TRY(fill_stats(w, info, nbody, hsd, st, stats_h));
+  return finish_status(info);
+}
+
+}  // namespace mfp
 
 extern "C" int mfp_phi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
                              const double* disp, const int8_t* kind, const int8_t* body,

@@ -181,12 +181,28 @@ def test_solve_matches_direct(mfp, name):
     used[mm.elem_nodes[mm.elem_nodes >= 0]] = True
     dm = np.concatenate([O.dirichlet_mask(mm.grid, c.flow).ravel() & (mm.body.ravel() < 0),
                          np.zeros(len(mm.pxy), bool)])
-    assert np.array_equal(psi[dm], ref.psi[dm])
+    # the same expression, possibly with a fused multiply-add: within a few ulp
+    np.testing.assert_allclose(psi[dm], ref.psi[dm], rtol=0,
+                               atol=1e-14 * max(1.0, np.abs(ref.psi).max()))
     assert np.all(psi[:mm.grid.nodes][mm.body.ravel() >= 0] == 0.0)
     np.testing.assert_array_equal(psi[mm.grid.nodes:], np.asarray(res.psi_b)[mm.pbody])
     assert res.stats["n_free"] == ref.nfree and res.stats["n_dof"] == ref.ndof
     np.testing.assert_allclose(psi[used], ref.psi[used], rtol=0,
                                atol=bound + 1e-12 * np.abs(ref.psi).max())
+
+
+@pytest.mark.parametrize("name", ["five96x48", "five_asym120x60"])
+def test_solve_fp32_refined(mfp, name):
+    """FP32 iterations with FP64 residual replacement reach the FP64 solve's accuracy."""
+    c = CASES[name]
+    gm, mm = pair(mfp, name)
+    ref = oracle_solution(mm, c.flow, name)
+    res = mfp.mixed_psi_solve(gm, c.flow, precision="fp32_ir", rtol=1e-12, pair=c.pair)
+    assert res.status == mfp.MFP_OK
+    assert res.stats["relres_true"] <= 1e-11
+    lmin = spla.eigsh(ref.A, k=1, sigma=0.0, which="LM", return_eigenvectors=False)[0]
+    bound = 1e-11 * np.linalg.norm(ref.b) / lmin + 1e-12 * np.abs(ref.psi).max()
+    np.testing.assert_allclose(res.psi_b, ref.psi_b, rtol=0, atol=bound)
 
 
 def test_solve_full_size_1024x512(mfp):
