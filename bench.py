@@ -479,6 +479,115 @@ def delta_sweep(mfp, W, count=256):
     return out
 
 
+def mixed_apply_bytes(gm):
+    """Algorithmic bytes of one mixed-node product (k_mx_apply): every mixed node reads
+    its input value and writes its output (2 x 8 B); every plain quadrilateral cell's
+    six coefficients (48 B) and every cell's kind (1 B) are read once; every element
+    of a cut cell is read whole (16 x 8 B matrix, 4 x 4 B node ids, 1 B size) with its
+    cell's first-element pair (8 B per cut cell); every cut point reads its edge
+    (4 B)."""
+    import torch
+    nc = gm.grid.nx * gm.grid.ny
+    first = gm.cell_first.to(torch.int64)
+    cnt = first[1:] - first[:-1]
+    nn = (gm.grid.nx + 1) * (gm.grid.ny + 1)
+    quad_like = (cnt == 1) & (gm.nne[first[:-1].clamp(max=max(gm.n_elems - 1, 0))] == 4)
+    ids = gm.elem[first[:-1].clamp(max=max(gm.n_elems - 1, 0))].to(torch.int64)
+    plain = quad_like & (ids < nn).all(dim=1)
+    n_plain = int(plain.sum().item())
+    cut_cells = (cnt > 0) & ~plain
+    n_cut_cells = int(cut_cells.sum().item())
+    n_cut_elems = int(cnt[cut_cells].sum().item())
+    return (16 * gm.n_nodes + 48 * n_plain + nc + 145 * n_cut_elems + 8 * n_cut_cells
+            + 4 * gm.n_points), n_plain, n_cut_cells, n_cut_elems
+
+
+def stored_step_bytes(case, body, n_tiles, n_plain, hc, esz=8):
+    """Algorithmic bytes of one iteration launch that reads stored element entries:
+    the vectors and tags of step_bytes, and instead of displacements the slab of every
+    geometry task ((hc + 1) cell rows x 6 entries x 64 lanes)."""
+    import torch
+    n = case.grid.nodes
+    nx, ny = case.grid.nx, case.grid.ny
+    boundary = 2 * (nx + 1) + 2 * (ny - 1)
+    bodies = int((body >= 0).sum().item())
+    return (15 * esz * n) // 2 + (boundary + bodies) + (n_tiles - n_plain) * (hc + 1) * 6 * 64 * esz
+
+
+def mixed_cell_mesh(mfp, W):
+    """The paper's mixed-cell mesh of the benchmark geometry (1024 x 512, five
+    cylinders): mesh time, the mixed-node product's roofline, and the constrained
+    solve (FP64 and FP32 + FP64 refinement to 1e-12) on the one-kernel iteration with
+    the cut cells condensed onto their corners, with its iteration kernel's roofline."""
+    import numpy as np
+    import torch
+    case = W.five_cyl_1024()
+    dev = "cuda:0"
+    gm, mesh_ms = _timed(lambda: mfp.mixed_mesh(case.grid, case.circles, case.nsweeps,
+                                                device=dev), reps=3)
+    p = torch.from_numpy(W.random_vector(gm.n_nodes, 1)).to(dev)
+    _, apply_ms = mfp.mixed_element_apply(gm, p, repeat=200)
+    nbytes, n_plain, n_cut_cells, n_cut_elems = mixed_apply_bytes(gm)
+    out = {"workload": "five cylinders, 1024x512 cells, delta 0.25; mixed-cell mesh (cut "
+                       "points on grid lines, triangles and split pentagons); rtol 1e-12",
+           "mesh_ms": round(mesh_ms, 3), "cut_points": gm.n_points, "elements": gm.n_elems,
+           "triangles": gm.n_tri, "plain_quad_cells": n_plain, "cut_cells": n_cut_cells,
+           "cut_cell_elements": n_cut_elems,
+           "product": {"kernel": "k_mx_apply", "ms": round(apply_ms, 5),
+                       "bytes": nbytes,
+                       "achieved_GBs": round(nbytes / (apply_ms * 1e-3) / 1e9, 1),
+                       "frac": round(nbytes / (apply_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+    res = {}
+    for prec in ("fp64", "fp32_ir"):
+        r, ms = _timed(lambda: mfp.mixed_psi_solve(gm, case.flow, precision=prec, rtol=1e-12,
+                                                   pair=case.pair, profile_every=1), reps=2)
+        res[prec] = r
+        s = r.stats
+        e = {"solve_ms": round(ms, 2), "iters": s["iters"], "n_dof": s["n_dof"],
+             "relres_true": s["relres_true"], "copfi": r.copfi,
+             "dof_iter_per_s": s["n_dof"] * s["iters"] / (ms * 1e-3)}
+        if s["apply_samples"] > 0 and prec == "fp64":
+            hc = _task_height(case, s["n_tiles"])
+            sb = stored_step_bytes(case, gm.body, s["n_tiles"], s["n_plain_tiles"], hc)
+            kms = s["apply_ms"]
+            e["roofline"] = {"kernel": "k_step<double, %d> (stored entries)" % hc,
+                             "launch_ms": round(kms, 5), "bytes_per_launch": sb,
+                             "achieved_GBs": round(sb / (kms * 1e-3) / 1e9, 1),
+                             "frac": round(sb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        out[prec] = e
+    rk = mfp.mixed_psi_solve(gm, case.flow, rtol=1e-12, pair=case.pair, estimate_kappa=True)
+    out["kappa_gpu_lanczos"] = {"kappa": rk.stats["kappa_est"], "ritz_min": rk.stats["ritz_min"],
+                                "ritz_max": rk.stats["ritz_max"]}
+    mixed_cell_mesh.last = (case, gm, res)
+    return out
+
+
+def mixed_vs_oracle(case, gm, res):
+    """CPU leg: the oracle's mixed-cell mesh and direct solve of the same workload
+    against the GPU's (mesh bit for bit; psi, psi_b and CoPFI errors)."""
+    import numpy as np
+    from oracle import mixed as OM
+    t0 = time.perf_counter()
+    mm = OM.mixed_mesh(case.grid, case.circles, case.nsweeps)
+    sol = OM.mixed_solve(mm, case.flow)
+    used = np.zeros(mm.n_nodes, bool)
+    used[mm.elem_nodes[mm.elem_nodes >= 0]] = True
+    scale = np.abs(sol.psi).max()
+    v = {"oracle_s": round(time.perf_counter() - t0, 1),
+         "mesh_bitwise": bool(np.array_equal(gm.disp.cpu().numpy(), mm.disp.reshape(-1))
+                              and np.array_equal(gm.pxy.cpu().numpy(), mm.pxy)
+                              and np.array_equal(gm.elem.cpu().numpy(), mm.elem_nodes))}
+    lo, hi = case.pair
+    ref_cop = (sol.psi_b[hi] - sol.psi_b[lo]) / (
+        case.flow.U * (case.circles[hi][1] - case.circles[lo][1]))
+    for prec, r in res.items():
+        psi = r.psi.cpu().numpy()
+        v[prec] = {"psi_node_max_rel": float(np.abs(psi - sol.psi)[used].max() / scale),
+                   "psi_b_max_abs": float(np.abs(np.asarray(r.psi_b) - sol.psi_b).max()),
+                   "copfi_abs": float(abs(r.copfi - ref_cop))}
+    return v
+
+
 def streamlines(mfp, W):
     """Stagnation streamlines psi = psi_4 and psi = psi_5 of the benchmark workload
     (1024 x 512): mfp_contour on the FP64 solution, timed (both lines, ms)."""
@@ -594,6 +703,7 @@ def main():
         extras["stagnation_streamlines_1024x512"] = streamlines(mfp, W)
         extras["delta_sweep_256"] = delta_sweep(mfp, W)
         extras["autotune"] = autotune_effect(mfp, W)
+        extras["mixed_cell_mesh_1024x512"] = mixed_cell_mesh(mfp, W)
     cpu = None
     vs_oracle = {"kappa_gpu_lanczos": kappa}
     if not args.no_cpu_baseline:
@@ -602,6 +712,9 @@ def main():
         if "potential_1024x512" in extras:
             pc, phi = potential_solve.last
             extras["potential_1024x512"]["vs_oracle"] = potential_vs_oracle(pc, phi, mesh_o)
+        if "mixed_cell_mesh_1024x512" in extras:
+            extras["mixed_cell_mesh_1024x512"]["vs_oracle"] = mixed_vs_oracle(
+                *mixed_cell_mesh.last)
     s = res.stats
     line = {
         "metric": METRIC,

@@ -130,9 +130,10 @@ typedef struct {
                              parameter sweep or a finite difference, this reaches an
                              absolute accuracy below what rtol ||b|| allows)            */
   /* Schedule of the iteration kernel; 0 = automatic: the entry for this device, grid
-   * and precision in the tuning cache named by the environment variable
-   * MFP_TUNE_CACHE (written by the package's tuner), else built-in rules.  The
-   * result does not depend on the schedule beyond rounding.                          */
+   * and precision in the tuning cache (written by the package's tuner): the file named
+   * by the environment variable MFP_TUNE_CACHE, else tune_cache.txt beside
+   * libmfpsi.so ("none" switches the cache off), else built-in rules.  The result
+   * does not depend on the schedule beyond rounding.                                 */
   int32_t task_rows;      /* node rows per task: 4, 5 or 8                              */
   int32_t element_mode;   /* 1: element geometry on the fly from the displacements every
                              iteration; 2: each distorted cell's element matrix evaluated

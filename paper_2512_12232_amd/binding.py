@@ -636,7 +636,7 @@ class MixedSolveResult:
 def mixed_psi_solve(mm: MixedMesh, flow, *, precision="fp64", rtol=1e-12, kmax=10 ** 7,
                     check_every=16, inner_rtol=0.1, max_outer=1000, pair=(-1, -1),
                     estimate_kappa: bool = False, schedule: Optional[dict] = None,
-                    allow_warn: bool = True) -> MixedSolveResult:
+                    profile_every: int = 0, allow_warn: bool = True) -> MixedSolveResult:
     lib = load()
     g = make_grid(mm.grid)
     c = make_circles(mm.circles)
@@ -644,6 +644,7 @@ def mixed_psi_solve(mm: MixedMesh, flow, *, precision="fp64", rtol=1e-12, kmax=1
     f = make_flow(flow)
     o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa,
               schedule)
+    o.profile_every = int(profile_every)
     dev = mm.disp.device
     psi = torch.empty(mm.n_nodes, dtype=torch.float64, device=dev)
     psib = (c_double * max(nb, 1))()
