@@ -33,7 +33,10 @@ Body-Conforming Grids"):
   and the Ritz extremes of the Lanczos process from a right-hand side;
 * ``mixed`` -- the paper's own mesher with mixed cells (grid points moved onto the
   body along grid lines, node splitting, triangles, pentagons cut into a triangle
-  and a quadrilateral) and the stream-function solve on it (P1 and Q1 elements).
+  and a quadrilateral) and the stream-function solve on it (P1 and Q1 elements);
+* ``kutta`` -- the Kutta condition as a constraint: psi at an added fluid point
+  equals the body's psi_b, in place of the body's zero-circulation row (section
+  "Boundary Conditions"), and the exact lifting cylinder that pins it.
 
 Readings of passages where the paper is silent or ambiguous are listed in the
 module docstrings where they are applied.
