@@ -21,6 +21,8 @@
  *   mfp_contour        contour lines of psi or phi: the flow net and the stagnation
  *                      streamlines of the transverse cylinders ("Effect of Gap Ratio");
  *   mfp_element_apply  the matrix-free element product of Algorithm 1 on its own;
+ *   mfp_psi_solve_kutta  the trailing-edge (Kutta) constraint of section "Boundary
+ *                      Conditions": psi at an added fluid point equals psi_b;
  *   mfp_mixed_*        the mixed-cell variant of the body-conforming grid (cut points
  *                      on the grid lines, triangles and quadrilaterals) with its
  *                      element product and constrained solve;
@@ -412,6 +414,42 @@ int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h, const mfp_cir
                           int32_t iters_per_launch, int32_t pair_lo, int32_t pair_hi,
                           double* psi_b_h, double* copfi_h, mfp_stats* stats_h, void* ws,
                           size_t ws_bytes, void* stream);
+
+/* ---- Kutta constraints ------------------------------------------------------------
+ * Section "Boundary Conditions" (trailing-edge paragraph): where the flow must leave a
+ * body at a given place, a point is added in the fluid and the dividing streamline
+ * psi = psi_b is made to pass through it.  For each body b with a Kutta point, the
+ * equation psi(K_b) = psi_b replaces the body's zero-circulation row of the
+ * constrained system (psi_b stays one unknown shared by the body's nodes; the body
+ * then carries the circulation the flow needs); other bodies keep zero circulation.
+ * K_b is the grid node nearest to the given point in undisplaced coordinates,
+ * i = floor((x - x0)/hx + 1/2), j likewise; it must be a fluid node off the
+ * Dirichlet sides (no node is moved: place the point on a grid node to have it
+ * exactly).  The system is no longer symmetric; it is solved by superposition of
+ * constrained CG solves (mfp_psi_solve's kernels and options): S0 with every Kutta
+ * body held at 0, and per Kutta body k one solve without side data (U = 0) with body
+ * k held at 1 and the others at 0; psi = S0 + sum_k c_k S_k with the nk x nk system
+ * S0(K_j) + sum_k c_k S_k(K_j) = c_j solved on the host (psi_b of Kutta body k is
+ * c_k).  Costs nk + 1 solves. */
+
+/* Workspace bytes for mfp_psi_solve_kutta with nkutta Kutta points (0 if invalid). */
+size_t mfp_kutta_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t nkutta,
+                                const mfp_solver_opts* opts);
+
+/* Stream-function solve with Kutta constraints.  kutta_xy_h: host double[2 nbody],
+ * (x, y) of body b's Kutta point, or (NaN, NaN) for a body without one.  Other
+ * arguments and outputs as mfp_psi_solve (no surface samples, no warm start);
+ * kutta_node_h (host int64[nbody], may be NULL) receives each body's Kutta node or -1.
+ * stats: iterations, applications and solve time summed over the sub-solves,
+ * relres_true their largest, kappa_est that of S0 (if requested).  MFP_E_ARG for a
+ * Kutta point whose node is outside the grid, on a Dirichlet side or inside a body. */
+int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                        const double* disp, const int8_t* kind, const int8_t* body,
+                        const mfp_flow* flow, const mfp_solver_opts* opts,
+                        const double* kutta_xy_h, int32_t pair_lo, int32_t pair_hi,
+                        double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
+                        int64_t* kutta_node_h, mfp_stats* stats_h, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /* ---- mixed-cell mesh ---------------------------------------------------------------
  * The mesh of section "Body-Conforming Grid Generation" that keeps the grid lines:

@@ -36,6 +36,7 @@ EXPORTS = [
     "mfp_element_apply_noalloc", "mfp_solve_workspace_size_opts",
     "mfp_batched_workspace_size_opts", "mfp_mixed_workspace_size", "mfp_mixed_mesh",
     "mfp_mixed_solve_workspace_size", "mfp_mixed_element_apply", "mfp_mixed_psi_solve",
+    "mfp_kutta_workspace_size", "mfp_psi_solve_kutta",
 ]
 
 
@@ -166,6 +167,14 @@ def load(path: str = LIB_PATH):
         c_int32, POINTER(MfpVariant), POINTER(MfpCircle), c_int32, POINTER(MfpFlow),
         POINTER(MfpSolverOpts), c_int32, c_int32, c_int32, POINTER(c_double),
         POINTER(c_double), POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
+    lib.mfp_kutta_workspace_size.restype = c_size_t
+    lib.mfp_kutta_workspace_size.argtypes = [POINTER(MfpGrid), c_int32, c_int32,
+                                             POINTER(MfpSolverOpts)]
+    lib.mfp_psi_solve_kutta.argtypes = [
+        POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_void_p, c_void_p, c_void_p,
+        POINTER(MfpFlow), POINTER(MfpSolverOpts), POINTER(c_double), c_int32, c_int32,
+        c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double), POINTER(c_int64),
+        POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
     lib.mfp_mixed_workspace_size.restype = c_size_t
     lib.mfp_mixed_workspace_size.argtypes = [POINTER(MfpGrid), c_int32]
     lib.mfp_mixed_mesh.argtypes = [POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_int32,
@@ -659,3 +668,50 @@ def mixed_psi_solve(mm: MixedMesh, flow, *, precision="fp64", rtol=1e-12, kmax=1
         psib, byref(Q), byref(cop), byref(st), _ptr(ws), ws.numel(), _stream()), allow_warn)
     stats = {k: getattr(st, k) for k, _ in MfpStats._fields_}
     return MixedSolveResult(psi, [psib[k] for k in range(nb)], Q.value, cop.value, stats, status)
+
+
+@dataclass
+class KuttaResult:
+    psi: torch.Tensor
+    psi_b: list
+    Q: float
+    copfi: float
+    kutta_nodes: list
+    stats: dict
+    status: int
+
+
+def psi_solve_kutta(grid, circles, disp, kind, body, flow, kutta_points, *, precision="fp64",
+                    rtol=1e-12, kmax=10 ** 7, check_every=16, inner_rtol=0.1, max_outer=1000,
+                    pair=(-1, -1), estimate_kappa: bool = False,
+                    schedule: Optional[dict] = None, allow_warn: bool = True) -> KuttaResult:
+    """Solve with Kutta constraints: kutta_points holds one (x, y) or None per body."""
+    lib = load()
+    g = make_grid(grid)
+    c = make_circles(circles)
+    nb = len(circles)
+    if len(kutta_points) != nb:
+        raise ValueError("one Kutta point (or None) per body")
+    f = make_flow(flow)
+    o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa,
+              schedule)
+    kxy = (c_double * max(2 * nb, 2))()
+    for b, pt in enumerate(kutta_points):
+        kxy[2 * b], kxy[2 * b + 1] = (float("nan"), float("nan")) if pt is None else (
+            float(pt[0]), float(pt[1]))
+    nk = sum(pt is not None for pt in kutta_points)
+    dev = disp.device
+    psi = torch.empty((g.nx + 1) * (g.ny + 1), dtype=torch.float64, device=dev)
+    psib = (c_double * max(nb, 1))()
+    Q = c_double(float("nan"))
+    cop = c_double(float("nan"))
+    kn = (c_int64 * max(nb, 1))()
+    st = MfpStats()
+    ws = workspace(lib.mfp_kutta_workspace_size(byref(g), nb, nk, byref(o)), dev)
+    status = _check(lib.mfp_psi_solve_kutta(
+        byref(g), c, nb, _ptr(disp), _ptr(kind), _ptr(body), byref(f), byref(o), kxy,
+        int(pair[0]), int(pair[1]), _ptr(psi), psib, byref(Q), byref(cop), kn, byref(st),
+        _ptr(ws), ws.numel(), _stream()), allow_warn)
+    stats = {k: getattr(st, k) for k, _ in MfpStats._fields_}
+    return KuttaResult(psi, [psib[k] for k in range(nb)], Q.value, cop.value,
+                       [kn[k] for k in range(nb)], stats, status)

@@ -57,6 +57,8 @@ struct SetupArgs {
   double* p1;
   double* q;
   long long* nfree;
+  unsigned long long fixed_mask;  // bit b: body b held at the value fixed[b] (Dirichlet)
+  double fixed[MFP_MAX_BODIES];
 };
 
 __device__ double side_value(int code, double x, double y, const SetupArgs& a) {
@@ -103,7 +105,10 @@ __global__ void k_setup(SetupArgs a) {
       const bool right = i == a.nx && a.bc[1] != MFP_BC_NATURAL;
       const bool bot = j == 0 && a.bc[2] != MFP_BC_NATURAL;
       const bool top = j == a.ny && a.bc[3] != MFP_BC_NATURAL;
-      if (b >= 0) {
+      if (b >= 0 && !a.phi && ((a.fixed_mask >> b) & 1ull)) {
+        tg = TAG_DIR;  // a body held at a given value: its nodes are Dirichlet nodes
+        gv = a.fixed[b];
+      } else if (b >= 0) {
         tg = a.phi ? tag_potential_body(b) : (int8_t)(TAG_BODY0 + b);
         if (a.phi && node_in_domain(a.body, a.nx, a.ny, i, j)) ++cnt;
       } else if (left || right || bot || top) {
@@ -731,6 +736,8 @@ struct SolveWs {
   double* kc64 = nullptr;   // slabs for an FP64 iteration
   float* kc32 = nullptr;    // slabs for an FP32 iteration
   const double* cellcoef = nullptr;  // per-cell element entries given by the caller
+  unsigned long long fixed_mask = 0;  // bodies held at given values (Dirichlet), bit b
+  double fixed[MFP_MAX_BODIES] = {};
 };
 
 // Task height of a single solve's layout.  The FP32 iteration with 8-row tasks uses
@@ -1065,6 +1072,8 @@ static int setup(const mfp_grid& g, const mfp_circle* circles_h, int nb, const d
   s.q = w.q;
   s.nfree = w.nfree;
   s.phi = w.phi;
+  s.fixed_mask = w.fixed_mask;
+  for (int b = 0; b < MFP_MAX_BODIES; ++b) s.fixed[b] = w.fixed[b];
   if (w.L.nstrip > SEG_MAX_STRIPS || w.L.nchunk > 0xffff ||
       (unsigned long long)w.L.n * sizeof(double) >= (1ull << 32)) {
     set_error("grid too large (nx <= %d, ny <= %d, padded nodes < 2^29)",
@@ -1942,6 +1951,227 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
   if (n_samples_h) *n_samples_h = nsamp;
   MFP_TRY(fill_stats(w, info, nb, hsd, st, stats_h));
   return finish_status(info);
+}
+
+namespace mfp {
+
+// ---- Kutta constraints ---------------------------------------------------------------
+// psi(K_b) = psi_b in place of body b's zero-circulation row.  The system stays
+// linear, and with those bodies held at given values it is the constrained system
+// of the other bodies: psi = S0 + sum_k c_k S_k, where S0 is the solve with every
+// Kutta body held at 0 and S_k the solve without side data (U = 0) with Kutta body
+// k held at 1 and the other Kutta bodies at 0.  The Kutta rows then read
+// S0(K_j) + sum_k c_k S_k(K_j) = c_j, an nk x nk system solved on the host; psi_b of
+// a Kutta body is c_b.
+
+// psi += c * s over the (unpadded) nodes
+__global__ void k_axpy_nodes(long long n, double c, const double* __restrict__ s,
+                             double* __restrict__ psi) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n;
+       e += (long long)gridDim.x * blockDim.x)
+    psi[e] += c * s[e];
+}
+
+// Dense nk x nk solve by Gaussian elimination with partial pivoting (nk <= 64).
+static bool dense_solve(int n, std::vector<double>& A, std::vector<double>& b) {
+  for (int k = 0; k < n; ++k) {
+    int piv = k;
+    for (int r = k + 1; r < n; ++r)
+      if (std::fabs(A[r * n + k]) > std::fabs(A[piv * n + k])) piv = r;
+    if (!(std::fabs(A[piv * n + k]) > 0.0)) return false;
+    if (piv != k) {
+      for (int c = 0; c < n; ++c) std::swap(A[k * n + c], A[piv * n + c]);
+      std::swap(b[k], b[piv]);
+    }
+    for (int r = k + 1; r < n; ++r) {
+      const double f = A[r * n + k] / A[k * n + k];
+      for (int c = k; c < n; ++c) A[r * n + c] -= f * A[k * n + c];
+      b[r] -= f * b[k];
+    }
+  }
+  for (int k = n - 1; k >= 0; --k) {
+    double v = b[k];
+    for (int c = k + 1; c < n; ++c) v -= A[k * n + c] * b[c];
+    b[k] = v / A[k * n + k];
+  }
+  return true;
+}
+
+}  // namespace mfp
+
+extern "C" size_t mfp_kutta_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t nkutta,
+                                           const mfp_solver_opts* opts) {
+  if (!grid || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES ||
+      nkutta < 0 || nkutta > nbody)
+    return 0;
+  Schedule sc;
+  if (resolve_schedule(grid, opts ? opts->precision : MFP_FP64, opts, &sc) != MFP_OK) return 0;
+  const size_t solve = solve_layout(grid, nbody, opts ? opts->precision : MFP_FP64, nullptr,
+                                    nullptr, &sc);
+  const size_t nn = (size_t)(grid->nx + 1) * (grid->ny + 1);
+  return ((solve + 255) & ~size_t(255)) + (size_t)nkutta * nn * sizeof(double) + 256;
+}
+
+extern "C" int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circles_h,
+                                   int32_t nbody, const double* disp, const int8_t* kind,
+                                   const int8_t* body, const mfp_flow* flow,
+                                   const mfp_solver_opts* opts, const double* kutta_xy_h,
+                                   int32_t pair_lo, int32_t pair_hi, double* psi,
+                                   double* psi_b_h, double* Q_h, double* copfi_h,
+                                   int64_t* kutta_node_h, mfp_stats* stats_h, void* ws,
+                                   size_t ws_bytes, void* stream_) {
+  clear_error();
+  MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, kind, body, flow, opts, ws));
+  if (!psi || !kutta_xy_h || (nbody > 0 && !psi_b_h) || pair_lo >= nbody || pair_hi >= nbody) {
+    set_error("NULL argument or pair index out of range");
+    return MFP_E_ARG;
+  }
+  if (opts->psi0) {
+    set_error("no warm start with Kutta constraints");
+    return MFP_E_ARG;
+  }
+  const mfp_grid& g = *grid;
+  const double hx = grid_hx(g), hy = grid_hy(g);
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  hipStream_t st = static_cast<hipStream_t>(stream_);
+  // Kutta bodies and their nodes: the grid node nearest to the point
+  std::vector<int> kb;
+  std::vector<long long> kn;
+  for (int b = 0; b < nbody; ++b) {
+    const double px = kutta_xy_h[2 * b], py = kutta_xy_h[2 * b + 1];
+    if (kutta_node_h) kutta_node_h[b] = -1;
+    if (std::isnan(px) && std::isnan(py)) continue;
+    if (!std::isfinite(px) || !std::isfinite(py)) {
+      set_error("Kutta point of body %d is not finite", b);
+      return MFP_E_ARG;
+    }
+    const double fi = std::floor((px - g.x0) / hx + 0.5), fj = std::floor((py - g.y0) / hy + 0.5);
+    const bool side = (fi == 0 && flow->side_bc[0] != MFP_BC_NATURAL) ||
+                      (fi == g.nx && flow->side_bc[1] != MFP_BC_NATURAL) ||
+                      (fj == 0 && flow->side_bc[2] != MFP_BC_NATURAL) ||
+                      (fj == g.ny && flow->side_bc[3] != MFP_BC_NATURAL);
+    if (!(fi >= 0 && fi <= g.nx && fj >= 0 && fj <= g.ny) || side) {
+      set_error("Kutta point of body %d: its node is outside the grid or on a Dirichlet side", b);
+      return MFP_E_ARG;
+    }
+    const long long n = (long long)fj * (g.nx + 1) + (long long)fi;
+    int8_t bn = 0;
+    MFP_TRY_HIP(hipMemcpyAsync(&bn, body + n, 1, hipMemcpyDeviceToHost, st));
+    MFP_TRY_HIP(hipStreamSynchronize(st));
+    if (bn >= 0) {
+      set_error("Kutta point of body %d: its node lies inside a body", b);
+      return MFP_E_ARG;
+    }
+    kb.push_back(b);
+    kn.push_back(n);
+    if (kutta_node_h) kutta_node_h[b] = n;
+  }
+  const int nk = (int)kb.size();
+  const size_t need = mfp_kutta_workspace_size(grid, nbody, nk, opts);
+  if (need == 0) {
+    set_error("invalid schedule options");
+    return MFP_E_ARG;
+  }
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  Schedule sc;
+  MFP_TRY(resolve_schedule(grid, opts->precision, opts, &sc));
+  const size_t solve_bytes = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, &sc);
+  double* fields = reinterpret_cast<double*>(static_cast<char*>(ws) +
+                                             ((solve_bytes + 255) & ~size_t(255)));
+  unsigned long long mask = 0;
+  for (int b : kb) mask |= 1ull << b;
+  mfp_flow zero_flow = *flow;
+  zero_flow.U = 0.0;
+  // sub-solve s = 0 (S0) into psi, s = 1 + k (S_k) into fields[k]
+  std::vector<double> at(((size_t)nk + 1) * (nk > 0 ? nk : 1));   // S_s(K_j)
+  std::vector<double> pb(((size_t)nk + 1) * (nbody > 0 ? nbody : 1));  // S_s body values
+  SolveInfo total;
+  double relres_max = 0.0;
+  DevState hsd0{};
+  SolveWs w0;
+  for (int s = 0; s <= nk; ++s) {
+    SolveWs w;
+    solve_layout(grid, nbody, opts->precision, ws, &w, &sc);
+    w.fixed_mask = mask;
+    for (int q = 0; q < nk; ++q) w.fixed[kb[q]] = (s >= 1 && q == s - 1) ? 1.0 : 0.0;
+    mfp_solver_opts o = *opts;
+    if (s > 0) o.estimate_kappa = 0;
+    SolveInfo info;
+    MFP_TRY(solve_core(g, circles_h, nbody, disp, body, s == 0 ? flow : &zero_flow, &o, nullptr,
+                       false, w, st, &info));
+    double* out = s == 0 ? psi : fields + (size_t)(s - 1) * nn;
+    k_output<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, w.x, w.g, w.st, out,
+                                                 -1, -1, 0.0, 0.0, 0.0);
+    MFP_TRY_HIP(hipGetLastError());
+    DevState hsd;
+    MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+    for (int j = 0; j < nk; ++j)
+      MFP_TRY_HIP(hipMemcpyAsync(&at[(size_t)s * nk + j], out + kn[j], sizeof(double),
+                                 hipMemcpyDeviceToHost, st));
+    MFP_TRY_HIP(hipStreamSynchronize(st));
+    for (int b = 0; b < nbody; ++b) pb[(size_t)s * nbody + b] = hsd.xb[hsd.iters & 1][b];
+    for (int q = 0; q < nk; ++q) pb[(size_t)s * nbody + kb[q]] = (s >= 1 && q == s - 1) ? 1.0 : 0.0;
+    if (s == 0) {
+      total = info;
+      hsd0 = hsd;
+      w0 = w;
+    } else {
+      total.iters += info.iters;
+      total.inner += info.inner;
+      total.outer += info.outer;
+      total.applies += info.applies;
+      total.solve_ms += info.solve_ms;
+      if (info.done != 1 && total.done == 1) total.done = info.done;
+      total.stagnated = total.stagnated || info.stagnated;
+    }
+    if (stats_h) {
+      mfp_stats one;
+      MFP_TRY(fill_stats(w, info, nbody, hsd, st, &one));
+      relres_max = std::max(relres_max, one.relres_true);
+    }
+    if (info.done == 2) return finish_status(info);  // breakdown: no result
+  }
+  // the Kutta rows: (I - M) c = S0(K), M_jk = S_k(K_j)
+  std::vector<double> c(nk);
+  if (nk > 0) {
+    std::vector<double> A((size_t)nk * nk), rhs(nk);
+    for (int j = 0; j < nk; ++j) {
+      rhs[j] = at[j];
+      for (int k = 0; k < nk; ++k)
+        A[(size_t)j * nk + k] = (j == k ? 1.0 : 0.0) - at[(size_t)(k + 1) * nk + j];
+    }
+    if (!dense_solve(nk, A, rhs)) {
+      set_error("Kutta system singular");
+      return MFP_E_BREAKDOWN;
+    }
+    c = rhs;
+    for (int k = 0; k < nk; ++k) {
+      k_axpy_nodes<<<grid_blocks(nn), BLOCK, 0, st>>>(nn, c[k], fields + (size_t)k * nn, psi);
+      MFP_TRY_HIP(hipGetLastError());
+    }
+  }
+  for (int b = 0; b < nbody; ++b) {
+    double v = pb[b];
+    for (int k = 0; k < nk; ++k) v += c[k] * pb[(size_t)(k + 1) * nbody + b];
+    psi_b_h[b] = v;
+  }
+  if (pair_lo >= 0 && pair_hi >= 0) {
+    const double Q = psi_b_h[pair_hi] - psi_b_h[pair_lo];
+    if (Q_h) *Q_h = Q;
+    if (copfi_h) *copfi_h = Q / (flow->U * (circles_h[pair_hi].cy - circles_h[pair_lo].cy));
+  }
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  if (stats_h) {
+    MFP_TRY(fill_stats(w0, total, nbody, hsd0, st, stats_h));
+    stats_h->iters = total.iters;
+    stats_h->applies = total.applies;
+    stats_h->solve_ms = total.solve_ms;
+    stats_h->relres_true = relres_max;
+  }
+  return finish_status(total);
 }
 
 namespace mfp {
