@@ -34,6 +34,9 @@ Body-Conforming Grids"):
 * ``mixed`` -- the paper's own mesher with mixed cells (grid points moved onto the
   body along grid lines, node splitting, triangles, pentagons cut into a triangle
   and a quadrilateral) and the stream-function solve on it (P1 and Q1 elements);
+* ``airfoil`` -- bodies with a sharp trailing edge (Joukowski airfoils) for the
+  mixed-cell mesh: inside test, cut points along grid lines, and the exact flow
+  with any circulation and with the Kutta circulation;
 * ``kutta`` -- the Kutta condition as a constraint: psi at an added fluid point
   equals the body's psi_b, in place of the body's zero-circulation row (section
   "Boundary Conditions"), and the exact lifting cylinder that pins it.

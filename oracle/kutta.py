@@ -123,3 +123,56 @@ def circulation_through(point, U, centre, a):
     y = point[1] - centre[1]
     r = np.hypot(x, y)
     return 2.0 * np.pi * U * y * (1.0 - a * a / (r * r)) / np.log(r / a)
+
+
+def mixed_solve_kutta(mm, flow, kutta_points, g=None):
+    """The Kutta rows on the mixed-cell mesh: as solve_kutta, with the mixed mesh's
+    unknowns (background fluid nodes of some element off the Dirichlet sides, one
+    psi_b per body for all its cut points).  Returns a KuttaSolution over the mixed
+    nodes (inside nodes 0; body_rows summed over each body's cut points)."""
+    from .mixed import assemble_mixed
+    grid = mm.grid
+    nb = len(mm.circles)
+    if len(kutta_points) != nb:
+        raise KuttaError("one Kutta point (or None) per body")
+    N = grid.nodes
+    n = mm.n_nodes
+    K = assemble_mixed(mm)
+    if g is None:
+        g = np.concatenate([dirichlet_values(grid, flow, mm.circles), np.zeros(len(mm.pxy))])
+    dmask = np.concatenate([dirichlet_mask(grid, flow).ravel() & (mm.body.ravel() < 0),
+                            np.zeros(len(mm.pxy), bool)])
+    g = np.where(dmask, np.asarray(g, dtype=float), 0.0)
+    used = np.zeros(n, bool)
+    used[mm.elem_nodes[mm.elem_nodes >= 0]] = True
+    free = used & ~dmask
+    free[N:] = False
+    dof = np.full(n, -1, dtype=np.int64)
+    nfree = int(free.sum())
+    dof[free] = np.arange(nfree)
+    dof[N:] = nfree + mm.pbody
+    ndof = nfree + nb
+    T = selection_matrix(dof, ndof)
+    A = (T.T @ K @ T).tolil()
+    rhs = -(T.T @ (K @ g))
+    knodes = []
+    for b, pt in enumerate(kutta_points):
+        if pt is None:
+            knodes.append(-1)
+            continue
+        kn = kutta_node(grid, pt)
+        if dof[kn] < 0 or dof[kn] >= nfree:
+            raise KuttaError("Kutta point must be a fluid node of the mesh off the "
+                             "Dirichlet sides")
+        knodes.append(kn)
+        r = nfree + b
+        A.rows[r] = []
+        A.data[r] = []
+        A[r, dof[kn]] = 1.0
+        A[r, r] = -1.0
+        rhs[r] = 0.0
+    y = spla.splu(sp.csc_matrix(A)).solve(rhs) if ndof > 0 else np.zeros(0)
+    psi = g + T @ y
+    Kpsi = K @ psi
+    rows = np.array([Kpsi[N:][mm.pbody == b].sum() for b in range(nb)])
+    return KuttaSolution(psi, y[nfree:].copy(), rows, knodes, nfree)

@@ -62,7 +62,9 @@ import numpy as np
 import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
-from .mesh import GeometryError, check_geometry, classify, spacing, node_coords, jacobi_weights
+from .mesh import (GeometryError, check_geometry, spacing, node_coords, jacobi_weights, FLUID,
+                   SNAPPED, DEEP)
+from .airfoil import Circle
 from .fem import element_stiffness
 from .solve import dirichlet_values, dirichlet_mask
 
@@ -127,9 +129,32 @@ class MixedMesh:
         return x, y
 
 
-def cut_points(grid, circles, body):
-    """Cut points of the grid edges that join an inside node to a fluid node (step 2).
-    Returns (hpt, vpt, pxy, pbody)."""
+def classify_bodies(grid, bodies):
+    """Body of every node (the last body whose contains() holds, -1 for fluid) and
+    the node kinds of the Q1 mesh's rule (a body node with a fluid node among its
+    eight neighbours is SNAPPED, else DEEP).  Returns (kind, body), (ny+1, nx+1)."""
+    X, Y = node_coords(grid)
+    body = np.full(X.shape, -1, dtype=np.int8)
+    for b, bd in enumerate(bodies):
+        body[bd.contains(X, Y)] = b
+    isbody = body >= 0
+    fluid = ~isbody
+    pad = np.pad(fluid, 1, constant_values=False)
+    near_fluid = np.zeros_like(fluid)
+    ny1, nx1 = fluid.shape
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            near_fluid |= pad[1 + dj:1 + dj + ny1, 1 + di:1 + di + nx1]
+    kind = np.full(X.shape, FLUID, dtype=np.int8)
+    kind[isbody & near_fluid] = SNAPPED
+    kind[isbody & ~near_fluid] = DEEP
+    return kind, body
+
+
+def cut_points(grid, bodies, body):
+    """Cut points of the grid edges that join an inside node to a fluid node (step 2),
+    each from its body's cut(): for a circle the root t in [0, 1) of
+    |I + t (O - I) - c| = r.  Returns (hpt, vpt, pxy, pbody)."""
     hx, hy = spacing(grid)
     X, Y = node_coords(grid)
     nx, ny = grid.nx, grid.ny
@@ -151,11 +176,7 @@ def cut_points(grid, circles, body):
             c = (j, i + 1) if horizontal else (j + 1, i)
             inside, outside = (a, c) if body[a] >= 0 else (c, a)
             b = int(body[inside])
-            cx, cy, r = circles[b]
-            ux, uy = X[inside] - cx, Y[inside] - cy
-            vx, vy = X[outside] - X[inside], Y[outside] - Y[inside]
-            t = _edge_root(ux, uy, vx, vy, r)
-            pts.append((X[inside] + t * vx, Y[inside] + t * vy))
+            pts.append(bodies[b].cut(X[inside], Y[inside], X[outside], Y[outside]))
             pb.append(b)
             (hpt if horizontal else vpt)[j, i] = len(pts) - 1
     pxy = np.array(pts, dtype=float).reshape(-1, 2)
@@ -283,10 +304,19 @@ def _cell_polygons(grid, body, hpt, vpt, pxy):
 
 
 def mixed_mesh(grid, circles, nsweeps=200):
-    """Steps 1-5: the mixed-cell mesh."""
+    """Steps 1-5: the mixed-cell mesh of circles (cx, cy, r)."""
+    return mixed_mesh_bodies(grid, [Circle(float(cx), float(cy), float(r))
+                                    for cx, cy, r in circles], nsweeps)
+
+
+def mixed_mesh_bodies(grid, bodies, nsweeps=200):
+    """The mixed-cell mesh of bodies with contains() and cut() (circles, airfoils).
+    The geometry checks use each body's bounding circle, which the mesh also keeps
+    (its centre is the reference point of the surface-sample angles)."""
+    circles = [bd.bounding_circle() for bd in bodies]
     check_geometry(grid, circles)
-    kind, body = classify(grid, circles)
-    hpt, vpt, pxy, pbody = cut_points(grid, circles, body)
+    kind, body = classify_bodies(grid, bodies)
+    hpt, vpt, pxy, pbody = cut_points(grid, bodies, body)
     d = smooth_mixed(grid, body, hpt, vpt, pxy, nsweeps)
     polys = _cell_polygons(grid, body, hpt, vpt, pxy)
     ne = len(polys)
