@@ -36,10 +36,15 @@ listed with the passage it follows):
    cut edges meet the circle there) is a sliver of no area and is not meshed: the
    smallest case of the paper's minimum spacing of boundary points, which changes
    the equations by O(1e-12 h);
-5. inputs this reading cannot mesh are rejected (GeometryError): besides the
+5. a cell whose inside and fluid corners alternate around it (a thin part of a
+   body, a trailing edge above all, crosses it diagonally; impossible for a circle
+   of radius >= 2h) has two separate fluid parts: each fluid corner k gets the
+   triangle (cut point of edge k-1, corner k, cut point of edge k), in corner
+   order, each subject to the sliver rule -- the corner treatment of section
+   "Boundary Conditions" read as node splitting of the inside corners;
+   inputs this reading cannot mesh are rejected (GeometryError): besides the
    quadrilateral mesher's checks, a grid edge or cell whose nodes lie in two
-   different bodies, and a cell with inside and fluid corners alternating around
-   it (impossible for a single circle);
+   different bodies;
 6. elements: triangles are linear (P1, exact integral), quadrilaterals bilinear
    (Q1, 2x2 Gauss) as in section "Weak formulation"; beyond the sliver rule of
    step 4 the paper's minimum-spacing redistribution of boundary points is omitted
@@ -282,8 +287,16 @@ def _cell_polygons(grid, body, hpt, vpt, pxy):
                     poly.append(edge_point(k))
             nf = 4 - sum(ins)
             changes = sum(ins[k] != ins[(k + 1) % 4] for k in range(4))
-            if changes != 2:
-                raise GeometryError("inside and fluid corners alternate in a cell")
+            if changes == 4:
+                # two fluid parts: a triangle at each fluid corner
+                for k in range(4):
+                    if ins[k]:
+                        continue
+                    pa, pb = edge_point((k + 3) % 4), edge_point(k)
+                    gap = np.abs(pxy[pa - N] - pxy[pb - N]).max()
+                    if not gap < SLIVER * hmax:
+                        out.append((cid, [pa, ids[k], pb]))
+                continue
             if nf == 1:
                 # a triangle whose two cut points (nearly) coincide is a sliver of no
                 # area (its fluid corner lies on the circle to rounding): not meshed

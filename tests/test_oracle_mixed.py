@@ -264,3 +264,32 @@ def test_smoother_mirror_symmetry_and_finite_propagation():
     for j, i in zip(J, I):
         near[max(0, j - k):j + k + 1, max(0, i - k):i + k + 1] = True
     assert moved.any() and not (moved & ~near).any()
+
+
+def test_alternating_cell_gets_a_triangle_per_fluid_corner():
+    """A cell with inside corners (0, 0) and (1, 1) and fluid corners (1, 0) and
+    (0, 1) (a thin body crossing it diagonally): one triangle at each fluid corner,
+    (cut point of the edge before it, the corner, cut point of the edge after it), in
+    corner order."""
+    g = W.Grid(2, 2, 0.0, 2.0, 0.0, 2.0)
+    body = np.full((3, 3), -1, dtype=np.int8)
+    body[0, 0] = body[1, 1] = 0
+    hpt = np.full((3, 2), -1, dtype=np.int64)
+    vpt = np.full((2, 3), -1, dtype=np.int64)
+    pts = []
+
+    def add(table, j, i, x, y):
+        table[j, i] = len(pts)
+        pts.append((x, y))
+    add(hpt, 0, 0, 0.4, 0.0)   # edge 0 of cell (0, 0): (0,0)-(1,0)
+    add(vpt, 0, 1, 1.0, 0.6)   # edge 1: (1,0)-(1,1)
+    add(hpt, 1, 0, 0.6, 1.0)   # edge 2: (1,1)-(0,1)
+    add(vpt, 0, 0, 0.0, 0.4)   # edge 3: (0,1)-(0,0)
+    pxy = np.array(pts)
+    polys = [p for p in M._cell_polygons(g, body, hpt, vpt, pxy) if p[0] == 0]
+    N = g.nodes
+    assert [ids for _, ids in polys] == [[N + 0, 1, N + 1], [N + 2, 3, N + 3]]
+    x = np.concatenate([O.node_coords(g)[0].ravel(), pxy[:, 0]])
+    y = np.concatenate([O.node_coords(g)[1].ravel(), pxy[:, 1]])
+    for _, ids in polys:
+        assert M.polygon_area(x[ids], y[ids]) > 0.0   # counter-clockwise
