@@ -464,9 +464,12 @@ int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circles_h, int32
  * lie within 1e-12 max(hx, hy) of each other (max norm) has no area and is not meshed.
  * Fluid nodes are then moved by `nsweeps` Jacobi sweeps of the displacement (weights
  * as for mfp_mesh_conform, start 0, outer-boundary nodes fixed) in which an inside
- * neighbour contributes its cut point's displacement P - I.  Cells with corners in two
- * bodies, grid edges joining two bodies and cells whose inside and fluid corners
- * alternate are rejected (MFP_E_GEOMETRY).
+ * neighbour contributes its cut point's displacement P - I.  A cell whose inside and
+ * fluid corners alternate (a thin part of a body, e.g. a trailing edge, crosses it)
+ * gets a triangle at each fluid corner (cut point of the edge before it, the corner,
+ * cut point of the edge after it), in corner order, slivers dropped.  Cells with
+ * corners in two bodies and grid edges joining two bodies are rejected
+ * (MFP_E_GEOMETRY).
  * Mixed-node numbering: background nodes j (nx+1) + i (inside ones unused), then the
  * cut points, numbered in edge order: horizontal edges (edge j nx + i joins (i, j) and
  * (i+1, j)), then vertical ones (edge (ny+1) nx + j (nx+1) + i joins (i, j), (i, j+1)).
@@ -492,6 +495,38 @@ typedef struct {
   int64_t n_tri;         /* out: triangles among them                                       */
 } mfp_mixed_mesh_t;
 
+/* Bodies of the mixed-cell mesh beyond circles (section "Boundary Conditions": bodies
+ * with corners and trailing edges; "Practical Applications": airfoil clusters).
+ * MFP_BODY_JOUKOWSKI: the Joukowski map z' = zeta + c^2/zeta of the circle
+ * |zeta - zeta0| = R through zeta = c (R^2 = (c - xi0)^2 + eta0^2): an airfoil with a
+ * cusped trailing edge at z' = 2c (chord about 4c; xi0 < 0 thickness, eta0 > 0
+ * camber), placed as z = (x, y) + e^{-i alpha} z' (angle of attack alpha against the
+ * horizontal free stream).  A point is inside (boundary included) iff both roots of
+ * zeta^2 - w zeta + c^2 = 0, w = e^{i alpha}(z - (x, y)), lie in the closed circle,
+ * i.e. |zeta - zeta0|^2 - R^2 <= 0 for the root farther from zeta0 (the map is one to
+ * one from outside the circle onto outside the airfoil).  A grid edge from an inside
+ * node I to a fluid node O is cut at I + t (O - I): t from the first sign change of
+ * that level among t = k/64, then 60 bisections (the inside end kept).  A trailing
+ * edge thinner than the grid is not resolved (an edge with two fluid ends is never
+ * cut).  All in FP64 without fused multiply-add; cos alpha and sin alpha from the C
+ * library. */
+#define MFP_BODY_CIRCLE 0
+#define MFP_BODY_JOUKOWSKI 1
+
+typedef struct {
+  int32_t kind;       /* MFP_BODY_CIRCLE or MFP_BODY_JOUKOWSKI                          */
+  double x, y;        /* circle centre; airfoil: position of the image of zeta = 0      */
+  double r;           /* circle radius; airfoil: the map constant c > 0                 */
+  double xi0, eta0;   /* airfoil: centre of the generating circle, -c <= xi0 <= 0       */
+  double alpha;       /* airfoil: angle of attack (radians)                             */
+} mfp_body;
+
+/* Host only: for each body a circle that holds it (the circle itself; an airfoil:
+ * about (x, y), 1.01 x the largest distance of 4097 boundary samples).  The mixed
+ * mesh's geometry checks and the solves' circle arguments (Q, CoPFI, the
+ * isolated-cylinder side data) use these.  MFP_E_ARG for an invalid body. */
+int mfp_body_bounds(const mfp_body* bodies_h, int32_t nbody, mfp_circle* bounds_h);
+
 /* Workspace bytes for mfp_mixed_mesh (0 for an invalid grid or body count). */
 size_t mfp_mixed_workspace_size(const mfp_grid* grid, int32_t nbody);
 
@@ -503,6 +538,12 @@ size_t mfp_mixed_workspace_size(const mfp_grid* grid, int32_t nbody);
 int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
                    int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
                    void* stream);
+
+/* mfp_mixed_mesh for general bodies (circles and airfoils, see mfp_body): the same
+ * mesh (for circles bit for bit), the geometry checks on mfp_body_bounds' circles. */
+int mfp_mixed_mesh_bodies(const mfp_grid* grid, const mfp_body* bodies_h, int32_t nbody,
+                          int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* Workspace bytes for mfp_mixed_element_apply / mfp_mixed_psi_solve on a mixed mesh of
  * n_points cut points and n_elems elements with these solver options (NULL: FP64 and
@@ -540,6 +581,22 @@ int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, int32
                         const mfp_solver_opts* opts, int32_t pair_lo, int32_t pair_hi,
                         double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
                         mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for mfp_mixed_psi_solve_kutta with nkutta Kutta points. */
+size_t mfp_mixed_kutta_workspace_size(const mfp_grid* grid, int64_t n_points, int64_t n_elems,
+                                      int32_t nbody, int32_t nkutta,
+                                      const mfp_solver_opts* opts);
+
+/* mfp_mixed_psi_solve with the Kutta constraints of mfp_psi_solve_kutta (kutta_xy_h:
+ * (x, y) or (NaN, NaN) per body; the Kutta node must be a fluid node of the mesh off
+ * the Dirichlet sides; kutta_node_h may be NULL).  circles_h: for airfoils the circles
+ * of mfp_body_bounds.  Outputs as mfp_mixed_psi_solve. */
+int mfp_mixed_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                              const mfp_mixed_mesh_t* m, const mfp_flow* flow,
+                              const mfp_solver_opts* opts, const double* kutta_xy_h,
+                              int32_t pair_lo, int32_t pair_hi, double* psi, double* psi_b_h,
+                              double* Q_h, double* copfi_h, int64_t* kutta_node_h,
+                              mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

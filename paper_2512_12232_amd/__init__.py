@@ -13,7 +13,8 @@ from .binding import (MFP_OK, MFP_W_NOCONV, MFP_W_STAGNATION, MFP_E_ARG, MFP_E_H
                       MFP_E_GEOMETRY, MFP_E_TANGLED, MFP_E_BREAKDOWN, MFP_E_WORKSPACE,
                       MfpError, check_geometry, contour, cubic_fit, element_apply,
                       element_apply_noalloc, MixedMesh, mixed_element_apply, mixed_mesh,
-                      mixed_psi_solve, psi_solve_kutta, last_error, load,
+                      mixed_psi_solve, psi_solve_kutta, mixed_mesh_bodies, body_bounds,
+                      mixed_psi_solve_kutta, last_error, load,
                       mesh_conform, mesh_conform_grad, phi_solve, psi_grad, psi_solve,
                       psi_solve_batched, solve_workspace_size, EXPORTS)
 from .autograd import CoPFIFunction, copfi
@@ -22,7 +23,8 @@ __all__ = ["MFP_OK", "MFP_W_NOCONV", "MFP_W_STAGNATION", "MFP_E_ARG", "MFP_E_HIP
            "MFP_E_GEOMETRY", "MFP_E_TANGLED", "MFP_E_BREAKDOWN", "MFP_E_WORKSPACE",
            "MfpError", "check_geometry", "contour", "cubic_fit", "element_apply",
            "element_apply_noalloc", "MixedMesh", "mixed_element_apply", "mixed_mesh",
-           "mixed_psi_solve", "psi_solve_kutta", "last_error", "load",
+           "mixed_psi_solve", "psi_solve_kutta", "mixed_mesh_bodies", "body_bounds",
+           "mixed_psi_solve_kutta", "last_error", "load",
            "mesh_conform", "mesh_conform_grad", "phi_solve", "psi_grad", "psi_solve",
            "psi_solve_batched",
            "solve_workspace_size", "EXPORTS", "CoPFIFunction", "copfi"]

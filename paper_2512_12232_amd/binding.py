@@ -36,7 +36,8 @@ EXPORTS = [
     "mfp_element_apply_noalloc", "mfp_solve_workspace_size_opts",
     "mfp_batched_workspace_size_opts", "mfp_mixed_workspace_size", "mfp_mixed_mesh",
     "mfp_mixed_solve_workspace_size", "mfp_mixed_element_apply", "mfp_mixed_psi_solve",
-    "mfp_kutta_workspace_size", "mfp_psi_solve_kutta",
+    "mfp_kutta_workspace_size", "mfp_psi_solve_kutta", "mfp_body_bounds",
+    "mfp_mixed_mesh_bodies", "mfp_mixed_kutta_workspace_size", "mfp_mixed_psi_solve_kutta",
 ]
 
 
@@ -87,6 +88,14 @@ class MfpStats(Structure):
 class MfpVariant(Structure):
     _fields_ = [("grid", MfpGrid), ("disp", c_void_p), ("kind", c_void_p), ("body", c_void_p),
                 ("psi", c_void_p)]
+
+
+BODY_CIRCLE, BODY_JOUKOWSKI = 0, 1
+
+
+class MfpBody(Structure):
+    _fields_ = [("kind", c_int32), ("x", c_double), ("y", c_double), ("r", c_double),
+                ("xi0", c_double), ("eta0", c_double), ("alpha", c_double)]
 
 
 class MfpMixedMesh(Structure):
@@ -174,6 +183,17 @@ def load(path: str = LIB_PATH):
         POINTER(MfpGrid), POINTER(MfpCircle), c_int32, c_void_p, c_void_p, c_void_p,
         POINTER(MfpFlow), POINTER(MfpSolverOpts), POINTER(c_double), c_int32, c_int32,
         c_void_p, POINTER(c_double), POINTER(c_double), POINTER(c_double), POINTER(c_int64),
+        POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
+    lib.mfp_body_bounds.argtypes = [POINTER(MfpBody), c_int32, POINTER(MfpCircle)]
+    lib.mfp_mixed_mesh_bodies.argtypes = [POINTER(MfpGrid), POINTER(MfpBody), c_int32, c_int32,
+                                          POINTER(MfpMixedMesh), c_void_p, c_size_t, c_void_p]
+    lib.mfp_mixed_kutta_workspace_size.restype = c_size_t
+    lib.mfp_mixed_kutta_workspace_size.argtypes = [POINTER(MfpGrid), c_int64, c_int64, c_int32,
+                                                   c_int32, POINTER(MfpSolverOpts)]
+    lib.mfp_mixed_psi_solve_kutta.argtypes = [
+        POINTER(MfpGrid), POINTER(MfpCircle), c_int32, POINTER(MfpMixedMesh), POINTER(MfpFlow),
+        POINTER(MfpSolverOpts), POINTER(c_double), c_int32, c_int32, c_void_p,
+        POINTER(c_double), POINTER(c_double), POINTER(c_double), POINTER(c_int64),
         POINTER(MfpStats), c_void_p, c_size_t, c_void_p]
     lib.mfp_mixed_workspace_size.restype = c_size_t
     lib.mfp_mixed_workspace_size.argtypes = [POINTER(MfpGrid), c_int32]
@@ -584,12 +604,49 @@ class MixedMesh:
                             self.n_elems, self.n_points, self.n_elems, self.n_tri)
 
 
-def mixed_mesh(grid, circles, nsweeps: int = 200, device="cuda") -> MixedMesh:
+def make_bodies(bodies: Sequence) -> ctypes.Array:
+    """Bodies as ("circle", cx, cy, r) or ("joukowski", x, y, c, xi0, eta0, alpha)."""
+    arr = (MfpBody * max(1, len(bodies)))()
+    for k, b in enumerate(bodies):
+        if b[0] == "circle":
+            arr[k] = MfpBody(BODY_CIRCLE, float(b[1]), float(b[2]), float(b[3]), 0.0, 0.0, 0.0)
+        elif b[0] == "joukowski":
+            arr[k] = MfpBody(BODY_JOUKOWSKI, *(float(v) for v in b[1:7]))
+        else:
+            raise ValueError(f"unknown body kind {b[0]!r}")
+    return arr
+
+
+def body_bounds(bodies: Sequence) -> list:
+    """The circle that mfp_body_bounds gives for each body: [(cx, cy, r), ...]."""
+    arr = make_bodies(bodies)
+    out = (MfpCircle * max(1, len(bodies)))()
+    _check(load().mfp_body_bounds(arr, len(bodies), out))
+    return [(out[k].cx, out[k].cy, out[k].r) for k in range(len(bodies))]
+
+
+def mixed_mesh_bodies(grid, bodies, nsweeps: int = 200, device="cuda") -> MixedMesh:
+    """Mixed-cell mesh of general bodies (see make_bodies); the mesh's circles are the
+    bodies' bounding circles (mfp_body_bounds)."""
+    return mixed_mesh(grid, body_bounds(bodies), nsweeps, device, _bodies=bodies)
+
+
+def mixed_mesh(grid, circles, nsweeps: int = 200, device="cuda", _bodies=None) -> MixedMesh:
     """Mixed-cell mesh: a sizing call (zero capacities), then the filling call."""
     lib = load()
     g = make_grid(grid)
     c = make_circles(circles)
     nb = len(circles)
+    if _bodies is not None:
+        barr = make_bodies(_bodies)
+
+        def build(m):
+            return lib.mfp_mixed_mesh_bodies(byref(g), barr, nb, int(nsweeps), byref(m),
+                                             _ptr(ws), ws.numel(), _stream())
+    else:
+        def build(m):
+            return lib.mfp_mixed_mesh(byref(g), c, nb, int(nsweeps), byref(m), _ptr(ws),
+                                      ws.numel(), _stream())
     n = (g.nx + 1) * (g.ny + 1)
     disp = torch.empty(2 * n, dtype=torch.float64, device=device)
     body = torch.empty(n, dtype=torch.int8, device=device)
@@ -598,8 +655,7 @@ def mixed_mesh(grid, circles, nsweeps: int = 200, device="cuda") -> MixedMesh:
     first = torch.empty(g.nx * g.ny + 1, dtype=torch.int32, device=device)
     ws = workspace(lib.mfp_mixed_workspace_size(byref(g), nb), device)
     m = MfpMixedMesh(_ptr(disp), _ptr(body), _ptr(hpt), _ptr(vpt), _ptr(first))
-    _check(lib.mfp_mixed_mesh(byref(g), c, nb, int(nsweeps), byref(m), _ptr(ws), ws.numel(),
-                              _stream()))
+    _check(build(m))
     npts, nel = m.n_points, m.n_elems
     pxy = torch.empty((max(npts, 1), 2), dtype=torch.float64, device=device)
     pbody = torch.empty(max(npts, 1), dtype=torch.int8, device=device)
@@ -609,8 +665,7 @@ def mixed_mesh(grid, circles, nsweeps: int = 200, device="cuda") -> MixedMesh:
     m.pxy, m.pbody, m.pedge = _ptr(pxy), _ptr(pbody), _ptr(pedge)
     m.elem, m.nne = _ptr(elem), _ptr(nne)
     m.cap_points, m.cap_elems = npts, nel
-    _check(lib.mfp_mixed_mesh(byref(g), c, nb, int(nsweeps), byref(m), _ptr(ws), ws.numel(),
-                              _stream()))
+    _check(build(m))
     return MixedMesh(grid, list(circles), disp, body, hpt, vpt, first, pxy[:npts],
                      pbody[:npts], pedge[:npts], elem[:nel], nne[:nel], int(m.n_tri))
 
@@ -715,3 +770,43 @@ def psi_solve_kutta(grid, circles, disp, kind, body, flow, kutta_points, *, prec
     stats = {k: getattr(st, k) for k, _ in MfpStats._fields_}
     return KuttaResult(psi, [psib[k] for k in range(nb)], Q.value, cop.value,
                        [kn[k] for k in range(nb)], stats, status)
+
+
+def mixed_psi_solve_kutta(mm: MixedMesh, flow, kutta_points, *, precision="fp64", rtol=1e-12,
+                          kmax=10 ** 7, check_every=16, inner_rtol=0.1, max_outer=1000,
+                          pair=(-1, -1), estimate_kappa: bool = False,
+                          schedule: Optional[dict] = None,
+                          allow_warn: bool = True) -> MixedSolveResult:
+    """mixed_psi_solve with Kutta constraints: one (x, y) or None per body."""
+    lib = load()
+    g = make_grid(mm.grid)
+    c = make_circles(mm.circles)
+    nb = len(mm.circles)
+    if len(kutta_points) != nb:
+        raise ValueError("one Kutta point (or None) per body")
+    f = make_flow(flow)
+    o = _opts(precision, rtol, kmax, check_every, inner_rtol, max_outer, estimate_kappa,
+              schedule)
+    kxy = (c_double * max(2 * nb, 2))()
+    for b, pt in enumerate(kutta_points):
+        kxy[2 * b], kxy[2 * b + 1] = (float("nan"), float("nan")) if pt is None else (
+            float(pt[0]), float(pt[1]))
+    nk = sum(pt is not None for pt in kutta_points)
+    dev = mm.disp.device
+    psi = torch.empty(mm.n_nodes, dtype=torch.float64, device=dev)
+    psib = (c_double * max(nb, 1))()
+    Q = c_double(float("nan"))
+    cop = c_double(float("nan"))
+    kn = (c_int64 * max(nb, 1))()
+    st = MfpStats()
+    m = mm.c_struct()
+    ws = workspace(lib.mfp_mixed_kutta_workspace_size(byref(g), mm.n_points, mm.n_elems, nb, nk,
+                                                      byref(o)), dev)
+    status = _check(lib.mfp_mixed_psi_solve_kutta(
+        byref(g), c, nb, byref(m), byref(f), byref(o), kxy, int(pair[0]), int(pair[1]),
+        _ptr(psi), psib, byref(Q), byref(cop), kn, byref(st), _ptr(ws), ws.numel(), _stream()),
+        allow_warn)
+    stats = {k: getattr(st, k) for k, _ in MfpStats._fields_}
+    res = MixedSolveResult(psi, [psib[k] for k in range(nb)], Q.value, cop.value, stats, status)
+    res.kutta_nodes = [kn[k] for k in range(nb)]
+    return res

@@ -58,6 +58,16 @@ int psi_solve_cells(const mfp_grid* grid, const mfp_circle* circles_h, int nbody
                     const mfp_flow* flow, const mfp_solver_opts* opts, int pair_lo,
                     int pair_hi, double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
                     mfp_stats* stats_h, void* ws, size_t ws_bytes, hipStream_t st);
+// The same with Kutta constraints (as mfp_psi_solve_kutta: kutta_xy_h holds (x, y) or
+// (NaN, NaN) per body).
+size_t psi_solve_cells_kutta_workspace(const mfp_grid* grid, int nbody, int nkutta,
+                                       const mfp_solver_opts* opts);
+int psi_solve_cells_kutta(const mfp_grid* grid, const mfp_circle* circles_h, int nbody,
+                          const double* disp, const int8_t* body, const double* cellcoef,
+                          const mfp_flow* flow, const mfp_solver_opts* opts,
+                          const double* kutta_xy_h, int pair_lo, int pair_hi, double* psi,
+                          double* psi_b_h, double* Q_h, double* copfi_h, int64_t* kutta_node_h,
+                          mfp_stats* stats_h, void* ws, size_t ws_bytes, hipStream_t st);
 
 // ---- workspace bump allocator ----------------------------------------------------
 struct Bump {

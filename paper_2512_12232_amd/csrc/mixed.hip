@@ -13,8 +13,9 @@
 //   k_mx_cut        the cut point I + t (O - I), |I - c + t (O - I)| = r, t in [0, 1)
 //   k_mx_sweep      Jacobi sweeps of the displacement on fluid nodes; an inside
 //                   neighbour contributes its cut point's displacement P - I
-//   k_mx_cell_count elements per cell (0, 1 or 2), errors for cells touching two bodies
-//                   or with alternating corners
+//   k_mx_cell_count elements per cell (0, 1 or 2), errors for cells touching two bodies;
+//                   a cell whose inside and fluid corners alternate (a thin part of a
+//                   body crosses it) gets a triangle at each fluid corner
 //   (scan)          elements numbered in cell order
 //   k_mx_cells      the polygon of each cell: fluid corners and cut points walked
 //                   counter-clockwise from corner (i, j); pentagons split from the cut
@@ -146,7 +147,48 @@ static int exclusive_scan(const int* in, long long n, int* bs, int* out, hipStre
 }
 
 // ---- mesh -----------------------------------------------------------------------------
-__global__ void k_mx_classify(G g, const mfp_circle* __restrict__ circ, int nb,
+// A body on the device: a circle (x, y, r), or a Joukowski airfoil placed at (x, y)
+// with map constant c (c2 = c^2), generating circle centre (xi0, eta0), R2 = R^2 and
+// the rotation's cos / sin (from the host's C library).
+struct MxBody {
+  int kind;
+  double x, y, r;
+  double xi0, eta0, c2, R2, ca, sa;
+};
+
+// Airfoil level |zeta - zeta0|^2 - R^2 (<= 0 in the body) with zeta the preimage of
+// (X, Y) farther from zeta0: the roots (w +- s)/2 of zeta^2 - w zeta + c^2, s a square
+// root of w^2 - 4 c^2 in the stable real form (branch chosen by the sign of its real
+// part).  The map is one to one from outside the circle onto outside the airfoil, so
+// a point is outside iff one preimage is outside the circle.
+__device__ double airfoil_level(const MxBody& b, double X, double Y) {
+  const double dx = X - b.x, dy = Y - b.y;
+  const double wr = b.ca * dx - b.sa * dy;
+  const double wi = b.sa * dx + b.ca * dy;
+  const double ar = wr * wr - wi * wi - 4.0 * b.c2;
+  const double ai = 2.0 * wr * wi;
+  const double m = sqrt(ar * ar + ai * ai);
+  double sr, si;
+  if (ar >= 0.0) {
+    sr = sqrt((m + ar) * 0.5);
+    si = sr > 0.0 ? ai / (2.0 * sr) : 0.0;
+  } else {
+    si = copysign(sqrt((m - ar) * 0.5), ai);
+    sr = si != 0.0 ? ai / (2.0 * si) : 0.0;
+  }
+  const double e1r = (wr + sr) * 0.5 - b.xi0, e1i = (wi + si) * 0.5 - b.eta0;
+  const double e2r = (wr - sr) * 0.5 - b.xi0, e2i = (wi - si) * 0.5 - b.eta0;
+  const double d1 = e1r * e1r + e1i * e1i, d2 = e2r * e2r + e2i * e2i;
+  return (d1 >= d2 ? d1 : d2) - b.R2;
+}
+
+__device__ __forceinline__ bool body_contains(const MxBody& b, double x, double y) {
+  if (b.kind == MFP_BODY_JOUKOWSKI) return airfoil_level(b, x, y) <= 0.0;
+  const double dx = x - b.x, dy = y - b.y;
+  return dx * dx + dy * dy <= b.r * b.r;
+}
+
+__global__ void k_mx_classify(G g, const MxBody* __restrict__ bodies, int nb,
                               int8_t* __restrict__ body) {
   const long long nn = g.nn();
   for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn;
@@ -154,10 +196,8 @@ __global__ void k_mx_classify(G g, const mfp_circle* __restrict__ circ, int nb,
     const int j = (int)(n / (g.nx + 1)), i = (int)(n - (long long)j * (g.nx + 1));
     const double x = node_x(g, i), y = node_y(g, j);
     int b_in = -1;
-    for (int b = 0; b < nb; ++b) {
-      const double dx = x - circ[b].cx, dy = y - circ[b].cy;
-      if (dx * dx + dy * dy <= circ[b].r * circ[b].r) b_in = b;
-    }
+    for (int b = 0; b < nb; ++b)
+      if (body_contains(bodies[b], x, y)) b_in = b;
     body[n] = (int8_t)b_in;
   }
 }
@@ -203,7 +243,27 @@ __device__ __forceinline__ double edge_root(double ux, double uy, double vx, dou
   return (-uv + sqrt(uv * uv - vv * (uu - r * r))) / vv;
 }
 
-__global__ void k_mx_cut(G g, const mfp_circle* __restrict__ circ, const int8_t* __restrict__ body,
+// Cut point parameter t of the edge from inside node (xi, yi) along (vx, vy): for a
+// circle the root of |I + t v - c| = r; for an airfoil the bracket of the first sign
+// change of the level among t = k/64, bisected 60 times (the lower, inside end kept).
+__device__ double cut_param(const MxBody& b, double xi, double yi, double vx, double vy) {
+  if (b.kind != MFP_BODY_JOUKOWSKI) return edge_root(xi - b.x, yi - b.y, vx, vy, b.r);
+  int k = 0;
+  while (k < 63 && !(airfoil_level(b, xi + ((double)(k + 1) / 64.0) * vx,
+                                   yi + ((double)(k + 1) / 64.0) * vy) > 0.0))
+    ++k;
+  double lo = (double)k / 64.0, hi = (double)(k + 1) / 64.0;
+  for (int it = 0; it < 60; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (airfoil_level(b, xi + mid * vx, yi + mid * vy) > 0.0)
+      hi = mid;
+    else
+      lo = mid;
+  }
+  return lo;
+}
+
+__global__ void k_mx_cut(G g, const MxBody* __restrict__ circ, const int8_t* __restrict__ body,
                          const int* __restrict__ flag, const int* __restrict__ off,
                          int* __restrict__ hpt, int* __restrict__ vpt, double* __restrict__ pxy,
                          int8_t* __restrict__ pbody, int* __restrict__ pedge, long long cap) {
@@ -225,7 +285,7 @@ __global__ void k_mx_cut(G g, const mfp_circle* __restrict__ circ, const int8_t*
     const int b = a_in ? ba : body[(long long)jc * (g.nx + 1) + ic];
     const double xi = node_x(g, ii), yi = node_y(g, ji);
     const double vx = node_x(g, io) - xi, vy = node_y(g, jo) - yi;
-    const double t = edge_root(xi - circ[b].cx, yi - circ[b].cy, vx, vy, circ[b].r);
+    const double t = cut_param(circ[b], xi, yi, vx, vy);
     pxy[2 * k] = xi + t * vx;
     pxy[2 * k + 1] = yi + t * vy;
     pbody[k] = (int8_t)b;
@@ -329,9 +389,29 @@ __device__ int cell_elements(const G& g, const int8_t* __restrict__ body,
   if (nf == 0) return 0;
   int changes = 0;
   for (int k = 0; k < 4; ++k) changes += ins[k] != ins[(k + 1) & 3];
-  if (changes != 2) {
-    if (err) err[2] = 1;
-    return 0;
+  const double hmax = g.hx > g.hy ? g.hx : g.hy;
+  if (changes == 4) {
+    // inside and fluid corners alternate (a thin part of the body crosses the cell):
+    // a triangle at each fluid corner, in corner order, slivers dropped
+    int m = 0;
+    for (int k = 0; k < 4; ++k) {
+      if (ins[k]) continue;
+      const int qa = cell_edge_point(g, hpt, vpt, i, j, (k + 3) & 3);
+      const int qb = cell_edge_point(g, hpt, vpt, i, j, k);
+      const double gx = fabs(pxy[2 * qa] - pxy[2 * qb]);
+      const double gy = fabs(pxy[2 * qa + 1] - pxy[2 * qb + 1]);
+      const double gap = gx > gy ? gx : gy;
+      if (!(gap >= SLIVER * hmax)) continue;
+      if (out) {
+        out[m][0] = (int)(nn + qa);
+        out[m][1] = (int)ids[k];
+        out[m][2] = (int)(nn + qb);
+        out[m][3] = -1;
+        nne[m] = 3;
+      }
+      ++m;
+    }
+    return m;
   }
   if (nf == 1) {
     // triangle: the fluid corner and the cut points on its two edges, CCW from corner 0
@@ -345,7 +425,6 @@ __device__ int cell_elements(const G& g, const int8_t* __restrict__ body,
         poly[np_++] = (int)(nn + q);
       }
     }
-    const double hmax = g.hx > g.hy ? g.hx : g.hy;
     const double gx = fabs(pxy[2 * pts[0]] - pxy[2 * pts[1]]);
     const double gy = fabs(pxy[2 * pts[0] + 1] - pxy[2 * pts[1] + 1]);
     const double gap = gx > gy ? gx : gy;
@@ -744,7 +823,7 @@ struct MeshWs {
   int* elem;        // 4 * 2 nc
   int8_t* nne;      // 2 nc
   double* dtmp;     // 2 nn
-  mfp_circle* circ;
+  MxBody* circ;
   int* err;         // 4 flags
 };
 
@@ -764,7 +843,7 @@ static size_t mesh_layout(const mfp_grid* gr, int nb, void* base, MeshWs* w) {
   m.elem = bp.take<int>(8 * nc);
   m.nne = bp.take<int8_t>(2 * nc);
   m.dtmp = bp.take<double>(2 * g.nn());
-  m.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
+  m.circ = bp.take<MxBody>(nb > 0 ? nb : 1);
   m.err = bp.take<int>(4);
   if (w) *w = m;
   return bp.off + 256;
@@ -781,11 +860,64 @@ extern "C" size_t mfp_mixed_workspace_size(const mfp_grid* grid, int32_t nbody) 
   return mesh_layout(grid, nbody, nullptr, nullptr);
 }
 
-extern "C" int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
-                              int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
-                              void* stream_) {
-  clear_error();
-  MFP_TRY(check_geometry(grid, circles_h, nbody));
+namespace mfp {
+namespace mixed {
+
+// A circle as a device body.
+static MxBody circle_body(const mfp_circle& c) {
+  MxBody b{};
+  b.kind = MFP_BODY_CIRCLE;
+  b.x = c.cx;
+  b.y = c.cy;
+  b.r = c.r;
+  return b;
+}
+
+// A body description as a device body (cos and sin of the angle of attack from the C
+// library), and a circle holding the whole body for the geometry checks: about the
+// airfoil's placement point, the largest distance of 4097 boundary samples + 1%.
+static int make_body(const mfp_body& d, MxBody* out, mfp_circle* bound) {
+  if (d.kind == MFP_BODY_CIRCLE) {
+    const mfp_circle c{d.x, d.y, d.r};
+    *out = circle_body(c);
+    *bound = c;
+    return MFP_OK;
+  }
+  if (d.kind != MFP_BODY_JOUKOWSKI || !(d.r > 0.0) || !std::isfinite(d.x) ||
+      !std::isfinite(d.y) || !std::isfinite(d.xi0) || !std::isfinite(d.eta0) ||
+      !std::isfinite(d.alpha) || !(d.xi0 <= 0.0) || d.xi0 < -d.r) {
+    set_error("body: kind MFP_BODY_CIRCLE or MFP_BODY_JOUKOWSKI with c > 0, -c <= xi0 <= 0 "
+              "and finite parameters");
+    return MFP_E_ARG;
+  }
+  MxBody b{};
+  b.kind = MFP_BODY_JOUKOWSKI;
+  b.x = d.x;
+  b.y = d.y;
+  b.r = d.r;
+  b.xi0 = d.xi0;
+  b.eta0 = d.eta0;
+  b.c2 = d.r * d.r;
+  b.R2 = (d.r - d.xi0) * (d.r - d.xi0) + d.eta0 * d.eta0;
+  b.ca = std::cos(d.alpha);
+  b.sa = std::sin(d.alpha);
+  *out = b;
+  const double R = std::sqrt(b.R2);
+  double rmax = 0.0;
+  for (int k = 0; k <= 4096; ++k) {
+    const double th = 2.0 * M_PI * k / 4096.0;
+    const double zr = d.xi0 + R * std::cos(th), zi = d.eta0 + R * std::sin(th);
+    const double q = zr * zr + zi * zi;
+    const double xr = zr + b.c2 * zr / q, xi = zi - b.c2 * zi / q;
+    rmax = std::max(rmax, std::sqrt(xr * xr + xi * xi));
+  }
+  *bound = mfp_circle{d.x, d.y, rmax * 1.01};
+  return MFP_OK;
+}
+
+static int mesh_impl(const mfp_grid* grid, const MxBody* bodies_h, int32_t nbody,
+                     int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
+                     void* stream_) {
   if (!m || !ws || !m->disp || !m->body || !m->hpt || !m->vpt || !m->cell_first ||
       nsweeps < 0 || m->cap_points < 0 || m->cap_elems < 0 ||
       (m->cap_points > 0 && (!m->pxy || !m->pbody || !m->pedge)) ||
@@ -804,8 +936,8 @@ extern "C" int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h,
   const G g = to_g(*grid);
   const long long nn = g.nn(), nh = g.nh(), ne = nh + g.nv(), nc = g.nc();
   if (nbody > 0)
-    MFP_TRY_HIP(hipMemcpyAsync(w.circ, circles_h, sizeof(mfp_circle) * nbody,
-                               hipMemcpyHostToDevice, st));
+    MFP_TRY_HIP(hipMemcpyAsync(w.circ, bodies_h, sizeof(MxBody) * nbody, hipMemcpyHostToDevice,
+                               st));
   MFP_TRY_HIP(hipMemsetAsync(w.err, 0, 4 * sizeof(int), st));
   k_mx_classify<<<blocks_for(nn), MB, 0, st>>>(g, w.circ, nbody, m->body);
   k_mx_edge_flags<<<blocks_for(ne), MB, 0, st>>>(g, m->body, w.eflag, w.err);
@@ -842,10 +974,8 @@ extern "C" int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h,
   MFP_TRY_HIP(hipMemcpyAsync(&counts[0], w.eoff + ne, sizeof(int), hipMemcpyDeviceToHost, st));
   MFP_TRY_HIP(hipMemcpyAsync(&counts[1], m->cell_first + nc, sizeof(int), hipMemcpyDeviceToHost, st));
   MFP_TRY_HIP(hipStreamSynchronize(st));
-  if (err[0] || err[1] || err[2]) {
-    set_error(err[0] ? "a grid edge joins two bodies"
-                     : err[1] ? "a cell touches two bodies"
-                              : "inside and fluid corners alternate in a cell");
+  if (err[0] || err[1]) {
+    set_error(err[0] ? "a grid edge joins two bodies" : "a cell touches two bodies");
     return MFP_E_GEOMETRY;
   }
   m->n_points = counts[0];
@@ -870,6 +1000,47 @@ extern "C" int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h,
   for (int8_t v : hn) ntri += v == 3;
   m->n_tri = ntri;
   return MFP_OK;
+}
+
+}  // namespace mixed
+}  // namespace mfp
+
+extern "C" int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                              int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
+                              void* stream_) {
+  clear_error();
+  MFP_TRY(check_geometry(grid, circles_h, nbody));
+  std::vector<MxBody> hb((size_t)(nbody > 0 ? nbody : 1));
+  for (int b = 0; b < nbody; ++b) hb[b] = circle_body(circles_h[b]);
+  return mesh_impl(grid, hb.data(), nbody, nsweeps, m, ws, ws_bytes, stream_);
+}
+
+extern "C" int mfp_body_bounds(const mfp_body* bodies_h, int32_t nbody, mfp_circle* bounds_h) {
+  clear_error();
+  if (!bodies_h || !bounds_h || nbody < 0 || nbody > MFP_MAX_BODIES) {
+    set_error("NULL argument or nbody outside [0, MFP_MAX_BODIES]");
+    return MFP_E_ARG;
+  }
+  for (int b = 0; b < nbody; ++b) {
+    MxBody tmp;
+    MFP_TRY(make_body(bodies_h[b], &tmp, &bounds_h[b]));
+  }
+  return MFP_OK;
+}
+
+extern "C" int mfp_mixed_mesh_bodies(const mfp_grid* grid, const mfp_body* bodies_h,
+                                     int32_t nbody, int32_t nsweeps, mfp_mixed_mesh_t* m,
+                                     void* ws, size_t ws_bytes, void* stream_) {
+  clear_error();
+  if (nbody < 0 || nbody > MFP_MAX_BODIES || (nbody > 0 && !bodies_h)) {
+    set_error("nbody outside [0, MFP_MAX_BODIES] or NULL bodies");
+    return MFP_E_ARG;
+  }
+  std::vector<MxBody> hb((size_t)(nbody > 0 ? nbody : 1));
+  std::vector<mfp_circle> bounds((size_t)(nbody > 0 ? nbody : 1));
+  for (int b = 0; b < nbody; ++b) MFP_TRY(make_body(bodies_h[b], &hb[b], &bounds[b]));
+  MFP_TRY(check_geometry(grid, bounds.data(), nbody));
+  return mesh_impl(grid, hb.data(), nbody, nsweeps, m, ws, ws_bytes, stream_);
 }
 
 namespace mfp {
@@ -985,14 +1156,29 @@ extern "C" int mfp_mixed_element_apply(const mfp_grid* grid, const mfp_mixed_mes
   return MFP_OK;
 }
 
-extern "C" int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h,
-                                   int32_t nbody, const mfp_mixed_mesh_t* m,
-                                   const mfp_flow* flow, const mfp_solver_opts* opts,
-                                   int32_t pair_lo, int32_t pair_hi, double* psi,
-                                   double* psi_b_h, double* Q_h, double* copfi_h,
-                                   mfp_stats* stats_h, void* ws, size_t ws_bytes,
-                                   void* stream_) {
-  clear_error();
+namespace mfp {
+namespace mixed {
+
+static int count_kutta(const double* kutta_xy_h, int nbody) {
+  int nk = 0;
+  if (kutta_xy_h)
+    for (int b = 0; b < nbody; ++b)
+      nk += !(std::isnan(kutta_xy_h[2 * b]) && std::isnan(kutta_xy_h[2 * b + 1]));
+  return nk;
+}
+
+static size_t mixed_solve_bytes(const mfp_grid* grid, int nbody, int nk,
+                                const mfp_solver_opts* opts, bool kutta) {
+  return kutta ? psi_solve_cells_kutta_workspace(grid, nbody, nk, opts)
+               : psi_solve_cells_workspace(grid, nbody, opts);
+}
+
+static int mixed_solve_impl(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                            const mfp_mixed_mesh_t* m, const mfp_flow* flow,
+                            const mfp_solver_opts* opts, const double* kutta_xy_h,
+                            int32_t pair_lo, int32_t pair_hi, double* psi, double* psi_b_h,
+                            double* Q_h, double* copfi_h, int64_t* kutta_node_h,
+                            mfp_stats* stats_h, void* ws, size_t ws_bytes, void* stream_) {
   MFP_TRY(check_geometry(grid, circles_h, nbody));
   MFP_TRY(check_mesh_arg(grid, m));
   if (!flow || !opts || !psi || !ws || (nbody > 0 && !psi_b_h)) {
@@ -1004,7 +1190,9 @@ extern "C" int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circl
     return MFP_E_ARG;
   }
   const G g = to_g(*grid);
-  const size_t sb = psi_solve_cells_workspace(grid, nbody, opts);
+  const bool kutta = kutta_xy_h != nullptr;
+  const int nk = count_kutta(kutta_xy_h, nbody);
+  const size_t sb = mixed_solve_bytes(grid, nbody, nk, opts, kutta);
   if (sb == 0) {
     set_error("invalid solver options");
     return MFP_E_ARG;
@@ -1021,9 +1209,13 @@ extern "C" int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circl
   MFP_TRY_HIP(hipGetLastError());
   // background-node values first (the mixed numbering starts with them)
   std::vector<double> pb((size_t)(nbody > 0 ? nbody : 1));
-  const int rc = psi_solve_cells(grid, circles_h, nbody, m->disp, m->body, s.kc, flow, opts,
-                                 pair_lo, pair_hi, psi, pb.data(), Q_h, copfi_h, stats_h,
-                                 s.solve_ws, s.solve_bytes, st);
+  const int rc = kutta ? psi_solve_cells_kutta(grid, circles_h, nbody, m->disp, m->body, s.kc,
+                                               flow, opts, kutta_xy_h, pair_lo, pair_hi, psi,
+                                               pb.data(), Q_h, copfi_h, kutta_node_h, stats_h,
+                                               s.solve_ws, s.solve_bytes, st)
+                       : psi_solve_cells(grid, circles_h, nbody, m->disp, m->body, s.kc, flow,
+                                         opts, pair_lo, pair_hi, psi, pb.data(), Q_h, copfi_h,
+                                         stats_h, s.solve_ws, s.solve_bytes, st);
   if (rc < 0) return rc;
   PsiB hb{};
   for (int b = 0; b < nbody; ++b) {
@@ -1035,4 +1227,48 @@ extern "C" int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circl
   MFP_TRY_HIP(hipGetLastError());
   MFP_TRY_HIP(hipStreamSynchronize(st));
   return rc;
+}
+
+}  // namespace mixed
+}  // namespace mfp
+
+extern "C" int mfp_mixed_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h,
+                                   int32_t nbody, const mfp_mixed_mesh_t* m,
+                                   const mfp_flow* flow, const mfp_solver_opts* opts,
+                                   int32_t pair_lo, int32_t pair_hi, double* psi,
+                                   double* psi_b_h, double* Q_h, double* copfi_h,
+                                   mfp_stats* stats_h, void* ws, size_t ws_bytes,
+                                   void* stream_) {
+  clear_error();
+  return mixed_solve_impl(grid, circles_h, nbody, m, flow, opts, nullptr, pair_lo, pair_hi, psi,
+                          psi_b_h, Q_h, copfi_h, nullptr, stats_h, ws, ws_bytes, stream_);
+}
+
+extern "C" size_t mfp_mixed_kutta_workspace_size(const mfp_grid* grid, int64_t n_points,
+                                                 int64_t n_elems, int32_t nbody, int32_t nkutta,
+                                                 const mfp_solver_opts* opts) {
+  if (!grid || grid->nx < 2 || grid->ny < 2 || n_points < 0 || n_elems < 0 || nbody < 0 ||
+      nbody > MFP_MAX_BODIES || nkutta < 0 || nkutta > nbody)
+    return 0;
+  const size_t sb = psi_solve_cells_kutta_workspace(grid, nbody, nkutta, opts);
+  if (sb == 0) return 0;
+  return solve_layout_mx(to_g(*grid), n_elems, sb, nullptr, nullptr);
+}
+
+extern "C" int mfp_mixed_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circles_h,
+                                         int32_t nbody, const mfp_mixed_mesh_t* m,
+                                         const mfp_flow* flow, const mfp_solver_opts* opts,
+                                         const double* kutta_xy_h, int32_t pair_lo,
+                                         int32_t pair_hi, double* psi, double* psi_b_h,
+                                         double* Q_h, double* copfi_h, int64_t* kutta_node_h,
+                                         mfp_stats* stats_h, void* ws, size_t ws_bytes,
+                                         void* stream_) {
+  clear_error();
+  if (!kutta_xy_h) {
+    set_error("NULL Kutta points");
+    return MFP_E_ARG;
+  }
+  return mixed_solve_impl(grid, circles_h, nbody, m, flow, opts, kutta_xy_h, pair_lo, pair_hi,
+                          psi, psi_b_h, Q_h, copfi_h, kutta_node_h, stats_h, ws, ws_bytes,
+                          stream_);
 }

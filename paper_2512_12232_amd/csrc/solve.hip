@@ -1955,6 +1955,69 @@ extern "C" int mfp_psi_solve(const mfp_grid* grid, const mfp_circle* circles_h, 
 
 namespace mfp {
 
+// Schedule of a solve whose element entries come from a per-cell table: the stored
+// form for every geometry task, the rest as for any solve.
+static int cells_schedule(const mfp_grid* grid, const mfp_solver_opts* opts, Schedule* sc) {
+  MFP_TRY(resolve_schedule(grid, opts ? opts->precision : MFP_FP64, opts, sc));
+  sc->kst = 1;
+  sc->cells = 1;
+  return MFP_OK;
+}
+
+size_t psi_solve_cells_workspace(const mfp_grid* grid, int nbody, const mfp_solver_opts* opts) {
+  Schedule sc;
+  if (cells_schedule(grid, opts, &sc) != MFP_OK) return 0;
+  return solve_layout(grid, nbody, opts ? opts->precision : MFP_FP64, nullptr, nullptr, &sc);
+}
+
+int psi_solve_cells(const mfp_grid* grid, const mfp_circle* circles_h, int nbody,
+                    const double* disp, const int8_t* body, const double* cellcoef,
+                    const mfp_flow* flow, const mfp_solver_opts* opts, int pair_lo,
+                    int pair_hi, double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
+                    mfp_stats* stats_h, void* ws, size_t ws_bytes, hipStream_t st) {
+  MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, body, body, flow, opts, ws));
+  if (!psi || !cellcoef || (nbody > 0 && !psi_b_h) || pair_lo >= nbody || pair_hi >= nbody) {
+    set_error("NULL argument or pair index out of range");
+    return MFP_E_ARG;
+  }
+  Schedule sc;
+  MFP_TRY(cells_schedule(grid, opts, &sc));
+  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, &sc);
+  if (ws_bytes < need) {
+    set_error("workspace too small: %zu < %zu", ws_bytes, need);
+    return MFP_E_WORKSPACE;
+  }
+  SolveWs w;
+  solve_layout(grid, nbody, opts->precision, ws, &w, &sc);
+  w.cellcoef = cellcoef;
+  const mfp_grid& g = *grid;
+  SolveInfo info;
+  MFP_TRY(solve_core(g, circles_h, nbody, disp, body, flow, opts, nullptr, false, w, st, &info));
+  double ylo = 0, yhi = 0;
+  if (pair_lo >= 0 && pair_hi >= 0) {
+    ylo = circles_h[pair_lo].cy;
+    yhi = circles_h[pair_hi].cy;
+  }
+  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
+  k_output<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, w.x, w.g, w.st, psi,
+                                               pair_lo, pair_hi, flow->U, ylo, yhi);
+  MFP_TRY_HIP(hipGetLastError());
+  DevState hsd;
+  MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
+  MFP_TRY_HIP(hipStreamSynchronize(st));
+  for (int b = 0; b < nbody; ++b) psi_b_h[b] = hsd.xb[hsd.iters & 1][b];
+  if (pair_lo >= 0 && pair_hi >= 0) {
+    if (Q_h) *Q_h = hsd.Q;
+    if (copfi_h) *copfi_h = hsd.copfi;
+  }
+  MFP_TRY(fill_stats(w, info, nbody, hsd, st, stats_h));
+  return finish_status(info);
+}
+
+}  // namespace mfp
+
+namespace mfp {
+
 // ---- Kutta constraints ---------------------------------------------------------------
 // psi(K_b) = psi_b in place of body b's zero-circulation row.  The system stays
 // linear, and with those bodies held at given values it is the constrained system
@@ -1999,29 +2062,34 @@ static bool dense_solve(int n, std::vector<double>& A, std::vector<double>& b) {
 
 }  // namespace mfp
 
-extern "C" size_t mfp_kutta_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t nkutta,
-                                           const mfp_solver_opts* opts) {
+namespace mfp {
+
+// Schedule of a Kutta sub-solve: as any solve, or with per-cell element entries.
+static int kutta_schedule(const mfp_grid* grid, const mfp_solver_opts* opts, bool cells,
+                          Schedule* sc) {
+  if (cells) return cells_schedule(grid, opts, sc);
+  return resolve_schedule(grid, opts ? opts->precision : MFP_FP64, opts, sc);
+}
+
+static size_t kutta_workspace(const mfp_grid* grid, int32_t nbody, int32_t nkutta,
+                              const mfp_solver_opts* opts, bool cells) {
   if (!grid || grid->nx < 2 || grid->ny < 2 || nbody < 0 || nbody > MFP_MAX_BODIES ||
       nkutta < 0 || nkutta > nbody)
     return 0;
   Schedule sc;
-  if (resolve_schedule(grid, opts ? opts->precision : MFP_FP64, opts, &sc) != MFP_OK) return 0;
+  if (kutta_schedule(grid, opts, cells, &sc) != MFP_OK) return 0;
   const size_t solve = solve_layout(grid, nbody, opts ? opts->precision : MFP_FP64, nullptr,
                                     nullptr, &sc);
   const size_t nn = (size_t)(grid->nx + 1) * (grid->ny + 1);
   return ((solve + 255) & ~size_t(255)) + (size_t)nkutta * nn * sizeof(double) + 256;
 }
 
-extern "C" int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circles_h,
-                                   int32_t nbody, const double* disp, const int8_t* kind,
-                                   const int8_t* body, const mfp_flow* flow,
-                                   const mfp_solver_opts* opts, const double* kutta_xy_h,
-                                   int32_t pair_lo, int32_t pair_hi, double* psi,
-                                   double* psi_b_h, double* Q_h, double* copfi_h,
-                                   int64_t* kutta_node_h, mfp_stats* stats_h, void* ws,
-                                   size_t ws_bytes, void* stream_) {
-  clear_error();
-  MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, kind, body, flow, opts, ws));
+static int kutta_drive(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
+                       const double* disp, const int8_t* body, const mfp_flow* flow,
+                       const mfp_solver_opts* opts, const double* kutta_xy_h, int32_t pair_lo,
+                       int32_t pair_hi, double* psi, double* psi_b_h, double* Q_h,
+                       double* copfi_h, int64_t* kutta_node_h, mfp_stats* stats_h, void* ws,
+                       size_t ws_bytes, hipStream_t st, const double* cellcoef) {
   if (!psi || !kutta_xy_h || (nbody > 0 && !psi_b_h) || pair_lo >= nbody || pair_hi >= nbody) {
     set_error("NULL argument or pair index out of range");
     return MFP_E_ARG;
@@ -2033,7 +2101,6 @@ extern "C" int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circl
   const mfp_grid& g = *grid;
   const double hx = grid_hx(g), hy = grid_hy(g);
   const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
-  hipStream_t st = static_cast<hipStream_t>(stream_);
   // Kutta bodies and their nodes: the grid node nearest to the point
   std::vector<int> kb;
   std::vector<long long> kn;
@@ -2067,7 +2134,7 @@ extern "C" int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circl
     if (kutta_node_h) kutta_node_h[b] = n;
   }
   const int nk = (int)kb.size();
-  const size_t need = mfp_kutta_workspace_size(grid, nbody, nk, opts);
+  const size_t need = kutta_workspace(grid, nbody, nk, opts, cellcoef != nullptr);
   if (need == 0) {
     set_error("invalid schedule options");
     return MFP_E_ARG;
@@ -2077,7 +2144,7 @@ extern "C" int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circl
     return MFP_E_WORKSPACE;
   }
   Schedule sc;
-  MFP_TRY(resolve_schedule(grid, opts->precision, opts, &sc));
+  MFP_TRY(kutta_schedule(grid, opts, cellcoef != nullptr, &sc));
   const size_t solve_bytes = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, &sc);
   double* fields = reinterpret_cast<double*>(static_cast<char*>(ws) +
                                              ((solve_bytes + 255) & ~size_t(255)));
@@ -2095,6 +2162,7 @@ extern "C" int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circl
   for (int s = 0; s <= nk; ++s) {
     SolveWs w;
     solve_layout(grid, nbody, opts->precision, ws, &w, &sc);
+    w.cellcoef = cellcoef;
     w.fixed_mask = mask;
     for (int q = 0; q < nk; ++q) w.fixed[kb[q]] = (s >= 1 && q == s - 1) ? 1.0 : 0.0;
     mfp_solver_opts o = *opts;
@@ -2174,65 +2242,49 @@ extern "C" int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circl
   return finish_status(total);
 }
 
+}  // namespace mfp
+
+extern "C" size_t mfp_kutta_workspace_size(const mfp_grid* grid, int32_t nbody, int32_t nkutta,
+                                           const mfp_solver_opts* opts) {
+  return kutta_workspace(grid, nbody, nkutta, opts, false);
+}
+
+extern "C" int mfp_psi_solve_kutta(const mfp_grid* grid, const mfp_circle* circles_h,
+                                   int32_t nbody, const double* disp, const int8_t* kind,
+                                   const int8_t* body, const mfp_flow* flow,
+                                   const mfp_solver_opts* opts, const double* kutta_xy_h,
+                                   int32_t pair_lo, int32_t pair_hi, double* psi,
+                                   double* psi_b_h, double* Q_h, double* copfi_h,
+                                   int64_t* kutta_node_h, mfp_stats* stats_h, void* ws,
+                                   size_t ws_bytes, void* stream_) {
+  clear_error();
+  MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, kind, body, flow, opts, ws));
+  return kutta_drive(grid, circles_h, nbody, disp, body, flow, opts, kutta_xy_h, pair_lo,
+                     pair_hi, psi, psi_b_h, Q_h, copfi_h, kutta_node_h, stats_h, ws, ws_bytes,
+                     static_cast<hipStream_t>(stream_), nullptr);
+}
+
 namespace mfp {
 
-// Schedule of a solve whose element entries come from a per-cell table: the stored
-// form for every geometry task, the rest as for any solve.
-static int cells_schedule(const mfp_grid* grid, const mfp_solver_opts* opts, Schedule* sc) {
-  MFP_TRY(resolve_schedule(grid, opts ? opts->precision : MFP_FP64, opts, sc));
-  sc->kst = 1;
-  sc->cells = 1;
-  return MFP_OK;
+size_t psi_solve_cells_kutta_workspace(const mfp_grid* grid, int nbody, int nkutta,
+                                       const mfp_solver_opts* opts) {
+  return kutta_workspace(grid, nbody, nkutta, opts, true);
 }
 
-size_t psi_solve_cells_workspace(const mfp_grid* grid, int nbody, const mfp_solver_opts* opts) {
-  Schedule sc;
-  if (cells_schedule(grid, opts, &sc) != MFP_OK) return 0;
-  return solve_layout(grid, nbody, opts ? opts->precision : MFP_FP64, nullptr, nullptr, &sc);
-}
-
-int psi_solve_cells(const mfp_grid* grid, const mfp_circle* circles_h, int nbody,
-                    const double* disp, const int8_t* body, const double* cellcoef,
-                    const mfp_flow* flow, const mfp_solver_opts* opts, int pair_lo,
-                    int pair_hi, double* psi, double* psi_b_h, double* Q_h, double* copfi_h,
-                    mfp_stats* stats_h, void* ws, size_t ws_bytes, hipStream_t st) {
+int psi_solve_cells_kutta(const mfp_grid* grid, const mfp_circle* circles_h, int nbody,
+                          const double* disp, const int8_t* body, const double* cellcoef,
+                          const mfp_flow* flow, const mfp_solver_opts* opts,
+                          const double* kutta_xy_h, int pair_lo, int pair_hi, double* psi,
+                          double* psi_b_h, double* Q_h, double* copfi_h, int64_t* kutta_node_h,
+                          mfp_stats* stats_h, void* ws, size_t ws_bytes, hipStream_t st) {
   MFP_TRY(check_solve_args(grid, circles_h, nbody, disp, body, body, flow, opts, ws));
-  if (!psi || !cellcoef || (nbody > 0 && !psi_b_h) || pair_lo >= nbody || pair_hi >= nbody) {
-    set_error("NULL argument or pair index out of range");
+  if (!cellcoef) {
+    set_error("NULL element entries");
     return MFP_E_ARG;
   }
-  Schedule sc;
-  MFP_TRY(cells_schedule(grid, opts, &sc));
-  const size_t need = solve_layout(grid, nbody, opts->precision, nullptr, nullptr, &sc);
-  if (ws_bytes < need) {
-    set_error("workspace too small: %zu < %zu", ws_bytes, need);
-    return MFP_E_WORKSPACE;
-  }
-  SolveWs w;
-  solve_layout(grid, nbody, opts->precision, ws, &w, &sc);
-  w.cellcoef = cellcoef;
-  const mfp_grid& g = *grid;
-  SolveInfo info;
-  MFP_TRY(solve_core(g, circles_h, nbody, disp, body, flow, opts, nullptr, false, w, st, &info));
-  double ylo = 0, yhi = 0;
-  if (pair_lo >= 0 && pair_hi >= 0) {
-    ylo = circles_h[pair_lo].cy;
-    yhi = circles_h[pair_hi].cy;
-  }
-  const long long nn = (long long)(g.nx + 1) * (g.ny + 1);
-  k_output<<<grid_blocks(nn), BLOCK, 0, st>>>(w.L, g.nx, g.ny, w.tag, w.x, w.g, w.st, psi,
-                                               pair_lo, pair_hi, flow->U, ylo, yhi);
-  MFP_TRY_HIP(hipGetLastError());
-  DevState hsd;
-  MFP_TRY_HIP(hipMemcpyAsync(&hsd, w.st, sizeof(DevState), hipMemcpyDeviceToHost, st));
-  MFP_TRY_HIP(hipStreamSynchronize(st));
-  for (int b = 0; b < nbody; ++b) psi_b_h[b] = hsd.xb[hsd.iters & 1][b];
-  if (pair_lo >= 0 && pair_hi >= 0) {
-    if (Q_h) *Q_h = hsd.Q;
-    if (copfi_h) *copfi_h = hsd.copfi;
-  }
-  MFP_TRY(fill_stats(w, info, nbody, hsd, st, stats_h));
-  return finish_status(info);
+  return kutta_drive(grid, circles_h, nbody, disp, body, flow, opts, kutta_xy_h, pair_lo,
+                     pair_hi, psi, psi_b_h, Q_h, copfi_h, kutta_node_h, stats_h, ws, ws_bytes, st,
+                     cellcoef);
 }
 
 }  // namespace mfp
