@@ -65,7 +65,7 @@ def traffic_from_profile():
     fields = dict(line.split(": ", 1) for line in text.splitlines() if ": " in line
                   and line.split(": ", 1)[0] in ("traffic_bytes_per_launch", "source_sha256_16"))
     h = hashlib.sha256()
-    for f in ("apply.h", "step.h", "solve.hip"):
+    for f in ("apply.h", "step.h", "solve.hip", "reduce.h"):
         with open(os.path.join(ROOT, "paper_2512_12232_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if fields.get("source_sha256_16", "").strip() != h.hexdigest()[:16]:
@@ -630,6 +630,9 @@ def main():
     ap.add_argument("--mixed-kmax", type=int, default=10 ** 7,
                     help="with --mixed-only: iteration cap of every solve (short "
                          "profiling runs)")
+    ap.add_argument("--mixed-cell-only", action="store_true",
+                    help="only run the mixed-cell mesh leg (1024x512) and print its JSON "
+                         "(for profiling that workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -653,6 +656,9 @@ def main():
     if args.mixed_only:
         print(json.dumps({"mixed_precision_4096x2048": mixed_precision(mfp, W, args.mixed_kmax)}),
               flush=True)
+        return
+    if args.mixed_cell_only:
+        print(json.dumps({"mixed_cell_mesh_1024x512": mixed_cell_mesh(mfp, W)}), flush=True)
         return
     case = W.five_cyl_1024()
     dev = "cuda:0"
