@@ -356,10 +356,11 @@ def _gradient_golden():
 
 def autotune_effect(mfp, W):
     """Tuned schedule (the package's tuning cache) against the built-in rules
-    (MFP_TUNE_CACHE=none) on the workloads the cache was tuned on: 1024x512 (the
-    benchmark's) and 2048x1024 to rtol 1e-12, 4096x2048 to 1e-10, each in FP64 and
-    FP32 + refinement, and the 256-variant batched sweep in FP32 + refinement.
-    Iteration-phase times (ms, best of two)."""
+    (MFP_TUNE_CACHE=none) on the workloads the cache was tuned on (the tuner's: five
+    cylinders, gap 0.25, on [-20, 20] x [-10, 10]): 1024x512 (the benchmark's) and
+    2048x1024 to rtol 1e-12, 4096x2048 to 1e-10, each in FP64 and FP32 + refinement,
+    and the 256-variant batched sweep in FP32 + refinement.  Iteration-phase times
+    (ms, best of two)."""
     import numpy as np
     out = {}
 
@@ -381,11 +382,14 @@ def autotune_effect(mfp, W):
 
     for case, prec, rtol, key in ((W.five_cyl_1024(), "fp64", 1e-12, "1024x512_fp64"),
                                   (W.five_cyl_1024(), "fp32_ir", 1e-12, "1024x512_fp32_ir"),
-                                  (W.five_cyl_2048_adjoint(), "fp64", 1e-12, "2048x1024_fp64"),
-                                  (W.five_cyl_2048_adjoint(), "fp32_ir", 1e-12,
+                                  (W.five_cylinders(2048, 1024, 0.25), "fp64", 1e-12,
+                                   "2048x1024_fp64"),
+                                  (W.five_cylinders(2048, 1024, 0.25), "fp32_ir", 1e-12,
                                    "2048x1024_fp32_ir"),
-                                  (W.five_cyl_4096(), "fp64", 1e-10, "4096x2048_fp64"),
-                                  (W.five_cyl_4096(), "fp32_ir", 1e-10, "4096x2048_fp32_ir")):
+                                  (W.five_cylinders(4096, 2048, 0.25), "fp64", 1e-10,
+                                   "4096x2048_fp64"),
+                                  (W.five_cylinders(4096, 2048, 0.25), "fp32_ir", 1e-10,
+                                   "4096x2048_fp32_ir")):
         d, k, b = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device="cuda:0")
         out[key] = both(lambda: mfp.psi_solve(case.grid, case.circles, d, k, b, case.flow,
                                               rtol=rtol, precision=prec, pair=case.pair,
