@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -566,6 +567,62 @@ def mixed_cell_mesh(mfp, W):
     return out
 
 
+def airfoils_kutta(mfp, W):
+    """Two cambered Joukowski airfoils (chord 2, sharp trailing edges) in the 1024 x 512
+    channel, mixed-cell mesh, each with a Kutta point 0.3 behind its trailing edge:
+    mesh time and the Kutta solve (three constrained FP64 solves to 1e-12 combined on
+    the host), with the circulation the flow gives each airfoil."""
+    import torch
+    bodies = [("joukowski", -1.0, 0.5, 0.5, -0.04, 0.05, 0.08),
+              ("joukowski", 1.5, -0.8, 0.5, -0.04, 0.05, 0.08)]
+    grid = W.Grid(1024, 512, -20.0, 20.0, -10.0, 10.0)
+    flow = W.Flow(1.0, (W.BC_DIRICHLET_UY, W.BC_NATURAL, W.BC_DIRICHLET_UY,
+                        W.BC_DIRICHLET_UY))
+    gm, mesh_ms = _timed(lambda: mfp.mixed_mesh_bodies(grid, bodies, 200, device="cuda:0"),
+                         reps=3)
+    pts = []
+    for b in bodies:
+        ca, sa = math.cos(b[6]), math.sin(b[6])
+        te = (b[1] + ca * 2.0 * b[3], b[2] - sa * 2.0 * b[3])
+        pts.append((te[0] + 0.3 * ca, te[1] - 0.3 * sa))
+    r, ms = _timed(lambda: mfp.mixed_psi_solve_kutta(gm, flow, pts, rtol=1e-12), reps=2)
+    airfoils_kutta.last = (grid, bodies, flow, pts, gm, r)
+    return {"workload": "two Joukowski airfoils (c = 0.5, xi0 = -0.04, eta0 = 0.05, "
+                        "alpha = 0.08) at (-1, 0.5) and (1.5, -0.8), 1024x512 cells on "
+                        "[-20,20]x[-10,10]; Kutta points 0.3 behind the trailing edges; "
+                        "FP64 to 1e-12",
+            "mesh_ms": round(mesh_ms, 3), "cut_points": gm.n_points, "elements": gm.n_elems,
+            "triangles": gm.n_tri, "kutta_nodes": r.kutta_nodes,
+            "solve_ms": round(ms, 2), "iters_all_subsolves": r.stats["iters"],
+            "relres_true_max": r.stats["relres_true"], "psi_b": r.psi_b}
+
+
+def airfoils_vs_oracle(grid, bodies, flow, pts, gm, r):
+    """CPU leg: the oracle's airfoil mesh and direct nonsymmetric Kutta solve against the
+    GPU's (mesh bit for bit; psi, psi_b; the circulation of each airfoil)."""
+    import numpy as np
+    from oracle import airfoil as OA
+    from oracle import kutta as OK
+    from oracle import mixed as OM
+    t0 = time.perf_counter()
+    obodies = [OA.Joukowski(*b[1:]) for b in bodies]
+    mm = OM.mixed_mesh_bodies(grid, obodies, 200)
+    sol = OK.mixed_solve_kutta(mm, flow, pts)
+    used = np.zeros(mm.n_nodes, bool)
+    used[mm.elem_nodes[mm.elem_nodes >= 0]] = True
+    psi = r.psi.cpu().numpy()
+    scale = np.abs(sol.psi).max()
+    return {"oracle_s": round(time.perf_counter() - t0, 1),
+            "mesh_bitwise": bool(np.array_equal(gm.pxy.cpu().numpy(), mm.pxy)
+                                 and np.array_equal(gm.disp.cpu().numpy(), mm.disp.reshape(-1))
+                                 and np.array_equal(gm.elem.cpu().numpy(), mm.elem_nodes)),
+            "psi_node_max_rel": float(np.abs(psi - sol.psi)[used].max() / scale),
+            "psi_b_max_abs": float(np.abs(np.asarray(r.psi_b) - sol.psi_b).max()),
+            "circulation": [float(v) for v in sol.body_rows],
+            "kutta_circulation_isolated": [OA.Joukowski(*b[1:]).kutta_circulation(1.0)
+                                           for b in bodies]}
+
+
 def mixed_vs_oracle(case, gm, res):
     """CPU leg: the oracle's mixed-cell mesh and direct solve of the same workload
     against the GPU's (mesh bit for bit; psi, psi_b and CoPFI errors)."""
@@ -662,7 +719,9 @@ def main():
               flush=True)
         return
     if args.mixed_cell_only:
-        print(json.dumps({"mixed_cell_mesh_1024x512": mixed_cell_mesh(mfp, W)}), flush=True)
+        out = {"mixed_cell_mesh_1024x512": mixed_cell_mesh(mfp, W),
+               "airfoils_kutta_1024x512": airfoils_kutta(mfp, W)}
+        print(json.dumps(out), flush=True)
         return
     case = W.five_cyl_1024()
     dev = "cuda:0"
@@ -714,6 +773,7 @@ def main():
         extras["delta_sweep_256"] = delta_sweep(mfp, W)
         extras["autotune"] = autotune_effect(mfp, W)
         extras["mixed_cell_mesh_1024x512"] = mixed_cell_mesh(mfp, W)
+        extras["airfoils_kutta_1024x512"] = airfoils_kutta(mfp, W)
     cpu = None
     vs_oracle = {"kappa_gpu_lanczos": kappa}
     if not args.no_cpu_baseline:
@@ -725,6 +785,9 @@ def main():
         if "mixed_cell_mesh_1024x512" in extras:
             extras["mixed_cell_mesh_1024x512"]["vs_oracle"] = mixed_vs_oracle(
                 *mixed_cell_mesh.last)
+        if "airfoils_kutta_1024x512" in extras:
+            extras["airfoils_kutta_1024x512"]["vs_oracle"] = airfoils_vs_oracle(
+                *airfoils_kutta.last)
     s = res.stats
     line = {
         "metric": METRIC,
