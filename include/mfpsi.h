@@ -530,9 +530,13 @@ int mfp_body_bounds(const mfp_body* bodies_h, int32_t nbody, mfp_circle* bounds_
 /* Workspace bytes for mfp_mixed_mesh (0 for an invalid grid or body count). */
 size_t mfp_mixed_workspace_size(const mfp_grid* grid, int32_t nbody);
 
-/* Builds the mixed-cell mesh into *m.  disp, body, hpt, vpt and cell_first are always
+/* Builds the mixed-cell mesh into *m.  body, hpt, vpt and cell_first are always
  * written; the cut points and elements are copied up to cap_points / cap_elems (the
  * counts are reported in full, so a first call with zero capacities sizes a second).
+ * disp holds the smoothed displacements, except after a call with both capacities
+ * zero, which skips the sweeps (counts do not depend on them) and leaves disp zero.
+ * Sweep k updates only the node box of the bodies' bounding circles widened by k + 1
+ * nodes: the displacement spreads one node per sweep, so the result is the same.
  * Synchronises `stream`.  MFP_E_GEOMETRY as mfp_check_geometry and for the mesh
  * rejections above (message names which). */
 int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,

@@ -301,14 +301,20 @@ __device__ __forceinline__ void cut_disp(const G& g, const double* __restrict__ 
   dy = pxy[2 * k + 1] - node_y(g, jn);
 }
 
-__global__ void k_mx_sweep(G g, double wx, double wy, const int8_t* __restrict__ body,
-                           const int* __restrict__ hpt, const int* __restrict__ vpt,
-                           const double* __restrict__ pxy, const double* __restrict__ din,
-                           double* __restrict__ dout) {
+// One Jacobi sweep over the node box [i0, i1] x [j0, j1] (nodes outside it are zero in
+// both buffers and stay so: the displacement spreads one node per sweep from the
+// fluid nodes next to a cut edge).
+__global__ void k_mx_sweep(G g, int i0, int i1, int j0, int j1, double wx, double wy,
+                           const int8_t* __restrict__ body, const int* __restrict__ hpt,
+                           const int* __restrict__ vpt, const double* __restrict__ pxy,
+                           const double* __restrict__ din, double* __restrict__ dout) {
   const long long nn = g.nn();
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < nn;
-       n += (long long)gridDim.x * blockDim.x) {
-    const int j = (int)(n / (g.nx + 1)), i = (int)(n - (long long)j * (g.nx + 1));
+  const int bw = i1 - i0 + 1;
+  const long long nbox = (long long)bw * (j1 - j0 + 1);
+  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nbox;
+       q += (long long)gridDim.x * blockDim.x) {
+    const int j = j0 + (int)(q / bw), i = i0 + (int)(q - (long long)(q / bw) * bw);
+    const long long n = (long long)j * (g.nx + 1) + i;
     double ox = din[n], oy = din[n + nn];
     if (body[n] < 0 && i > 0 && i < g.nx && j > 0 && j < g.ny) {
       double ex, ey, wxx, wyy, nx_, ny_, sx, sy;
@@ -915,9 +921,36 @@ static int make_body(const mfp_body& d, MxBody* out, mfp_circle* bound) {
   return MFP_OK;
 }
 
-static int mesh_impl(const mfp_grid* grid, const MxBody* bodies_h, int32_t nbody,
-                     int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
-                     void* stream_) {
+static int mesh_impl(const mfp_grid* grid, const MxBody* bodies_h, const mfp_circle* bounds,
+                     int32_t nbody, int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws,
+                     size_t ws_bytes, void* stream_) {
+  // node box of every fluid node next to a cut edge: the bodies' bounding circles'
+  // boxes widened by one node (empty when there is no body)
+  int box[4] = {1, 0, 1, 0};
+  {
+    const double bhx = grid_hx(*grid), bhy = grid_hy(*grid);
+    for (int b = 0; b < nbody; ++b) {
+      const int i0 = (int)std::floor((bounds[b].cx - bounds[b].r - grid->x0) / bhx) - 1;
+      const int i1 = (int)std::ceil((bounds[b].cx + bounds[b].r - grid->x0) / bhx) + 1;
+      const int j0 = (int)std::floor((bounds[b].cy - bounds[b].r - grid->y0) / bhy) - 1;
+      const int j1 = (int)std::ceil((bounds[b].cy + bounds[b].r - grid->y0) / bhy) + 1;
+      if (b == 0 || box[0] > box[1]) {
+        box[0] = i0;
+        box[1] = i1;
+        box[2] = j0;
+        box[3] = j1;
+      } else {
+        box[0] = std::min(box[0], i0);
+        box[1] = std::max(box[1], i1);
+        box[2] = std::min(box[2], j0);
+        box[3] = std::max(box[3], j1);
+      }
+    }
+    box[0] = std::max(box[0], 0);
+    box[2] = std::max(box[2], 0);
+    box[1] = std::min(box[1], grid->nx);
+    box[3] = std::min(box[3], grid->ny);
+  }
   if (!m || !ws || !m->disp || !m->body || !m->hpt || !m->vpt || !m->cell_first ||
       nsweeps < 0 || m->cap_points < 0 || m->cap_elems < 0 ||
       (m->cap_points > 0 && (!m->pxy || !m->pbody || !m->pedge)) ||
@@ -948,13 +981,21 @@ static int mesh_impl(const mfp_grid* grid, const MxBody* bodies_h, int32_t nbody
   MFP_TRY_HIP(hipGetLastError());
   // sweeps, ping-pong between the caller's array and the workspace
   MFP_TRY_HIP(hipMemsetAsync(m->disp, 0, sizeof(double) * 2 * nn, st));
+  MFP_TRY_HIP(hipMemsetAsync(w.dtmp, 0, sizeof(double) * 2 * nn, st));
   const double hx = g.hx, hy = g.hy;
   const double s = 2.0 * (hx * hx + hy * hy);
   const double wx = (hy * hy) / s, wy = (hx * hx) / s;
   double* a = m->disp;
   double* b = w.dtmp;
-  for (int k = 0; k < nsweeps; ++k) {
-    k_mx_sweep<<<blocks_for(nn), MB, 0, st>>>(g, wx, wy, m->body, m->hpt, m->vpt, w.pxy, a, b);
+  // a sizing call (no room for points or elements) needs no displacements
+  const int sweeps = (m->cap_points == 0 && m->cap_elems == 0) || nbody == 0 ? 0 : nsweeps;
+  for (int k = 0; k < sweeps; ++k) {
+    const int i0 = std::max(0, box[0] - k), i1 = std::min(g.nx, box[1] + k);
+    const int j0 = std::max(0, box[2] - k), j1 = std::min(g.ny, box[3] + k);
+    const long long nbox =
+        (i1 < i0 || j1 < j0) ? 0 : (long long)(i1 - i0 + 1) * (j1 - j0 + 1);
+    k_mx_sweep<<<blocks_for(nbox), MB, 0, st>>>(g, i0, i1, j0, j1, wx, wy, m->body, m->hpt,
+                                                 m->vpt, w.pxy, a, b);
     double* t = a;
     a = b;
     b = t;
@@ -1012,7 +1053,7 @@ extern "C" int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h,
   MFP_TRY(check_geometry(grid, circles_h, nbody));
   std::vector<MxBody> hb((size_t)(nbody > 0 ? nbody : 1));
   for (int b = 0; b < nbody; ++b) hb[b] = circle_body(circles_h[b]);
-  return mesh_impl(grid, hb.data(), nbody, nsweeps, m, ws, ws_bytes, stream_);
+  return mesh_impl(grid, hb.data(), circles_h, nbody, nsweeps, m, ws, ws_bytes, stream_);
 }
 
 extern "C" int mfp_body_bounds(const mfp_body* bodies_h, int32_t nbody, mfp_circle* bounds_h) {
@@ -1040,7 +1081,7 @@ extern "C" int mfp_mixed_mesh_bodies(const mfp_grid* grid, const mfp_body* bodie
   std::vector<mfp_circle> bounds((size_t)(nbody > 0 ? nbody : 1));
   for (int b = 0; b < nbody; ++b) MFP_TRY(make_body(bodies_h[b], &hb[b], &bounds[b]));
   MFP_TRY(check_geometry(grid, bounds.data(), nbody));
-  return mesh_impl(grid, hb.data(), nbody, nsweeps, m, ws, ws_bytes, stream_);
+  return mesh_impl(grid, hb.data(), bounds.data(), nbody, nsweeps, m, ws, ws_bytes, stream_);
 }
 
 namespace mfp {
