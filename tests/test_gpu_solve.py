@@ -358,8 +358,8 @@ def test_bench_workload_1024x512_matches_oracle_direct_solve(mfp):
     """The benchmark's workload at its full size (1024x512, 520,722 unknowns) and in
     the benchmark's configuration (FP64 to relative residual 1e-12, default batches)
     against the oracle's direct sparse solve: nodal psi, psi_b, Q, CoPFI and every
-    surface sample.  At kappa ~ 1e5 a residual of 1e-12 allows relative errors up to
-    ~1e-7 in the worst case; measured: psi 1.0e-11, psi_b 1.8e-11, Q 3.5e-11, CoPFI
+    surface sample.  At kappa = 2.6e6 (the oracle's eigenvalues) a residual of 1e-12
+    allows relative errors up to ~3e-6 in the worst case; measured: psi 1.0e-11, psi_b 1.8e-11, Q 3.5e-11, CoPFI
     1.4e-11, u_t 6.8e-11 of max|u_t|.  Bars: 2e-10 on psi (relative L2) and on psi_b,
     Q, CoPFI (absolute), 1e-8 of max|u_t| on u_t (it divides psi differences by d ~ h)."""
     c = W.five_cyl_1024()
