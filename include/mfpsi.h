@@ -517,7 +517,7 @@ typedef struct {
   int32_t kind;       /* MFP_BODY_CIRCLE or MFP_BODY_JOUKOWSKI                          */
   double x, y;        /* circle centre; airfoil: position of the image of zeta = 0      */
   double r;           /* circle radius; airfoil: the map constant c > 0                 */
-  double xi0, eta0;   /* airfoil: centre of the generating circle, -c <= xi0 <= 0       */
+  double xi0, eta0;   /* airfoil: centre of the generating circle, -c <= xi0 < 0        */
   double alpha;       /* airfoil: angle of attack (radians)                             */
 } mfp_body;
 
@@ -537,8 +537,9 @@ size_t mfp_mixed_workspace_size(const mfp_grid* grid, int32_t nbody);
  * zero, which skips the sweeps (counts do not depend on them) and leaves disp zero.
  * Sweep k updates only the node box of the bodies' bounding circles widened by k + 1
  * nodes: the displacement spreads one node per sweep, so the result is the same.
- * Synchronises `stream`.  MFP_E_GEOMETRY as mfp_check_geometry and for the mesh
- * rejections above (message names which). */
+ * Synchronises `stream`.  MFP_E_GEOMETRY as mfp_check_geometry, for the mesh
+ * rejections above, and for a body that holds no grid node (too thin for the grid;
+ * the message names which). */
 int mfp_mixed_mesh(const mfp_grid* grid, const mfp_circle* circles_h, int32_t nbody,
                    int32_t nsweeps, mfp_mixed_mesh_t* m, void* ws, size_t ws_bytes,
                    void* stream);

@@ -330,6 +330,9 @@ def mixed_mesh_bodies(grid, bodies, nsweeps=200):
     check_geometry(grid, circles)
     kind, body = classify_bodies(grid, bodies)
     hpt, vpt, pxy, pbody = cut_points(grid, bodies, body)
+    for b in range(len(bodies)):
+        if not np.any(pbody == b):
+            raise GeometryError(f"body {b} holds no grid node: the grid does not resolve it")
     d = smooth_mixed(grid, body, hpt, vpt, pxy, nsweeps)
     polys = _cell_polygons(grid, body, hpt, vpt, pxy)
     ne = len(polys)

@@ -891,8 +891,8 @@ static int make_body(const mfp_body& d, MxBody* out, mfp_circle* bound) {
   }
   if (d.kind != MFP_BODY_JOUKOWSKI || !(d.r > 0.0) || !std::isfinite(d.x) ||
       !std::isfinite(d.y) || !std::isfinite(d.xi0) || !std::isfinite(d.eta0) ||
-      !std::isfinite(d.alpha) || !(d.xi0 <= 0.0) || d.xi0 < -d.r) {
-    set_error("body: kind MFP_BODY_CIRCLE or MFP_BODY_JOUKOWSKI with c > 0, -c <= xi0 <= 0 "
+      !std::isfinite(d.alpha) || !(d.xi0 < 0.0) || d.xi0 < -d.r) {
+    set_error("body: kind MFP_BODY_CIRCLE or MFP_BODY_JOUKOWSKI with c > 0, -c <= xi0 < 0 "
               "and finite parameters");
     return MFP_E_ARG;
   }
@@ -1032,14 +1032,24 @@ static int mesh_impl(const mfp_grid* grid, const MxBody* bodies_h, const mfp_cir
     MFP_TRY_HIP(hipMemcpyAsync(m->elem, w.elem, sizeof(int) * 4 * nel, hipMemcpyDeviceToDevice, st));
     MFP_TRY_HIP(hipMemcpyAsync(m->nne, w.nne, nel, hipMemcpyDeviceToDevice, st));
   }
-  // triangles among the elements
+  // triangles among the elements, and cut points per body
   std::vector<int8_t> hn((size_t)counts[1]);
+  std::vector<int8_t> hp((size_t)counts[0]);
   if (counts[1] > 0)
     MFP_TRY_HIP(hipMemcpyAsync(hn.data(), w.nne, hn.size(), hipMemcpyDeviceToHost, st));
+  if (counts[0] > 0)
+    MFP_TRY_HIP(hipMemcpyAsync(hp.data(), w.pbody, hp.size(), hipMemcpyDeviceToHost, st));
   MFP_TRY_HIP(hipStreamSynchronize(st));
   long long ntri = 0;
   for (int8_t v : hn) ntri += v == 3;
   m->n_tri = ntri;
+  std::vector<int> per((size_t)(nbody > 0 ? nbody : 1), 0);
+  for (int8_t v : hp) ++per[v];
+  for (int b = 0; b < nbody; ++b)
+    if (per[b] == 0) {
+      set_error("body %d holds no grid node: the grid does not resolve it", b);
+      return MFP_E_GEOMETRY;
+    }
   return MFP_OK;
 }
 

@@ -150,3 +150,14 @@ def test_two_airfoils_full_size_1024x512(mfp):
     used = np.zeros(mm.n_nodes, bool)
     used[mm.elem_nodes[mm.elem_nodes >= 0]] = True
     assert np.abs(res.psi.cpu().numpy() - ref.psi)[used].max() <= 1e-8 * scale
+
+
+def test_unresolved_and_invalid_bodies_rejected(mfp):
+    g = W.Grid(16, 16, -4.0, 4.0, -4.0, 4.0)
+    with pytest.raises(mfp.MfpError, match="holds no grid node") as e:
+        mfp.mixed_mesh_bodies(g, [("joukowski", 0.0, 0.25, 1.0, -0.001, 0.0, 0.0)], 10,
+                              device=DEV)
+    assert e.value.status == mfp.MFP_E_GEOMETRY
+    with pytest.raises(mfp.MfpError) as e:
+        mfp.body_bounds([("joukowski", 0.0, 0.0, 1.0, 0.0, 0.1, 0.0)])   # no thickness
+    assert e.value.status == mfp.MFP_E_ARG

@@ -136,3 +136,12 @@ def test_kutta_point_on_the_dividing_streamline_recovers_the_kutta_flow():
     rel = [abs(r - gk) / abs(gk) for r in rows]
     assert rel[0] > rel[1] > rel[2] and rel[2] < 0.02
     assert min(mpc) > 0.2
+
+
+def test_a_body_the_grid_does_not_resolve_is_rejected():
+    """A thin airfoil (0.4% thick) placed between the node rows of a coarse grid holds
+    no node: no cut point, no constraint to solve for."""
+    g = W.Grid(16, 16, -4.0, 4.0, -4.0, 4.0)
+    thin = A.Joukowski(0.0, 0.25, 1.0, -0.001, 0.0, 0.0)
+    with pytest.raises(O.GeometryError, match="holds no grid node"):
+        M.mixed_mesh_bodies(g, [thin], 10)
