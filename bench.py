@@ -192,6 +192,15 @@ def _timed(fn, reps=1):
     return out, 1e3 * best
 
 
+def _kernel_label(case, stats, prec="fp64"):
+    """The iteration kernel of a solve: element type, task rows and launch shape."""
+    label = "k_step<%s, %d>" % ("double" if prec == "fp64" else "float",
+                                _task_height(case, stats["n_tiles"]))
+    if stats.get("step_block_waves") == 8:
+        label += " (8-wavefront blocks, task table)"
+    return label
+
+
 def _task_height(case, n_tiles):
     """Node rows per task of a solve's layout, from its task count (strips of 62 node
     columns x chunks of hc node rows)."""
@@ -223,9 +232,8 @@ def mixed_precision(mfp, W, kmax=10 ** 7):
         if r.stats["apply_samples"] > 0:
             nbytes = nbytes64 if prec == "fp64" else nbytes32
             kms = r.stats["apply_ms"]
-            hc = _task_height(case, r.stats["n_tiles"])
             out[prec]["roofline"] = {
-                "kernel": "k_step<%s, %d>" % ("double" if prec == "fp64" else "float", hc),
+                "kernel": _kernel_label(case, r.stats, prec),
                 "launch_ms": round(kms, 5), "bytes_per_launch": nbytes,
                 "achieved_GBs": round(nbytes / (kms * 1e-3) / 1e9, 1),
                 "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -430,7 +438,7 @@ def potential_solve(mfp, W):
            "dof_iter_per_s": s["n_dof"] * s["iters"] / (ms * 1e-3)}
     if s["apply_samples"] > 0:
         kms = s["apply_ms"]
-        out["roofline"] = {"kernel": "k_step<double, %d>" % _task_height(case, s["n_tiles"]),
+        out["roofline"] = {"kernel": _kernel_label(case, s),
                            "launch_ms": round(kms, 5), "bytes_per_launch": nbytes,
                            "achieved_GBs": round(nbytes / (kms * 1e-3) / 1e9, 1),
                            "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
@@ -754,7 +762,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": traffic_from_profile(),
-                    "kernel": "k_step<double, %d>" % _task_height(case, res.stats["n_tiles"]),
+                    "kernel": _kernel_label(case, res.stats),
                     "launch_ms": round(ms, 5), "bytes_per_launch": nbytes,
                     "samples": int(sum(r.stats["apply_samples"] for _, _, r in outs))}
     # condition estimate of the benchmark solve from its CG scalars (an extra,

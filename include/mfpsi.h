@@ -177,6 +177,12 @@ typedef struct {
   double kappa_est;
   double ritz_min, ritz_max;
   int64_t kappa_steps;    /* order of T                                                 */
+  /* Launch shape of the last CG run's iteration kernel: work-groups per launch and
+   * wavefronts per work-group (8: one task per wavefront from a table that puts the
+   * tasks with element geometry on distinct SIMDs; 4: wavefront w takes tasks w,
+   * w + W, ...).                                                                     */
+  int64_t step_blocks;
+  int64_t step_block_waves;
 } mfp_stats;
 
 /* Message for the last non-zero status returned on this thread ("" if none). */

@@ -82,7 +82,8 @@ class MfpStats(Structure):
                 ("rnorm0", c_double), ("solve_ms", c_double), ("apply_ms", c_double),
                 ("apply_samples", c_int64), ("n_plain_tiles", c_int64), ("n_tiles", c_int64),
                 ("inner_iters", c_int64), ("kappa_est", c_double), ("ritz_min", c_double),
-                ("ritz_max", c_double), ("kappa_steps", c_int64)]
+                ("ritz_max", c_double), ("kappa_steps", c_int64),
+                ("step_blocks", c_int64), ("step_block_waves", c_int64)]
 
 
 class MfpVariant(Structure):

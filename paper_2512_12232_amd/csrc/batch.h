@@ -387,7 +387,6 @@ static StepArgs<T> batch_step_args(const SolveWs& w, const mfp_grid& g, int nb, 
                                    T* p1, T* q0, T* q1, T* x, DevState* st) {
   StepRun<T> run = make_step_run<T>(w, g, nb, dx, dy, r0, r1, p0, p1, q0, q1, x, st);
   StepArgs<T> a = run.a;
-  a.kdev = 1;
   a.G = GS;
   a.stream = 1;  // k_step_batch stores streaming
   a.npart0 = npart0;

@@ -32,6 +32,16 @@ __device__ __forceinline__ double wave_sum(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// Sum of N per-wavefront values held in LDS at s[0], s[4], s[8], ... (four values per
+// wavefront), as a balanced tree in a fixed order: (w0 + w1) + (w2 + w3), and so on.
+template <int N>
+__device__ __forceinline__ double wave_tree(const double* s) {
+  if constexpr (N == 1)
+    return s[0];
+  else
+    return wave_tree<N / 2>(s) + wave_tree<N / 2>(s + 4 * (N / 2));
+}
+
 // Sum over a 256-thread block; every thread receives the total.  Fixed reduction
 // order, so results are reproducible run to run.
 __device__ __forceinline__ double block_sum(double v, double* s_red) {

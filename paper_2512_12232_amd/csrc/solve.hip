@@ -17,6 +17,7 @@
 #include <dlfcn.h>
 #include <sys/stat.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdlib>
 #include <cstddef>
@@ -650,6 +651,90 @@ static int step_blocks(const Layout& L, int kst = 0, int forced = 0) {
   return (int)g;
 }
 
+// ---- one task per wavefront, geometry tasks on distinct SIMDs --------------------
+// When the tasks fit the wavefronts that a launch of 8-wavefront blocks keeps resident
+// with one block per CU, every wavefront runs one task and the launch lasts as long as
+// its busiest SIMD.  A task that evaluates geometry issues several times the vector
+// instructions of a constant-stencil task, and two on one SIMD take turns at its
+// issue port.  The table below deals the tasks so that no SIMD holds two geometry tasks
+// while another holds none, and gives every XCD an eighth of each kind.  It relies on
+// where the hardware places work-groups and wavefronts (checked on the target with
+// the hardware-id register): work-group k runs on XCD k mod 8, a 512-thread group
+// that fills a CU is alone there, and its wavefronts w and w + 4 share SIMD w mod 4.
+// Were the placement different, the result would be the same, only slower.
+constexpr int PAIR_SLOTS = 8 * 1024;  // table entries: 8 wavefronts x up to 1024 CUs
+
+// Blocks of the table launch for k_step<T, hc> (the device's CU count), or 0 when the
+// table does not apply: the 8-wavefront kernel does not fit exactly one block per CU,
+// or there are more tasks than its wavefronts.
+template <typename T>
+static int pair_blocks(int hc, int ntask) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (cus <= 0 || cus % 8 != 0 || 8 * cus > PAIR_SLOTS || ntask > 8 * cus) return 0;
+  const void* f = hc == 8   ? reinterpret_cast<const void*>(&k_step<T, 8, false, true, false, 8>)
+                  : hc == 5 ? reinterpret_cast<const void*>(&k_step<T, 5, false, true, false, 8>)
+                            : reinterpret_cast<const void*>(&k_step<T, 4, false, true, false, 8>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 8 * 64, 0) != hipSuccess ||
+      per_cu != 1)
+    return 0;
+  return cus;
+}
+
+// The table for `cus` blocks of 8 wavefronts: tab[8 k + w] is the task of wavefront w
+// of block k, or -1, and its flags (bit 0: constant stencil, plain[t] != 0; bit 1: the
+// task holds body nodes, tbody[t] != 0; bits 2..: its body-sum slot tslot[t] + 1), so
+// that the kernel loads no flags before the task's data.  XCD x takes the
+// x-th eighth of the geometry tasks and of the others (each a run of neighbouring
+// tasks in task order); its geometry tasks go one per SIMD (a second one per SIMD only
+// when they outnumber its SIMDs), its other tasks first to the SIMDs left empty, then
+// as second tasks of the SIMDs without a geometry task, then of the rest.  False if
+// some XCD's share exceeds its wavefronts.
+static bool pair_table(const uint8_t* plain, const unsigned long long* tbody, const int* tslot,
+                       int ntask, int cus, int2* tab) {
+  std::vector<int> geo, pl;
+  for (int t = 0; t < ntask; ++t) (plain[t] ? pl : geo).push_back(t);
+  const int S = 4 * (cus / 8);  // SIMDs per XCD
+  const long long ng = (long long)geo.size(), np = (long long)pl.size();
+  for (int e = 0; e < 8 * cus; ++e) tab[e] = make_int2(-1, 1);
+  std::vector<int> first(S), second(S);
+  for (int x = 0; x < 8; ++x) {
+    const int g0 = (int)(ng * x / 8), g1 = (int)(ng * (x + 1) / 8);
+    const int p0 = (int)(np * x / 8), p1 = (int)(np * (x + 1) / 8);
+    if ((g1 - g0) + (p1 - p0) > 2 * S) return false;
+    std::fill(first.begin(), first.end(), -1);
+    std::fill(second.begin(), second.end(), -1);
+    for (int i = g0; i < g1; ++i) {
+      const int u = i - g0;
+      (u < S ? first[u] : second[u - S]) = geo[i];
+    }
+    int k = p0;
+    for (int u = 0; u < S && k < p1; ++u)
+      if (first[u] < 0) first[u] = pl[k++];
+    for (int u = S - 1; u >= 0 && k < p1; --u)
+      if (second[u] < 0) second[u] = pl[k++];
+    if (k != p1) return false;
+    for (int u = 0; u < S; ++u) {
+      const int blk = x + 8 * (u / 4), w = u % 4;
+      tab[8 * blk + w].x = first[u];
+      tab[8 * blk + w + 4].x = second[u];
+    }
+  }
+  // every task exactly once; the flags
+  std::vector<uint8_t> seen(ntask, 0);
+  for (int e = 0; e < 8 * cus; ++e) {
+    const int t = tab[e].x;
+    if (t >= 0 && t < ntask)
+      tab[e].y = (plain[t] ? 1 : 0) | (tbody[t] ? 2 : 0) | ((tslot[t] + 1) << 2);
+    if (t < -1 || t >= ntask || (t >= 0 && seen[t]++)) return false;
+  }
+  for (int t = 0; t < ntask; ++t)
+    if (!seen[t]) return false;
+  return true;
+}
+
 // Segments for a single solve: about as many as the solve loop's kernel keeps
 // resident, less the per-strip slack of the segment bound, so that the whole list runs
 // in one round of wavefronts.
@@ -738,6 +823,8 @@ struct SolveWs {
   const double* cellcoef = nullptr;  // per-cell element entries given by the caller
   unsigned long long fixed_mask = 0;  // bodies held at given values (Dirichlet), bit b
   double fixed[MFP_MAX_BODIES] = {};
+  int2* wtask = nullptr;         // one task per wavefront (pair_table), PAIR_SLOTS entries
+  mutable int pair_blocks = 0;   // blocks of the launch that uses it; 0: table not built
 };
 
 // Task height of a single solve's layout.  The FP32 iteration with 8-row tasks uses
@@ -917,6 +1004,7 @@ static size_t solve_layout(const mfp_grid* g, int nb, int precision, void* base,
   w.circ = bp.take<mfp_circle>(nb > 0 ? nb : 1);
   w.boxes = bp.take<int>(4 * (nb > 0 ? nb : 1));
   w.count = bp.take<int>(1);
+  w.wtask = bp.take<int2>(PAIR_SLOTS);
   if (w.sc.kst) {
     // every task could be a geometry task
     w.tgeo = bp.take<int>(nt);
@@ -1209,6 +1297,8 @@ struct CgCount {
   long long applies = 0;   // operator applications over all runs
   double tsum = 0.0;       // sampled kernel durations (ms)
   long long tcnt = 0;
+  int blocks = 0;          // launch shape of the last run: blocks, wavefronts per block
+  int block_waves = 0;
 };
 
 // The one-kernel iteration over one set of vectors (FP64: w.r/r1, p0/p1, q/q1, x;
@@ -1381,7 +1471,14 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
   }
   volatile int* flag = &io->flag;
   *flag = 0;  // no launch of an earlier run is in flight (every run ends synchronised)
-  const int G = step_blocks<T>(w.L, run.a.kcoef ? 1 : 0, w.sc.blocks);
+  int G = step_blocks<T>(w.L, run.a.kcoef ? 1 : 0, w.sc.blocks);
+  if (w.pair_blocks > 0 && !run.a.kcoef &&
+      pair_blocks<T>(w.L.hc, w.L.ntasks()) == w.pair_blocks) {
+    run.a.wtask = w.wtask;
+    G = w.pair_blocks;
+  }
+  cnt->blocks = G;
+  cnt->block_waves = run.a.wtask ? 8 : WAVES;
   const int every = o.check_every > 0 ? o.check_every : 16;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
   // ev[b % NE] marks the end of batch b - 1 (ev[0]: the start of batch 0); an event is
@@ -1588,6 +1685,7 @@ struct SolveInfo {
   double apply_ms = 0.0, solve_ms = 0.0;
   double kappa = 0.0, ritz_min = 0.0, ritz_max = 0.0;
   long long kappa_steps = 0;
+  int step_blocks = 0, step_block_waves = 0;
 };
 
 // Number of eigenvalues below x of the symmetric tridiagonal with diagonal d[0..m) and
@@ -1724,7 +1822,34 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
                                hipMemcpyHostToDevice, st));
   }
   MFP_TRY_HIP(hipMemcpyAsync(&w.nslots_h, w.nslots, sizeof(int), hipMemcpyDeviceToHost, st));
+  // one task per wavefront when the tasks fit (not with stored entries or a forced
+  // launch size)
+  w.pair_blocks = 0;
+  int pcus = 0;
+  if (!w.sc.kst && w.sc.blocks == 0) {
+    pcus = pair_blocks<double>(w.L.hc, w.L.ntasks());
+    if (opts->precision != MFP_FP64 && !pcus) pcus = pair_blocks<float>(w.L.hc, w.L.ntasks());
+  }
+  const size_t ntp = pcus ? (size_t)w.L.ntasks() : 0;
+  std::vector<uint8_t> plain(ntp);
+  std::vector<unsigned long long> tbody(ntp);
+  std::vector<int> tslot(ntp);
+  if (pcus) {
+    MFP_TRY_HIP(hipMemcpyAsync(plain.data(), w.tplain, ntp, hipMemcpyDeviceToHost, st));
+    MFP_TRY_HIP(hipMemcpyAsync(tbody.data(), w.tbody, sizeof(unsigned long long) * ntp,
+                               hipMemcpyDeviceToHost, st));
+    MFP_TRY_HIP(hipMemcpyAsync(tslot.data(), w.tslot, sizeof(int) * ntp, hipMemcpyDeviceToHost, st));
+  }
   MFP_TRY_HIP(hipStreamSynchronize(st));  // host-side staging buffers above, slot count
+  if (pcus) {
+    std::vector<int2> tab(8 * (size_t)pcus);
+    if (pair_table(plain.data(), tbody.data(), tslot.data(), w.L.ntasks(), pcus, tab.data())) {
+      MFP_TRY_HIP(hipMemcpyAsync(w.wtask, tab.data(), sizeof(int2) * tab.size(),
+                                 hipMemcpyHostToDevice, st));
+      MFP_TRY_HIP(hipStreamSynchronize(st));  // the table's staging buffer
+      w.pair_blocks = pcus;
+    }
+  }
 
   hipEvent_t e0, e1;
   MFP_TRY_HIP(hipEventCreate(&e0));
@@ -1798,6 +1923,8 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
   info->applies = cnt.applies;
   info->apply_ms = cnt.tcnt ? cnt.tsum / cnt.tcnt : 0.0;
   info->apply_samples = cnt.tcnt;
+  info->step_blocks = cnt.blocks;
+  info->step_block_waves = cnt.block_waves;
   info->solve_ms = ms;
   return MFP_OK;
 }
@@ -1846,6 +1973,8 @@ static int fill_stats(const SolveWs& w, const SolveInfo& info, int nb, const Dev
   stats_h->ritz_min = info.ritz_min;
   stats_h->ritz_max = info.ritz_max;
   stats_h->kappa_steps = info.kappa_steps;
+  stats_h->step_blocks = info.step_blocks;
+  stats_h->step_block_waves = info.step_block_waves;
   return MFP_OK;
 }
 

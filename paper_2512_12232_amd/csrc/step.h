@@ -104,16 +104,18 @@ struct StepArgs {
   long long j;                   // this launch
   T cC, cE, cN, cD;              // constant stencil
   T ry;                          // hy / hx
-  // batched launches (kdev != 0): the launch index is st->jbase + the launch's offset in
-  // the replayed block and the start launch is st->k0; the parity slots below replace
-  // the per-launch pointers; G = this system's blocks
-  int kdev;
+  // batched launches (k_step_batch): the launch index is st->jbase + the launch's offset
+  // in the replayed block and the start launch is st->k0; the parity slots below
+  // replace the per-launch pointers; G = this system's blocks
   int G;
   int* host_done;                // single solve: stop code also written here (pinned host)
   double* hist;                  // single solve, may be NULL: hist[2j] = alpha_{j-1} and
   long long hist_cap;            // hist[2j+1] = beta_j as launch j forms them (j < hist_cap)
   const T* kcoef;                // stored element entries (KST instances): slab per task
   const int* tgeo;               // per task: its slab, -1 for constant-stencil tasks
+  const int2* wtask;             // 8-wavefront blocks: one task per wavefront, entry
+                                 // blockIdx * 8 + wave = (task or -1, flags: bit 0 constant
+                                 // stencil, bit 1 body nodes, bits 2.. body-sum slot + 1)
   T* rs[2];
   T* ps[2];
   T* qs[2];
@@ -128,10 +130,18 @@ struct StepArgs {
 // neighbouring tasks share).  Every task's rows, iterate rows and flags are requested
 // one task ahead (a task that evaluates geometry requests its tags and displacements
 // first and the next task's data after its cell march, which needs the registers).
-template <typename T, int HC, bool STREAM, bool XUPD, bool KST>
+// BATCH: a launch of k_step_batch (launch index and parity slots from the device
+// state).  A compile-time choice: with a run-time branch there the compiler splits the
+// kernel-argument loads into several dependent round trips ahead of the first vector
+// load.
+template <typename T, int HC, bool STREAM, bool XUPD, bool KST, int NW = WAVES, bool BATCH = false>
 __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, const int G,
                                           const int koff, double* s_red, double* s_pb,
                                           double* s_qb) {
+  constexpr int NT = NW * 64;  // threads per block
+  // 8-wavefront blocks take their one task and its flags from a table (a.wtask)
+  constexpr bool TAB = NW == 8;
+  static_assert(!(TAB && KST), "the task table is for tasks without stored entries");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs;
@@ -141,7 +151,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   const int nstrip = a.nstrip;
   const int ntask = nstrip * a.nchunk;
   const bool owner = lane >= 1 && lane <= SW;
-  const int W = G * WAVES;
+  const int W = G * NW;
   long long j = a.j, k0 = a.k0;
   gmem<DevState>* const st = as_global(a.st);
   const T* rp = a.rp;
@@ -154,12 +164,12 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   double* part_c = a.part_c;
   const double* bpart_p = a.bpart_p;
   double* bpart_c = a.bpart_c;
-  if (a.kdev) {
+  if constexpr (BATCH) {
     // The launch index must arrive before any vector is requested (the parity slots
     // depend on it), so the stop flag comes with it and a stopped system's blocks
     // leave before they request anything.  One thread reads, the block decides
     // together (see the stop decision below).
-    long long* const s_hdr = reinterpret_cast<long long*>(s_red + 4 * WAVES + 1);
+    long long* const s_hdr = reinterpret_cast<long long*>(s_red + 4 * NW + 1);
     if (tid == 0) {
       s_hdr[0] = st->jbase;
       s_hdr[1] = st->k0;
@@ -213,13 +223,20 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   // next task's data (requested one task ahead)
   T nr[HC + 2], nq[HC + 2], np[HC + 2], nx[HC], n2[HC];  // n2: p_{j-2} (XUPD)
   int n_plain = 1, n_body = 0, n_slot = -1, n_geo = 0;
+  int t = vb * NW + wv, tstep = W, tflags = 1;  // first task, step to the next, flags
   const gmem<int>* const tgeo = as_global(a.tgeo);
   auto fetch = [&](int t) {
-    // flags first: the geometry request waits for them, not for the rows
-    n_plain = tplain[t];
-    n_body = tbody[t] != 0ull;
-    n_slot = tslot[t];
-    if (KST) n_geo = tgeo[t];
+    if constexpr (TAB) {
+      n_plain = tflags & 1;
+      n_body = (tflags >> 1) & 1;
+      n_slot = (tflags >> 2) - 1;
+    } else {
+      // flags first: the geometry request waits for them, not for the rows
+      n_plain = tplain[t];
+      n_body = tbody[t] != 0ull;
+      n_slot = tslot[t];
+      if (KST) n_geo = tgeo[t];
+    }
     const unsigned bo = (unsigned)((int)node0(t) + shift_of(t)) * TS;
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
@@ -257,7 +274,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   double pv[PU][4];
 #pragma unroll
   for (int u = 0; u < PU; ++u) {
-    const int i = min(tid + u * BLOCK, npart - 1);
+    const int i = min(tid + u * NT, npart - 1);
 #pragma unroll
     for (int c = 0; c < 4; ++c) pv[u][c] = pt[4 * i + c];
   }
@@ -272,11 +289,27 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   // slot sums of bodies b0, b1 (K p of iteration j-1); the slot buffer holds at least
   // 64 slots of max(nb, 1) bodies
   const gmem<double>* const bq = bpart_pg;
-  const int b0 = wv, b1 = wv + WAVES;
+  const int b0 = wv, b1 = wv + NW;
   const int nbc = nb > 0 ? nb : 1;
   const double q0_l = bq[(long long)lane * nb + min(b0, nbc - 1)];
   const double q1_l = bq[(long long)lane * nb + min(b1, nbc - 1)];
-  int t = vb * WAVES + wv;
+  if constexpr (TAB) {
+    // the table's entry: the wavefront's task and its flags, by a scalar load issued
+    // behind the vector loads above (which then travel while it waits).  Written out:
+    // the compiler issues a table load that it cannot prove unwritten as a vector load,
+    // and waiting for that one would wait for every vector load before it; and a scalar
+    // load it places first delays those vector loads by its round trip.  The asm waits
+    // for its own result.
+    __builtin_amdgcn_sched_barrier(0);
+    const long long* const ep =
+        reinterpret_cast<const long long*>(a.wtask) + vblk * NW + __builtin_amdgcn_readfirstlane(wv);
+    long long e;
+    asm volatile("s_load_dwordx2 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(e) : "s"(ep));
+    const int ex = (int)(unsigned)e;  // int2 (x, y) in memory: x in the low word
+    t = ex >= 0 ? ex : ntask;
+    tstep = ntask;
+    tflags = (int)(e >> 32);
+  }
   fetch(t < ntask ? t : ntask - 1);  // a wavefront without a task drops what it fetched
 
   int8_t tg[HC + 2];
@@ -302,17 +335,23 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       }
     }
   };
+  // with the table the flags came with the task: the geometry follows the rows at once
+  if constexpr (TAB) {
+    if (t < ntask && !n_plain) load_geom(t, n_geo);
+  }
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
   for (int u = 0; u < PU; ++u) {
-    const bool in = tid + u * BLOCK < npart;
+    const bool in = tid + u * NT < npart;
     s0 += in ? pv[u][0] : 0.0;
     s1 += in ? pv[u][1] : 0.0;
     s2 += in ? pv[u][2] : 0.0;
     s3 += in ? pv[u][3] : 0.0;
   }
-  if (t < ntask && !n_plain) load_geom(t, n_geo);
-  for (int i = tid + PU * BLOCK; i < npart; i += BLOCK) {  // launches of more than 512 blocks
+  if constexpr (!TAB) {
+    if (t < ntask && !n_plain) load_geom(t, n_geo);
+  }
+  for (int i = tid + PU * NT; i < npart; i += NT) {  // launches of more than 512 blocks
     s0 += pt[4 * i];
     s1 += pt[4 * i + 1];
     s2 += pt[4 * i + 2];
@@ -345,10 +384,10 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     // the block leaves on wave 0's reading of the stop flag: the waves read it at
     // different times, and block 0 may set it during this launch (a wave that left
     // alone would leave its share of the block sums unwritten)
-    if (wv == 0) s_red[4 * WAVES] = done ? 1.0 : 0.0;
+    if (wv == 0) s_red[4 * NW] = done ? 1.0 : 0.0;
   }
-  // bodies beyond 2 x WAVES (rare)
-  for (int b = wv + 2 * WAVES; b < nb; b += WAVES) {
+  // bodies beyond 2 NW (rare)
+  for (int b = wv + 2 * NW; b < nb; b += NW) {
     double v = 0.0;
     if (!start)
       for (int sl = lane; sl < nsl; sl += 64) v += bq[(long long)sl * nb + b];
@@ -356,14 +395,14 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     if (lane == 0) s_qb[b] = v;
   }
   __syncthreads();
-  if (s_red[4 * WAVES] != 0.0) return;  // stopped (the same decision in every wave)
+  if (s_red[4 * NW] != 0.0) return;  // stopped (the same decision in every wave)
   const double qb = lane < nb ? s_qb[lane] : 0.0;
   // body parts of r.r and p.Kp, two independent chains
   const double brr = wave_sum(rbp * rbp), bpq = wave_sum(pbp * qb);
-  const double S_rr = (s_red[0] + s_red[4]) + (s_red[8] + s_red[12]);
-  const double S_pq = (s_red[1] + s_red[5]) + (s_red[9] + s_red[13]);
-  const double S_rq = (s_red[2] + s_red[6]) + (s_red[10] + s_red[14]);
-  const double S_qq = (s_red[3] + s_red[7]) + (s_red[11] + s_red[15]);
+  const double S_rr = wave_tree<NW>(s_red);
+  const double S_pq = wave_tree<NW>(s_red + 1);
+  const double S_rq = wave_tree<NW>(s_red + 2);
+  const double S_qq = wave_tree<NW>(s_red + 3);
   double alpha = 0.0, rr_prev;
   int code = 0;
   if (start) {
@@ -429,7 +468,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   // ---- tasks ----
   double prr = 0.0, ppq = 0.0, prq = 0.0, pqq = 0.0;
   bool first = true;
-  for (; t < ntask; t += W) {
+  for (; t < ntask; t += tstep) {
     const unsigned n0 = node0(t);
     const unsigned bo = n0 * TS;
     const bool plain = n_plain != 0;
@@ -455,7 +494,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     first = false;
     T qr[HC];
     if (plain) {
-      if (t + W < ntask) fetch(t + W);
+      if (t + tstep < ntask) fetch(t + tstep);
       stencil_task<T, HC>(a.cC, a.cE, a.cN, a.cD, v, qr);
     } else {
       // body nodes carry p_b, Dirichlet and halo nodes 0 (r is zero there); the
@@ -473,7 +512,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       else
         march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
       // requested after the cell march, which needs the registers
-      if (t + W < ntask) fetch(t + W);
+      if (t + tstep < ntask) fetch(t + tstep);
     }
     double bacc = 0.0;
 #pragma unroll
@@ -516,17 +555,18 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   }
   __syncthreads();
   if (tid < 4) {
-    part_cg[4 * vblk + tid] =
-        (s_fin[tid] + s_fin[4 + tid]) + (s_fin[8 + tid] + s_fin[12 + tid]);
+    part_cg[4 * vblk + tid] = wave_tree<NW>(s_fin + tid);
   }
 }
 
-template <typename T, int HC, bool STREAM, bool XUPD, bool KST>
-__global__ void __launch_bounds__(BLOCK) k_step(StepArgs<T> a) {
-  __shared__ double s_red[4 * WAVES + 4];  // + stop flag, launch header (batched)
+// NW wavefronts per block: 4, or 8 for launches with one task per wavefront from a
+// table (one block per CU; wavefronts w and w + 4 of a block share a SIMD).
+template <typename T, int HC, bool STREAM, bool XUPD, bool KST, int NW = WAVES>
+__global__ void __launch_bounds__(NW * 64) k_step(StepArgs<T> a) {
+  __shared__ double s_red[4 * NW + 4];  // + stop flag, launch header (batched)
   __shared__ double s_pb[MFP_MAX_BODIES];
-  __shared__ double s_qb[MFP_MAX_BODIES + 4 * WAVES];  // + final block sums
-  step_core<T, HC, STREAM, XUPD, KST>(a, blockIdx.x, gridDim.x, 0, s_red, s_pb, s_qb);
+  __shared__ double s_qb[MFP_MAX_BODIES + 4 * NW];  // + final block sums
+  step_core<T, HC, STREAM, XUPD, KST, NW>(a, blockIdx.x, gridDim.x, 0, s_red, s_pb, s_qb);
 }
 
 // Many independent systems in one launch: block b works for system map[b].x as its
@@ -542,7 +582,7 @@ __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restr
   const StepArgs<T>& a = args[vm.x];
   // streaming stores: the systems' vectors together exceed the memory-side cache
   // (measured on a 256-system sweep: 2% faster than cached stores)
-  step_core<T, 4, true, XUPD, KST>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
+  step_core<T, 4, true, XUPD, KST, WAVES, true>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
 }
 
 // Tasks of HC node rows (the layout's); odd launches update the iterate; a.stream
@@ -550,6 +590,24 @@ __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restr
 template <typename T, int HC, bool KST>
 inline void launch_step_k(int G, hipStream_t st, const StepArgs<T>& a) {
   const bool xu = (a.j & 1) != 0;
+  if constexpr (!KST) {
+    if (a.wtask) {
+      // one task per wavefront from the table: G blocks of 8 wavefronts, one per CU
+      constexpr int T8 = 8 * 64;
+      if (a.stream) {
+        if (xu)
+          k_step<T, HC, true, true, false, 8><<<G, T8, 0, st>>>(a);
+        else
+          k_step<T, HC, true, false, false, 8><<<G, T8, 0, st>>>(a);
+      } else {
+        if (xu)
+          k_step<T, HC, false, true, false, 8><<<G, T8, 0, st>>>(a);
+        else
+          k_step<T, HC, false, false, false, 8><<<G, T8, 0, st>>>(a);
+      }
+      return;
+    }
+  }
   if (a.stream) {
     if (xu)
       k_step<T, HC, true, true, KST><<<G, BLOCK, 0, st>>>(a);
