@@ -338,6 +338,8 @@ def test_full_size_4096x2048_matches_oracle_reference(mfp, precision):
     rho_max = 3e-13 if precision == "fp64" else 1.5e-13
     assert res.status == 0
     assert res.stats["relres_true"] <= rho_max
+    # more tasks than wavefronts: the strided assignment, 4-wavefront blocks
+    assert res.stats["step_block_waves"] == 4
     scale = rho_max / cg_meta["true_relative_residual"][0] * 4.0
     psi = res.psi.cpu().numpy()
     dmax = np.abs(psi[nodes] - ref).max()
@@ -366,8 +368,12 @@ def test_bench_workload_1024x512_matches_oracle_direct_solve(mfp):
     res, ref, mesh = run_pair(mfp, c, rtol=1e-12)
     assert res.status == 0 and res.stats["relres_true"] <= 1.5e-12
     # 17 strips x 103 chunks of 5 rows: the layout of 5-row tasks (2193 4-row tasks
-    # would not fit the resident wavefronts in one round)
-    say(f"  tasks {res.stats['n_tiles']}")
+    # would not fit the resident wavefronts in one round); one task per wavefront from
+    # the task table (8-wavefront blocks, at least one wavefront per task)
+    say(f"  tasks {res.stats['n_tiles']} launch {res.stats['step_blocks']} x "
+        f"{res.stats['step_block_waves']}")
+    assert res.stats["step_block_waves"] == 8
+    assert 8 * res.stats["step_blocks"] >= res.stats["n_tiles"]
     assert res.stats["n_dof"] == ref.ndof
     psi = res.psi.cpu().numpy()
     err = np.linalg.norm(psi - ref.psi) / np.linalg.norm(ref.psi)
@@ -386,6 +392,34 @@ def test_bench_workload_1024x512_matches_oracle_direct_solve(mfp):
     assert np.array_equal(res.sample_body.cpu().numpy(), bb)
     np.testing.assert_allclose(res.theta.cpu().numpy(), th, rtol=0, atol=1e-12)
     assert dut <= 1e-8
+
+
+@pytest.mark.parametrize("name", ["five_ragged130x67", "five_gap_lt_h_256x128", "bench1024"])
+def test_task_table_agrees_with_strided_assignment(mfp, name):
+    """The FP64 iteration with one task per wavefront from the task table (8-wavefront
+    blocks, the default when the tasks fit) and with the strided assignment of a forced
+    launch size (4-wavefront blocks, wavefront w taking tasks w, w + W, ...; 8 blocks,
+    so most wavefronts run several tasks) solve the same system: psi within 1e-11 of
+    max|psi| node by node, psi_b within 1e-11, iteration counts within 2 % (the block
+    sums are added in another order)."""
+    c = W.five_cyl_1024() if name == "bench1024" else CASES[name]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    runs = {}
+    for mode, sched in (("table", None), ("strided", {"launch_blocks": 8})):
+        runs[mode] = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-12,
+                                   pair=c.pair, sample_cap=0, schedule=sched)
+        r = runs[mode]
+        say(f"  {name} {mode}: {r.stats['iters']} iterations, launch {r.stats['step_blocks']}"
+            f" x {r.stats['step_block_waves']}")
+        assert r.status == 0 and r.stats["relres_true"] <= 1.5e-12
+    assert runs["table"].stats["step_block_waves"] == 8
+    assert runs["strided"].stats["step_block_waves"] == 4
+    assert runs["strided"].stats["step_blocks"] == 8
+    a, b = runs["table"].psi.cpu().numpy(), runs["strided"].psi.cpu().numpy()
+    assert np.abs(a - b).max() <= 1e-11 * np.abs(b).max()
+    np.testing.assert_allclose(runs["table"].psi_b, runs["strided"].psi_b, rtol=0, atol=1e-11)
+    ia, ib = runs["table"].stats["iters"], runs["strided"].stats["iters"]
+    assert abs(ia - ib) <= 0.02 * ib
 
 
 @pytest.mark.parametrize("name", ["cyl64", "five96x48", "five_ragged130x67",
