@@ -468,13 +468,11 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   // ---- tasks ----
   double prr = 0.0, ppq = 0.0, prq = 0.0, pqq = 0.0;
   bool first = true;
-  for (; t < ntask; t += tstep) {
+  // one task: its rows are in nr, nq, np (and nx, n2); next() requests the next task's
+  auto task = [&](const int t, const bool plain, const bool bm, const int slot, const int geo,
+                  auto&& next) {
     const unsigned n0 = node0(t);
     const unsigned bo = n0 * TS;
-    const bool plain = n_plain != 0;
-    const bool bm = !plain && n_body != 0;
-    const int slot = n_slot;
-    const int geo = n_geo;
     // r_j, p_j (as at a free node until corrected) and p_{j-1} at rows 0..HC+1
     T rj[HC + 2], v[HC + 2], po[HC + 2], xo[HC], p2[HC];
 #pragma unroll
@@ -494,7 +492,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     first = false;
     T qr[HC];
     if (plain) {
-      if (t + tstep < ntask) fetch(t + tstep);
+      next();
       stencil_task<T, HC>(a.cC, a.cE, a.cN, a.cD, v, qr);
     } else {
       // body nodes carry p_b, Dirichlet and halo nodes 0 (r is zero there); the
@@ -512,7 +510,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       else
         march_task<T, HC>(a.ry, lane, tg, v, ddx, ddy, qr);
       // requested after the cell march, which needs the registers
-      if (t + tstep < ntask) fetch(t + tstep);
+      next();
     }
     double bacc = 0.0;
 #pragma unroll
@@ -538,6 +536,12 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       if (bm) body_row(owner, g, (double)qr[r - 1], lane, bacc);
     }
     if (bm && lane < nb) bpart_cg[(long long)slot * nb + lane] = bacc;
+  };
+  for (; t < ntask; t += tstep) {
+    const bool plain = n_plain != 0;
+    task(t, plain, !plain && n_body != 0, n_slot, n_geo, [&] {
+      if (t + tstep < ntask) fetch(t + tstep);
+    });
   }
   // four block sums, fixed order
   prr = wave_sum(prr);
