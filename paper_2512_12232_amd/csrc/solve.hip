@@ -664,36 +664,52 @@ static int step_blocks(const Layout& L, int kst = 0, int forced = 0) {
 // Were the placement different, the result would be the same, only slower.
 constexpr int PAIR_SLOTS = 8 * 1024;  // table entries: 8 wavefronts x up to 1024 CUs
 
-// Blocks of the table launch for k_step<T, hc> (the device's CU count), or 0 when the
-// table does not apply: the 8-wavefront kernel does not fit exactly one block per CU,
-// or there are more tasks than its wavefronts.
+// Blocks of the table launch for k_step<T, hc> (with stored entries: kst) - the
+// device's CU count, one block per CU (where two would fit, the dispatcher still deals
+// the first block of every CU before any second one) - or 0 when the table does not
+// apply: the 8-wavefront kernel does not fit a CU, needs scratch memory (spilled
+// registers), or there are more tasks than its wavefronts.
+template <typename T, bool KST>
+static const void* table_kernel(int hc, bool odd) {
+  if (odd)
+    return hc == 8   ? reinterpret_cast<const void*>(&k_step<T, 8, false, true, KST, 8>)
+           : hc == 5 ? reinterpret_cast<const void*>(&k_step<T, 5, false, true, KST, 8>)
+                     : reinterpret_cast<const void*>(&k_step<T, 4, false, true, KST, 8>);
+  return hc == 8   ? reinterpret_cast<const void*>(&k_step<T, 8, false, false, KST, 8>)
+         : hc == 5 ? reinterpret_cast<const void*>(&k_step<T, 5, false, false, KST, 8>)
+                   : reinterpret_cast<const void*>(&k_step<T, 4, false, false, KST, 8>);
+}
+
 template <typename T>
-static int pair_blocks(int hc, int ntask) {
+static int pair_blocks(int hc, int ntask, bool kst) {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
   if (cus <= 0 || cus % 8 != 0 || 8 * cus > PAIR_SLOTS || ntask > 8 * cus) return 0;
-  const void* f = hc == 8   ? reinterpret_cast<const void*>(&k_step<T, 8, false, true, false, 8>)
-                  : hc == 5 ? reinterpret_cast<const void*>(&k_step<T, 5, false, true, false, 8>)
-                            : reinterpret_cast<const void*>(&k_step<T, 4, false, true, false, 8>);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 8 * 64, 0) != hipSuccess ||
-      per_cu != 1)
-    return 0;
+  for (int odd = 0; odd < 2; ++odd) {
+    const void* f = kst ? table_kernel<T, true>(hc, odd) : table_kernel<T, false>(hc, odd);
+    hipFuncAttributes fa;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, 8 * 64, 0) != hipSuccess ||
+        per_cu < 1 || hipFuncGetAttributes(&fa, f) != hipSuccess || fa.localSizeBytes != 0)
+      return 0;
+  }
   return cus;
 }
 
 // The table for `cus` blocks of 8 wavefronts: tab[8 k + w] is the task of wavefront w
 // of block k, or -1, and its flags (bit 0: constant stencil, plain[t] != 0; bit 1: the
-// task holds body nodes, tbody[t] != 0; bits 2..: its body-sum slot tslot[t] + 1), so
-// that the kernel loads no flags before the task's data.  XCD x takes the
+// task holds body nodes, tbody[t] != 0; bits 2..15: its body-sum slot tslot[t] + 1;
+// bits 16..30: its stored-entry slab tgeo[t] + 1, tgeo may be NULL), so that the
+// kernel loads no flags before the task's data.  XCD x takes the
 // x-th eighth of the geometry tasks and of the others (each a run of neighbouring
 // tasks in task order); its geometry tasks go one per SIMD (a second one per SIMD only
 // when they outnumber its SIMDs), its other tasks first to the SIMDs left empty, then
 // as second tasks of the SIMDs without a geometry task, then of the rest.  False if
 // some XCD's share exceeds its wavefronts.
 static bool pair_table(const uint8_t* plain, const unsigned long long* tbody, const int* tslot,
-                       int ntask, int cus, int2* tab) {
+                       const int* tgeo, int ntask, int cus, int2* tab) {
+  if (ntask >= (1 << 14) - 1) return false;  // slot and slab fields
   std::vector<int> geo, pl;
   for (int t = 0; t < ntask; ++t) (plain[t] ? pl : geo).push_back(t);
   const int S = 4 * (cus / 8);  // SIMDs per XCD
@@ -727,7 +743,8 @@ static bool pair_table(const uint8_t* plain, const unsigned long long* tbody, co
   for (int e = 0; e < 8 * cus; ++e) {
     const int t = tab[e].x;
     if (t >= 0 && t < ntask)
-      tab[e].y = (plain[t] ? 1 : 0) | (tbody[t] ? 2 : 0) | ((tslot[t] + 1) << 2);
+      tab[e].y = (plain[t] ? 1 : 0) | (tbody[t] ? 2 : 0) | ((tslot[t] + 1) << 2) |
+                 ((tgeo ? tgeo[t] + 1 : 0) << 16);
     if (t < -1 || t >= ntask || (t >= 0 && seen[t]++)) return false;
   }
   for (int t = 0; t < ntask; ++t)
@@ -1472,8 +1489,8 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
   volatile int* flag = &io->flag;
   *flag = 0;  // no launch of an earlier run is in flight (every run ends synchronised)
   int G = step_blocks<T>(w.L, run.a.kcoef ? 1 : 0, w.sc.blocks);
-  if (w.pair_blocks > 0 && !run.a.kcoef &&
-      pair_blocks<T>(w.L.hc, w.L.ntasks()) == w.pair_blocks) {
+  if (w.pair_blocks > 0 &&
+      pair_blocks<T>(w.L.hc, w.L.ntasks(), run.a.kcoef != nullptr) == w.pair_blocks) {
     run.a.wtask = w.wtask;
     G = w.pair_blocks;
   }
@@ -1826,24 +1843,28 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
   // launch size)
   w.pair_blocks = 0;
   int pcus = 0;
-  if (!w.sc.kst && w.sc.blocks == 0) {
-    pcus = pair_blocks<double>(w.L.hc, w.L.ntasks());
-    if (opts->precision != MFP_FP64 && !pcus) pcus = pair_blocks<float>(w.L.hc, w.L.ntasks());
+  if (w.sc.blocks == 0) {
+    const bool kst = w.sc.kst != 0;
+    pcus = pair_blocks<double>(w.L.hc, w.L.ntasks(), kst);
+    if (opts->precision != MFP_FP64 && !pcus) pcus = pair_blocks<float>(w.L.hc, w.L.ntasks(), kst);
   }
   const size_t ntp = pcus ? (size_t)w.L.ntasks() : 0;
   std::vector<uint8_t> plain(ntp);
   std::vector<unsigned long long> tbody(ntp);
-  std::vector<int> tslot(ntp);
+  std::vector<int> tslot(ntp), tgeo(w.sc.kst ? ntp : 0);
   if (pcus) {
     MFP_TRY_HIP(hipMemcpyAsync(plain.data(), w.tplain, ntp, hipMemcpyDeviceToHost, st));
     MFP_TRY_HIP(hipMemcpyAsync(tbody.data(), w.tbody, sizeof(unsigned long long) * ntp,
                                hipMemcpyDeviceToHost, st));
     MFP_TRY_HIP(hipMemcpyAsync(tslot.data(), w.tslot, sizeof(int) * ntp, hipMemcpyDeviceToHost, st));
+    if (!tgeo.empty())
+      MFP_TRY_HIP(hipMemcpyAsync(tgeo.data(), w.tgeo, sizeof(int) * ntp, hipMemcpyDeviceToHost, st));
   }
   MFP_TRY_HIP(hipStreamSynchronize(st));  // host-side staging buffers above, slot count
   if (pcus) {
     std::vector<int2> tab(8 * (size_t)pcus);
-    if (pair_table(plain.data(), tbody.data(), tslot.data(), w.L.ntasks(), pcus, tab.data())) {
+    if (pair_table(plain.data(), tbody.data(), tslot.data(), tgeo.empty() ? nullptr : tgeo.data(),
+                   w.L.ntasks(), pcus, tab.data())) {
       MFP_TRY_HIP(hipMemcpyAsync(w.wtask, tab.data(), sizeof(int2) * tab.size(),
                                  hipMemcpyHostToDevice, st));
       MFP_TRY_HIP(hipStreamSynchronize(st));  // the table's staging buffer

@@ -115,7 +115,8 @@ struct StepArgs {
   const int* tgeo;               // per task: its slab, -1 for constant-stencil tasks
   const int2* wtask;             // 8-wavefront blocks: one task per wavefront, entry
                                  // blockIdx * 8 + wave = (task or -1, flags: bit 0 constant
-                                 // stencil, bit 1 body nodes, bits 2.. body-sum slot + 1)
+                                 // stencil, bit 1 body nodes, bits 2..15 body-sum slot + 1,
+                                 // bits 16..30 stored-entry slab + 1)
   T* rs[2];
   T* ps[2];
   T* qs[2];
@@ -141,7 +142,6 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   constexpr int NT = NW * 64;  // threads per block
   // 8-wavefront blocks take their one task and its flags from a table (a.wtask)
   constexpr bool TAB = NW == 8;
-  static_assert(!(TAB && KST), "the task table is for tasks without stored entries");
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   // consecutive virtual blocks share an XCD (work-groups are dealt round-robin to 8 XCDs;
@@ -229,7 +229,8 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     if constexpr (TAB) {
       n_plain = tflags & 1;
       n_body = (tflags >> 1) & 1;
-      n_slot = (tflags >> 2) - 1;
+      n_slot = ((tflags >> 2) & 0x3fff) - 1;
+      if (KST) n_geo = ((tflags >> 16) & 0x7fff) - 1;
     } else {
       // flags first: the geometry request waits for them, not for the rows
       n_plain = tplain[t];
@@ -336,7 +337,9 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     }
   };
   // with the table the flags came with the task: the geometry follows the rows at once
-  if constexpr (TAB) {
+  // (stored entries, 36 or 72 registers, wait for the task: held through the scalar
+  // phase, they made the FP64 kernel spill)
+  if constexpr (TAB && !KST) {
     if (t < ntask && !n_plain) load_geom(t, n_geo);
   }
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
@@ -474,21 +477,19 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     const unsigned n0 = node0(t);
     const unsigned bo = n0 * TS;
     // r_j, p_j (as at a free node until corrected) and p_{j-1} at rows 0..HC+1
-    T rj[HC + 2], v[HC + 2], po[HC + 2], xo[HC], p2[HC];
+    // and the new iterate at the owned rows (odd launches), formed at once so that the
+    // old directions and iterate need no registers during the cell march
+    T rj[HC + 2], v[HC + 2], xn[HC];
 #pragma unroll
     for (int r = 0; r < HC + 2; ++r) {
       rj[r] = nr[r] - al * nq[r];
       v[r] = rj[r] + be * np[r];
-      po[r] = np[r];
     }
     if (XUPD) {
 #pragma unroll
-      for (int r = 0; r < HC; ++r) {
-        xo[r] = nx[r];
-        p2[r] = n2[r];
-      }
+      for (int r = 0; r < HC; ++r) xn[r] = (nx[r] + al2 * n2[r]) + al * np[r + 1];
     }
-    if (!plain && !first) load_geom(t, geo);
+    if (!plain && (!first || (TAB && KST))) load_geom(t, geo);
     first = false;
     T qr[HC];
     if (plain) {
@@ -523,7 +524,7 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       st_vec<STREAM>(rcg, go, owner ? rj[r] : (T)0);
       st_vec<STREAM>(pcg, go, owner ? v[r] : (T)0);
       st_vec<STREAM>(qcg, go, qv);
-      if (XUPD) st_vec<STREAM>(xg, go, owner ? (xo[r - 1] + al2 * p2[r - 1]) + al * po[r] : (T)0);
+      if (XUPD) st_vec<STREAM>(xg, go, owner ? xn[r - 1] : (T)0);
       if (owner) {
         if (fr) {
           const double rd = (double)rj[r], qd = (double)qv;
@@ -537,11 +538,16 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     }
     if (bm && lane < nb) bpart_cg[(long long)slot * nb + lane] = bacc;
   };
-  for (; t < ntask; t += tstep) {
-    const bool plain = n_plain != 0;
-    task(t, plain, !plain && n_body != 0, n_slot, n_geo, [&] {
-      if (t + tstep < ntask) fetch(t + tstep);
-    });
+  if constexpr (TAB) {
+    // one task, nothing to request after it
+    if (t < ntask) task(t, n_plain != 0, n_plain == 0 && n_body != 0, n_slot, n_geo, [] {});
+  } else {
+    for (; t < ntask; t += tstep) {
+      const bool plain = n_plain != 0;
+      task(t, plain, !plain && n_body != 0, n_slot, n_geo, [&] {
+        if (t + tstep < ntask) fetch(t + tstep);
+      });
+    }
   }
   // four block sums, fixed order
   prr = wave_sum(prr);
@@ -594,23 +600,21 @@ __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restr
 template <typename T, int HC, bool KST>
 inline void launch_step_k(int G, hipStream_t st, const StepArgs<T>& a) {
   const bool xu = (a.j & 1) != 0;
-  if constexpr (!KST) {
-    if (a.wtask) {
-      // one task per wavefront from the table: G blocks of 8 wavefronts, one per CU
-      constexpr int T8 = 8 * 64;
-      if (a.stream) {
-        if (xu)
-          k_step<T, HC, true, true, false, 8><<<G, T8, 0, st>>>(a);
-        else
-          k_step<T, HC, true, false, false, 8><<<G, T8, 0, st>>>(a);
-      } else {
-        if (xu)
-          k_step<T, HC, false, true, false, 8><<<G, T8, 0, st>>>(a);
-        else
-          k_step<T, HC, false, false, false, 8><<<G, T8, 0, st>>>(a);
-      }
-      return;
+  if (a.wtask) {
+    // one task per wavefront from the table: G blocks of 8 wavefronts, one per CU
+    constexpr int T8 = 8 * 64;
+    if (a.stream) {
+      if (xu)
+        k_step<T, HC, true, true, KST, 8><<<G, T8, 0, st>>>(a);
+      else
+        k_step<T, HC, true, false, KST, 8><<<G, T8, 0, st>>>(a);
+    } else {
+      if (xu)
+        k_step<T, HC, false, true, KST, 8><<<G, T8, 0, st>>>(a);
+      else
+        k_step<T, HC, false, false, KST, 8><<<G, T8, 0, st>>>(a);
     }
+    return;
   }
   if (a.stream) {
     if (xu)
