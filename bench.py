@@ -193,12 +193,24 @@ def _timed(fn, reps=1):
 
 
 def _kernel_label(case, stats, prec="fp64"):
-    """The iteration kernel of a solve: element type, task rows and launch shape."""
+    """The iteration kernel of a solve: element type, task rows, element mode and launch
+    shape."""
     label = "k_step<%s, %d>" % ("double" if prec == "fp64" else "float",
                                 _task_height(case, stats["n_tiles"]))
+    notes = []
+    if stats.get("step_element_mode") == 2:
+        notes.append("stored entries")
     if stats.get("step_block_waves") == 8:
-        label += " (8-wavefront blocks, task table)"
-    return label
+        notes.append("8-wavefront blocks, task table")
+    return label + (" (%s)" % ", ".join(notes) if notes else "")
+
+
+def _launch_bytes(case, disp, body, stats, esz=8):
+    """Algorithmic bytes per iteration launch for the solve's element mode."""
+    if stats.get("step_element_mode") == 2:
+        return stored_step_bytes(case, body, stats["n_tiles"], stats["n_plain_tiles"],
+                                 _task_height(case, stats["n_tiles"]), esz)
+    return step_bytes(case, disp, body, esz)[0]
 
 
 def _task_height(case, n_tiles):
@@ -219,8 +231,6 @@ def mixed_precision(mfp, W, kmax=10 ** 7):
     disp, kind, body = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device="cuda:0")
     out = {"workload": "five cylinders, 4096x2048 cells, delta 0.5, rtol 1e-10"}
     res = {}
-    nbytes64, _ = step_bytes(case, disp, body)
-    nbytes32, _ = step_bytes(case, disp, body, esz=4)
     for prec, rtol in (("fp64", 1e-10), ("fp32_ir", 1e-10), ("fp32", 1e-6)):
         r, ms = _timed(lambda: mfp.psi_solve(case.grid, case.circles, disp, kind, body,
                                              case.flow, precision=prec, rtol=rtol, kmax=kmax,
@@ -230,7 +240,7 @@ def mixed_precision(mfp, W, kmax=10 ** 7):
                      "relres_true": r.stats["relres_true"], "rtol": rtol,
                      "dof_iter_per_s": r.stats["n_dof"] * r.stats["iters"] / (ms * 1e-3)}
         if r.stats["apply_samples"] > 0:
-            nbytes = nbytes64 if prec == "fp64" else nbytes32
+            nbytes = _launch_bytes(case, disp, body, r.stats, 8 if prec == "fp64" else 4)
             kms = r.stats["apply_ms"]
             out[prec]["roofline"] = {
                 "kernel": _kernel_label(case, r.stats, prec),
@@ -420,9 +430,9 @@ def autotune_effect(mfp, W):
 def potential_solve(mfp, W):
     """The velocity potential of the benchmark workload (1024 x 512 cells, five
     cylinders): phi = U x on inlet and outlet, natural walls and bodies, FP64 CG to
-    1e-12 on the same mesh, with the iteration kernel's roofline (same algorithmic
-    bytes per launch as the stream function's: the same vectors, displacements and
-    tags)."""
+    1e-12 on the same mesh, with the iteration kernel's roofline (the stream
+    function's byte model for the element mode the solve used: the same vectors,
+    tags, and displacements or stored entries)."""
     case = W.potential_flow(W.five_cyl_1024())
     dev = "cuda:0"
     d, k, b = mfp.mesh_conform(case.grid, case.circles, case.nsweeps, device=dev)
@@ -430,7 +440,7 @@ def potential_solve(mfp, W):
                                          rtol=1e-12, profile_every=1), reps=2)
     potential_solve.last = (case, r.phi)
     s = r.stats
-    nbytes, _ = step_bytes(case, d, b)
+    nbytes = _launch_bytes(case, d, b, s)
     out = {"workload": "five cylinders, 1024x512 cells, delta 0.25; phi = U x on inlet and "
                        "outlet, natural walls and bodies; FP64 CG to 1e-12",
            "solve_ms": round(ms, 2), "iters": s["iters"], "n_dof": s["n_dof"],
@@ -754,7 +764,8 @@ def main():
     value = dof_iters / wall
     timed = [(r.stats["apply_ms"], r.stats["apply_samples"]) for _, _, r in outs
              if r.stats["apply_samples"] > 0]
-    nbytes, moved = step_bytes(case, disp, body)
+    nbytes = _launch_bytes(case, disp, body, res.stats)
+    _, moved = step_bytes(case, disp, body)
     roofline = None
     if timed:
         ms = sum(m * n for m, n in timed) / sum(n for _, n in timed)

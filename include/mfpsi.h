@@ -183,6 +183,7 @@ typedef struct {
    * w + W, ...).                                                                     */
   int64_t step_blocks;
   int64_t step_block_waves;
+  int64_t step_element_mode;  /* 1: element geometry on the fly; 2: stored entries      */
 } mfp_stats;
 
 /* Message for the last non-zero status returned on this thread ("" if none). */

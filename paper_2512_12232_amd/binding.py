@@ -83,7 +83,8 @@ class MfpStats(Structure):
                 ("apply_samples", c_int64), ("n_plain_tiles", c_int64), ("n_tiles", c_int64),
                 ("inner_iters", c_int64), ("kappa_est", c_double), ("ritz_min", c_double),
                 ("ritz_max", c_double), ("kappa_steps", c_int64),
-                ("step_blocks", c_int64), ("step_block_waves", c_int64)]
+                ("step_blocks", c_int64), ("step_block_waves", c_int64),
+                ("step_element_mode", c_int64)]
 
 
 class MfpVariant(Structure):

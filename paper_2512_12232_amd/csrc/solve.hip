@@ -1314,8 +1314,9 @@ struct CgCount {
   long long applies = 0;   // operator applications over all runs
   double tsum = 0.0;       // sampled kernel durations (ms)
   long long tcnt = 0;
-  int blocks = 0;          // launch shape of the last run: blocks, wavefronts per block
-  int block_waves = 0;
+  int blocks = 0;          // launch shape of the last run: blocks, wavefronts per block,
+  int block_waves = 0;     // element mode (1 geometry on the fly, 2 stored entries)
+  int element_mode = 0;
 };
 
 // The one-kernel iteration over one set of vectors (FP64: w.r/r1, p0/p1, q/q1, x;
@@ -1496,6 +1497,7 @@ static int step_run(const SolveWs& w, StepRun<T> run, const mfp_solver_opts& o, 
   }
   cnt->blocks = G;
   cnt->block_waves = run.a.wtask ? 8 : WAVES;
+  cnt->element_mode = run.a.kcoef ? 2 : 1;
   const int every = o.check_every > 0 ? o.check_every : 16;
   const int prof = o.profile_every > 0 ? o.profile_every : 0;
   // ev[b % NE] marks the end of batch b - 1 (ev[0]: the start of batch 0); an event is
@@ -1702,7 +1704,7 @@ struct SolveInfo {
   double apply_ms = 0.0, solve_ms = 0.0;
   double kappa = 0.0, ritz_min = 0.0, ritz_max = 0.0;
   long long kappa_steps = 0;
-  int step_blocks = 0, step_block_waves = 0;
+  int step_blocks = 0, step_block_waves = 0, step_element_mode = 0;
 };
 
 // Number of eigenvalues below x of the symmetric tridiagonal with diagonal d[0..m) and
@@ -1946,6 +1948,7 @@ static int solve_core(const mfp_grid& g, const mfp_circle* circles_h, int nb, co
   info->apply_samples = cnt.tcnt;
   info->step_blocks = cnt.blocks;
   info->step_block_waves = cnt.block_waves;
+  info->step_element_mode = cnt.element_mode;
   info->solve_ms = ms;
   return MFP_OK;
 }
@@ -1996,6 +1999,7 @@ static int fill_stats(const SolveWs& w, const SolveInfo& info, int nb, const Dev
   stats_h->kappa_steps = info.kappa_steps;
   stats_h->step_blocks = info.step_blocks;
   stats_h->step_block_waves = info.step_block_waves;
+  stats_h->step_element_mode = info.step_element_mode;
   return MFP_OK;
 }
 
