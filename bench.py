@@ -573,7 +573,7 @@ def mixed_cell_mesh(mfp, W):
             hc = _task_height(case, s["n_tiles"])
             sb = stored_step_bytes(case, gm.body, s["n_tiles"], s["n_plain_tiles"], hc)
             kms = s["apply_ms"]
-            e["roofline"] = {"kernel": "k_step<double, %d> (stored entries)" % hc,
+            e["roofline"] = {"kernel": _kernel_label(case, s),
                              "launch_ms": round(kms, 5), "bytes_per_launch": sb,
                              "achieved_GBs": round(sb / (kms * 1e-3) / 1e9, 1),
                              "frac": round(sb / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
