@@ -719,6 +719,10 @@ __device__ double cut_cell_row(const ApplyMx& a, long long c, long long n, const
 // (its rows sum to zero), a cut cell through its element lists.  Cut point: the two
 // cells on either side of its edge.
 template <class V>
+__device__ __forceinline__ double apply_bg(const ApplyMx& a, long long n, int i, int j,
+                                           double vn, const V& v);
+
+template <class V>
 __device__ __forceinline__ double apply_row(const ApplyMx& a, long long n, double vn,
                                             const V& v) {
   const G& g = a.g;
@@ -733,45 +737,79 @@ __device__ __forceinline__ double apply_row(const ApplyMx& a, long long n, doubl
   }
   const int W = g.nx + 1;
   const int j = (int)(n / W), i = (int)(n - (long long)j * W);
+  return apply_bg(a, n, i, j, vn, v);
+}
+
+// (K v)[n] at background node n = (i, j), as apply_row.
+template <class V>
+__device__ __forceinline__ double apply_bg(const ApplyMx& a, long long n, int i, int j,
+                                           double vn, const V& v) {
+  const G& g = a.g;
+  const int W = g.nx + 1;
   const long long nc = g.nc();
-  // the 3 x 3 neighbourhood, only where a cell can use it
+  // Everything a plain cell needs is requested at once, at clamped addresses (a value
+  // outside the grid belongs to a cell that is skipped): the 3 x 3 neighbourhood, the
+  // four cells' kinds and the three entries of each cell's row of this node.  Tested
+  // first, the kinds would put a second round trip before the entries.
   double P[3][3];
+#pragma unroll
   for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
     for (int dx = 0; dx < 3; ++dx) {
-      const int ii = i + dx - 1, jj = j + dy - 1;
-      P[dy][dx] = (ii >= 0 && ii <= g.nx && jj >= 0 && jj <= g.ny)
-                      ? (dx == 1 && dy == 1 ? vn : v.bg(n + (long long)(dy - 1) * W + (dx - 1)))
-                      : 0.0;
+      const int ii = min(max(i + dx - 1, 0), g.nx), jj = min(max(j + dy - 1, 0), g.ny);
+      P[dy][dx] = (dx == 1 && dy == 1) ? vn : v.bg((long long)jj * W + ii);
     }
   double acc = 0.0;
+  bool cut = false;
+  long long cc[4];
+  // cell k = (i - 1 + (k & 1), j - 1 + (k >> 1)); the node is its corner ca (corners
+  // CCW from the cell's (i, j)): 2, 3, 1, 0
+#pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int ci = i - 1 + (k & 1), cj = j - 1 + (k >> 1);
-    if (ci < 0 || cj < 0 || ci >= g.nx || cj >= g.ny) continue;
-    const long long c = (long long)cj * g.nx + ci;
+    const bool in = ci >= 0 && cj >= 0 && ci < g.nx && cj < g.ny;
+    const long long c =
+        (long long)min(max(cj, 0), g.ny - 1) * g.nx + min(max(ci, 0), g.nx - 1);
+    cc[k] = in ? c : -1;
     const int8_t kind = a.ckind[c];
-    if (kind == CK_QUAD) {
-      // corner a of node (i, j) in cell (ci, cj); corners CCW from (ci, cj)
-      const int ox = i - ci, oy = j - cj;
-      const int ca = oy == 0 ? ox : 3 - ox;
-      const int cx[4] = {0, 1, 1, 0}, cy[4] = {0, 0, 1, 1};
-      for (int b = 0; b < 4; ++b) {
-        if (b == ca) continue;
-        const double vb = P[cj - j + 1 + cy[b]][ci - i + 1 + cx[b]];
-        acc += a.kc[pair_index(ca, b) * nc + c] * (vb - vn);
-      }
-    } else if (kind == CK_CUT) {
-      acc += cut_cell_row(a, c, n, v);
+    constexpr int CA[4] = {2, 3, 1, 0};
+    const int ca = CA[k];
+    const int cx[4] = {0, 1, 1, 0}, cy[4] = {0, 0, 1, 1};
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      if (b == ca) continue;
+      const double vb = P[cj - j + 1 + cy[b]][ci - i + 1 + cx[b]];
+      s += a.kc[pair_index(ca, b) * nc + c] * (vb - vn);
     }
+    acc += (in && kind == CK_QUAD) ? s : 0.0;
+    cut = cut || (in && kind == CK_CUT);
+  }
+  if (cut) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (cc[k] >= 0 && a.ckind[cc[k]] == CK_CUT) acc += cut_cell_row(a, cc[k], n, v);
   }
   return acc;
 }
 
-__global__ void __launch_bounds__(MB) k_mx_apply(ApplyMx a, const double* __restrict__ p,
+// Blocks [0, rows * bpr): background row j = block / bpr (a division per block, none per
+// node), columns (block % bpr) MB + thread; the blocks after them: the cut points.
+__global__ void __launch_bounds__(MB) k_mx_apply(ApplyMx a, int bpr, const double* __restrict__ p,
                                                  double* __restrict__ q) {
   const PlainVec v{p};
-  for (long long n = blockIdx.x * (long long)blockDim.x + threadIdx.x; n < a.ntot;
-       n += (long long)gridDim.x * blockDim.x)
-    q[n] = apply_row(a, n, p[n], v);
+  const G& g = a.g;
+  const int nbg = (g.ny + 1) * bpr;
+  const int b = blockIdx.x;
+  if (b < nbg) {
+    const int j = b / bpr, i = (b - j * bpr) * MB + threadIdx.x;
+    if (i > g.nx) return;
+    const long long n = (long long)j * (g.nx + 1) + i;
+    q[n] = apply_bg(a, n, i, j, p[n], v);
+  } else {
+    const long long n = g.nn() + (long long)(b - nbg) * MB + threadIdx.x;
+    if (n < a.ntot) q[n] = apply_row(a, n, p[n], v);
+  }
 }
 
 }  // namespace mixed
@@ -1191,7 +1229,10 @@ extern "C" int mfp_mixed_element_apply(const mfp_grid* grid, const mfp_mixed_mes
   MFP_TRY_HIP(hipEventCreate(&e0));
   MFP_TRY_HIP(hipEventCreate(&e1));
   MFP_TRY_HIP(hipEventRecord(e0, st));
-  for (int k = 0; k < repeat; ++k) k_mx_apply<<<blocks_for(ntot), MB, 0, st>>>(a, p, q);
+  const int bpr = (grid->nx + 1 + MB - 1) / MB;
+  const long long ncut = ntot - (long long)(grid->nx + 1) * (grid->ny + 1);
+  const long long nblk = (long long)(grid->ny + 1) * bpr + (ncut + MB - 1) / MB;
+  for (int k = 0; k < repeat; ++k) k_mx_apply<<<(unsigned)nblk, MB, 0, st>>>(a, bpr, p, q);
   MFP_TRY_HIP(hipEventRecord(e1, st));
   const hipError_t le = hipGetLastError();
   float ms = 0.f;
