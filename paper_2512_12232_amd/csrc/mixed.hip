@@ -11,8 +11,11 @@
 //                   an edge joining two bodies is an error
 //   (scan)          cut points numbered in edge order: horizontal edges, then vertical
 //   k_mx_cut        the cut point I + t (O - I), |I - c + t (O - I)| = r, t in [0, 1)
-//   k_mx_sweep      Jacobi sweeps of the displacement on fluid nodes; an inside
-//                   neighbour contributes its cut point's displacement P - I
+//   k_mx_sweep_multi Jacobi sweeps of the displacement on fluid nodes, up to 8 per
+//                   launch on LDS tiles; an inside neighbour contributes its cut point's
+//                   displacement P - I.  Sweep k covers the box of the fluid nodes next
+//                   to a cut edge widened by k nodes: outside it every displacement is
+//                   still zero
 //   k_mx_cell_count elements per cell (0, 1 or 2), errors for cells touching two bodies;
 //                   a cell whose inside and fluid corners alternate (a thin part of a
 //                   body crosses it) gets a triangle at each fluid corner
@@ -301,53 +304,114 @@ __device__ __forceinline__ void cut_disp(const G& g, const double* __restrict__ 
   dy = pxy[2 * k + 1] - node_y(g, jn);
 }
 
-// One Jacobi sweep over the node box [i0, i1] x [j0, j1] (nodes outside it are zero in
-// both buffers and stay so: the displacement spreads one node per sweep from the
-// fluid nodes next to a cut edge).
-__global__ void k_mx_sweep(G g, int i0, int i1, int j0, int j1, double wx, double wy,
-                           const int8_t* __restrict__ body, const int* __restrict__ hpt,
-                           const int* __restrict__ vpt, const double* __restrict__ pxy,
-                           const double* __restrict__ din, double* __restrict__ dout) {
+// Up to MJS Jacobi sweeps in one launch (temporal blocking, as the bilinear mesh's
+// k_jacobi_multi); the sweep of one fluid node off the domain's edge is
+// d <- wx (d_E + d_W) + wy (d_N + d_S), an inside neighbour's d being its cut point's
+// displacement P - I.  A block takes one displacement component of an MJT_X x MJT_Y tile of
+// the last sweep's box, reads the tile widened by MJS nodes on every side into LDS and
+// runs the sweeps there: after s sweeps the values are exact at least s nodes in from
+// the region's edge.  A fluid node's inside neighbours contribute fixed values (their
+// cut points' displacements), worked out once per launch into registers.  Every update
+// is the single sweep's expression with the same operands in the same order, so the
+// result is bit for bit that of the sweeps launched one by one.  Nodes outside a
+// sweep's box have not changed since the start (the boxes only grow) and stay as they
+// are.
+constexpr int MJT_X = 64, MJT_Y = 16, MJS = 8;
+struct MxBoxes {
+  int i0[MJS], i1[MJS], j0[MJS], j1[MJS];
+};
+
+__global__ void __launch_bounds__(MB) k_mx_sweep_multi(G g, int ns, MxBoxes bx, double wx,
+                                                       double wy,
+                                                       const int8_t* __restrict__ body,
+                                                       const int* __restrict__ hpt,
+                                                       const int* __restrict__ vpt,
+                                                       const double* __restrict__ pxy,
+                                                       const double* __restrict__ src,
+                                                       double* __restrict__ dst) {
+  constexpr int RW = MJT_X + 2 * MJS, RH = MJT_Y + 2 * MJS;
+  __shared__ double buf[2][RW * RH];
+  __shared__ int8_t bd[RW * RH];  // node bodies (off the grid: -1)
   const long long nn = g.nn();
-  const int bw = i1 - i0 + 1;
-  const long long nbox = (long long)bw * (j1 - j0 + 1);
-  for (long long q = blockIdx.x * (long long)blockDim.x + threadIdx.x; q < nbox;
-       q += (long long)gridDim.x * blockDim.x) {
-    const int j = j0 + (int)(q / bw), i = i0 + (int)(q - (long long)(q / bw) * bw);
+  const int comp = blockIdx.z;  // 0: x, 1: y
+  const double* sv = src + comp * nn;
+  double* dv = dst + comp * nn;
+  const int last = ns - 1;
+  const int gi0 = bx.i0[last] + (int)blockIdx.x * MJT_X - MJS;
+  const int gj0 = bx.j0[last] + (int)blockIdx.y * MJT_Y - MJS;
+  for (int e = threadIdx.x; e < RW * RH; e += MB) {
+    const int i = gi0 + e % RW, j = gj0 + e / RW;
+    const bool in = i >= 0 && i <= g.nx && j >= 0 && j <= g.ny;
     const long long n = (long long)j * (g.nx + 1) + i;
-    double ox = din[n], oy = din[n + nn];
-    if (body[n] < 0 && i > 0 && i < g.nx && j > 0 && j < g.ny) {
-      double ex, ey, wxx, wyy, nx_, ny_, sx, sy;
-      const long long nE = n + 1, nW = n - 1, nN = n + g.nx + 1, nS = n - g.nx - 1;
-      if (body[nE] >= 0)
-        cut_disp(g, pxy, hpt[(long long)j * g.nx + i], i + 1, j, ex, ey);
-      else {
-        ex = din[nE];
-        ey = din[nE + nn];
-      }
-      if (body[nW] >= 0)
-        cut_disp(g, pxy, hpt[(long long)j * g.nx + i - 1], i - 1, j, wxx, wyy);
-      else {
-        wxx = din[nW];
-        wyy = din[nW + nn];
-      }
-      if (body[nN] >= 0)
-        cut_disp(g, pxy, vpt[(long long)j * (g.nx + 1) + i], i, j + 1, nx_, ny_);
-      else {
-        nx_ = din[nN];
-        ny_ = din[nN + nn];
-      }
-      if (body[nS] >= 0)
-        cut_disp(g, pxy, vpt[(long long)(j - 1) * (g.nx + 1) + i], i, j - 1, sx, sy);
-      else {
-        sx = din[nS];
-        sy = din[nS + nn];
-      }
-      ox = wx * (ex + wxx) + wy * (nx_ + sx);
-      oy = wx * (ey + wyy) + wy * (ny_ + sy);
+    buf[0][e] = in ? sv[n] : 0.0;
+    bd[e] = in ? body[n] : (int8_t)-1;
+  }
+  __syncthreads();
+  // per entry of this thread: updatable (a fluid node off the domain's edge), and the
+  // fixed values of its inside neighbours (E, W, N, S; bit d of msk)
+  static_assert(RW * RH % MB == 0, "whole region entries per thread");
+  constexpr int NE = RW * RH / MB;
+  int eli[NE], elj[NE], msk[NE];
+  bool upd[NE];
+  double fix[NE][4];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = (int)threadIdx.x + k * MB;
+    eli[k] = e % RW;
+    elj[k] = e / RW;
+    const int i = gi0 + eli[k], j = gj0 + elj[k];
+    // entries on the region's edge are never updated (their neighbours are not here)
+    const bool inner = eli[k] > 0 && eli[k] < RW - 1 && elj[k] > 0 && elj[k] < RH - 1;
+    const bool interior = i > 0 && i < g.nx && j > 0 && j < g.ny;
+    upd[k] = inner && interior && bd[e] < 0;
+    msk[k] = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) fix[k][d] = 0.0;
+    if (upd[k]) {
+      const int ne[4] = {e + 1, e - 1, e + RW, e - RW};
+      const int ni[4] = {i + 1, i - 1, i, i}, nj[4] = {j, j, j + 1, j - 1};
+#pragma unroll
+      for (int d = 0; d < 4; ++d)
+        if (bd[ne[d]] >= 0) {
+          const int pk = d == 0   ? hpt[(long long)j * g.nx + i]
+                         : d == 1 ? hpt[(long long)j * g.nx + i - 1]
+                         : d == 2 ? vpt[(long long)j * (g.nx + 1) + i]
+                                  : vpt[(long long)(j - 1) * (g.nx + 1) + i];
+          double cx, cy;
+          cut_disp(g, pxy, pk, ni[d], nj[d], cx, cy);
+          fix[k][d] = comp ? cy : cx;
+          msk[k] |= 1 << d;
+        }
     }
-    dout[n] = ox;
-    dout[n + nn] = oy;
+  }
+  int cur = 0;
+  for (int sw = 0; sw < ns; ++sw) {
+    const int li0 = max(bx.i0[sw] - gi0, sw + 1), li1 = min(bx.i1[sw] - gi0, RW - 2 - sw);
+    const int lj0 = max(bx.j0[sw] - gj0, sw + 1), lj1 = min(bx.j1[sw] - gj0, RH - 2 - sw);
+    const double* a = buf[cur];
+    double* b = buf[cur ^ 1];
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      const int e = (int)threadIdx.x + k * MB;
+      double v = a[e];
+      if (upd[k] && eli[k] >= li0 && eli[k] <= li1 && elj[k] >= lj0 && elj[k] <= lj1) {
+        const double ve = (msk[k] & 1) ? fix[k][0] : a[e + 1];
+        const double vw = (msk[k] & 2) ? fix[k][1] : a[e - 1];
+        const double vn = (msk[k] & 4) ? fix[k][2] : a[e + RW];
+        const double vs = (msk[k] & 8) ? fix[k][3] : a[e - RW];
+        v = wx * (ve + vw) + wy * (vn + vs);
+      }
+      b[e] = v;
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  const int bi0 = bx.i0[last], bi1 = bx.i1[last], bj0 = bx.j0[last], bj1 = bx.j1[last];
+  for (int e = threadIdx.x; e < MJT_X * MJT_Y; e += MB) {
+    const int li = MJS + e % MJT_X, lj = MJS + e / MJT_X;
+    const int i = gi0 + li, j = gj0 + lj;
+    if (i >= bi0 && i <= bi1 && j >= bj0 && j <= bj1)
+      dv[(long long)j * (g.nx + 1) + i] = buf[cur][lj * RW + li];
   }
 }
 
@@ -1027,13 +1091,23 @@ static int mesh_impl(const mfp_grid* grid, const MxBody* bodies_h, const mfp_cir
   double* b = w.dtmp;
   // a sizing call (no room for points or elements) needs no displacements
   const int sweeps = (m->cap_points == 0 && m->cap_elems == 0) || nbody == 0 ? 0 : nsweeps;
-  for (int k = 0; k < sweeps; ++k) {
-    const int i0 = std::max(0, box[0] - k), i1 = std::min(g.nx, box[1] + k);
-    const int j0 = std::max(0, box[2] - k), j1 = std::min(g.ny, box[3] + k);
-    const long long nbox =
-        (i1 < i0 || j1 < j0) ? 0 : (long long)(i1 - i0 + 1) * (j1 - j0 + 1);
-    k_mx_sweep<<<blocks_for(nbox), MB, 0, st>>>(g, i0, i1, j0, j1, wx, wy, m->body, m->hpt,
-                                                 m->vpt, w.pxy, a, b);
+  // MJS sweeps per launch (k_mx_sweep_multi); sweep k covers box widened by k
+  for (int k0 = 0; k0 < sweeps; k0 += MJS) {
+    const int ns = std::min(MJS, sweeps - k0);
+    MxBoxes bx;
+    for (int q = 0; q < ns; ++q) {
+      const int k = k0 + q;
+      bx.i0[q] = std::max(0, box[0] - k);
+      bx.i1[q] = std::min(g.nx, box[1] + k);
+      bx.j0[q] = std::max(0, box[2] - k);
+      bx.j1[q] = std::min(g.ny, box[3] + k);
+    }
+    const int lw = bx.i1[ns - 1] - bx.i0[ns - 1] + 1, lh = bx.j1[ns - 1] - bx.j0[ns - 1] + 1;
+    if (lw > 0 && lh > 0) {
+      const dim3 grid3((lw + MJT_X - 1) / MJT_X, (lh + MJT_Y - 1) / MJT_Y, 2);
+      k_mx_sweep_multi<<<grid3, MB, 0, st>>>(g, ns, bx, wx, wy, m->body, m->hpt, m->vpt, w.pxy,
+                                             a, b);
+    }
     double* t = a;
     a = b;
     b = t;
