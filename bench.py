@@ -249,7 +249,7 @@ def mixed_precision(mfp, W, kmax=10 ** 7):
                 "frac": round(nbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     # condition estimate of this operator from an FP64 solve's CG scalars (untimed)
     rk = mfp.psi_solve(case.grid, case.circles, disp, kind, body, case.flow, rtol=1e-10,
-                       pair=case.pair, sample_cap=0, estimate_kappa=True)
+                       kmax=kmax, pair=case.pair, sample_cap=0, estimate_kappa=True)
     out["kappa_gpu_lanczos"] = {"kappa": rk.stats["kappa_est"], "ritz_min": rk.stats["ritz_min"],
                                 "ritz_max": rk.stats["ritz_max"], "steps": rk.stats["kappa_steps"]}
     ref = res["fp64"].psi
@@ -471,6 +471,10 @@ def delta_sweep(mfp, W, count=256):
                        "256x128..1024x512 cells, rtol 1e-10",
            "nodes": sum(c.grid.nodes for c in cases)}
     res = {}
+    # algorithmic bytes of one iteration launch of each system (geometry on the fly,
+    # the batched layouts' element mode), FP64 and FP32 vectors
+    per_launch = {esz: [step_bytes(c, d, b, esz)[0] for c, (_, _, d, _, b) in zip(cases, systems)]
+                  for esz in (8, 4)}
     for prec in ("fp32_ir", "fp64"):
         ws = mfp.binding.workspace(mfp.binding.batched_workspace_size(systems, prec), "cuda:0")
         r, ms = _timed(lambda: mfp.psi_solve_batched(systems, flow, precision=prec,
@@ -478,10 +482,17 @@ def delta_sweep(mfp, W, count=256):
         del ws
         res[prec] = r
         its = [s["iters"] for s in r.stats]
+        # every system's iteration launches (FP32 ones for FP32 + refinement); their
+        # bytes over the whole batched solve's wall time (set-up, refinement residuals
+        # and the other kernels included) bound the iteration kernel's rate from below
+        nbytes = sum(k * v for k, v in zip(its, per_launch[4 if prec == "fp32_ir" else 8]))
         out["batched_" + prec] = {
             "ms": round(ms, 1), "iters_mean": sum(its) / len(its), "iters_max": max(its),
             "max_relres_true": max(s["relres_true"] for s in r.stats),
-            "dof_iter_per_s": sum(s["n_dof"] * s["iters"] for s in r.stats) / (ms * 1e-3)}
+            "dof_iter_per_s": sum(s["n_dof"] * s["iters"] for s in r.stats) / (ms * 1e-3),
+            "iteration_bytes": nbytes,
+            "achieved_GBs_wall": round(nbytes / (ms * 1e-3) / 1e9, 1),
+            "frac_wall": round(nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
 
     def seq():
         return [mfp.psi_solve(g, c, d, k, b, flow, rtol=1e-10, pair=pair, sample_cap=0)
@@ -712,6 +723,9 @@ def main():
     ap.add_argument("--mixed-cell-only", action="store_true",
                     help="only run the mixed-cell mesh leg (1024x512) and print its JSON "
                          "(for profiling that workload)")
+    ap.add_argument("--sweep-only", action="store_true",
+                    help="only run the 256-system batched delta sweep and print its JSON "
+                         "(for profiling that workload)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -735,6 +749,9 @@ def main():
     if args.mixed_only:
         print(json.dumps({"mixed_precision_4096x2048": mixed_precision(mfp, W, args.mixed_kmax)}),
               flush=True)
+        return
+    if args.sweep_only:
+        print(json.dumps({"delta_sweep_256": delta_sweep(mfp, W)}), flush=True)
         return
     if args.mixed_cell_only:
         out = {"mixed_cell_mesh_1024x512": mixed_cell_mesh(mfp, W),
