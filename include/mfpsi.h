@@ -395,7 +395,7 @@ typedef struct {
 } mfp_variant;
 
 /* Workspace bytes for mfp_psi_solve_batched (automatic schedule), and for these options
- * (precision, element_mode, batch_tasks_per_wave; 0 for invalid options). */
+ * (precision, task_rows, element_mode, batch_tasks_per_wave; 0 for invalid options). */
 size_t mfp_batched_workspace_size(int32_t nvar, const mfp_variant* vars_h, int32_t nbody,
                                   int32_t precision);
 size_t mfp_batched_workspace_size_opts(int32_t nvar, const mfp_variant* vars_h, int32_t nbody,
@@ -413,8 +413,9 @@ size_t mfp_batched_workspace_size_opts(int32_t nvar, const mfp_variant* vars_h, 
  * (FP32 CG; after every block, at most 256 iterations, the FP32 correction is folded
  * into the FP64 iterate, the FP64 residual replaces the FP32 one and the iteration
  * restarts from it with its last direction kept; systems stop on that FP64 residual).
- * Schedule: 4-row tasks; opts->element_mode and opts->batch_tasks_per_wave (or the
- * tuning cache's batched entry) choose the element mode and the tasks per wavefront.
+ * Schedule: opts->task_rows (4 or 5), opts->element_mode and opts->batch_tasks_per_wave
+ * (or the tuning cache's batched entry) choose the rows per task, the element mode and
+ * the tasks per wavefront of every system; other task_rows values are MFP_E_ARG.
  * Returns the worst status over the systems. */
 int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h, const mfp_circle* circles_h,
                           int32_t nbody, const mfp_flow* flow, const mfp_solver_opts* opts,

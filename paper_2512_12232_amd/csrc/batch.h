@@ -279,9 +279,12 @@ constexpr int BATCH_SEG = 4;
 // 4: 1297 / 896, 8: 1286 / 910.
 constexpr int BATCH_TPW = 4;
 
-// Schedule of a batched solve: tasks per wavefront and the element mode (stored
-// entries or geometry on the fly) of every system; 4-row tasks throughout.
+// Schedule of a batched solve: node rows per task (4 or 5), tasks per wavefront and
+// the element mode (stored entries or geometry on the fly) of every system.  5-row
+// tasks by default (256-system sweep, geometry on the fly, 4 tasks per wavefront:
+// FP64 1270 -> 1244 ms, FP32 + refinement 890 -> 881 ms against 4-row tasks).
 struct BatchSchedule {
+  int hc = 5;
   int tpw = BATCH_TPW;
   int kst = 0;
   int ipl = 0;  // launches per replayed block when the caller passes 0 (0: 64)
@@ -294,16 +297,20 @@ static int resolve_batch_schedule(int precision, const mfp_solver_opts* o, Batch
   TuneEntry e;
   mfp_grid any{};
   if (tuned_entry(&any, precision, 1, &e)) {
+    if (e.task_rows == 4 || e.task_rows == 5) bs.hc = e.task_rows;
     if (e.tasks_per_wave >= 1 && e.tasks_per_wave <= 64) bs.tpw = e.tasks_per_wave;
     if (e.element_mode == 1 || e.element_mode == 2) bs.kst = e.element_mode == 2;
     if (e.iters_per_launch >= 2 && e.iters_per_launch <= 1024) bs.ipl = e.iters_per_launch;
   }
   if (o) {
     if (o->element_mode < 0 || o->element_mode > 2 || o->batch_tasks_per_wave < 0 ||
-        o->batch_tasks_per_wave > 64) {
-      set_error("invalid batched schedule: element_mode 0..2, batch_tasks_per_wave 0..64");
+        o->batch_tasks_per_wave > 64 ||
+        (o->task_rows != 0 && o->task_rows != 4 && o->task_rows != 5)) {
+      set_error("invalid batched schedule: task_rows 0, 4 or 5, element_mode 0..2, "
+                "batch_tasks_per_wave 0..64");
       return MFP_E_ARG;
     }
+    if (o->task_rows) bs.hc = o->task_rows;
     if (o->element_mode) bs.kst = o->element_mode == 2;
     if (o->batch_tasks_per_wave) bs.tpw = o->batch_tasks_per_wave;
   }
@@ -320,7 +327,8 @@ static int batch_step_blocks(const Layout& L, int tpw) {
 
 static size_t batch_layout(int nvar, const mfp_variant* v, int nb, int precision, void* base,
                            BatchPlan* P, const BatchSchedule& bs) {
-  Schedule sc;  // 4-row tasks
+  Schedule sc;
+  sc.hc = bs.hc;
   sc.kst = bs.kst;
   Bump bp(base);
   if (P) {
@@ -400,21 +408,39 @@ static StepArgs<T> batch_step_args(const SolveWs& w, const mfp_grid& g, int nb, 
   return a;
 }
 
-template <typename T>
-static void launch_step_batch(int G, hipStream_t st, const StepArgs<T>* args, const int2* map,
-                              int koff, int kst) {
+template <typename T, int HC>
+static void launch_step_batch_k(int G, hipStream_t st, const StepArgs<T>* args,
+                                const int2* map, int koff, int kst) {
   // launch jbase + koff is odd (jbase is odd) for even koff: those update the iterate
   if (kst) {
     if ((koff & 1) == 0)
-      k_step_batch<T, true, true><<<G, BLOCK, 0, st>>>(args, map, koff);
+      k_step_batch<T, HC, true, true><<<G, BLOCK, 0, st>>>(args, map, koff);
     else
-      k_step_batch<T, false, true><<<G, BLOCK, 0, st>>>(args, map, koff);
+      k_step_batch<T, HC, false, true><<<G, BLOCK, 0, st>>>(args, map, koff);
   } else {
     if ((koff & 1) == 0)
-      k_step_batch<T, true, false><<<G, BLOCK, 0, st>>>(args, map, koff);
+      k_step_batch<T, HC, true, false><<<G, BLOCK, 0, st>>>(args, map, koff);
     else
-      k_step_batch<T, false, false><<<G, BLOCK, 0, st>>>(args, map, koff);
+      k_step_batch<T, HC, false, false><<<G, BLOCK, 0, st>>>(args, map, koff);
   }
+}
+
+template <typename T>
+static void launch_step_batch(int G, hipStream_t st, const StepArgs<T>* args, const int2* map,
+                              int koff, const BatchSchedule& bs) {
+  if (bs.hc == 5)
+    launch_step_batch_k<T, 5>(G, st, args, map, koff, bs.kst);
+  else
+    launch_step_batch_k<T, 4>(G, st, args, map, koff, bs.kst);
+}
+
+// The FP64 residual apply of every system (the layouts' task rows).
+static void launch_apply_batch(int G, hipStream_t st, const ApplyArgs<double>* args,
+                               const int2* map, const BatchSchedule& bs) {
+  if (bs.hc == 5)
+    k_apply_batch<double, 5><<<G, BLOCK, 0, st>>>(args, map);
+  else
+    k_apply_batch<double, 4><<<G, BLOCK, 0, st>>>(args, map);
 }
 
 }  // namespace mfp
@@ -563,7 +589,7 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   MFP_TRY_HIP(hipEventRecord(e0, st));
   // start: residual of x = 0 for every system
   k_b_formw<<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, mixed ? 1 : 0);
-  k_apply_batch<double, 4><<<P.totG, BLOCK, 0, st>>>(P.a64, P.amap);
+  launch_apply_batch(P.totG, st, P.a64, P.amap, bs);
   k_b_resid<<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, mixed ? 1 : 0);
   k_b_fin<<<nvar, BLOCK, 0, st>>>(P.be, mixed ? 1 : 0, 1, rtol2, kmax_abs, P.flags);
   MFP_TRY_HIP(hipGetLastError());
@@ -578,14 +604,14 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
   if (he == hipSuccess) {
     for (int k = 0; k < m; ++k) {
       if (mixed)
-        launch_step_batch<float>(P.totGS, cs, P.s32, P.smap, k, bs.kst);
+        launch_step_batch<float>(P.totGS, cs, P.s32, P.smap, k, bs);
       else
-        launch_step_batch<double>(P.totGS, cs, P.s64, P.smap, k, bs.kst);
+        launch_step_batch<double>(P.totGS, cs, P.s64, P.smap, k, bs);
     }
     if (mixed) {
       k_b_finish<float><<<P.totG2, BLOCK, 0, cs>>>(P.be, P.umap, m - 1, 1);
       k_b_formw<<<P.totG2, BLOCK, 0, cs>>>(P.be, P.umap, 1);
-      k_apply_batch<double, 4><<<P.totG, BLOCK, 0, cs>>>(P.a64, P.amap);
+      launch_apply_batch(P.totG, cs, P.a64, P.amap, bs);
       k_b_resid<<<P.totG2, BLOCK, 0, cs>>>(P.be, P.umap, 1);
       k_b_fin<<<nvar, BLOCK, 0, cs>>>(P.be, 1, 0, rtol2, kmax_abs, P.flags);
     }
@@ -623,7 +649,7 @@ extern "C" int mfp_psi_solve_batched(int32_t nvar, const mfp_variant* vars_h,
     // complete the iterates, then the true residual of every system
     k_b_finish<double><<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, -1, 0);
     k_b_formw<<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, 0);
-    k_apply_batch<double, 4><<<P.totG, BLOCK, 0, st>>>(P.a64, P.amap);
+    launch_apply_batch(P.totG, st, P.a64, P.amap, bs);
     k_b_resid<<<P.totG2, BLOCK, 0, st>>>(P.be, P.umap, 2);
     k_b_fin<<<nvar, BLOCK, 0, st>>>(P.be, 2, 0, rtol2, kmax_abs, P.flags);
     MFP_TRY_HIP(hipGetLastError());

@@ -581,8 +581,9 @@ __global__ void __launch_bounds__(NW * 64) k_step(StepArgs<T> a) {
 
 // Many independent systems in one launch: block b works for system map[b].x as its
 // virtual block map[b].y (each system's blocks start at a multiple of 8); koff is this
-// launch's offset in the replayed block of launches.
-template <typename T, bool XUPD, bool KST>
+// launch's offset in the replayed block of launches; tasks of HC node rows (the
+// layouts').
+template <typename T, int HC, bool XUPD, bool KST>
 __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restrict__ args,
                                                       const int2* __restrict__ map, int koff) {
   __shared__ double s_red[4 * WAVES + 4];  // + stop flag, launch header
@@ -592,7 +593,7 @@ __global__ void __launch_bounds__(BLOCK) k_step_batch(const StepArgs<T>* __restr
   const StepArgs<T>& a = args[vm.x];
   // streaming stores: the systems' vectors together exceed the memory-side cache
   // (measured on a 256-system sweep: 2% faster than cached stores)
-  step_core<T, 4, true, XUPD, KST, WAVES, true>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
+  step_core<T, HC, true, XUPD, KST, WAVES, true>(a, vm.y, a.G, koff, s_red, s_pb, s_qb);
 }
 
 // Tasks of HC node rows (the layout's); odd launches update the iterate; a.stream

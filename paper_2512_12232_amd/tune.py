@@ -10,8 +10,8 @@ share of distorted cells:
                  once per solve and its six off-diagonal entries read every iteration;
 * store_mode     1: cached vector stores; 2: streaming (non-temporal) stores;
 * launch_blocks  work-groups per launch (0: as many as stay resident);
-* batched solves: tasks per wavefront, element mode and launches per replayed
-  block (iters_per_launch).
+* batched solves: task rows (4 or 5), tasks per wavefront, element mode and
+  launches per replayed block (iters_per_launch).
 
 The tuner times complete solves of a representative workload for candidate
 schedules with the library's own event timing (the iteration phase,
@@ -171,9 +171,15 @@ def tune_batched(precision, count=256, seed=0, reps=2, log=print):
     def ok(r):
         return r is not None and np.abs(np.array(r.copfi) - np.array(ref.copfi)).max() <= 1e-7
 
-    best = {"element_mode": 0, "batch_tasks_per_wave": 0}
+    best = {"task_rows": 0, "element_mode": 0, "batch_tasks_per_wave": 0}
     best_ipl, t_best = 0, t_def
     with _no_cache():
+        for rows in (4, 5):
+            cand = dict(best, task_rows=rows)
+            t, r = time_batched(systems, flow, precision, cand, best_ipl, reps)
+            log(f"  {cand}: {t:.1f} ms")
+            if ok(r) and t < MARGIN * t_best:
+                best, t_best = cand, t
         for em in (1, 2):
             for tpw in (1, 2, 4, 8):
                 cand = dict(best, element_mode=em, batch_tasks_per_wave=tpw)
@@ -244,7 +250,7 @@ def main(argv=None):
         print(f"[tune] batched {prec} ({a.count} systems)", flush=True)
         best, ipl, t_best, t_def = tune_batched(prec, a.count, 0, a.reps,
                                                 log=lambda s: print(s, flush=True))
-        entries.append([arch, 0, 0, prec_code[prec], 1, 0, best["element_mode"], 0, 0,
+        entries.append([arch, 0, 0, prec_code[prec], 1, best["task_rows"], best["element_mode"], 0, 0,
                         best["batch_tasks_per_wave"], ipl,
                         f"{t_best:.1f} ms vs built-in {t_def:.1f} ms"])
         report.append(dict(grid="batched", precision=prec, schedule=dict(best, iters_per_launch=ipl),

@@ -43,12 +43,14 @@ def meshes(mfp, cases):
     return out
 
 
+@pytest.mark.parametrize("rows", [4, 5])
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
-def test_batched_matches_single_and_oracle(mfp, precision):
-    say(f"[batched] {precision}")
+def test_batched_matches_single_and_oracle(mfp, precision, rows):
+    say(f"[batched] {precision} {rows}-row tasks")
     systems = meshes(mfp, SMALL)
     res = mfp.psi_solve_batched(systems, SMALL[0].flow, precision=precision, rtol=1e-12,
-                                pair=(3, 4), want_psi=True, iters_per_launch=32)
+                                pair=(3, 4), want_psi=True, iters_per_launch=32,
+                                schedule={"task_rows": rows})
     assert res.status == 0, res.status
     for i, c in enumerate(SMALL):
         s = res.stats[i]
@@ -109,3 +111,14 @@ def test_batched_full_sweep_every_system_converges(mfp):
         assert a["relres_true"] <= 1.5e-10, (i, a["relres_true"])
         assert a["iters"] <= 1.6 * b["iters"] + 64, (i, a["iters"], b["iters"])
     np.testing.assert_allclose(r32.copfi, r64.copfi, rtol=0, atol=1e-7)
+
+
+def test_batched_schedule_rejects_other_task_rows(mfp):
+    """The batched layouts take 4- or 5-row tasks; 8 is an argument error before any
+    launch."""
+    systems = meshes(mfp, SMALL[:2])
+    with pytest.raises(mfp.MfpError) as e:
+        mfp.psi_solve_batched(systems, SMALL[0].flow, precision="fp64", rtol=1e-10,
+                              pair=(3, 4), schedule={"task_rows": 8},
+                              ws=torch.empty(1 << 20, dtype=torch.uint8, device=DEV))
+    assert e.value.status == mfp.MFP_E_ARG
