@@ -223,7 +223,18 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
   // next task's data (requested one task ahead)
   T nr[HC + 2], nq[HC + 2], np[HC + 2], nx[HC], n2[HC];  // n2: p_{j-2} (XUPD)
   int n_plain = 1, n_body = 0, n_slot = -1, n_geo = 0;
-  int t = vb * NW + wv, tstep = W, tflags = 1;  // first task, step to the next, flags
+  // Wavefront u takes tasks u, u + W, u + 2W, ... through the full rounds (F = ntask / W
+  // of them).  The last, partial round's R tasks go out in eight contiguous runs, one to
+  // each XCD's group of W / 8 wavefronts (u / (W / 8) is the XCD): dealt to the first R
+  // wavefronts, as a full round is, they would all sit on the first XCDs, which would
+  // then run that round alone while the rest of the chip waited for the launch's end
+  // (2048x1024, 8738 tasks over 2048 wavefronts: the last 7-11 us of a 24-33 us launch).
+  const int u = vb * NW + wv;
+  const int F = ntask / W, FW = F * W, R = ntask - FW;
+  const int gw = W >> 3, gx = u / gw, gl = u - gx * gw;
+  const int rb = (gx * R) >> 3, re = ((gx + 1) * R) >> 3;
+  const int t_last = gl < re - rb ? FW + rb + gl : ntask;  // its task of the last round
+  int t = F > 0 ? u : t_last, tflags = 1;  // first task, table flags
   const gmem<int>* const tgeo = as_global(a.tgeo);
   auto fetch = [&](int t) {
     if constexpr (TAB) {
@@ -308,7 +319,6 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     asm volatile("s_load_dwordx2 %0, %1, 0x0\n\ts_waitcnt lgkmcnt(0)" : "=s"(e) : "s"(ep));
     const int ex = (int)(unsigned)e;  // int2 (x, y) in memory: x in the low word
     t = ex >= 0 ? ex : ntask;
-    tstep = ntask;
     tflags = (int)(e >> 32);
   }
   fetch(t < ntask ? t : ntask - 1);  // a wavefront without a task drops what it fetched
@@ -542,11 +552,13 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     // one task, nothing to request after it
     if (t < ntask) task(t, n_plain != 0, n_plain == 0 && n_body != 0, n_slot, n_geo, [] {});
   } else {
-    for (; t < ntask; t += tstep) {
+    while (t < ntask) {
       const bool plain = n_plain != 0;
+      const int tn = t + W < FW ? t + W : (t < FW ? t_last : ntask);
       task(t, plain, !plain && n_body != 0, n_slot, n_geo, [&] {
-        if (t + tstep < ntask) fetch(t + tstep);
+        if (tn < ntask) fetch(tn);
       });
+      t = tn;
     }
   }
   // four block sums, fixed order
