@@ -422,6 +422,35 @@ def test_task_table_agrees_with_strided_assignment(mfp, name):
     assert abs(ia - ib) <= 0.02 * ib
 
 
+@pytest.mark.parametrize("name,blocks", [("five_ragged130x67", 8), ("five_ragged130x67", 16),
+                                         ("five_gap_lt_h_256x128", 8),
+                                         ("five_gap_lt_h_256x128", 48)])
+def test_strided_launch_rounds_match_oracle(mfp, name, blocks):
+    """The strided launch deals full rounds of W = 4 x blocks tasks, wavefront u taking
+    u, u + W, ..., and splits the last, partial round into eight contiguous runs, one
+    per XCD group of W / 8 wavefronts.  Forced launch sizes reach both cases with 4-row
+    tasks: 51 tasks (130x67) over W = 32 (one full round, 19 left over) and W = 64 (no
+    full round); 165 tasks (256x128) over W = 32 (five rounds, 5 left over) and
+    W = 192 (none).  Every case must solve the oracle's system (a task dealt twice or
+    not at all would not)."""
+    c = CASES[name]
+    disp, kind, body = mfp.mesh_conform(c.grid, c.circles, c.nsweeps, device=DEV)
+    res = mfp.psi_solve(c.grid, c.circles, disp, kind, body, c.flow, rtol=1e-13,
+                        pair=c.pair, schedule={"task_rows": 4, "element_mode": 1,
+                                               "launch_blocks": blocks})
+    assert res.status == 0
+    ntask = -(-(c.grid.nx + 1) // 62) * -(-(c.grid.ny + 1) // 4)
+    assert res.stats["n_tiles"] == ntask
+    assert res.stats["step_blocks"] == blocks and res.stats["step_block_waves"] == 4
+    ref = O.solve(O.conform(c.grid, c.circles, c.nsweeps), c.flow)
+    psi = res.psi.cpu().numpy()
+    say(f"  {name}: {ntask} tasks over {4 * blocks} wavefronts, {res.stats['iters']} "
+        f"iterations, node max {node_max_err(psi, ref.psi):.2e}")
+    assert node_max_err(psi, ref.psi) <= 1e-10
+    np.testing.assert_allclose(res.psi_b, ref.psi_b, rtol=0, atol=1e-10)
+    assert res.stats["relres_true"] <= 2e-13
+
+
 @pytest.mark.parametrize("name", ["cyl64", "five96x48", "five_ragged130x67",
                                   "five_gap_lt_h_256x128"])
 @pytest.mark.parametrize("precision,rows", [("fp64", 4), ("fp64", 5), ("fp32_ir", 4),
