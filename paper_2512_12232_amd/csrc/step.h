@@ -473,8 +473,12 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
     }
   }
   if (code) return;
-  if (wv == 0 && lane < nb) s_pb[lane] = pbj;
-  __syncthreads();
+  if constexpr (!TAB) {
+    if (wv == 0 && lane < nb) s_pb[lane] = pbj;
+    __syncthreads();
+  }
+  // the table launch needs no second barrier: every wavefront holds the same body
+  // values (lane b: body b) and its tasks read them from its own lanes
   const T al = (T)alpha, be = (T)beta, al2 = (T)alpha2;
   __builtin_amdgcn_s_setprio(0);
 
@@ -511,10 +515,19 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
 #pragma unroll
       for (int r = 0; r < HC + 2; ++r) {
         const int8_t g = tg[r];
-        if (g >= TAG_BODY0)
-          v[r] = (T)s_pb[g - TAG_BODY0];
-        else if (g > TAG_FREE)
-          v[r] = (T)0;
+        if constexpr (TAB) {
+          // every lane takes part in the lane permute; lanes off a body read their own
+          const double pv = __shfl(pbj, g >= TAG_BODY0 ? g - TAG_BODY0 : lane);
+          if (g >= TAG_BODY0)
+            v[r] = (T)pv;
+          else if (g > TAG_FREE)
+            v[r] = (T)0;
+        } else {
+          if (g >= TAG_BODY0)
+            v[r] = (T)s_pb[g - TAG_BODY0];
+          else if (g > TAG_FREE)
+            v[r] = (T)0;
+        }
       }
       if constexpr (KST)
         march_task_stored<T, HC>(v, kc, qr);
