@@ -380,13 +380,20 @@ __device__ __forceinline__ void step_core(const StepArgs<T>& a, const int vblk, 
       if (b1 < nb) q1 += bq[(long long)sl * nb + b1];
     }
   }
-  // wave sums, six independent chains
-  s0 = wave_sum(s0);
-  s1 = wave_sum(s1);
-  s2 = wave_sum(s2);
-  s3 = wave_sum(s3);
-  q0 = wave_sum(q0);
-  q1 = wave_sum(q1);
+  // wave sums, six independent chains.  A wavefront skips the chains whose lanes are
+  // all zero: the partials when the previous launch had no more blocks than the
+  // wavefronts before it have lanes (a table launch of 256 blocks: wavefronts 4..7),
+  // the slot sums of bodies that do not exist.  All of a block's wavefronts run this
+  // FP64 arithmetic at once, two to a SIMD, so the idle chains cost the others issue
+  // slots.
+  if (npart > wv * 64) {
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    s3 = wave_sum(s3);
+  }
+  if (b0 < nb) q0 = wave_sum(q0);
+  if (b1 < nb) q1 = wave_sum(q1);
   if (lane == 0) {
     s_red[4 * wv] = s0;
     s_red[4 * wv + 1] = s1;
